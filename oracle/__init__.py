@@ -1,0 +1,417 @@
+"""FP64 CPU oracle for the coupled pressure-temperature solve.
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the benchmark's CPU
+baseline may use it; the product library never does.  It shares no code
+with the HIP path; the only common module is the seeded input generator
+(`workloads`), which holds no solver arithmetic.
+
+Exact solutions come from a sparse direct solve of the canonical system
+(`direct_solve`, small and medium grids) or from the oracle's own FP64
+multigrid defect-correction loop (`mg_solve`, any grid), whose answer is
+certified by its own residual.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+from typing import Optional, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "ptorc.c")
+_LIB = os.path.join(_HERE, "libptorc.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (FP64, no FMA contraction, OpenMP)."""
+    stale = (not os.path.exists(_LIB)
+             or os.path.getmtime(_LIB) < os.path.getmtime(_SRC))
+    if force or stale:
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared",
+                               "-ffp-contract=off", "-std=c99", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build(force=False)
+        _lib = ctypes.CDLL(_LIB)
+        _declare(_lib)
+    return _lib
+
+
+class _Phase(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_double) for f in
+                ("rho", "k", "cp", "cv", "c", "gamma", "Gamma", "Pi", "b", "beta")]
+
+
+_D = ctypes.POINTER(ctypes.c_double)
+_I = ctypes.POINTER(ctypes.c_int)
+_L = ctypes.POINTER(ctypes.c_long)
+_P = ctypes.POINTER(_Phase)
+
+
+def _declare(lib):
+    c_long, c_int, c_double = ctypes.c_long, ctypes.c_int, ctypes.c_double
+    sig = {
+        "orc_beta": (c_double, [_P, c_double, c_double]),
+        "orc_phase_lambdas": (None, [_P, c_double, c_double, c_double, _D]),
+        "orc_block_from_lambdas": (None, [_D, _D]),
+        "orc_cell_lambdas": (None, [c_double, _P, _P, c_double, c_double, c_double, _D, _D]),
+        "orc_assemble_phases": (c_long, [c_long, _D, _P, _P, c_double, _D, c_double,
+                                         _D, c_double, _D, _D, _D, _D]),
+        "orc_paper_rhs": (None, [c_long, _D, _D, c_double, _D, c_double, _D, c_double,
+                                 _D, _D]),
+        "orc_canonical_rhs": (None, [c_long, _D, _D, _D, _D, _D]),
+        "orc_faces_from_cells": (None, [c_int, _I, _D, _D, _D]),
+        "orc_apply": (None, [c_int, _I, c_double, _D, _D, _D, _D, _D, _D]),
+        "orc_residual": (None, [c_int, _I, c_double, _D, _D, _D, _D, _D, _D, _D, _D]),
+        "orc_paper_residual": (None, [c_int, _I, c_double, _D, _D, _D, _D, _D, _D, _D, _D]),
+        "orc_lex_sweep": (None, [c_int, _I, c_double, _D, _D, _D, _D, _D, _D]),
+        "orc_rb_sweep": (None, [c_int, _I, c_double, _D, _D, _D, _D, _D, _D]),
+        "orc_coarse_operator": (None, [c_int, _I, _D, _D, _D, _D]),
+        "orc_restrict": (None, [c_int, _I, _D, _D, _D, _D]),
+        "orc_prolong_add": (None, [c_int, _I, _D, _D, _D, _D]),
+        "orc_dense_matrix": (None, [c_int, _I, c_double, _D, _D, c_int, _D]),
+        "orc_lu": (c_int, [c_long, _D, _L]),
+        "orc_lu_solve": (None, [c_long, _D, _L, _D]),
+        "orc_mg_solve": (c_int, [c_int, _I, c_double, _D, _D, _D, _D, _D, _D, _D, _D, _D,
+                                 c_double, c_int, c_int, c_int, c_int, _D]),
+        "orc_mg_levels": (c_int, [c_int, _I]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+
+
+def _d(a: Optional[np.ndarray]):
+    if a is None:
+        return ctypes.cast(None, _D)
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(_D)
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64)).reshape(-1)
+
+
+def _dims(n) -> ctypes.Array:
+    return (ctypes.c_int * 3)(*[int(v) for v in n])
+
+
+def phase(ph) -> _Phase:
+    """ctypes phase record from a workloads.Phase."""
+    return _Phase(*ph.as_tuple())
+
+
+# ---------------------------------------------------------------------------
+# operator
+# ---------------------------------------------------------------------------
+@dataclass
+class Operator:
+    """Assembled canonical operator on one grid (all arrays flat, FP64).
+
+    F: faces [6, N] ((component, axis) major; lower face of each cell),
+    B: block [4, N] in the order (pp, pT, Tp, TT),
+    lam: paper coefficients [4, N] (l1, l2, l3, l4) in phases mode, else None.
+    """
+    dim: int
+    n: Tuple[int, int, int]
+    h: float
+    F: np.ndarray
+    B: np.ndarray
+    lam: Optional[np.ndarray] = None
+    a_p: Optional[np.ndarray] = None
+    a_T: Optional[np.ndarray] = None
+
+    @property
+    def N(self) -> int:
+        return self.n[0] * self.n[1] * self.n[2]
+
+
+def beta(ph, p: float, T: float) -> float:
+    """Eq. (10)."""
+    return _load().orc_beta(ctypes.byref(phase(ph)), p, T)
+
+
+def phase_lambdas(ph, p: float, T: float, dt: float) -> np.ndarray:
+    """Eqs. (29)-(32) for one phase: (l1, l2, l3, l4)."""
+    out = np.zeros(4)
+    _load().orc_phase_lambdas(ctypes.byref(phase(ph)), p, T, dt, _d(out))
+    return out
+
+
+def block_from_lambdas(lam) -> np.ndarray:
+    lam = _f64(lam)
+    out = np.zeros(4)
+    _load().orc_block_from_lambdas(_d(lam), _d(out))
+    return out
+
+
+def cell_lambdas(C: float, liquid, gas, p: float, T: float, dt: float):
+    lam, B = np.zeros(4), np.zeros(4)
+    _load().orc_cell_lambdas(C, ctypes.byref(phase(liquid)), ctypes.byref(phase(gas)),
+                             p, T, dt, _d(lam), _d(B))
+    return lam, B
+
+
+def faces_from_cells(dim, n, a_p, a_T) -> np.ndarray:
+    a_p, a_T = _f64(a_p), _f64(a_T)
+    N = a_p.size
+    F = np.zeros(6 * N)
+    _load().orc_faces_from_cells(dim, _dims(n), _d(a_p), _d(a_T), _d(F))
+    return F.reshape(6, N)
+
+
+def assemble(prob) -> Operator:
+    """Assemble the canonical operator of a workloads.Problem."""
+    lib = _load()
+    N = prob.ncells
+    if prob.mode == "explicit":
+        a_p = np.full(N, float(prob.alpha_p))
+        a_T = np.full(N, float(prob.alpha_T))
+        B = np.repeat(np.asarray(prob.B_const, dtype=np.float64)[:, None], N, axis=1)
+        F = faces_from_cells(prob.dim, prob.n, a_p, a_T)
+        return Operator(prob.dim, prob.n, prob.h, F, np.ascontiguousarray(B), None, a_p, a_T)
+    C = _f64(prob.C)
+    a_p, a_T = np.zeros(N), np.zeros(N)
+    lam, B = np.zeros(4 * N), np.zeros(4 * N)
+    p_adv = None if prob.p_adv is None else _f64(prob.p_adv)
+    T_adv = None if prob.T_adv is None else _f64(prob.T_adv)
+    bad = lib.orc_assemble_phases(N, _d(C), ctypes.byref(phase(prob.liquid)),
+                                  ctypes.byref(phase(prob.gas)), prob.dt,
+                                  _d(p_adv), prob.p_adv_const, _d(T_adv),
+                                  prob.T_adv_const, _d(a_p), _d(a_T), _d(lam), _d(B))
+    if bad:
+        raise ValueError(f"{bad} cells with a non-positive block")
+    F = faces_from_cells(prob.dim, prob.n, a_p, a_T)
+    return Operator(prob.dim, prob.n, prob.h, F, B.reshape(4, N), lam.reshape(4, N),
+                    a_p, a_T)
+
+
+def paper_rhs(op: Operator, prob) -> Tuple[np.ndarray, np.ndarray]:
+    """b = (lambda_p, lambda_T) of Eqs. (33)-(34)."""
+    N = op.N
+    b_p, b_T = np.zeros(N), np.zeros(N)
+    lam = np.ascontiguousarray(op.lam).reshape(-1)
+    p_adv = None if prob.p_adv is None else _f64(prob.p_adv)
+    T_adv = None if prob.T_adv is None else _f64(prob.T_adv)
+    div = None if prob.div_ustar is None else _f64(prob.div_ustar)
+    _load().orc_paper_rhs(N, _d(lam), _d(p_adv), prob.p_adv_const, _d(T_adv),
+                          prob.T_adv_const, _d(div), prob.dt, _d(b_p), _d(b_T))
+    return b_p, b_T
+
+
+def rhs(op: Operator, prob) -> Tuple[np.ndarray, np.ndarray]:
+    """The mode-native right-hand side: paper b in phases mode, f otherwise."""
+    if op.lam is None:
+        return _f64(prob.f_p).copy(), _f64(prob.f_T).copy()
+    return paper_rhs(op, prob)
+
+
+def canonical_rhs(op: Operator, b_p, b_T) -> Tuple[np.ndarray, np.ndarray]:
+    if op.lam is None:
+        return _f64(b_p).copy(), _f64(b_T).copy()
+    N = op.N
+    f_p, f_T = np.zeros(N), np.zeros(N)
+    lam = np.ascontiguousarray(op.lam).reshape(-1)
+    _load().orc_canonical_rhs(N, _d(lam), _d(_f64(b_p)), _d(_f64(b_T)), _d(f_p), _d(f_T))
+    return f_p, f_T
+
+
+def _fb(op: Operator):
+    return (np.ascontiguousarray(op.F).reshape(-1), np.ascontiguousarray(op.B).reshape(-1))
+
+
+def apply(op: Operator, p, T) -> Tuple[np.ndarray, np.ndarray]:
+    F, B = _fb(op)
+    Ap, AT = np.zeros(op.N), np.zeros(op.N)
+    _load().orc_apply(op.dim, _dims(op.n), op.h, _d(F), _d(B), _d(_f64(p)), _d(_f64(T)),
+                      _d(Ap), _d(AT))
+    return Ap, AT
+
+
+def residual(op: Operator, f_p, f_T, p, T) -> Tuple[np.ndarray, np.ndarray]:
+    F, B = _fb(op)
+    rp, rT = np.zeros(op.N), np.zeros(op.N)
+    _load().orc_residual(op.dim, _dims(op.n), op.h, _d(F), _d(B), _d(_f64(f_p)),
+                         _d(_f64(f_T)), _d(_f64(p)), _d(_f64(T)), _d(rp), _d(rT))
+    return rp, rT
+
+
+def paper_residual(op: Operator, b_p, b_T, p, T) -> Tuple[np.ndarray, np.ndarray]:
+    """res = b - L(a) of Eqs. (27)-(28) (phases mode)."""
+    F, _ = _fb(op)
+    lam = np.ascontiguousarray(op.lam).reshape(-1)
+    rp, rT = np.zeros(op.N), np.zeros(op.N)
+    _load().orc_paper_residual(op.dim, _dims(op.n), op.h, _d(F), _d(lam), _d(_f64(b_p)),
+                               _d(_f64(b_T)), _d(_f64(p)), _d(_f64(T)), _d(rp), _d(rT))
+    return rp, rT
+
+
+def relres(op: Operator, b_p, b_T, p, T) -> np.ndarray:
+    """Per-component ||res||_2 / ||b||_2 in the mode-native (paper) form."""
+    if op.lam is None:
+        rp, rT = residual(op, b_p, b_T, p, T)
+    else:
+        rp, rT = paper_residual(op, b_p, b_T, p, T)
+    return np.array([np.linalg.norm(rp) / np.linalg.norm(b_p),
+                     np.linalg.norm(rT) / np.linalg.norm(b_T)])
+
+
+# ---------------------------------------------------------------------------
+# multigrid steps (for step-by-step comparisons)
+# ---------------------------------------------------------------------------
+def sweep(op: Operator, f_p, f_T, p, T, order: str = "rb"):
+    """One block Gauss-Seidel sweep in place ("rb" or "lex")."""
+    F, B = _fb(op)
+    fn = _load().orc_rb_sweep if order == "rb" else _load().orc_lex_sweep
+    assert p.dtype == np.float64 and T.dtype == np.float64
+    fn(op.dim, _dims(op.n), op.h, _d(F), _d(B), _d(_f64(f_p)), _d(_f64(f_T)), _d(p), _d(T))
+
+
+def coarse_dims(dim, n):
+    return tuple(int(n[a]) // 2 if a < dim else 1 for a in range(3))
+
+
+def coarse_operator(op: Operator) -> Operator:
+    nc = coarse_dims(op.dim, op.n)
+    Nc = nc[0] * nc[1] * nc[2]
+    F, B = _fb(op)
+    Fc, Bc = np.zeros(6 * Nc), np.zeros(4 * Nc)
+    _load().orc_coarse_operator(op.dim, _dims(op.n), _d(F), _d(B), _d(Fc), _d(Bc))
+    return Operator(op.dim, nc, 2 * op.h, Fc.reshape(6, Nc), Bc.reshape(4, Nc))
+
+
+def restrict(dim, n, r_p, r_T):
+    nc = coarse_dims(dim, n)
+    Nc = nc[0] * nc[1] * nc[2]
+    fp, fT = np.zeros(Nc), np.zeros(Nc)
+    _load().orc_restrict(dim, _dims(n), _d(_f64(r_p)), _d(_f64(r_T)), _d(fp), _d(fT))
+    return fp, fT
+
+
+def prolong_add(dim, n, e_p, e_T, p, T):
+    assert p.dtype == np.float64 and T.dtype == np.float64
+    _load().orc_prolong_add(dim, _dims(n), _d(_f64(e_p)), _d(_f64(e_T)), _d(p), _d(T))
+
+
+def dense_matrix(op: Operator, pin_mean: bool = False) -> np.ndarray:
+    F, B = _fb(op)
+    m = 2 * op.N
+    M = np.zeros(m * m)
+    _load().orc_dense_matrix(op.dim, _dims(op.n), op.h, _d(F), _d(B), int(pin_mean), _d(M))
+    return M.reshape(m, m)
+
+
+def lu_solve_dense(M: np.ndarray, x: np.ndarray) -> np.ndarray:
+    """The oracle's own LU with partial pivoting."""
+    m = M.shape[0]
+    A = np.ascontiguousarray(M, dtype=np.float64).copy().reshape(-1)
+    piv = np.zeros(m, dtype=np.int64)
+    if _load().orc_lu(m, _d(A), piv.ctypes.data_as(_L)):
+        raise np.linalg.LinAlgError("singular")
+    y = _f64(x).copy()
+    _load().orc_lu_solve(m, _d(A), piv.ctypes.data_as(_L), _d(y))
+    return y
+
+
+def mg_levels(dim, n) -> int:
+    return _load().orc_mg_levels(dim, _dims(n))
+
+
+# ---------------------------------------------------------------------------
+# solves
+# ---------------------------------------------------------------------------
+def mg_solve(op: Operator, b_p, b_T, p0=None, T0=None, rtol: float = 1e-13,
+             max_cycles: int = 200, nu1: int = 2, nu2: int = 2,
+             pin_mean: bool = False):
+    """Defect-correction multigrid solve (Sec. 3) in FP64.
+
+    (b_p, b_T) is the mode-native right-hand side (paper b in phases mode).
+    Returns (p, T, cycles, history[cycles+1, 2]); cycles = -1 when the
+    tolerance was not reached within max_cycles.
+    """
+    N = op.N
+    b_p, b_T = _f64(b_p), _f64(b_T)
+    f_p, f_T = canonical_rhs(op, b_p, b_T)
+    p = np.zeros(N) if p0 is None else _f64(p0).copy()
+    T = np.zeros(N) if T0 is None else _f64(T0).copy()
+    hist = np.zeros(2 * (max_cycles + 2))
+    F, B = _fb(op)
+    lam = None if op.lam is None else np.ascontiguousarray(op.lam).reshape(-1)
+    cyc = _load().orc_mg_solve(op.dim, _dims(op.n), op.h, _d(F), _d(B), _d(lam),
+                               _d(b_p), _d(b_T), _d(f_p), _d(f_T), _d(p), _d(T),
+                               rtol, max_cycles, nu1, nu2, int(pin_mean), _d(hist))
+    ncyc = max_cycles if cyc < 0 else cyc
+    return p, T, cyc, hist[: 2 * (ncyc + 1)].reshape(-1, 2)
+
+
+def sparse_matrix(op: Operator):
+    """The canonical operator as a scipy CSR matrix, unknowns [p; T]."""
+    import scipy.sparse as sp
+    N = op.N
+    nx, ny, nz = op.n
+    idx = np.arange(N).reshape(nz, ny, nx)
+    rows, cols, vals = [], [], []
+    inv_h2 = 1.0 / (op.h * op.h)
+    for c in range(2):
+        diag = np.zeros(N)
+        for a in range(op.dim):
+            Fa = op.F[c * 3 + a].reshape(nz, ny, nx)
+            ax = 2 - a
+            sl_hi = [slice(None)] * 3
+            sl_lo = [slice(None)] * 3
+            sl_hi[ax] = slice(1, None)
+            sl_lo[ax] = slice(0, -1)
+            w = (Fa[tuple(sl_hi)] * inv_h2).reshape(-1)
+            i_hi = idx[tuple(sl_hi)].reshape(-1)
+            i_lo = idx[tuple(sl_lo)].reshape(-1)
+            off = c * N
+            rows += [i_hi + off, i_lo + off]
+            cols += [i_lo + off, i_hi + off]
+            vals += [-w, -w]
+            np.add.at(diag, i_hi, w)
+            np.add.at(diag, i_lo, w)
+        rows.append(np.arange(N) + c * N)
+        cols.append(np.arange(N) + c * N)
+        vals.append(diag + op.B[0 if c == 0 else 3])
+    rows += [np.arange(N), np.arange(N) + N]
+    cols += [np.arange(N) + N, np.arange(N)]
+    vals += [op.B[1].copy(), op.B[2].copy()]
+    A = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                      shape=(2 * N, 2 * N))
+    return A
+
+
+def direct_solve(op: Operator, b_p, b_T) -> Tuple[np.ndarray, np.ndarray]:
+    """Sparse direct solve of A u = f (mode-native right-hand side)."""
+    import scipy.sparse.linalg as spla
+    f_p, f_T = canonical_rhs(op, b_p, b_T)
+    A = sparse_matrix(op).tocsc()
+    x = spla.spsolve(A, np.concatenate([f_p, f_T]))
+    return x[: op.N].copy(), x[op.N:].copy()
+
+
+def solve(prob, rtol: float = 1e-13, max_cycles: int = 200, direct_max: int = 70000):
+    """Reference solution of a workloads.Problem: sparse direct when the grid
+    has at most `direct_max` cells, else the oracle multigrid to `rtol`.
+    Returns (op, b_p, b_T, p, T)."""
+    op = assemble(prob)
+    b_p, b_T = rhs(op, prob)
+    if op.N <= direct_max:
+        p, T = direct_solve(op, b_p, b_T)
+    else:
+        p, T, cyc, _ = mg_solve(op, b_p, b_T, rtol=rtol, max_cycles=max_cycles,
+                                pin_mean=prob.mean_constraint)
+        if cyc < 0:
+            raise RuntimeError("oracle multigrid did not converge")
+    return op, b_p, b_T, p, T

@@ -1,0 +1,463 @@
+"""Pins of the FP64 oracle against what mathematics and the paper fix.
+
+Each test checks the oracle against an independent fact: a closed form, a
+textbook limit, a library routine applied to an independently built matrix,
+or a printed table.  None of them re-types the oracle's own formula.
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.fft
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+import workloads as W
+
+
+def _const_op(orc, dim, n, h, a_p, a_T, B):
+    N = n[0] * n[1] * n[2]
+    F = orc.faces_from_cells(dim, n, np.full(N, a_p), np.full(N, a_T))
+    Bm = np.repeat(np.asarray(B, float)[:, None], N, axis=1)
+    return orc.Operator(dim, n, h, F, Bm)
+
+
+def _cos_mode(dim, n, ks):
+    shape = tuple(n[dim - 1 - a] for a in range(dim))
+    u = np.ones(shape)
+    for a in range(dim):
+        x = (np.arange(n[a]) + 0.5)
+        shp = [1] * dim
+        shp[dim - 1 - a] = n[a]
+        u = u * np.cos(math.pi * ks[a] * x / n[a]).reshape(shp)
+    return u.reshape(-1)
+
+
+def _random_faces(orc, dim, n, seed):
+    rng = np.random.default_rng(seed)
+    N = n[0] * n[1] * n[2]
+    a_p = rng.uniform(0.1, 2.0, N)
+    a_T = 10.0 ** rng.uniform(-3, 1, N)
+    return orc.faces_from_cells(dim, n, a_p, a_T)
+
+
+def _face_list(dim, n, F, c):
+    """(lower cell, upper cell, coefficient) of every interior face, built
+    with numpy indexing (independent of the oracle's loops)."""
+    nx, ny, nz = n
+    idx = np.arange(nx * ny * nz).reshape(nz, ny, nx)
+    out = []
+    for a in range(dim):
+        ax = 2 - a
+        hi = [slice(None)] * 3
+        lo = [slice(None)] * 3
+        hi[ax] = slice(1, None)
+        lo[ax] = slice(0, -1)
+        ih = idx[tuple(hi)].reshape(-1)
+        il = idx[tuple(lo)].reshape(-1)
+        out.append((il, ih, F[c * 3 + a][ih]))
+    return out
+
+
+# ---------------------------------------------------------------- P1 operator
+@pytest.mark.parametrize("dim,n,ks", [(2, (16, 12, 1), (3, 5)), (2, (10, 10, 1), (0, 7)),
+                                      (3, (8, 6, 10, 1)[:3], (1, 2, 4))])
+def test_P1_cosine_modes_are_eigenvectors(orc, dim, n, ks):
+    """Neumann cosine modes (the DCT-II basis) are eigenvectors of the
+    cell-centred Laplacian with eigenvalue (4/h^2) sum sin^2(pi k/(2n))."""
+    h = 0.37
+    ap, aT = 1.7, 0.05
+    op = _const_op(orc, dim, n, h, ap, aT, (0, 0, 0, 0))
+    u = _cos_mode(dim, n, ks)
+    mu = 4.0 / h ** 2 * sum(math.sin(math.pi * ks[a] / (2 * n[a])) ** 2 for a in range(dim))
+    Ap, AT = orc.apply(op, u, 2.0 * u)
+    np.testing.assert_allclose(Ap, ap * mu * u, atol=1e-12 * ap * mu + 1e-13)
+    np.testing.assert_allclose(AT, aT * mu * 2.0 * u, atol=1e-12 * aT * mu + 1e-13)
+
+
+@pytest.mark.parametrize("dim,n", [(2, (9, 7, 1)), (3, (5, 6, 4))])
+def test_P1_energy_conservation_symmetry(orc, dim, n):
+    rng = np.random.default_rng(1)
+    N = n[0] * n[1] * n[2]
+    F = _random_faces(orc, dim, n, 3)
+    op = orc.Operator(dim, n, 0.5, F, np.zeros((4, N)))
+    u, v = rng.standard_normal(N), rng.standard_normal(N)
+    Lu_p, Lu_T = orc.apply(op, u, u)
+    Lv_p, Lv_T = orc.apply(op, v, v)
+    for c, (Lu, Lv) in enumerate([(Lu_p, Lv_p), (Lu_T, Lv_T)]):
+        energy = sum(np.sum(w * (u[il] - u[ih]) ** 2) for il, ih, w in _face_list(dim, n, F, c)) / 0.25
+        assert abs(u @ Lu - energy) <= 1e-12 * energy
+        assert abs(Lu.sum()) <= 1e-12 * np.abs(Lu).sum()          # telescoping flux
+        assert abs(v @ Lu - u @ Lv) <= 1e-12 * (np.abs(v) @ np.abs(Lu))
+
+
+def test_P1_matrix_free_equals_assembled(orc):
+    prob = W.bubble_problem("t", 2, (12, 10), [(0.5, 0.4)], [0.3], W.P0, 10 * W.P0)
+    op = orc.assemble(prob)
+    A = orc.sparse_matrix(op)
+    rng = np.random.default_rng(5)
+    u = rng.standard_normal(2 * op.N)
+    Ap, AT = orc.apply(op, u[: op.N], u[op.N:])
+    ref = A @ u
+    scale = abs(A) @ np.abs(u)
+    assert np.all(np.abs(np.concatenate([Ap, AT]) - ref) <= 1e-14 * scale)
+
+
+# --------------------------------------------------------- P2 exact DCT solve
+def test_P2_constant_case_matches_dct_solution(orc):
+    """64x64 constant-coefficient case: the DCT-II diagonalises the Neumann
+    Laplacian, leaving one 2x2 system per mode."""
+    prob = W.explicit_const()
+    nx, ny = 64, 64
+    h = prob.h
+    Bm = np.array(prob.B_const).reshape(2, 2)
+    fh = np.stack([scipy.fft.dctn(prob.f_p, type=2, norm="ortho"),
+                   scipy.fft.dctn(prob.f_T, type=2, norm="ortho")])
+    ky = np.arange(ny)[:, None]
+    kx = np.arange(nx)[None, :]
+    mu = 4 / h ** 2 * (np.sin(np.pi * kx / (2 * nx)) ** 2 + np.sin(np.pi * ky / (2 * ny)) ** 2)
+    M = np.zeros((ny, nx, 2, 2))
+    M[..., 0, 0] = prob.alpha_p * mu + Bm[0, 0]
+    M[..., 0, 1] = Bm[0, 1]
+    M[..., 1, 0] = Bm[1, 0]
+    M[..., 1, 1] = prob.alpha_T * mu + Bm[1, 1]
+    uh = np.linalg.solve(M, np.moveaxis(fh, 0, -1)[..., None])[..., 0]
+    p_ex = scipy.fft.idctn(uh[..., 0], type=2, norm="ortho").reshape(-1)
+    T_ex = scipy.fft.idctn(uh[..., 1], type=2, norm="ortho").reshape(-1)
+    op = orc.assemble(prob)
+    b_p, b_T = orc.rhs(op, prob)
+    p, T, cyc, hist = orc.mg_solve(op, b_p, b_T, rtol=1e-13)
+    assert cyc > 0
+    assert np.linalg.norm(p - p_ex) <= 1e-11 * np.linalg.norm(p_ex)
+    assert np.linalg.norm(T - T_ex) <= 1e-11 * np.linalg.norm(T_ex)
+    pd, Td = orc.direct_solve(op, b_p, b_T)
+    assert np.linalg.norm(pd - p_ex) <= 1e-12 * np.linalg.norm(p_ex)
+
+
+# ------------------------------------------------------ P3 paper-form dense LU
+def _paper_form_matrix(op):
+    """Dense matrix of Eqs. (27)-(28) with unknown order [T; p]:
+    rows T: div(k grad T) + l1 T + l2 p; rows p: div(grad p/rho) + l3 p +
+    l4 div(k grad T).  div(a grad) is built from the face list."""
+    N = op.N
+    Lk = np.zeros((N, N))
+    Lr = np.zeros((N, N))
+    for c, L in ((1, Lk), (0, Lr)):
+        for il, ih, w in _face_list(op.dim, op.n, op.F, c):
+            w = w / op.h ** 2
+            L[il, ih] += w
+            L[ih, il] += w
+            L[il, il] -= w
+            L[ih, ih] -= w
+    l1, l2, l3, l4 = op.lam
+    M = np.zeros((2 * N, 2 * N))
+    M[:N, :N] = Lk + np.diag(l1)
+    M[:N, N:] = np.diag(l2)
+    M[N:, :N] = l4[:, None] * Lk
+    M[N:, N:] = Lr + np.diag(l3)
+    return M
+
+
+@pytest.mark.parametrize("dim,n,c,r,pl,pg,amp", [
+    (2, (24, 20), (0.5, 0.45), 0.25, W.P0, 10 * W.P0, 1e-6),
+    (2, (32, 32), (0.5, 0.5), 0.1, W.P0, W.P0, 1e-6),
+    (3, (8, 8, 10), (0.5, 0.5, 0.4), 0.3, 100 * W.P0, 0.01 * W.P0, 0.0),
+])
+def test_P3_paper_form_dense_solve(orc, dim, n, c, r, pl, pg, amp):
+    prob = W.bubble_problem("t", dim, n, [c], [r], pl, pg, div_amp=amp, div_seed=7)
+    op = orc.assemble(prob)
+    b_p, b_T = orc.paper_rhs(op, prob)
+    M = _paper_form_matrix(op)
+    x = np.linalg.solve(M, np.concatenate([b_T, b_p]))
+    T_ex, p_ex = x[: op.N], x[op.N:]
+    # the p error is ~1e4 times the paper-form relative residual here (the
+    # l4 coupling), so the oracle is run to 1e-14
+    p, T, cyc, _ = orc.mg_solve(op, b_p, b_T, rtol=1e-14)
+    assert cyc >= 0
+    # errors in the perturbation about the provisional state
+    p_adv = prob.p_adv if prob.p_adv is not None else np.full(op.N, prob.p_adv_const)
+    dp = p_ex - p_adv.reshape(-1)
+    dT = T_ex - prob.T_adv_const
+    # (FP64 round-off amplified ~1e4 by the coupling bounds the agreement at
+    # a few 1e-12 of |p|; a wrong term would change dp at O(1))
+    assert np.linalg.norm(p - p_ex) <= 2e-11 * np.linalg.norm(p_ex)
+    assert np.linalg.norm(p - p_ex) <= 1e-7 * np.linalg.norm(dp)
+    assert np.linalg.norm(T - T_ex) <= 1e-13 * np.linalg.norm(T_ex)
+    assert np.linalg.norm(T - T_ex) <= 1e-7 * max(np.linalg.norm(dT), 1e-30)
+    # the oracle's own LU on its dense canonical matrix agrees too
+    Mc = orc.dense_matrix(op)
+    f_p, f_T = orc.canonical_rhs(op, b_p, b_T)
+    y = orc.lu_solve_dense(Mc, np.concatenate([f_p, f_T]))
+    # the canonical p-row right-hand side cancels ~4 digits (f_p ~ l4 lT)
+    assert np.linalg.norm(y[: op.N] - p_ex) <= 1e-10 * np.linalg.norm(p_ex)
+
+
+# ----------------------------------------------------- P4 uncoupled limits
+def _scalar_helmholtz(dim, n, h, F, c, shift):
+    N = n[0] * n[1] * n[2]
+    rows, cols, vals = [], [], []
+    diag = np.array(shift, dtype=float) * np.ones(N)
+    for il, ih, w in _face_list(dim, n, F, c):
+        w = w / h ** 2
+        rows += [il, ih]
+        cols += [ih, il]
+        vals += [-w, -w]
+        np.add.at(diag, il, w)
+        np.add.at(diag, ih, w)
+    rows.append(np.arange(N)); cols.append(np.arange(N)); vals.append(diag)
+    return sp.csc_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                         shape=(N, N))
+
+
+def test_P4_uncoupled_helmholtz(orc):
+    dim, n, h = 2, (20, 14, 1), 0.1
+    N = n[0] * n[1]
+    F = _random_faces(orc, dim, n, 11)
+    rng = np.random.default_rng(2)
+    Bpp, BTT = rng.uniform(1, 5, N), rng.uniform(0.1, 3, N)
+    B = np.stack([Bpp, np.zeros(N), np.zeros(N), BTT])
+    op = orc.Operator(dim, n, h, F, B)
+    f_p, f_T = rng.standard_normal(N), rng.standard_normal(N)
+    p, T, cyc, _ = orc.mg_solve(op, f_p, f_T, rtol=1e-14)
+    assert cyc > 0
+    for c, u, f, sh in ((0, p, f_p, Bpp), (1, T, f_T, BTT)):
+        ref = spla.spsolve(_scalar_helmholtz(dim, n, h, F, c, sh), f)
+        assert np.linalg.norm(u - ref) <= 1e-12 * np.linalg.norm(ref)
+
+
+def test_P4_neumann_poisson_with_mean_constraint(orc):
+    """B = 0: the constant mode is fixed by a zero mean; the answer is the
+    minimum-norm least-squares solution of the singular system."""
+    dim, n, h = 2, (16, 12, 1), 1.0 / 16
+    N = n[0] * n[1]
+    F = _random_faces(orc, dim, n, 4)
+    op = orc.Operator(dim, n, h, F, np.zeros((4, N)))
+    rng = np.random.default_rng(9)
+    f_p, f_T = rng.standard_normal(N), rng.standard_normal(N)
+    f_p -= f_p.mean(); f_T -= f_T.mean()
+    p, T, cyc, _ = orc.mg_solve(op, f_p, f_T, rtol=1e-12, pin_mean=True)
+    assert cyc > 0
+    for c, u, f in ((0, p, f_p), (1, T, f_T)):
+        A = _scalar_helmholtz(dim, n, h, F, c, 0.0).toarray()
+        ref = np.linalg.lstsq(A, f, rcond=None)[0]
+        assert abs(u.mean()) < 1e-12 * np.abs(u).max()
+        assert np.linalg.norm(u - ref) <= 1e-10 * np.linalg.norm(ref)
+
+
+# ------------------------------------------------ P5 adiabatic (k -> 0) limit
+def _ideal_gas(p, T, gamma=1.4, R=287.0):
+    """A thermodynamically consistent ideal gas at (p, T)."""
+    rho = p / (R * T)
+    cp = gamma * R / (gamma - 1)
+    return W.Phase(rho=rho, k=0.0, cp=cp, cv=cp / gamma, c=math.sqrt(gamma * p / rho),
+                   gamma=gamma, Gamma=gamma, Pi=0.0, b=0.0)
+
+
+def test_P5_adiabatic_limit_ideal_gas(orc):
+    """Without conduction the p-row is the adiabatic pressure equation with
+    the isentropic compressibility of an ideal gas, 1/(gamma p), and the
+    temperature follows the isentrope dT/dp = (gamma-1) T / (gamma p)."""
+    p0, T0 = 2.0e5, 300.0
+    gas = _ideal_gas(p0, T0)
+    n = (24, 16)
+    dt = 1e-7
+    h = 1e-3 / 24
+    N = n[0] * n[1]
+    rng = np.random.default_rng(3)
+    div = 1e-3 / dt * rng.uniform(-1, 1, N)
+    prob = W.Problem(name="ad", dim=2, n=(24, 16, 1), h=h, mode="phases", C=np.ones(N),
+                     liquid=gas, gas=gas, dt=dt, p_adv=None, p_adv_const=p0,
+                     T_adv=None, T_adv_const=T0, div_ustar=div)
+    op = orc.assemble(prob)
+    b_p, b_T = orc.paper_rhs(op, prob)
+    p, T, cyc, _ = orc.mg_solve(op, b_p, b_T, rtol=1e-14)
+    assert cyc > 0
+    # scalar equation: -div(grad p / rho) + kappa_s/dt^2 (p - p0) = -div/dt
+    kappa_s = 1.0 / (gas.gamma * p0)
+    A = _scalar_helmholtz(2, (24, 16, 1), h, op.F, 0, kappa_s / dt ** 2)
+    dp = spla.spsolve(A, -div / dt)
+    assert np.linalg.norm((p - p0) - dp) <= 1e-9 * np.linalg.norm(dp)
+    dT_ref = (gas.gamma - 1) / gas.gamma * T0 / p0 * (p - p0)
+    assert np.linalg.norm((T - T0) - dT_ref) <= 1e-9 * np.linalg.norm(dT_ref)
+
+
+# ----------------------------------------------------------- P6 uniform state
+@pytest.mark.parametrize("dim,n", [(2, (40, 36)), (3, (12, 10, 8))])
+def test_P6_uniform_state_is_exact(orc, dim, n):
+    prob = W.bubble_problem("u", dim, n, [(0.5,) * dim], [0.2], W.P0, W.P0)
+    op = orc.assemble(prob)
+    b_p, b_T = orc.paper_rhs(op, prob)
+    pa = np.full(op.N, W.P0)
+    Ta = np.full(op.N, W.T0)
+    rp, rT = orc.paper_residual(op, b_p, b_T, pa, Ta)
+    assert np.abs(rp).max() <= 1e-14 * np.abs(b_p).max()
+    assert np.abs(rT).max() <= 1e-14 * np.abs(b_T).max()
+    p, T, cyc, _ = orc.mg_solve(op, b_p, b_T, rtol=1e-13)
+    assert np.abs(p - W.P0).max() <= 1e-10 * W.P0
+    assert np.abs(T - W.T0).max() <= 1e-12 * W.T0
+
+
+# ------------------------------------------------------- P7 block assembly
+def test_P7_thermal_dilation_matches_nasg_volume(orc):
+    """Eq. (10) against a finite difference of the NASG specific volume
+    v = (Gamma-1) c_v T/(p + Pi) + b, with Table 1's water parameters."""
+    tab = {}
+    import os
+    for line in open(os.path.join(os.path.dirname(__file__), "golden", "table1_water_nasg.txt")):
+        if line.strip() and not line.startswith("#"):
+            k, v, _ = line.split()
+            tab[k] = float(v)
+    liq = W.LIQUID
+    assert (liq.Gamma, liq.Pi, liq.b, liq.cv) == (tab["Gamma"], tab["Pi"], tab["b"], tab["c_v"])
+    assert liq.gamma == pytest.approx(tab["c_p"] / tab["c_v"])
+    for p, T in ((W.P0, W.T0), (100 * W.P0, 350.0), (5e6, 400.0)):
+        v = lambda TT: (liq.Gamma - 1) * liq.cv * TT / (p + liq.Pi) + liq.b
+        dT = 1e-3
+        beta_fd = (v(T + dT) - v(T - dT)) / (2 * dT) / v(T)
+        assert orc.beta(liq, p, T) == pytest.approx(beta_fd, rel=1e-9)
+    assert orc.beta(W.GAS, W.P0, W.T0) == pytest.approx(1 / W.T0, rel=1e-15)
+
+
+def test_P7_ideal_gas_block(orc):
+    """For a consistent ideal gas: -l3 dt^2 = 1/(gamma p) (isentropic
+    compressibility), -l2/l1 = (gamma-1) T/(gamma p) (isentrope), and the
+    canonical block has det = l1 l3 with the symmetrised coupling
+    sqrt(1 - 1/gamma)."""
+    p, T, dt = 3e5, 320.0, 2e-8
+    gas = _ideal_gas(p, T)
+    l1, l2, l3, l4 = orc.phase_lambdas(gas, p, T, dt)
+    assert -l3 * dt ** 2 == pytest.approx(1 / (gas.gamma * p), rel=1e-13)
+    assert -l2 / l1 == pytest.approx((gas.gamma - 1) * T / (gas.gamma * p), rel=1e-13)
+    B = orc.block_from_lambdas([l1, l2, l3, l4])
+    assert B[0] * B[3] - B[1] * B[2] == pytest.approx(l1 * l3, rel=1e-12)
+    o = B[1] * B[2] / (B[0] * B[3])
+    assert math.sqrt(o) == pytest.approx(math.sqrt(1 - 1 / gas.gamma), rel=1e-12)
+
+
+def test_P7_mixed_cell_block_is_average(orc):
+    """A mixed cell's block is the C-weighted average of the pure blocks and
+    its determinant is l1 l3 of the cell coefficients."""
+    for C in (0.0, 0.3, 0.77, 1.0):
+        lam, B = orc.cell_lambdas(C, W.LIQUID, W.GAS, 2 * W.P0, W.T0, 1e-9)
+        _, Bl = orc.cell_lambdas(1.0, W.LIQUID, W.GAS, 2 * W.P0, W.T0, 1e-9)
+        _, Bg = orc.cell_lambdas(0.0, W.LIQUID, W.GAS, 2 * W.P0, W.T0, 1e-9)
+        np.testing.assert_allclose(B, C * Bl + (1 - C) * Bg, rtol=1e-14)
+        assert B[0] * B[3] - B[1] * B[2] == pytest.approx(lam[0] * lam[2], rel=1e-10)
+        assert B[0] > 0 and B[3] > 0 and lam[0] * lam[2] > 0
+
+
+# ------------------------------------------------------ P9 symmetrizability
+def test_P9_symmetrizable(orc):
+    rng = np.random.default_rng(8)
+    prob = W.explicit_const(16, 12)
+    op = orc.assemble(prob)
+    D = np.array([1.0, 1.5])
+    prob2 = W.bubble_problem("s", 2, (20, 18), [(0.4, 0.5)], [0.22], W.P0, 10 * W.P0)
+    op2 = orc.assemble(prob2)
+    D2 = np.array([1.0, 1.0 / (W.T0 * prob2.dt)])
+    for o, d in ((op, D), (op2, D2)):
+        u = rng.standard_normal((2, o.N))
+        v = rng.standard_normal((2, o.N))
+        Au = orc.apply(o, u[0], u[1])
+        Av = orc.apply(o, v[0], v[1])
+        lhs = d[0] * v[0] @ Au[0] + d[1] * v[1] @ Au[1]
+        rhs = d[0] * u[0] @ Av[0] + d[1] * u[1] @ Av[1]
+        scale = d[0] * np.abs(v[0]) @ np.abs(Au[0]) + d[1] * np.abs(v[1]) @ np.abs(Au[1])
+        assert abs(lhs - rhs) <= 1e-12 * scale
+        assert lhs == lhs
+
+
+# ------------------------------------------------- P10 discretisation order
+def test_P10_second_order_in_space(orc):
+    """Smooth manufactured solution of the continuous coupled equations with
+    variable coefficients: the discrete error falls as h^2."""
+    ap = lambda x, y: 1.0 + 0.5 * x + 0.25 * y * y
+    aT = lambda x, y: 0.2 + 0.1 * np.sin(x)
+    P = lambda x, y: np.cos(np.pi * x) * np.cos(2 * np.pi * y)
+    Tf = lambda x, y: np.cos(2 * np.pi * x) * np.cos(np.pi * y)
+    # continuous -div(a grad u) computed analytically
+    def minus_div(a, dax, day, ux, uy, uxx, uyy, x, y):
+        return -(dax(x, y) * ux(x, y) + a(x, y) * uxx(x, y) + day(x, y) * uy(x, y) + a(x, y) * uyy(x, y))
+    pi = np.pi
+    Px = lambda x, y: -pi * np.sin(pi * x) * np.cos(2 * pi * y)
+    Py = lambda x, y: -2 * pi * np.cos(pi * x) * np.sin(2 * pi * y)
+    Pxx = lambda x, y: -pi ** 2 * P(x, y)
+    Pyy = lambda x, y: -4 * pi ** 2 * P(x, y)
+    Tx = lambda x, y: -2 * pi * np.sin(2 * pi * x) * np.cos(pi * y)
+    Ty = lambda x, y: -pi * np.cos(2 * pi * x) * np.sin(pi * y)
+    Txx = lambda x, y: -4 * pi ** 2 * Tf(x, y)
+    Tyy = lambda x, y: -pi ** 2 * Tf(x, y)
+    Bc = (3.0, 0.7, 0.4, 2.0)
+    errs = []
+    for n in (16, 32, 64):
+        h = 1.0 / n
+        x = ((np.arange(n) + 0.5) * h)[None, :]
+        y = ((np.arange(n) + 0.5) * h)[:, None]
+        fp = minus_div(ap, lambda x, y: 0.5 + 0 * x, lambda x, y: 0.5 * y + 0 * x, Px, Py, Pxx, Pyy, x, y) \
+            + Bc[0] * P(x, y) + Bc[1] * Tf(x, y)
+        fT = minus_div(aT, lambda x, y: 0.1 * np.cos(x) + 0 * y, lambda x, y: 0 * x * y, Tx, Ty, Txx, Tyy, x, y) \
+            + Bc[2] * P(x, y) + Bc[3] * Tf(x, y)
+        F = orc.faces_from_cells(2, (n, n, 1), (ap(x, y) + 0 * y).reshape(-1), (aT(x, y) + 0 * y).reshape(-1))
+        op = orc.Operator(2, (n, n, 1), h, F, np.repeat(np.array(Bc)[:, None], n * n, 1))
+        p, T = orc.direct_solve(op, fp.reshape(-1), fT.reshape(-1))
+        errs.append(max(np.abs(p - P(x, y).reshape(-1)).max(), np.abs(T - Tf(x, y).reshape(-1)).max()))
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert 3.5 < r1 < 4.6 and 3.5 < r2 < 4.6, errs
+
+
+# ------------------------------------------- multigrid steps and the solver
+def test_mg_steps_linear_and_consistent(orc):
+    """Restriction is the mean of the children, prolongation reproduces
+    constants and linear functions away from the boundary, and the coarse
+    operator of a constant-coefficient grid is the same operator at 2h."""
+    dim, n = 2, (8, 6, 1)
+    rng = np.random.default_rng(0)
+    r = rng.standard_normal(48)
+    fp, fT = orc.restrict(dim, n, r, 2 * r)
+    np.testing.assert_allclose(fp, r.reshape(6, 8).reshape(3, 2, 4, 2).mean(axis=(1, 3)).reshape(-1))
+    np.testing.assert_allclose(fT, 2 * fp)
+    p = np.zeros(48); T = np.zeros(48)
+    orc.prolong_add(dim, n, np.full(12, 2.5), np.full(12, -1.0), p, T)
+    np.testing.assert_allclose(p, 2.5); np.testing.assert_allclose(T, -1.0)
+    # linear in x: coarse centres at X = 2I+1 (fine units) -> fine value = x_f
+    ec = np.tile(np.arange(4) * 2.0 + 1.0, 3)
+    p = np.zeros(48); T = np.zeros(48)
+    orc.prolong_add(dim, n, ec, ec, p, T)
+    xf = np.tile(np.arange(8) + 0.5, 6)
+    inner = (np.tile(np.arange(8), 6) > 0) & (np.tile(np.arange(8), 6) < 7)
+    np.testing.assert_allclose(p[inner], xf[inner])
+    op = _const_op(orc, 3, (8, 4, 6), 0.3, 1.2, 0.4, (1, 2, 3, 4))
+    opc = orc.coarse_operator(op)
+    ref = _const_op(orc, 3, (4, 2, 3), 0.6, 1.2, 0.4, (1, 2, 3, 4))
+    np.testing.assert_allclose(opc.F, ref.F, rtol=1e-15)
+    np.testing.assert_allclose(opc.B, ref.B, rtol=1e-15)
+
+
+def test_mg_solve_matches_direct_on_bubbles(orc):
+    for prob in (W.bubble_problem("a", 2, (48, 40), [(0.3, 0.5), (0.7, 0.5)], [0.12, 0.15],
+                                  W.P0, 10 * W.P0, div_amp=1e-6, div_seed=1),
+                 W.bubble_problem("b", 3, (16, 12, 20), [(0.5, 0.4, 0.6)], [0.3],
+                                  100 * W.P0, 0.01 * W.P0)):
+        op = orc.assemble(prob)
+        b_p, b_T = orc.rhs(op, prob)
+        pd, Td = orc.direct_solve(op, b_p, b_T)
+        p, T, cyc, hist = orc.mg_solve(op, b_p, b_T, rtol=1e-13)
+        assert cyc > 0 and hist[-1].max() <= 1e-13
+        assert np.linalg.norm(p - pd) <= 1e-11 * np.linalg.norm(pd)
+        assert np.linalg.norm(T - Td) <= 1e-12 * np.linalg.norm(Td)
+        # the contraction per cycle is strong in this diagonally dominant regime
+        assert hist[1].max() < 1e-3
+
+
+def test_rb_and_lex_sweeps_reduce_error(orc):
+    prob = W.bubble_problem("a", 2, (20, 20), [(0.5, 0.5)], [0.2], W.P0, 10 * W.P0)
+    op = orc.assemble(prob)
+    b_p, b_T = orc.rhs(op, prob)
+    f_p, f_T = orc.canonical_rhs(op, b_p, b_T)
+    pd, Td = orc.direct_solve(op, b_p, b_T)
+    for order in ("rb", "lex"):
+        p = np.zeros(op.N); T = np.zeros(op.N)
+        e0 = np.linalg.norm(p - pd)
+        for _ in range(3):
+            orc.sweep(op, f_p, f_T, p, T, order)
+        assert np.linalg.norm(p - pd) < 0.5 * e0
