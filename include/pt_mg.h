@@ -1,0 +1,263 @@
+/*
+ * pt_mg.h -- C ABI of libptmg, a multigrid solver for the implicit, two-way
+ * coupled pressure-temperature system of an all-Mach VoF time step
+ * (Saade, Lohse & Fuster, "A multigrid solver for the coupled
+ * pressure-temperature equations in an all-Mach solver with VoF").
+ *
+ * The problem (Sec. 3, Eqs. 27-34).  On a uniform 2-D or 3-D grid of
+ * cubic cells of size h, each cell carries the pressure p and temperature T
+ * at the end of the step.  In the paper's form
+ *     div(k grad T) + l1 T + l2 p                   = lT      (Eq. 27)
+ *     div(grad p / rho) + l3 p + l4 div(k grad T)   = lp      (Eq. 28)
+ * with l1 = -rho c_p/dt, l2 = beta T_adv/dt,
+ * l3 = -(gamma/(rho c^2) - beta^2 T_adv/(rho c_p))/dt^2 (Eqs. 29-31),
+ * l4 = beta/(rho c_p dt) (Eq. 32 read as the form that makes Eq. 28 equal
+ * to Eq. 19 divided by dt), lT = l1 T_adv + l2 p_adv and
+ * lp = l3 p_adv + div(u*)/dt (Eqs. 33-34).  The library solves the
+ * equivalent canonical form, obtained by the exact row operations
+ * T-row := -(Eq. 27), p-row := -(Eq. 28 - l4 * Eq. 27):
+ *     -div(a_p grad p) + Bpp p + BpT T = f_p        a_p = 1/rho
+ *     -div(a_T grad T) + BTp p + BTT T = f_T        a_T = k
+ * with Bpp = -l3 + l4 l2, BpT = l4 l1, BTp = -l2, BTT = -l1,
+ * f_T = -lT, f_p = -lp + l4 lT.
+ *
+ * Discretisation: cell-centred finite volumes, zero flux through every
+ * boundary face, face coefficient = harmonic mean of the two cell values
+ * (a face is closed when both are zero).  Mixed cells use the averaging
+ * rule of Sec. 3 with the liquid (reference-phase) volume fraction C:
+ * rho and k are averaged, and so is each phase's canonical block; the
+ * cell's l1..l4 are the ones that reproduce the averaged block.
+ *
+ * Solve (Sec. 3, defect correction): repeat { residual in FP64; stop when
+ * max over components of ||res||_2/||b||_2 <= rtol (paper row form);
+ * one multigrid V-cycle on the correction; add it }.  The V-cycle runs in
+ * FP64 (PT_PREC_FP64) or FP32 (PT_PREC_MIXED: FP32 smoother, restriction
+ * and prolongation under FP64 iterative refinement; the coarsest grid is
+ * always solved in FP64).
+ *
+ * Conventions for every function below.
+ *  - Field pointers are HIP device pointers to contiguous float64 arrays of
+ *    the grid's N = n[0]*n[1]*n[2] cells, cell (i,j,k) at i + n[0]*(j +
+ *    n[1]*k) (x fastest).  p and T are separate arrays.
+ *  - Work is ordered on the stream given to pt_mg_setup (NULL = the null
+ *    stream).  Calls return when their results are in the caller's arrays
+ *    unless stated otherwise.
+ *  - The caller owns every array it passes; the library never keeps a
+ *    caller pointer past the call.  The handle owns its device memory
+ *    until pt_mg_destroy.
+ *  - Functions return a pt_status; nothing is thrown across the ABI.  After
+ *    an error the handle stays valid; pt_mg_last_error gives a message.
+ *  - A handle must not be used by two host threads at once.
+ */
+#ifndef PT_MG_H
+#define PT_MG_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pt_mg_s *pt_mg_t;
+
+typedef enum {
+    PT_OK = 0,
+    PT_ERR_ARG = 1,       /* invalid argument (dims, h, dt, C outside [0,1], non-finite input, ...) */
+    PT_ERR_OOM = 2,       /* device allocation failed */
+    PT_ERR_SINGULAR = 3,  /* a cell block has det <= 0 or a non-positive diagonal */
+    PT_ERR_NOCONV = 4,    /* max_cycles reached, or a residual norm was not finite */
+    PT_ERR_HIP = 5,       /* HIP runtime error */
+    PT_ERR_STATE = 6      /* call not valid for this handle (wrong mode, level, ...) */
+} pt_status;
+
+typedef enum { PT_COEF_EXPLICIT = 0, PT_COEF_PHASES = 1 } pt_coef_mode;
+typedef enum { PT_PREC_FP64 = 0, PT_PREC_MIXED = 1 } pt_precision;
+
+/* Per-phase properties (SI).  beta <= 0: thermal dilation from Eq. (10),
+ * beta = (Gamma-1) c_v / ((Gamma-1) c_v T + b (p + Pi)), evaluated at the
+ * cell's (p_adv, T_adv); an ideal gas has Gamma = gamma, Pi = b = 0, which
+ * gives 1/T.  gamma = c_p/c_v and the sound speed c enter l3 (Eq. 31). */
+typedef struct {
+    double rho, k, cp, cv, c, gamma, Gamma, Pi, b, beta;
+} pt_phase;
+
+/* Problem description.  Unused fields are ignored; arrays are device
+ * pointers and are read during pt_mg_setup / pt_mg_update only. */
+typedef struct {
+    int dim;                 /* 2 or 3 */
+    int n[3];                /* cells per axis (>= 2 on active axes); n[2] = 1 in 2-D */
+    double h;                /* cell size, > 0 */
+    int mode;                /* pt_coef_mode */
+    /* PT_COEF_EXPLICIT: canonical form given directly. */
+    const double *alpha_p;   /* cell a_p [N] or NULL -> alpha_p_const */
+    const double *alpha_T;   /* cell a_T [N] or NULL -> alpha_T_const */
+    double alpha_p_const, alpha_T_const;
+    const double *B;         /* [4][N] component-major (pp, pT, Tp, TT) or NULL -> B_const */
+    double B_const[4];
+    /* PT_COEF_PHASES: paper form (Eqs. 27-34). */
+    const double *C;         /* liquid volume fraction [N], in [0, 1] */
+    pt_phase liquid, gas;    /* phase 1 = liquid (reference phase), phase 2 = gas */
+    double dt;               /* time step, > 0 */
+    const double *p_adv;     /* provisional pressure [N] or NULL -> p_adv_const */
+    const double *T_adv;     /* provisional temperature [N] or NULL -> T_adv_const */
+    double p_adv_const, T_adv_const;
+    /* Pure-Neumann Poisson limit only (every B entry zero): fix the free
+     * constant of each component by a zero mean (the right-hand side is
+     * projected to zero mean).  PT_ERR_ARG if set while B is not zero. */
+    int mean_constraint;
+} pt_problem;
+
+typedef struct {
+    double rtol;             /* stop when max_c ||res_c||/||b_c|| <= rtol (paper row form) */
+    int max_cycles;          /* V-cycles at most (<= PT_MAX_HIST - 1 recorded) */
+    int nu1, nu2;            /* pre/post red-black smoothing sweeps (0..8) */
+    int zero_guess;          /* 1: start from zero, ignoring the contents of p, T */
+} pt_solve_opts;
+
+#define PT_MAX_HIST 64
+
+typedef struct {
+    int cycles;                        /* V-cycles performed */
+    double relres[2];                  /* final (p, T) relative residual, paper row form */
+    double relres_hist[2 * PT_MAX_HIST]; /* (p, T) after 0, 1, ... cycles */
+    int hist_len;                      /* number of recorded pairs */
+    double t_solve_s;                  /* wall time of the call */
+    int status;                        /* same as the return value */
+} pt_solve_info;
+
+/* Device bytes that pt_mg_setup will allocate for this problem and
+ * precision (the handle's hierarchy, coarse inverse and work buffers).
+ * 0 if the problem is invalid.  For admission control. */
+size_t pt_mg_footprint_bytes(const pt_problem *prob, int precision);
+
+/* Assemble the operator (Sec. 3: averaging rule; Eqs. 27-32 via the
+ * canonical form above) and build the multigrid hierarchy for the given
+ * V-cycle precision (pt_precision): coarse coefficients, and the inverse
+ * of the coarsest-grid matrix in FP64.  hip_stream is a hipStream_t or
+ * NULL.  On success *out owns all device memory; on failure *out = NULL.
+ * Errors: PT_ERR_ARG, PT_ERR_OOM, PT_ERR_SINGULAR, PT_ERR_HIP. */
+int pt_mg_setup(const pt_problem *prob, int precision, void *hip_stream, pt_mg_t *out);
+
+/* Re-assemble with new coefficient fields (same dim, n, mode) into the
+ * existing handle, without allocating (one call per time step).  Errors as
+ * pt_mg_setup; on error the handle must be updated again before a solve. */
+int pt_mg_update(pt_mg_t h, const pt_problem *prob);
+
+/* Right-hand side of the paper form, Eqs. (33)-(34):
+ * b_T = l1 T_adv + l2 p_adv, b_p = l3 p_adv + div_ustar / dt, with the
+ * cell coefficients of the handle (PT_COEF_PHASES only, else
+ * PT_ERR_STATE).  p_adv / T_adv NULL -> the constants given at setup;
+ * div_ustar NULL -> zero.  Outputs b_p, b_T [N]. */
+int pt_mg_paper_rhs(pt_mg_t h, const double *p_adv, const double *T_adv,
+                    const double *div_ustar, double *b_p, double *b_T);
+
+/* Solve L(a) = b (Sec. 3, defect correction).  b is mode-native: the
+ * paper's (lp, lT) in PT_COEF_PHASES, the canonical (f_p, f_T) in
+ * PT_COEF_EXPLICIT.  p, T [N] are the initial guess on entry (unless
+ * opts->zero_guess) and the solution on return.  opts NULL -> rtol 1e-9,
+ * 50 cycles, V(2,2), zero guess.  info may be NULL.  Returns PT_OK, or
+ * PT_ERR_NOCONV with the last iterate in p, T and info filled. */
+int pt_mg_solve(pt_mg_t h, const double *b_p, const double *b_T, double *p, double *T,
+                const pt_solve_opts *opts, pt_solve_info *info);
+
+/* Residual in FP64, mode-native form: res = b - L(a) of Eqs. (27)-(28)
+ * (PT_COEF_PHASES) or f - A u (PT_COEF_EXPLICIT).  r_p, r_T [N] may be
+ * NULL.  relres (may be NULL) receives ||res_c||_2 / ||b_c||_2 for
+ * c = p, T, reduced in a fixed order (bitwise reproducible). */
+int pt_mg_residual(pt_mg_t h, const double *b_p, const double *b_T, const double *p,
+                   const double *T, double *r_p, double *r_T, double relres[2]);
+
+void pt_mg_destroy(pt_mg_t h);
+
+/* Last error message of the handle, or of the calling thread when h is
+ * NULL (errors of pt_mg_setup).  Never NULL. */
+const char *pt_mg_last_error(pt_mg_t h);
+
+/* ---------------------------------------------------------------------
+ * Multigrid steps on one level, for step-by-step comparison and
+ * measurement.  The paper cites its multigrid without details (Sec. 3);
+ * the steps are this library's: red-black 2x2-block Gauss-Seidel,
+ * residual with averaging restriction to the 2^dim children's parent,
+ * cell-centred linear prolongation, coarse coefficients by averaging the
+ * fine faces that make up a coarse face and the 2^dim children's blocks,
+ * and an exact FP64 solve on the coarsest grid.  All arrays are FP64
+ * device arrays of the level's cell count, canonical form; they are
+ * converted to and from the handle's V-cycle precision.
+ * --------------------------------------------------------------------- */
+
+/* Number of levels (finest = 0) and the grid of one level. */
+int pt_mg_num_levels(pt_mg_t h);
+int pt_mg_level_dims(pt_mg_t h, int level, int n[3], double *hl);
+
+/* The level's operator as the V-cycle uses it: faces [6][N_l] with
+ * index (component*3 + axis)*N_l + cell = coefficient of the face between
+ * the cell and its lower neighbour along the axis (0 on the boundary;
+ * axis 2 unused in 2-D), and the block [4][N_l] (pp, pT, Tp, TT). */
+int pt_mg_get_operator(pt_mg_t h, int level, double *faces, double *B);
+
+/* `sweeps` red-black sweeps in place on (u_p, u_T): cells with i+j+k even
+ * first, then odd, each solving its 2x2 block with the latest neighbours. */
+int pt_mg_smooth(pt_mg_t h, int level, const double *f_p, const double *f_T,
+                 double *u_p, double *u_T, int sweeps);
+
+/* Coarse right-hand side fc = mean over the 2^dim children of f - A u on
+ * `level`; fc has the cell count of level+1. */
+int pt_mg_restrict_residual(pt_mg_t h, int level, const double *f_p, const double *f_T,
+                            const double *u_p, const double *u_T, double *fc_p,
+                            double *fc_T);
+
+/* u += P e on `level` from e on level+1 (linear interpolation: along each
+ * axis 3/4 of the parent and 1/4 of the parent's neighbour on the fine
+ * cell's side, the parent itself at a boundary). */
+int pt_mg_prolong_add(pt_mg_t h, int level, const double *ec_p, const double *ec_T,
+                      double *u_p, double *u_T);
+
+/* Exact FP64 solve on the coarsest level: u = A^-1 f. */
+int pt_mg_coarse_solve(pt_mg_t h, const double *f_p, const double *f_T, double *u_p,
+                       double *u_T);
+
+/* One V(nu1, nu2) cycle on level 0 for A e = f from a zero guess. */
+int pt_mg_vcycle(pt_mg_t h, const double *f_p, const double *f_T, double *e_p,
+                 double *e_T, int nu1, int nu2);
+
+/* ---------------------------------------------------------------------
+ * Measurement.
+ * --------------------------------------------------------------------- */
+
+/* Kernel classes timed with HIP events when timing is on. */
+typedef enum {
+    PT_K_OUTER_RESIDUAL = 0,  /* FP64 residual (+ update) + norm partial sums, finest grid */
+    PT_K_SMOOTH_FINE = 1,     /* red-black smoother, finest grid (one launch = one sweep) */
+    PT_K_SMOOTH_COARSE = 2,   /* smoother, coarser grids */
+    PT_K_RESTRICT = 3,        /* residual + restriction, all levels */
+    PT_K_PROLONG = 4,         /* prolongation + correction, all levels */
+    PT_K_COARSE_SOLVE = 5,    /* coarsest-grid solve */
+    PT_K_OTHER = 6,           /* norm reduction, conversions, copies */
+    PT_K_COUNT = 7
+} pt_kernel_class;
+
+/* Turn per-launch event timing on or off (off by default; on adds an
+ * event pair around each launch). */
+int pt_mg_set_timing(pt_mg_t h, int on);
+
+/* Launches and summed milliseconds of one class since the last reset,
+ * plus the algorithmic bytes the launches moved (the model of each
+ * kernel: every array it must read or write once, halos excluded). */
+int pt_mg_kernel_stats(pt_mg_t h, int kernel_class, long *launches, double *ms,
+                       double *bytes);
+int pt_mg_reset_stats(pt_mg_t h);
+
+/* Cell-updates performed by the last pt_mg_solve: smoother cell updates
+ * on every level plus residual evaluations (the finest-grid FP64 one and
+ * the one inside each restriction). */
+long long pt_mg_last_cell_updates(pt_mg_t h);
+
+/* A plain device copy of `bytes` bytes on the stream (hipStream_t or
+ * NULL), for calibrating bandwidth counters.  Asynchronous. */
+int pt_copy_kernel(void *dst, const void *src, size_t bytes, void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PT_MG_H */

@@ -1,0 +1,873 @@
+// Host side of libptmg: the C ABI, handle and memory plan, assembly and
+// hierarchy set-up, the defect-correction (iterative refinement) driver and
+// the V-cycle schedule.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "ptmg_internal.h"
+
+using namespace ptmg;
+
+namespace {
+
+thread_local std::string g_thread_err = "no error";
+
+// ------------------------------------------------------------ memory plan
+struct LevelPlan {
+    int n[3];
+    long long N;
+    double h;
+    size_t o_u, o_f, o_ac, o_fx, o_fy, o_fz, o_B;
+};
+
+struct Plan {
+    int dim = 0, prec = 0, nlev = 0, m = 0, nblocks = 0;
+    int n[3] = {1, 1, 1};
+    long long N = 0;
+    LevelPlan lv[kMaxLevels];
+    size_t o_ac64, o_B64, o_xp, o_xT, o_partials, o_flags, o_norms, o_gj0, o_gj1;
+    size_t total = 0;
+    size_t take(size_t bytes)
+    {
+        size_t o = total;
+        total += (bytes + 255) & ~size_t(255);
+        return o;
+    }
+};
+
+constexpr long long kMaxCoarseCells = 2048;   // coarsest grid solved by a dense inverse
+
+// Coarsen while every active axis is even and its half is at least 4.
+bool can_coarsen(int dim, const int *n)
+{
+    for (int a = 0; a < dim; a++)
+        if (n[a] % 2 != 0 || n[a] / 2 < 4) return false;
+    return true;
+}
+
+const char *plan_problem(const pt_problem *p, int prec, Plan &P)
+{
+    if (!p) return "problem is NULL";
+    if (p->dim != 2 && p->dim != 3) return "dim must be 2 or 3";
+    if (prec != PT_PREC_FP64 && prec != PT_PREC_MIXED) return "unknown precision";
+    for (int a = 0; a < 3; a++) {
+        if (a < p->dim && p->n[a] < 2) return "n[a] must be >= 2 on active axes";
+        if (a >= p->dim && p->n[a] != 1) return "n[2] must be 1 in 2-D";
+        if (p->n[a] > (1 << 20)) return "grid too large";
+    }
+    if (!(p->h > 0.0) || !std::isfinite(p->h)) return "h must be positive";
+    if (p->mode != PT_COEF_EXPLICIT && p->mode != PT_COEF_PHASES) return "unknown mode";
+    if (p->mode == PT_COEF_PHASES) {
+        if (!p->C) return "phases mode needs C";
+        if (!(p->dt > 0.0) || !std::isfinite(p->dt)) return "dt must be positive";
+        if (p->mean_constraint) return "mean_constraint only applies to B = 0 (explicit mode)";
+        const pt_phase *ph[2] = {&p->liquid, &p->gas};
+        for (int q = 0; q < 2; q++) {
+            const pt_phase &f = *ph[q];
+            if (!(f.rho > 0) || !(f.k >= 0) || !(f.cp > 0) || !(f.c > 0) || !(f.gamma > 0))
+                return "phase properties must be positive (k >= 0)";
+            if (!(f.beta > 0) && !((f.Gamma - 1.0) * f.cv > 0))
+                return "phase needs beta > 0 or (Gamma-1) c_v > 0 for Eq. (10)";
+        }
+    }
+    P = Plan();
+    P.dim = p->dim;
+    P.prec = prec;
+    for (int a = 0; a < 3; a++) P.n[a] = p->n[a];
+    P.N = (long long)p->n[0] * p->n[1] * p->n[2];
+    const size_t R = prec == PT_PREC_MIXED ? 4 : 8;
+    // finest grid FP64 operator, FP64 ping-pong iterate
+    P.o_ac64 = P.take(16 * P.N);
+    P.o_B64 = P.take(32 * P.N);
+    P.o_xp = P.take(8 * P.N);
+    P.o_xT = P.take(8 * P.N);
+    // hierarchy
+    int n[3] = {p->n[0], p->n[1], p->n[2]};
+    double h = p->h;
+    int l = 0;
+    for (;;) {
+        LevelPlan &L = P.lv[l];
+        for (int a = 0; a < 3; a++) L.n[a] = n[a];
+        L.N = (long long)n[0] * n[1] * n[2];
+        L.h = h;
+        L.o_u = P.take(2 * R * L.N);
+        L.o_f = P.take(2 * R * L.N);
+        L.o_ac = L.o_fx = L.o_fy = L.o_fz = L.o_B = (size_t)-1;
+        if (l == 0) {
+            if (prec == PT_PREC_MIXED) {
+                L.o_ac = P.take(2 * R * L.N);
+                L.o_B = P.take(4 * R * L.N);
+            }
+        } else {
+            L.o_fx = P.take(2 * R * L.N);
+            L.o_fy = P.take(2 * R * L.N);
+            if (p->dim == 3) L.o_fz = P.take(2 * R * L.N);
+            L.o_B = P.take(4 * R * L.N);
+        }
+        if (!can_coarsen(p->dim, n) || l + 1 >= kMaxLevels) break;
+        for (int a = 0; a < p->dim; a++) n[a] /= 2;
+        h *= 2.0;
+        l++;
+    }
+    P.nlev = l + 1;
+    const long long Nc = P.lv[l].N;
+    if (Nc > kMaxCoarseCells)
+        return "grid does not coarsen to at most 2048 cells (use sizes m*2^k with m <= 7)";
+    P.m = (int)(2 * Nc);
+    P.o_gj0 = P.take(8ull * P.m * P.m);
+    P.o_gj1 = P.take(8ull * P.m * P.m);
+    P.nblocks = std::max(outer_blocks(P.N), sum2_blocks(P.N));
+    P.o_partials = P.take(8ull * (4 * (size_t)P.nblocks + 16));
+    P.o_flags = P.take(sizeof(int) * NFLAGS);
+    P.o_norms = P.take(8 * 8);
+    return nullptr;
+}
+
+struct TimerRec {
+    int cls;
+    hipEvent_t a, b;
+};
+
+}  // namespace
+
+// ------------------------------------------------------------------ handle
+struct pt_mg_s {
+    Plan P;
+    pt_problem prob;             // copy; array pointers are not kept
+    hipStream_t stream = nullptr;
+    char *base = nullptr;
+    double *norms_host = nullptr;   // pinned
+    int *flags_host = nullptr;      // pinned
+    std::string err = "no error";
+    double *Ainv = nullptr;
+    bool ready = false;
+    // measurement
+    bool timing = false;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    std::vector<TimerRec> pending;
+    long launches[PT_K_COUNT] = {0};
+    double ms[PT_K_COUNT] = {0};
+    double bytes[PT_K_COUNT] = {0};
+    long long updates = 0, last_updates = 0;
+
+    template <typename T> T *at(size_t off) { return off == (size_t)-1 ? nullptr : (T *)(base + off); }
+    double2 *ac64() { return at<double2>(P.o_ac64); }
+    double4 *B64() { return at<double4>(P.o_B64); }
+    double *partials() { return at<double>(P.o_partials); }
+    int *flags() { return at<int>(P.o_flags); }
+    double *norms_dev() { return at<double>(P.o_norms); }
+
+    template <typename R> Lvl<R> level(int l)
+    {
+        const LevelPlan &L = P.lv[l];
+        Lvl<R> o;
+        o.nx = L.n[0];
+        o.ny = L.n[1];
+        o.nz = L.n[2];
+        o.N = L.N;
+        o.inv_h2 = 1.0 / (L.h * L.h);
+        o.u = at<typename VT<R>::v2>(L.o_u);
+        o.f = at<typename VT<R>::v2>(L.o_f);
+        o.fx = at<typename VT<R>::v2>(L.o_fx);
+        o.fy = at<typename VT<R>::v2>(L.o_fy);
+        o.fz = at<typename VT<R>::v2>(L.o_fz);
+        if (l == 0 && P.prec == PT_PREC_FP64) {
+            o.ac = (const typename VT<R>::v2 *)ac64();
+            o.B = (const typename VT<R>::v4 *)B64();
+        } else {
+            o.ac = at<typename VT<R>::v2>(L.o_ac);
+            o.B = at<typename VT<R>::v4>(L.o_B);
+        }
+        return o;
+    }
+    // FP64 view of the finest-grid operator (coarsening source, exports).
+    Lvl<double> level0_fp64()
+    {
+        Lvl<double> o = level<double>(0);
+        o.u = nullptr;
+        o.f = nullptr;
+        o.ac = ac64();
+        o.B = B64();
+        return o;
+    }
+
+    // --- timing --------------------------------------------------------
+    void begin(int cls, double nbytes)
+    {
+        launches[cls]++;
+        bytes[cls] += nbytes;
+        if (!timing) return;
+        TimerRec r;
+        r.cls = cls;
+        r.a = event();
+        r.b = event();
+        (void)hipEventRecord(r.a, stream);
+        pending.push_back(r);
+    }
+    void end()
+    {
+        if (!timing) return;
+        (void)hipEventRecord(pending.back().b, stream);
+    }
+    hipEvent_t event()
+    {
+        if (ev_used == ev_pool.size()) {
+            hipEvent_t e;
+            (void)hipEventCreate(&e);
+            ev_pool.push_back(e);
+        }
+        return ev_pool[ev_used++];
+    }
+    void flush_timing()   // after the stream has been synchronised
+    {
+        for (auto &r : pending) {
+            float t = 0.f;
+            if (hipEventElapsedTime(&t, r.a, r.b) == hipSuccess) ms[r.cls] += t;
+        }
+        pending.clear();
+        ev_used = 0;
+    }
+};
+
+namespace {
+
+int fail(pt_mg_t h, int code, const std::string &msg)
+{
+    if (h) h->err = msg;
+    else g_thread_err = msg;
+    return code;
+}
+
+int check_hip(pt_mg_t h, hipError_t e, const char *what)
+{
+    if (e == hipSuccess) return PT_OK;
+    return fail(h, PT_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+int sync(pt_mg_t h, const char *what)
+{
+    hipError_t e = hipStreamSynchronize(h->stream);
+    if (e == hipSuccess) e = hipGetLastError();
+    h->flush_timing();
+    return check_hip(h, e, what);
+}
+
+// Algorithmic bytes of one kernel launch (each array read or written once).
+double bytes_sweep_half(const Plan &P, int l, bool zero_guess)
+{
+    const double R = P.prec == PT_PREC_MIXED ? 4 : 8;
+    const double N = (double)P.lv[l].N;
+    const double coef = (l == 0 ? 2 : 2 * P.dim) * R;     // cell or face coefficients
+    // one colour: reads the other colour's u, its own f and B, all coefficients
+    // (harmonic means need the neighbours'), writes its own u
+    return N * (0.5 * (zero_guess ? 0 : 2 * R) + 0.5 * 2 * R + 0.5 * 4 * R + coef + 0.5 * 2 * R);
+}
+
+template <typename R> void smooth(pt_mg_t h, int l, int sweeps, bool zero_guess)
+{
+    Lvl<R> L = h->level<R>(l);
+    const int cls = l == 0 ? PT_K_SMOOTH_FINE : PT_K_SMOOTH_COARSE;
+    for (int s = 0; s < sweeps; s++) {
+        const bool zg = zero_guess && s == 0;
+        h->begin(cls, bytes_sweep_half(h->P, l, zg));
+        launch_rb_pass<R>(h->P.dim, l == 0, L, 0, zg ? 1 : 0, h->stream);
+        h->end();
+        h->begin(cls, bytes_sweep_half(h->P, l, false));
+        launch_rb_pass<R>(h->P.dim, l == 0, L, 1, 0, h->stream);
+        h->end();
+        h->updates += L.N;
+    }
+}
+
+template <typename R> void restrict_level(pt_mg_t h, int l)
+{
+    Lvl<R> F = h->level<R>(l), C = h->level<R>(l + 1);
+    const double Rb = sizeof(R);
+    const double coef = (l == 0 ? 2 : 2 * h->P.dim) * Rb;
+    h->begin(PT_K_RESTRICT, (double)F.N * (8 * Rb + coef) + (double)C.N * 2 * Rb);
+    launch_restrict<R>(h->P.dim, l == 0, F, C, h->stream);
+    h->end();
+    h->updates += F.N;
+}
+
+template <typename R> void prolong_level(pt_mg_t h, int l)
+{
+    Lvl<R> F = h->level<R>(l), C = h->level<R>(l + 1);
+    const double Rb = sizeof(R);
+    h->begin(PT_K_PROLONG, (double)F.N * 4 * Rb + (double)C.N * 2 * Rb);
+    launch_prolong<R>(h->P.dim, F, C, h->stream);
+    h->end();
+}
+
+template <typename R> void coarse_solve(pt_mg_t h)
+{
+    Lvl<R> L = h->level<R>(h->P.nlev - 1);
+    const int m = h->P.m;
+    h->begin(PT_K_COARSE_SOLVE, 8.0 * m * m + 2.0 * m * sizeof(R));
+    launch_coarse_apply<R>(h->Ainv, m, (const R *)L.f, (R *)L.u, h->stream);
+    h->end();
+}
+
+// V(nu1, nu2) cycle on level l for A e = f_l, e in u_l, from a zero guess.
+template <typename R> void vcycle(pt_mg_t h, int l, int nu1, int nu2)
+{
+    if (l == h->P.nlev - 1) {
+        coarse_solve<R>(h);
+        return;
+    }
+    Lvl<R> L = h->level<R>(l);
+    if (nu1 == 0) {
+        h->begin(PT_K_OTHER, (double)L.N * 2 * sizeof(R));
+        launch_zero(L.u, (size_t)L.N * 2 * sizeof(R), h->stream);
+        h->end();
+    }
+    smooth<R>(h, l, nu1, true);
+    restrict_level<R>(h, l);
+    vcycle<R>(h, l + 1, nu1, nu2);
+    prolong_level<R>(h, l);
+    smooth<R>(h, l, nu2, false);
+}
+
+void vcycle_any(pt_mg_t h, int nu1, int nu2)
+{
+    if (h->P.prec == PT_PREC_MIXED) vcycle<float>(h, 0, nu1, nu2);
+    else vcycle<double>(h, 0, nu1, nu2);
+}
+
+// ---- assembly + hierarchy + coarsest inverse --------------------------
+template <typename R> void build_hierarchy(pt_mg_t h)
+{
+    const Plan &P = h->P;
+    if (P.nlev > 1) {
+        Lvl<R> c1 = h->level<R>(1);
+        launch_coarsen<double, R>(P.dim, 1, h->level0_fp64(), (typename VT<R>::v2 *)c1.fx,
+                                  (typename VT<R>::v2 *)c1.fy, (typename VT<R>::v2 *)c1.fz,
+                                  (typename VT<R>::v4 *)c1.B, h->stream);
+        for (int l = 1; l + 1 < P.nlev; l++) {
+            Lvl<R> f = h->level<R>(l), c = h->level<R>(l + 1);
+            launch_coarsen<R, R>(P.dim, 0, f, (typename VT<R>::v2 *)c.fx,
+                                 (typename VT<R>::v2 *)c.fy, (typename VT<R>::v2 *)c.fz,
+                                 (typename VT<R>::v4 *)c.B, h->stream);
+        }
+    }
+    // dense coarsest matrix, inverted by Gauss-Jordan
+    double *M0 = h->at<double>(P.o_gj0), *M1 = h->at<double>(P.o_gj1);
+    const int pin = h->prob.mean_constraint ? 1 : 0;
+    if (P.nlev == 1)
+        launch_coarse_dense<double>(P.dim, 1, h->level0_fp64(), pin, M0, h->stream);
+    else
+        launch_coarse_dense<R>(P.dim, 0, h->level<R>(P.nlev - 1), pin, M0, h->stream);
+    double *src = M0, *dst = M1;
+    for (int k = 0; k < P.m; k++) {
+        launch_gj_step(src, dst, P.m, k, h->flags(), h->stream);
+        std::swap(src, dst);
+    }
+    h->Ainv = src;
+}
+
+int assemble(pt_mg_t h, const pt_problem *p)
+{
+    const Plan &P = h->P;
+    AsmArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.N = P.N;
+    a.mode = p->mode;
+    a.alpha_p = p->alpha_p;
+    a.alpha_T = p->alpha_T;
+    a.alpha_p_const = p->alpha_p_const;
+    a.alpha_T_const = p->alpha_T_const;
+    a.B = p->B;
+    for (int q = 0; q < 4; q++) a.B_const[q] = p->B_const[q];
+    a.C = p->C;
+    a.liq = p->liquid;
+    a.gas = p->gas;
+    a.dt = p->dt;
+    a.p_adv = p->p_adv;
+    a.T_adv = p->T_adv;
+    a.p_adv_const = p->p_adv_const;
+    a.T_adv_const = p->T_adv_const;
+    a.ac64 = h->ac64();
+    a.B64 = h->B64();
+    if (P.prec == PT_PREC_MIXED) {
+        a.ac32 = h->at<float2>(P.lv[0].o_ac);
+        a.B32 = h->at<float4>(P.lv[0].o_B);
+    }
+    a.flags = h->flags();
+    h->ready = false;
+    // the handle keeps the scalars of the problem (not its array pointers)
+    h->prob = *p;
+    h->prob.alpha_p = h->prob.alpha_T = h->prob.B = h->prob.C = h->prob.p_adv = h->prob.T_adv = nullptr;
+    launch_zero(h->flags(), sizeof(int) * NFLAGS, h->stream);
+    launch_assemble(a, h->stream);
+    if (P.prec == PT_PREC_MIXED) build_hierarchy<float>(h);
+    else build_hierarchy<double>(h);
+    hipError_t e = hipMemcpyAsync(h->flags_host, h->flags(), sizeof(int) * NFLAGS,
+                                  hipMemcpyDeviceToHost, h->stream);
+    if (e != hipSuccess) return check_hip(h, e, "setup copy");
+    int rc = sync(h, "setup");
+    if (rc) return rc;
+    const int *f = h->flags_host;
+    if (f[FLAG_ARG]) return fail(h, PT_ERR_ARG, "invalid input field (C outside [0,1], non-finite value, T <= 0 or negative coefficient)");
+    if (p->mean_constraint) {
+        if (f[FLAG_BNONZERO]) return fail(h, PT_ERR_ARG, "mean_constraint requires B = 0 everywhere");
+    } else if (f[FLAG_SINGULAR]) {
+        return fail(h, PT_ERR_SINGULAR, "a cell block has det <= 0 or a non-positive diagonal");
+    }
+    if (f[FLAG_PIVOT]) return fail(h, PT_ERR_SINGULAR, "coarsest-grid elimination met a non-positive pivot");
+    h->ready = true;
+    return PT_OK;
+}
+
+bool same_grid(const pt_problem *a, const pt_problem *b)
+{
+    return a->dim == b->dim && a->n[0] == b->n[0] && a->n[1] == b->n[1] && a->n[2] == b->n[2] &&
+           a->h == b->h && a->mode == b->mode && a->mean_constraint == b->mean_constraint;
+}
+
+double elapsed(std::chrono::steady_clock::time_point t0)
+{
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
+}  // namespace
+
+// ================================================================== C ABI
+// (the declarations in pt_mg.h give these definitions C linkage)
+
+size_t pt_mg_footprint_bytes(const pt_problem *prob, int precision)
+{
+    Plan P;
+    if (plan_problem(prob, precision, P)) return 0;
+    return P.total;
+}
+
+int pt_mg_setup(const pt_problem *prob, int precision, void *hip_stream, pt_mg_t *out)
+{
+    if (!out) return fail(nullptr, PT_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    Plan P;
+    if (const char *why = plan_problem(prob, precision, P)) return fail(nullptr, PT_ERR_ARG, why);
+    pt_mg_t h = new pt_mg_s();
+    h->P = P;
+    h->stream = (hipStream_t)hip_stream;
+    hipError_t e = hipMalloc(&h->base, P.total);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        delete h;
+        return fail(nullptr, PT_ERR_OOM, "hipMalloc of " + std::to_string(P.total) + " bytes failed");
+    }
+    e = hipHostMalloc(&h->norms_host, 16 * sizeof(double), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc(&h->flags_host, 16 * sizeof(int), hipHostMallocDefault);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        pt_mg_destroy(h);
+        return fail(nullptr, PT_ERR_OOM, "pinned host allocation failed");
+    }
+    int rc = assemble(h, prob);
+    if (rc != PT_OK) {
+        g_thread_err = h->err;
+        pt_mg_destroy(h);
+        return rc;
+    }
+    *out = h;
+    return PT_OK;
+}
+
+int pt_mg_update(pt_mg_t h, const pt_problem *prob)
+{
+    if (!h) return fail(nullptr, PT_ERR_ARG, "handle is NULL");
+    Plan P;
+    if (const char *why = plan_problem(prob, h->P.prec, P)) return fail(h, PT_ERR_ARG, why);
+    if (!same_grid(prob, &h->prob))
+        return fail(h, PT_ERR_STATE, "update must keep dim, n, h, mode and mean_constraint");
+    if (P.total != h->P.total) return fail(h, PT_ERR_STATE, "update changes the memory plan");
+    return assemble(h, prob);
+}
+
+void pt_mg_destroy(pt_mg_t h)
+{
+    if (!h) return;
+    if (h->stream || h->base) (void)hipStreamSynchronize(h->stream);
+    for (auto e : h->ev_pool) (void)hipEventDestroy(e);
+    if (h->base) (void)hipFree(h->base);
+    if (h->norms_host) (void)hipHostFree(h->norms_host);
+    if (h->flags_host) (void)hipHostFree(h->flags_host);
+    delete h;
+}
+
+const char *pt_mg_last_error(pt_mg_t h) { return h ? h->err.c_str() : g_thread_err.c_str(); }
+
+int pt_mg_paper_rhs(pt_mg_t h, const double *p_adv, const double *T_adv, const double *div_ustar,
+                    double *b_p, double *b_T)
+{
+    if (!h || !h->ready) return fail(h, PT_ERR_STATE, "handle not ready");
+    if (h->prob.mode != PT_COEF_PHASES) return fail(h, PT_ERR_STATE, "paper_rhs needs phases mode");
+    if (!b_p || !b_T) return fail(h, PT_ERR_ARG, "outputs are NULL");
+    h->begin(PT_K_OTHER, 48.0 * h->P.N);
+    launch_paper_rhs(h->P.N, h->B64(), p_adv, h->prob.p_adv_const, T_adv, h->prob.T_adv_const,
+                     div_ustar, h->prob.dt, b_p, b_T, h->stream);
+    h->end();
+    return sync(h, "paper_rhs");
+}
+
+namespace {
+
+// Outer residual on the finest grid; returns blocks of partial sums.
+template <typename RV>
+int outer(pt_mg_t h, const double *b_p, const double *b_T, const double *src_p,
+          const double *src_T, double *dst_p, double *dst_T, bool update, bool want_r,
+          double *res_p, double *res_T, const double *bshift)
+{
+    const Plan &P = h->P;
+    OuterArgs<RV> a;
+    a.nx = P.n[0];
+    a.ny = P.n[1];
+    a.nz = P.n[2];
+    a.N = P.N;
+    a.inv_h2 = 1.0 / (h->prob.h * h->prob.h);
+    a.phases = h->prob.mode == PT_COEF_PHASES;
+    a.ac = h->ac64();
+    a.B = h->B64();
+    a.b_p = b_p;
+    a.b_T = b_T;
+    a.bshift = bshift;
+    a.bshift_scale = 1.0 / (double)P.N;
+    a.src_p = src_p;
+    a.src_T = src_T;
+    a.dst_p = dst_p;
+    a.dst_T = dst_T;
+    a.du = h->at<typename VT<RV>::v2>(P.lv[0].o_u);
+    a.r = want_r ? h->at<typename VT<RV>::v2>(P.lv[0].o_f) : nullptr;
+    a.res_p = res_p;
+    a.res_T = res_T;
+    a.partials = h->partials();
+    a.update = update ? 1 : 0;
+    const double Rb = sizeof(RV);
+    double nbytes = (double)P.N * (16 + 16 + 32 + 16);
+    if (update) nbytes += (double)P.N * (2 * Rb + 16);
+    if (want_r) nbytes += (double)P.N * 2 * Rb;
+    if (res_p) nbytes += 8.0 * P.N;
+    if (res_T) nbytes += 8.0 * P.N;
+    h->begin(PT_K_OUTER_RESIDUAL, nbytes);
+    int nb = launch_outer<RV>(P.dim, a, h->stream);
+    h->end();
+    h->updates += P.N;
+    return nb;
+}
+
+int outer_any(pt_mg_t h, const double *b_p, const double *b_T, const double *src_p,
+              const double *src_T, double *dst_p, double *dst_T, bool update, bool want_r,
+              double *res_p, double *res_T, const double *bshift)
+{
+    if (h->P.prec == PT_PREC_MIXED)
+        return outer<float>(h, b_p, b_T, src_p, src_T, dst_p, dst_T, update, want_r, res_p, res_T,
+                            bshift);
+    return outer<double>(h, b_p, b_T, src_p, src_T, dst_p, dst_T, update, want_r, res_p, res_T,
+                         bshift);
+}
+
+// Reduce the partial sums to 4 doubles and bring them to the host (sync).
+int read_norms(pt_mg_t h, int nb, double out[4])
+{
+    h->begin(PT_K_OTHER, 32.0 * nb);
+    launch_reduce4(h->partials(), nb, h->norms_dev(), h->stream);
+    h->end();
+    hipError_t e = hipMemcpyAsync(h->norms_host, h->norms_dev(), 4 * sizeof(double),
+                                  hipMemcpyDeviceToHost, h->stream);
+    if (e != hipSuccess) return check_hip(h, e, "norm copy");
+    int rc = sync(h, "residual");
+    if (rc) return rc;
+    for (int q = 0; q < 4; q++) out[q] = h->norms_host[q];
+    return PT_OK;
+}
+
+// Sums of (x, y) over the grid (mean constraint), in fixed order; `slot`
+// 0 or 1 selects one of two result pairs kept after the partial sums.
+double *grid_sums(pt_mg_t h, const double *x, const double *y, int slot)
+{
+    const int nb = sum2_blocks(h->P.N);
+    double *part = h->partials();
+    double *out = part + 4ll * h->P.nblocks + 8 + 2 * slot;
+    h->begin(PT_K_OTHER, 16.0 * h->P.N);
+    launch_sum2(h->P.N, x, y, part, nb, out, h->stream);
+    h->end();
+    return out;
+}
+
+}  // namespace
+
+int pt_mg_residual(pt_mg_t h, const double *b_p, const double *b_T, const double *p, const double *T,
+                   double *r_p, double *r_T, double relres[2])
+{
+    if (!h || !h->ready) return fail(h, PT_ERR_STATE, "handle not ready");
+    if (!b_p || !b_T || !p || !T) return fail(h, PT_ERR_ARG, "NULL field");
+    int nb = outer_any(h, b_p, b_T, p, T, nullptr, nullptr, false, false, r_p, r_T, nullptr);
+    double s[4];
+    int rc = read_norms(h, nb, s);
+    if (rc) return rc;
+    if (relres) {
+        relres[0] = s[2] > 0 ? std::sqrt(s[0] / s[2]) : std::sqrt(s[0]);
+        relres[1] = s[3] > 0 ? std::sqrt(s[1] / s[3]) : std::sqrt(s[1]);
+    }
+    return PT_OK;
+}
+
+int pt_mg_solve(pt_mg_t h, const double *b_p, const double *b_T, double *p, double *T,
+                const pt_solve_opts *opts_in, pt_solve_info *info)
+{
+    auto t0 = std::chrono::steady_clock::now();
+    if (!h || !h->ready) return fail(h, PT_ERR_STATE, "handle not ready");
+    if (!b_p || !b_T || !p || !T) return fail(h, PT_ERR_ARG, "NULL field");
+    pt_solve_opts o = {1e-9, 50, 2, 2, 1};
+    if (opts_in) o = *opts_in;
+    if (!(o.rtol >= 0) || o.max_cycles < 0 || o.nu1 < 0 || o.nu2 < 0 || o.nu1 > 8 || o.nu2 > 8 ||
+        o.nu1 + o.nu2 == 0)
+        return fail(h, PT_ERR_ARG, "bad solve options");
+    const Plan &P = h->P;
+    h->updates = 0;
+    pt_solve_info inf;
+    std::memset(&inf, 0, sizeof inf);
+    if (o.zero_guess) {
+        h->begin(PT_K_OTHER, 16.0 * P.N);
+        launch_zero(p, 8 * (size_t)P.N, h->stream);
+        launch_zero(T, 8 * (size_t)P.N, h->stream);
+        h->end();
+    }
+    // mean constraint: the right-hand side is used with its mean removed
+    const double *bshift = h->prob.mean_constraint ? grid_sums(h, b_p, b_T, 0) : nullptr;
+    double *X[2] = {h->at<double>(P.o_xp), h->at<double>(P.o_xT)};
+    const double *cur_p = p, *cur_T = T;
+    bool in_caller = true;
+    int status = PT_ERR_NOCONV;
+    int cycles = 0;
+    for (;;) {
+        const bool update = cycles > 0;
+        double *dp = nullptr, *dT = nullptr;
+        if (update) {
+            dp = in_caller ? X[0] : p;
+            dT = in_caller ? X[1] : T;
+        }
+        int nb = outer_any(h, b_p, b_T, cur_p, cur_T, dp, dT, update, true, nullptr, nullptr,
+                           bshift);
+        if (update) {
+            cur_p = dp;
+            cur_T = dT;
+            in_caller = !in_caller;
+        }
+        double s[4];
+        int rc = read_norms(h, nb, s);
+        if (rc) return rc;
+        double rel[2] = {s[2] > 0 ? std::sqrt(s[0] / s[2]) : std::sqrt(s[0]),
+                         s[3] > 0 ? std::sqrt(s[1] / s[3]) : std::sqrt(s[1])};
+        if (inf.hist_len < PT_MAX_HIST) {
+            inf.relres_hist[2 * inf.hist_len] = rel[0];
+            inf.relres_hist[2 * inf.hist_len + 1] = rel[1];
+            inf.hist_len++;
+        }
+        inf.relres[0] = rel[0];
+        inf.relres[1] = rel[1];
+        if (!std::isfinite(rel[0]) || !std::isfinite(rel[1])) {
+            status = PT_ERR_NOCONV;
+            h->err = "residual norm is not finite";
+            break;
+        }
+        if (rel[0] <= o.rtol && rel[1] <= o.rtol) {
+            status = PT_OK;
+            break;
+        }
+        if (cycles >= o.max_cycles) {
+            status = PT_ERR_NOCONV;
+            h->err = "max_cycles reached";
+            break;
+        }
+        vcycle_any(h, o.nu1, o.nu2);
+        cycles++;
+    }
+    if (!in_caller) {
+        h->begin(PT_K_OTHER, 32.0 * P.N);
+        launch_convert<double, double>(P.N, cur_p, p, h->stream);
+        launch_convert<double, double>(P.N, cur_T, T, h->stream);
+        h->end();
+    }
+    if (h->prob.mean_constraint) {
+        double *us = grid_sums(h, p, T, 1);
+        launch_shift2(P.N, p, T, us, 1.0 / (double)P.N, h->stream);
+    }
+    int rc = sync(h, "solve");
+    if (rc) return rc;
+    h->last_updates = h->updates;
+    inf.cycles = cycles;
+    inf.t_solve_s = elapsed(t0);
+    inf.status = status;
+    if (info) *info = inf;
+    return status;
+}
+
+// ---------------------------------------------------------- step entries
+int pt_mg_num_levels(pt_mg_t h) { return h ? h->P.nlev : 0; }
+
+int pt_mg_level_dims(pt_mg_t h, int level, int n[3], double *hl)
+{
+    if (!h) return fail(nullptr, PT_ERR_ARG, "handle is NULL");
+    if (level < 0 || level >= h->P.nlev) return fail(h, PT_ERR_ARG, "level out of range");
+    for (int a = 0; a < 3; a++) n[a] = h->P.lv[level].n[a];
+    if (hl) *hl = h->P.lv[level].h;
+    return PT_OK;
+}
+
+namespace {
+template <typename R> void export_level(pt_mg_t h, int level, double *faces, double *B)
+{
+    if (level == 0)
+        launch_export_op<double>(h->P.dim, 1, h->level0_fp64(), faces, B, h->stream);
+    else
+        launch_export_op<R>(h->P.dim, 0, h->level<R>(level), faces, B, h->stream);
+}
+}  // namespace
+
+int pt_mg_get_operator(pt_mg_t h, int level, double *faces, double *B)
+{
+    if (!h || !h->ready) return fail(h, PT_ERR_STATE, "handle not ready");
+    if (level < 0 || level >= h->P.nlev) return fail(h, PT_ERR_ARG, "level out of range");
+    if (!faces || !B) return fail(h, PT_ERR_ARG, "NULL output");
+    if (h->P.prec == PT_PREC_MIXED) export_level<float>(h, level, faces, B);
+    else export_level<double>(h, level, faces, B);
+    return sync(h, "get_operator");
+}
+
+namespace {
+template <typename R> void pack_lv(pt_mg_t h, int l, bool f, const double *x, const double *y)
+{
+    Lvl<R> L = h->level<R>(l);
+    launch_pack<R>(L.N, x, y, f ? L.f : L.u, h->stream);
+}
+template <typename R> void unpack_lv(pt_mg_t h, int l, bool f, double *x, double *y)
+{
+    Lvl<R> L = h->level<R>(l);
+    launch_unpack<R>(L.N, f ? L.f : L.u, x, y, h->stream);
+}
+}  // namespace
+
+#define PT_DISPATCH(h, CALL)                                    \
+    do {                                                        \
+        if ((h)->P.prec == PT_PREC_MIXED) { using R = float; CALL; } \
+        else { using R = double; CALL; }                        \
+    } while (0)
+
+int pt_mg_smooth(pt_mg_t h, int level, const double *f_p, const double *f_T, double *u_p,
+                 double *u_T, int sweeps)
+{
+    if (!h || !h->ready) return fail(h, PT_ERR_STATE, "handle not ready");
+    if (level < 0 || level >= h->P.nlev) return fail(h, PT_ERR_ARG, "level out of range");
+    if (sweeps < 0 || !f_p || !f_T || !u_p || !u_T) return fail(h, PT_ERR_ARG, "bad arguments");
+    PT_DISPATCH(h, {
+        pack_lv<R>(h, level, true, f_p, f_T);
+        pack_lv<R>(h, level, false, u_p, u_T);
+        smooth<R>(h, level, sweeps, false);
+        unpack_lv<R>(h, level, false, u_p, u_T);
+    });
+    return sync(h, "smooth");
+}
+
+int pt_mg_restrict_residual(pt_mg_t h, int level, const double *f_p, const double *f_T,
+                            const double *u_p, const double *u_T, double *fc_p, double *fc_T)
+{
+    if (!h || !h->ready) return fail(h, PT_ERR_STATE, "handle not ready");
+    if (level < 0 || level + 1 >= h->P.nlev) return fail(h, PT_ERR_ARG, "level out of range");
+    if (!f_p || !f_T || !u_p || !u_T || !fc_p || !fc_T) return fail(h, PT_ERR_ARG, "NULL field");
+    PT_DISPATCH(h, {
+        pack_lv<R>(h, level, true, f_p, f_T);
+        pack_lv<R>(h, level, false, u_p, u_T);
+        restrict_level<R>(h, level);
+        unpack_lv<R>(h, level + 1, true, fc_p, fc_T);
+    });
+    return sync(h, "restrict_residual");
+}
+
+int pt_mg_prolong_add(pt_mg_t h, int level, const double *ec_p, const double *ec_T, double *u_p,
+                      double *u_T)
+{
+    if (!h || !h->ready) return fail(h, PT_ERR_STATE, "handle not ready");
+    if (level < 0 || level + 1 >= h->P.nlev) return fail(h, PT_ERR_ARG, "level out of range");
+    if (!ec_p || !ec_T || !u_p || !u_T) return fail(h, PT_ERR_ARG, "NULL field");
+    PT_DISPATCH(h, {
+        pack_lv<R>(h, level + 1, false, ec_p, ec_T);
+        pack_lv<R>(h, level, false, u_p, u_T);
+        prolong_level<R>(h, level);
+        unpack_lv<R>(h, level, false, u_p, u_T);
+    });
+    return sync(h, "prolong_add");
+}
+
+int pt_mg_coarse_solve(pt_mg_t h, const double *f_p, const double *f_T, double *u_p, double *u_T)
+{
+    if (!h || !h->ready) return fail(h, PT_ERR_STATE, "handle not ready");
+    if (!f_p || !f_T || !u_p || !u_T) return fail(h, PT_ERR_ARG, "NULL field");
+    const int l = h->P.nlev - 1;
+    PT_DISPATCH(h, {
+        pack_lv<R>(h, l, true, f_p, f_T);
+        coarse_solve<R>(h);
+        unpack_lv<R>(h, l, false, u_p, u_T);
+    });
+    return sync(h, "coarse_solve");
+}
+
+int pt_mg_vcycle(pt_mg_t h, const double *f_p, const double *f_T, double *e_p, double *e_T, int nu1,
+                 int nu2)
+{
+    if (!h || !h->ready) return fail(h, PT_ERR_STATE, "handle not ready");
+    if (!f_p || !f_T || !e_p || !e_T || nu1 < 0 || nu2 < 0 || nu1 > 8 || nu2 > 8)
+        return fail(h, PT_ERR_ARG, "bad arguments");
+    PT_DISPATCH(h, {
+        pack_lv<R>(h, 0, true, f_p, f_T);
+        vcycle<R>(h, 0, nu1, nu2);
+        unpack_lv<R>(h, 0, false, e_p, e_T);
+    });
+    return sync(h, "vcycle");
+}
+
+// ------------------------------------------------------------ measurement
+int pt_mg_set_timing(pt_mg_t h, int on)
+{
+    if (!h) return fail(nullptr, PT_ERR_ARG, "handle is NULL");
+    h->timing = on != 0;
+    return PT_OK;
+}
+
+int pt_mg_kernel_stats(pt_mg_t h, int cls, long *launches, double *ms, double *bytes)
+{
+    if (!h) return fail(nullptr, PT_ERR_ARG, "handle is NULL");
+    if (cls < 0 || cls >= PT_K_COUNT) return fail(h, PT_ERR_ARG, "kernel class out of range");
+    if (launches) *launches = h->launches[cls];
+    if (ms) *ms = h->ms[cls];
+    if (bytes) *bytes = h->bytes[cls];
+    return PT_OK;
+}
+
+int pt_mg_reset_stats(pt_mg_t h)
+{
+    if (!h) return fail(nullptr, PT_ERR_ARG, "handle is NULL");
+    for (int c = 0; c < PT_K_COUNT; c++) {
+        h->launches[c] = 0;
+        h->ms[c] = 0;
+        h->bytes[c] = 0;
+    }
+    return PT_OK;
+}
+
+long long pt_mg_last_cell_updates(pt_mg_t h) { return h ? h->last_updates : 0; }
+
+int pt_copy_kernel(void *dst, const void *src, size_t bytes, void *hip_stream)
+{
+    if ((!dst || !src) && bytes) return fail(nullptr, PT_ERR_ARG, "NULL pointer");
+    launch_copy(dst, src, bytes, (hipStream_t)hip_stream);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(nullptr, PT_ERR_HIP, hipGetErrorString(e));
+    return PT_OK;
+}

@@ -1,0 +1,125 @@
+// Internal declarations shared by the kernels and the host driver of libptmg.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pt_mg.h"
+
+namespace ptmg {
+
+// Vector types of one precision: a (p, T) pair and a 2x2 block.
+template <typename R> struct VT;
+template <> struct VT<float> { using v2 = float2; using v4 = float4; };
+template <> struct VT<double> { using v2 = double2; using v4 = double4; };
+
+// One grid level as the kernels see it.  Level 0 stores cell coefficients
+// (faces are their harmonic means); coarser levels store face coefficients
+// (lower face of each cell, 0 on the boundary).  Coefficients are
+// unscaled; kernels multiply by inv_h2.
+template <typename R> struct Lvl {
+    int nx, ny, nz;
+    long long N;
+    double inv_h2;
+    const typename VT<R>::v2 *ac;              // cell (a_p, a_T), level 0 only
+    const typename VT<R>::v2 *fx, *fy, *fz;    // faces, coarse levels only
+    const typename VT<R>::v4 *B;               // block (pp, pT, Tp, TT)
+    typename VT<R>::v2 *u;                     // unknowns (p, T)
+    typename VT<R>::v2 *f;                     // right-hand side (p, T)
+};
+
+// Outer FP64 residual arguments (finest grid).
+template <typename RV> struct OuterArgs {
+    int nx, ny, nz;
+    long long N;
+    double inv_h2;
+    int phases;                    // 1: paper form (b = (lp, lT)), 0: canonical
+    const double2 *ac;             // FP64 cell coefficients
+    const double4 *B;              // FP64 block
+    const double *b_p, *b_T;       // mode-native right-hand side
+    const double *bshift;          // [2] sums of b (mean constraint) or null
+    double bshift_scale;           // b -= bshift_scale * bshift (1/N: the mean)
+    const double *src_p, *src_T;   // current iterate
+    double *dst_p, *dst_T;         // updated iterate (update = 1)
+    const typename VT<RV>::v2 *du; // correction of the last V-cycle (update = 1)
+    typename VT<RV>::v2 *r;        // canonical residual out (V-cycle RHS) or null
+    double *res_p, *res_T;         // mode-native residual out or null
+    double *partials;              // [4 * gridDim.x]: sum res_p^2, res_T^2, b_p^2, b_T^2
+    int update;
+};
+
+struct AsmArgs {
+    long long N;
+    int mode;
+    // explicit
+    const double *alpha_p, *alpha_T;
+    double alpha_p_const, alpha_T_const;
+    const double *B;
+    double B_const[4];
+    // phases
+    const double *C;
+    pt_phase liq, gas;
+    double dt;
+    const double *p_adv, *T_adv;
+    double p_adv_const, T_adv_const;
+    // outputs
+    double2 *ac64;
+    double4 *B64;
+    float2 *ac32;   // may be null
+    float4 *B32;    // may be null
+    int *flags;     // [0] argument errors, [1] singular blocks, [2] nonzero B
+};
+
+enum { FLAG_ARG = 0, FLAG_SINGULAR = 1, FLAG_BNONZERO = 2, FLAG_PIVOT = 3, NFLAGS = 4 };
+
+constexpr int kBlock = 256;
+constexpr int kMaxLevels = 24;
+
+// ---- launch wrappers (implemented in ptmg_kernels.hip) --------------------
+void launch_assemble(const AsmArgs &a, hipStream_t s);
+void launch_paper_rhs(long long N, const double4 *B64, const double *p_adv, double p_const,
+                      const double *T_adv, double T_const, const double *div, double dt,
+                      double *b_p, double *b_T, hipStream_t s);
+
+template <typename RV>
+int launch_outer(int dim, const OuterArgs<RV> &a, hipStream_t s);   // returns #blocks
+int outer_blocks(long long N);
+void launch_reduce4(const double *partials, int nblocks, double *out4, hipStream_t s);
+void launch_sum2(long long N, const double *x, const double *y, double *partials, int nblocks,
+                 double *out2, hipStream_t s);   // out2 = (sum x, sum y), fixed order
+int sum2_blocks(long long N);
+void launch_shift2(long long N, double *x, double *y, const double *mean2, double scale,
+                   hipStream_t s);  // x -= scale*sum2[0], y -= scale*sum2[1]
+
+template <typename R>
+void launch_rb_pass(int dim, int level0, const Lvl<R> &L, int color, int zero_guess,
+                    hipStream_t s);
+template <typename R>
+void launch_restrict(int dim, int level0, const Lvl<R> &F, const Lvl<R> &C, hipStream_t s);
+template <typename R>
+void launch_prolong(int dim, const Lvl<R> &F, const Lvl<R> &C, hipStream_t s);
+template <typename RIN, typename ROUT>
+void launch_coarsen(int dim, int level0, const Lvl<RIN> &F, typename VT<ROUT>::v2 *fx,
+                    typename VT<ROUT>::v2 *fy, typename VT<ROUT>::v2 *fz,
+                    typename VT<ROUT>::v4 *B, hipStream_t s);
+template <typename R>
+void launch_coarse_dense(int dim, int level0, const Lvl<R> &L, int pin_mean, double *M,
+                         hipStream_t s);
+void launch_gj_step(const double *A, double *Bm, int m, int k, int *flags, hipStream_t s);
+template <typename R>
+void launch_coarse_apply(const double *Ainv, int m, const R *f, R *u, hipStream_t s);
+template <typename R>
+void launch_export_op(int dim, int level0, const Lvl<R> &L, double *faces, double *B,
+                      hipStream_t s);
+template <typename R>
+void launch_pack(long long N, const double *p, const double *T, typename VT<R>::v2 *out,
+                 hipStream_t s);
+template <typename R>
+void launch_unpack(long long N, const typename VT<R>::v2 *in, double *p, double *T,
+                   hipStream_t s);
+template <typename RIN, typename ROUT>
+void launch_convert(long long n, const RIN *in, ROUT *out, hipStream_t s);
+void launch_copy(void *dst, const void *src, size_t bytes, hipStream_t s);
+void launch_zero(void *p, size_t bytes, hipStream_t s);
+
+}  // namespace ptmg

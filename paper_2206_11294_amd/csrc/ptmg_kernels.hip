@@ -1,0 +1,911 @@
+// HIP kernels of libptmg (gfx950, wave64).
+//
+// Grid conventions: cell (i, j, k) at i + nx*(j + ny*k); 2-D grids have
+// nz = 1.  Unknowns and right-hand sides of the V-cycle are interleaved
+// (p, T) pairs; the caller's FP64 fields are separate p and T arrays.
+//
+// The operator is the canonical form of the paper's coupled system
+// (Eqs. 27-28 after the row operations T-row := -Eq. 27,
+// p-row := -(Eq. 28 - l4 Eq. 27)):
+//   (A u)_c = sum_faces w_c (u_c,cell - u_c,nbr) + (B u)_c,   w = a_face / h^2,
+// with zero flux through boundary faces.
+#include "ptmg_internal.h"
+
+namespace ptmg {
+
+// ---------------------------------------------------------------- helpers
+template <typename R>
+__device__ __forceinline__ R harm(R a, R b)
+{
+    R s = a + b;
+    return s > R(0) ? R(2) * a * b / s : R(0);
+}
+
+template <typename V2>
+__device__ __forceinline__ V2 harm2(V2 a, V2 b)
+{
+    V2 o;
+    o.x = harm(a.x, b.x);
+    o.y = harm(a.y, b.y);
+    return o;
+}
+
+__device__ __forceinline__ void decode(long long t, int nx, int ny, int &i, int &j, int &k)
+{
+    i = (int)(t % nx);
+    long long r = t / nx;
+    j = (int)(r % ny);
+    k = (int)(r / ny);
+}
+
+// Face coefficient (unscaled) between cell `me` and neighbour `q` along
+// `axis`; `upper` when q is the upper neighbour.
+template <typename R, bool CF>
+__device__ __forceinline__ typename VT<R>::v2 face_coef(const Lvl<R> &L,
+                                                        typename VT<R>::v2 am, long long me,
+                                                        long long q, int axis, bool upper)
+{
+    if (CF) return harm2(am, L.ac[q]);
+    const typename VT<R>::v2 *F = axis == 0 ? L.fx : (axis == 1 ? L.fy : L.fz);
+    return upper ? F[q] : F[me];
+}
+
+// Sums over the faces of cell (i,j,k): S = sum w, nb = sum w u_nbr (when
+// USE_U), per component.  Face order: x-, x+, y-, y+, z-, z+.
+template <typename R, int DIM, bool CF, bool USE_U>
+__device__ __forceinline__ void gather(const Lvl<R> &L, int i, int j, int k, long long me,
+                                       R &nbp, R &nbT, R &Sp, R &ST)
+{
+    using V2 = typename VT<R>::v2;
+    const R ih2 = (R)L.inv_h2;
+    nbp = nbT = Sp = ST = R(0);
+    V2 am;
+    if (CF) am = L.ac[me];
+    const long long sx = 1, sy = L.nx, sz = (long long)L.nx * L.ny;
+    auto acc = [&](long long q, int axis, bool upper) {
+        V2 w = face_coef<R, CF>(L, am, me, q, axis, upper);
+        R wp = w.x * ih2, wT = w.y * ih2;
+        Sp += wp;
+        ST += wT;
+        if (USE_U) {
+            V2 uq = L.u[q];
+            nbp += wp * uq.x;
+            nbT += wT * uq.y;
+        }
+    };
+    if (i > 0) acc(me - sx, 0, false);
+    if (i < L.nx - 1) acc(me + sx, 0, true);
+    if (j > 0) acc(me - sy, 1, false);
+    if (j < L.ny - 1) acc(me + sy, 1, true);
+    if (DIM == 3) {
+        if (k > 0) acc(me - sz, 2, false);
+        if (k < L.nz - 1) acc(me + sz, 2, true);
+    }
+}
+
+__device__ __forceinline__ void block_reduce_store(double *v, int width, double *out)
+{
+    for (int q = 0; q < width; q++)
+        for (int off = 32; off >= 1; off >>= 1) v[q] += __shfl_xor(v[q], off, 64);
+    __shared__ double sm[4][kBlock / 64];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0)
+        for (int q = 0; q < width; q++) sm[q][w] = v[q];
+    __syncthreads();
+    if (threadIdx.x < (unsigned)width) {
+        double s = 0.0;
+        for (int i = 0; i < kBlock / 64; i++) s += sm[threadIdx.x][i];
+        out[threadIdx.x] = s;
+    }
+}
+
+static inline unsigned nblk(long long n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+// ---------------------------------------------------------------- assembly
+// Per cell: thermal dilation (Eq. 10), the phase coefficients l1..l4
+// (Eqs. 29-32, l4 = beta/(rho c_p dt)), each phase's canonical block
+// (Bpp = -l3 + l4 l2, BpT = l4 l1, BTp = -l2, BTT = -l1), averaged with the
+// liquid fraction C (Sec. 3 averaging rule), and the cell coefficients
+// a_p = 1/(C rho_1 + (1-C) rho_2), a_T = C k_1 + (1-C) k_2.
+__device__ __forceinline__ double4 phase_block(const pt_phase &ph, double p, double T, double dt)
+{
+    double beta = ph.beta;
+    if (!(beta > 0.0)) {
+        double gcv = (ph.Gamma - 1.0) * ph.cv;
+        beta = gcv / (gcv * T + ph.b * (p + ph.Pi));
+    }
+    double rcp = ph.rho * ph.cp;
+    double l1 = -rcp / dt;
+    double l2 = beta * T / dt;
+    double l3 = -(ph.gamma / (ph.rho * ph.c * ph.c) - beta * beta * T / rcp) / (dt * dt);
+    double l4 = beta / (rcp * dt);
+    double4 B;
+    B.x = -l3 + l4 * l2;
+    B.y = l4 * l1;
+    B.z = -l2;
+    B.w = -l1;
+    return B;
+}
+
+__global__ __launch_bounds__(kBlock) void k_assemble(AsmArgs a)
+{
+    long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= a.N) return;
+    double2 ac;
+    double4 B;
+    bool argbad = false;
+    if (a.mode == PT_COEF_PHASES) {
+        double c = a.C[t];
+        double p = a.p_adv ? a.p_adv[t] : a.p_adv_const;
+        double T = a.T_adv ? a.T_adv[t] : a.T_adv_const;
+        argbad = !(c >= 0.0 && c <= 1.0) || !isfinite(p) || !(T > 0.0) || !isfinite(T);
+        double4 B1 = phase_block(a.liq, p, T, a.dt);
+        double4 B2 = phase_block(a.gas, p, T, a.dt);
+        double g = 1.0 - c;
+        B.x = c * B1.x + g * B2.x;
+        B.y = c * B1.y + g * B2.y;
+        B.z = c * B1.z + g * B2.z;
+        B.w = c * B1.w + g * B2.w;
+        ac.x = 1.0 / (c * a.liq.rho + g * a.gas.rho);
+        ac.y = c * a.liq.k + g * a.gas.k;
+    } else {
+        ac.x = a.alpha_p ? a.alpha_p[t] : a.alpha_p_const;
+        ac.y = a.alpha_T ? a.alpha_T[t] : a.alpha_T_const;
+        if (a.B) {
+            B.x = a.B[t];
+            B.y = a.B[a.N + t];
+            B.z = a.B[2 * a.N + t];
+            B.w = a.B[3 * a.N + t];
+        } else {
+            B.x = a.B_const[0];
+            B.y = a.B_const[1];
+            B.z = a.B_const[2];
+            B.w = a.B_const[3];
+        }
+        if (B.x != 0.0 || B.y != 0.0 || B.z != 0.0 || B.w != 0.0) atomicOr(&a.flags[FLAG_BNONZERO], 1);
+    }
+    argbad = argbad || !(ac.x >= 0.0) || !(ac.y >= 0.0) || !isfinite(ac.x) || !isfinite(ac.y) ||
+             !isfinite(B.x) || !isfinite(B.y) || !isfinite(B.z) || !isfinite(B.w);
+    bool sing = !(B.x > 0.0 && B.w > 0.0 && B.x * B.w - B.y * B.z > 0.0);
+    if (argbad) atomicOr(&a.flags[FLAG_ARG], 1);
+    if (sing) atomicOr(&a.flags[FLAG_SINGULAR], 1);
+    a.ac64[t] = ac;
+    a.B64[t] = B;
+    if (a.ac32) {
+        a.ac32[t] = make_float2((float)ac.x, (float)ac.y);
+        a.B32[t] = make_float4((float)B.x, (float)B.y, (float)B.z, (float)B.w);
+    }
+}
+
+void launch_assemble(const AsmArgs &a, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_assemble, dim3(nblk(a.N)), dim3(kBlock), 0, s, a);
+}
+
+// Paper right-hand side (Eqs. 33-34) from the cell block:
+// l1 = -BTT, l2 = -BTp, l4 = BpT / l1, l3 = -Bpp + l4 l2.
+__global__ __launch_bounds__(kBlock) void k_paper_rhs(long long N, const double4 *B64,
+                                                      const double *p_adv, double p_const,
+                                                      const double *T_adv, double T_const,
+                                                      const double *div, double dt,
+                                                      double *b_p, double *b_T)
+{
+    long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= N) return;
+    double4 B = B64[t];
+    double l1 = -B.w, l2 = -B.z, l4 = B.y / l1, l3 = -B.x + l4 * l2;
+    double p = p_adv ? p_adv[t] : p_const;
+    double T = T_adv ? T_adv[t] : T_const;
+    double d = div ? div[t] : 0.0;
+    b_T[t] = l1 * T + l2 * p;
+    b_p[t] = l3 * p + d / dt;
+}
+
+void launch_paper_rhs(long long N, const double4 *B64, const double *p_adv, double p_const,
+                      const double *T_adv, double T_const, const double *div, double dt,
+                      double *b_p, double *b_T, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_paper_rhs, dim3(nblk(N)), dim3(kBlock), 0, s, N, B64, p_adv, p_const,
+                       T_adv, T_const, div, dt, b_p, b_T);
+}
+
+// ---------------------------------------------------- outer FP64 residual
+// u_new = u + du (when update), residual of the mode-native form (paper
+// form Eqs. 27-28 in phases mode, computed directly so that its rounding
+// does not depend on the size of b), the canonical residual for the
+// V-cycle (r_T = -res_T, r_p = -res_p + l4 res_T), and per-block sums of
+// res_p^2, res_T^2, b_p^2, b_T^2.
+template <int DIM, typename RV>
+__global__ __launch_bounds__(kBlock) void k_outer(OuterArgs<RV> a)
+{
+    using V2 = typename VT<RV>::v2;
+    long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    if (t < a.N) {
+        int i, j, k;
+        decode(t, a.nx, a.ny, i, j, k);
+        const long long me = t;
+        auto U = [&](long long q) {
+            double2 v = make_double2(a.src_p[q], a.src_T[q]);
+            if (a.update) {
+                V2 d = a.du[q];
+                v.x += (double)d.x;
+                v.y += (double)d.y;
+            }
+            return v;
+        };
+        double2 um = U(me);
+        double2 am = a.ac[me];
+        double nbp = 0.0, nbT = 0.0, Sp = 0.0, ST = 0.0;
+        auto acc_nb = [&](long long q) {
+            double2 w = harm2(am, a.ac[q]);
+            w.x *= a.inv_h2;
+            w.y *= a.inv_h2;
+            double2 uq = U(q);
+            Sp += w.x;
+            ST += w.y;
+            nbp += w.x * uq.x;
+            nbT += w.y * uq.y;
+        };
+        const long long sy = a.nx, sz = (long long)a.nx * a.ny;
+        if (i > 0) acc_nb(me - 1);
+        if (i < a.nx - 1) acc_nb(me + 1);
+        if (j > 0) acc_nb(me - sy);
+        if (j < a.ny - 1) acc_nb(me + sy);
+        if (DIM == 3) {
+            if (k > 0) acc_nb(me - sz);
+            if (k < a.nz - 1) acc_nb(me + sz);
+        }
+        const double Lp = Sp * um.x - nbp;   // -div(a_p grad p)
+        const double LT = ST * um.y - nbT;   // -div(a_T grad T)
+        const double4 B = a.B[me];
+        double bp = a.b_p[me], bT = a.b_T[me];
+        if (a.bshift) {
+            bp -= a.bshift_scale * a.bshift[0];
+            bT -= a.bshift_scale * a.bshift[1];
+        }
+        double resp, resT, rp, rT;
+        if (a.phases) {
+            const double l1 = -B.w, l2 = -B.z, l4 = B.y / l1, l3 = -B.x + l4 * l2;
+            resT = bT - (-LT + l1 * um.y + l2 * um.x);
+            resp = bp - (-Lp + l3 * um.x + l4 * (-LT));
+            rT = -resT;
+            rp = -resp + l4 * resT;
+        } else {
+            rp = bp - (Lp + B.x * um.x + B.y * um.y);
+            rT = bT - (LT + B.z * um.x + B.w * um.y);
+            resp = rp;
+            resT = rT;
+        }
+        if (a.update) {
+            a.dst_p[me] = um.x;
+            a.dst_T[me] = um.y;
+        }
+        if (a.r) {
+            V2 o;
+            o.x = (RV)rp;
+            o.y = (RV)rT;
+            a.r[me] = o;
+        }
+        if (a.res_p) a.res_p[me] = resp;
+        if (a.res_T) a.res_T[me] = resT;
+        acc[0] = resp * resp;
+        acc[1] = resT * resT;
+        acc[2] = bp * bp;
+        acc[3] = bT * bT;
+    }
+    block_reduce_store(acc, 4, a.partials + 4ll * blockIdx.x);
+}
+
+int outer_blocks(long long N) { return (int)nblk(N); }
+
+template <typename RV>
+int launch_outer(int dim, const OuterArgs<RV> &a, hipStream_t s)
+{
+    unsigned nb = nblk(a.N);
+    if (dim == 3)
+        hipLaunchKernelGGL((k_outer<3, RV>), dim3(nb), dim3(kBlock), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_outer<2, RV>), dim3(nb), dim3(kBlock), 0, s, a);
+    return (int)nb;
+}
+template int launch_outer<float>(int, const OuterArgs<float> &, hipStream_t);
+template int launch_outer<double>(int, const OuterArgs<double> &, hipStream_t);
+
+// Fixed-order reduction of per-block partial sums (`width` per block).
+__global__ __launch_bounds__(kBlock) void k_reduce(const double *partials, int nblocks, int width,
+                                                   double *out)
+{
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < nblocks; b += kBlock)
+        for (int q = 0; q < width; q++) v[q] += partials[(long long)b * width + q];
+    block_reduce_store(v, width, out);
+}
+
+void launch_reduce4(const double *partials, int nblocks, double *out4, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, s, partials, nblocks, 4, out4);
+}
+
+__global__ __launch_bounds__(kBlock) void k_sum2(long long N, const double *x, const double *y,
+                                                 double *partials)
+{
+    long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
+    double v[2] = {0.0, 0.0};
+    if (t < N) {
+        v[0] = x[t];
+        v[1] = y[t];
+    }
+    block_reduce_store(v, 2, partials + 2ll * blockIdx.x);
+}
+
+int sum2_blocks(long long N) { return (int)nblk(N); }
+
+void launch_sum2(long long N, const double *x, const double *y, double *partials, int nblocks,
+                 double *out2, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_sum2, dim3(nblk(N)), dim3(kBlock), 0, s, N, x, y, partials);
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, s, partials, nblocks, 2, out2);
+}
+
+__global__ __launch_bounds__(kBlock) void k_shift2(long long N, double *x, double *y,
+                                                   const double *sum2, double scale)
+{
+    long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= N) return;
+    x[t] -= scale * sum2[0];
+    y[t] -= scale * sum2[1];
+}
+
+void launch_shift2(long long N, double *x, double *y, const double *sum2, double scale,
+                   hipStream_t s)
+{
+    hipLaunchKernelGGL(k_shift2, dim3(nblk(N)), dim3(kBlock), 0, s, N, x, y, sum2, scale);
+}
+
+// ------------------------------------------------------------ smoother
+// One colour of a red-black 2x2-block Gauss-Seidel sweep: each cell of
+// colour (i+j+k) mod 2 == color solves
+//   (B + diag(S_p, S_T)) u = f + sum_faces w u_nbr
+// by Cramer's rule.  zero_guess: the neighbours are taken as zero (first
+// red pass from a zero initial guess; the stale values are never read).
+template <typename R, int DIM, bool CF>
+__global__ __launch_bounds__(kBlock) void k_rb_pass(Lvl<R> L, int color, int zero_guess)
+{
+    using V2 = typename VT<R>::v2;
+    using V4 = typename VT<R>::v4;
+    long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
+    const int nxh = (L.nx + 1) >> 1;
+    const long long tot = (long long)nxh * L.ny * L.nz;
+    if (t >= tot) return;
+    int ti, j, k;
+    decode(t, nxh, L.ny, ti, j, k);
+    const int i = 2 * ti + ((j + k + color) & 1);
+    if (i >= L.nx) return;
+    const long long me = i + (long long)L.nx * (j + (long long)L.ny * k);
+    R nbp, nbT, Sp, ST;
+    if (zero_guess)
+        gather<R, DIM, CF, false>(L, i, j, k, me, nbp, nbT, Sp, ST);
+    else
+        gather<R, DIM, CF, true>(L, i, j, k, me, nbp, nbT, Sp, ST);
+    const V2 f = L.f[me];
+    const V4 b = L.B[me];
+    const R gp = f.x + nbp, gT = f.y + nbT;
+    const R a = b.x + Sp, d = b.w + ST;
+    const R inv = R(1) / (a * d - b.y * b.z);
+    V2 o;
+    o.x = (d * gp - b.y * gT) * inv;
+    o.y = (a * gT - b.z * gp) * inv;
+    L.u[me] = o;
+}
+
+template <typename R>
+void launch_rb_pass(int dim, int level0, const Lvl<R> &L, int color, int zero_guess,
+                    hipStream_t s)
+{
+    const long long tot = (long long)((L.nx + 1) >> 1) * L.ny * L.nz;
+    dim3 g(nblk(tot)), b(kBlock);
+    if (dim == 3) {
+        if (level0) hipLaunchKernelGGL((k_rb_pass<R, 3, true>), g, b, 0, s, L, color, zero_guess);
+        else hipLaunchKernelGGL((k_rb_pass<R, 3, false>), g, b, 0, s, L, color, zero_guess);
+    } else {
+        if (level0) hipLaunchKernelGGL((k_rb_pass<R, 2, true>), g, b, 0, s, L, color, zero_guess);
+        else hipLaunchKernelGGL((k_rb_pass<R, 2, false>), g, b, 0, s, L, color, zero_guess);
+    }
+}
+template void launch_rb_pass<float>(int, int, const Lvl<float> &, int, int, hipStream_t);
+template void launch_rb_pass<double>(int, int, const Lvl<double> &, int, int, hipStream_t);
+
+// ------------------------------------------------ residual + restriction
+// Coarse right-hand side = mean over the 2^DIM children of f - A u.
+template <typename R, int DIM, bool CF>
+__global__ __launch_bounds__(kBlock) void k_restrict(Lvl<R> F, Lvl<R> C)
+{
+    using V2 = typename VT<R>::v2;
+    using V4 = typename VT<R>::v4;
+    long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= C.N) return;
+    int I, J, K;
+    decode(t, C.nx, C.ny, I, J, K);
+    R sp = R(0), sT = R(0);
+#pragma unroll
+    for (int m = 0; m < (1 << DIM); m++) {
+        const int i = 2 * I + (m & 1), j = 2 * J + ((m >> 1) & 1);
+        const int k = DIM == 3 ? 2 * K + ((m >> 2) & 1) : 0;
+        const long long me = i + (long long)F.nx * (j + (long long)F.ny * k);
+        R nbp, nbT, Sp, ST;
+        gather<R, DIM, CF, true>(F, i, j, k, me, nbp, nbT, Sp, ST);
+        const V2 u = F.u[me];
+        const V2 f = F.f[me];
+        const V4 b = F.B[me];
+        const R Ap = Sp * u.x - nbp + b.x * u.x + b.y * u.y;
+        const R AT = ST * u.y - nbT + b.z * u.x + b.w * u.y;
+        sp += f.x - Ap;
+        sT += f.y - AT;
+    }
+    const R sc = R(1) / R(1 << DIM);
+    V2 o;
+    o.x = sp * sc;
+    o.y = sT * sc;
+    C.f[t] = o;
+}
+
+template <typename R>
+void launch_restrict(int dim, int level0, const Lvl<R> &F, const Lvl<R> &C, hipStream_t s)
+{
+    dim3 g(nblk(C.N)), b(kBlock);
+    if (dim == 3) {
+        if (level0) hipLaunchKernelGGL((k_restrict<R, 3, true>), g, b, 0, s, F, C);
+        else hipLaunchKernelGGL((k_restrict<R, 3, false>), g, b, 0, s, F, C);
+    } else {
+        if (level0) hipLaunchKernelGGL((k_restrict<R, 2, true>), g, b, 0, s, F, C);
+        else hipLaunchKernelGGL((k_restrict<R, 2, false>), g, b, 0, s, F, C);
+    }
+}
+template void launch_restrict<float>(int, int, const Lvl<float> &, const Lvl<float> &, hipStream_t);
+template void launch_restrict<double>(int, int, const Lvl<double> &, const Lvl<double> &,
+                                      hipStream_t);
+
+// ------------------------------------------- prolongation + correction
+// u += P e: along each axis weight 3/4 on the parent and 1/4 on the
+// parent's neighbour on the fine cell's side (the parent at a boundary).
+template <typename R, int DIM>
+__global__ __launch_bounds__(kBlock) void k_prolong(Lvl<R> F, Lvl<R> C)
+{
+    using V2 = typename VT<R>::v2;
+    long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= F.N) return;
+    int i, j, k;
+    decode(t, F.nx, F.ny, i, j, k);
+    int par[3] = {i >> 1, j >> 1, DIM == 3 ? k >> 1 : 0};
+    int nbr[3];
+    const int fi[3] = {i, j, k};
+    const int cn[3] = {C.nx, C.ny, C.nz};
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        if (a >= DIM) {
+            nbr[a] = par[a];
+            continue;
+        }
+        int q = par[a] + ((fi[a] & 1) ? 1 : -1);
+        nbr[a] = (q < 0 || q >= cn[a]) ? par[a] : q;
+    }
+    R vp = R(0), vT = R(0);
+#pragma unroll
+    for (int m = 0; m < (1 << DIM); m++) {
+        R w = R(1);
+        int c[3] = {par[0], par[1], par[2]};
+#pragma unroll
+        for (int a = 0; a < DIM; a++) {
+            if ((m >> a) & 1) {
+                c[a] = nbr[a];
+                w *= R(0.25);
+            } else {
+                w *= R(0.75);
+            }
+        }
+        const V2 e = C.u[c[0] + (long long)C.nx * (c[1] + (long long)C.ny * c[2])];
+        vp += w * e.x;
+        vT += w * e.y;
+    }
+    V2 u = F.u[t];
+    u.x += vp;
+    u.y += vT;
+    F.u[t] = u;
+}
+
+template <typename R>
+void launch_prolong(int dim, const Lvl<R> &F, const Lvl<R> &C, hipStream_t s)
+{
+    dim3 g(nblk(F.N)), b(kBlock);
+    if (dim == 3) hipLaunchKernelGGL((k_prolong<R, 3>), g, b, 0, s, F, C);
+    else hipLaunchKernelGGL((k_prolong<R, 2>), g, b, 0, s, F, C);
+}
+template void launch_prolong<float>(int, const Lvl<float> &, const Lvl<float> &, hipStream_t);
+template void launch_prolong<double>(int, const Lvl<double> &, const Lvl<double> &, hipStream_t);
+
+// ------------------------------------------------------ coarse operator
+// Coarse face coefficient = mean of the 2^(DIM-1) fine faces that make up
+// the coarse face; coarse block = mean of the 2^DIM children's blocks.
+template <typename RIN, typename ROUT, int DIM, bool CF>
+__global__ __launch_bounds__(kBlock) void k_coarsen(Lvl<RIN> F, int cnx, int cny, int cnz,
+                                                    typename VT<ROUT>::v2 *fx,
+                                                    typename VT<ROUT>::v2 *fy,
+                                                    typename VT<ROUT>::v2 *fz,
+                                                    typename VT<ROUT>::v4 *Bo)
+{
+    using V2 = typename VT<RIN>::v2;
+    using V4 = typename VT<RIN>::v4;
+    using O2 = typename VT<ROUT>::v2;
+    using O4 = typename VT<ROUT>::v4;
+    long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
+    const long long CN = (long long)cnx * cny * cnz;
+    if (t >= CN) return;
+    int I, J, K;
+    decode(t, cnx, cny, I, J, K);
+    const int base[3] = {2 * I, 2 * J, DIM == 3 ? 2 * K : 0};
+    const int Ci[3] = {I, J, K};
+    const long long st[3] = {1, F.nx, (long long)F.nx * F.ny};
+    double b4[4] = {0, 0, 0, 0};
+    double fs[3][2] = {{0, 0}, {0, 0}, {0, 0}};
+#pragma unroll
+    for (int m = 0; m < (1 << DIM); m++) {
+        const int c[3] = {base[0] + (m & 1), base[1] + ((m >> 1) & 1),
+                          DIM == 3 ? base[2] + ((m >> 2) & 1) : 0};
+        const long long me = c[0] + (long long)F.nx * (c[1] + (long long)F.ny * c[2]);
+        const V4 b = F.B[me];
+        b4[0] += (double)b.x;
+        b4[1] += (double)b.y;
+        b4[2] += (double)b.z;
+        b4[3] += (double)b.w;
+#pragma unroll
+        for (int a = 0; a < DIM; a++) {
+            if (c[a] != base[a] || Ci[a] == 0) continue;
+            V2 w;
+            if (CF) {
+                w = harm2(F.ac[me], F.ac[me - st[a]]);
+            } else {
+                const V2 *Fa = a == 0 ? F.fx : (a == 1 ? F.fy : F.fz);
+                w = Fa[me];
+            }
+            fs[a][0] += (double)w.x;
+            fs[a][1] += (double)w.y;
+        }
+    }
+    const double inv_nc = 1.0 / (1 << DIM), inv_nf = 1.0 / (1 << (DIM - 1));
+    O4 ob;
+    ob.x = (ROUT)(b4[0] * inv_nc);
+    ob.y = (ROUT)(b4[1] * inv_nc);
+    ob.z = (ROUT)(b4[2] * inv_nc);
+    ob.w = (ROUT)(b4[3] * inv_nc);
+    Bo[t] = ob;
+    O2 o;
+    o.x = (ROUT)(fs[0][0] * inv_nf);
+    o.y = (ROUT)(fs[0][1] * inv_nf);
+    fx[t] = o;
+    o.x = (ROUT)(fs[1][0] * inv_nf);
+    o.y = (ROUT)(fs[1][1] * inv_nf);
+    fy[t] = o;
+    if (DIM == 3) {
+        o.x = (ROUT)(fs[2][0] * inv_nf);
+        o.y = (ROUT)(fs[2][1] * inv_nf);
+        fz[t] = o;
+    }
+}
+
+template <typename RIN, typename ROUT>
+void launch_coarsen(int dim, int level0, const Lvl<RIN> &F, typename VT<ROUT>::v2 *fx,
+                    typename VT<ROUT>::v2 *fy, typename VT<ROUT>::v2 *fz,
+                    typename VT<ROUT>::v4 *B, hipStream_t s)
+{
+    const int cnx = F.nx / 2, cny = F.ny / 2, cnz = dim == 3 ? F.nz / 2 : 1;
+    dim3 g(nblk((long long)cnx * cny * cnz)), b(kBlock);
+    if (dim == 3) {
+        if (level0)
+            hipLaunchKernelGGL((k_coarsen<RIN, ROUT, 3, true>), g, b, 0, s, F, cnx, cny, cnz, fx,
+                               fy, fz, B);
+        else
+            hipLaunchKernelGGL((k_coarsen<RIN, ROUT, 3, false>), g, b, 0, s, F, cnx, cny, cnz,
+                               fx, fy, fz, B);
+    } else {
+        if (level0)
+            hipLaunchKernelGGL((k_coarsen<RIN, ROUT, 2, true>), g, b, 0, s, F, cnx, cny, cnz, fx,
+                               fy, fz, B);
+        else
+            hipLaunchKernelGGL((k_coarsen<RIN, ROUT, 2, false>), g, b, 0, s, F, cnx, cny, cnz,
+                               fx, fy, fz, B);
+    }
+}
+template void launch_coarsen<double, double>(int, int, const Lvl<double> &, double2 *, double2 *,
+                                             double2 *, double4 *, hipStream_t);
+template void launch_coarsen<double, float>(int, int, const Lvl<double> &, float2 *, float2 *,
+                                            float2 *, float4 *, hipStream_t);
+template void launch_coarsen<float, float>(int, int, const Lvl<float> &, float2 *, float2 *,
+                                           float2 *, float4 *, hipStream_t);
+
+// ------------------------------------------------ coarsest-grid matrix
+// Dense FP64 matrix of the level operator, unknown (2*cell + component).
+// pin_mean: adds s_c = (diagonal of cell 0, component c) / N to every
+// entry of each component block.  For a consistent pure-Neumann system
+// (A 1 = 0, 1^T f = 0) the solution of (A + s 1 1^T) x = f is the
+// zero-mean solution of A x = f, and A + s 1 1^T stays positive definite.
+template <typename R, int DIM, bool CF>
+__device__ double dense_row_diag(const Lvl<R> &L, long long cell, int c, double *row)
+{
+    using V2 = typename VT<R>::v2;
+    int i, j, k;
+    decode(cell, L.nx, L.ny, i, j, k);
+    V2 am;
+    if (CF) am = L.ac[cell];
+    const long long st[3] = {1, L.nx, (long long)L.nx * L.ny};
+    const int ii[3] = {i, j, k};
+    const int nn[3] = {L.nx, L.ny, L.nz};
+    double S = 0.0;
+    for (int a = 0; a < DIM; a++) {
+        for (int up = 0; up < 2; up++) {
+            if (up == 0 && ii[a] == 0) continue;
+            if (up == 1 && ii[a] == nn[a] - 1) continue;
+            const long long q = up ? cell + st[a] : cell - st[a];
+            V2 w = face_coef<R, CF>(L, am, cell, q, a, up == 1);
+            double wc = (double)(c == 0 ? w.x : w.y) * L.inv_h2;
+            S += wc;
+            if (row) row[2 * q + c] -= wc;
+        }
+    }
+    const typename VT<R>::v4 b = L.B[cell];
+    return S + (double)(c == 0 ? b.x : b.w);
+}
+
+template <typename R, int DIM, bool CF>
+__global__ __launch_bounds__(kBlock) void k_coarse_dense(Lvl<R> L, int pin_mean, double *M)
+{
+    using V4 = typename VT<R>::v4;
+    long long r = (long long)blockIdx.x * kBlock + threadIdx.x;
+    const long long m = 2 * L.N;
+    if (r >= m) return;
+    const long long cell = r >> 1;
+    const int c = (int)(r & 1);
+    double *row = M + r * m;
+    for (long long q = 0; q < m; q++) row[q] = 0.0;
+    const double D = dense_row_diag<R, DIM, CF>(L, cell, c, row);
+    const V4 b = L.B[cell];
+    row[r] += D;
+    row[2 * cell + (1 - c)] += (double)(c == 0 ? b.y : b.z);
+    if (pin_mean) {
+        double d0 = dense_row_diag<R, DIM, CF>(L, 0, c, nullptr);
+        if (!(d0 > 0.0)) d0 = L.inv_h2;
+        const double sh = d0 / (double)L.N;
+        for (long long q = 0; q < L.N; q++) row[2 * q + c] += sh;
+    }
+}
+
+template <typename R>
+void launch_coarse_dense(int dim, int level0, const Lvl<R> &L, int pin_mean, double *M,
+                         hipStream_t s)
+{
+    dim3 g(nblk(2 * L.N)), b(kBlock);
+    if (dim == 3) {
+        if (level0) hipLaunchKernelGGL((k_coarse_dense<R, 3, true>), g, b, 0, s, L, pin_mean, M);
+        else hipLaunchKernelGGL((k_coarse_dense<R, 3, false>), g, b, 0, s, L, pin_mean, M);
+    } else {
+        if (level0) hipLaunchKernelGGL((k_coarse_dense<R, 2, true>), g, b, 0, s, L, pin_mean, M);
+        else hipLaunchKernelGGL((k_coarse_dense<R, 2, false>), g, b, 0, s, L, pin_mean, M);
+    }
+}
+template void launch_coarse_dense<float>(int, int, const Lvl<float> &, int, double *, hipStream_t);
+template void launch_coarse_dense<double>(int, int, const Lvl<double> &, int, double *,
+                                          hipStream_t);
+
+// One Gauss-Jordan elimination step without pivoting (out of place):
+// pivot p = A[k][k]; A'[k][k] = 1/p; A'[k][j] = A[k][j]/p;
+// A'[i][k] = -A[i][k]/p; A'[i][j] = A[i][j] - A[i][k] A[k][j]/p.
+// After m steps the matrix holds its inverse.  Pivots of the coarse
+// operator are positive (positive diagonals and det of every 2x2 block,
+// block-diagonally dominant rows); a pivot that is not is flagged.
+__global__ __launch_bounds__(kBlock) void k_gj_step(const double *A, double *Bm, int m, int k,
+                                                    int *flags)
+{
+    long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= (long long)m * m) return;
+    const int i = (int)(t / m), j = (int)(t % m);
+    const double p = A[(long long)k * m + k];
+    double v;
+    if (i == k && j == k) {
+        v = 1.0 / p;
+        if (!(p > 0.0) || !isfinite(p)) atomicOr(&flags[FLAG_PIVOT], 1);
+    } else if (i == k) {
+        v = A[(long long)k * m + j] / p;
+    } else if (j == k) {
+        v = -A[(long long)i * m + k] / p;
+    } else {
+        v = A[t] - A[(long long)i * m + k] * (A[(long long)k * m + j] / p);
+    }
+    Bm[t] = v;
+}
+
+void launch_gj_step(const double *A, double *Bm, int m, int k, int *flags, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_gj_step, dim3(nblk((long long)m * m)), dim3(kBlock), 0, s, A, Bm, m, k,
+                       flags);
+}
+
+// u = Ainv f on the coarsest grid, FP64 accumulation; one wave per row.
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_coarse_apply(const double *Ainv, int m, const R *f,
+                                                         R *u)
+{
+    const int row = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (row >= m) return;
+    const double *a = Ainv + (long long)row * m;
+    double s = 0.0;
+    for (int c = lane; c < m; c += 64) s += a[c] * (double)f[c];
+    for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (lane == 0) u[row] = (R)s;
+}
+
+template <typename R>
+void launch_coarse_apply(const double *Ainv, int m, const R *f, R *u, hipStream_t s)
+{
+    const int rows_per_block = kBlock / 64;
+    hipLaunchKernelGGL((k_coarse_apply<R>), dim3((m + rows_per_block - 1) / rows_per_block),
+                       dim3(kBlock), 0, s, Ainv, m, f, u);
+}
+template void launch_coarse_apply<float>(const double *, int, const float *, float *, hipStream_t);
+template void launch_coarse_apply<double>(const double *, int, const double *, double *,
+                                          hipStream_t);
+
+// ------------------------------------------------------ export / convert
+template <typename R, int DIM, bool CF>
+__global__ __launch_bounds__(kBlock) void k_export_op(Lvl<R> L, double *faces, double *Bout)
+{
+    using V2 = typename VT<R>::v2;
+    long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= L.N) return;
+    int i, j, k;
+    decode(t, L.nx, L.ny, i, j, k);
+    const int ii[3] = {i, j, k};
+    const long long st[3] = {1, L.nx, (long long)L.nx * L.ny};
+    V2 am;
+    if (CF) am = L.ac[t];
+    for (int a = 0; a < 3; a++) {
+        double wp = 0.0, wT = 0.0;
+        if (a < DIM && ii[a] > 0) {
+            V2 w = face_coef<R, CF>(L, am, t, t - st[a], a, false);
+            wp = (double)w.x;
+            wT = (double)w.y;
+        }
+        faces[(0 * 3 + a) * L.N + t] = wp;
+        faces[(1 * 3 + a) * L.N + t] = wT;
+    }
+    const typename VT<R>::v4 b = L.B[t];
+    Bout[t] = (double)b.x;
+    Bout[L.N + t] = (double)b.y;
+    Bout[2 * L.N + t] = (double)b.z;
+    Bout[3 * L.N + t] = (double)b.w;
+}
+
+template <typename R>
+void launch_export_op(int dim, int level0, const Lvl<R> &L, double *faces, double *B,
+                      hipStream_t s)
+{
+    dim3 g(nblk(L.N)), b(kBlock);
+    if (dim == 3) {
+        if (level0) hipLaunchKernelGGL((k_export_op<R, 3, true>), g, b, 0, s, L, faces, B);
+        else hipLaunchKernelGGL((k_export_op<R, 3, false>), g, b, 0, s, L, faces, B);
+    } else {
+        if (level0) hipLaunchKernelGGL((k_export_op<R, 2, true>), g, b, 0, s, L, faces, B);
+        else hipLaunchKernelGGL((k_export_op<R, 2, false>), g, b, 0, s, L, faces, B);
+    }
+}
+template void launch_export_op<float>(int, int, const Lvl<float> &, double *, double *, hipStream_t);
+template void launch_export_op<double>(int, int, const Lvl<double> &, double *, double *,
+                                       hipStream_t);
+
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_pack(long long N, const double *p, const double *T,
+                                                 typename VT<R>::v2 *out)
+{
+    long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= N) return;
+    typename VT<R>::v2 o;
+    o.x = (R)p[t];
+    o.y = (R)T[t];
+    out[t] = o;
+}
+
+template <typename R>
+void launch_pack(long long N, const double *p, const double *T, typename VT<R>::v2 *out,
+                 hipStream_t s)
+{
+    hipLaunchKernelGGL((k_pack<R>), dim3(nblk(N)), dim3(kBlock), 0, s, N, p, T, out);
+}
+template void launch_pack<float>(long long, const double *, const double *, float2 *, hipStream_t);
+template void launch_pack<double>(long long, const double *, const double *, double2 *,
+                                  hipStream_t);
+
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_unpack(long long N, const typename VT<R>::v2 *in,
+                                                   double *p, double *T)
+{
+    long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= N) return;
+    typename VT<R>::v2 v = in[t];
+    p[t] = (double)v.x;
+    T[t] = (double)v.y;
+}
+
+template <typename R>
+void launch_unpack(long long N, const typename VT<R>::v2 *in, double *p, double *T, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_unpack<R>), dim3(nblk(N)), dim3(kBlock), 0, s, N, in, p, T);
+}
+template void launch_unpack<float>(long long, const float2 *, double *, double *, hipStream_t);
+template void launch_unpack<double>(long long, const double2 *, double *, double *, hipStream_t);
+
+template <typename RIN, typename ROUT>
+__global__ __launch_bounds__(kBlock) void k_convert(long long n, const RIN *in, ROUT *out)
+{
+    long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (t < n) out[t] = (ROUT)in[t];
+}
+
+template <typename RIN, typename ROUT>
+void launch_convert(long long n, const RIN *in, ROUT *out, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_convert<RIN, ROUT>), dim3(nblk(n)), dim3(kBlock), 0, s, n, in, out);
+}
+template void launch_convert<double, double>(long long, const double *, double *, hipStream_t);
+template void launch_convert<double, float>(long long, const double *, float *, hipStream_t);
+template void launch_convert<float, double>(long long, const float *, double *, hipStream_t);
+
+// Plain copy (16-byte vectors, then a byte tail): bandwidth calibration.
+__global__ __launch_bounds__(kBlock) void k_copy(uint4 *dst, const uint4 *src, long long nvec,
+                                                 unsigned char *dtail, const unsigned char *stail,
+                                                 int ntail)
+{
+    long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
+    const long long stride = (long long)gridDim.x * kBlock;
+    for (long long q = t; q < nvec; q += stride) dst[q] = src[q];
+    if (t < ntail) dtail[t] = stail[t];
+}
+
+void launch_copy(void *dst, const void *src, size_t bytes, hipStream_t s)
+{
+    const long long nvec = (long long)(bytes / 16);
+    const int ntail = (int)(bytes % 16);
+    long long blocks = (nvec + kBlock - 1) / kBlock;
+    if (blocks > 8192) blocks = 8192;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_copy, dim3((unsigned)blocks), dim3(kBlock), 0, s, (uint4 *)dst,
+                       (const uint4 *)src, nvec, (unsigned char *)dst + nvec * 16,
+                       (const unsigned char *)src + nvec * 16, ntail);
+}
+
+}  // namespace ptmg
+
+namespace ptmg {
+
+// Zero fill with vector stores (kept out of hipMemsetAsync so that the
+// work can be captured in a graph).
+__global__ __launch_bounds__(kBlock) void k_zero(uint4 *p, long long nvec, unsigned char *tail,
+                                                 int ntail)
+{
+    long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
+    const long long stride = (long long)gridDim.x * kBlock;
+    for (long long q = t; q < nvec; q += stride) p[q] = make_uint4(0, 0, 0, 0);
+    if (t < ntail) tail[t] = 0;
+}
+
+void launch_zero(void *p, size_t bytes, hipStream_t s)
+{
+    const long long nvec = (long long)(bytes / 16);
+    const int ntail = (int)(bytes % 16);
+    long long blocks = (nvec + kBlock - 1) / kBlock;
+    if (blocks > 8192) blocks = 8192;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_zero, dim3((unsigned)blocks), dim3(kBlock), 0, s, (uint4 *)p, nvec,
+                       (unsigned char *)p + nvec * 16, ntail);
+}
+
+}  // namespace ptmg

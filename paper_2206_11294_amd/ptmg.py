@@ -1,0 +1,287 @@
+"""ctypes binding of libptmg (the C ABI in include/pt_mg.h).
+
+Argument marshalling only: every step of the solve runs in the HIP library.
+PyTorch provides device memory (float64 CUDA/HIP tensors) and streams.
+Loading fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Dict, Optional, Sequence, Tuple
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libptmg.so")
+
+PT_OK, PT_ERR_ARG, PT_ERR_OOM, PT_ERR_SINGULAR, PT_ERR_NOCONV, PT_ERR_HIP, PT_ERR_STATE = range(7)
+STATUS_NAMES = {0: "PT_OK", 1: "PT_ERR_ARG", 2: "PT_ERR_OOM", 3: "PT_ERR_SINGULAR",
+                4: "PT_ERR_NOCONV", 5: "PT_ERR_HIP", 6: "PT_ERR_STATE"}
+PT_COEF_EXPLICIT, PT_COEF_PHASES = 0, 1
+PT_PREC_FP64, PT_PREC_MIXED = 0, 1
+PT_MAX_HIST = 64
+KERNEL_CLASSES = ["outer_residual", "smooth_fine", "smooth_coarse", "restrict", "prolong",
+                  "coarse_solve", "other"]
+
+
+class PtMgError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+        self.message = message
+
+
+class pt_phase(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_double) for f in
+                ("rho", "k", "cp", "cv", "c", "gamma", "Gamma", "Pi", "b", "beta")]
+
+
+_Dp = ctypes.c_void_p
+
+
+class pt_problem(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int), ("n", ctypes.c_int * 3), ("h", ctypes.c_double),
+        ("mode", ctypes.c_int),
+        ("alpha_p", _Dp), ("alpha_T", _Dp),
+        ("alpha_p_const", ctypes.c_double), ("alpha_T_const", ctypes.c_double),
+        ("B", _Dp), ("B_const", ctypes.c_double * 4),
+        ("C", _Dp), ("liquid", pt_phase), ("gas", pt_phase), ("dt", ctypes.c_double),
+        ("p_adv", _Dp), ("T_adv", _Dp),
+        ("p_adv_const", ctypes.c_double), ("T_adv_const", ctypes.c_double),
+        ("mean_constraint", ctypes.c_int),
+    ]
+
+
+class pt_solve_opts(ctypes.Structure):
+    _fields_ = [("rtol", ctypes.c_double), ("max_cycles", ctypes.c_int),
+                ("nu1", ctypes.c_int), ("nu2", ctypes.c_int), ("zero_guess", ctypes.c_int)]
+
+
+class pt_solve_info(ctypes.Structure):
+    _fields_ = [("cycles", ctypes.c_int), ("relres", ctypes.c_double * 2),
+                ("relres_hist", ctypes.c_double * (2 * PT_MAX_HIST)),
+                ("hist_len", ctypes.c_int), ("t_solve_s", ctypes.c_double),
+                ("status", ctypes.c_int)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded libptmg.so (built by paper_2206_11294_amd.build)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"libptmg.so is not built ({LIB_PATH}); "
+                              "run `python -m paper_2206_11294_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        c_int, c_void, c_double = ctypes.c_int, ctypes.c_void_p, ctypes.c_double
+        P = ctypes.POINTER
+        sig = {
+            "pt_mg_footprint_bytes": (ctypes.c_size_t, [P(pt_problem), c_int]),
+            "pt_mg_setup": (c_int, [P(pt_problem), c_int, c_void, P(c_void)]),
+            "pt_mg_update": (c_int, [c_void, P(pt_problem)]),
+            "pt_mg_paper_rhs": (c_int, [c_void] + [c_void] * 5),
+            "pt_mg_solve": (c_int, [c_void, c_void, c_void, c_void, c_void,
+                                    P(pt_solve_opts), P(pt_solve_info)]),
+            "pt_mg_residual": (c_int, [c_void] + [c_void] * 6 + [P(c_double)]),
+            "pt_mg_destroy": (None, [c_void]),
+            "pt_mg_last_error": (ctypes.c_char_p, [c_void]),
+            "pt_mg_num_levels": (c_int, [c_void]),
+            "pt_mg_level_dims": (c_int, [c_void, c_int, P(c_int), P(c_double)]),
+            "pt_mg_get_operator": (c_int, [c_void, c_int, c_void, c_void]),
+            "pt_mg_smooth": (c_int, [c_void, c_int, c_void, c_void, c_void, c_void, c_int]),
+            "pt_mg_restrict_residual": (c_int, [c_void, c_int] + [c_void] * 6),
+            "pt_mg_prolong_add": (c_int, [c_void, c_int] + [c_void] * 4),
+            "pt_mg_coarse_solve": (c_int, [c_void] + [c_void] * 4),
+            "pt_mg_vcycle": (c_int, [c_void] + [c_void] * 4 + [c_int, c_int]),
+            "pt_mg_set_timing": (c_int, [c_void, c_int]),
+            "pt_mg_kernel_stats": (c_int, [c_void, c_int, P(ctypes.c_long), P(c_double),
+                                           P(c_double)]),
+            "pt_mg_reset_stats": (c_int, [c_void]),
+            "pt_mg_last_cell_updates": (ctypes.c_longlong, [c_void]),
+            "pt_copy_kernel": (c_int, [c_void, c_void, ctypes.c_size_t, c_void]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def exported_symbols() -> Sequence[str]:
+    """Names of the C-ABI functions the binding uses."""
+    lib()
+    return ["pt_mg_footprint_bytes", "pt_mg_setup", "pt_mg_update", "pt_mg_paper_rhs",
+            "pt_mg_solve", "pt_mg_residual", "pt_mg_destroy", "pt_mg_last_error",
+            "pt_mg_num_levels", "pt_mg_level_dims", "pt_mg_get_operator", "pt_mg_smooth",
+            "pt_mg_restrict_residual", "pt_mg_prolong_add", "pt_mg_coarse_solve",
+            "pt_mg_vcycle", "pt_mg_set_timing", "pt_mg_kernel_stats", "pt_mg_reset_stats",
+            "pt_mg_last_cell_updates", "pt_copy_kernel"]
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise TypeError("fields must be contiguous float64 device tensors")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream_ptr(stream) -> Optional[int]:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream or None
+
+
+def phase_struct(rho, k, cp, cv, c, gamma, Gamma, Pi, b, beta=0.0) -> pt_phase:
+    return pt_phase(rho, k, cp, cv, c, gamma, Gamma, Pi, b, beta)
+
+
+def footprint_bytes(prob: pt_problem, precision: int) -> int:
+    return int(lib().pt_mg_footprint_bytes(ctypes.byref(prob), precision))
+
+
+def copy_kernel(dst: torch.Tensor, src: torch.Tensor, nbytes: int, stream=None) -> None:
+    rc = lib().pt_copy_kernel(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()),
+                              nbytes, _stream_ptr(stream))
+    if rc:
+        raise PtMgError(rc, lib().pt_mg_last_error(None).decode())
+
+
+class PtMg:
+    """One handle: assembled operator + hierarchy on the device."""
+
+    def __init__(self, prob: pt_problem, precision: int = PT_PREC_FP64, stream=None,
+                 keepalive=None):
+        self._h = ctypes.c_void_p()
+        self.precision = precision
+        self.N = prob.n[0] * prob.n[1] * prob.n[2]
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self._stream = stream
+        rc = lib().pt_mg_setup(ctypes.byref(prob), precision, _stream_ptr(stream),
+                               ctypes.byref(self._h))
+        if rc:
+            raise PtMgError(rc, lib().pt_mg_last_error(None).decode())
+
+    # -- plumbing ----------------------------------------------------------
+    def _check(self, rc: int):
+        if rc not in (PT_OK,):
+            raise PtMgError(rc, lib().pt_mg_last_error(self._h).decode())
+
+    def _empty(self, n: Optional[int] = None) -> torch.Tensor:
+        return torch.empty(self.N if n is None else n, dtype=torch.float64, device=self.device)
+
+    def destroy(self):
+        if self._h:
+            lib().pt_mg_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+    # -- the C ABI ----------------------------------------------------------
+    def update(self, prob: pt_problem, keepalive=None):
+        self._check(lib().pt_mg_update(self._h, ctypes.byref(prob)))
+
+    def paper_rhs(self, p_adv=None, T_adv=None, div_ustar=None) -> Tuple[torch.Tensor, torch.Tensor]:
+        b_p, b_T = self._empty(), self._empty()
+        self._check(lib().pt_mg_paper_rhs(self._h, _ptr(p_adv), _ptr(T_adv), _ptr(div_ustar),
+                                          _ptr(b_p), _ptr(b_T)))
+        return b_p, b_T
+
+    def solve(self, b_p, b_T, p, T, rtol=1e-9, max_cycles=50, nu1=2, nu2=2,
+              zero_guess=True, raise_on_noconv=True) -> Dict:
+        opts = pt_solve_opts(rtol, max_cycles, nu1, nu2, int(zero_guess))
+        info = pt_solve_info()
+        rc = lib().pt_mg_solve(self._h, _ptr(b_p), _ptr(b_T), _ptr(p), _ptr(T),
+                               ctypes.byref(opts), ctypes.byref(info))
+        if rc and (rc != PT_ERR_NOCONV or raise_on_noconv):
+            self._check(rc)
+        n = info.hist_len
+        return {"status": rc, "cycles": info.cycles, "relres": (info.relres[0], info.relres[1]),
+                "hist": [(info.relres_hist[2 * q], info.relres_hist[2 * q + 1]) for q in range(n)],
+                "t_solve_s": info.t_solve_s}
+
+    def residual(self, b_p, b_T, p, T, want_fields=True):
+        r_p = self._empty() if want_fields else None
+        r_T = self._empty() if want_fields else None
+        rel = (ctypes.c_double * 2)()
+        self._check(lib().pt_mg_residual(self._h, _ptr(b_p), _ptr(b_T), _ptr(p), _ptr(T),
+                                         _ptr(r_p), _ptr(r_T), rel))
+        return r_p, r_T, (rel[0], rel[1])
+
+    def last_error(self) -> str:
+        return lib().pt_mg_last_error(self._h).decode()
+
+    def num_levels(self) -> int:
+        return int(lib().pt_mg_num_levels(self._h))
+
+    def level_dims(self, level: int):
+        n = (ctypes.c_int * 3)()
+        hl = ctypes.c_double()
+        self._check(lib().pt_mg_level_dims(self._h, level, n, ctypes.byref(hl)))
+        return (n[0], n[1], n[2]), hl.value
+
+    def _nl(self, level):
+        n, _ = self.level_dims(level)
+        return n[0] * n[1] * n[2]
+
+    def get_operator(self, level: int):
+        Nl = self._nl(level)
+        faces, B = self._empty(6 * Nl), self._empty(4 * Nl)
+        self._check(lib().pt_mg_get_operator(self._h, level, _ptr(faces), _ptr(B)))
+        return faces.view(6, Nl), B.view(4, Nl)
+
+    def smooth(self, level, f_p, f_T, u_p, u_T, sweeps=1):
+        self._check(lib().pt_mg_smooth(self._h, level, _ptr(f_p), _ptr(f_T), _ptr(u_p),
+                                       _ptr(u_T), sweeps))
+
+    def restrict_residual(self, level, f_p, f_T, u_p, u_T):
+        Nc = self._nl(level + 1)
+        fc_p, fc_T = self._empty(Nc), self._empty(Nc)
+        self._check(lib().pt_mg_restrict_residual(self._h, level, _ptr(f_p), _ptr(f_T),
+                                                  _ptr(u_p), _ptr(u_T), _ptr(fc_p), _ptr(fc_T)))
+        return fc_p, fc_T
+
+    def prolong_add(self, level, ec_p, ec_T, u_p, u_T):
+        self._check(lib().pt_mg_prolong_add(self._h, level, _ptr(ec_p), _ptr(ec_T), _ptr(u_p),
+                                            _ptr(u_T)))
+
+    def coarse_solve(self, f_p, f_T):
+        Nc = self._nl(self.num_levels() - 1)
+        u_p, u_T = self._empty(Nc), self._empty(Nc)
+        self._check(lib().pt_mg_coarse_solve(self._h, _ptr(f_p), _ptr(f_T), _ptr(u_p), _ptr(u_T)))
+        return u_p, u_T
+
+    def vcycle(self, f_p, f_T, nu1=2, nu2=2):
+        e_p, e_T = self._empty(), self._empty()
+        self._check(lib().pt_mg_vcycle(self._h, _ptr(f_p), _ptr(f_T), _ptr(e_p), _ptr(e_T),
+                                       nu1, nu2))
+        return e_p, e_T
+
+    def set_timing(self, on: bool):
+        self._check(lib().pt_mg_set_timing(self._h, int(on)))
+
+    def kernel_stats(self) -> Dict[str, Dict[str, float]]:
+        out = {}
+        for c, name in enumerate(KERNEL_CLASSES):
+            n = ctypes.c_long()
+            ms = ctypes.c_double()
+            by = ctypes.c_double()
+            self._check(lib().pt_mg_kernel_stats(self._h, c, ctypes.byref(n), ctypes.byref(ms),
+                                                 ctypes.byref(by)))
+            out[name] = {"launches": n.value, "ms": ms.value, "bytes": by.value}
+        return out
+
+    def reset_stats(self):
+        self._check(lib().pt_mg_reset_stats(self._h))
+
+    def last_cell_updates(self) -> int:
+        return int(lib().pt_mg_last_cell_updates(self._h))

@@ -1,0 +1,191 @@
+"""Solve parity of the HIP library (FP64 V-cycle, and FP32 V-cycle under FP64
+iterative refinement) against the FP64 oracle, plus error paths and
+determinism.  Bar: the oracle's own paper-form relative residual of the
+GPU solution <= the requested tolerance (x2 for round-off), and a
+relative error <= 1e-8 per component against the oracle's solution.  The
+p error is ~1e4 x the paper-form residual for bubble problems (the l4
+coupling), so the solves that check the error run to 1e-12."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle as orc
+import workloads as W
+from gpu_util import dev, host, rel_err, step_problems
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+_REF = {}
+
+
+def _reference(name, prob):
+    if name not in _REF:
+        _REF[name] = orc.solve(prob, rtol=1e-14, direct_max=40000)
+    return _REF[name]
+
+
+@pytest.mark.parametrize("name", list(step_problems()))
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_solve_matches_oracle(name, prec):
+    import workloads.device as D
+    prob = step_problems()[name]
+    op, b_p, b_T, p_ref, T_ref = _reference(name, prob)
+    h, gb_p, gb_T, _ = D.setup(prob, 1 if prec == "mixed" else 0)
+    p, T = torch.empty_like(gb_p), torch.empty_like(gb_T)
+    info = h.solve(gb_p, gb_T, p, T, rtol=1e-12, max_cycles=40)
+    assert info["status"] == 0, info
+    assert info["cycles"] <= 12, info
+    P, Tt = host(p), host(T)
+    rel = orc.relres(op, host(gb_p), host(gb_T), P, Tt)
+    assert rel.max() <= 2e-12, rel
+    assert rel_err(P, p_ref) <= 1e-8
+    assert rel_err(Tt, T_ref) <= 1e-8
+    if prob.mode == "phases":   # the stricter perturbation measure
+        p_adv = prob.p_adv.reshape(-1) if prob.p_adv is not None else prob.p_adv_const
+        assert rel_err(P - p_adv, p_ref - p_adv) <= 1e-6
+        assert rel_err(Tt - prob.T_adv_const, T_ref - prob.T_adv_const) <= 1e-6
+
+
+def test_mixed_history_contracts_like_fp64():
+    """Iterative refinement with the FP32 V-cycle converges at the same
+    rate as the FP64 V-cycle until FP32 limits the correction."""
+    import workloads.device as D
+    prob = step_problems()["bubble2d_200x136"]
+    hist = {}
+    for prec in (0, 1):
+        h, b_p, b_T, _ = D.setup(prob, prec)
+        p, T = torch.empty_like(b_p), torch.empty_like(b_T)
+        info = h.solve(b_p, b_T, p, T, rtol=1e-13, max_cycles=30)
+        hist[prec] = np.array(info["hist"])
+    n = min(len(hist[0]), len(hist[1]), 4)
+    for c in range(2):
+        assert hist[1][n - 1, c] <= 10 * max(hist[0][n - 1, c], 1e-13)
+
+
+def test_deterministic_bitwise():
+    import workloads.device as D
+    prob = step_problems()["bubble3d_40x24x56"]
+    h, b_p, b_T, _ = D.setup(prob, 1)
+    outs = []
+    for _ in range(2):
+        p, T = torch.empty_like(b_p), torch.empty_like(b_T)
+        h.solve(b_p, b_T, p, T, rtol=1e-10)
+        outs.append((p.clone(), T.clone()))
+    assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1])
+
+
+def test_warm_start_and_update():
+    """The initial guess is used (paper: a good guess saves work), and an
+    update with new fields reuses the handle."""
+    import workloads.device as D
+    prob = step_problems()["twobubble2d_96x80"]
+    h, b_p, b_T, t = D.setup(prob, 1)
+    p, T = torch.empty_like(b_p), torch.empty_like(b_T)
+    cold = h.solve(b_p, b_T, p, T, rtol=1e-11)
+    warm = h.solve(b_p, b_T, p, T, rtol=1e-11, zero_guess=False)
+    assert warm["cycles"] == 0 and cold["cycles"] > 0
+    prob2 = W.bubble_problem("b4", 2, (96, 80), [(0.35, 0.45)], [0.2], W.P0, 3 * W.P0)
+    s2, t2 = D.to_device(prob2)
+    h.update(s2)
+    b2p, b2T = h.paper_rhs(t2.get("p_adv"), None, None)
+    info = h.solve(b2p, b2T, p, T, rtol=1e-12)
+    op2, rb_p, rb_T, p2, T2 = orc.solve(prob2, direct_max=40000)
+    assert rel_err(host(p), p2) <= 1e-8 and rel_err(host(T), T2) <= 1e-8
+    assert info["status"] == 0
+
+
+def test_stiff_time_step():
+    """Diffusive-CFL time step (much larger dt): still converges."""
+    import workloads.device as D
+    prob = W.bubble_problem("st", 2, (128, 128), [(0.5, 0.5)], [0.1], W.P0, W.P0,
+                            div_amp=1e-6, div_seed=2, stiff=True)
+    op, b_p, b_T, p_ref, T_ref = orc.solve(prob, direct_max=40000)
+    for prec in (0, 1):
+        h, gb_p, gb_T, _ = D.setup(prob, prec)
+        p, T = torch.empty_like(gb_p), torch.empty_like(gb_T)
+        info = h.solve(gb_p, gb_T, p, T, rtol=1e-11, max_cycles=60)
+        assert info["status"] == 0, info
+        assert rel_err(host(p), p_ref) <= 1e-8 and rel_err(host(T), T_ref) <= 1e-8
+
+
+def test_mean_constraint_poisson():
+    """a11: B = 0 (pure Neumann Poisson in both components): zero-mean
+    solution of the projected right-hand side."""
+    import workloads.device as D
+    from paper_2206_11294_amd import ptmg
+    n = (80, 48)
+    N = n[0] * n[1]
+    rng = np.random.default_rng(1)
+    prob = W.Problem(name="poisson", dim=2, n=(80, 48, 1), h=1.0 / 80, mode="explicit",
+                     alpha_p=1.0, alpha_T=0.25, B_const=(0.0, 0.0, 0.0, 0.0),
+                     f_p=rng.uniform(-1, 1, N), f_T=rng.uniform(-1, 1, N), mean_constraint=True)
+    op = orc.assemble(prob)
+    fp = prob.f_p - prob.f_p.mean()
+    fT = prob.f_T - prob.f_T.mean()
+    p_ref, T_ref, cyc, _ = orc.mg_solve(op, fp, fT, rtol=1e-13, pin_mean=True)
+    assert cyc > 0
+    for prec in (0, 1):
+        h, b_p, b_T, _ = D.setup(prob, prec)
+        p, T = torch.empty_like(b_p), torch.empty_like(b_T)
+        info = h.solve(b_p, b_T, p, T, rtol=1e-11, max_cycles=60)
+        assert info["status"] == 0, info
+        assert abs(host(p).mean()) < 1e-12 * np.abs(p_ref).max()
+        assert rel_err(host(p), p_ref) <= 1e-8 and rel_err(host(T), T_ref) <= 1e-8
+
+
+def test_error_paths():
+    import workloads.device as D
+    from paper_2206_11294_amd import ptmg
+    prob = W.bubble_problem("e", 2, (32, 32), [(0.5, 0.5)], [0.2], W.P0, W.P0)
+    # C outside [0, 1]
+    bad = prob.C.copy()
+    bad.reshape(-1)[7] = 1.5
+    prob_bad = W.Problem(**{**prob.__dict__, "C": bad})
+    s, t = D.to_device(prob_bad)
+    with pytest.raises(ptmg.PtMgError) as e:
+        ptmg.PtMg(s, 0)
+    assert e.value.status == ptmg.PT_ERR_ARG
+    # a block with det < 0
+    pe = W.explicit_const(32, 32)
+    pe = W.Problem(**{**pe.__dict__, "B_const": (1.0, 3.0, 2.0, 1.0)})
+    s, t = D.to_device(pe)
+    with pytest.raises(ptmg.PtMgError) as e:
+        ptmg.PtMg(s, 0)
+    assert e.value.status == ptmg.PT_ERR_SINGULAR
+    # max_cycles reached: status returned, iterate finite, handle usable
+    h, b_p, b_T, _ = D.setup(prob, 1)
+    p, T = torch.empty_like(b_p), torch.empty_like(b_T)
+    info = h.solve(b_p, b_T, p, T, rtol=1e-15, max_cycles=1, raise_on_noconv=False)
+    assert info["status"] == ptmg.PT_ERR_NOCONV and info["cycles"] == 1
+    assert torch.isfinite(p).all() and torch.isfinite(T).all()
+    # non-finite right-hand side
+    b_nan = b_p.clone()
+    b_nan[5] = float("nan")
+    info = h.solve(b_nan, b_T, p, T, rtol=1e-9, raise_on_noconv=False)
+    assert info["status"] == ptmg.PT_ERR_NOCONV
+    info = h.solve(b_p, b_T, p, T, rtol=1e-10)
+    assert info["status"] == 0
+
+
+def test_timing_and_counters():
+    import workloads.device as D
+    prob = step_problems()["bubble3d_40x24x56"]
+    h, b_p, b_T, _ = D.setup(prob, 1)
+    p, T = torch.empty_like(b_p), torch.empty_like(b_T)
+    h.set_timing(True)
+    h.reset_stats()
+    info = h.solve(b_p, b_T, p, T, rtol=1e-9)
+    st = h.kernel_stats()
+    assert st["smooth_fine"]["launches"] == 2 * 4 * info["cycles"]
+    assert st["outer_residual"]["launches"] == info["cycles"] + 1
+    assert st["smooth_fine"]["ms"] > 0 and st["smooth_fine"]["bytes"] > 0
+    assert h.last_cell_updates() > 0

@@ -1,0 +1,77 @@
+"""Device-side marshalling of a workloads.Problem for the HIP library:
+copies the input fields to float64 device tensors and fills the C-ABI
+problem record.  No solver arithmetic."""
+from __future__ import annotations
+
+from typing import Dict, Optional, Tuple
+
+import numpy as np
+import torch
+
+from paper_2206_11294_amd import ptmg
+
+from . import Problem
+
+
+def _dev(a: Optional[np.ndarray], device) -> Optional[torch.Tensor]:
+    if a is None:
+        return None
+    return torch.from_numpy(np.array(a, dtype=np.float64, order="C").reshape(-1)).to(device)
+
+
+def _ph(ph) -> ptmg.pt_phase:
+    return ptmg.pt_phase(*ph.as_tuple())
+
+
+def to_device(prob: Problem, device="cuda") -> Tuple[ptmg.pt_problem, Dict[str, torch.Tensor]]:
+    """(pt_problem record, dict of device tensors it points to).  Keep the
+    dict alive while the record is used."""
+    t: Dict[str, torch.Tensor] = {}
+    s = ptmg.pt_problem()
+    s.dim = prob.dim
+    s.n[0], s.n[1], s.n[2] = prob.n
+    s.h = prob.h
+    if prob.mode == "explicit":
+        s.mode = ptmg.PT_COEF_EXPLICIT
+        s.alpha_p_const = prob.alpha_p
+        s.alpha_T_const = prob.alpha_T
+        for q in range(4):
+            s.B_const[q] = prob.B_const[q]
+        s.mean_constraint = int(prob.mean_constraint)
+        t["f_p"] = _dev(prob.f_p, device)
+        t["f_T"] = _dev(prob.f_T, device)
+    else:
+        s.mode = ptmg.PT_COEF_PHASES
+        t["C"] = _dev(prob.C, device)
+        s.C = t["C"].data_ptr()
+        s.liquid = _ph(prob.liquid)
+        s.gas = _ph(prob.gas)
+        s.dt = prob.dt
+        if prob.p_adv is not None:
+            t["p_adv"] = _dev(prob.p_adv, device)
+            s.p_adv = t["p_adv"].data_ptr()
+        if prob.T_adv is not None:
+            t["T_adv"] = _dev(prob.T_adv, device)
+            s.T_adv = t["T_adv"].data_ptr()
+        s.p_adv_const = prob.p_adv_const
+        s.T_adv_const = prob.T_adv_const
+        if prob.div_ustar is not None:
+            t["div"] = _dev(prob.div_ustar, device)
+    return s, t
+
+
+def precision_code(prob: Problem) -> int:
+    return ptmg.PT_PREC_MIXED if prob.precision == "mixed" else ptmg.PT_PREC_FP64
+
+
+def setup(prob: Problem, precision: Optional[int] = None, device="cuda", stream=None):
+    """Build the handle and the mode-native right-hand side on the device.
+    Returns (handle, b_p, b_T, tensors)."""
+    s, t = to_device(prob, device)
+    prec = precision_code(prob) if precision is None else precision
+    h = ptmg.PtMg(s, prec, stream=stream)
+    if prob.mode == "explicit":
+        b_p, b_T = t["f_p"], t["f_T"]
+    else:
+        b_p, b_T = h.paper_rhs(t.get("p_adv"), t.get("T_adv"), t.get("div"))
+    return h, b_p, b_T, t
