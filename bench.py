@@ -1,0 +1,256 @@
+#!/usr/bin/env python3
+"""Benchmark of the coupled pressure-temperature multigrid solve on one GPU.
+
+One step = one pass of the whole hot path over one synthetic input:
+re-assembly of the operator and hierarchy (pt_mg_update), the paper's
+right-hand side (pt_mg_paper_rhs) and the solve to tolerance
+(pt_mg_solve), with every input already resident in device memory.
+
+Prints one JSON line: cell-updates/s of the timed steps, the roofline of
+the dominant kernel (HIP-event durations of its launches inside the timed
+region, algorithmic bytes per launch), and the FP64 CPU oracle timed on
+the host on a bounded sample of the same workload.
+
+  python bench.py [--steps K] [--warmup W] [--workload NAME] [--precision fp64|mixed]
+  python bench.py --copy-calib BYTES    # plain copy kernel (counter calibration)
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E peak
+
+# name -> (constructor, default precision, rtol, configuration text)
+WORKLOADS = {
+    "explicit_64": ("explicit_const", "fp64", 1e-10),
+    "bubble2d_1024": ("bubble2d", "fp64", 1e-12),
+    "wall3d_256": ("wall3d", "mixed", 1e-12),
+    "collapse3d_512": ("collapse3d", "mixed", 1e-12),
+}
+
+
+def make_problem(name):
+    import workloads as W
+    if name == "explicit_64":
+        return W.explicit_const(64, 64)
+    if name == "bubble2d_1024":
+        return W.bubble2d(1024)
+    if name == "wall3d_256":
+        return W.wall3d(256)
+    if name == "collapse3d_512":
+        return W.collapse3d(512)
+    raise SystemExit(f"unknown workload {name}")
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("ptmg_kernels.hip", "ptmg_host.hip", "ptmg_internal.h"):
+        with open(os.path.join(ROOT, "paper_2206_11294_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(workload, kernel_class, launches_per_step):
+    """HBM bytes per launch of the dominant kernel from committed rocprofv3
+    counter summaries, when they were taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("source_hash") != kernel_source_hash() or rec.get("kernel_class") != kernel_class:
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def oracle_updates(orc, prob, cycles):
+    """Cell-updates of the oracle's solve: per V-cycle 4 sweeps and one
+    residual on every non-coarsest level, plus the two finest-grid
+    residuals of the outer loop; one final residual."""
+    import numpy as np  # noqa: F401
+    n = list(prob.n)
+    sizes = [n[0] * n[1] * n[2]]
+    for _ in range(orc.mg_levels(prob.dim, prob.n) - 1):
+        n = [n[a] // 2 if a < prob.dim else 1 for a in range(3)]
+        sizes.append(n[0] * n[1] * n[2])
+    per_cycle = sum(5 * s for s in sizes[:-1]) + 2 * sizes[0]
+    return cycles * per_cycle + sizes[0]
+
+
+def cpu_baseline(prob, rtol, budget_s):
+    """The oracle as it stands, on the host cores, on a bounded sample of
+    the same workload: whole steps (assembly, right-hand side, multigrid
+    solve to the same tolerance) repeated until the budget is used; when
+    one V-cycle already takes a large share of the budget, a single step
+    capped at one V-cycle."""
+    import oracle as orc
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+
+    def one_step(max_cycles):
+        t = time.perf_counter()
+        op = orc.assemble(prob)
+        b_p, b_T = orc.rhs(op, prob)
+        _, _, cyc, hist = orc.mg_solve(op, b_p, b_T, rtol=rtol, max_cycles=max_cycles,
+                                       pin_mean=prob.mean_constraint)
+        done = max_cycles if cyc < 0 else cyc
+        return time.perf_counter() - t, oracle_updates(orc, prob, done), done
+
+    total, updates, cycles = one_step(1)
+    reps, capped = 1, True
+    if total * 4 < budget_s:
+        capped = False
+        total, updates, reps, cycles = 0.0, 0, 0, 0
+        while total < budget_s:
+            dt, up, done = one_step(50)
+            total += dt
+            updates += up
+            cycles += done
+            reps += 1
+    sample = (f"{prob.name}: {reps} oracle step(s) of assembly + paper RHS + FP64 V(2,2) "
+              f"lexicographic multigrid ({cycles} V-cycles in all"
+              + (", capped at one V-cycle" if capped else f", rtol {rtol:g}")
+              + f"), {total:.1f} s")
+    return {"value": updates / total, "unit": "cell-updates/s", "cores": threads,
+            "kind": "oracle", "sample": sample}
+
+
+def copy_calibration(nbytes):
+    import torch
+    from paper_2206_11294_amd import ptmg
+    src = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        ptmg.copy_kernel(dst, src, nbytes)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes": nbytes, "launches": 3}), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="bubble2d_1024", choices=sorted(WORKLOADS))
+    ap.add_argument("--precision", choices=["fp64", "mixed"], default=None)
+    ap.add_argument("--rtol", type=float, default=None)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-oracle-check", action="store_true")
+    ap.add_argument("--copy-calib", type=int, default=0, metavar="BYTES")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(one request or grid per GPU); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import workloads.device as D
+    from paper_2206_11294_amd import ptmg
+
+    if args.copy_calib:
+        copy_calibration(args.copy_calib)
+
+    name = args.workload
+    _, prec_default, rtol_default = WORKLOADS[name]
+    prec_name = args.precision or prec_default
+    rtol = args.rtol if args.rtol is not None else rtol_default
+    prec = ptmg.PT_PREC_MIXED if prec_name == "mixed" else ptmg.PT_PREC_FP64
+    prob = make_problem(name)
+    print(f"# workload {name} grid {prob.n} precision {prec_name} rtol {rtol:g}",
+          file=sys.stderr, flush=True)
+
+    stream = torch.cuda.Stream()   # the library's stream (default priority)
+    with torch.cuda.stream(stream):
+        s, tens = D.to_device(prob)
+        h = ptmg.PtMg(s, prec, stream=stream)
+        p = torch.empty(prob.ncells, dtype=torch.float64, device="cuda")
+        T = torch.empty_like(p)
+
+        def step():
+            h.update(s)
+            if prob.mode == "phases":
+                b_p, b_T = h.paper_rhs(tens.get("p_adv"), tens.get("T_adv"), tens.get("div"))
+            else:
+                b_p, b_T = tens["f_p"], tens["f_T"]
+            info = h.solve(b_p, b_T, p, T, rtol=rtol, max_cycles=50)
+            return info, b_p, b_T
+
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        h.set_timing(True)
+        h.reset_stats()
+        updates = 0
+        cycles = []
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            info, b_p, b_T = step()
+            updates += h.last_cell_updates()
+            cycles.append(info["cycles"])
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        stats = h.kernel_stats()
+        h.set_timing(False)
+
+    # dominant kernel: the class with the most measured time
+    dom = max((k for k in stats if k != "other"), key=lambda k: stats[k]["ms"])
+    st = stats[dom]
+    avg_ms = st["ms"] / max(st["launches"], 1)
+    bytes_per_launch = st["bytes"] / max(st["launches"], 1)
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    traffic = traffic_from_profile(name, dom, st["launches"] / args.steps)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": dom, "avg_launch_us": round(avg_ms * 1e3, 2),
+                "alg_bytes_per_launch": bytes_per_launch, "launches": st["launches"]}
+    all_ms = sum(v["ms"] for v in stats.values())
+    all_bytes = sum(v["bytes"] for v in stats.values())
+
+    out = {
+        "metric": "coupled p-T cell-updates/s",
+        "value": updates / elapsed,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec_name == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": name, "grid": list(prob.n[: prob.dim]), "precision": prec_name,
+                   "rtol": rtol, "cycles_per_solve": float(np.mean(cycles)),
+                   "step": "pt_mg_update + pt_mg_paper_rhs + pt_mg_solve",
+                   "parallelism": "single GPU"},
+        "roofline": roofline,
+        "all_kernels": {"alg_GB_per_s": round(all_bytes / (all_ms * 1e-3) / 1e9, 1),
+                        "kernel_ms_per_step": round(all_ms / args.steps, 4),
+                        "by_class_ms_per_step": {k: round(v["ms"] / args.steps, 4)
+                                                 for k, v in stats.items()}},
+        "relres_last": list(info["relres"]),
+    }
+    if not args.no_oracle_check and prob.ncells <= 2_500_000:
+        import oracle as orc
+        op = orc.assemble(prob)
+        P, TT = p.cpu().numpy(), T.cpu().numpy()
+        bp, bT = b_p.cpu().numpy(), b_T.cpu().numpy()
+        out["oracle_relres_of_gpu_solution"] = [float(x) for x in orc.relres(op, bp, bT, P, TT)]
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(prob, rtol, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
