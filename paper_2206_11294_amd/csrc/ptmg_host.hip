@@ -22,7 +22,7 @@ struct LevelPlan {
     int n[3];
     long long N;
     double h;
-    size_t o_u, o_f, o_ac, o_fx, o_fy, o_fz, o_B;
+    size_t o_u, o_u2, o_f, o_ac, o_fx, o_fy, o_fz, o_B;   // o_u2: finest grid only
 };
 
 struct Plan {
@@ -97,8 +97,9 @@ const char *plan_problem(const pt_problem *p, int prec, Plan &P)
         L.h = h;
         L.o_u = P.take(2 * R * L.N);
         L.o_f = P.take(2 * R * L.N);
-        L.o_ac = L.o_fx = L.o_fy = L.o_fz = L.o_B = (size_t)-1;
+        L.o_u2 = L.o_ac = L.o_fx = L.o_fy = L.o_fz = L.o_B = (size_t)-1;
         if (l == 0) {
+            L.o_u2 = P.take(2 * R * L.N);   // the fused sweep writes to the other buffer
             if (prec == PT_PREC_MIXED) {
                 L.o_ac = P.take(2 * R * L.N);
                 L.o_B = P.take(4 * R * L.N);
@@ -122,7 +123,7 @@ const char *plan_problem(const pt_problem *p, int prec, Plan &P)
     P.o_gj0 = P.take(8ull * P.m * P.m);
     P.o_gj1 = P.take(8ull * P.m * P.m);
     P.nblocks = std::max(outer_blocks(P.N), sum2_blocks(P.N));
-    P.o_partials = P.take(8ull * (4 * (size_t)P.nblocks + 16));
+    P.o_partials = P.take(8ull * (4 * ((size_t)P.nblocks + reduce_scratch(P.nblocks)) + 16));
     P.o_flags = P.take(sizeof(int) * NFLAGS);
     P.o_norms = P.take(8 * 8);
     return nullptr;
@@ -146,6 +147,7 @@ struct pt_mg_s {
     std::string err = "no error";
     double *Ainv = nullptr;
     bool ready = false;
+    int u0_cur = 0;                 // which finest-grid buffer holds the current iterate
     // measurement
     bool timing = false;
     std::vector<hipEvent_t> ev_pool;
@@ -172,7 +174,7 @@ struct pt_mg_s {
         o.nz = L.n[2];
         o.N = L.N;
         o.inv_h2 = 1.0 / (L.h * L.h);
-        o.u = at<typename VT<R>::v2>(L.o_u);
+        o.u = at<typename VT<R>::v2>(l == 0 && u0_cur ? L.o_u2 : L.o_u);
         o.f = at<typename VT<R>::v2>(L.o_f);
         o.fx = at<typename VT<R>::v2>(L.o_fx);
         o.fy = at<typename VT<R>::v2>(L.o_fy);
@@ -269,10 +271,32 @@ double bytes_sweep_half(const Plan &P, int l, bool zero_guess)
     return N * (0.5 * (zero_guess ? 0 : 2 * R) + 0.5 * 2 * R + 0.5 * 4 * R + coef + 0.5 * 2 * R);
 }
 
+// Algorithmic bytes of one fused sweep: u, f, cell coefficients and block
+// read once (u not at all from a zero guess), u written once.
+double bytes_sweep_fused(const Plan &P, bool zero_guess)
+{
+    const double R = P.prec == PT_PREC_MIXED ? 4 : 8;
+    return (double)P.lv[0].N * R * (zero_guess ? 10 : 12);
+}
+
 template <typename R> void smooth(pt_mg_t h, int l, int sweeps, bool zero_guess)
 {
+    if (l == 0) {
+        // finest grid: fused red-black sweeps, ping-ponging the iterate
+        for (int s = 0; s < sweeps; s++) {
+            const bool zg = zero_guess && s == 0;
+            Lvl<R> L = h->level<R>(0);
+            h->u0_cur ^= 1;
+            typename VT<R>::v2 *uo = h->level<R>(0).u;
+            h->begin(PT_K_SMOOTH_FINE, bytes_sweep_fused(h->P, zg));
+            launch_rb_fused<R>(h->P.dim, L, uo, zg ? 1 : 0, h->stream);
+            h->end();
+            h->updates += L.N;
+        }
+        return;
+    }
     Lvl<R> L = h->level<R>(l);
-    const int cls = l == 0 ? PT_K_SMOOTH_FINE : PT_K_SMOOTH_COARSE;
+    const int cls = PT_K_SMOOTH_COARSE;
     for (int s = 0; s < sweeps; s++) {
         const bool zg = zero_guess && s == 0;
         h->begin(cls, bytes_sweep_half(h->P, l, zg));
@@ -542,7 +566,7 @@ int outer(pt_mg_t h, const double *b_p, const double *b_T, const double *src_p,
     a.src_T = src_T;
     a.dst_p = dst_p;
     a.dst_T = dst_T;
-    a.du = h->at<typename VT<RV>::v2>(P.lv[0].o_u);
+    a.du = h->level<RV>(0).u;
     a.r = want_r ? h->at<typename VT<RV>::v2>(P.lv[0].o_f) : nullptr;
     a.res_p = res_p;
     a.res_T = res_T;
@@ -593,7 +617,7 @@ double *grid_sums(pt_mg_t h, const double *x, const double *y, int slot)
 {
     const int nb = sum2_blocks(h->P.N);
     double *part = h->partials();
-    double *out = part + 4ll * h->P.nblocks + 8 + 2 * slot;
+    double *out = part + 4ll * (h->P.nblocks + reduce_scratch(h->P.nblocks)) + 8 + 2 * slot;
     h->begin(PT_K_OTHER, 16.0 * h->P.N);
     launch_sum2(h->P.N, x, y, part, nb, out, h->stream);
     h->end();

@@ -84,6 +84,7 @@ void launch_paper_rhs(long long N, const double4 *B64, const double *p_adv, doub
 template <typename RV>
 int launch_outer(int dim, const OuterArgs<RV> &a, hipStream_t s);   // returns #blocks
 int outer_blocks(long long N);
+int reduce_scratch(int nblocks);   // extra partial slots launch_reduce4 needs
 void launch_reduce4(const double *partials, int nblocks, double *out4, hipStream_t s);
 void launch_sum2(long long N, const double *x, const double *y, double *partials, int nblocks,
                  double *out2, hipStream_t s);   // out2 = (sum x, sum y), fixed order
@@ -94,6 +95,9 @@ void launch_shift2(long long N, double *x, double *y, const double *mean2, doubl
 template <typename R>
 void launch_rb_pass(int dim, int level0, const Lvl<R> &L, int color, int zero_guess,
                     hipStream_t s);
+template <typename R>
+void launch_rb_fused(int dim, const Lvl<R> &L, typename VT<R>::v2 *uo, int zero_guess,
+                     hipStream_t s);
 template <typename R>
 void launch_restrict(int dim, int level0, const Lvl<R> &F, const Lvl<R> &C, hipStream_t s);
 template <typename R>

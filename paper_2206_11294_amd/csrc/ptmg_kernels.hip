@@ -9,6 +9,8 @@
 // p-row := -(Eq. 28 - l4 Eq. 27)):
 //   (A u)_c = sum_faces w_c (u_c,cell - u_c,nbr) + (B u)_c,   w = a_face / h^2,
 // with zero flux through boundary faces.
+#include <algorithm>
+
 #include "ptmg_internal.h"
 
 namespace ptmg {
@@ -219,8 +221,8 @@ template <int DIM, typename RV>
 __global__ __launch_bounds__(kBlock) void k_outer(OuterArgs<RV> a)
 {
     using V2 = typename VT<RV>::v2;
-    long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    const long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
     if (t < a.N) {
         int i, j, k;
         decode(t, a.nx, a.ny, i, j, k);
@@ -289,10 +291,10 @@ __global__ __launch_bounds__(kBlock) void k_outer(OuterArgs<RV> a)
         }
         if (a.res_p) a.res_p[me] = resp;
         if (a.res_T) a.res_T[me] = resT;
-        acc[0] = resp * resp;
-        acc[1] = resT * resT;
-        acc[2] = bp * bp;
-        acc[3] = bT * bT;
+        acc[0] += resp * resp;
+        acc[1] += resT * resT;
+        acc[2] += bp * bp;
+        acc[3] += bT * bT;
     }
     block_reduce_store(acc, 4, a.partials + 4ll * blockIdx.x);
 }
@@ -302,7 +304,7 @@ int outer_blocks(long long N) { return (int)nblk(N); }
 template <typename RV>
 int launch_outer(int dim, const OuterArgs<RV> &a, hipStream_t s)
 {
-    unsigned nb = nblk(a.N);
+    unsigned nb = (unsigned)outer_blocks(a.N);
     if (dim == 3)
         hipLaunchKernelGGL((k_outer<3, RV>), dim3(nb), dim3(kBlock), 0, s, a);
     else
@@ -322,29 +324,56 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const double *partials, int n
     block_reduce_store(v, width, out);
 }
 
-void launch_reduce4(const double *partials, int nblocks, double *out4, hipStream_t s)
+// First stage of a two-stage fixed-order reduction: block b sums the
+// partials [b*kChunk, (b+1)*kChunk) (width doubles each).
+constexpr int kChunk = 1024;
+__global__ __launch_bounds__(kBlock) void k_reduce_stage(const double *partials, int nblocks,
+                                                         int width, double *out)
 {
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, s, partials, nblocks, 4, out4);
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    const int b0 = blockIdx.x * kChunk;
+    const int b1 = min(b0 + kChunk, nblocks);
+    for (int b = b0 + threadIdx.x; b < b1; b += kBlock)
+        for (int q = 0; q < width; q++) v[q] += partials[(long long)b * width + q];
+    block_reduce_store(v, width, out + (long long)blockIdx.x * width);
 }
 
+int reduce_scratch(int nblocks) { return nblocks > kChunk ? (nblocks + kChunk - 1) / kChunk : 0; }
+
+// partials[0 .. 4*nblocks) -> out4; uses partials[4*nblocks ..
+// 4*(nblocks + reduce_scratch(nblocks))) as scratch.
+void launch_reduce4(const double *partials, int nblocks, double *out4, hipStream_t s)
+{
+    const int g2 = reduce_scratch(nblocks);
+    if (g2 == 0) {
+        hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, s, partials, nblocks, 4, out4);
+        return;
+    }
+    double *mid = const_cast<double *>(partials) + 4ll * nblocks;
+    hipLaunchKernelGGL(k_reduce_stage, dim3(g2), dim3(kBlock), 0, s, partials, nblocks, 4, mid);
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, s, mid, g2, 4, out4);
+}
+
+// Grid-strided over at most kSumBlocks blocks (used once per solve).
+constexpr int kSumBlocks = 1024;
 __global__ __launch_bounds__(kBlock) void k_sum2(long long N, const double *x, const double *y,
                                                  double *partials)
 {
-    long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
     double v[2] = {0.0, 0.0};
-    if (t < N) {
-        v[0] = x[t];
-        v[1] = y[t];
+    const long long stride = (long long)gridDim.x * kBlock;
+    for (long long t = (long long)blockIdx.x * kBlock + threadIdx.x; t < N; t += stride) {
+        v[0] += x[t];
+        v[1] += y[t];
     }
     block_reduce_store(v, 2, partials + 2ll * blockIdx.x);
 }
 
-int sum2_blocks(long long N) { return (int)nblk(N); }
+int sum2_blocks(long long N) { return (int)std::min<long long>(nblk(N), kSumBlocks); }
 
 void launch_sum2(long long N, const double *x, const double *y, double *partials, int nblocks,
                  double *out2, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_sum2, dim3(nblk(N)), dim3(kBlock), 0, s, N, x, y, partials);
+    hipLaunchKernelGGL(k_sum2, dim3(sum2_blocks(N)), dim3(kBlock), 0, s, N, x, y, partials);
     hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, s, partials, nblocks, 2, out2);
 }
 
@@ -907,5 +936,418 @@ void launch_zero(void *p, size_t bytes, hipStream_t s)
     hipLaunchKernelGGL(k_zero, dim3((unsigned)blocks), dim3(kBlock), 0, s, (uint4 *)p, nvec,
                        (unsigned char *)p + nvec * 16, ntail);
 }
+
+}  // namespace ptmg
+
+namespace ptmg {
+
+// ------------------------------------------------ fused red-black sweep
+// One whole red-black sweep on the finest grid (cell coefficients) in a
+// single pass over memory.  A block owns an x-y tile of TX x TY cells and a
+// chunk of planes along the slowest axis (z in 3-D, y in 2-D), which it
+// walks in order.  LDS keeps a rolling window of 4 planes of (p, T) and of
+// the cell coefficients, each with a ring of 2 cells.  A red-black sweep
+// never reads a red cell's old value, so one LDS array per plane holds old
+// black and new red values.  At plane step k the block
+//   loads plane k+2, updates red on plane k+1 over the tile and a ring of
+//   one cell (reads old black on planes k..k+2), updates black on plane k
+//   over the tile (reads new red on planes k-1..k+1), writes plane k.
+// Cells outside the grid get zero coefficients, so the harmonic-mean face
+// weight to them is zero (no flux through the boundary).
+//
+// Block-to-tile mapping is XCD-aware: the hardware deals consecutive block
+// ids to the 8 XCDs in turn, so XCD x runs blocks b = x, x + 8, ...; block
+// b takes logical tile (tiles of XCDs before x) + b / 8, which gives each
+// XCD (and its L2) a contiguous run of tiles whose halos overlap.  With
+// q = nb / 8 and r = nb % 8, XCD x has q + (x < r) blocks, so the map is a
+// bijection of [0, nb).
+__device__ __forceinline__ int xcd_tile(int b, int nb)
+{
+    const int x = b & 7, q = nb >> 3, r = nb & 7;
+    return x * q + min(x, r) + (b >> 3);
+}
+
+template <typename R>
+__device__ __forceinline__ void block_solve(typename VT<R>::v2 f, typename VT<R>::v4 b, R gp_nb,
+                                            R gT_nb, R Sp, R ST, typename VT<R>::v2 &o)
+{
+    const R gp = f.x + gp_nb, gT = f.y + gT_nb;
+    const R a = b.x + Sp, d = b.w + ST;
+    const R inv = R(1) / (a * d - b.y * b.z);
+    o.x = (d * gp - b.y * gT) * inv;
+    o.y = (a * gT - b.z * gp) * inv;
+}
+
+template <typename R, int TX, int TY, bool ZG>
+__global__ __launch_bounds__(TX *TY) void k_rb_fused3(Lvl<R> L, typename VT<R>::v2 *__restrict__ uo,
+                                                      int zc, int tiles_x, int tiles_y, int ntiles)
+{
+    // Software-pipelined walk over a 5-plane LDS ring: while plane step k
+    // computes, the global loads of step k+1 (plane k+3 and the f, B of
+    // the next red and black cells) are in flight in registers.  Five
+    // slots let the store of plane k+2 overwrite plane k-3, whose last
+    // reader finished before the previous barrier, so each step needs
+    // two barriers.
+    using V2 = typename VT<R>::v2;
+    using V4 = typename VT<R>::v4;
+    constexpr int NT = TX * TY;
+    constexpr int PX = TX + 4, PY = TY + 4, PS = PX * PY;
+    constexpr int NLD = (PS + NT - 1) / NT;     // plane cells loaded per thread
+    constexpr int RW = (TX + 2) / 2;            // red cells per row of the ring region
+    constexpr int BW = TX / 2;                  // black cells per tile row
+    __shared__ V2 su[5][PS];
+    __shared__ V2 sa[5][PS];
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    if (tile >= ntiles) return;
+    const int txi = tile % tiles_x;
+    const int rr = tile / tiles_x;
+    const int tyi = rr % tiles_y;
+    const int tzi = rr / tiles_y;
+    const int x0 = txi * TX, y0 = tyi * TY;
+    const int z0 = tzi * zc, z1 = min(z0 + zc, L.nz);
+    const R ih2 = (R)L.inv_h2;
+    const long long nxy = (long long)L.nx * L.ny;
+    const int t = threadIdx.x;
+    auto slot = [](int z) { return (z + 10) % 5; };   // z >= -2
+
+    // ---- per-thread pieces of a plane step
+    V2 pu[NLD], pa[NLD];
+    auto fetch_plane = [&](int z) {
+#pragma unroll
+        for (int i = 0; i < NLD; i++) {
+            const int c = t + i * NT;
+            pu[i].x = pu[i].y = R(0);
+            pa[i].x = pa[i].y = R(0);
+            if (c < PS) {
+                const int gx = x0 + c % PX - 2, gy = y0 + c / PX - 2;
+                if (z >= 0 && z < L.nz && gx >= 0 && gx < L.nx && gy >= 0 && gy < L.ny) {
+                    const long long g = gx + (long long)L.nx * gy + nxy * z;
+                    pa[i] = L.ac[g];
+                    if (!ZG) pu[i] = L.u[g];
+                }
+            }
+        }
+    };
+    auto store_plane = [&](int z) {
+        const int s = slot(z);
+#pragma unroll
+        for (int i = 0; i < NLD; i++) {
+            const int c = t + i * NT;
+            if (c < PS) {
+                su[s][c] = pu[i];
+                sa[s][c] = pa[i];
+            }
+        }
+    };
+    // red cell of this thread on plane z: ring region [1, TX+2] x [1, TY+2]
+    auto red_cell = [&](int z, int &c, long long &g) {
+        c = -1;
+        if (z < 0 || z >= L.nz || t >= RW * (TY + 2)) return;
+        const int ly = 1 + t / RW;
+        const int gy = y0 + ly - 2;
+        const int lx = 1 + 2 * (t % RW) + ((x0 - 1 + gy + z) & 1);
+        const int gx = x0 + lx - 2;
+        if (gx < 0 || gx >= L.nx || gy < 0 || gy >= L.ny) return;
+        c = ly * PX + lx;
+        g = gx + (long long)L.nx * gy + nxy * z;
+    };
+    // black cell of this thread on plane z: tile interior
+    auto black_cell = [&](int z, int &c, long long &g) {
+        c = -1;
+        if (z < 0 || z >= L.nz || t >= BW * TY) return;
+        const int ly = 2 + t / BW;
+        const int gy = y0 + ly - 2;
+        const int lx = 2 + 2 * (t % BW) + (1 - ((x0 + gy + z) & 1));
+        const int gx = x0 + lx - 2;
+        if (gx >= L.nx || gy >= L.ny) return;
+        c = ly * PX + lx;
+        g = gx + (long long)L.nx * gy + nxy * z;
+    };
+    auto update = [&](int z, int c, V2 f, V4 b) {
+        const int s = slot(z), sm = slot(z - 1), sp = slot(z + 1);
+        const V2 am = sa[s][c];
+        R gp = R(0), gT = R(0), Sp = R(0), ST = R(0);
+        auto acc = [&](int ss, int q) {
+            V2 w = harm2(am, sa[ss][q]);
+            const R wp = w.x * ih2, wT = w.y * ih2;
+            const V2 uq = su[ss][q];
+            Sp += wp;
+            ST += wT;
+            gp += wp * uq.x;
+            gT += wT * uq.y;
+        };
+        acc(s, c - 1);
+        acc(s, c + 1);
+        acc(s, c - PX);
+        acc(s, c + PX);
+        acc(sm, c);
+        acc(sp, c);
+        V2 o;
+        block_solve<R>(f, b, gp, gT, Sp, ST, o);
+        su[s][c] = o;
+    };
+    auto write_plane = [&](int z) {
+        if (z < z0 || z >= z1) return;
+        const int s = slot(z);
+        const int lx = 2 + t % TX, ly = 2 + t / TX;
+        const int gx = x0 + lx - 2, gy = y0 + ly - 2;
+        if (gx < L.nx && gy < L.ny) uo[gx + (long long)L.nx * gy + nxy * z] = su[s][ly * PX + lx];
+    };
+
+    // ---- prologue: planes z0-2 .. z0+1, red on z0-1 and z0
+    for (int z = z0 - 2; z <= z0 + 1; z++) {
+        fetch_plane(z);
+        store_plane(z);
+    }
+    __syncthreads();
+    for (int z = z0 - 1; z <= z0; z++) {
+        int c;
+        long long g;
+        red_cell(z, c, g);
+        if (c >= 0) update(z, c, L.f[g], L.B[g]);
+        __syncthreads();
+    }
+    // in flight for step z0: plane z0+2, red of z0+1, black of z0
+    int rc, bc;
+    long long rg, bg;
+    V2 rf, bf;
+    V4 rB, bB;
+    fetch_plane(z0 + 2);
+    red_cell(z0 + 1, rc, rg);
+    if (rc >= 0) {
+        rf = L.f[rg];
+        rB = L.B[rg];
+    }
+    black_cell(z0, bc, bg);
+    if (bc >= 0) {
+        bf = L.f[bg];
+        bB = L.B[bg];
+    }
+    for (int k = z0; k < z1; k++) {
+        store_plane(k + 2);
+        // issue the loads of step k+1
+        int rcn, bcn;
+        long long rgn, bgn;
+        V2 rfn, bfn;
+        V4 rBn, bBn;
+        fetch_plane(k + 3);
+        red_cell(k + 2, rcn, rgn);
+        if (rcn >= 0) {
+            rfn = L.f[rgn];
+            rBn = L.B[rgn];
+        }
+        black_cell(k + 1, bcn, bgn);
+        if (bcn >= 0 && k + 1 < z1) {
+            bfn = L.f[bgn];
+            bBn = L.B[bgn];
+        }
+        __syncthreads();
+        write_plane(k - 1);
+        if (rc >= 0) update(k + 1, rc, rf, rB);
+        __syncthreads();
+        if (bc >= 0) update(k, bc, bf, bB);
+        rc = rcn;
+        rg = rgn;
+        rf = rfn;
+        rB = rBn;
+        bc = (k + 1 < z1) ? bcn : -1;
+        bg = bgn;
+        bf = bfn;
+        bB = bBn;
+    }
+    __syncthreads();
+    write_plane(z1 - 1);
+}
+
+// 2-D: planes are rows (march along y), the tile is TX cells along x; the
+// same software-pipelined 5-row ring as the 3-D kernel.
+template <typename R, int TX, bool ZG>
+__global__ __launch_bounds__(TX) void k_rb_fused2(Lvl<R> L, typename VT<R>::v2 *__restrict__ uo,
+                                                  int yc, int tiles_x, int ntiles)
+{
+    using V2 = typename VT<R>::v2;
+    using V4 = typename VT<R>::v4;
+    constexpr int PX = TX + 4;
+    constexpr int NLD = (PX + TX - 1) / TX;
+    constexpr int RW = (TX + 2) / 2;
+    __shared__ V2 su[5][PX];
+    __shared__ V2 sa[5][PX];
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    if (tile >= ntiles) return;
+    const int x0 = (tile % tiles_x) * TX;
+    const int y0 = (tile / tiles_x) * yc, y1 = min(y0 + yc, L.ny);
+    const R ih2 = (R)L.inv_h2;
+    const int t = threadIdx.x;
+    auto slot = [](int y) { return (y + 10) % 5; };
+
+    V2 pu[NLD], pa[NLD];
+    auto fetch_row = [&](int y) {
+#pragma unroll
+        for (int i = 0; i < NLD; i++) {
+            const int c = t + i * TX;
+            pu[i].x = pu[i].y = R(0);
+            pa[i].x = pa[i].y = R(0);
+            const int gx = x0 + c - 2;
+            if (c < PX && y >= 0 && y < L.ny && gx >= 0 && gx < L.nx) {
+                const long long g = gx + (long long)L.nx * y;
+                pa[i] = L.ac[g];
+                if (!ZG) pu[i] = L.u[g];
+            }
+        }
+    };
+    auto store_row = [&](int y) {
+        const int s = slot(y);
+#pragma unroll
+        for (int i = 0; i < NLD; i++) {
+            const int c = t + i * TX;
+            if (c < PX) {
+                su[s][c] = pu[i];
+                sa[s][c] = pa[i];
+            }
+        }
+    };
+    auto red_cell = [&](int y, int &c, long long &g) {
+        c = -1;
+        if (y < 0 || y >= L.ny || t >= RW) return;
+        const int lx = 1 + 2 * t + ((x0 - 1 + y) & 1);
+        const int gx = x0 + lx - 2;
+        if (gx < 0 || gx >= L.nx) return;
+        c = lx;
+        g = gx + (long long)L.nx * y;
+    };
+    auto black_cell = [&](int y, int &c, long long &g) {
+        c = -1;
+        if (y < 0 || y >= L.ny || t >= TX / 2) return;
+        const int lx = 2 + 2 * t + (1 - ((x0 + y) & 1));
+        const int gx = x0 + lx - 2;
+        if (gx >= L.nx) return;
+        c = lx;
+        g = gx + (long long)L.nx * y;
+    };
+    auto update = [&](int y, int c, V2 f, V4 b) {
+        const int s = slot(y), sm = slot(y - 1), sp = slot(y + 1);
+        const V2 am = sa[s][c];
+        R gp = R(0), gT = R(0), Sp = R(0), ST = R(0);
+        auto acc = [&](int ss, int q) {
+            V2 w = harm2(am, sa[ss][q]);
+            const R wp = w.x * ih2, wT = w.y * ih2;
+            const V2 uq = su[ss][q];
+            Sp += wp;
+            ST += wT;
+            gp += wp * uq.x;
+            gT += wT * uq.y;
+        };
+        acc(s, c - 1);
+        acc(s, c + 1);
+        acc(sm, c);
+        acc(sp, c);
+        V2 o;
+        block_solve<R>(f, b, gp, gT, Sp, ST, o);
+        su[s][c] = o;
+    };
+    auto write_row = [&](int y) {
+        if (y < y0 || y >= y1) return;
+        const int gx = x0 + t;
+        if (gx < L.nx) uo[gx + (long long)L.nx * y] = su[slot(y)][2 + t];
+    };
+
+    for (int y = y0 - 2; y <= y0 + 1; y++) {
+        fetch_row(y);
+        store_row(y);
+    }
+    __syncthreads();
+    for (int y = y0 - 1; y <= y0; y++) {
+        int c;
+        long long g;
+        red_cell(y, c, g);
+        if (c >= 0) update(y, c, L.f[g], L.B[g]);
+        __syncthreads();
+    }
+    int rc, bc;
+    long long rg, bg;
+    V2 rf, bf;
+    V4 rB, bB;
+    fetch_row(y0 + 2);
+    red_cell(y0 + 1, rc, rg);
+    if (rc >= 0) {
+        rf = L.f[rg];
+        rB = L.B[rg];
+    }
+    black_cell(y0, bc, bg);
+    if (bc >= 0) {
+        bf = L.f[bg];
+        bB = L.B[bg];
+    }
+    for (int k = y0; k < y1; k++) {
+        store_row(k + 2);
+        int rcn, bcn;
+        long long rgn, bgn;
+        V2 rfn, bfn;
+        V4 rBn, bBn;
+        fetch_row(k + 3);
+        red_cell(k + 2, rcn, rgn);
+        if (rcn >= 0) {
+            rfn = L.f[rgn];
+            rBn = L.B[rgn];
+        }
+        black_cell(k + 1, bcn, bgn);
+        if (bcn >= 0 && k + 1 < y1) {
+            bfn = L.f[bgn];
+            bBn = L.B[bgn];
+        }
+        __syncthreads();
+        write_row(k - 1);
+        if (rc >= 0) update(k + 1, rc, rf, rB);
+        __syncthreads();
+        if (bc >= 0) update(k, bc, bf, bB);
+        rc = rcn;
+        rg = rgn;
+        rf = rfn;
+        rB = rBn;
+        bc = (k + 1 < y1) ? bcn : -1;
+        bg = bgn;
+        bf = bfn;
+        bB = bBn;
+    }
+    __syncthreads();
+    write_row(y1 - 1);
+}
+
+// Reads the old iterate from L.u and writes the swept one to uo (a
+// different buffer: blocks read halo cells that other blocks update).
+template <typename R>
+void launch_rb_fused(int dim, const Lvl<R> &L, typename VT<R>::v2 *uo, int zero_guess,
+                     hipStream_t s)
+{
+    if (dim == 3) {
+        constexpr int TX = 64, TY = 4;
+        const int tx = (L.nx + TX - 1) / TX, ty = (L.ny + TY - 1) / TY;
+        // chunk the z walk so that the grid has a few thousand blocks
+        int zc = L.nz;
+        while (zc > 16 && (long long)tx * ty * ((L.nz + zc - 1) / zc) < 2048) zc = (zc + 1) / 2;
+        const int tz = (L.nz + zc - 1) / zc;
+        const int nt = tx * ty * tz;
+        if (zero_guess)
+            hipLaunchKernelGGL((k_rb_fused3<R, TX, TY, true>), dim3(nt), dim3(TX * TY), 0, s, L, uo,
+                               zc, tx, ty, nt);
+        else
+            hipLaunchKernelGGL((k_rb_fused3<R, TX, TY, false>), dim3(nt), dim3(TX * TY), 0, s, L,
+                               uo, zc, tx, ty, nt);
+    } else {
+        constexpr int TX = 256;
+        const int tx = (L.nx + TX - 1) / TX;
+        int yc = L.ny;
+        while (yc > 8 && (long long)tx * ((L.ny + yc - 1) / yc) < 1024) yc = (yc + 1) / 2;
+        const int nt = tx * ((L.ny + yc - 1) / yc);
+        if (zero_guess)
+            hipLaunchKernelGGL((k_rb_fused2<R, TX, true>), dim3(nt), dim3(TX), 0, s, L, uo, yc, tx,
+                               nt);
+        else
+            hipLaunchKernelGGL((k_rb_fused2<R, TX, false>), dim3(nt), dim3(TX), 0, s, L, uo, yc, tx,
+                               nt);
+    }
+}
+template void launch_rb_fused<float>(int, const Lvl<float> &, float2 *, int, hipStream_t);
+template void launch_rb_fused<double>(int, const Lvl<double> &, double2 *, int, hipStream_t);
 
 }  // namespace ptmg
