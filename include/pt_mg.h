@@ -236,8 +236,10 @@ typedef enum {
     PT_K_COUNT = 7
 } pt_kernel_class;
 
-/* Turn per-launch event timing on or off (off by default; on adds an
- * event pair around each launch). */
+/* Per-launch HIP-event timing (off by default): on = 0 off, 1 every
+ * kernel class, otherwise 1 + 2 * (bit mask of pt_kernel_class values)
+ * times only those classes.  Each timed launch gets an event pair on the
+ * handle's stream. */
 int pt_mg_set_timing(pt_mg_t h, int on);
 
 /* Launches and summed milliseconds of one class since the last reset,

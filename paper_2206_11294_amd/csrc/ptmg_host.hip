@@ -149,7 +149,7 @@ struct pt_mg_s {
     bool ready = false;
     int u0_cur = 0;                 // which finest-grid buffer holds the current iterate
     // measurement
-    bool timing = false;
+    unsigned timing = 0;            // bit c set: time launches of kernel class c
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used = 0;
     std::vector<TimerRec> pending;
@@ -204,7 +204,8 @@ struct pt_mg_s {
     {
         launches[cls]++;
         bytes[cls] += nbytes;
-        if (!timing) return;
+        timed_now = (timing >> cls) & 1u;
+        if (!timed_now) return;
         TimerRec r;
         r.cls = cls;
         r.a = event();
@@ -212,9 +213,10 @@ struct pt_mg_s {
         (void)hipEventRecord(r.a, stream);
         pending.push_back(r);
     }
+    bool timed_now = false;
     void end()
     {
-        if (!timing) return;
+        if (!timed_now) return;
         (void)hipEventRecord(pending.back().b, stream);
     }
     hipEvent_t event()
@@ -860,7 +862,7 @@ int pt_mg_vcycle(pt_mg_t h, const double *f_p, const double *f_T, double *e_p, d
 int pt_mg_set_timing(pt_mg_t h, int on)
 {
     if (!h) return fail(nullptr, PT_ERR_ARG, "handle is NULL");
-    h->timing = on != 0;
+    h->timing = on == 0 ? 0u : (on == 1 ? (1u << PT_K_COUNT) - 1u : (unsigned)on >> 1);
     return PT_OK;
 }
 

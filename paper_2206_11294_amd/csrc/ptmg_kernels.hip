@@ -10,6 +10,7 @@
 //   (A u)_c = sum_faces w_c (u_c,cell - u_c,nbr) + (B u)_c,   w = a_face / h^2,
 // with zero flux through boundary faces.
 #include <algorithm>
+#include <cstdlib>
 
 #include "ptmg_internal.h"
 
@@ -1320,19 +1321,37 @@ void launch_rb_fused(int dim, const Lvl<R> &L, typename VT<R>::v2 *uo, int zero_
                      hipStream_t s)
 {
     if (dim == 3) {
-        constexpr int TX = 64, TY = 4;
+        // tile 64 x TY: TY = 8 by default; 16 (FP32 only: its 5-plane LDS
+        // ring of a 68 x 20 plane needs 109 KB) or 4 through PTMG_TILE_Y
+        static const int ty_env = [] {
+            const char *e = getenv("PTMG_TILE_Y");
+            return e ? atoi(e) : 8;
+        }();
+        constexpr int TX = 64;
+        const int TY = (ty_env == 16 && sizeof(R) == 4) ? 16 : (ty_env == 4 ? 4 : 8);
         const int tx = (L.nx + TX - 1) / TX, ty = (L.ny + TY - 1) / TY;
-        // chunk the z walk so that the grid has a few thousand blocks
+        // chunk the z walk so that the grid has enough blocks to fill the chip
+        const long long want = TY == 16 ? 512 : (TY == 8 ? 1024 : 2048);
         int zc = L.nz;
-        while (zc > 16 && (long long)tx * ty * ((L.nz + zc - 1) / zc) < 2048) zc = (zc + 1) / 2;
+        while (zc > 16 && (long long)tx * ty * ((L.nz + zc - 1) / zc) < want) zc = (zc + 1) / 2;
         const int tz = (L.nz + zc - 1) / zc;
         const int nt = tx * ty * tz;
-        if (zero_guess)
-            hipLaunchKernelGGL((k_rb_fused3<R, TX, TY, true>), dim3(nt), dim3(TX * TY), 0, s, L, uo,
-                               zc, tx, ty, nt);
-        else
-            hipLaunchKernelGGL((k_rb_fused3<R, TX, TY, false>), dim3(nt), dim3(TX * TY), 0, s, L,
-                               uo, zc, tx, ty, nt);
+#define PTMG_FUSED3(TYC, ZGC)                                                                  \
+    hipLaunchKernelGGL((k_rb_fused3<R, TX, TYC, ZGC>), dim3(nt), dim3(TX * TYC), 0, s, L, uo, zc, \
+                       tx, ty, nt)
+        if (TY == 16) {
+            if constexpr (sizeof(R) == 4) {
+                if (zero_guess) PTMG_FUSED3(16, true);
+                else PTMG_FUSED3(16, false);
+            }
+        } else if (TY == 8) {
+            if (zero_guess) PTMG_FUSED3(8, true);
+            else PTMG_FUSED3(8, false);
+        } else {
+            if (zero_guess) PTMG_FUSED3(4, true);
+            else PTMG_FUSED3(4, false);
+        }
+#undef PTMG_FUSED3
     } else {
         constexpr int TX = 256;
         const int tx = (L.nx + TX - 1) / TX;

@@ -266,8 +266,18 @@ class PtMg:
                                        nu1, nu2))
         return e_p, e_T
 
-    def set_timing(self, on: bool):
-        self._check(lib().pt_mg_set_timing(self._h, int(on)))
+    def set_timing(self, on, classes=None):
+        """on: bool; classes: names from KERNEL_CLASSES to time (default all)."""
+        if not on:
+            code = 0
+        elif classes is None:
+            code = 1
+        else:
+            mask = 0
+            for c in classes:
+                mask |= 1 << KERNEL_CLASSES.index(c)
+            code = 1 + 2 * mask
+        self._check(lib().pt_mg_set_timing(self._h, code))
 
     def kernel_stats(self) -> Dict[str, Dict[str, float]]:
         out = {}
