@@ -254,6 +254,16 @@ int pt_mg_reset_stats(pt_mg_t h);
  * the one inside each restriction). */
 long long pt_mg_last_cell_updates(pt_mg_t h);
 
+/* Execution options of a handle (results are the same either way):
+ *  PT_OPT_GRAPHS: replay the coarse-level part of each V-cycle from a HIP
+ *    graph captured on first use (needs a non-null stream); default 1.
+ *  PT_OPT_TAIL: run the coarsest levels that fit in one block's LDS as a
+ *    single-block kernel; default 1.  pt_mg_get_option returns, for
+ *    PT_OPT_TAIL, the number of levels the tail covers (0 if none). */
+typedef enum { PT_OPT_GRAPHS = 1, PT_OPT_TAIL = 2 } pt_option;
+int pt_mg_set_option(pt_mg_t h, int option, int value);
+int pt_mg_get_option(pt_mg_t h, int option);
+
 /* A plain device copy of `bytes` bytes on the stream (hipStream_t or
  * NULL), for calibrating bandwidth counters.  Asynchronous. */
 int pt_copy_kernel(void *dst, const void *src, size_t bytes, void *hip_stream);

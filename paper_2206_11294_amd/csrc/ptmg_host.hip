@@ -5,6 +5,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -122,7 +123,8 @@ const char *plan_problem(const pt_problem *p, int prec, Plan &P)
     P.m = (int)(2 * Nc);
     P.o_gj0 = P.take(8ull * P.m * P.m);
     P.o_gj1 = P.take(8ull * P.m * P.m);
-    P.nblocks = std::max(outer_blocks(P.N), sum2_blocks(P.N));
+    P.nblocks = std::max(std::max(outer_blocks(P.N), sum2_blocks(P.N)),
+                         outer_zm_blocks(p->dim, p->n[0], p->n[1], p->n[2]));
     P.o_partials = P.take(8ull * (4 * ((size_t)P.nblocks + reduce_scratch(P.nblocks)) + 16));
     P.o_flags = P.take(sizeof(int) * NFLAGS);
     P.o_norms = P.take(8 * 8);
@@ -132,6 +134,17 @@ const char *plan_problem(const pt_problem *p, int prec, Plan &P)
 struct TimerRec {
     int cls;
     hipEvent_t a, b;
+};
+
+// A captured V-cycle of the coarse levels (1 .. L-1), with the counters its
+// launches add (capture records them once; each replay adds them again).
+struct CoarseGraph {
+    int key = -1;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    long launches[PT_K_COUNT] = {0};
+    double bytes[PT_K_COUNT] = {0};
+    long long updates = 0;
 };
 
 }  // namespace
@@ -157,6 +170,12 @@ struct pt_mg_s {
     double ms[PT_K_COUNT] = {0};
     double bytes[PT_K_COUNT] = {0};
     long long updates = 0, last_updates = 0;
+    std::vector<CoarseGraph> graphs;
+    bool use_graphs = true;
+    // single-block tail cycle over levels tail_lt .. nlev-1 (0: not used)
+    int tail_lt = 0;
+    size_t tail_lds = 0;
+    bool use_tail = true;
 
     template <typename T> T *at(size_t off) { return off == (size_t)-1 ? nullptr : (T *)(base + off); }
     double2 *ac64() { return at<double2>(P.o_ac64); }
@@ -317,7 +336,8 @@ template <typename R> void restrict_level(pt_mg_t h, int l)
     const double Rb = sizeof(R);
     const double coef = (l == 0 ? 2 : 2 * h->P.dim) * Rb;
     h->begin(PT_K_RESTRICT, (double)F.N * (8 * Rb + coef) + (double)C.N * 2 * Rb);
-    launch_restrict<R>(h->P.dim, l == 0, F, C, h->stream);
+    if (l == 0) launch_restrict_zm<R>(h->P.dim, F, C, h->stream);
+    else launch_restrict<R>(h->P.dim, 0, F, C, h->stream);
     h->end();
     h->updates += F.N;
 }
@@ -340,9 +360,109 @@ template <typename R> void coarse_solve(pt_mg_t h)
     h->end();
 }
 
+template <typename R> void vcycle(pt_mg_t h, int l, int nu1, int nu2);
+
+// Kernel classes launched by the coarse-level cycle.
+constexpr unsigned kCoarseClasses =
+    (1u << PT_K_SMOOTH_COARSE) | (1u << PT_K_RESTRICT) | (1u << PT_K_PROLONG) |
+    (1u << PT_K_COARSE_SOLVE) | (1u << PT_K_OTHER);
+
+// The V-cycle of levels 1 .. L-1 as one HIP graph launch (captured on first
+// use per (nu1, nu2)): the coarse levels are small and their kernels are
+// bound by launch submission.  Direct launches when the handle's stream is
+// the null stream (it cannot be captured) or a coarse class is being timed.
+template <typename R> void coarse_cycle(pt_mg_t h, int nu1, int nu2)
+{
+    if (!h->use_graphs || !h->stream || (h->timing & kCoarseClasses)) {
+        vcycle<R>(h, 1, nu1, nu2);
+        return;
+    }
+    const int key = nu1 * 16 + nu2;
+    CoarseGraph *g = nullptr;
+    for (auto &c : h->graphs)
+        if (c.key == key) g = &c;
+    if (!g) {
+        CoarseGraph c;
+        c.key = key;
+        long l0[PT_K_COUNT];
+        double b0[PT_K_COUNT];
+        for (int q = 0; q < PT_K_COUNT; q++) {
+            l0[q] = h->launches[q];
+            b0[q] = h->bytes[q];
+        }
+        const long long u0 = h->updates;
+        bool ok = hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
+        if (ok) {
+            vcycle<R>(h, 1, nu1, nu2);
+            ok = hipStreamEndCapture(h->stream, &c.graph) == hipSuccess && c.graph;
+        }
+        if (ok) ok = hipGraphInstantiate(&c.exec, c.graph, nullptr, nullptr, 0) == hipSuccess;
+        for (int q = 0; q < PT_K_COUNT; q++) {
+            c.launches[q] = h->launches[q] - l0[q];
+            c.bytes[q] = h->bytes[q] - b0[q];
+            h->launches[q] = l0[q];
+            h->bytes[q] = b0[q];
+        }
+        c.updates = h->updates - u0;
+        h->updates = u0;
+        if (!ok) {
+            (void)hipGetLastError();
+            if (c.graph) (void)hipGraphDestroy(c.graph);
+            h->use_graphs = false;   // fall back to direct launches for good
+            vcycle<R>(h, 1, nu1, nu2);
+            return;
+        }
+        h->graphs.push_back(c);
+        g = &h->graphs.back();
+    }
+    (void)hipGraphLaunch(g->exec, h->stream);
+    for (int q = 0; q < PT_K_COUNT; q++) {
+        h->launches[q] += g->launches[q];
+        h->bytes[q] += g->bytes[q];
+    }
+    h->updates += g->updates;
+}
+
+template <typename R> void tail_cycle(pt_mg_t h, int nu1, int nu2)
+{
+    const Plan &P = h->P;
+    TailArgs<R> a;
+    std::memset(&a, 0, sizeof a);
+    a.nl = P.nlev - h->tail_lt;
+    a.m = P.m;
+    a.nu1 = nu1;
+    a.nu2 = nu2;
+    a.Ainv = h->Ainv;
+    size_t off = 0;
+    double nbytes = 8.0 * P.m * P.m;
+    for (int q = 0; q < a.nl; q++) {
+        const int l = h->tail_lt + q;
+        a.g[q] = h->level<R>(l);
+        const long long N = P.lv[l].N;
+        const size_t v2 = ((2 * sizeof(R) * N) + 15) & ~size_t(15);
+        const size_t v4 = ((4 * sizeof(R) * N) + 15) & ~size_t(15);
+        a.off[q][0] = (int)off; off += v2;
+        a.off[q][1] = (int)off; off += v2;
+        a.off[q][2] = (int)off; off += v2;
+        a.off[q][3] = (int)off; off += v2;
+        a.off[q][4] = (int)off; if (P.dim == 3) off += v2;
+        a.off[q][5] = (int)off; off += v4;
+        nbytes += (double)N * sizeof(R) * (4 + 2 * P.dim);
+        if (q + 1 < a.nl) h->updates += (long long)(nu1 + nu2 + 1) * N;
+    }
+    nbytes += 4.0 * sizeof(R) * P.lv[h->tail_lt].N;   // f in, u out
+    h->begin(PT_K_COARSE_SOLVE, nbytes);
+    launch_tail<R>(P.dim, a, h->tail_lds, h->stream);
+    h->end();
+}
+
 // V(nu1, nu2) cycle on level l for A e = f_l, e in u_l, from a zero guess.
 template <typename R> void vcycle(pt_mg_t h, int l, int nu1, int nu2)
 {
+    if (h->use_tail && h->tail_lt > 0 && l == h->tail_lt) {
+        tail_cycle<R>(h, nu1, nu2);
+        return;
+    }
     if (l == h->P.nlev - 1) {
         coarse_solve<R>(h);
         return;
@@ -355,7 +475,8 @@ template <typename R> void vcycle(pt_mg_t h, int l, int nu1, int nu2)
     }
     smooth<R>(h, l, nu1, true);
     restrict_level<R>(h, l);
-    vcycle<R>(h, l + 1, nu1, nu2);
+    if (l == 0) coarse_cycle<R>(h, nu1, nu2);
+    else vcycle<R>(h, l + 1, nu1, nu2);
     prolong_level<R>(h, l);
     smooth<R>(h, l, nu2, false);
 }
@@ -389,12 +510,16 @@ template <typename R> void build_hierarchy(pt_mg_t h)
         launch_coarse_dense<double>(P.dim, 1, h->level0_fp64(), pin, M0, h->stream);
     else
         launch_coarse_dense<R>(P.dim, 0, h->level<R>(P.nlev - 1), pin, M0, h->stream);
-    double *src = M0, *dst = M1;
-    for (int k = 0; k < P.m; k++) {
-        launch_gj_step(src, dst, P.m, k, h->flags(), h->stream);
-        std::swap(src, dst);
+    if (launch_gj_lds(M0, M1, P.m, h->flags(), h->stream)) {
+        h->Ainv = M1;
+    } else {
+        double *src = M0, *dst = M1;
+        for (int k = 0; k < P.m; k++) {
+            launch_gj_step(src, dst, P.m, k, h->flags(), h->stream);
+            std::swap(src, dst);
+        }
+        h->Ainv = src;
     }
-    h->Ainv = src;
 }
 
 int assemble(pt_mg_t h, const pt_problem *p)
@@ -450,6 +575,36 @@ int assemble(pt_mg_t h, const pt_problem *p)
     return PT_OK;
 }
 
+// The single-block tail covers the coarsest levels (at least two, none the
+// finest) whose arrays fit together in one block's LDS.
+void plan_tail(pt_mg_t h)
+{
+    const Plan &P = h->P;
+    h->tail_lt = 0;
+    if (P.nlev < 3) return;
+    int dev = 0, lds_max = 0;
+    (void)hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+        lds_max = 65536;
+    const size_t budget = (size_t)std::max(0, lds_max - 4096);
+    const bool f32 = P.prec == PT_PREC_MIXED;
+    auto need = [&](int l) {
+        return f32 ? tail_level_lds<float>(P.dim, P.lv[l].N) : tail_level_lds<double>(P.dim, P.lv[l].N);
+    };
+    size_t total = need(P.nlev - 1);
+    int lt = P.nlev - 1;
+    for (int l = P.nlev - 2; l >= 1; l--) {
+        if (total + need(l) > budget || P.nlev - l > kMaxTail) break;
+        total += need(l);
+        lt = l;
+    }
+    if (P.nlev - lt < 2) return;
+    h->tail_lt = lt;
+    h->tail_lds = total;
+    if (f32) tail_set_lds_limit<float>(P.dim, total);
+    else tail_set_lds_limit<double>(P.dim, total);
+}
+
 bool same_grid(const pt_problem *a, const pt_problem *b)
 {
     return a->dim == b->dim && a->n[0] == b->n[0] && a->n[1] == b->n[1] && a->n[2] == b->n[2] &&
@@ -475,12 +630,14 @@ size_t pt_mg_footprint_bytes(const pt_problem *prob, int precision)
 
 int pt_mg_setup(const pt_problem *prob, int precision, void *hip_stream, pt_mg_t *out)
 {
+    static const bool graphs_env = !getenv("PTMG_NO_GRAPHS");
     if (!out) return fail(nullptr, PT_ERR_ARG, "out is NULL");
     *out = nullptr;
     Plan P;
     if (const char *why = plan_problem(prob, precision, P)) return fail(nullptr, PT_ERR_ARG, why);
     pt_mg_t h = new pt_mg_s();
     h->P = P;
+    h->use_graphs = graphs_env;
     h->stream = (hipStream_t)hip_stream;
     hipError_t e = hipMalloc(&h->base, P.total);
     if (e != hipSuccess) {
@@ -495,6 +652,7 @@ int pt_mg_setup(const pt_problem *prob, int precision, void *hip_stream, pt_mg_t
         pt_mg_destroy(h);
         return fail(nullptr, PT_ERR_OOM, "pinned host allocation failed");
     }
+    plan_tail(h);
     int rc = assemble(h, prob);
     if (rc != PT_OK) {
         g_thread_err = h->err;
@@ -581,7 +739,7 @@ int outer(pt_mg_t h, const double *b_p, const double *b_T, const double *src_p,
     if (res_p) nbytes += 8.0 * P.N;
     if (res_T) nbytes += 8.0 * P.N;
     h->begin(PT_K_OUTER_RESIDUAL, nbytes);
-    int nb = launch_outer<RV>(P.dim, a, h->stream);
+    int nb = launch_outer_zm<RV>(P.dim, a, h->stream);
     h->end();
     h->updates += P.N;
     return nb;
@@ -888,6 +1046,23 @@ int pt_mg_reset_stats(pt_mg_t h)
 }
 
 long long pt_mg_last_cell_updates(pt_mg_t h) { return h ? h->last_updates : 0; }
+
+int pt_mg_set_option(pt_mg_t h, int option, int value)
+{
+    if (!h) return fail(nullptr, PT_ERR_ARG, "handle is NULL");
+    if (option == PT_OPT_GRAPHS) h->use_graphs = value != 0;
+    else if (option == PT_OPT_TAIL) h->use_tail = value != 0;
+    else return fail(h, PT_ERR_ARG, "unknown option");
+    return PT_OK;
+}
+
+int pt_mg_get_option(pt_mg_t h, int option)
+{
+    if (!h) return -1;
+    if (option == PT_OPT_GRAPHS) return h->use_graphs ? 1 : 0;
+    if (option == PT_OPT_TAIL) return (h->use_tail && h->tail_lt > 0) ? h->P.nlev - h->tail_lt : 0;
+    return -1;
+}
 
 int pt_copy_kernel(void *dst, const void *src, size_t bytes, void *hip_stream)
 {

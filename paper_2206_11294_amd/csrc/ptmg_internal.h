@@ -74,6 +74,16 @@ enum { FLAG_ARG = 0, FLAG_SINGULAR = 1, FLAG_BNONZERO = 2, FLAG_PIVOT = 3, NFLAG
 
 constexpr int kBlock = 256;
 constexpr int kMaxLevels = 24;
+constexpr int kMaxTail = 8;
+
+// Arguments of the single-block tail cycle: global views of its levels and
+// the LDS byte offsets of each level's u, f, fx, fy, fz, B.
+template <typename R> struct TailArgs {
+    int nl, m, nu1, nu2;
+    Lvl<R> g[kMaxTail];
+    int off[kMaxTail][6];
+    const double *Ainv;
+};
 
 // ---- launch wrappers (implemented in ptmg_kernels.hip) --------------------
 void launch_assemble(const AsmArgs &a, hipStream_t s);
@@ -83,6 +93,9 @@ void launch_paper_rhs(long long N, const double4 *B64, const double *p_adv, doub
 
 template <typename RV>
 int launch_outer(int dim, const OuterArgs<RV> &a, hipStream_t s);   // returns #blocks
+template <typename RV>
+int launch_outer_zm(int dim, const OuterArgs<RV> &a, hipStream_t s);   // returns #blocks
+int outer_zm_blocks(int dim, int nx, int ny, int nz);
 int outer_blocks(long long N);
 int reduce_scratch(int nblocks);   // extra partial slots launch_reduce4 needs
 void launch_reduce4(const double *partials, int nblocks, double *out4, hipStream_t s);
@@ -101,6 +114,12 @@ void launch_rb_fused(int dim, const Lvl<R> &L, typename VT<R>::v2 *uo, int zero_
 template <typename R>
 void launch_restrict(int dim, int level0, const Lvl<R> &F, const Lvl<R> &C, hipStream_t s);
 template <typename R>
+void launch_restrict_zm(int dim, const Lvl<R> &F, const Lvl<R> &C, hipStream_t s);  // finest grid
+template <typename R> size_t tail_level_lds(int dim, long long N);
+template <typename R>
+bool launch_tail(int dim, const TailArgs<R> &a, size_t lds_bytes, hipStream_t s);
+template <typename R> void tail_set_lds_limit(int dim, size_t bytes);
+template <typename R>
 void launch_prolong(int dim, const Lvl<R> &F, const Lvl<R> &C, hipStream_t s);
 template <typename RIN, typename ROUT>
 void launch_coarsen(int dim, int level0, const Lvl<RIN> &F, typename VT<ROUT>::v2 *fx,
@@ -110,6 +129,7 @@ template <typename R>
 void launch_coarse_dense(int dim, int level0, const Lvl<R> &L, int pin_mean, double *M,
                          hipStream_t s);
 void launch_gj_step(const double *A, double *Bm, int m, int k, int *flags, hipStream_t s);
+bool launch_gj_lds(const double *A, double *Ainv, int m, int *flags, hipStream_t s);  // m <= 128
 template <typename R>
 void launch_coarse_apply(const double *Ainv, int m, const R *f, R *u, hipStream_t s);
 template <typename R>

@@ -399,25 +399,15 @@ void launch_shift2(long long N, double *x, double *y, const double *sum2, double
 //   (B + diag(S_p, S_T)) u = f + sum_faces w u_nbr
 // by Cramer's rule.  zero_guess: the neighbours are taken as zero (first
 // red pass from a zero initial guess; the stale values are never read).
-template <typename R, int DIM, bool CF>
-__global__ __launch_bounds__(kBlock) void k_rb_pass(Lvl<R> L, int color, int zero_guess)
+// The block Gauss-Seidel update of one cell (shared by the grid kernels
+// and the single-block tail cycle, whose arrays live in LDS).
+template <typename R, int DIM, bool CF, bool USE_U>
+__device__ __forceinline__ void rb_cell(const Lvl<R> &L, int i, int j, int k, long long me)
 {
     using V2 = typename VT<R>::v2;
     using V4 = typename VT<R>::v4;
-    long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
-    const int nxh = (L.nx + 1) >> 1;
-    const long long tot = (long long)nxh * L.ny * L.nz;
-    if (t >= tot) return;
-    int ti, j, k;
-    decode(t, nxh, L.ny, ti, j, k);
-    const int i = 2 * ti + ((j + k + color) & 1);
-    if (i >= L.nx) return;
-    const long long me = i + (long long)L.nx * (j + (long long)L.ny * k);
     R nbp, nbT, Sp, ST;
-    if (zero_guess)
-        gather<R, DIM, CF, false>(L, i, j, k, me, nbp, nbT, Sp, ST);
-    else
-        gather<R, DIM, CF, true>(L, i, j, k, me, nbp, nbT, Sp, ST);
+    gather<R, DIM, CF, USE_U>(L, i, j, k, me, nbp, nbT, Sp, ST);
     const V2 f = L.f[me];
     const V4 b = L.B[me];
     const R gp = f.x + nbp, gT = f.y + nbT;
@@ -429,49 +419,41 @@ __global__ __launch_bounds__(kBlock) void k_rb_pass(Lvl<R> L, int color, int zer
     L.u[me] = o;
 }
 
-template <typename R>
-void launch_rb_pass(int dim, int level0, const Lvl<R> &L, int color, int zero_guess,
-                    hipStream_t s)
-{
-    const long long tot = (long long)((L.nx + 1) >> 1) * L.ny * L.nz;
-    dim3 g(nblk(tot)), b(kBlock);
-    if (dim == 3) {
-        if (level0) hipLaunchKernelGGL((k_rb_pass<R, 3, true>), g, b, 0, s, L, color, zero_guess);
-        else hipLaunchKernelGGL((k_rb_pass<R, 3, false>), g, b, 0, s, L, color, zero_guess);
-    } else {
-        if (level0) hipLaunchKernelGGL((k_rb_pass<R, 2, true>), g, b, 0, s, L, color, zero_guess);
-        else hipLaunchKernelGGL((k_rb_pass<R, 2, false>), g, b, 0, s, L, color, zero_guess);
-    }
-}
-template void launch_rb_pass<float>(int, int, const Lvl<float> &, int, int, hipStream_t);
-template void launch_rb_pass<double>(int, int, const Lvl<double> &, int, int, hipStream_t);
-
-// ------------------------------------------------ residual + restriction
-// Coarse right-hand side = mean over the 2^DIM children of f - A u.
+// Residual f - A u at one cell.
 template <typename R, int DIM, bool CF>
-__global__ __launch_bounds__(kBlock) void k_restrict(Lvl<R> F, Lvl<R> C)
+__device__ __forceinline__ typename VT<R>::v2 residual_cell(const Lvl<R> &F, int i, int j, int k,
+                                                            long long me)
 {
     using V2 = typename VT<R>::v2;
     using V4 = typename VT<R>::v4;
-    long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
-    if (t >= C.N) return;
-    int I, J, K;
-    decode(t, C.nx, C.ny, I, J, K);
+    R nbp, nbT, Sp, ST;
+    gather<R, DIM, CF, true>(F, i, j, k, me, nbp, nbT, Sp, ST);
+    const V2 u = F.u[me];
+    const V2 f = F.f[me];
+    const V4 b = F.B[me];
+    const R Ap = Sp * u.x - nbp + b.x * u.x + b.y * u.y;
+    const R AT = ST * u.y - nbT + b.z * u.x + b.w * u.y;
+    V2 r;
+    r.x = f.x - Ap;
+    r.y = f.y - AT;
+    return r;
+}
+
+// Coarse right-hand side at coarse cell (I, J, K): mean over the children.
+template <typename R, int DIM, bool CF>
+__device__ __forceinline__ void restrict_cell(const Lvl<R> &F, const Lvl<R> &C, int I, int J, int K,
+                                              long long t)
+{
+    using V2 = typename VT<R>::v2;
     R sp = R(0), sT = R(0);
 #pragma unroll
     for (int m = 0; m < (1 << DIM); m++) {
         const int i = 2 * I + (m & 1), j = 2 * J + ((m >> 1) & 1);
         const int k = DIM == 3 ? 2 * K + ((m >> 2) & 1) : 0;
         const long long me = i + (long long)F.nx * (j + (long long)F.ny * k);
-        R nbp, nbT, Sp, ST;
-        gather<R, DIM, CF, true>(F, i, j, k, me, nbp, nbT, Sp, ST);
-        const V2 u = F.u[me];
-        const V2 f = F.f[me];
-        const V4 b = F.B[me];
-        const R Ap = Sp * u.x - nbp + b.x * u.x + b.y * u.y;
-        const R AT = ST * u.y - nbT + b.z * u.x + b.w * u.y;
-        sp += f.x - Ap;
-        sT += f.y - AT;
+        const V2 r = residual_cell<R, DIM, CF>(F, i, j, k, me);
+        sp += r.x;
+        sT += r.y;
     }
     const R sc = R(1) / R(1 << DIM);
     V2 o;
@@ -480,33 +462,14 @@ __global__ __launch_bounds__(kBlock) void k_restrict(Lvl<R> F, Lvl<R> C)
     C.f[t] = o;
 }
 
-template <typename R>
-void launch_restrict(int dim, int level0, const Lvl<R> &F, const Lvl<R> &C, hipStream_t s)
-{
-    dim3 g(nblk(C.N)), b(kBlock);
-    if (dim == 3) {
-        if (level0) hipLaunchKernelGGL((k_restrict<R, 3, true>), g, b, 0, s, F, C);
-        else hipLaunchKernelGGL((k_restrict<R, 3, false>), g, b, 0, s, F, C);
-    } else {
-        if (level0) hipLaunchKernelGGL((k_restrict<R, 2, true>), g, b, 0, s, F, C);
-        else hipLaunchKernelGGL((k_restrict<R, 2, false>), g, b, 0, s, F, C);
-    }
-}
-template void launch_restrict<float>(int, int, const Lvl<float> &, const Lvl<float> &, hipStream_t);
-template void launch_restrict<double>(int, int, const Lvl<double> &, const Lvl<double> &,
-                                      hipStream_t);
-
-// ------------------------------------------- prolongation + correction
-// u += P e: along each axis weight 3/4 on the parent and 1/4 on the
-// parent's neighbour on the fine cell's side (the parent at a boundary).
+// u += P e at fine cell (i, j, k): along each axis weight 3/4 on the parent
+// and 1/4 on the parent's neighbour on the fine cell's side (the parent at
+// a boundary).
 template <typename R, int DIM>
-__global__ __launch_bounds__(kBlock) void k_prolong(Lvl<R> F, Lvl<R> C)
+__device__ __forceinline__ void prolong_cell(const Lvl<R> &F, const Lvl<R> &C, int i, int j, int k,
+                                             long long t)
 {
     using V2 = typename VT<R>::v2;
-    long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
-    if (t >= F.N) return;
-    int i, j, k;
-    decode(t, F.nx, F.ny, i, j, k);
     int par[3] = {i >> 1, j >> 1, DIM == 3 ? k >> 1 : 0};
     int nbr[3];
     const int fi[3] = {i, j, k};
@@ -542,6 +505,83 @@ __global__ __launch_bounds__(kBlock) void k_prolong(Lvl<R> F, Lvl<R> C)
     u.x += vp;
     u.y += vT;
     F.u[t] = u;
+}
+
+// One colour of a red-black 2x2-block Gauss-Seidel sweep: each cell of
+// colour (i+j+k) mod 2 == color solves
+//   (B + diag(S_p, S_T)) u = f + sum_faces w u_nbr
+// by Cramer's rule.  zero_guess: the neighbours are taken as zero (first
+// red pass from a zero initial guess; the stale values are never read).
+template <typename R, int DIM, bool CF>
+__global__ __launch_bounds__(kBlock) void k_rb_pass(Lvl<R> L, int color, int zero_guess)
+{
+    long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
+    const int nxh = (L.nx + 1) >> 1;
+    const long long tot = (long long)nxh * L.ny * L.nz;
+    if (t >= tot) return;
+    int ti, j, k;
+    decode(t, nxh, L.ny, ti, j, k);
+    const int i = 2 * ti + ((j + k + color) & 1);
+    if (i >= L.nx) return;
+    const long long me = i + (long long)L.nx * (j + (long long)L.ny * k);
+    if (zero_guess) rb_cell<R, DIM, CF, false>(L, i, j, k, me);
+    else rb_cell<R, DIM, CF, true>(L, i, j, k, me);
+}
+
+template <typename R>
+void launch_rb_pass(int dim, int level0, const Lvl<R> &L, int color, int zero_guess,
+                    hipStream_t s)
+{
+    const long long tot = (long long)((L.nx + 1) >> 1) * L.ny * L.nz;
+    dim3 g(nblk(tot)), b(kBlock);
+    if (dim == 3) {
+        if (level0) hipLaunchKernelGGL((k_rb_pass<R, 3, true>), g, b, 0, s, L, color, zero_guess);
+        else hipLaunchKernelGGL((k_rb_pass<R, 3, false>), g, b, 0, s, L, color, zero_guess);
+    } else {
+        if (level0) hipLaunchKernelGGL((k_rb_pass<R, 2, true>), g, b, 0, s, L, color, zero_guess);
+        else hipLaunchKernelGGL((k_rb_pass<R, 2, false>), g, b, 0, s, L, color, zero_guess);
+    }
+}
+template void launch_rb_pass<float>(int, int, const Lvl<float> &, int, int, hipStream_t);
+template void launch_rb_pass<double>(int, int, const Lvl<double> &, int, int, hipStream_t);
+
+// ------------------------------------------------ residual + restriction
+// Coarse right-hand side = mean over the 2^DIM children of f - A u.
+template <typename R, int DIM, bool CF>
+__global__ __launch_bounds__(kBlock) void k_restrict(Lvl<R> F, Lvl<R> C)
+{
+    long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= C.N) return;
+    int I, J, K;
+    decode(t, C.nx, C.ny, I, J, K);
+    restrict_cell<R, DIM, CF>(F, C, I, J, K, t);
+}
+
+template <typename R>
+void launch_restrict(int dim, int level0, const Lvl<R> &F, const Lvl<R> &C, hipStream_t s)
+{
+    dim3 g(nblk(C.N)), b(kBlock);
+    if (dim == 3) {
+        if (level0) hipLaunchKernelGGL((k_restrict<R, 3, true>), g, b, 0, s, F, C);
+        else hipLaunchKernelGGL((k_restrict<R, 3, false>), g, b, 0, s, F, C);
+    } else {
+        if (level0) hipLaunchKernelGGL((k_restrict<R, 2, true>), g, b, 0, s, F, C);
+        else hipLaunchKernelGGL((k_restrict<R, 2, false>), g, b, 0, s, F, C);
+    }
+}
+template void launch_restrict<float>(int, int, const Lvl<float> &, const Lvl<float> &, hipStream_t);
+template void launch_restrict<double>(int, int, const Lvl<double> &, const Lvl<double> &,
+                                      hipStream_t);
+
+// ------------------------------------------- prolongation + correction
+template <typename R, int DIM>
+__global__ __launch_bounds__(kBlock) void k_prolong(Lvl<R> F, Lvl<R> C)
+{
+    long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= F.N) return;
+    int i, j, k;
+    decode(t, F.nx, F.ny, i, j, k);
+    prolong_cell<R, DIM>(F, C, i, j, k, t);
 }
 
 template <typename R>
@@ -727,8 +767,8 @@ template void launch_coarse_dense<double>(int, int, const Lvl<double> &, int, do
                                           hipStream_t);
 
 // One Gauss-Jordan elimination step without pivoting (out of place):
-// pivot p = A[k][k]; A'[k][k] = 1/p; A'[k][j] = A[k][j]/p;
-// A'[i][k] = -A[i][k]/p; A'[i][j] = A[i][j] - A[i][k] A[k][j]/p.
+// pivot p = A[k][k], q = 1/p; A'[k][k] = q; A'[k][j] = A[k][j] q;
+// A'[i][k] = -A[i][k] q; A'[i][j] = A[i][j] - A[i][k] (A[k][j] q).
 // After m steps the matrix holds its inverse.  Pivots of the coarse
 // operator are positive (positive diagonals and det of every 2x2 block,
 // block-diagonally dominant rows); a pivot that is not is flagged.
@@ -739,16 +779,17 @@ __global__ __launch_bounds__(kBlock) void k_gj_step(const double *A, double *Bm,
     if (t >= (long long)m * m) return;
     const int i = (int)(t / m), j = (int)(t % m);
     const double p = A[(long long)k * m + k];
+    const double q = 1.0 / p;
     double v;
     if (i == k && j == k) {
-        v = 1.0 / p;
+        v = q;
         if (!(p > 0.0) || !isfinite(p)) atomicOr(&flags[FLAG_PIVOT], 1);
     } else if (i == k) {
-        v = A[(long long)k * m + j] / p;
+        v = A[(long long)k * m + j] * q;
     } else if (j == k) {
-        v = -A[(long long)i * m + k] / p;
+        v = -A[(long long)i * m + k] * q;
     } else {
-        v = A[t] - A[(long long)i * m + k] * (A[(long long)k * m + j] / p);
+        v = A[t] - A[(long long)i * m + k] * (A[(long long)k * m + j] * q);
     }
     Bm[t] = v;
 }
@@ -1368,5 +1409,571 @@ void launch_rb_fused(int dim, const Lvl<R> &L, typename VT<R>::v2 *uo, int zero_
 }
 template void launch_rb_fused<float>(int, const Lvl<float> &, float2 *, int, hipStream_t);
 template void launch_rb_fused<double>(int, const Lvl<double> &, double2 *, int, hipStream_t);
+
+}  // namespace ptmg
+
+namespace ptmg {
+
+// Gauss-Jordan inversion without pivoting of an m x m matrix (m <= 128) in
+// one block, the matrix resident in LDS: the same elimination as k_gj_step,
+// with the pivot row and column copied aside before each update.
+constexpr int kGJLdsMax = 128;
+__global__ __launch_bounds__(1024) void k_gj_lds(const double *A, double *Ainv, int m, int *flags)
+{
+    __shared__ double M[kGJLdsMax * kGJLdsMax];
+    __shared__ double rowk[kGJLdsMax], colk[kGJLdsMax];
+    const int nt = blockDim.x;
+    const int mm = m * m;
+    for (int e = threadIdx.x; e < mm; e += nt) M[e] = A[e];
+    __syncthreads();
+    for (int k = 0; k < m; k++) {
+        const double p = M[k * m + k];
+        const double q = 1.0 / p;
+        // scaled pivot row and the pivot column, as in k_gj_step
+        for (int e = threadIdx.x; e < m; e += nt) {
+            rowk[e] = M[k * m + e] * q;
+            colk[e] = M[e * m + k];
+        }
+        if (threadIdx.x == 0 && (!(p > 0.0) || !isfinite(p))) atomicOr(&flags[FLAG_PIVOT], 1);
+        __syncthreads();
+        for (int i = threadIdx.x / m; i < m; i += nt / m) {
+            const int j = threadIdx.x % m;
+            const int e = i * m + j;
+            double v;
+            if (i == k && j == k) v = q;
+            else if (i == k) v = rowk[j];
+            else if (j == k) v = -colk[i] * q;
+            else v = M[e] - colk[i] * rowk[j];
+            M[e] = v;
+        }
+        __syncthreads();
+    }
+    for (int e = threadIdx.x; e < mm; e += nt) Ainv[e] = M[e];
+}
+
+bool launch_gj_lds(const double *A, double *Ainv, int m, int *flags, hipStream_t s)
+{
+    if (m > kGJLdsMax) return false;
+    // threads per block: a multiple of m (each thread keeps one column j)
+    const int nt = (1024 / m) * m;
+    hipLaunchKernelGGL(k_gj_lds, dim3(1), dim3(nt), 0, s, A, Ainv, m, flags);
+    return true;
+}
+
+}  // namespace ptmg
+
+namespace ptmg {
+
+// -------------------------------------------- plane-marching stencils
+// The FP64 outer residual and the finest-grid residual + restriction as
+// z-marching tiles: a 4-slot LDS ring of planes (tile + a ring of one
+// cell) so that every array element is read from HBM once, with the next
+// plane and the next cells' pointwise data prefetched into registers while
+// the current plane computes (one barrier per plane).  A 2-D grid runs as a
+// flat 3-D one (ny = 1, planes = rows, TY = 1, no y neighbours).
+template <int TY> struct Flat { static constexpr bool v = TY == 1; };
+
+template <int DIM, typename RV, int TX, int TY>
+__global__ __launch_bounds__(TX *TY) void k_outer_zm(OuterArgs<RV> a, int NX, int NY, int NZ,
+                                                     int zc, int tiles_x, int tiles_y, int ntiles)
+{
+    using V2 = typename VT<RV>::v2;
+    constexpr bool FLAT = Flat<TY>::v;
+    constexpr int NT = TX * TY;
+    constexpr int PX = TX + 2, PY = FLAT ? 1 : TY + 2, PS = PX * PY;
+    constexpr int NLD = (PS + NT - 1) / NT;
+    __shared__ double2 su[4][PS];
+    __shared__ double2 sa[4][PS];
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int t = threadIdx.x;
+    if (tile < ntiles) {
+        const int txi = tile % tiles_x;
+        const int rr = tile / tiles_x;
+        const int x0 = txi * TX, y0 = (rr % tiles_y) * TY;
+        const int z0 = (rr / tiles_y) * zc, z1 = min(z0 + zc, NZ);
+        const long long nxy = (long long)NX * NY;
+        const int oy = FLAT ? 0 : 1;
+        double2 pu[NLD], pa[NLD];
+        auto fetch = [&](int z) {
+#pragma unroll
+            for (int i = 0; i < NLD; i++) {
+                const int c = t + i * NT;
+                pu[i] = make_double2(0.0, 0.0);
+                pa[i] = make_double2(0.0, 0.0);
+                const int gx = x0 + c % PX - 1, gy = y0 + c / PX - oy;
+                if (c < PS && z >= 0 && z < NZ && gx >= 0 && gx < NX && gy >= 0 && gy < NY) {
+                    const long long g = gx + (long long)NX * gy + nxy * z;
+                    double2 v = make_double2(a.src_p[g], a.src_T[g]);
+                    if (a.update) {
+                        const V2 d = a.du[g];
+                        v.x += (double)d.x;
+                        v.y += (double)d.y;
+                    }
+                    pu[i] = v;
+                    pa[i] = a.ac[g];
+                }
+            }
+        };
+        auto store = [&](int z) {
+            const int s = z & 3;
+#pragma unroll
+            for (int i = 0; i < NLD; i++) {
+                const int c = t + i * NT;
+                if (c < PS) {
+                    su[s][c] = pu[i];
+                    sa[s][c] = pa[i];
+                }
+            }
+        };
+        // this thread's interior cell
+        const int lx = 1 + t % TX, ly = oy + t / TX;
+        const int gx = x0 + lx - 1, gy = y0 + ly - oy;
+        const bool mine = gx < NX && gy < NY;
+        const int c = ly * PX + lx;
+        double4 Bn;
+        double bpn = 0.0, bTn = 0.0;
+        auto fetch_cell = [&](int z) {
+            if (mine && z < z1) {
+                const long long g = gx + (long long)NX * gy + nxy * z;
+                Bn = a.B[g];
+                bpn = a.b_p[g];
+                bTn = a.b_T[g];
+            }
+        };
+        fetch(z0 - 1);
+        store(z0 - 1);
+        fetch(z0);
+        store(z0);
+        fetch_cell(z0);
+        double4 B = Bn;
+        double bp0 = bpn, bT0 = bTn;
+        fetch(z0 + 1);
+        for (int k = z0; k < z1; k++) {
+            store(k + 1);
+            fetch(k + 2);
+            fetch_cell(k + 1);
+            __syncthreads();
+            if (mine) {
+                const int s = k & 3, sm = (k + 3) & 3, sp = (k + 1) & 3;
+                const double2 um = su[s][c];
+                const double2 am = sa[s][c];
+                double nbp = 0.0, nbT = 0.0, Sp = 0.0, ST = 0.0;
+                auto nb = [&](int ss, int q) {
+                    double2 w = harm2(am, sa[ss][q]);
+                    w.x *= a.inv_h2;
+                    w.y *= a.inv_h2;
+                    const double2 uq = su[ss][q];
+                    Sp += w.x;
+                    ST += w.y;
+                    nbp += w.x * uq.x;
+                    nbT += w.y * uq.y;
+                };
+                nb(s, c - 1);
+                nb(s, c + 1);
+                if (!FLAT) {
+                    nb(s, c - PX);
+                    nb(s, c + PX);
+                }
+                nb(sm, c);
+                nb(sp, c);
+                const double Lp = Sp * um.x - nbp;   // -div(a_p grad p)
+                const double LT = ST * um.y - nbT;   // -div(a_T grad T)
+                double bp = bp0, bT = bT0;
+                if (a.bshift) {
+                    bp -= a.bshift_scale * a.bshift[0];
+                    bT -= a.bshift_scale * a.bshift[1];
+                }
+                double resp, resT, rp, rT;
+                if (a.phases) {
+                    const double l1 = -B.w, l2 = -B.z, l4 = B.y / l1, l3 = -B.x + l4 * l2;
+                    resT = bT - (-LT + l1 * um.y + l2 * um.x);
+                    resp = bp - (-Lp + l3 * um.x + l4 * (-LT));
+                    rT = -resT;
+                    rp = -resp + l4 * resT;
+                } else {
+                    rp = bp - (Lp + B.x * um.x + B.y * um.y);
+                    rT = bT - (LT + B.z * um.x + B.w * um.y);
+                    resp = rp;
+                    resT = rT;
+                }
+                const long long g = gx + (long long)NX * gy + nxy * k;
+                if (a.update) {
+                    a.dst_p[g] = um.x;
+                    a.dst_T[g] = um.y;
+                }
+                if (a.r) {
+                    V2 o;
+                    o.x = (RV)rp;
+                    o.y = (RV)rT;
+                    a.r[g] = o;
+                }
+                if (a.res_p) a.res_p[g] = resp;
+                if (a.res_T) a.res_T[g] = resT;
+                acc[0] += resp * resp;
+                acc[1] += resT * resT;
+                acc[2] += bp * bp;
+                acc[3] += bT * bT;
+            }
+            B = Bn;
+            bp0 = bpn;
+            bT0 = bTn;
+        }
+    }
+    block_reduce_store(acc, 4, a.partials + 4ll * blockIdx.x);
+}
+
+// Launch geometry of the plane-marching outer residual (shared with the
+// host's partial-sum sizing).
+struct ZmGeom {
+    int NX, NY, NZ, tx, ty, zc, nt;
+};
+
+static ZmGeom outer_geom(int dim, int nx, int ny, int nz)
+{
+    ZmGeom g;
+    if (dim == 3) {
+        g.NX = nx; g.NY = ny; g.NZ = nz;
+        g.tx = (nx + 63) / 64;
+        g.ty = (ny + 3) / 4;
+    } else {
+        g.NX = nx; g.NY = 1; g.NZ = ny;
+        g.tx = (nx + 255) / 256;
+        g.ty = 1;
+    }
+    g.zc = g.NZ;
+    while (g.zc > 8 && (long long)g.tx * g.ty * ((g.NZ + g.zc - 1) / g.zc) < 2048)
+        g.zc = (g.zc + 1) / 2;
+    g.nt = g.tx * g.ty * ((g.NZ + g.zc - 1) / g.zc);
+    return g;
+}
+
+int outer_zm_blocks(int dim, int nx, int ny, int nz) { return outer_geom(dim, nx, ny, nz).nt; }
+
+template <typename RV>
+int launch_outer_zm(int dim, const OuterArgs<RV> &a, hipStream_t s)
+{
+    const ZmGeom g = outer_geom(dim, a.nx, a.ny, a.nz);
+    if (dim == 3)
+        hipLaunchKernelGGL((k_outer_zm<3, RV, 64, 4>), dim3(g.nt), dim3(256), 0, s, a, g.NX, g.NY,
+                           g.NZ, g.zc, g.tx, g.ty, g.nt);
+    else
+        hipLaunchKernelGGL((k_outer_zm<2, RV, 256, 1>), dim3(g.nt), dim3(256), 0, s, a, g.NX, g.NY,
+                           g.NZ, g.zc, g.tx, g.ty, g.nt);
+    return g.nt;
+}
+template int launch_outer_zm<float>(int, const OuterArgs<float> &, hipStream_t);
+template int launch_outer_zm<double>(int, const OuterArgs<double> &, hipStream_t);
+
+// Finest-grid residual f - A u and its restriction (mean of the 2^d
+// children) to the coarse right-hand side, plane-marching like k_outer_zm.
+// Coarse plane K collects fine planes 2K and 2K+1, so chunks start on even
+// planes; the 2x2 (2-D: 2) in-plane sums go through LDS.
+template <typename R, int TX, int TY>
+__global__ __launch_bounds__(TX *TY) void k_restrict_zm(Lvl<R> F, Lvl<R> C, int NX, int NY, int NZ,
+                                                        int zc, int tiles_x, int tiles_y,
+                                                        int ntiles)
+{
+    using V2 = typename VT<R>::v2;
+    using V4 = typename VT<R>::v4;
+    constexpr bool FLAT = Flat<TY>::v;
+    constexpr int NT = TX * TY;
+    constexpr int PX = TX + 2, PY = FLAT ? 1 : TY + 2, PS = PX * PY;
+    constexpr int NLD = (PS + NT - 1) / NT;
+    constexpr int CX = TX / 2, CY = FLAT ? 1 : TY / 2;
+    __shared__ V2 su[4][PS];
+    __shared__ V2 sa[4][PS];
+    __shared__ V2 sr[NT];
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    if (tile >= ntiles) return;
+    const int t = threadIdx.x;
+    const int txi = tile % tiles_x;
+    const int rr = tile / tiles_x;
+    const int x0 = txi * TX, y0 = (rr % tiles_y) * TY;
+    const int z0 = (rr / tiles_y) * zc, z1 = min(z0 + zc, NZ);
+    const long long nxy = (long long)NX * NY;
+    const int oy = FLAT ? 0 : 1;
+    const R ih2 = (R)F.inv_h2;
+    V2 pu[NLD], pa[NLD];
+    auto fetch = [&](int z) {
+#pragma unroll
+        for (int i = 0; i < NLD; i++) {
+            const int c = t + i * NT;
+            pu[i].x = pu[i].y = R(0);
+            pa[i].x = pa[i].y = R(0);
+            const int gx = x0 + c % PX - 1, gy = y0 + c / PX - oy;
+            if (c < PS && z >= 0 && z < NZ && gx >= 0 && gx < NX && gy >= 0 && gy < NY) {
+                const long long g = gx + (long long)NX * gy + nxy * z;
+                pu[i] = F.u[g];
+                pa[i] = F.ac[g];
+            }
+        }
+    };
+    auto store = [&](int z) {
+        const int s = z & 3;
+#pragma unroll
+        for (int i = 0; i < NLD; i++) {
+            const int c = t + i * NT;
+            if (c < PS) {
+                su[s][c] = pu[i];
+                sa[s][c] = pa[i];
+            }
+        }
+    };
+    const int lx = 1 + t % TX, ly = oy + t / TX;
+    const int gx = x0 + lx - 1, gy = y0 + ly - oy;
+    const bool mine = gx < NX && gy < NY;
+    const int c = ly * PX + lx;
+    V2 fn;
+    V4 Bn;
+    auto fetch_cell = [&](int z) {
+        if (mine && z < z1) {
+            const long long g = gx + (long long)NX * gy + nxy * z;
+            fn = F.f[g];
+            Bn = F.B[g];
+        }
+    };
+    // coarse cell of this thread (t < CX * CY)
+    const int cxl = t % CX, cyl = t / CX;
+    const int CNX = NX / 2, CNY = FLAT ? 1 : NY / 2;
+    const int gcx = x0 / 2 + cxl, gcy = FLAT ? 0 : y0 / 2 + cyl;
+    const bool cmine = t < CX * CY && gcx < CNX && gcy < CNY;
+    R accp = R(0), accT = R(0);
+
+    fetch(z0 - 1);
+    store(z0 - 1);
+    fetch(z0);
+    store(z0);
+    fetch_cell(z0);
+    V2 f = fn;
+    V4 B = Bn;
+    fetch(z0 + 1);
+    for (int k = z0; k < z1; k++) {
+        store(k + 1);
+        fetch(k + 2);
+        fetch_cell(k + 1);
+        __syncthreads();
+        V2 r;
+        r.x = r.y = R(0);
+        if (mine) {
+            const int s = k & 3, sm = (k + 3) & 3, sp = (k + 1) & 3;
+            const V2 um = su[s][c];
+            const V2 am = sa[s][c];
+            R nbp = R(0), nbT = R(0), Sp = R(0), ST = R(0);
+            auto nb = [&](int ss, int q) {
+                V2 w = harm2(am, sa[ss][q]);
+                const R wp = w.x * ih2, wT = w.y * ih2;
+                const V2 uq = su[ss][q];
+                Sp += wp;
+                ST += wT;
+                nbp += wp * uq.x;
+                nbT += wT * uq.y;
+            };
+            nb(s, c - 1);
+            nb(s, c + 1);
+            if (!FLAT) {
+                nb(s, c - PX);
+                nb(s, c + PX);
+            }
+            nb(sm, c);
+            nb(sp, c);
+            const R Ap = Sp * um.x - nbp + B.x * um.x + B.y * um.y;
+            const R AT = ST * um.y - nbT + B.z * um.x + B.w * um.y;
+            r.x = f.x - Ap;
+            r.y = f.y - AT;
+        }
+        sr[t] = r;
+        __syncthreads();
+        if (cmine) {
+            // children (2 cxl + a, 2 cyl + b) of the tile, in x then y order
+            const int base = 2 * cyl * TX + 2 * cxl;
+            const V2 r00 = sr[base], r10 = sr[base + 1];
+            R sp_ = r00.x + r10.x, sT_ = r00.y + r10.y;
+            if (!FLAT) {
+                const V2 r01 = sr[base + TX], r11 = sr[base + TX + 1];
+                sp_ += r01.x + r11.x;
+                sT_ += r01.y + r11.y;
+            }
+            accp += sp_;
+            accT += sT_;
+            if (k & 1) {
+                const R sc = FLAT ? R(0.25) : R(0.125);
+                V2 o;
+                o.x = accp * sc;
+                o.y = accT * sc;
+                C.f[gcx + (long long)CNX * gcy + (long long)CNX * CNY * (k >> 1)] = o;
+                accp = accT = R(0);
+            }
+        }
+        f = fn;
+        B = Bn;
+    }
+}
+
+template <typename R>
+void launch_restrict_zm(int dim, const Lvl<R> &F, const Lvl<R> &C, hipStream_t s)
+{
+    int NX, NY, NZ, tx, ty;
+    if (dim == 3) {
+        NX = F.nx; NY = F.ny; NZ = F.nz;
+        tx = (NX + 63) / 64;
+        ty = (NY + 3) / 4;
+    } else {
+        NX = F.nx; NY = 1; NZ = F.ny;
+        tx = (NX + 255) / 256;
+        ty = 1;
+    }
+    int zc = NZ;   // even (the grid coarsens), kept even below
+    while (zc > 8 && (long long)tx * ty * ((NZ + zc - 1) / zc) < 2048) zc = ((zc + 1) / 2 + 1) & ~1;
+    const int nt = tx * ty * ((NZ + zc - 1) / zc);
+    if (dim == 3)
+        hipLaunchKernelGGL((k_restrict_zm<R, 64, 4>), dim3(nt), dim3(256), 0, s, F, C, NX, NY, NZ,
+                           zc, tx, ty, nt);
+    else
+        hipLaunchKernelGGL((k_restrict_zm<R, 256, 1>), dim3(nt), dim3(256), 0, s, F, C, NX, NY, NZ,
+                           zc, tx, ty, nt);
+}
+template void launch_restrict_zm<float>(int, const Lvl<float> &, const Lvl<float> &, hipStream_t);
+template void launch_restrict_zm<double>(int, const Lvl<double> &, const Lvl<double> &, hipStream_t);
+
+}  // namespace ptmg
+
+namespace ptmg {
+
+// ------------------------------------------------- single-block tail cycle
+// The V-cycle of the coarsest few levels (all with stored faces) in one
+// block of 1024 threads, every array in LDS: these levels have tens to a
+// few thousand cells, so as separate kernels they are bound by launch
+// latency.  Same steps and arithmetic as the grid kernels: red-black
+// sweeps (zero guess on the first red pass), residual + restriction, the
+// FP64 inverse on the coarsest grid (matrix read from global memory),
+// prolongation + correction.  Input: f of the first tail level; output:
+// its u.
+template <typename R, int DIM>
+__global__ __launch_bounds__(1024) void k_tail(TailArgs<R> A)
+{
+    using V2 = typename VT<R>::v2;
+    using V4 = typename VT<R>::v4;
+    extern __shared__ __align__(16) unsigned char lds[];
+    __shared__ Lvl<R> L[kMaxTail];
+    const int nt = blockDim.x, t = threadIdx.x;
+    const int nl = A.nl;
+    if (t < nl) {
+        Lvl<R> v = A.g[t];
+        v.u = (V2 *)(lds + A.off[t][0]);
+        v.f = (V2 *)(lds + A.off[t][1]);
+        v.fx = (const V2 *)(lds + A.off[t][2]);
+        v.fy = (const V2 *)(lds + A.off[t][3]);
+        v.fz = DIM == 3 ? (const V2 *)(lds + A.off[t][4]) : nullptr;
+        v.B = (const V4 *)(lds + A.off[t][5]);
+        L[t] = v;
+    }
+    __syncthreads();
+    // operators of every tail level and the right-hand side of the first
+    for (int q = 0; q < nl; q++) {
+        const Lvl<R> &G = A.g[q];
+        const long long N = G.N;
+        for (long long e = t; e < N; e += nt) {
+            ((V2 *)L[q].fx)[e] = G.fx[e];
+            ((V2 *)L[q].fy)[e] = G.fy[e];
+            if (DIM == 3) ((V2 *)L[q].fz)[e] = G.fz[e];
+            ((V4 *)L[q].B)[e] = G.B[e];
+            if (q == 0) L[q].f[e] = G.f[e];
+        }
+    }
+    __syncthreads();
+    auto sweep = [&](int q, bool zero_guess) {
+        const Lvl<R> &V = L[q];
+        for (int color = 0; color < 2; color++) {
+            for (long long e = t; e < V.N; e += nt) {
+                int i, j, k;
+                decode(e, V.nx, V.ny, i, j, k);
+                if (((i + j + k) & 1) != color) continue;
+                if (zero_guess && color == 0) rb_cell<R, DIM, false, false>(V, i, j, k, e);
+                else rb_cell<R, DIM, false, true>(V, i, j, k, e);
+            }
+            __syncthreads();
+        }
+    };
+    for (int q = 0; q + 1 < nl; q++) {
+        if (A.nu1 == 0) {
+            for (long long e = t; e < L[q].N; e += nt) {
+                V2 z;
+                z.x = z.y = R(0);
+                L[q].u[e] = z;
+            }
+            __syncthreads();
+        }
+        for (int s = 0; s < A.nu1; s++) sweep(q, s == 0);
+        const Lvl<R> &C = L[q + 1];
+        for (long long e = t; e < C.N; e += nt) {
+            int I, J, K;
+            decode(e, C.nx, C.ny, I, J, K);
+            restrict_cell<R, DIM, false>(L[q], C, I, J, K, e);
+        }
+        __syncthreads();
+    }
+    {   // coarsest grid: u = Ainv f in FP64, one wave per row
+        const Lvl<R> &C = L[nl - 1];
+        const R *f = (const R *)C.f;
+        R *u = (R *)C.u;
+        const int lane = t & 63, wave = t >> 6, nw = nt >> 6;
+        for (int row = wave; row < A.m; row += nw) {
+            const double *a = A.Ainv + (long long)row * A.m;
+            double s = 0.0;
+            for (int c = lane; c < A.m; c += 64) s += a[c] * (double)f[c];
+            for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+            if (lane == 0) u[row] = (R)s;
+        }
+        __syncthreads();
+    }
+    for (int q = nl - 2; q >= 0; q--) {
+        const Lvl<R> &V = L[q];
+        for (long long e = t; e < V.N; e += nt) {
+            int i, j, k;
+            decode(e, V.nx, V.ny, i, j, k);
+            prolong_cell<R, DIM>(V, L[q + 1], i, j, k, e);
+        }
+        __syncthreads();
+        for (int s = 0; s < A.nu2; s++) sweep(q, false);
+    }
+    for (long long e = t; e < L[0].N; e += nt) A.g[0].u[e] = L[0].u[e];
+}
+
+template <typename R>
+size_t tail_level_lds(int dim, long long N)
+{
+    // u, f, faces (dim), block; each array 16-byte aligned
+    auto al = [](size_t b) { return (b + 15) & ~size_t(15); };
+    const size_t v2 = al(2 * sizeof(R) * N), v4 = al(4 * sizeof(R) * N);
+    return v2 * (2 + dim) + v4;
+}
+template size_t tail_level_lds<float>(int, long long);
+template size_t tail_level_lds<double>(int, long long);
+
+template <typename R>
+bool launch_tail(int dim, const TailArgs<R> &a, size_t lds_bytes, hipStream_t s)
+{
+    if (dim == 3)
+        hipLaunchKernelGGL((k_tail<R, 3>), dim3(1), dim3(1024), lds_bytes, s, a);
+    else
+        hipLaunchKernelGGL((k_tail<R, 2>), dim3(1), dim3(1024), lds_bytes, s, a);
+    return true;
+}
+template bool launch_tail<float>(int, const TailArgs<float> &, size_t, hipStream_t);
+template bool launch_tail<double>(int, const TailArgs<double> &, size_t, hipStream_t);
+
+template <typename R>
+void tail_set_lds_limit(int dim, size_t bytes)
+{
+    if (dim == 3)
+        (void)hipFuncSetAttribute((const void *)k_tail<R, 3>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    else
+        (void)hipFuncSetAttribute((const void *)k_tail<R, 2>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+template void tail_set_lds_limit<float>(int, size_t);
+template void tail_set_lds_limit<double>(int, size_t);
 
 }  // namespace ptmg

@@ -21,6 +21,7 @@ STATUS_NAMES = {0: "PT_OK", 1: "PT_ERR_ARG", 2: "PT_ERR_OOM", 3: "PT_ERR_SINGULA
 PT_COEF_EXPLICIT, PT_COEF_PHASES = 0, 1
 PT_PREC_FP64, PT_PREC_MIXED = 0, 1
 PT_MAX_HIST = 64
+PT_OPT_GRAPHS, PT_OPT_TAIL = 1, 2
 KERNEL_CLASSES = ["outer_residual", "smooth_fine", "smooth_coarse", "restrict", "prolong",
                   "coarse_solve", "other"]
 
@@ -103,6 +104,8 @@ def lib() -> ctypes.CDLL:
             "pt_mg_reset_stats": (c_int, [c_void]),
             "pt_mg_last_cell_updates": (ctypes.c_longlong, [c_void]),
             "pt_copy_kernel": (c_int, [c_void, c_void, ctypes.c_size_t, c_void]),
+            "pt_mg_set_option": (c_int, [c_void, c_int, c_int]),
+            "pt_mg_get_option": (c_int, [c_void, c_int]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -120,7 +123,8 @@ def exported_symbols() -> Sequence[str]:
             "pt_mg_num_levels", "pt_mg_level_dims", "pt_mg_get_operator", "pt_mg_smooth",
             "pt_mg_restrict_residual", "pt_mg_prolong_add", "pt_mg_coarse_solve",
             "pt_mg_vcycle", "pt_mg_set_timing", "pt_mg_kernel_stats", "pt_mg_reset_stats",
-            "pt_mg_last_cell_updates", "pt_copy_kernel"]
+            "pt_mg_last_cell_updates", "pt_copy_kernel", "pt_mg_set_option",
+            "pt_mg_get_option"]
 
 
 def _ptr(t: Optional[torch.Tensor]):
@@ -292,6 +296,12 @@ class PtMg:
 
     def reset_stats(self):
         self._check(lib().pt_mg_reset_stats(self._h))
+
+    def set_option(self, option: int, value: int):
+        self._check(lib().pt_mg_set_option(self._h, option, int(value)))
+
+    def get_option(self, option: int) -> int:
+        return int(lib().pt_mg_get_option(self._h, option))
 
     def last_cell_updates(self) -> int:
         return int(lib().pt_mg_last_cell_updates(self._h))

@@ -189,3 +189,62 @@ def test_timing_and_counters():
     assert st["outer_residual"]["launches"] == info["cycles"] + 1
     assert st["smooth_fine"]["ms"] > 0 and st["smooth_fine"]["bytes"] > 0
     assert h.last_cell_updates() > 0
+
+
+@pytest.mark.parametrize("name", ["bubble2d_200x136", "bubble3d_40x24x56"])
+def test_graph_replay_matches_direct_launches(name):
+    """On a non-null stream the coarse-level V-cycle is replayed from a HIP
+    graph (several replays per solve, host synchronisations in between);
+    every solve must equal the one with direct launches bit for bit."""
+    import workloads.device as D
+    prob = step_problems()[name]
+    outs = {}
+    for mode in ("direct", "graph"):
+        stream = torch.cuda.Stream() if mode == "graph" else None
+        ctx = torch.cuda.stream(stream) if stream is not None else torch.cuda.stream(
+            torch.cuda.current_stream())
+        with ctx:
+            h, b_p, b_T, _ = D.setup(prob, 1, stream=stream)
+            res = []
+            for _ in range(3):
+                p, T = torch.empty_like(b_p), torch.empty_like(b_T)
+                info = h.solve(b_p, b_T, p, T, rtol=1e-12)
+                assert info["status"] == 0 and info["cycles"] >= 2
+                res.append((p.clone(), T.clone()))
+            torch.cuda.synchronize()
+        for r in res[1:]:
+            assert torch.equal(r[0], res[0][0]) and torch.equal(r[1], res[0][1])
+        outs[mode] = res[0]
+    assert torch.equal(outs["direct"][0], outs["graph"][0])
+    assert torch.equal(outs["direct"][1], outs["graph"][1])
+
+
+@pytest.mark.parametrize("name", ["bubble2d_200x136", "bubble3d_40x24x56", "explicit_64",
+                                  "twobubble2d_96x80"])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_tail_and_graph_paths_agree(name, prec):
+    """The single-block tail cycle and the graph replay run the same
+    per-cell arithmetic as the grid kernels: solves and V-cycles agree with
+    the plain launch path bit for bit."""
+    import workloads.device as D
+    from paper_2206_11294_amd import ptmg
+    prob = step_problems()[name]
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        h, b_p, b_T, _ = D.setup(prob, prec, stream=stream)
+        rng = np.random.default_rng(2)
+        f_p, f_T = dev(rng.uniform(-1, 1, h.N)), dev(rng.uniform(-1, 1, h.N))
+        out = {}
+        for opts in ((1, 1), (0, 0)):
+            h.set_option(ptmg.PT_OPT_GRAPHS, opts[0])
+            h.set_option(ptmg.PT_OPT_TAIL, opts[1])
+            p, T = torch.empty_like(b_p), torch.empty_like(b_T)
+            h.solve(b_p, b_T, p, T, rtol=1e-12)
+            e = h.vcycle(f_p, f_T)
+            torch.cuda.synchronize()
+            out[opts] = (p.clone(), T.clone(), e[0].clone(), e[1].clone())
+        h.set_option(ptmg.PT_OPT_TAIL, 1)
+        if name == "explicit_64":   # 32^2 .. 4^2 fit in one block's LDS
+            assert h.get_option(ptmg.PT_OPT_TAIL) >= 4
+    for a, b in zip(out[(1, 1)], out[(0, 0)]):
+        assert torch.equal(a, b), (a - b).abs().max().item()
