@@ -123,6 +123,106 @@ def cpu_baseline(prob, rtol, budget_s):
             "kind": "oracle", "sample": sample}
 
 
+def _make_serve_request(rid):
+    import workloads as W
+    return W.serve_request(rid)
+
+
+def serve_bench(args):
+    """The serving mix: Poisson arrivals at `rate`/s of requests drawn
+    from a pool of distinct seeded requests (2-D 128^2..2048^2 and 3-D
+    64^3..192^3, 1-4 bubbles, mixed precision), through the continuous-
+    batching engine.  Reports solves/s and p50/p99 latency (arrival to
+    result ready) over the arrivals after the warm-up."""
+    import multiprocessing as mp
+
+    import numpy as np
+    import torch
+
+    import workloads as W
+    import workloads.device as D
+    from paper_2206_11294_amd import ptmg, serve
+
+    pool_n = args.serve_pool
+    with mp.get_context("fork").Pool(min(16, os.cpu_count() or 1)) as pool:
+        probs = pool.map(_make_serve_request, range(pool_n))
+    print(f"# serving pool of {pool_n} requests generated", file=sys.stderr, flush=True)
+    entries = []
+    for pr in probs:
+        s, t = D.to_device(pr)
+        p = torch.empty(pr.ncells, dtype=torch.float64, device="cuda")
+        entries.append({"prob": pr, "s": s, "t": t, "p": p, "T": torch.empty_like(p),
+                        "busy": None})
+    torch.cuda.synchronize()
+    srv = serve.Server(hbm_budget=int(args.serve_budget_gb * (1 << 30)),
+                       max_active=args.serve_slots, use_graphs=False)
+    arrivals = W.poisson_arrivals(args.serve_rate, args.serve_seconds, seed=4)
+    rtol = args.rtol if args.rtol is not None else 1e-9
+    t0 = serve.now() + 0.05
+    submitted = []   # (rid, arrival time, entry index)
+    nxt = 0
+    for k, ta in enumerate(arrivals):
+        srv.progress(t0 + ta)
+        for e in entries:   # release entries whose request finished
+            if e["busy"] is not None and srv.request(e["busy"])["status"] not in (-2, -3):
+                e["busy"] = None
+        # the next free pool entry (outputs of an entry are in use while busy)
+        for _ in range(pool_n):
+            e = entries[nxt % pool_n]
+            nxt += 1
+            if e["busy"] is None:
+                break
+        else:
+            srv.progress(float("inf"))
+            e["busy"] = None
+        rid = srv.submit(e["s"], ptmg.PT_PREC_MIXED, e["p"], e["T"], div=e["t"].get("div"),
+                         rtol=rtol, t_arrival=t0 + ta, keepalive=e["t"])
+        e["busy"] = rid
+        submitted.append((rid, ta, e["prob"]))
+    srv.run_until_idle()
+    torch.cuda.synchronize()
+    lat, done_t, cycles, cells, status = [], [], [], [], []
+    for rid, ta, pr in submitted:
+        info = srv.request(rid)
+        status.append(info["status"])
+        if ta < args.serve_warmup:
+            continue
+        lat.append(info["t_done"] - info["t_arrival"])
+        done_t.append(info["t_done"] - t0)
+        cycles.append(info["cycles"])
+        cells.append(pr.ncells)
+    srv.destroy()
+    lat = np.array(lat)
+    window = max(done_t) - args.serve_warmup
+    out = {
+        "metric": "coupled p-T solves/s at p99 latency (serving mix)",
+        "value": len(lat) / window,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": len(lat),
+        "warmup": int(sum(1 for _, ta, _ in submitted if ta < args.serve_warmup)),
+        "ms_per_step": 1e3 * float(np.mean(lat)),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "serving_mix", "rate_per_s": args.serve_rate,
+                   "seconds": args.serve_seconds, "pool": pool_n, "slots": args.serve_slots,
+                   "hbm_budget_gb": args.serve_budget_gb, "rtol": rtol,
+                   "sizes_2d": [W.SERVE_SIZES_2D[0], W.SERVE_SIZES_2D[-1]],
+                   "sizes_3d": [W.SERVE_SIZES_3D[0], W.SERVE_SIZES_3D[-1]]},
+        "latency_ms": {"p50": 1e3 * float(np.percentile(lat, 50)),
+                       "p90": 1e3 * float(np.percentile(lat, 90)),
+                       "p99": 1e3 * float(np.percentile(lat, 99)),
+                       "max": 1e3 * float(lat.max())},
+        "mean_cycles": float(np.mean(cycles)),
+        "mean_cells": float(np.mean(cells)),
+        "failed": int(sum(1 for s in status if s != 0)),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def copy_calibration(nbytes):
     import torch
     from paper_2206_11294_amd import ptmg
@@ -147,6 +247,13 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-oracle-check", action="store_true")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="BYTES")
+    ap.add_argument("--serve", action="store_true", help="the serving mix instead of a workload")
+    ap.add_argument("--serve-rate", type=float, default=50.0)
+    ap.add_argument("--serve-seconds", type=float, default=40.0)
+    ap.add_argument("--serve-warmup", type=float, default=5.0)
+    ap.add_argument("--serve-pool", type=int, default=48)
+    ap.add_argument("--serve-slots", type=int, default=8)
+    ap.add_argument("--serve-budget-gb", type=float, default=64.0)
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -163,6 +270,9 @@ def main():
 
     if args.copy_calib:
         copy_calibration(args.copy_calib)
+    if args.serve:
+        serve_bench(args)
+        return
 
     name = args.workload
     _, prec_default, rtol_default = WORKLOADS[name]

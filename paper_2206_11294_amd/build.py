@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libptmg.so")
-SOURCES = ["ptmg_kernels.hip", "ptmg_host.hip"]
+SOURCES = ["ptmg_kernels.hip", "ptmg_host.hip", "ptmg_serve.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

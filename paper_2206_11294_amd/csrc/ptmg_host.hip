@@ -160,6 +160,21 @@ struct pt_mg_s {
     std::string err = "no error";
     double *Ainv = nullptr;
     bool ready = false;
+    bool owns_memory = true;        // false: device + pinned memory belong to a server arena
+    hipEvent_t done_ev = nullptr;   // marks the end of the last enqueued step
+    // asynchronous solve (pt_mg_solve drives it to the end; a server polls it)
+    struct Solve {
+        int phase = 0;              // 0 idle, 1 iterating (norms in flight), 2 finishing
+        pt_solve_opts o;
+        const double *b_p = nullptr, *b_T = nullptr;
+        double *p = nullptr, *T = nullptr;
+        const double *cur_p = nullptr, *cur_T = nullptr;
+        bool in_caller = true;
+        const double *bshift = nullptr;
+        int cycles = 0, status = PT_ERR_NOCONV, nb = 0;
+        pt_solve_info inf;
+        std::chrono::steady_clock::time_point t0;
+    } sv;
     int u0_cur = 0;                 // which finest-grid buffer holds the current iterate
     // measurement
     unsigned timing = 0;            // bit c set: time launches of kernel class c
@@ -522,7 +537,9 @@ template <typename R> void build_hierarchy(pt_mg_t h)
     }
 }
 
-int assemble(pt_mg_t h, const pt_problem *p)
+// Enqueue assembly, hierarchy, coarsest inverse and the flag read-back on
+// the handle's stream; done_ev marks the end.
+int assemble_enqueue(pt_mg_t h, const pt_problem *p)
 {
     const Plan &P = h->P;
     AsmArgs a;
@@ -560,12 +577,17 @@ int assemble(pt_mg_t h, const pt_problem *p)
     else build_hierarchy<double>(h);
     hipError_t e = hipMemcpyAsync(h->flags_host, h->flags(), sizeof(int) * NFLAGS,
                                   hipMemcpyDeviceToHost, h->stream);
-    if (e != hipSuccess) return check_hip(h, e, "setup copy");
-    int rc = sync(h, "setup");
-    if (rc) return rc;
+    if (e == hipSuccess) e = hipEventRecord(h->done_ev, h->stream);
+    return check_hip(h, e, "setup enqueue");
+}
+
+// After done_ev: interpret the flags of the assembly.
+int assemble_check(pt_mg_t h)
+{
+    h->flush_timing();
     const int *f = h->flags_host;
     if (f[FLAG_ARG]) return fail(h, PT_ERR_ARG, "invalid input field (C outside [0,1], non-finite value, T <= 0 or negative coefficient)");
-    if (p->mean_constraint) {
+    if (h->prob.mean_constraint) {
         if (f[FLAG_BNONZERO]) return fail(h, PT_ERR_ARG, "mean_constraint requires B = 0 everywhere");
     } else if (f[FLAG_SINGULAR]) {
         return fail(h, PT_ERR_SINGULAR, "a cell block has det <= 0 or a non-positive diagonal");
@@ -573,6 +595,16 @@ int assemble(pt_mg_t h, const pt_problem *p)
     if (f[FLAG_PIVOT]) return fail(h, PT_ERR_SINGULAR, "coarsest-grid elimination met a non-positive pivot");
     h->ready = true;
     return PT_OK;
+}
+
+int assemble(pt_mg_t h, const pt_problem *p)
+{
+    int rc = assemble_enqueue(h, p);
+    if (rc) return rc;
+    rc = check_hip(h, hipEventSynchronize(h->done_ev), "setup");
+    if (rc == PT_OK) rc = check_hip(h, hipGetLastError(), "setup");
+    if (rc) return rc;
+    return assemble_check(h);
 }
 
 // The single-block tail covers the coarsest levels (at least two, none the
@@ -628,32 +660,108 @@ size_t pt_mg_footprint_bytes(const pt_problem *prob, int precision)
     return P.total;
 }
 
-int pt_mg_setup(const pt_problem *prob, int precision, void *hip_stream, pt_mg_t *out)
+namespace ptmg {
+
+// A handle on caller-provided device memory (`bytes` >= the plan's total)
+// and pinned host memory (16 doubles + 16 ints); with own_memory both are
+// allocated here.  The assembly is enqueued, not waited for: the caller
+// waits on handle_event and calls handle_setup_check.
+int handle_create(const pt_problem *prob, int precision, hipStream_t stream, char *dev_mem,
+                  size_t bytes, void *pinned, pt_mg_t *out, std::string *err)
 {
-    static const bool graphs_env = !getenv("PTMG_NO_GRAPHS");
-    if (!out) return fail(nullptr, PT_ERR_ARG, "out is NULL");
     *out = nullptr;
+    static const bool graphs_env = !getenv("PTMG_NO_GRAPHS");
     Plan P;
-    if (const char *why = plan_problem(prob, precision, P)) return fail(nullptr, PT_ERR_ARG, why);
+    if (const char *why = plan_problem(prob, precision, P)) {
+        *err = why;
+        return PT_ERR_ARG;
+    }
     pt_mg_t h = new pt_mg_s();
     h->P = P;
+    h->stream = stream;
     h->use_graphs = graphs_env;
-    h->stream = (hipStream_t)hip_stream;
-    hipError_t e = hipMalloc(&h->base, P.total);
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        delete h;
-        return fail(nullptr, PT_ERR_OOM, "hipMalloc of " + std::to_string(P.total) + " bytes failed");
+    h->owns_memory = dev_mem == nullptr;
+    if (h->owns_memory) {
+        hipError_t e = hipMalloc(&h->base, P.total);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            delete h;
+            *err = "hipMalloc of " + std::to_string(P.total) + " bytes failed";
+            return PT_ERR_OOM;
+        }
+        e = hipHostMalloc(&h->norms_host, 16 * sizeof(double) + 16 * sizeof(int),
+                          hipHostMallocDefault);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            h->norms_host = nullptr;
+            pt_mg_destroy(h);
+            *err = "pinned host allocation failed";
+            return PT_ERR_OOM;
+        }
+    } else {
+        if (bytes < P.total || !pinned) {
+            delete h;
+            *err = "external memory too small";
+            return PT_ERR_ARG;
+        }
+        h->base = dev_mem;
+        h->norms_host = (double *)pinned;
     }
-    e = hipHostMalloc(&h->norms_host, 16 * sizeof(double), hipHostMallocDefault);
-    if (e == hipSuccess) e = hipHostMalloc(&h->flags_host, 16 * sizeof(int), hipHostMallocDefault);
-    if (e != hipSuccess) {
+    h->flags_host = (int *)(h->norms_host + 16);
+    if (hipEventCreateWithFlags(&h->done_ev, hipEventDisableTiming) != hipSuccess) {
         (void)hipGetLastError();
+        h->done_ev = nullptr;
         pt_mg_destroy(h);
-        return fail(nullptr, PT_ERR_OOM, "pinned host allocation failed");
+        *err = "event creation failed";
+        return PT_ERR_HIP;
     }
     plan_tail(h);
-    int rc = assemble(h, prob);
+    int rc = assemble_enqueue(h, prob);
+    if (rc != PT_OK) {
+        *err = h->err;
+        pt_mg_destroy(h);
+        return rc;
+    }
+    *out = h;
+    return PT_OK;
+}
+
+hipEvent_t handle_event(pt_mg_t h) { return h->done_ev; }
+
+// Paper right-hand side (Eqs. 33-34) enqueued without waiting.
+int handle_paper_rhs_async(pt_mg_t h, const double *p_adv, const double *T_adv,
+                           const double *div_ustar, double *b_p, double *b_T)
+{
+    if (h->prob.mode != PT_COEF_PHASES) return fail(h, PT_ERR_STATE, "paper_rhs needs phases mode");
+    h->begin(PT_K_OTHER, 48.0 * h->P.N);
+    launch_paper_rhs(h->P.N, h->B64(), p_adv, h->prob.p_adv_const, T_adv, h->prob.T_adv_const,
+                     div_ustar, h->prob.dt, b_p, b_T, h->stream);
+    h->end();
+    return PT_OK;
+}
+
+const char *handle_error(pt_mg_t h) { return h->err.c_str(); }
+int handle_setup_check(pt_mg_t h) { return assemble_check(h); }
+size_t handle_plan_bytes(const pt_problem *prob, int precision)
+{
+    Plan P;
+    if (plan_problem(prob, precision, P)) return 0;
+    return P.total;
+}
+
+}  // namespace ptmg
+
+int pt_mg_setup(const pt_problem *prob, int precision, void *hip_stream, pt_mg_t *out)
+{
+    if (!out) return fail(nullptr, PT_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    pt_mg_t h = nullptr;
+    std::string err;
+    int rc = handle_create(prob, precision, (hipStream_t)hip_stream, nullptr, 0, nullptr, &h, &err);
+    if (rc != PT_OK) return fail(nullptr, rc, err);
+    rc = check_hip(h, hipEventSynchronize(h->done_ev), "setup");
+    if (rc == PT_OK) rc = check_hip(h, hipGetLastError(), "setup");
+    if (rc == PT_OK) rc = assemble_check(h);
     if (rc != PT_OK) {
         g_thread_err = h->err;
         pt_mg_destroy(h);
@@ -678,10 +786,12 @@ void pt_mg_destroy(pt_mg_t h)
 {
     if (!h) return;
     if (h->stream || h->base) (void)hipStreamSynchronize(h->stream);
+    if (h->done_ev) (void)hipEventDestroy(h->done_ev);
     for (auto e : h->ev_pool) (void)hipEventDestroy(e);
-    if (h->base) (void)hipFree(h->base);
-    if (h->norms_host) (void)hipHostFree(h->norms_host);
-    if (h->flags_host) (void)hipHostFree(h->flags_host);
+    if (h->owns_memory) {
+        if (h->base) (void)hipFree(h->base);
+        if (h->norms_host) (void)hipHostFree(h->norms_host);
+    }
     delete h;
 }
 
@@ -756,16 +866,24 @@ int outer_any(pt_mg_t h, const double *b_p, const double *b_T, const double *src
                          bshift);
 }
 
-// Reduce the partial sums to 4 doubles and bring them to the host (sync).
-int read_norms(pt_mg_t h, int nb, double out[4])
+// Reduce the partial sums to 4 doubles and copy them to pinned host memory
+// (asynchronous; done_ev marks their arrival).
+int enqueue_norms(pt_mg_t h, int nb)
 {
     h->begin(PT_K_OTHER, 32.0 * nb);
     launch_reduce4(h->partials(), nb, h->norms_dev(), h->stream);
     h->end();
     hipError_t e = hipMemcpyAsync(h->norms_host, h->norms_dev(), 4 * sizeof(double),
                                   hipMemcpyDeviceToHost, h->stream);
-    if (e != hipSuccess) return check_hip(h, e, "norm copy");
-    int rc = sync(h, "residual");
+    if (e == hipSuccess) e = hipEventRecord(h->done_ev, h->stream);
+    return check_hip(h, e, "norm copy");
+}
+
+int read_norms(pt_mg_t h, int nb, double out[4])
+{
+    int rc = enqueue_norms(h, nb);
+    if (rc) return rc;
+    rc = sync(h, "residual");
     if (rc) return rc;
     for (int q = 0; q < 4; q++) out[q] = h->norms_host[q];
     return PT_OK;
@@ -802,10 +920,13 @@ int pt_mg_residual(pt_mg_t h, const double *b_p, const double *b_T, const double
     return PT_OK;
 }
 
-int pt_mg_solve(pt_mg_t h, const double *b_p, const double *b_T, double *p, double *T,
-                const pt_solve_opts *opts_in, pt_solve_info *info)
+namespace ptmg {
+
+// Start a solve: enqueue the initial residual and its norms.  Returns an
+// error, or PT_OK with the solve running (done_ev marks the norms).
+int solve_begin(pt_mg_t h, const double *b_p, const double *b_T, double *p, double *T,
+                const pt_solve_opts *opts_in)
 {
-    auto t0 = std::chrono::steady_clock::now();
     if (!h || !h->ready) return fail(h, PT_ERR_STATE, "handle not ready");
     if (!b_p || !b_T || !p || !T) return fail(h, PT_ERR_ARG, "NULL field");
     pt_solve_opts o = {1e-9, 50, 2, 2, 1};
@@ -814,9 +935,16 @@ int pt_mg_solve(pt_mg_t h, const double *b_p, const double *b_T, double *p, doub
         o.nu1 + o.nu2 == 0)
         return fail(h, PT_ERR_ARG, "bad solve options");
     const Plan &P = h->P;
+    auto &S = h->sv;
+    S = pt_mg_s::Solve();
+    S.t0 = std::chrono::steady_clock::now();
+    S.o = o;
+    S.b_p = b_p;
+    S.b_T = b_T;
+    S.p = p;
+    S.T = T;
+    std::memset(&S.inf, 0, sizeof S.inf);
     h->updates = 0;
-    pt_solve_info inf;
-    std::memset(&inf, 0, sizeof inf);
     if (o.zero_guess) {
         h->begin(PT_K_OTHER, 16.0 * P.N);
         launch_zero(p, 8 * (size_t)P.N, h->stream);
@@ -824,31 +952,30 @@ int pt_mg_solve(pt_mg_t h, const double *b_p, const double *b_T, double *p, doub
         h->end();
     }
     // mean constraint: the right-hand side is used with its mean removed
-    const double *bshift = h->prob.mean_constraint ? grid_sums(h, b_p, b_T, 0) : nullptr;
-    double *X[2] = {h->at<double>(P.o_xp), h->at<double>(P.o_xT)};
-    const double *cur_p = p, *cur_T = T;
-    bool in_caller = true;
-    int status = PT_ERR_NOCONV;
-    int cycles = 0;
-    for (;;) {
-        const bool update = cycles > 0;
-        double *dp = nullptr, *dT = nullptr;
-        if (update) {
-            dp = in_caller ? X[0] : p;
-            dT = in_caller ? X[1] : T;
-        }
-        int nb = outer_any(h, b_p, b_T, cur_p, cur_T, dp, dT, update, true, nullptr, nullptr,
-                           bshift);
-        if (update) {
-            cur_p = dp;
-            cur_T = dT;
-            in_caller = !in_caller;
-        }
-        double s[4];
-        int rc = read_norms(h, nb, s);
-        if (rc) return rc;
+    S.bshift = h->prob.mean_constraint ? grid_sums(h, b_p, b_T, 0) : nullptr;
+    S.cur_p = p;
+    S.cur_T = T;
+    S.in_caller = true;
+    S.nb = outer_any(h, b_p, b_T, p, T, nullptr, nullptr, false, true, nullptr, nullptr, S.bshift);
+    int rc = enqueue_norms(h, S.nb);
+    if (rc) return rc;
+    S.phase = 1;
+    return PT_OK;
+}
+
+// Advance a running solve once its done_ev has completed: returns
+// PT_RUNNING (-1) after enqueuing the next step, or the final status.
+int solve_advance(pt_mg_t h, pt_solve_info *info)
+{
+    auto &S = h->sv;
+    const Plan &P = h->P;
+    hipError_t e;
+    h->flush_timing();
+    if (S.phase == 1) {
+        const double *s = h->norms_host;
         double rel[2] = {s[2] > 0 ? std::sqrt(s[0] / s[2]) : std::sqrt(s[0]),
                          s[3] > 0 ? std::sqrt(s[1] / s[3]) : std::sqrt(s[1])};
+        auto &inf = S.inf;
         if (inf.hist_len < PT_MAX_HIST) {
             inf.relres_hist[2 * inf.hist_len] = rel[0];
             inf.relres_hist[2 * inf.hist_len + 1] = rel[1];
@@ -856,41 +983,81 @@ int pt_mg_solve(pt_mg_t h, const double *b_p, const double *b_T, double *p, doub
         }
         inf.relres[0] = rel[0];
         inf.relres[1] = rel[1];
+        bool finish = true;
         if (!std::isfinite(rel[0]) || !std::isfinite(rel[1])) {
-            status = PT_ERR_NOCONV;
+            S.status = PT_ERR_NOCONV;
             h->err = "residual norm is not finite";
-            break;
-        }
-        if (rel[0] <= o.rtol && rel[1] <= o.rtol) {
-            status = PT_OK;
-            break;
-        }
-        if (cycles >= o.max_cycles) {
-            status = PT_ERR_NOCONV;
+        } else if (rel[0] <= S.o.rtol && rel[1] <= S.o.rtol) {
+            S.status = PT_OK;
+        } else if (S.cycles >= S.o.max_cycles) {
+            S.status = PT_ERR_NOCONV;
             h->err = "max_cycles reached";
-            break;
+        } else {
+            finish = false;
         }
-        vcycle_any(h, o.nu1, o.nu2);
-        cycles++;
+        if (!finish) {
+            vcycle_any(h, S.o.nu1, S.o.nu2);
+            S.cycles++;
+            double *X[2] = {h->at<double>(P.o_xp), h->at<double>(P.o_xT)};
+            double *dp = S.in_caller ? X[0] : S.p;
+            double *dT = S.in_caller ? X[1] : S.T;
+            S.nb = outer_any(h, S.b_p, S.b_T, S.cur_p, S.cur_T, dp, dT, true, true, nullptr,
+                             nullptr, S.bshift);
+            S.cur_p = dp;
+            S.cur_T = dT;
+            S.in_caller = !S.in_caller;
+            int rc = enqueue_norms(h, S.nb);
+            if (rc) {
+                S.phase = 0;
+                return rc;
+            }
+            return PT_RUNNING;
+        }
+        if (!S.in_caller) {
+            h->begin(PT_K_OTHER, 32.0 * P.N);
+            launch_convert<double, double>(P.N, S.cur_p, S.p, h->stream);
+            launch_convert<double, double>(P.N, S.cur_T, S.T, h->stream);
+            h->end();
+        }
+        if (h->prob.mean_constraint) {
+            double *us = grid_sums(h, S.p, S.T, 1);
+            launch_shift2(P.N, S.p, S.T, us, 1.0 / (double)P.N, h->stream);
+        }
+        e = hipEventRecord(h->done_ev, h->stream);
+        if (e != hipSuccess) {
+            S.phase = 0;
+            return check_hip(h, e, "solve");
+        }
+        S.phase = 2;
+        return PT_RUNNING;
     }
-    if (!in_caller) {
-        h->begin(PT_K_OTHER, 32.0 * P.N);
-        launch_convert<double, double>(P.N, cur_p, p, h->stream);
-        launch_convert<double, double>(P.N, cur_T, T, h->stream);
-        h->end();
-    }
-    if (h->prob.mean_constraint) {
-        double *us = grid_sums(h, p, T, 1);
-        launch_shift2(P.N, p, T, us, 1.0 / (double)P.N, h->stream);
-    }
-    int rc = sync(h, "solve");
-    if (rc) return rc;
+    // phase 2: the final copies are done
+    S.phase = 0;
     h->last_updates = h->updates;
-    inf.cycles = cycles;
-    inf.t_solve_s = elapsed(t0);
-    inf.status = status;
-    if (info) *info = inf;
-    return status;
+    S.inf.cycles = S.cycles;
+    S.inf.t_solve_s = elapsed(S.t0);
+    S.inf.status = S.status;
+    if (info) *info = S.inf;
+    return S.status;
+}
+
+}  // namespace ptmg
+
+int pt_mg_solve(pt_mg_t h, const double *b_p, const double *b_T, double *p, double *T,
+                const pt_solve_opts *opts_in, pt_solve_info *info)
+{
+    int rc = solve_begin(h, b_p, b_T, p, T, opts_in);
+    if (rc != PT_OK) return rc;
+    for (;;) {
+        rc = check_hip(h, hipEventSynchronize(h->done_ev), "solve");
+        if (rc == PT_OK) rc = check_hip(h, hipGetLastError(), "solve");
+        if (rc != PT_OK) {
+            h->sv.phase = 0;
+            return rc;
+        }
+        rc = solve_advance(h, info);
+        if (rc != PT_RUNNING) return rc;
+    }
 }
 
 // ---------------------------------------------------------- step entries

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <string>
+
 #include "pt_mg.h"
 
 namespace ptmg {
@@ -145,5 +147,19 @@ template <typename RIN, typename ROUT>
 void launch_convert(long long n, const RIN *in, ROUT *out, hipStream_t s);
 void launch_copy(void *dst, const void *src, size_t bytes, hipStream_t s);
 void launch_zero(void *p, size_t bytes, hipStream_t s);
+
+// ---- handle internals used by the serving engine (ptmg_host.hip) ---------
+constexpr int PT_RUNNING = -1;
+int handle_create(const pt_problem *prob, int precision, hipStream_t stream, char *dev_mem,
+                  size_t bytes, void *pinned, pt_mg_t *out, std::string *err);
+hipEvent_t handle_event(pt_mg_t h);
+int handle_setup_check(pt_mg_t h);
+size_t handle_plan_bytes(const pt_problem *prob, int precision);
+int solve_begin(pt_mg_t h, const double *b_p, const double *b_T, double *p, double *T,
+                const pt_solve_opts *opts);
+int solve_advance(pt_mg_t h, pt_solve_info *info);
+int handle_paper_rhs_async(pt_mg_t h, const double *p_adv, const double *T_adv,
+                           const double *div_ustar, double *b_p, double *b_T);
+const char *handle_error(pt_mg_t h);
 
 }  // namespace ptmg

@@ -8,13 +8,16 @@ import re
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "pt_mg.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("pt_mg.h", "pt_serve.h")]
 
 
 def _declared():
-    src = open(HEADER).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(pt_[a-z_0-9]+)\s*\(", src)))
+    names = set()
+    for hdr in HEADERS:
+        src = open(hdr).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        names |= set(re.findall(r"\b(pt_[a-z_0-9]+)\s*\(", src))
+    return sorted(names)
 
 
 @pytest.fixture(scope="module")
@@ -31,8 +34,8 @@ def test_every_declared_symbol_is_exported(L):
 
 
 def test_binding_covers_header(L):
-    from paper_2206_11294_amd import ptmg
-    assert set(ptmg.exported_symbols()) == set(_declared())
+    from paper_2206_11294_amd import ptmg, serve
+    assert set(ptmg.exported_symbols()) | set(serve.exported_symbols()) == set(_declared())
 
 
 def _prob(dim=2, n=(64, 64, 1), mode=0):
