@@ -223,6 +223,31 @@ def serve_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def stream_probe():
+    """Attainable HBM bandwidth: plain copies of 2 GiB timed with HIP
+    events (the library's copy kernel and torch's copy_)."""
+    import torch
+    from paper_2206_11294_amd import ptmg
+    nbytes = 2 << 30
+    src = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    res = {}
+    for name, fn in (("pt_copy_kernel", lambda: ptmg.copy_kernel(dst, src, nbytes)),
+                     ("torch_copy", lambda: dst.copy_(src))):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(10):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 10
+        res[name] = {"GB_per_s": round(2 * nbytes / (ms * 1e-3) / 1e9, 1), "ms": round(ms, 4)}
+    print(json.dumps({"stream_probe_bytes_moved": 2 * nbytes, **res}), flush=True)
+
+
 def copy_calibration(nbytes):
     import torch
     from paper_2206_11294_amd import ptmg
@@ -248,6 +273,7 @@ def main():
     ap.add_argument("--no-oracle-check", action="store_true")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="BYTES")
     ap.add_argument("--serve", action="store_true", help="the serving mix instead of a workload")
+    ap.add_argument("--stream-probe", action="store_true", help="copy bandwidth, then exit")
     ap.add_argument("--serve-rate", type=float, default=50.0)
     ap.add_argument("--serve-seconds", type=float, default=40.0)
     ap.add_argument("--serve-warmup", type=float, default=5.0)
@@ -268,6 +294,9 @@ def main():
     import workloads.device as D
     from paper_2206_11294_amd import ptmg
 
+    if args.stream_probe:
+        stream_probe()
+        return
     if args.copy_calib:
         copy_calibration(args.copy_calib)
     if args.serve:

@@ -259,8 +259,10 @@ long long pt_mg_last_cell_updates(pt_mg_t h);
  *    graph captured on first use (needs a non-null stream); default 1.
  *  PT_OPT_TAIL: run the coarsest levels that fit in one block's LDS as a
  *    single-block kernel; default 1.  pt_mg_get_option returns, for
- *    PT_OPT_TAIL, the number of levels the tail covers (0 if none). */
-typedef enum { PT_OPT_GRAPHS = 1, PT_OPT_TAIL = 2 } pt_option;
+ *    PT_OPT_TAIL, the number of levels the tail covers (0 if none).
+ *  PT_OPT_FUSED: each red-black sweep as one fused pass over memory;
+ *    0: two colour passes (the reference path); default 1. */
+typedef enum { PT_OPT_GRAPHS = 1, PT_OPT_TAIL = 2, PT_OPT_FUSED = 3 } pt_option;
 int pt_mg_set_option(pt_mg_t h, int option, int value);
 int pt_mg_get_option(pt_mg_t h, int option);
 

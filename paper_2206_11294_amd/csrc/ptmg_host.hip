@@ -23,7 +23,7 @@ struct LevelPlan {
     int n[3];
     long long N;
     double h;
-    size_t o_u, o_u2, o_f, o_ac, o_fx, o_fy, o_fz, o_B;   // o_u2: finest grid only
+    size_t o_u, o_u2, o_f, o_ac, o_fx, o_fy, o_fz, o_B;   // o_u2: second iterate buffer
 };
 
 struct Plan {
@@ -43,11 +43,11 @@ struct Plan {
 
 constexpr long long kMaxCoarseCells = 2048;   // coarsest grid solved by a dense inverse
 
-// Coarsen while every active axis is even and its half is at least 4.
+// Coarsen while every active axis is even and its half is at least 2.
 bool can_coarsen(int dim, const int *n)
 {
     for (int a = 0; a < dim; a++)
-        if (n[a] % 2 != 0 || n[a] / 2 < 4) return false;
+        if (n[a] % 2 != 0 || n[a] / 2 < 2) return false;
     return true;
 }
 
@@ -98,9 +98,9 @@ const char *plan_problem(const pt_problem *p, int prec, Plan &P)
         L.h = h;
         L.o_u = P.take(2 * R * L.N);
         L.o_f = P.take(2 * R * L.N);
-        L.o_u2 = L.o_ac = L.o_fx = L.o_fy = L.o_fz = L.o_B = (size_t)-1;
+        L.o_ac = L.o_fx = L.o_fy = L.o_fz = L.o_B = (size_t)-1;
+        L.o_u2 = P.take(2 * R * L.N);   // the fused sweep writes to the other buffer
         if (l == 0) {
-            L.o_u2 = P.take(2 * R * L.N);   // the fused sweep writes to the other buffer
             if (prec == PT_PREC_MIXED) {
                 L.o_ac = P.take(2 * R * L.N);
                 L.o_B = P.take(4 * R * L.N);
@@ -140,6 +140,7 @@ struct TimerRec {
 // launches add (capture records them once; each replay adds them again).
 struct CoarseGraph {
     int key = -1;
+    unsigned state_in = 0, state_out = 0;   // iterate-buffer bits of levels >= 1
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     long launches[PT_K_COUNT] = {0};
@@ -175,7 +176,8 @@ struct pt_mg_s {
         pt_solve_info inf;
         std::chrono::steady_clock::time_point t0;
     } sv;
-    int u0_cur = 0;                 // which finest-grid buffer holds the current iterate
+    unsigned u_cur = 0;             // bit l: level l's current iterate is in its second buffer
+    bool use_fused = true;          // false: two colour passes per sweep (reference path)
     // measurement
     unsigned timing = 0;            // bit c set: time launches of kernel class c
     std::vector<hipEvent_t> ev_pool;
@@ -208,7 +210,7 @@ struct pt_mg_s {
         o.nz = L.n[2];
         o.N = L.N;
         o.inv_h2 = 1.0 / (L.h * L.h);
-        o.u = at<typename VT<R>::v2>(l == 0 && u0_cur ? L.o_u2 : L.o_u);
+        o.u = at<typename VT<R>::v2>(((u_cur >> l) & 1u) ? L.o_u2 : L.o_u);
         o.f = at<typename VT<R>::v2>(L.o_f);
         o.fx = at<typename VT<R>::v2>(L.o_fx);
         o.fy = at<typename VT<R>::v2>(L.o_fy);
@@ -315,24 +317,36 @@ double bytes_sweep_fused(const Plan &P, bool zero_guess)
     return (double)P.lv[0].N * R * (zero_guess ? 10 : 12);
 }
 
+// One pass over memory per sweep pays off where a level has enough
+// work for the whole chip: every 2-D level (independent tiles), 3-D
+// levels of at least 2^20 cells (the plane-marching kernel).
+bool fused_level(pt_mg_t h, int l)
+{
+    return h->use_fused && (h->P.dim == 2 || l == 0 || h->P.lv[l].N >= (1ll << 20));
+}
+
 template <typename R> void smooth(pt_mg_t h, int l, int sweeps, bool zero_guess)
 {
-    if (l == 0) {
-        // finest grid: fused red-black sweeps, ping-ponging the iterate
+    if (fused_level(h, l)) {
+        // fused red-black sweeps (one pass over memory each), ping-ponging
+        // the iterate between the level's two buffers
+        const double Rb = sizeof(R);
         for (int s = 0; s < sweeps; s++) {
             const bool zg = zero_guess && s == 0;
-            Lvl<R> L = h->level<R>(0);
-            h->u0_cur ^= 1;
-            typename VT<R>::v2 *uo = h->level<R>(0).u;
-            h->begin(PT_K_SMOOTH_FINE, bytes_sweep_fused(h->P, zg));
-            launch_rb_fused<R>(h->P.dim, L, uo, zg ? 1 : 0, h->stream);
+            Lvl<R> L = h->level<R>(l);
+            h->u_cur ^= 1u << l;
+            typename VT<R>::v2 *uo = h->level<R>(l).u;
+            const double coef = (l == 0 ? 2 : 2 * h->P.dim) * Rb;   // cell or face coefficients
+            const double nb = (double)L.N * ((zg ? 0 : 2 * Rb) + 2 * Rb + coef + 4 * Rb + 2 * Rb);
+            h->begin(l == 0 ? PT_K_SMOOTH_FINE : PT_K_SMOOTH_COARSE, nb);
+            launch_rb_fused<R>(h->P.dim, L, uo, zg ? 1 : 0, l == 0 ? 0 : 1, h->stream);
             h->end();
             h->updates += L.N;
         }
         return;
     }
     Lvl<R> L = h->level<R>(l);
-    const int cls = PT_K_SMOOTH_COARSE;
+    const int cls = l == 0 ? PT_K_SMOOTH_FINE : PT_K_SMOOTH_COARSE;
     for (int s = 0; s < sweeps; s++) {
         const bool zg = zero_guess && s == 0;
         h->begin(cls, bytes_sweep_half(h->P, l, zg));
@@ -392,13 +406,15 @@ template <typename R> void coarse_cycle(pt_mg_t h, int nu1, int nu2)
         vcycle<R>(h, 1, nu1, nu2);
         return;
     }
-    const int key = nu1 * 16 + nu2;
+    const int key = nu1 * 16 + nu2 + (h->use_fused ? 256 : 0) + (h->use_tail ? 512 : 0);
+    const unsigned state = h->u_cur & ~1u;
     CoarseGraph *g = nullptr;
     for (auto &c : h->graphs)
-        if (c.key == key) g = &c;
+        if (c.key == key && c.state_in == state) g = &c;
     if (!g) {
         CoarseGraph c;
         c.key = key;
+        c.state_in = state;
         long l0[PT_K_COUNT];
         double b0[PT_K_COUNT];
         for (int q = 0; q < PT_K_COUNT; q++) {
@@ -420,6 +436,7 @@ template <typename R> void coarse_cycle(pt_mg_t h, int nu1, int nu2)
         }
         c.updates = h->updates - u0;
         h->updates = u0;
+        c.state_out = h->u_cur & ~1u;
         if (!ok) {
             (void)hipGetLastError();
             if (c.graph) (void)hipGraphDestroy(c.graph);
@@ -431,6 +448,7 @@ template <typename R> void coarse_cycle(pt_mg_t h, int nu1, int nu2)
         g = &h->graphs.back();
     }
     (void)hipGraphLaunch(g->exec, h->stream);
+    h->u_cur = (h->u_cur & 1u) | g->state_out;
     for (int q = 0; q < PT_K_COUNT; q++) {
         h->launches[q] += g->launches[q];
         h->bytes[q] += g->bytes[q];
@@ -1219,6 +1237,7 @@ int pt_mg_set_option(pt_mg_t h, int option, int value)
     if (!h) return fail(nullptr, PT_ERR_ARG, "handle is NULL");
     if (option == PT_OPT_GRAPHS) h->use_graphs = value != 0;
     else if (option == PT_OPT_TAIL) h->use_tail = value != 0;
+    else if (option == PT_OPT_FUSED) h->use_fused = value != 0;
     else return fail(h, PT_ERR_ARG, "unknown option");
     return PT_OK;
 }
@@ -1227,6 +1246,7 @@ int pt_mg_get_option(pt_mg_t h, int option)
 {
     if (!h) return -1;
     if (option == PT_OPT_GRAPHS) return h->use_graphs ? 1 : 0;
+    if (option == PT_OPT_FUSED) return h->use_fused ? 1 : 0;
     if (option == PT_OPT_TAIL) return (h->use_tail && h->tail_lt > 0) ? h->P.nlev - h->tail_lt : 0;
     return -1;
 }

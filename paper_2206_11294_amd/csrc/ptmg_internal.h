@@ -111,7 +111,7 @@ template <typename R>
 void launch_rb_pass(int dim, int level0, const Lvl<R> &L, int color, int zero_guess,
                     hipStream_t s);
 template <typename R>
-void launch_rb_fused(int dim, const Lvl<R> &L, typename VT<R>::v2 *uo, int zero_guess,
+void launch_rb_fused(int dim, const Lvl<R> &L, typename VT<R>::v2 *uo, int zero_guess, int faces,
                      hipStream_t s);
 template <typename R>
 void launch_restrict(int dim, int level0, const Lvl<R> &F, const Lvl<R> &C, hipStream_t s);

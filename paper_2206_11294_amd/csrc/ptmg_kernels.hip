@@ -1020,10 +1020,13 @@ __device__ __forceinline__ void block_solve(typename VT<R>::v2 f, typename VT<R>
     o.y = (a * gT - b.z * gp) * inv;
 }
 
-template <typename R, int TX, int TY, bool ZG>
+template <typename R, int TX, int TY, bool ZG, bool FACES>
 __global__ __launch_bounds__(TX *TY) void k_rb_fused3(Lvl<R> L, typename VT<R>::v2 *__restrict__ uo,
                                                       int zc, int tiles_x, int tiles_y, int ntiles)
 {
+    // FACES: a coarse level with stored lower-face coefficients (fx, fy,
+    // fz) instead of cell coefficients; faces of plane z are needed while
+    // planes z-1 .. z+1 update, so they live in a 4-slot ring.
     // Software-pipelined walk over a 5-plane LDS ring: while plane step k
     // computes, the global loads of step k+1 (plane k+3 and the f, B of
     // the next red and black cells) are in flight in registers.  Five
@@ -1037,8 +1040,11 @@ __global__ __launch_bounds__(TX *TY) void k_rb_fused3(Lvl<R> L, typename VT<R>::
     constexpr int NLD = (PS + NT - 1) / NT;     // plane cells loaded per thread
     constexpr int RW = (TX + 2) / 2;            // red cells per row of the ring region
     constexpr int BW = TX / 2;                  // black cells per tile row
+    constexpr int NA = FACES ? 1 : 5, PA = FACES ? 1 : PS;
+    constexpr int NF = FACES ? 4 : 1, PF = FACES ? PS : 1, NLF = FACES ? NLD : 1;
     __shared__ V2 su[5][PS];
-    __shared__ V2 sa[5][PS];
+    __shared__ V2 sa[NA][PA];
+    __shared__ V2 sfx[NF][PF], sfy[NF][PF], sfz[NF][PF];
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     if (tile >= ntiles) return;
     const int txi = tile % tiles_x;
@@ -1051,20 +1057,32 @@ __global__ __launch_bounds__(TX *TY) void k_rb_fused3(Lvl<R> L, typename VT<R>::
     const long long nxy = (long long)L.nx * L.ny;
     const int t = threadIdx.x;
     auto slot = [](int z) { return (z + 10) % 5; };   // z >= -2
+    auto fslot = [](int z) { return (z + 8) & 3; };
 
     // ---- per-thread pieces of a plane step
-    V2 pu[NLD], pa[NLD];
+    V2 pu[NLD], pa[NLD], pfx[NLF], pfy[NLF], pfz[NLF];
     auto fetch_plane = [&](int z) {
 #pragma unroll
         for (int i = 0; i < NLD; i++) {
             const int c = t + i * NT;
             pu[i].x = pu[i].y = R(0);
             pa[i].x = pa[i].y = R(0);
+            if (FACES) {
+                pfx[i].x = pfx[i].y = R(0);
+                pfy[i].x = pfy[i].y = R(0);
+                pfz[i].x = pfz[i].y = R(0);
+            }
             if (c < PS) {
                 const int gx = x0 + c % PX - 2, gy = y0 + c / PX - 2;
                 if (z >= 0 && z < L.nz && gx >= 0 && gx < L.nx && gy >= 0 && gy < L.ny) {
                     const long long g = gx + (long long)L.nx * gy + nxy * z;
-                    pa[i] = L.ac[g];
+                    if (FACES) {
+                        pfx[i] = L.fx[g];
+                        pfy[i] = L.fy[g];
+                        pfz[i] = L.fz[g];
+                    } else {
+                        pa[i] = L.ac[g];
+                    }
                     if (!ZG) pu[i] = L.u[g];
                 }
             }
@@ -1077,7 +1095,14 @@ __global__ __launch_bounds__(TX *TY) void k_rb_fused3(Lvl<R> L, typename VT<R>::
             const int c = t + i * NT;
             if (c < PS) {
                 su[s][c] = pu[i];
-                sa[s][c] = pa[i];
+                if (FACES) {
+                    const int fs = fslot(z);
+                    sfx[fs][c] = pfx[i];
+                    sfy[fs][c] = pfy[i];
+                    sfz[fs][c] = pfz[i];
+                } else {
+                    sa[s][c] = pa[i];
+                }
             }
         }
     };
@@ -1107,10 +1132,8 @@ __global__ __launch_bounds__(TX *TY) void k_rb_fused3(Lvl<R> L, typename VT<R>::
     };
     auto update = [&](int z, int c, V2 f, V4 b) {
         const int s = slot(z), sm = slot(z - 1), sp = slot(z + 1);
-        const V2 am = sa[s][c];
         R gp = R(0), gT = R(0), Sp = R(0), ST = R(0);
-        auto acc = [&](int ss, int q) {
-            V2 w = harm2(am, sa[ss][q]);
+        auto accw = [&](V2 w, int ss, int q) {
             const R wp = w.x * ih2, wT = w.y * ih2;
             const V2 uq = su[ss][q];
             Sp += wp;
@@ -1118,12 +1141,23 @@ __global__ __launch_bounds__(TX *TY) void k_rb_fused3(Lvl<R> L, typename VT<R>::
             gp += wp * uq.x;
             gT += wT * uq.y;
         };
-        acc(s, c - 1);
-        acc(s, c + 1);
-        acc(s, c - PX);
-        acc(s, c + PX);
-        acc(sm, c);
-        acc(sp, c);
+        if (FACES) {
+            const int fs = fslot(z), fsp = fslot(z + 1);
+            accw(sfx[fs][c], s, c - 1);
+            accw(sfx[fs][c + 1], s, c + 1);
+            accw(sfy[fs][c], s, c - PX);
+            accw(sfy[fs][c + PX], s, c + PX);
+            accw(sfz[fs][c], sm, c);
+            accw(sfz[fsp][c], sp, c);
+        } else {
+            const V2 am = sa[s][c];
+            accw(harm2(am, sa[s][c - 1]), s, c - 1);
+            accw(harm2(am, sa[s][c + 1]), s, c + 1);
+            accw(harm2(am, sa[s][c - PX]), s, c - PX);
+            accw(harm2(am, sa[s][c + PX]), s, c + PX);
+            accw(harm2(am, sa[sm][c]), sm, c);
+            accw(harm2(am, sa[sp][c]), sp, c);
+        }
         V2 o;
         block_solve<R>(f, b, gp, gT, Sp, ST, o);
         su[s][c] = o;
@@ -1201,175 +1235,118 @@ __global__ __launch_bounds__(TX *TY) void k_rb_fused3(Lvl<R> L, typename VT<R>::
     write_plane(z1 - 1);
 }
 
-// 2-D: planes are rows (march along y), the tile is TX cells along x; the
-// same software-pipelined 5-row ring as the 3-D kernel.
-template <typename R, int TX, bool ZG>
-__global__ __launch_bounds__(TX) void k_rb_fused2(Lvl<R> L, typename VT<R>::v2 *__restrict__ uo,
-                                                  int yc, int tiles_x, int ntiles)
+// 2-D: one whole red-black sweep per TX x TY tile, not marching: the tile
+// and a ring of 2 cells (u and the cell coefficients, or the stored faces)
+// in LDS, red over the tile and a ring of one, then black over the tile.
+// 2-D levels are small enough that thousands of independent tiles fill
+// the chip.  Cells outside the grid carry zero coefficients.
+template <typename R, int TX, int TY, bool ZG, bool FACES>
+__global__ __launch_bounds__(TX *TY) void k_rb_tile2(Lvl<R> L, typename VT<R>::v2 *__restrict__ uo,
+                                                     int tiles_x, int ntiles)
 {
     using V2 = typename VT<R>::v2;
     using V4 = typename VT<R>::v4;
-    constexpr int PX = TX + 4;
-    constexpr int NLD = (PX + TX - 1) / TX;
-    constexpr int RW = (TX + 2) / 2;
-    __shared__ V2 su[5][PX];
-    __shared__ V2 sa[5][PX];
+    constexpr int NT = TX * TY;
+    constexpr int PX = TX + 4, PY = TY + 4, PS = PX * PY;
+    constexpr int RW = (TX + 2) / 2, BW = TX / 2;
+    constexpr int PA = FACES ? 1 : PS, PF = FACES ? PS : 1;
+    __shared__ V2 su[PS];
+    __shared__ V2 sa[PA];
+    __shared__ V2 sfx[PF], sfy[PF];
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     if (tile >= ntiles) return;
-    const int x0 = (tile % tiles_x) * TX;
-    const int y0 = (tile / tiles_x) * yc, y1 = min(y0 + yc, L.ny);
+    const int x0 = (tile % tiles_x) * TX, y0 = (tile / tiles_x) * TY;
     const R ih2 = (R)L.inv_h2;
     const int t = threadIdx.x;
-    auto slot = [](int y) { return (y + 10) % 5; };
-
-    V2 pu[NLD], pa[NLD];
-    auto fetch_row = [&](int y) {
-#pragma unroll
-        for (int i = 0; i < NLD; i++) {
-            const int c = t + i * TX;
-            pu[i].x = pu[i].y = R(0);
-            pa[i].x = pa[i].y = R(0);
-            const int gx = x0 + c - 2;
-            if (c < PX && y >= 0 && y < L.ny && gx >= 0 && gx < L.nx) {
-                const long long g = gx + (long long)L.nx * y;
-                pa[i] = L.ac[g];
-                if (!ZG) pu[i] = L.u[g];
+    for (int c = t; c < PS; c += NT) {
+        const int gx = x0 + c % PX - 2, gy = y0 + c / PX - 2;
+        V2 u, a, fx, fy;
+        u.x = u.y = a.x = a.y = fx.x = fx.y = fy.x = fy.y = R(0);
+        if (gx >= 0 && gx < L.nx && gy >= 0 && gy < L.ny) {
+            const long long g = gx + (long long)L.nx * gy;
+            if (FACES) {
+                fx = L.fx[g];
+                fy = L.fy[g];
+            } else {
+                a = L.ac[g];
             }
+            if (!ZG) u = L.u[g];
         }
-    };
-    auto store_row = [&](int y) {
-        const int s = slot(y);
-#pragma unroll
-        for (int i = 0; i < NLD; i++) {
-            const int c = t + i * TX;
-            if (c < PX) {
-                su[s][c] = pu[i];
-                sa[s][c] = pa[i];
-            }
+        su[c] = u;
+        if (FACES) {
+            sfx[c] = fx;
+            sfy[c] = fy;
+        } else {
+            sa[c] = a;
         }
-    };
-    auto red_cell = [&](int y, int &c, long long &g) {
-        c = -1;
-        if (y < 0 || y >= L.ny || t >= RW) return;
-        const int lx = 1 + 2 * t + ((x0 - 1 + y) & 1);
-        const int gx = x0 + lx - 2;
-        if (gx < 0 || gx >= L.nx) return;
-        c = lx;
-        g = gx + (long long)L.nx * y;
-    };
-    auto black_cell = [&](int y, int &c, long long &g) {
-        c = -1;
-        if (y < 0 || y >= L.ny || t >= TX / 2) return;
-        const int lx = 2 + 2 * t + (1 - ((x0 + y) & 1));
-        const int gx = x0 + lx - 2;
-        if (gx >= L.nx) return;
-        c = lx;
-        g = gx + (long long)L.nx * y;
-    };
-    auto update = [&](int y, int c, V2 f, V4 b) {
-        const int s = slot(y), sm = slot(y - 1), sp = slot(y + 1);
-        const V2 am = sa[s][c];
+    }
+    __syncthreads();
+    auto update = [&](int c, long long g) {
         R gp = R(0), gT = R(0), Sp = R(0), ST = R(0);
-        auto acc = [&](int ss, int q) {
-            V2 w = harm2(am, sa[ss][q]);
+        auto accw = [&](V2 w, int q) {
             const R wp = w.x * ih2, wT = w.y * ih2;
-            const V2 uq = su[ss][q];
+            const V2 uq = su[q];
             Sp += wp;
             ST += wT;
             gp += wp * uq.x;
             gT += wT * uq.y;
         };
-        acc(s, c - 1);
-        acc(s, c + 1);
-        acc(sm, c);
-        acc(sp, c);
+        if (FACES) {
+            accw(sfx[c], c - 1);
+            accw(sfx[c + 1], c + 1);
+            accw(sfy[c], c - PX);
+            accw(sfy[c + PX], c + PX);
+        } else {
+            const V2 am = sa[c];
+            accw(harm2(am, sa[c - 1]), c - 1);
+            accw(harm2(am, sa[c + 1]), c + 1);
+            accw(harm2(am, sa[c - PX]), c - PX);
+            accw(harm2(am, sa[c + PX]), c + PX);
+        }
         V2 o;
-        block_solve<R>(f, b, gp, gT, Sp, ST, o);
-        su[s][c] = o;
+        block_solve<R>(L.f[g], L.B[g], gp, gT, Sp, ST, o);
+        su[c] = o;
     };
-    auto write_row = [&](int y) {
-        if (y < y0 || y >= y1) return;
-        const int gx = x0 + t;
-        if (gx < L.nx) uo[gx + (long long)L.nx * y] = su[slot(y)][2 + t];
-    };
-
-    for (int y = y0 - 2; y <= y0 + 1; y++) {
-        fetch_row(y);
-        store_row(y);
+    if (t < RW * (TY + 2)) {   // red cells ((x+y) even) of the tile and a ring of one
+        const int ly = 1 + t / RW;
+        const int gy = y0 + ly - 2;
+        const int lx = 1 + 2 * (t % RW) + ((x0 - 1 + gy) & 1);
+        const int gx = x0 + lx - 2;
+        if (gx >= 0 && gx < L.nx && gy >= 0 && gy < L.ny) update(ly * PX + lx, gx + (long long)L.nx * gy);
     }
     __syncthreads();
-    for (int y = y0 - 1; y <= y0; y++) {
-        int c;
-        long long g;
-        red_cell(y, c, g);
-        if (c >= 0) update(y, c, L.f[g], L.B[g]);
-        __syncthreads();
-    }
-    int rc, bc;
-    long long rg, bg;
-    V2 rf, bf;
-    V4 rB, bB;
-    fetch_row(y0 + 2);
-    red_cell(y0 + 1, rc, rg);
-    if (rc >= 0) {
-        rf = L.f[rg];
-        rB = L.B[rg];
-    }
-    black_cell(y0, bc, bg);
-    if (bc >= 0) {
-        bf = L.f[bg];
-        bB = L.B[bg];
-    }
-    for (int k = y0; k < y1; k++) {
-        store_row(k + 2);
-        int rcn, bcn;
-        long long rgn, bgn;
-        V2 rfn, bfn;
-        V4 rBn, bBn;
-        fetch_row(k + 3);
-        red_cell(k + 2, rcn, rgn);
-        if (rcn >= 0) {
-            rfn = L.f[rgn];
-            rBn = L.B[rgn];
-        }
-        black_cell(k + 1, bcn, bgn);
-        if (bcn >= 0 && k + 1 < y1) {
-            bfn = L.f[bgn];
-            bBn = L.B[bgn];
-        }
-        __syncthreads();
-        write_row(k - 1);
-        if (rc >= 0) update(k + 1, rc, rf, rB);
-        __syncthreads();
-        if (bc >= 0) update(k, bc, bf, bB);
-        rc = rcn;
-        rg = rgn;
-        rf = rfn;
-        rB = rBn;
-        bc = (k + 1 < y1) ? bcn : -1;
-        bg = bgn;
-        bf = bfn;
-        bB = bBn;
+    if (t < BW * TY) {         // black cells of the tile
+        const int ly = 2 + t / BW;
+        const int gy = y0 + ly - 2;
+        const int lx = 2 + 2 * (t % BW) + (1 - ((x0 + gy) & 1));
+        const int gx = x0 + lx - 2;
+        if (gx < L.nx && gy < L.ny) update(ly * PX + lx, gx + (long long)L.nx * gy);
     }
     __syncthreads();
-    write_row(y1 - 1);
+    {
+        const int lx = 2 + t % TX, ly = 2 + t / TX;
+        const int gx = x0 + lx - 2, gy = y0 + ly - 2;
+        if (gx < L.nx && gy < L.ny) uo[gx + (long long)L.nx * gy] = su[ly * PX + lx];
+    }
 }
 
 // Reads the old iterate from L.u and writes the swept one to uo (a
 // different buffer: blocks read halo cells that other blocks update).
+// faces = 0: the finest grid (cell coefficients); 1: a coarse level.
 template <typename R>
-void launch_rb_fused(int dim, const Lvl<R> &L, typename VT<R>::v2 *uo, int zero_guess,
+void launch_rb_fused(int dim, const Lvl<R> &L, typename VT<R>::v2 *uo, int zero_guess, int faces,
                      hipStream_t s)
 {
     if (dim == 3) {
-        // tile 64 x TY: TY = 8 by default; 16 (FP32 only: its 5-plane LDS
-        // ring of a 68 x 20 plane needs 109 KB) or 4 through PTMG_TILE_Y
+        // tile 64 x TY: TY = 8 on the finest grid by default (16: FP32 only,
+        // 4: through PTMG_TILE_Y); 4 on coarse levels (their LDS rings are
+        // larger)
         static const int ty_env = [] {
             const char *e = getenv("PTMG_TILE_Y");
             return e ? atoi(e) : 8;
         }();
         constexpr int TX = 64;
-        const int TY = (ty_env == 16 && sizeof(R) == 4) ? 16 : (ty_env == 4 ? 4 : 8);
+        const int TY = faces ? 4 : ((ty_env == 16 && sizeof(R) == 4) ? 16 : (ty_env == 4 ? 4 : 8));
         const int tx = (L.nx + TX - 1) / TX, ty = (L.ny + TY - 1) / TY;
         // chunk the z walk so that the grid has enough blocks to fill the chip
         const long long want = TY == 16 ? 512 : (TY == 8 ? 1024 : 2048);
@@ -1377,38 +1354,43 @@ void launch_rb_fused(int dim, const Lvl<R> &L, typename VT<R>::v2 *uo, int zero_
         while (zc > 16 && (long long)tx * ty * ((L.nz + zc - 1) / zc) < want) zc = (zc + 1) / 2;
         const int tz = (L.nz + zc - 1) / zc;
         const int nt = tx * ty * tz;
-#define PTMG_FUSED3(TYC, ZGC)                                                                  \
-    hipLaunchKernelGGL((k_rb_fused3<R, TX, TYC, ZGC>), dim3(nt), dim3(TX * TYC), 0, s, L, uo, zc, \
-                       tx, ty, nt)
-        if (TY == 16) {
+#define PTMG_FUSED3(TYC, ZGC, FC)                                                              \
+    hipLaunchKernelGGL((k_rb_fused3<R, TX, TYC, ZGC, FC>), dim3(nt), dim3(TX * TYC), 0, s, L, uo, \
+                       zc, tx, ty, nt)
+        if (faces) {
+            if (zero_guess) PTMG_FUSED3(4, true, true);
+            else PTMG_FUSED3(4, false, true);
+        } else if (TY == 16) {
             if constexpr (sizeof(R) == 4) {
-                if (zero_guess) PTMG_FUSED3(16, true);
-                else PTMG_FUSED3(16, false);
+                if (zero_guess) PTMG_FUSED3(16, true, false);
+                else PTMG_FUSED3(16, false, false);
             }
         } else if (TY == 8) {
-            if (zero_guess) PTMG_FUSED3(8, true);
-            else PTMG_FUSED3(8, false);
+            if (zero_guess) PTMG_FUSED3(8, true, false);
+            else PTMG_FUSED3(8, false, false);
         } else {
-            if (zero_guess) PTMG_FUSED3(4, true);
-            else PTMG_FUSED3(4, false);
+            if (zero_guess) PTMG_FUSED3(4, true, false);
+            else PTMG_FUSED3(4, false, false);
         }
 #undef PTMG_FUSED3
     } else {
-        constexpr int TX = 256;
-        const int tx = (L.nx + TX - 1) / TX;
-        int yc = L.ny;
-        while (yc > 8 && (long long)tx * ((L.ny + yc - 1) / yc) < 1024) yc = (yc + 1) / 2;
-        const int nt = tx * ((L.ny + yc - 1) / yc);
-        if (zero_guess)
-            hipLaunchKernelGGL((k_rb_fused2<R, TX, true>), dim3(nt), dim3(TX), 0, s, L, uo, yc, tx,
-                               nt);
-        else
-            hipLaunchKernelGGL((k_rb_fused2<R, TX, false>), dim3(nt), dim3(TX), 0, s, L, uo, yc, tx,
-                               nt);
+        constexpr int TX = 64, TY = 8;
+        const int tx = (L.nx + TX - 1) / TX, ty = (L.ny + TY - 1) / TY;
+        const int nt = tx * ty;
+#define PTMG_TILE2(ZGC, FC) \
+    hipLaunchKernelGGL((k_rb_tile2<R, TX, TY, ZGC, FC>), dim3(nt), dim3(TX * TY), 0, s, L, uo, tx, nt)
+        if (faces) {
+            if (zero_guess) PTMG_TILE2(true, true);
+            else PTMG_TILE2(false, true);
+        } else {
+            if (zero_guess) PTMG_TILE2(true, false);
+            else PTMG_TILE2(false, false);
+        }
+#undef PTMG_TILE2
     }
 }
-template void launch_rb_fused<float>(int, const Lvl<float> &, float2 *, int, hipStream_t);
-template void launch_rb_fused<double>(int, const Lvl<double> &, double2 *, int, hipStream_t);
+template void launch_rb_fused<float>(int, const Lvl<float> &, float2 *, int, int, hipStream_t);
+template void launch_rb_fused<double>(int, const Lvl<double> &, double2 *, int, int, hipStream_t);
 
 }  // namespace ptmg
 

@@ -21,7 +21,7 @@ STATUS_NAMES = {0: "PT_OK", 1: "PT_ERR_ARG", 2: "PT_ERR_OOM", 3: "PT_ERR_SINGULA
 PT_COEF_EXPLICIT, PT_COEF_PHASES = 0, 1
 PT_PREC_FP64, PT_PREC_MIXED = 0, 1
 PT_MAX_HIST = 64
-PT_OPT_GRAPHS, PT_OPT_TAIL = 1, 2
+PT_OPT_GRAPHS, PT_OPT_TAIL, PT_OPT_FUSED = 1, 2, 3
 KERNEL_CLASSES = ["outer_residual", "smooth_fine", "smooth_coarse", "restrict", "prolong",
                   "coarse_solve", "other"]
 

@@ -223,9 +223,9 @@ def test_graph_replay_matches_direct_launches(name):
                                   "twobubble2d_96x80"])
 @pytest.mark.parametrize("prec", [0, 1])
 def test_tail_and_graph_paths_agree(name, prec):
-    """The single-block tail cycle and the graph replay run the same
-    per-cell arithmetic as the grid kernels: solves and V-cycles agree with
-    the plain launch path bit for bit."""
+    """The fused sweeps, the single-block tail cycle and the graph replay
+    run the same per-cell arithmetic as the plain colour passes: solves and
+    V-cycles agree with the reference launch path bit for bit."""
     import workloads.device as D
     from paper_2206_11294_amd import ptmg
     prob = step_problems()[name]
@@ -235,9 +235,10 @@ def test_tail_and_graph_paths_agree(name, prec):
         rng = np.random.default_rng(2)
         f_p, f_T = dev(rng.uniform(-1, 1, h.N)), dev(rng.uniform(-1, 1, h.N))
         out = {}
-        for opts in ((1, 1), (0, 0)):
+        for opts in ((1, 1, 1), (0, 0, 0)):
             h.set_option(ptmg.PT_OPT_GRAPHS, opts[0])
             h.set_option(ptmg.PT_OPT_TAIL, opts[1])
+            h.set_option(ptmg.PT_OPT_FUSED, opts[2])
             p, T = torch.empty_like(b_p), torch.empty_like(b_T)
             h.solve(b_p, b_T, p, T, rtol=1e-12)
             e = h.vcycle(f_p, f_T)
@@ -246,5 +247,5 @@ def test_tail_and_graph_paths_agree(name, prec):
         h.set_option(ptmg.PT_OPT_TAIL, 1)
         if name == "explicit_64":   # 32^2 .. 4^2 fit in one block's LDS
             assert h.get_option(ptmg.PT_OPT_TAIL) >= 4
-    for a, b in zip(out[(1, 1)], out[(0, 0)]):
+    for a, b in zip(out[(1, 1, 1)], out[(0, 0, 0)]):
         assert torch.equal(a, b), (a - b).abs().max().item()
