@@ -236,12 +236,15 @@ struct pt_mg_s {
     }
 
     // --- timing --------------------------------------------------------
-    void begin(int cls, double nbytes)
+    // A run of back-to-back launches of one class may share one event pair
+    // (open only on the first, close only on the last): the per-launch
+    // average then carries the event overhead once per run.
+    void begin(int cls, double nbytes, bool open = true)
     {
         launches[cls]++;
         bytes[cls] += nbytes;
         timed_now = (timing >> cls) & 1u;
-        if (!timed_now) return;
+        if (!timed_now || !open) return;
         TimerRec r;
         r.cls = cls;
         r.a = event();
@@ -250,9 +253,9 @@ struct pt_mg_s {
         pending.push_back(r);
     }
     bool timed_now = false;
-    void end()
+    void end(bool close = true)
     {
-        if (!timed_now) return;
+        if (!timed_now || !close) return;
         (void)hipEventRecord(pending.back().b, stream);
     }
     hipEvent_t event()
@@ -338,9 +341,9 @@ template <typename R> void smooth(pt_mg_t h, int l, int sweeps, bool zero_guess)
             typename VT<R>::v2 *uo = h->level<R>(l).u;
             const double coef = (l == 0 ? 2 : 2 * h->P.dim) * Rb;   // cell or face coefficients
             const double nb = (double)L.N * ((zg ? 0 : 2 * Rb) + 2 * Rb + coef + 4 * Rb + 2 * Rb);
-            h->begin(l == 0 ? PT_K_SMOOTH_FINE : PT_K_SMOOTH_COARSE, nb);
+            h->begin(l == 0 ? PT_K_SMOOTH_FINE : PT_K_SMOOTH_COARSE, nb, s == 0);
             launch_rb_fused<R>(h->P.dim, L, uo, zg ? 1 : 0, l == 0 ? 0 : 1, h->stream);
-            h->end();
+            h->end(s == sweeps - 1);
             h->updates += L.N;
         }
         return;
