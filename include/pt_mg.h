@@ -236,17 +236,25 @@ typedef enum {
     PT_K_COUNT = 7
 } pt_kernel_class;
 
-/* Per-launch HIP-event timing (off by default): on = 0 off, 1 every
- * kernel class, otherwise 1 + 2 * (bit mask of pt_kernel_class values)
- * times only those classes.  Each timed launch gets an event pair on the
- * handle's stream. */
+/* HIP-event timing (off by default): on = 0 off, 1 every kernel class,
+ * otherwise 1 + 2 * (bit mask of pt_kernel_class values) times only those
+ * classes.  A run of back-to-back launches of one class (the nu sweeps of
+ * one smoothing step on one level, or a single launch) is bracketed by one
+ * event pair on the handle's stream; option PT_OPT_TIMING_EVERY = n times
+ * only every n-th run of each class (the events themselves cost a few
+ * microseconds of stream time). */
 int pt_mg_set_timing(pt_mg_t h, int on);
 
-/* Launches and summed milliseconds of one class since the last reset,
- * plus the algorithmic bytes the launches moved (the model of each
- * kernel: every array it must read or write once, halos excluded). */
+/* All launches of one class since the last reset and their algorithmic
+ * bytes (the model of each kernel: every array it must read or write
+ * once, halos excluded), plus the summed milliseconds of its timed runs. */
 int pt_mg_kernel_stats(pt_mg_t h, int kernel_class, long *launches, double *ms,
                        double *bytes);
+/* The timed runs of one class alone: their launches, summed milliseconds
+ * and algorithmic bytes (bytes / ms is the class's achieved bandwidth).
+ * Call after the stream has been synchronised; pairs still in flight are
+ * counted once they complete. */
+int pt_mg_timed_stats(pt_mg_t h, int kernel_class, long *launches, double *ms, double *bytes);
 int pt_mg_reset_stats(pt_mg_t h);
 
 /* Cell-updates performed by the last pt_mg_solve: smoother cell updates
@@ -261,8 +269,23 @@ long long pt_mg_last_cell_updates(pt_mg_t h);
  *    single-block kernel; default 1.  pt_mg_get_option returns, for
  *    PT_OPT_TAIL, the number of levels the tail covers (0 if none).
  *  PT_OPT_FUSED: each red-black sweep as one fused pass over memory;
- *    0: two colour passes (the reference path); default 1. */
-typedef enum { PT_OPT_GRAPHS = 1, PT_OPT_TAIL = 2, PT_OPT_FUSED = 3 } pt_option;
+ *    0: two colour passes (the reference path); default 1.
+ *  PT_OPT_TIMING_EVERY: with timing on, time one run in every n of each
+ *    class (n >= 1, default 1; PT_ERR_ARG otherwise).
+ *  PT_OPT_SPECULATE: enqueue the next outer iteration (V-cycle, FP64
+ *    update, residual and norms) before the host has read the current
+ *    norms, whenever the contraction seen so far predicts that the
+ *    current iterate misses the tolerance by a factor of 30 or more (and,
+ *    from a zero guess, the first cycle at once).  The solution, cycles
+ *    and history are those of the step-by-step loop; a wrong guess costs
+ *    one V-cycle of device time.  Default 1. */
+typedef enum {
+    PT_OPT_GRAPHS = 1,
+    PT_OPT_TAIL = 2,
+    PT_OPT_FUSED = 3,
+    PT_OPT_TIMING_EVERY = 4,
+    PT_OPT_SPECULATE = 5
+} pt_option;
 int pt_mg_set_option(pt_mg_t h, int option, int value);
 int pt_mg_get_option(pt_mg_t h, int option);
 

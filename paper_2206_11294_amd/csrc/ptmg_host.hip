@@ -31,7 +31,7 @@ struct Plan {
     int n[3] = {1, 1, 1};
     long long N = 0;
     LevelPlan lv[kMaxLevels];
-    size_t o_ac64, o_B64, o_xp, o_xT, o_partials, o_flags, o_norms, o_gj0, o_gj1;
+    size_t o_ac64, o_B64, o_xp, o_xT, o_partials, o_flags, o_gj0, o_gj1;
     size_t total = 0;
     size_t take(size_t bytes)
     {
@@ -127,13 +127,14 @@ const char *plan_problem(const pt_problem *p, int prec, Plan &P)
                          outer_zm_blocks(p->dim, p->n[0], p->n[1], p->n[2]));
     P.o_partials = P.take(8ull * (4 * ((size_t)P.nblocks + reduce_scratch(P.nblocks)) + 16));
     P.o_flags = P.take(sizeof(int) * NFLAGS);
-    P.o_norms = P.take(8 * 8);
     return nullptr;
 }
 
 struct TimerRec {
     int cls;
     hipEvent_t a, b;
+    long launches = 0;   // launches between a and b
+    double bytes = 0;    // their algorithmic bytes
 };
 
 // A captured V-cycle of the coarse levels (1 .. L-1), with the counters its
@@ -164,34 +165,51 @@ struct pt_mg_s {
     bool owns_memory = true;        // false: device + pinned memory belong to a server arena
     hipEvent_t done_ev = nullptr;   // marks the end of the last enqueued step
     // asynchronous solve (pt_mg_solve drives it to the end; a server polls it)
+    // Outer iteration k computes u_k (k >= 1: after V-cycle k-1) and the
+    // norms of its residual into pinned slot k & 1, marked by norm_ev[k & 1].
+    // u_k lives in the caller's (p, T) for even k and in the handle's
+    // second FP64 pair for odd k.  The host reads the norms of k_wait while
+    // outer k_wait + 1 (and, when the contraction so far predicts that k_wait
+    // + 1 cannot meet the tolerance, outer k_wait + 2) is already enqueued,
+    // so the device does not idle while the host decides.
+    hipEvent_t norm_ev[2] = {nullptr, nullptr};
+    double *norms_devp = nullptr;   // device address of norms_host
     struct Solve {
         int phase = 0;              // 0 idle, 1 iterating (norms in flight), 2 finishing
         pt_solve_opts o;
         const double *b_p = nullptr, *b_T = nullptr;
         double *p = nullptr, *T = nullptr;
-        const double *cur_p = nullptr, *cur_T = nullptr;
-        bool in_caller = true;
         const double *bshift = nullptr;
-        int cycles = 0, status = PT_ERR_NOCONV, nb = 0;
+        int k_wait = 0, k_enq = -1;
+        int status = PT_ERR_NOCONV;
+        bool have_prev = false;
+        double prev[2] = {0, 0};
+        long long upd[2] = {0, 0};  // cell-updates enqueued up to outer k (slot k & 1)
         pt_solve_info inf;
         std::chrono::steady_clock::time_point t0;
     } sv;
+    bool speculate = true;
     unsigned u_cur = 0;             // bit l: level l's current iterate is in its second buffer
     bool use_fused = true;          // false: two colour passes per sweep (reference path)
     // measurement
     unsigned timing = 0;            // bit c set: time launches of kernel class c
-    std::vector<hipEvent_t> ev_pool;
-    size_t ev_used = 0;
+    int timing_every = 1;           // time one run in this many of a timed class
+    long runs[PT_K_COUNT] = {0};
+    std::vector<hipEvent_t> ev_free;
+    std::vector<hipEvent_t> ev_all;
     std::vector<TimerRec> pending;
     long launches[PT_K_COUNT] = {0};
-    double ms[PT_K_COUNT] = {0};
     double bytes[PT_K_COUNT] = {0};
+    long timed_launches[PT_K_COUNT] = {0};
+    double timed_bytes[PT_K_COUNT] = {0};
+    double ms[PT_K_COUNT] = {0};
     long long updates = 0, last_updates = 0;
     std::vector<CoarseGraph> graphs;
     bool use_graphs = true;
     // single-block tail cycle over levels tail_lt .. nlev-1 (0: not used)
     int tail_lt = 0;
     size_t tail_lds = 0;
+    int tail_ainv_off = -1;
     bool use_tail = true;
 
     template <typename T> T *at(size_t off) { return off == (size_t)-1 ? nullptr : (T *)(base + off); }
@@ -199,7 +217,6 @@ struct pt_mg_s {
     double4 *B64() { return at<double4>(P.o_B64); }
     double *partials() { return at<double>(P.o_partials); }
     int *flags() { return at<int>(P.o_flags); }
-    double *norms_dev() { return at<double>(P.o_norms); }
 
     template <typename R> Lvl<R> level(int l)
     {
@@ -236,45 +253,72 @@ struct pt_mg_s {
     }
 
     // --- timing --------------------------------------------------------
-    // A run of back-to-back launches of one class may share one event pair
-    // (open only on the first, close only on the last): the per-launch
-    // average then carries the event overhead once per run.
+    // A run of back-to-back launches of one class shares one event pair
+    // (opened by the first launch, closed by the last), so the per-launch
+    // average carries the event overhead once per run; with timing_every
+    // = n only one run in n of a class is timed at all.
     void begin(int cls, double nbytes, bool open = true)
     {
         launches[cls]++;
         bytes[cls] += nbytes;
-        timed_now = (timing >> cls) & 1u;
-        if (!timed_now || !open) return;
-        TimerRec r;
-        r.cls = cls;
-        r.a = event();
-        r.b = event();
-        (void)hipEventRecord(r.a, stream);
-        pending.push_back(r);
+        if (open) {
+            timed_now = ((timing >> cls) & 1u) && (runs[cls]++ % timing_every) == 0;
+            if (timed_now) {
+                TimerRec r;
+                r.cls = cls;
+                r.a = event();
+                r.b = event();
+                (void)hipEventRecord(r.a, stream);
+                pending.push_back(r);
+            }
+        }
+        if (timed_now) {
+            pending.back().launches++;
+            pending.back().bytes += nbytes;
+        }
     }
     bool timed_now = false;
     void end(bool close = true)
     {
         if (!timed_now || !close) return;
         (void)hipEventRecord(pending.back().b, stream);
+        timed_now = false;
     }
     hipEvent_t event()
     {
-        if (ev_used == ev_pool.size()) {
+        if (ev_free.empty()) {
             hipEvent_t e;
             (void)hipEventCreate(&e);
-            ev_pool.push_back(e);
+            ev_all.push_back(e);
+            return e;
         }
-        return ev_pool[ev_used++];
+        hipEvent_t e = ev_free.back();
+        ev_free.pop_back();
+        return e;
     }
-    void flush_timing()   // after the stream has been synchronised
+    void flush_timing()   // takes the pairs whose launches have completed
     {
-        for (auto &r : pending) {
+        size_t keep = 0;
+        bool not_ready = false;
+        for (size_t i = 0; i < pending.size(); i++) {
+            TimerRec &r = pending[i];
             float t = 0.f;
-            if (hipEventElapsedTime(&t, r.a, r.b) == hipSuccess) ms[r.cls] += t;
+            hipError_t e = hipEventElapsedTime(&t, r.a, r.b);
+            if (e == hipErrorNotReady) {
+                pending[keep++] = r;
+                not_ready = true;
+                continue;
+            }
+            if (e == hipSuccess) {
+                ms[r.cls] += t;
+                timed_launches[r.cls] += r.launches;
+                timed_bytes[r.cls] += r.bytes;
+            }
+            ev_free.push_back(r.a);
+            ev_free.push_back(r.b);
         }
-        pending.clear();
-        ev_used = 0;
+        pending.resize(keep);
+        if (not_ready) (void)hipGetLastError();   // not an error of the next call
     }
 };
 
@@ -328,6 +372,14 @@ bool fused_level(pt_mg_t h, int l)
     return h->use_fused && (h->P.dim == 2 || l == 0 || h->P.lv[l].N >= (1ll << 20));
 }
 
+// 2-D coarse levels (not the coarsest) with nu1, nu2 in {1, 2}: each
+// visit of the level in a V-cycle is a single kernel.
+bool half_level(pt_mg_t h, int l, int nu1, int nu2)
+{
+    return h->use_fused && h->P.dim == 2 && l >= 1 && l + 1 < h->P.nlev && nu1 >= 1 && nu1 <= 2 &&
+           nu2 >= 1 && nu2 <= 2;
+}
+
 template <typename R> void smooth(pt_mg_t h, int l, int sweeps, bool zero_guess)
 {
     if (fused_level(h, l)) {
@@ -359,6 +411,31 @@ template <typename R> void smooth(pt_mg_t h, int l, int sweeps, bool zero_guess)
         launch_rb_pass<R>(h->P.dim, l == 0, L, 1, 0, h->stream);
         h->end();
         h->updates += L.N;
+    }
+}
+
+// 2-D finest level with fused transfers: the first sweep after the coarse
+// correction adds the prolonged correction as it loads the iterate (pro),
+// the last sweep before the coarse cycle restricts its residual (res).
+bool fused_transfers0(pt_mg_t h, int nu1, int nu2)
+{
+    return h->use_fused && h->P.dim == 2 && h->P.nlev > 1 && nu1 >= 1 && nu2 >= 1;
+}
+
+template <typename R> void smooth0_fused(pt_mg_t h, int sweeps, bool zero_guess, bool pro, bool res)
+{
+    const double Rb = sizeof(R);
+    for (int s = 0; s < sweeps; s++) {
+        const bool zg = zero_guess && s == 0, p = pro && s == 0, r = res && s == sweeps - 1;
+        Lvl<R> L = h->level<R>(0), C = h->level<R>(1);
+        h->u_cur ^= 1u;
+        typename VT<R>::v2 *uo = h->level<R>(0).u;
+        double nb = (double)L.N * ((zg ? 0 : 2 * Rb) + 2 * Rb + 2 * Rb + 4 * Rb + 2 * Rb);
+        if (p || r) nb += (double)C.N * 2 * Rb;   // coarse u read, or coarse f written
+        h->begin(PT_K_SMOOTH_FINE, nb, s == 0);
+        launch_tile2x<R>(L, C, uo, zg ? 1 : 0, p ? 1 : 0, r ? 1 : 0, h->stream);
+        h->end(s == sweeps - 1);
+        h->updates += L.N * (r ? 2 : 1);
     }
 }
 
@@ -469,6 +546,7 @@ template <typename R> void tail_cycle(pt_mg_t h, int nu1, int nu2)
     a.nu1 = nu1;
     a.nu2 = nu2;
     a.Ainv = h->Ainv;
+    a.ainv_off = h->tail_ainv_off;
     size_t off = 0;
     double nbytes = 8.0 * P.m * P.m;
     for (int q = 0; q < a.nl; q++) {
@@ -501,6 +579,32 @@ template <typename R> void vcycle(pt_mg_t h, int l, int nu1, int nu2)
     }
     if (l == h->P.nlev - 1) {
         coarse_solve<R>(h);
+        return;
+    }
+    if (l == 0 && fused_transfers0(h, nu1, nu2)) {
+        smooth0_fused<R>(h, nu1, true, false, true);
+        coarse_cycle<R>(h, nu1, nu2);
+        smooth0_fused<R>(h, nu2, false, true, false);
+        return;
+    }
+    if (half_level(h, l, nu1, nu2)) {
+        // one kernel per visit: down (sweeps + residual + restriction) and
+        // up (prolongation + sweeps)
+        const double Rb = sizeof(R);
+        Lvl<R> L = h->level<R>(l), C = h->level<R>(l + 1);
+        h->begin(PT_K_SMOOTH_COARSE, (double)L.N * 12 * Rb + (double)C.N * 2 * Rb);
+        launch_half2<R>(false, nu1, L, C, nullptr, h->stream);
+        h->end();
+        h->updates += (long long)(nu1 + 1) * L.N;
+        vcycle<R>(h, l + 1, nu1, nu2);
+        L = h->level<R>(l);
+        C = h->level<R>(l + 1);
+        h->u_cur ^= 1u << l;
+        typename VT<R>::v2 *uo = h->level<R>(l).u;
+        h->begin(PT_K_SMOOTH_COARSE, (double)L.N * 14 * Rb + (double)C.N * 2 * Rb);
+        launch_half2<R>(true, nu2, L, C, uo, h->stream);
+        h->end();
+        h->updates += (long long)nu2 * L.N;
         return;
     }
     Lvl<R> L = h->level<R>(l);
@@ -652,6 +756,13 @@ void plan_tail(pt_mg_t h)
         lt = l;
     }
     if (P.nlev - lt < 2) return;
+    // a small coarsest inverse is copied into LDS with the levels
+    h->tail_ainv_off = -1;
+    const size_t ainv = ((size_t)8 * P.m * P.m + 15) & ~size_t(15);
+    if (P.m <= 32 && total + ainv <= budget) {
+        h->tail_ainv_off = (int)total;
+        total += ainv;
+    }
     h->tail_lt = lt;
     h->tail_lds = total;
     if (f32) tail_set_lds_limit<float>(P.dim, total);
@@ -729,11 +840,15 @@ int handle_create(const pt_problem *prob, int precision, hipStream_t stream, cha
         h->norms_host = (double *)pinned;
     }
     h->flags_host = (int *)(h->norms_host + 16);
-    if (hipEventCreateWithFlags(&h->done_ev, hipEventDisableTiming) != hipSuccess) {
+    bool ok = hipEventCreateWithFlags(&h->done_ev, hipEventDisableTiming) == hipSuccess;
+    for (int q = 0; q < 2 && ok; q++)
+        ok = hipEventCreateWithFlags(&h->norm_ev[q], hipEventDisableTiming) == hipSuccess;
+    // the reductions write the norms straight into the pinned slots
+    ok = ok && hipHostGetDevicePointer((void **)&h->norms_devp, h->norms_host, 0) == hipSuccess;
+    if (!ok) {
         (void)hipGetLastError();
-        h->done_ev = nullptr;
         pt_mg_destroy(h);
-        *err = "event creation failed";
+        *err = "event creation or pinned mapping failed";
         return PT_ERR_HIP;
     }
     plan_tail(h);
@@ -746,8 +861,6 @@ int handle_create(const pt_problem *prob, int precision, hipStream_t stream, cha
     *out = h;
     return PT_OK;
 }
-
-hipEvent_t handle_event(pt_mg_t h) { return h->done_ev; }
 
 // Paper right-hand side (Eqs. 33-34) enqueued without waiting.
 int handle_paper_rhs_async(pt_mg_t h, const double *p_adv, const double *T_adv,
@@ -808,7 +921,9 @@ void pt_mg_destroy(pt_mg_t h)
     if (!h) return;
     if (h->stream || h->base) (void)hipStreamSynchronize(h->stream);
     if (h->done_ev) (void)hipEventDestroy(h->done_ev);
-    for (auto e : h->ev_pool) (void)hipEventDestroy(e);
+    for (auto ev : h->norm_ev)
+        if (ev) (void)hipEventDestroy(ev);
+    for (auto e : h->ev_all) (void)hipEventDestroy(e);
     if (h->owns_memory) {
         if (h->base) (void)hipFree(h->base);
         if (h->norms_host) (void)hipHostFree(h->norms_host);
@@ -887,22 +1002,19 @@ int outer_any(pt_mg_t h, const double *b_p, const double *b_T, const double *src
                          bshift);
 }
 
-// Reduce the partial sums to 4 doubles and copy them to pinned host memory
-// (asynchronous; done_ev marks their arrival).
-int enqueue_norms(pt_mg_t h, int nb)
+// Reduce the partial sums to 4 doubles written straight into pinned host
+// slot `slot`; norm_ev[slot] marks their arrival.
+int enqueue_norms(pt_mg_t h, int nb, int slot)
 {
     h->begin(PT_K_OTHER, 32.0 * nb);
-    launch_reduce4(h->partials(), nb, h->norms_dev(), h->stream);
+    launch_reduce4(h->partials(), nb, h->norms_devp + 4 * slot, h->stream);
     h->end();
-    hipError_t e = hipMemcpyAsync(h->norms_host, h->norms_dev(), 4 * sizeof(double),
-                                  hipMemcpyDeviceToHost, h->stream);
-    if (e == hipSuccess) e = hipEventRecord(h->done_ev, h->stream);
-    return check_hip(h, e, "norm copy");
+    return check_hip(h, hipEventRecord(h->norm_ev[slot], h->stream), "norm event");
 }
 
 int read_norms(pt_mg_t h, int nb, double out[4])
 {
-    int rc = enqueue_norms(h, nb);
+    int rc = enqueue_norms(h, nb, 0);
     if (rc) return rc;
     rc = sync(h, "residual");
     if (rc) return rc;
@@ -941,10 +1053,53 @@ int pt_mg_residual(pt_mg_t h, const double *b_p, const double *b_T, const double
     return PT_OK;
 }
 
+namespace {
+
+// Where u_k lives (see pt_mg_s::Solve).
+void iterate_at(pt_mg_t h, int k, double **p, double **T)
+{
+    if (k % 2 == 0) {
+        *p = h->sv.p;
+        *T = h->sv.T;
+    } else {
+        *p = h->at<double>(h->P.o_xp);
+        *T = h->at<double>(h->P.o_xT);
+    }
+}
+
+// Enqueue outer iteration k: V-cycle k-1 on r_{k-1} and the FP64 update
+// u_k = u_{k-1} + du (k >= 1), the residual of u_k and its norms.
+int enqueue_outer(pt_mg_t h, int k)
+{
+    auto &S = h->sv;
+    int nb;
+    if (k == 0) {
+        nb = outer_any(h, S.b_p, S.b_T, S.p, S.T, nullptr, nullptr, false, true, nullptr, nullptr,
+                       S.bshift);
+    } else {
+        vcycle_any(h, S.o.nu1, S.o.nu2);
+        double *sp, *sT, *dp, *dT;
+        iterate_at(h, k - 1, &sp, &sT);
+        iterate_at(h, k, &dp, &dT);
+        nb = outer_any(h, S.b_p, S.b_T, sp, sT, dp, dT, true, true, nullptr, nullptr, S.bshift);
+    }
+    S.k_enq = k;
+    S.upd[k & 1] = h->updates;
+    return enqueue_norms(h, nb, k & 1);
+}
+
+}  // namespace
+
 namespace ptmg {
 
-// Start a solve: enqueue the initial residual and its norms.  Returns an
-// error, or PT_OK with the solve running (done_ev marks the norms).
+hipEvent_t handle_event(pt_mg_t h)
+{
+    return h->sv.phase == 1 ? h->norm_ev[h->sv.k_wait & 1] : h->done_ev;
+}
+
+// Start a solve: enqueue the initial residual and its norms (and, from a
+// zero guess, whose relative residual is 1, the first cycle).  Returns an
+// error, or PT_OK with the solve running (handle_event marks progress).
 int solve_begin(pt_mg_t h, const double *b_p, const double *b_T, double *p, double *T,
                 const pt_solve_opts *opts_in)
 {
@@ -974,18 +1129,17 @@ int solve_begin(pt_mg_t h, const double *b_p, const double *b_T, double *p, doub
     }
     // mean constraint: the right-hand side is used with its mean removed
     S.bshift = h->prob.mean_constraint ? grid_sums(h, b_p, b_T, 0) : nullptr;
-    S.cur_p = p;
-    S.cur_T = T;
-    S.in_caller = true;
-    S.nb = outer_any(h, b_p, b_T, p, T, nullptr, nullptr, false, true, nullptr, nullptr, S.bshift);
-    int rc = enqueue_norms(h, S.nb);
+    int rc = enqueue_outer(h, 0);
+    if (rc == PT_OK && h->speculate && o.zero_guess && o.rtol < 0.5 && o.max_cycles >= 1)
+        rc = enqueue_outer(h, 1);
     if (rc) return rc;
+    S.k_wait = 0;
     S.phase = 1;
     return PT_OK;
 }
 
-// Advance a running solve once its done_ev has completed: returns
-// PT_RUNNING (-1) after enqueuing the next step, or the final status.
+// Advance a running solve once handle_event has completed: returns
+// PT_RUNNING (-1) after enqueuing what follows, or the final status.
 int solve_advance(pt_mg_t h, pt_solve_info *info)
 {
     auto &S = h->sv;
@@ -993,7 +1147,8 @@ int solve_advance(pt_mg_t h, pt_solve_info *info)
     hipError_t e;
     h->flush_timing();
     if (S.phase == 1) {
-        const double *s = h->norms_host;
+        const int k = S.k_wait;
+        const double *s = h->norms_host + 4 * (k & 1);
         double rel[2] = {s[2] > 0 ? std::sqrt(s[0] / s[2]) : std::sqrt(s[0]),
                          s[3] > 0 ? std::sqrt(s[1] / s[3]) : std::sqrt(s[1])};
         auto &inf = S.inf;
@@ -1010,34 +1165,48 @@ int solve_advance(pt_mg_t h, pt_solve_info *info)
             h->err = "residual norm is not finite";
         } else if (rel[0] <= S.o.rtol && rel[1] <= S.o.rtol) {
             S.status = PT_OK;
-        } else if (S.cycles >= S.o.max_cycles) {
+        } else if (k >= S.o.max_cycles) {
             S.status = PT_ERR_NOCONV;
             h->err = "max_cycles reached";
         } else {
             finish = false;
         }
         if (!finish) {
-            vcycle_any(h, S.o.nu1, S.o.nu2);
-            S.cycles++;
-            double *X[2] = {h->at<double>(P.o_xp), h->at<double>(P.o_xT)};
-            double *dp = S.in_caller ? X[0] : S.p;
-            double *dT = S.in_caller ? X[1] : S.T;
-            S.nb = outer_any(h, S.b_p, S.b_T, S.cur_p, S.cur_T, dp, dT, true, true, nullptr,
-                             nullptr, S.bshift);
-            S.cur_p = dp;
-            S.cur_T = dT;
-            S.in_caller = !S.in_caller;
-            int rc = enqueue_norms(h, S.nb);
+            int rc = PT_OK;
+            if (S.k_enq == k) rc = enqueue_outer(h, k + 1);
+            // Outer k+2 ahead of the norms of k+1 when, at the contraction
+            // seen so far (0.1 before any), u_{k+1} still misses the
+            // tolerance by a wide margin; a wrong guess costs one cycle of
+            // device time, never a different result.
+            if (rc == PT_OK && h->speculate && S.k_enq == k + 1 && k + 2 <= S.o.max_cycles) {
+                constexpr double kMargin = 30.0;
+                bool ahead = false;
+                for (int c = 0; c < 2; c++) {
+                    double rate = S.have_prev && S.prev[c] > 0 ? rel[c] / S.prev[c] : 0.1;
+                    rate = std::min(rate, 1.0);
+                    if (rel[c] * rate > kMargin * S.o.rtol) ahead = true;
+                }
+                if (ahead) rc = enqueue_outer(h, k + 2);
+            }
             if (rc) {
                 S.phase = 0;
                 return rc;
             }
+            S.prev[0] = rel[0];
+            S.prev[1] = rel[1];
+            S.have_prev = true;
+            S.k_wait = k + 1;
             return PT_RUNNING;
         }
-        if (!S.in_caller) {
+        // u_k is the answer; later speculative outers wrote only the other
+        // buffer pair, and the copy below is ordered after them.
+        S.k_wait = k;
+        if (k % 2 == 1) {
+            double *xp, *xT;
+            iterate_at(h, k, &xp, &xT);
             h->begin(PT_K_OTHER, 32.0 * P.N);
-            launch_convert<double, double>(P.N, S.cur_p, S.p, h->stream);
-            launch_convert<double, double>(P.N, S.cur_T, S.T, h->stream);
+            launch_convert<double, double>(P.N, xp, S.p, h->stream);
+            launch_convert<double, double>(P.N, xT, S.T, h->stream);
             h->end();
         }
         if (h->prob.mean_constraint) {
@@ -1054,8 +1223,8 @@ int solve_advance(pt_mg_t h, pt_solve_info *info)
     }
     // phase 2: the final copies are done
     S.phase = 0;
-    h->last_updates = h->updates;
-    S.inf.cycles = S.cycles;
+    h->last_updates = S.upd[S.k_wait & 1];
+    S.inf.cycles = S.k_wait;
     S.inf.t_solve_s = elapsed(S.t0);
     S.inf.status = S.status;
     if (info) *info = S.inf;
@@ -1070,7 +1239,7 @@ int pt_mg_solve(pt_mg_t h, const double *b_p, const double *b_T, double *p, doub
     int rc = solve_begin(h, b_p, b_T, p, T, opts_in);
     if (rc != PT_OK) return rc;
     for (;;) {
-        rc = check_hip(h, hipEventSynchronize(h->done_ev), "solve");
+        rc = check_hip(h, hipEventSynchronize(handle_event(h)), "solve");
         if (rc == PT_OK) rc = check_hip(h, hipGetLastError(), "solve");
         if (rc != PT_OK) {
             h->sv.phase = 0;
@@ -1222,6 +1391,17 @@ int pt_mg_kernel_stats(pt_mg_t h, int cls, long *launches, double *ms, double *b
     return PT_OK;
 }
 
+int pt_mg_timed_stats(pt_mg_t h, int cls, long *launches, double *ms, double *bytes)
+{
+    if (!h) return fail(nullptr, PT_ERR_ARG, "handle is NULL");
+    if (cls < 0 || cls >= PT_K_COUNT) return fail(h, PT_ERR_ARG, "kernel class out of range");
+    h->flush_timing();
+    if (launches) *launches = h->timed_launches[cls];
+    if (ms) *ms = h->ms[cls];
+    if (bytes) *bytes = h->timed_bytes[cls];
+    return PT_OK;
+}
+
 int pt_mg_reset_stats(pt_mg_t h)
 {
     if (!h) return fail(nullptr, PT_ERR_ARG, "handle is NULL");
@@ -1229,6 +1409,9 @@ int pt_mg_reset_stats(pt_mg_t h)
         h->launches[c] = 0;
         h->ms[c] = 0;
         h->bytes[c] = 0;
+        h->timed_launches[c] = 0;
+        h->timed_bytes[c] = 0;
+        h->runs[c] = 0;
     }
     return PT_OK;
 }
@@ -1241,7 +1424,11 @@ int pt_mg_set_option(pt_mg_t h, int option, int value)
     if (option == PT_OPT_GRAPHS) h->use_graphs = value != 0;
     else if (option == PT_OPT_TAIL) h->use_tail = value != 0;
     else if (option == PT_OPT_FUSED) h->use_fused = value != 0;
-    else return fail(h, PT_ERR_ARG, "unknown option");
+    else if (option == PT_OPT_SPECULATE) h->speculate = value != 0;
+    else if (option == PT_OPT_TIMING_EVERY) {
+        if (value < 1) return fail(h, PT_ERR_ARG, "PT_OPT_TIMING_EVERY must be >= 1");
+        h->timing_every = value;
+    } else return fail(h, PT_ERR_ARG, "unknown option");
     return PT_OK;
 }
 
@@ -1250,6 +1437,8 @@ int pt_mg_get_option(pt_mg_t h, int option)
     if (!h) return -1;
     if (option == PT_OPT_GRAPHS) return h->use_graphs ? 1 : 0;
     if (option == PT_OPT_FUSED) return h->use_fused ? 1 : 0;
+    if (option == PT_OPT_TIMING_EVERY) return h->timing_every;
+    if (option == PT_OPT_SPECULATE) return h->speculate ? 1 : 0;
     if (option == PT_OPT_TAIL) return (h->use_tail && h->tail_lt > 0) ? h->P.nlev - h->tail_lt : 0;
     return -1;
 }

@@ -85,6 +85,7 @@ template <typename R> struct TailArgs {
     Lvl<R> g[kMaxTail];
     int off[kMaxTail][6];
     const double *Ainv;
+    int ainv_off;   // LDS offset of a copy of Ainv, or -1 (read from global memory)
 };
 
 // ---- launch wrappers (implemented in ptmg_kernels.hip) --------------------
@@ -110,6 +111,16 @@ void launch_shift2(long long N, double *x, double *y, const double *mean2, doubl
 template <typename R>
 void launch_rb_pass(int dim, int level0, const Lvl<R> &L, int color, int zero_guess,
                     hipStream_t s);
+// 2-D finest level: one sweep, optionally with the prolonged correction
+// added on load (pro) or the restricted residual written to C.f (res).
+template <typename R>
+void launch_tile2x(const Lvl<R> &L, const Lvl<R> &C, typename VT<R>::v2 *uo, int zero_guess,
+                   int pro, int res, hipStream_t s);
+// 2-D coarse level, nu in {1, 2}: down = nu sweeps from zero + restricted
+// residual into C.f; up = prolongation from C.u + nu sweeps into uo.
+template <typename R>
+void launch_half2(bool up, int nu, const Lvl<R> &L, const Lvl<R> &C, typename VT<R>::v2 *uo,
+                  hipStream_t s);
 template <typename R>
 void launch_rb_fused(int dim, const Lvl<R> &L, typename VT<R>::v2 *uo, int zero_guess, int faces,
                      hipStream_t s);

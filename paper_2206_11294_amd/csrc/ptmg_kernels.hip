@@ -462,12 +462,11 @@ __device__ __forceinline__ void restrict_cell(const Lvl<R> &F, const Lvl<R> &C, 
     C.f[t] = o;
 }
 
-// u += P e at fine cell (i, j, k): along each axis weight 3/4 on the parent
-// and 1/4 on the parent's neighbour on the fine cell's side (the parent at
-// a boundary).
+// P e at fine cell (i, j, k): along each axis weight 3/4 on the parent and
+// 1/4 on the parent's neighbour on the fine cell's side (the parent at a
+// boundary).
 template <typename R, int DIM>
-__device__ __forceinline__ void prolong_cell(const Lvl<R> &F, const Lvl<R> &C, int i, int j, int k,
-                                             long long t)
+__device__ __forceinline__ void prolong_delta(const Lvl<R> &C, int i, int j, int k, R &vp, R &vT)
 {
     using V2 = typename VT<R>::v2;
     int par[3] = {i >> 1, j >> 1, DIM == 3 ? k >> 1 : 0};
@@ -483,7 +482,7 @@ __device__ __forceinline__ void prolong_cell(const Lvl<R> &F, const Lvl<R> &C, i
         int q = par[a] + ((fi[a] & 1) ? 1 : -1);
         nbr[a] = (q < 0 || q >= cn[a]) ? par[a] : q;
     }
-    R vp = R(0), vT = R(0);
+    vp = vT = R(0);
 #pragma unroll
     for (int m = 0; m < (1 << DIM); m++) {
         R w = R(1);
@@ -501,6 +500,16 @@ __device__ __forceinline__ void prolong_cell(const Lvl<R> &F, const Lvl<R> &C, i
         vp += w * e.x;
         vT += w * e.y;
     }
+}
+
+// u += P e at fine cell (i, j, k).
+template <typename R, int DIM>
+__device__ __forceinline__ void prolong_cell(const Lvl<R> &F, const Lvl<R> &C, int i, int j, int k,
+                                             long long t)
+{
+    using V2 = typename VT<R>::v2;
+    R vp, vT;
+    prolong_delta<R, DIM>(C, i, j, k, vp, vT);
     V2 u = F.u[t];
     u.x += vp;
     u.y += vT;
@@ -1349,6 +1358,427 @@ __global__ __launch_bounds__(TX *TY) void k_rb_tile2(Lvl<R> L, typename VT<R>::v
     }
 }
 
+// 2-D finest grid (cell coefficients), one sweep per TX x TY tile with
+// optional fused transfers:
+//  PRO: the prolonged coarse correction is added to the iterate as it is
+//       loaded (the first sweep after the coarse-grid correction);
+//  RES: after the sweep, the residual on the tile is restricted to the
+//       next level's f (the last sweep before restriction); the tile then
+//       carries a ring of 3 cells, so that black is final on a ring of one
+//       around it.
+// The per-cell arithmetic and the restriction's summation order are those
+// of the separate kernels (k_rb_tile2, k_prolong, k_restrict_zm).
+template <typename R, int TX, int TY, bool ZG, bool PRO, bool RES>
+__global__ __launch_bounds__(TX *TY) void k_rb_tile2x(Lvl<R> L, Lvl<R> C,
+                                                      typename VT<R>::v2 *__restrict__ uo,
+                                                      int tiles_x, int ntiles)
+{
+    using V2 = typename VT<R>::v2;
+    using V4 = typename VT<R>::v4;
+    constexpr int NT = TX * TY;
+    constexpr int RG = RES ? 3 : 2;
+    constexpr int PX = TX + 2 * RG, PY = TY + 2 * RG, PS = PX * PY;
+    constexpr int RWR = TX / 2 + RG - 1, RYR = TY + 2 * (RG - 1);   // red: ring RG - 1
+    constexpr int RWB = TX / 2 + RG - 2, RYB = TY + 2 * (RG - 2);   // black: ring RG - 2
+    static_assert(RWR * RYR <= NT && RWB * RYB <= NT, "tile too small for its rings");
+    __shared__ V2 su[PS], sa[PS];
+    __shared__ V2 sr[RES ? NT : 1];
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    if (tile >= ntiles) return;
+    const int x0 = (tile % tiles_x) * TX, y0 = (tile / tiles_x) * TY;
+    const int ox = x0 - RG, oy = y0 - RG;
+    const R ih2 = (R)L.inv_h2;
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int it = 0; it < (PS + NT - 1) / NT; it++) {
+        const int c = t + it * NT;
+        if (c >= PS) break;
+        const int gx = ox + c % PX, gy = oy + c / PX;
+        V2 u, a;
+        u.x = u.y = a.x = a.y = R(0);
+        if (gx >= 0 && gx < L.nx && gy >= 0 && gy < L.ny) {
+            const long long g = gx + (long long)L.nx * gy;
+            a = L.ac[g];
+            if (!ZG) {
+                u = L.u[g];
+                if (PRO) {
+                    R vp, vT;
+                    prolong_delta<R, 2>(C, gx, gy, 0, vp, vT);
+                    u.x += vp;
+                    u.y += vT;
+                }
+            }
+        }
+        su[c] = u;
+        sa[c] = a;
+    }
+    __syncthreads();
+    auto update = [&](int c, long long g) {
+        R gp = R(0), gT = R(0), Sp = R(0), ST = R(0);
+        const V2 am = sa[c];
+        auto accw = [&](V2 w, int q) {
+            const R wp = w.x * ih2, wT = w.y * ih2;
+            const V2 uq = su[q];
+            Sp += wp;
+            ST += wT;
+            gp += wp * uq.x;
+            gT += wT * uq.y;
+        };
+        accw(harm2(am, sa[c - 1]), c - 1);
+        accw(harm2(am, sa[c + 1]), c + 1);
+        accw(harm2(am, sa[c - PX]), c - PX);
+        accw(harm2(am, sa[c + PX]), c + PX);
+        V2 o;
+        block_solve<R>(L.f[g], L.B[g], gp, gT, Sp, ST, o);
+        su[c] = o;
+    };
+    // cells of colour `color` in row ly within ring d of the tile
+    auto pass = [&](int color, int d, int rw, int ry) {
+        if (t < rw * ry) {
+            const int ly = RG - d + t / rw;
+            const int gy = oy + ly;
+            const int xs = x0 - d;
+            const int gx = xs + 2 * (t % rw) + ((xs + gy + color) & 1);
+            const int lx = gx - ox;
+            if (gx >= 0 && gx < L.nx && gy >= 0 && gy < L.ny)
+                update(ly * PX + lx, gx + (long long)L.nx * gy);
+        }
+        __syncthreads();
+    };
+    pass(0, RG - 1, RWR, RYR);
+    pass(1, RG - 2, RWB, RYB);
+    const int lx = RG + t % TX, ly = RG + t / TX;
+    const int gx = x0 + t % TX, gy = y0 + t / TX;
+    const bool mine = gx < L.nx && gy < L.ny;
+    const int c = ly * PX + lx;
+    if (mine) uo[gx + (long long)L.nx * gy] = su[c];
+    if (!RES) return;
+    // residual f - A u on the tile, then the mean of each 2 x 2 block
+    V2 r;
+    r.x = r.y = R(0);
+    if (mine) {
+        const long long g = gx + (long long)L.nx * gy;
+        const V2 um = su[c], am = sa[c];
+        R nbp = R(0), nbT = R(0), Sp = R(0), ST = R(0);
+        auto nb = [&](int q) {
+            V2 w = harm2(am, sa[q]);
+            const R wp = w.x * ih2, wT = w.y * ih2;
+            const V2 uq = su[q];
+            Sp += wp;
+            ST += wT;
+            nbp += wp * uq.x;
+            nbT += wT * uq.y;
+        };
+        nb(c - 1);
+        nb(c + 1);
+        nb(c - PX);
+        nb(c + PX);
+        const V2 f = L.f[g];
+        const V4 B = L.B[g];
+        const R Ap = Sp * um.x - nbp + B.x * um.x + B.y * um.y;
+        const R AT = ST * um.y - nbT + B.z * um.x + B.w * um.y;
+        r.x = f.x - Ap;
+        r.y = f.y - AT;
+    }
+    sr[t] = r;
+    __syncthreads();
+    if (t < (TX / 2) * (TY / 2)) {
+        const int ci = t % (TX / 2), cj = t / (TX / 2);
+        const int I = x0 / 2 + ci, J = y0 / 2 + cj;
+        if (I < C.nx && J < C.ny) {
+            const int b0 = 2 * cj * TX + 2 * ci;
+            const V2 r00 = sr[b0], r10 = sr[b0 + 1], r01 = sr[b0 + TX], r11 = sr[b0 + TX + 1];
+            // row pairs first, as the plane-marching restriction sums them
+            R accp = R(0), accT = R(0);
+            accp += r00.x + r10.x;
+            accT += r00.y + r10.y;
+            accp += r01.x + r11.x;
+            accT += r01.y + r11.y;
+            const R sc = R(0.25);
+            V2 o;
+            o.x = accp * sc;
+            o.y = accT * sc;
+            C.f[I + (long long)C.nx * J] = o;
+        }
+    }
+}
+
+// The finest 2-D level: one sweep with its fused transfers (see
+// k_rb_tile2x); C is level 1 (its u for pro, its f written for res).
+template <typename R>
+void launch_tile2x(const Lvl<R> &L, const Lvl<R> &C, typename VT<R>::v2 *uo, int zero_guess,
+                   int pro, int res, hipStream_t s)
+{
+    constexpr int TX = 64, TY = 8;
+    const int tx = (L.nx + TX - 1) / TX, ty = (L.ny + TY - 1) / TY;
+    const int nt = tx * ty;
+#define PTMG_TILE2X(ZGC, PC, RC)                                                                \
+    hipLaunchKernelGGL((k_rb_tile2x<R, TX, TY, ZGC, PC, RC>), dim3(nt), dim3(TX * TY), 0, s, L, C, \
+                       uo, tx, nt)
+    if (res) {
+        if (zero_guess) PTMG_TILE2X(true, false, true);
+        else PTMG_TILE2X(false, false, true);
+    } else if (pro) {
+        PTMG_TILE2X(false, true, false);
+    } else {
+        if (zero_guess) PTMG_TILE2X(true, false, false);
+        else PTMG_TILE2X(false, false, false);
+    }
+#undef PTMG_TILE2X
+}
+template void launch_tile2x<float>(const Lvl<float> &, const Lvl<float> &, float2 *, int, int, int,
+                                   hipStream_t);
+template void launch_tile2x<double>(const Lvl<double> &, const Lvl<double> &, double2 *, int, int,
+                                    int, hipStream_t);
+
+// ------------------------------------------ 2-D coarse-level half cycles
+// On the coarse 2-D levels a V-cycle visits each level twice: on the way
+// down (nu1 sweeps from a zero guess, then the residual restricted to the
+// next level) and on the way up (the prolonged correction added, then nu2
+// sweeps).  These levels are small, so as separate kernels each step is
+// bound by launch and memory latency; here each half is one kernel.  A
+// block owns a TX x TY tile and recomputes a ring of 2 nu cells around it
+// in LDS (each sweep needs its input one red and one black cell further
+// out), so no block reads another block's intermediate values.  The
+// arithmetic is that of the separate kernels cell for cell: the same face
+// order (x-, x+, y-, y+; faces outside the grid are zero, which adds
+// exact zeros), the same block solve, residual, restriction sum and
+// prolongation weights.
+//
+// Patch coordinates: (lx, ly) in [0, PX) x [0, PY) at global
+// (x0 - RG + lx, y0 - RG + ly); cells at ring distance d from the tile are
+// those with lx in [RG - d, RG + TX + d), ly in [RG - d, RG + TY + d).  The
+// extra column pair and row on the upper side hold the upper faces of the
+// outermost cells.  Thread t owns the cell pairs (2 px, 2 px + 1) of row
+// ly for pair indices t, t + NT, ...; their f and B are read once, before
+// the first sweep.
+template <typename R, int TX, int TY, int NU> struct HalfTile {
+    static constexpr int NT = TX * TY;
+    static constexpr int RG = 2 * NU;
+    static constexpr int PX = TX + 2 * RG + 2, PY = TY + 2 * RG + 1, PS = PX * PY;
+    static constexpr int HP = PX / 2, NPAIR = HP * PY, QP = (NPAIR + NT - 1) / NT;
+};
+
+template <typename R, int TX, int TY, int NU, bool UP>
+__device__ __forceinline__ void half_cycle2(const Lvl<R> &L, const Lvl<R> &C,
+                                            typename VT<R>::v2 *__restrict__ uo, int tiles_x,
+                                            int ntiles)
+{
+    using V2 = typename VT<R>::v2;
+    using V4 = typename VT<R>::v4;
+    using H = HalfTile<R, TX, TY, NU>;
+    constexpr int NT = H::NT, RG = H::RG, PX = H::PX, PY = H::PY, PS = H::PS, HP = H::HP,
+                  NPAIR = H::NPAIR, QP = H::QP;
+    __shared__ V2 su[PS], sfx[PS], sfy[PS];
+    __shared__ V2 sr[UP ? 1 : NT];
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    if (tile >= ntiles) return;
+    const int x0 = (tile % tiles_x) * TX, y0 = (tile / tiles_x) * TY;
+    const int ox = x0 - RG, oy = y0 - RG;
+    const R ih2 = (R)L.inv_h2;
+    const int t = threadIdx.x;
+    auto inside = [&](int gx, int gy) { return gx >= 0 && gx < L.nx && gy >= 0 && gy < L.ny; };
+    auto in_ring = [&](int lx, int ly, int d) {
+        return lx >= RG - d && lx < RG + TX + d && ly >= RG - d && ly < RG + TY + d;
+    };
+    // faces and the iterate (zero going down; u + P e going up); a constant
+    // trip count lets the loads of all iterations issue before any wait
+#pragma unroll
+    for (int it = 0; it < (PS + NT - 1) / NT; it++) {
+        const int c = t + it * NT;
+        if (c >= PS) break;
+        const int lx = c % PX, ly = c / PX;
+        const int gx = ox + lx, gy = oy + ly;
+        V2 fx, fy, u;
+        fx.x = fx.y = fy.x = fy.y = u.x = u.y = R(0);
+        if (inside(gx, gy)) {
+            const long long g = gx + (long long)L.nx * gy;
+            fx = L.fx[g];
+            fy = L.fy[g];
+            if (UP && in_ring(lx, ly, RG)) {
+                R vp, vT;
+                prolong_delta<R, 2>(C, gx, gy, 0, vp, vT);
+                u = L.u[g];
+                u.x += vp;
+                u.y += vT;
+            }
+        }
+        sfx[c] = fx;
+        sfy[c] = fy;
+        su[c] = u;
+    }
+    // f and B of the owned cells that some sweep updates
+    constexpr int DMAX = UP ? RG - 1 : RG;
+    V2 f[QP][2];
+    V4 B[QP][2];
+#pragma unroll
+    for (int q = 0; q < QP; q++) {
+        const int p = t + q * NT;
+#pragma unroll
+        for (int k = 0; k < 2; k++) {
+            f[q][k].x = f[q][k].y = R(0);
+            B[q][k].x = B[q][k].y = B[q][k].z = B[q][k].w = R(0);
+            if (p < NPAIR) {
+                const int ly = p / HP, lx = 2 * (p % HP) + k;
+                const int gx = ox + lx, gy = oy + ly;
+                if (in_ring(lx, ly, DMAX) && inside(gx, gy)) {
+                    const long long g = gx + (long long)L.nx * gy;
+                    f[q][k] = L.f[g];
+                    B[q][k] = L.B[g];
+                }
+            }
+        }
+    }
+    __syncthreads();
+    auto update = [&](int c, const V2 &fc, const V4 &Bc, bool zg) {
+        R gp = R(0), gT = R(0), Sp = R(0), ST = R(0);
+        auto accw = [&](V2 w, int q) {
+            const R wp = w.x * ih2, wT = w.y * ih2;
+            Sp += wp;
+            ST += wT;
+            if (!zg) {
+                const V2 uq = su[q];
+                gp += wp * uq.x;
+                gT += wT * uq.y;
+            }
+        };
+        accw(sfx[c], c - 1);
+        accw(sfx[c + 1], c + 1);
+        accw(sfy[c], c - PX);
+        accw(sfy[c + PX], c + PX);
+        V2 o;
+        block_solve<R>(fc, Bc, gp, gT, Sp, ST, o);
+        su[c] = o;
+    };
+    // one colour over the cells within ring distance d
+    auto phase = [&](int color, int d, bool zg) {
+#pragma unroll
+        for (int q = 0; q < QP; q++) {
+            const int p = t + q * NT;
+            if (p >= NPAIR) continue;
+            const int ly = p / HP;
+            const int k = (color + ly) & 1;
+            const int lx = 2 * (p % HP) + k;
+            if (!in_ring(lx, ly, d) || !inside(ox + lx, oy + ly)) continue;
+            // (selects, not a dynamic index: the arrays stay in registers)
+            update(ly * PX + lx, k ? f[q][1] : f[q][0], k ? B[q][1] : B[q][0], zg);
+        }
+        __syncthreads();
+    };
+    if (UP) {
+        for (int s = 1; s <= NU; s++) {
+            phase(0, 2 * (NU - s) + 1, false);
+            phase(1, 2 * (NU - s), false);
+        }
+        const int lx = RG + t % TX, ly = RG + t / TX;
+        const int gx = ox + lx, gy = oy + ly;
+        if (gx < L.nx && gy < L.ny) uo[gx + (long long)L.nx * gy] = su[ly * PX + lx];
+        return;
+    }
+    for (int s = 1; s <= NU; s++) {
+        phase(0, 2 * (NU - s) + 2, s == 1);
+        phase(1, 2 * (NU - s) + 1, false);
+    }
+    // residual f - A u on the tile (the owned cells in it), u written out
+#pragma unroll
+    for (int q = 0; q < QP; q++) {
+        const int p = t + q * NT;
+        if (p >= NPAIR) continue;
+        const int ly = p / HP;
+#pragma unroll
+        for (int k = 0; k < 2; k++) {
+            const int lx = 2 * (p % HP) + k;
+            const int gx = ox + lx, gy = oy + ly;
+            if (!in_ring(lx, ly, 0) || !inside(gx, gy)) continue;
+            const int c = ly * PX + lx;
+            R nbp = R(0), nbT = R(0), Sp = R(0), ST = R(0);
+            auto acc = [&](V2 w, int qq) {
+                const R wp = w.x * ih2, wT = w.y * ih2;
+                Sp += wp;
+                ST += wT;
+                const V2 uq = su[qq];
+                nbp += wp * uq.x;
+                nbT += wT * uq.y;
+            };
+            acc(sfx[c], c - 1);
+            acc(sfx[c + 1], c + 1);
+            acc(sfy[c], c - PX);
+            acc(sfy[c + PX], c + PX);
+            const V2 u = su[c];
+            const V4 b = B[q][k];
+            const R Ap = Sp * u.x - nbp + b.x * u.x + b.y * u.y;
+            const R AT = ST * u.y - nbT + b.z * u.x + b.w * u.y;
+            V2 r;
+            r.x = f[q][k].x - Ap;
+            r.y = f[q][k].y - AT;
+            sr[(ly - RG) * TX + (lx - RG)] = r;
+            L.u[gx + (long long)L.nx * gy] = u;
+        }
+    }
+    __syncthreads();
+    // restriction: coarse f = mean of the four children, in child order
+    if (t < (TX / 2) * (TY / 2)) {
+        const int ci = t % (TX / 2), cj = t / (TX / 2);
+        const int I = x0 / 2 + ci, J = y0 / 2 + cj;
+        if (I < C.nx && J < C.ny) {
+            const int b0 = 2 * cj * TX + 2 * ci;
+            const V2 r00 = sr[b0], r10 = sr[b0 + 1], r01 = sr[b0 + TX], r11 = sr[b0 + TX + 1];
+            R sp = R(0), sT = R(0);
+            sp += r00.x;
+            sT += r00.y;
+            sp += r10.x;
+            sT += r10.y;
+            sp += r01.x;
+            sT += r01.y;
+            sp += r11.x;
+            sT += r11.y;
+            const R sc = R(1) / R(4);
+            V2 o;
+            o.x = sp * sc;
+            o.y = sT * sc;
+            C.f[I + (long long)C.nx * J] = o;
+        }
+    }
+}
+
+template <typename R, int TX, int TY, int NU>
+__global__ __launch_bounds__(TX *TY) void k_down2(Lvl<R> L, Lvl<R> C, int tiles_x, int ntiles)
+{
+    half_cycle2<R, TX, TY, NU, false>(L, C, nullptr, tiles_x, ntiles);
+}
+
+template <typename R, int TX, int TY, int NU>
+__global__ __launch_bounds__(TX *TY) void k_up2(Lvl<R> L, Lvl<R> C,
+                                                typename VT<R>::v2 *__restrict__ uo, int tiles_x,
+                                                int ntiles)
+{
+    half_cycle2<R, TX, TY, NU, true>(L, C, uo, tiles_x, ntiles);
+}
+
+// Down: u_L = nu sweeps from zero on f_L (written to L.u), C.f = restricted
+// residual.  Up: L.u + P C.u, then nu sweeps, written to uo (another
+// buffer).  nu is 1 or 2; L is a coarse 2-D level (stored faces) whose
+// dimensions are even.
+template <typename R>
+void launch_half2(bool up, int nu, const Lvl<R> &L, const Lvl<R> &C, typename VT<R>::v2 *uo,
+                  hipStream_t s)
+{
+    constexpr int TX = 64, TY = 8;
+    const int tx = (L.nx + TX - 1) / TX, ty = (L.ny + TY - 1) / TY;
+    const int nt = tx * ty;
+    if (up) {
+        if (nu == 1) hipLaunchKernelGGL((k_up2<R, TX, TY, 1>), dim3(nt), dim3(TX * TY), 0, s, L, C, uo, tx, nt);
+        else hipLaunchKernelGGL((k_up2<R, TX, TY, 2>), dim3(nt), dim3(TX * TY), 0, s, L, C, uo, tx, nt);
+    } else {
+        if (nu == 1) hipLaunchKernelGGL((k_down2<R, TX, TY, 1>), dim3(nt), dim3(TX * TY), 0, s, L, C, tx, nt);
+        else hipLaunchKernelGGL((k_down2<R, TX, TY, 2>), dim3(nt), dim3(TX * TY), 0, s, L, C, tx, nt);
+    }
+}
+template void launch_half2<float>(bool, int, const Lvl<float> &, const Lvl<float> &, float2 *,
+                                  hipStream_t);
+template void launch_half2<double>(bool, int, const Lvl<double> &, const Lvl<double> &, double2 *,
+                                   hipStream_t);
+
 // Reads the old iterate from L.u and writes the swept one to uo (a
 // different buffer: blocks read halo cells that other blocks update).
 // faces = 0: the finest grid (cell coefficients); 1: a coarse level.
@@ -1853,100 +2283,287 @@ namespace ptmg {
 // The V-cycle of the coarsest few levels (all with stored faces) in one
 // block of 1024 threads, every array in LDS: these levels have tens to a
 // few thousand cells, so as separate kernels they are bound by launch
-// latency.  Same steps and arithmetic as the grid kernels: red-black
-// sweeps (zero guess on the first red pass), residual + restriction, the
-// FP64 inverse on the coarsest grid (matrix read from global memory),
-// prolongation + correction.  Input: f of the first tail level; output:
-// its u.
+// latency.  Same steps and arithmetic as the grid kernels (the same cell
+// functions): red-black sweeps (zero guess on the first red pass),
+// residual + restriction, the FP64 inverse on the coarsest grid (matrix
+// read from global memory), prolongation + correction.  Input: f of the
+// first tail level; output: its u.  The level loops are unrolled over
+// kMaxTail (guarded by nl) so that every per-level constant is a static
+// kernel argument and every level view is built from the LDS base.
+template <int DIM>
+__device__ __forceinline__ void decode32(int e, int nx, int ny, int &i, int &j, int &k)
+{
+    const int r = e / nx;
+    i = e - r * nx;
+    if (DIM == 2) {
+        j = r;
+        k = 0;
+    } else {
+        k = r / ny;
+        j = r - k * ny;
+    }
+}
+
 template <typename R, int DIM>
-__global__ __launch_bounds__(1024) void k_tail(TailArgs<R> A)
+__global__ __launch_bounds__(DIM == 3 ? 512 : 1024) void k_tail(TailArgs<R> A)
 {
     using V2 = typename VT<R>::v2;
     using V4 = typename VT<R>::v4;
     extern __shared__ __align__(16) unsigned char lds[];
-    __shared__ Lvl<R> L[kMaxTail];
-    const int nt = blockDim.x, t = threadIdx.x;
+    // 3-D tails start at 8^3 cells or fewer (LDS), and half the threads
+    // leave each twice the registers
+    constexpr int NT = DIM == 3 ? 512 : 1024;
+    const int t = threadIdx.x;
     const int nl = A.nl;
-    if (t < nl) {
-        Lvl<R> v = A.g[t];
-        v.u = (V2 *)(lds + A.off[t][0]);
-        v.f = (V2 *)(lds + A.off[t][1]);
-        v.fx = (const V2 *)(lds + A.off[t][2]);
-        v.fy = (const V2 *)(lds + A.off[t][3]);
-        v.fz = DIM == 3 ? (const V2 *)(lds + A.off[t][4]) : nullptr;
-        v.B = (const V4 *)(lds + A.off[t][5]);
-        L[t] = v;
+    auto view = [&](int q) {
+        Lvl<R> v = A.g[q];
+        v.u = (V2 *)(lds + A.off[q][0]);
+        v.f = (V2 *)(lds + A.off[q][1]);
+        v.fx = (const V2 *)(lds + A.off[q][2]);
+        v.fy = (const V2 *)(lds + A.off[q][3]);
+        v.fz = DIM == 3 ? (const V2 *)(lds + A.off[q][4]) : nullptr;
+        v.B = (const V4 *)(lds + A.off[q][5]);
+        return v;
+    };
+    // operators of every tail level, the right-hand side of the first and
+    // the coarsest inverse.  Element t of five levels at a time is loaded
+    // unconditionally (level and index clamped into range) before any is
+    // stored, so a round costs one memory latency rather than one per
+    // level; larger arrays loop on.
+    {
+        struct Cell {
+            R fx0, fx1, fy0, fy1, fz0, fz1, f0, f1, b0, b1, b2, b3;
+        };
+        // a level past the last reads element 0 of level 0 (static indices
+        // only: a dynamic one would copy A to scratch)
+        auto ld = [&](int q) {
+            const bool ok = q < nl;
+            const int qq = q < kMaxTail ? q : 0;
+            const V2 *gfx = ok ? A.g[qq].fx : A.g[0].fx;
+            const V2 *gfy = ok ? A.g[qq].fy : A.g[0].fy;
+            const V2 *gfz = ok ? A.g[qq].fz : A.g[0].fz;
+            const V4 *gB = ok ? A.g[qq].B : A.g[0].B;
+            const int e = ok ? min(t, (int)A.g[qq].N - 1) : 0;
+            Cell c;
+            const V2 a = gfx[e], b = gfy[e];
+            const V4 B = gB[e];
+            c.fx0 = a.x; c.fx1 = a.y;
+            c.fy0 = b.x; c.fy1 = b.y;
+            c.fz0 = c.fz1 = R(0);
+            if (DIM == 3) {
+                const V2 z = gfz[e];
+                c.fz0 = z.x; c.fz1 = z.y;
+            }
+            c.b0 = B.x; c.b1 = B.y; c.b2 = B.z; c.b3 = B.w;
+            c.f0 = c.f1 = R(0);
+            if (q == 0) {
+                const V2 f = A.g[0].f[e];
+                c.f0 = f.x; c.f1 = f.y;
+            }
+            return c;
+        };
+        auto st = [&](int q, const Cell &c) {
+            if (q >= nl || q >= kMaxTail || t >= (int)A.g[q < kMaxTail ? q : 0].N) return;
+            const Lvl<R> V = view(q);
+            V2 v;
+            v.x = c.fx0; v.y = c.fx1;
+            ((V2 *)V.fx)[t] = v;
+            v.x = c.fy0; v.y = c.fy1;
+            ((V2 *)V.fy)[t] = v;
+            if (DIM == 3) {
+                v.x = c.fz0; v.y = c.fz1;
+                ((V2 *)V.fz)[t] = v;
+            }
+            V4 B;
+            B.x = c.b0; B.y = c.b1; B.z = c.b2; B.w = c.b3;
+            ((V4 *)V.B)[t] = B;
+            if (q == 0) {
+                v.x = c.f0; v.y = c.f1;
+                V.f[t] = v;
+            }
+        };
+        const double ainv = A.ainv_off >= 0 ? A.Ainv[min(t, A.m * A.m - 1)] : 0.0;
+#pragma unroll
+        for (int q0 = 0; q0 < kMaxTail; q0 += 5) {
+            if (q0 >= nl) break;
+            const Cell c0 = ld(q0), c1 = ld(q0 + 1), c2 = ld(q0 + 2), c3 = ld(q0 + 3),
+                       c4 = ld(q0 + 4);
+            st(q0, c0);
+            st(q0 + 1, c1);
+            st(q0 + 2, c2);
+            st(q0 + 3, c3);
+            st(q0 + 4, c4);
+        }
+        if (A.ainv_off >= 0 && t < A.m * A.m) ((double *)(lds + A.ainv_off))[t] = ainv;
     }
-    __syncthreads();
-    // operators of every tail level and the right-hand side of the first
-    for (int q = 0; q < nl; q++) {
+#pragma unroll
+    for (int q = 0; q < kMaxTail; q++) {
+        if (q >= nl) break;
         const Lvl<R> &G = A.g[q];
-        const long long N = G.N;
-        for (long long e = t; e < N; e += nt) {
-            ((V2 *)L[q].fx)[e] = G.fx[e];
-            ((V2 *)L[q].fy)[e] = G.fy[e];
-            if (DIM == 3) ((V2 *)L[q].fz)[e] = G.fz[e];
-            ((V4 *)L[q].B)[e] = G.B[e];
-            if (q == 0) L[q].f[e] = G.f[e];
+        const Lvl<R> V = view(q);
+        for (int e = t + NT; e < (int)G.N; e += NT) {
+            ((V2 *)V.fx)[e] = G.fx[e];
+            ((V2 *)V.fy)[e] = G.fy[e];
+            if (DIM == 3) ((V2 *)V.fz)[e] = G.fz[e];
+            ((V4 *)V.B)[e] = G.B[e];
+            if (q == 0) V.f[e] = G.f[e];
         }
     }
+    if (A.ainv_off >= 0)
+        for (int e = t + NT; e < A.m * A.m; e += NT)
+            ((double *)(lds + A.ainv_off))[e] = A.Ainv[e];
     __syncthreads();
-    auto sweep = [&](int q, bool zero_guess) {
-        const Lvl<R> &V = L[q];
-        for (int color = 0; color < 2; color++) {
-            for (long long e = t; e < V.N; e += nt) {
-                int i, j, k;
-                decode(e, V.nx, V.ny, i, j, k);
-                if (((i + j + k) & 1) != color) continue;
-                if (zero_guess && color == 0) rb_cell<R, DIM, false, false>(V, i, j, k, e);
-                else rb_cell<R, DIM, false, true>(V, i, j, k, e);
-            }
+    // Levels of at most 64 cells run in wavefront 0 alone: its lanes
+    // exchange values through LDS in program order, so a wavefront-scope
+    // fence replaces the block barrier between phases.
+    int w0 = nl;   // first level of the wavefront part
+#pragma unroll
+    for (int q = kMaxTail - 1; q >= 0; q--)
+        if (q < nl && A.g[q].N <= 64) w0 = q;
+    auto sync = [&](bool wave) {
+        if (wave) {
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+        } else {
             __syncthreads();
         }
     };
-    for (int q = 0; q + 1 < nl; q++) {
+    // one colour of a sweep: cells of colour c enumerated directly when nx
+    // is even (half the index space), else by test
+    auto colour = [&](const Lvl<R> &V, int c, bool zero_guess, bool wave) {
+        const int N = (int)V.N, stride = wave ? 64 : NT;
+        if ((V.nx & 1) == 0) {
+            const int hx = V.nx >> 1, NH = N >> 1;
+            for (int e2 = t; e2 < NH; e2 += stride) {
+                const int row = e2 / hx, ii = e2 - row * hx;
+                const int k = DIM == 2 ? 0 : row / V.ny;
+                const int j = DIM == 2 ? row : row - k * V.ny;
+                const int i = 2 * ii + ((j + k + c) & 1);
+                const int me = i + V.nx * row;
+                if (zero_guess) rb_cell<R, DIM, false, false>(V, i, j, k, me);
+                else rb_cell<R, DIM, false, true>(V, i, j, k, me);
+            }
+        } else {
+            for (int e = t; e < N; e += stride) {
+                int i, j, k;
+                decode32<DIM>(e, V.nx, V.ny, i, j, k);
+                if (((i + j + k) & 1) != c) continue;
+                if (zero_guess) rb_cell<R, DIM, false, false>(V, i, j, k, e);
+                else rb_cell<R, DIM, false, true>(V, i, j, k, e);
+            }
+        }
+        sync(wave);
+    };
+    // down on level q: smoothing from a zero guess, residual restricted
+    auto down = [&](int q, bool wave) {
+        const Lvl<R> V = view(q), C = view(q + 1);
+        const int stride = wave ? 64 : NT;
         if (A.nu1 == 0) {
-            for (long long e = t; e < L[q].N; e += nt) {
+            for (int e = t; e < (int)V.N; e += stride) {
                 V2 z;
                 z.x = z.y = R(0);
-                L[q].u[e] = z;
+                V.u[e] = z;
             }
-            __syncthreads();
+            sync(wave);
         }
-        for (int s = 0; s < A.nu1; s++) sweep(q, s == 0);
-        const Lvl<R> &C = L[q + 1];
-        for (long long e = t; e < C.N; e += nt) {
+        for (int s = 0; s < A.nu1; s++) {
+            colour(V, 0, s == 0, wave);
+            colour(V, 1, false, wave);
+        }
+        for (int e = t; e < (int)C.N; e += stride) {
             int I, J, K;
-            decode(e, C.nx, C.ny, I, J, K);
-            restrict_cell<R, DIM, false>(L[q], C, I, J, K, e);
+            decode32<DIM>(e, C.nx, C.ny, I, J, K);
+            restrict_cell<R, DIM, false>(V, C, I, J, K, e);
         }
-        __syncthreads();
-    }
-    {   // coarsest grid: u = Ainv f in FP64, one wave per row
-        const Lvl<R> &C = L[nl - 1];
+        sync(wave);
+    };
+    // up on level q: prolongation + correction, then smoothing
+    auto up = [&](int q, bool wave) {
+        const Lvl<R> V = view(q), C = view(q + 1);
+        const int stride = wave ? 64 : NT;
+        for (int e = t; e < (int)V.N; e += stride) {
+            int i, j, k;
+            decode32<DIM>(e, V.nx, V.ny, i, j, k);
+            prolong_cell<R, DIM>(V, C, i, j, k, e);
+        }
+        sync(wave);
+        for (int s = 0; s < A.nu2; s++) {
+            colour(V, 0, false, wave);
+            colour(V, 1, false, wave);
+        }
+    };
+    // coarsest grid: u = Ainv f in FP64.  Row sums in the order of the grid
+    // kernel k_coarse_apply (a 64-lane butterfly over lane-strided partial
+    // sums); for m <= 64 the products sit in groups of G = 2^ceil(log2 m)
+    // lanes, 64 / G rows at a time, and the butterfly's first steps, which
+    // only add zeros, are skipped.
+    auto coarsest = [&](int q, bool wave) {
+        const Lvl<R> C = view(q);
         const R *f = (const R *)C.f;
         R *u = (R *)C.u;
-        const int lane = t & 63, wave = t >> 6, nw = nt >> 6;
-        for (int row = wave; row < A.m; row += nw) {
-            const double *a = A.Ainv + (long long)row * A.m;
-            double s = 0.0;
-            for (int c = lane; c < A.m; c += 64) s += a[c] * (double)f[c];
-            for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
-            if (lane == 0) u[row] = (R)s;
+        const int lane = t & 63, wv = t >> 6;
+        const int nw = wave ? 1 : NT / 64;
+        const int m = A.m;
+        const double *Ainv_l = (const double *)(lds + (A.ainv_off >= 0 ? A.ainv_off : 0));
+        if (m <= 64) {
+            int G = 1;
+            while (G < m) G <<= 1;
+            const int rpp = 64 / G;
+            const int c = lane & (G - 1);
+            for (int row0 = wv * rpp; row0 < m; row0 += nw * rpp) {
+                const int row = row0 + lane / G;
+                double x = 0.0;
+                if (row < m && c < m) {
+                    const double a = A.ainv_off >= 0 ? Ainv_l[row * m + c]
+                                                     : A.Ainv[(long long)row * m + c];
+                    x += a * (double)f[c];
+                }
+                for (int off = G >> 1; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+                if (c == 0 && row < m) u[row] = (R)x;
+            }
+        } else {
+            for (int row = wv; row < m; row += nw) {
+                const double *a = A.Ainv + (long long)row * m;
+                double sacc = 0.0;
+                for (int c = lane; c < m; c += 64) sacc += a[c] * (double)f[c];
+                for (int off = 32; off >= 1; off >>= 1) sacc += __shfl_xor(sacc, off, 64);
+                if (lane == 0) u[row] = (R)sacc;
+            }
+        }
+        sync(wave);
+    };
+    // block part, down
+#pragma unroll
+    for (int q = 0; q + 1 < kMaxTail; q++)
+        if (q + 1 < nl && q < w0) down(q, false);
+    if (w0 >= nl - 1) {   // no wavefront part: the coarsest grid block-wide
+#pragma unroll
+        for (int q = 1; q < kMaxTail; q++)
+            if (q == nl - 1) coarsest(q, false);
+    }
+    // wavefront part: down, coarsest, up
+    if (w0 < nl - 1) {
+        if (t < 64) {
+#pragma unroll
+            for (int q = 0; q + 1 < kMaxTail; q++)
+                if (q + 1 < nl && q >= w0) down(q, true);
+#pragma unroll
+            for (int q = 1; q < kMaxTail; q++)
+                if (q == nl - 1) coarsest(q, true);
+#pragma unroll
+            for (int q = kMaxTail - 2; q >= 0; q--)
+                if (q + 1 < nl && q >= w0) up(q, true);
         }
         __syncthreads();
     }
-    for (int q = nl - 2; q >= 0; q--) {
-        const Lvl<R> &V = L[q];
-        for (long long e = t; e < V.N; e += nt) {
-            int i, j, k;
-            decode(e, V.nx, V.ny, i, j, k);
-            prolong_cell<R, DIM>(V, L[q + 1], i, j, k, e);
-        }
-        __syncthreads();
-        for (int s = 0; s < A.nu2; s++) sweep(q, false);
+    // block part, up
+#pragma unroll
+    for (int q = kMaxTail - 2; q >= 0; q--)
+        if (q + 1 < nl && q < w0) up(q, false);
+    {
+        const Lvl<R> V = view(0);
+        for (int e = t; e < (int)V.N; e += NT) A.g[0].u[e] = V.u[e];
     }
-    for (long long e = t; e < L[0].N; e += nt) A.g[0].u[e] = L[0].u[e];
 }
 
 template <typename R>
@@ -1964,7 +2581,7 @@ template <typename R>
 bool launch_tail(int dim, const TailArgs<R> &a, size_t lds_bytes, hipStream_t s)
 {
     if (dim == 3)
-        hipLaunchKernelGGL((k_tail<R, 3>), dim3(1), dim3(1024), lds_bytes, s, a);
+        hipLaunchKernelGGL((k_tail<R, 3>), dim3(1), dim3(512), lds_bytes, s, a);
     else
         hipLaunchKernelGGL((k_tail<R, 2>), dim3(1), dim3(1024), lds_bytes, s, a);
     return true;

@@ -21,7 +21,7 @@ STATUS_NAMES = {0: "PT_OK", 1: "PT_ERR_ARG", 2: "PT_ERR_OOM", 3: "PT_ERR_SINGULA
 PT_COEF_EXPLICIT, PT_COEF_PHASES = 0, 1
 PT_PREC_FP64, PT_PREC_MIXED = 0, 1
 PT_MAX_HIST = 64
-PT_OPT_GRAPHS, PT_OPT_TAIL, PT_OPT_FUSED = 1, 2, 3
+PT_OPT_GRAPHS, PT_OPT_TAIL, PT_OPT_FUSED, PT_OPT_TIMING_EVERY, PT_OPT_SPECULATE = 1, 2, 3, 4, 5
 KERNEL_CLASSES = ["outer_residual", "smooth_fine", "smooth_coarse", "restrict", "prolong",
                   "coarse_solve", "other"]
 
@@ -101,6 +101,8 @@ def lib() -> ctypes.CDLL:
             "pt_mg_set_timing": (c_int, [c_void, c_int]),
             "pt_mg_kernel_stats": (c_int, [c_void, c_int, P(ctypes.c_long), P(c_double),
                                            P(c_double)]),
+            "pt_mg_timed_stats": (c_int, [c_void, c_int, P(ctypes.c_long), P(c_double),
+                                          P(c_double)]),
             "pt_mg_reset_stats": (c_int, [c_void]),
             "pt_mg_last_cell_updates": (ctypes.c_longlong, [c_void]),
             "pt_copy_kernel": (c_int, [c_void, c_void, ctypes.c_size_t, c_void]),
@@ -122,7 +124,7 @@ def exported_symbols() -> Sequence[str]:
             "pt_mg_solve", "pt_mg_residual", "pt_mg_destroy", "pt_mg_last_error",
             "pt_mg_num_levels", "pt_mg_level_dims", "pt_mg_get_operator", "pt_mg_smooth",
             "pt_mg_restrict_residual", "pt_mg_prolong_add", "pt_mg_coarse_solve",
-            "pt_mg_vcycle", "pt_mg_set_timing", "pt_mg_kernel_stats", "pt_mg_reset_stats",
+            "pt_mg_vcycle", "pt_mg_set_timing", "pt_mg_kernel_stats", "pt_mg_timed_stats", "pt_mg_reset_stats",
             "pt_mg_last_cell_updates", "pt_copy_kernel", "pt_mg_set_option",
             "pt_mg_get_option"]
 
@@ -291,6 +293,18 @@ class PtMg:
             by = ctypes.c_double()
             self._check(lib().pt_mg_kernel_stats(self._h, c, ctypes.byref(n), ctypes.byref(ms),
                                                  ctypes.byref(by)))
+            out[name] = {"launches": n.value, "ms": ms.value, "bytes": by.value}
+        return out
+
+    def timed_stats(self) -> Dict[str, Dict[str, float]]:
+        """Per class: launches inside timed runs, their ms and bytes."""
+        out = {}
+        for c, name in enumerate(KERNEL_CLASSES):
+            n = ctypes.c_long()
+            ms = ctypes.c_double()
+            by = ctypes.c_double()
+            self._check(lib().pt_mg_timed_stats(self._h, c, ctypes.byref(n), ctypes.byref(ms),
+                                                ctypes.byref(by)))
             out[name] = {"launches": n.value, "ms": ms.value, "bytes": by.value}
         return out
 

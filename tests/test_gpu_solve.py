@@ -181,6 +181,8 @@ def test_timing_and_counters():
     prob = step_problems()["bubble3d_40x24x56"]
     h, b_p, b_T, _ = D.setup(prob, 1)
     p, T = torch.empty_like(b_p), torch.empty_like(b_T)
+    from paper_2206_11294_amd import ptmg
+    h.set_option(ptmg.PT_OPT_SPECULATE, 0)     # exact launch counts
     h.set_timing(True)
     h.reset_stats()
     info = h.solve(b_p, b_T, p, T, rtol=1e-9)
@@ -189,6 +191,22 @@ def test_timing_and_counters():
     assert st["outer_residual"]["launches"] == info["cycles"] + 1
     assert st["smooth_fine"]["ms"] > 0 and st["smooth_fine"]["bytes"] > 0
     assert h.last_cell_updates() > 0
+    ts = h.timed_stats()
+    for c in st:      # every run timed: the timed launches are all launches
+        assert ts[c]["launches"] == st[c]["launches"] and ts[c]["bytes"] == st[c]["bytes"], c
+    # one run in three of the finest-grid smoother: two runs per cycle
+    h.set_timing(True, classes=["smooth_fine"])
+    h.set_option(ptmg.PT_OPT_TIMING_EVERY, 3)
+    assert h.get_option(ptmg.PT_OPT_TIMING_EVERY) == 3
+    h.reset_stats()
+    info = h.solve(b_p, b_T, p, T, rtol=1e-9)
+    st, ts = h.kernel_stats(), h.timed_stats()
+    runs = 2 * info["cycles"]
+    assert ts["smooth_fine"]["launches"] == 2 * ((runs + 2) // 3)
+    assert ts["smooth_fine"]["ms"] > 0 and ts["outer_residual"]["launches"] == 0
+    assert st["smooth_fine"]["launches"] == 4 * info["cycles"]
+    with pytest.raises(ptmg.PtMgError):
+        h.set_option(ptmg.PT_OPT_TIMING_EVERY, 0)
 
 
 @pytest.mark.parametrize("name", ["bubble2d_200x136", "bubble3d_40x24x56"])
@@ -245,7 +263,71 @@ def test_tail_and_graph_paths_agree(name, prec):
             torch.cuda.synchronize()
             out[opts] = (p.clone(), T.clone(), e[0].clone(), e[1].clone())
         h.set_option(ptmg.PT_OPT_TAIL, 1)
-        if name == "explicit_64":   # 32^2 .. 4^2 fit in one block's LDS
+        if name == "explicit_64":   # 32^2 .. 2^2 fit in one block's LDS
             assert h.get_option(ptmg.PT_OPT_TAIL) >= 4
     for a, b in zip(out[(1, 1, 1)], out[(0, 0, 0)]):
         assert torch.equal(a, b), (a - b).abs().max().item()
+
+
+@pytest.mark.parametrize("nu", [(1, 1), (2, 1), (1, 2), (2, 2), (3, 2), (0, 2)])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_coarse_half_cycles_match_reference(nu, prec):
+    """2-D coarse levels run each visit of a V-cycle as one kernel (sweeps +
+    residual + restriction down, prolongation + sweeps up, nu in {1, 2});
+    V-cycles and solves equal the separate-kernel reference bit for bit, on
+    coarse levels of several ragged tiles down to an odd coarsest grid."""
+    import workloads.device as D
+    from paper_2206_11294_amd import ptmg
+    prob = W.bubble_problem("b5", 2, (384, 320), [(0.4, 0.45)], [0.2], W.P0, 10 * W.P0,
+                            div_amp=1e-6, div_seed=11)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        h, b_p, b_T, _ = D.setup(prob, prec, stream=stream)
+        rng = np.random.default_rng(5)
+        f_p, f_T = dev(rng.uniform(-1, 1, h.N)), dev(rng.uniform(-1, 1, h.N))
+        out = {}
+        for fused in (1, 0):
+            h.set_option(ptmg.PT_OPT_FUSED, fused)
+            e = h.vcycle(f_p, f_T, nu[0], nu[1])
+            p, T = torch.empty_like(b_p), torch.empty_like(b_T)
+            info = h.solve(b_p, b_T, p, T, rtol=1e-11, nu1=nu[0], nu2=nu[1])
+            torch.cuda.synchronize()
+            out[fused] = (e[0].clone(), e[1].clone(), p.clone(), T.clone(), info["cycles"])
+    assert out[1][4] == out[0][4]
+    for a, b in zip(out[1][:4], out[0][:4]):
+        assert torch.equal(a, b), (a - b).abs().max().item()
+
+
+@pytest.mark.parametrize("name", ["bubble2d_200x136", "explicit_64", "bubble3d_40x24x56"])
+def test_speculation_changes_no_result(name):
+    """Outer iterations enqueued ahead of the host's convergence test give
+    the step-by-step loop's bits, cycles and history (zero guess, warm
+    start, and a tolerance met at cycle 0)."""
+    import workloads.device as D
+    from paper_2206_11294_amd import ptmg
+    prob = step_problems()[name]
+    h, b_p, b_T, _ = D.setup(prob, 1)
+    out = {}
+    for spec in (0, 1):
+        h.set_option(ptmg.PT_OPT_SPECULATE, spec)
+        assert h.get_option(ptmg.PT_OPT_SPECULATE) == spec
+        p, T = torch.empty_like(b_p), torch.empty_like(b_T)
+        i1 = h.solve(b_p, b_T, p, T, rtol=1e-11)
+        u1 = h.last_cell_updates()
+        # warm start from a rougher solution
+        p2, T2 = torch.empty_like(b_p), torch.empty_like(b_T)
+        h.solve(b_p, b_T, p2, T2, rtol=1e-4)
+        i2 = h.solve(b_p, b_T, p2, T2, rtol=1e-11, zero_guess=False)
+        # converged on arrival
+        p3, T3 = p.clone(), T.clone()
+        i3 = h.solve(b_p, b_T, p3, T3, rtol=1e-3, zero_guess=False)
+        torch.cuda.synchronize()
+        out[spec] = (p, T, i1, u1, p2, T2, i2, p3, T3, i3)
+    a, b = out[0], out[1]
+    for x, y in ((a[0], b[0]), (a[1], b[1]), (a[4], b[4]), (a[5], b[5]), (a[7], b[7]), (a[8], b[8])):
+        assert torch.equal(x, y)
+    for ia, ib in ((a[2], b[2]), (a[6], b[6]), (a[9], b[9])):
+        assert ia["cycles"] == ib["cycles"] and ia["status"] == ib["status"] == 0
+        assert ia["hist"] == ib["hist"]
+    assert a[9]["cycles"] == 0 and torch.equal(b[7], b[0])
+    assert a[3] == b[3]      # cell-updates count only the kept cycles
