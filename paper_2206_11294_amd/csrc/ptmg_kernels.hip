@@ -17,11 +17,21 @@
 namespace ptmg {
 
 // ---------------------------------------------------------------- helpers
+// Quotient of the smoother and transfer arithmetic: correctly rounded in
+// FP64; in FP32 (the mixed-precision V-cycle, a preconditioner under FP64
+// refinement) the hardware reciprocal (1 ulp) times the numerator, a
+// third of the instructions of a rounded division.
+template <typename R> __device__ __forceinline__ R quot(R a, R b) { return a / b; }
+template <> __device__ __forceinline__ float quot<float>(float a, float b)
+{
+    return a * __builtin_amdgcn_rcpf(b);
+}
+
 template <typename R>
 __device__ __forceinline__ R harm(R a, R b)
 {
     R s = a + b;
-    return s > R(0) ? R(2) * a * b / s : R(0);
+    return s > R(0) ? quot(R(2) * a * b, s) : R(0);
 }
 
 template <typename V2>
@@ -412,7 +422,7 @@ __device__ __forceinline__ void rb_cell(const Lvl<R> &L, int i, int j, int k, lo
     const V4 b = L.B[me];
     const R gp = f.x + nbp, gT = f.y + nbT;
     const R a = b.x + Sp, d = b.w + ST;
-    const R inv = R(1) / (a * d - b.y * b.z);
+    const R inv = quot(R(1), a * d - b.y * b.z);
     V2 o;
     o.x = (d * gp - b.y * gT) * inv;
     o.y = (a * gT - b.z * gp) * inv;
@@ -1038,7 +1048,7 @@ __device__ __forceinline__ void block_solve(typename VT<R>::v2 f, typename VT<R>
 {
     const R gp = f.x + gp_nb, gT = f.y + gT_nb;
     const R a = b.x + Sp, d = b.w + ST;
-    const R inv = R(1) / (a * d - b.y * b.z);
+    const R inv = quot(R(1), a * d - b.y * b.z);
     o.x = (d * gp - b.y * gT) * inv;
     o.y = (a * gT - b.z * gp) * inv;
 }
@@ -1381,7 +1391,13 @@ __global__ __launch_bounds__(TX *TY) void k_rb_tile2x(Lvl<R> L, Lvl<R> C,
     constexpr int RWR = TX / 2 + RG - 1, RYR = TY + 2 * (RG - 1);   // red: ring RG - 1
     constexpr int RWB = TX / 2 + RG - 2, RYB = TY + 2 * (RG - 2);   // black: ring RG - 2
     static_assert(RWR * RYR <= NT && RWB * RYB <= NT, "tile too small for its rings");
+    // sw[c] = (x- face, y- face) harmonic coefficients of cell c; every
+    // face of a black cell or of a tile cell borders a red cell of the red
+    // region, so the red pass computes each face once and the black pass
+    // and the residual read it (scaled by 1/h^2 where used, in the same
+    // expressions as the other kernels, so that contractions match)
     __shared__ V2 su[PS], sa[PS];
+    __shared__ V4 sw[PS];
     __shared__ V2 sr[RES ? NT : 1];
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     if (tile >= ntiles) return;
@@ -1413,9 +1429,9 @@ __global__ __launch_bounds__(TX *TY) void k_rb_tile2x(Lvl<R> L, Lvl<R> C,
         sa[c] = a;
     }
     __syncthreads();
-    auto update = [&](int c, long long g) {
+    // block solve of cell c from its four face weights
+    auto solve = [&](int c, long long g, V2 wxm, V2 wxp, V2 wym, V2 wyp) {
         R gp = R(0), gT = R(0), Sp = R(0), ST = R(0);
-        const V2 am = sa[c];
         auto accw = [&](V2 w, int q) {
             const R wp = w.x * ih2, wT = w.y * ih2;
             const V2 uq = su[q];
@@ -1424,29 +1440,69 @@ __global__ __launch_bounds__(TX *TY) void k_rb_tile2x(Lvl<R> L, Lvl<R> C,
             gp += wp * uq.x;
             gT += wT * uq.y;
         };
-        accw(harm2(am, sa[c - 1]), c - 1);
-        accw(harm2(am, sa[c + 1]), c + 1);
-        accw(harm2(am, sa[c - PX]), c - PX);
-        accw(harm2(am, sa[c + PX]), c + PX);
+        accw(wxm, c - 1);
+        accw(wxp, c + 1);
+        accw(wym, c - PX);
+        accw(wyp, c + PX);
         V2 o;
         block_solve<R>(L.f[g], L.B[g], gp, gT, Sp, ST, o);
         su[c] = o;
     };
-    // cells of colour `color` in row ly within ring d of the tile
-    auto pass = [&](int color, int d, int rw, int ry) {
-        if (t < rw * ry) {
-            const int ly = RG - d + t / rw;
-            const int gy = oy + ly;
-            const int xs = x0 - d;
-            const int gx = xs + 2 * (t % rw) + ((xs + gy + color) & 1);
-            const int lx = gx - ox;
-            if (gx >= 0 && gx < L.nx && gy >= 0 && gy < L.ny)
-                update(ly * PX + lx, gx + (long long)L.nx * gy);
-        }
-        __syncthreads();
+    auto weight = [&](V2 am, int q) { return harm2(am, sa[q]); };
+    auto wget = [&](int c, V2 &wxm, V2 &wxp, V2 &wym, V2 &wyp) {
+        const V4 a = sw[c], b = sw[c + 1], d = sw[c + PX];
+        wxm.x = a.x;
+        wxm.y = a.y;
+        wym.x = a.z;
+        wym.y = a.w;
+        wxp.x = b.x;
+        wxp.y = b.y;
+        wyp.x = d.z;
+        wyp.y = d.w;
     };
-    pass(0, RG - 1, RWR, RYR);
-    pass(1, RG - 2, RWB, RYB);
+    // red: cells within ring RG - 1 (faces computed and kept for everyone)
+    if (t < RWR * RYR) {
+        const int d = RG - 1;
+        const int ly = RG - d + t / RWR;
+        const int gy = oy + ly;
+        const int xs = x0 - d;
+        const int gx = xs + 2 * (t % RWR) + ((xs + gy) & 1);
+        const int c = ly * PX + gx - ox;
+        const V2 am = sa[c];
+        const V2 wxm = weight(am, c - 1), wxp = weight(am, c + 1);
+        const V2 wym = weight(am, c - PX), wyp = weight(am, c + PX);
+        V4 w;
+        w.x = wxm.x;
+        w.y = wxm.y;
+        w.z = wym.x;
+        w.w = wym.y;
+        sw[c] = w;
+        w.x = wxp.x;
+        w.y = wxp.y;
+        w.z = R(0);
+        w.w = R(0);
+        // x+ face of c is the x- face of c + 1 (a black cell), the y+ face
+        // the y- face of c + PX: written into their slots
+        ((V2 *)&sw[c + 1])[0] = wxp;
+        ((V2 *)&sw[c + PX])[1] = wyp;
+        if (gx >= 0 && gx < L.nx && gy >= 0 && gy < L.ny)
+            solve(c, gx + (long long)L.nx * gy, wxm, wxp, wym, wyp);
+    }
+    __syncthreads();
+    if (t < RWB * RYB) {
+        const int d = RG - 2;
+        const int ly = RG - d + t / RWB;
+        const int gy = oy + ly;
+        const int xs = x0 - d;
+        const int gx = xs + 2 * (t % RWB) + ((xs + gy + 1) & 1);
+        const int c = ly * PX + gx - ox;
+        if (gx >= 0 && gx < L.nx && gy >= 0 && gy < L.ny) {
+            V2 wxm, wxp, wym, wyp;
+            wget(c, wxm, wxp, wym, wyp);
+            solve(c, gx + (long long)L.nx * gy, wxm, wxp, wym, wyp);
+        }
+    }
+    __syncthreads();
     const int lx = RG + t % TX, ly = RG + t / TX;
     const int gx = x0 + t % TX, gy = y0 + t / TX;
     const bool mine = gx < L.nx && gy < L.ny;
@@ -1458,10 +1514,11 @@ __global__ __launch_bounds__(TX *TY) void k_rb_tile2x(Lvl<R> L, Lvl<R> C,
     r.x = r.y = R(0);
     if (mine) {
         const long long g = gx + (long long)L.nx * gy;
-        const V2 um = su[c], am = sa[c];
+        const V2 um = su[c];
         R nbp = R(0), nbT = R(0), Sp = R(0), ST = R(0);
-        auto nb = [&](int q) {
-            V2 w = harm2(am, sa[q]);
+        V2 wxm, wxp, wym, wyp;
+        wget(c, wxm, wxp, wym, wyp);
+        auto nb = [&](V2 w, int q) {
             const R wp = w.x * ih2, wT = w.y * ih2;
             const V2 uq = su[q];
             Sp += wp;
@@ -1469,10 +1526,10 @@ __global__ __launch_bounds__(TX *TY) void k_rb_tile2x(Lvl<R> L, Lvl<R> C,
             nbp += wp * uq.x;
             nbT += wT * uq.y;
         };
-        nb(c - 1);
-        nb(c + 1);
-        nb(c - PX);
-        nb(c + PX);
+        nb(wxm, c - 1);
+        nb(wxp, c + 1);
+        nb(wym, c - PX);
+        nb(wyp, c + PX);
         const V2 f = L.f[g];
         const V4 B = L.B[g];
         const R Ap = Sp * um.x - nbp + B.x * um.x + B.y * um.y;
