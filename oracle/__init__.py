@@ -49,7 +49,7 @@ def _load():
 
 class _Phase(ctypes.Structure):
     _fields_ = [(f, ctypes.c_double) for f in
-                ("rho", "k", "cp", "cv", "c", "gamma", "Gamma", "Pi", "b", "beta")]
+                ("rho", "k", "cp", "cv", "c", "gamma", "Gamma", "Pi", "b", "beta", "q")]
 
 
 _D = ctypes.POINTER(ctypes.c_double)
@@ -69,6 +69,10 @@ def _declare(lib):
                                          _D, c_double, _D, _D, _D, _D]),
         "orc_paper_rhs": (None, [c_long, _D, _D, c_double, _D, c_double, _D, c_double,
                                  _D, _D]),
+        "orc_state": (None, [c_long, c_int, _D, _D, _D, _D, _D, _P, _P, _D, _D]),
+        "orc_sound2": (c_double, [_P, c_double, c_double]),
+        "orc_assemble_state": (c_long, [c_long, _D, _D, _D, _P, _P, c_double, _D, _D, _D,
+                                        _D, _D, _D]),
         "orc_canonical_rhs": (None, [c_long, _D, _D, _D, _D, _D]),
         "orc_faces_from_cells": (None, [c_int, _I, _D, _D, _D]),
         "orc_apply": (None, [c_int, _I, c_double, _D, _D, _D, _D, _D, _D]),
@@ -121,7 +125,9 @@ class Operator:
 
     F: faces [6, N] ((component, axis) major; lower face of each cell),
     B: block [4, N] in the order (pp, pT, Tp, TT),
-    lam: paper coefficients [4, N] (l1, l2, l3, l4) in phases mode, else None.
+    lam: paper coefficients [4, N] (l1, l2, l3, l4) in phases mode, else None;
+    p_adv, T_adv: the provisional state the operator was assembled at, when
+    the problem gives it through conserved variables (state mode).
     """
     dim: int
     n: Tuple[int, int, int]
@@ -131,6 +137,8 @@ class Operator:
     lam: Optional[np.ndarray] = None
     a_p: Optional[np.ndarray] = None
     a_T: Optional[np.ndarray] = None
+    p_adv: Optional[np.ndarray] = None
+    T_adv: Optional[np.ndarray] = None
 
     @property
     def N(self) -> int:
@@ -171,10 +179,40 @@ def faces_from_cells(dim, n, a_p, a_T) -> np.ndarray:
     return F.reshape(6, N)
 
 
+def state(prob) -> Tuple[np.ndarray, np.ndarray]:
+    """Provisional (p, T) of a state-mode problem, Eqs. (20) and (23)."""
+    N = prob.ncells
+    p, T = np.zeros(N), np.zeros(N)
+    mom = None if prob.mom is None else np.concatenate([_f64(m) for m in prob.mom])
+    _load().orc_state(N, prob.dim, _d(_f64(prob.C)), _d(_f64(prob.m1)), _d(_f64(prob.m2)),
+                      _d(_f64(prob.E)), _d(mom), ctypes.byref(phase(prob.liquid)),
+                      ctypes.byref(phase(prob.gas)), _d(p), _d(T))
+    return p, T
+
+
+def sound2(ph, rho: float, p: float) -> float:
+    """Eq. (11)."""
+    return _load().orc_sound2(ctypes.byref(phase(ph)), rho, p)
+
+
 def assemble(prob) -> Operator:
     """Assemble the canonical operator of a workloads.Problem."""
     lib = _load()
     N = prob.ncells
+    if prob.mode == "state":
+        p_adv, T_adv = (state(prob) if prob.p_adv is None
+                        else (_f64(prob.p_adv).copy(), _f64(prob.T_adv).copy()))
+        a_p, a_T = np.zeros(N), np.zeros(N)
+        lam, B = np.zeros(4 * N), np.zeros(4 * N)
+        bad = lib.orc_assemble_state(N, _d(_f64(prob.C)), _d(_f64(prob.m1)),
+                                     _d(_f64(prob.m2)), ctypes.byref(phase(prob.liquid)),
+                                     ctypes.byref(phase(prob.gas)), prob.dt, _d(p_adv),
+                                     _d(T_adv), _d(a_p), _d(a_T), _d(lam), _d(B))
+        if bad:
+            raise ValueError(f"{bad} cells with a non-positive block")
+        F = faces_from_cells(prob.dim, prob.n, a_p, a_T)
+        return Operator(prob.dim, prob.n, prob.h, F, B.reshape(4, N), lam.reshape(4, N),
+                        a_p, a_T, p_adv, T_adv)
     if prob.mode == "explicit":
         a_p = np.full(N, float(prob.alpha_p))
         a_T = np.full(N, float(prob.alpha_T))
@@ -204,6 +242,8 @@ def paper_rhs(op: Operator, prob) -> Tuple[np.ndarray, np.ndarray]:
     lam = np.ascontiguousarray(op.lam).reshape(-1)
     p_adv = None if prob.p_adv is None else _f64(prob.p_adv)
     T_adv = None if prob.T_adv is None else _f64(prob.T_adv)
+    if op.p_adv is not None:
+        p_adv, T_adv = op.p_adv, op.T_adv
     div = None if prob.div_ustar is None else _f64(prob.div_ustar)
     _load().orc_paper_rhs(N, _d(lam), _d(p_adv), prob.p_adv_const, _d(T_adv),
                           prob.T_adv_const, _d(div), prob.dt, _d(b_p), _d(b_T))

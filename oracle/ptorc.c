@@ -42,7 +42,7 @@
 #include <string.h>
 
 typedef struct {
-    double rho, k, cp, cv, c, gamma, Gamma, Pi, b, beta;
+    double rho, k, cp, cv, c, gamma, Gamma, Pi, b, beta, q;
 } orc_phase;
 
 /* ------------------------------------------------------------------ */
@@ -117,6 +117,106 @@ long orc_assemble_phases(long n, const double *C, const orc_phase *liq,
         orc_cell_lambdas(c, liq, gas, p, T, dt, l, b);
         a_p[i] = 1.0 / (c * liq->rho + (1.0 - c) * gas->rho);
         a_T[i] = c * liq->k + (1.0 - c) * gas->k;
+        for (int q = 0; q < 4; q++) {
+            lam[q * n + i] = l[q];
+            B[q * n + i] = b[q];
+        }
+        if (!(b[0] > 0.0 && b[3] > 0.0 && b[0] * b[3] - b[1] * b[2] > 0.0)) bad++;
+    }
+    return bad;
+}
+
+/* ------------------------------------------------------------------ */
+/* provisional state from the advected conserved variables            */
+/* ------------------------------------------------------------------ */
+
+/* Provisional pressure, Eq. (20), and temperature, Eq. (23), of n cells
+ * from the advected conserved variables of Sec. 3: C (liquid volume
+ * fraction), m1 = C rho_1 and m2 = (1 - C) rho_2 (phase masses per
+ * volume), E (the cell's total energy per volume, both phases) and the
+ * averaged momentum mom[dim * n] (component-major; NULL: at rest).  The
+ * bar average of a phase quantity phi(rho_i) is C phi(rho_1) +
+ * (1 - C) phi(rho_2) with rho_i = m_i / C_i (a phase absent from the cell
+ * adds nothing); the kinetic energy is 1/2 rho_bar |u_bar|^2 with
+ * rho_bar = m1 + m2 and u_bar = mom / rho_bar. */
+void orc_state(long n, int dim, const double *C, const double *m1, const double *m2,
+               const double *E, const double *mom, const orc_phase *liq,
+               const orc_phase *gas, double *p, double *T)
+{
+#pragma omp parallel for schedule(static)
+    for (long i = 0; i < n; i++) {
+        const double frac[2] = {C[i], 1.0 - C[i]};
+        const double mass[2] = {m1[i], m2[i]};
+        const orc_phase *ph[2] = {liq, gas};
+        double e_static = 0.0, inv_gm1 = 0.0;          /* the two bars of Eq. (20) */
+        double vol = 0.0, vol_pi = 0.0, heat = 0.0;    /* the three bars of Eq. (23) */
+        for (int q = 0; q < 2; q++) {
+            if (frac[q] <= 0.0) continue;
+            const double rho = mass[q] / frac[q];
+            const double G = ph[q]->Gamma, Pi = ph[q]->Pi, b = ph[q]->b;
+            const double free_vol = 1.0 - rho * b;
+            e_static += frac[q] * (G * Pi / (G - 1.0) * free_vol + rho * ph[q]->q);
+            inv_gm1 += frac[q] * (free_vol / (G - 1.0));
+            vol += frac[q] * free_vol;
+            vol_pi += frac[q] * (Pi * free_vol);
+            heat += frac[q] * (rho * (ph[q]->cp - ph[q]->cv));
+        }
+        const double rho_bar = m1[i] + m2[i];
+        double u2 = 0.0;
+        if (mom)
+            for (int a = 0; a < dim; a++) {
+                const double u = mom[(long)a * n + i] / rho_bar;
+                u2 += u * u;
+            }
+        const double pc = (E[i] - 0.5 * rho_bar * u2 - e_static) / inv_gm1;
+        p[i] = pc;
+        T[i] = (vol * pc + vol_pi) / heat;
+    }
+}
+
+/* Sound speed squared of a phase, Eq. (11). */
+double orc_sound2(const orc_phase *ph, double rho, double p)
+{
+    return ph->Gamma * (p + ph->Pi) / (rho * (1.0 - rho * ph->b));
+}
+
+/* Assembly from the cell state (state mode): in each cell every phase
+ * present has the density rho_i = m_i / C_i, the sound speed of Eq. (11)
+ * at (rho_i, p_adv), the thermal dilation of Eq. (10) at (p_adv, T_adv)
+ * and the gamma of its record; its coefficients (Eqs. 29-32) and canonical
+ * block follow as in the phases mode; the blocks and k are averaged with
+ * the phase fractions, and a_p = 1 / (m1 + m2).  Outputs as
+ * orc_assemble_phases; returns the number of non-positive blocks. */
+long orc_assemble_state(long n, const double *C, const double *m1, const double *m2,
+                        const orc_phase *liq, const orc_phase *gas, double dt,
+                        const double *p_adv, const double *T_adv, double *a_p, double *a_T,
+                        double *lam, double *B)
+{
+    long bad = 0;
+#pragma omp parallel for reduction(+ : bad) schedule(static)
+    for (long i = 0; i < n; i++) {
+        const double frac[2] = {C[i], 1.0 - C[i]};
+        const double mass[2] = {m1[i], m2[i]};
+        const orc_phase *src[2] = {liq, gas};
+        const double p = p_adv[i], T = T_adv[i];
+        double b[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int q = 0; q < 2; q++) {
+            if (frac[q] <= 0.0) continue;
+            orc_phase ph = *src[q];
+            ph.rho = mass[q] / frac[q];
+            ph.c = sqrt(orc_sound2(&ph, ph.rho, p));
+            double l[4], bq[4];
+            orc_phase_lambdas(&ph, p, T, dt, l);
+            orc_block_from_lambdas(l, bq);
+            for (int k = 0; k < 4; k++) b[k] += frac[q] * bq[k];
+        }
+        a_p[i] = 1.0 / (m1[i] + m2[i]);
+        a_T[i] = C[i] * liq->k + (1.0 - C[i]) * gas->k;
+        double l[4];
+        l[0] = -b[3];
+        l[1] = -b[2];
+        l[3] = b[1] / l[0];
+        l[2] = -b[0] + l[3] * l[1];
         for (int q = 0; q < 4; q++) {
             lam[q * n + i] = l[q];
             B[q * n + i] = b[q];

@@ -48,16 +48,34 @@ class Phase:
     Pi: float
     b: float
     beta: float = 0.0
+    q: float = 0.0          # NASG energy offset of Eq. (9) (state mode)
 
     def as_tuple(self) -> Tuple[float, ...]:
         return (self.rho, self.k, self.cp, self.cv, self.c, self.gamma,
-                self.Gamma, self.Pi, self.b, self.beta)
+                self.Gamma, self.Pi, self.b, self.beta, self.q)
 
 
 LIQUID = Phase(rho=1000.0, k=0.6, cp=4000.0, cv=3610.0, c=1500.0,
                gamma=4285.0 / 3610.0, Gamma=1.19, Pi=7028e5, b=6.61e-4)
 GAS = Phase(rho=1.0, k=0.6 / 23.0, cp=1000.0, cv=1000.0 / 1.4, c=340.0,
             gamma=1.4, Gamma=1.4, Pi=0.0, b=0.0)
+
+# State mode (densities and sound speeds from the cell state): the full
+# Table 1 record of water (c_p = 4285, q) and an ideal gas; rho and c of
+# these records are nominal only.
+LIQUID_NASG = Phase(rho=1055.9, k=0.6, cp=4285.0, cv=3610.0, c=1500.0,
+                    gamma=4285.0 / 3610.0, Gamma=1.19, Pi=7028e5, b=6.61e-4,
+                    q=-1177788.0)
+GAS_IDEAL = Phase(rho=1.2, k=0.6 / 23.0, cp=1000.0, cv=1000.0 / 1.4, c=340.0,
+                  gamma=1.4, Gamma=1.4, Pi=0.0, b=0.0)
+
+# Reference conserved state of the state-mode workloads: phase densities
+# and specific internal energies near (1 atm, 293 K) for the two records
+# above (the liquid and the gas at 1 and 10 atm).  They are input data;
+# the provisional pressure and temperature are what Eqs. (20), (23) make
+# of them.
+REF_LIQUID = (1055.899893, 81526.1000)          # rho [kg/m^3], e [J/kg]
+REF_GAS = {1: (1.20974757, 209392.8571), 10: (12.0974757, 209392.8571)}
 
 
 @dataclasses.dataclass
@@ -71,7 +89,7 @@ class Problem:
     dim: int
     n: Tuple[int, int, int]
     h: float
-    mode: str                      # "explicit" or "phases"
+    mode: str                      # "explicit", "phases" or "state"
     # explicit mode (canonical form):  -div(a grad u) + B u = f
     alpha_p: float = 0.0
     alpha_T: float = 0.0
@@ -91,6 +109,12 @@ class Problem:
     rtol: float = 1e-9
     precision: str = "fp64"                 # "fp64" or "mixed"
     mean_constraint: bool = False
+    # state mode: advected conserved variables (Sec. 3); p_adv, T_adv are
+    # derived from them (Eqs. 20, 23)
+    m1: Optional[np.ndarray] = None         # C rho_1
+    m2: Optional[np.ndarray] = None         # (1 - C) rho_2
+    E: Optional[np.ndarray] = None          # total energy per volume
+    mom: Optional[List[np.ndarray]] = None  # averaged momentum, one array per axis
 
     @property
     def ncells(self) -> int:
@@ -219,6 +243,64 @@ def collapse3d(n: int = 512, precision: str = "mixed") -> Problem:
     return bubble_problem(f"collapse3d_{n}", 3, (n, n, n),
                           [(0.5, 0.5, 0.5)], [0.25], 100 * P0, 0.01 * P0,
                           precision=precision)
+
+
+def state_problem(name: str, dim: int, n: Sequence[int],
+                  centres_unit: Sequence[Sequence[float]], radii_unit: Sequence[float],
+                  gas_atm: int = 1, u_amp: float = 1.0, seed: int = 12,
+                  div_amp: float = 1e-6, precision: str = "fp64",
+                  rtol: float = 1e-9) -> Problem:
+    """Bubbles in liquid given by advected conserved variables (Sec. 3):
+    C from the bubble geometry; phase masses m1 = C rho_l, m2 = (1-C) rho_g
+    and total energy E = C rho_l e_l + (1-C) rho_g e_g + 1/2 rho |u|^2
+    from the reference states REF_LIQUID, REF_GAS[gas_atm] with seeded
+    smooth relative variations (rho_g 5 %, e_l 1e-4, e_g 1 %); a smooth
+    velocity of amplitude u_amp [m/s] per axis (momentum = rho u); the
+    acoustic time step; velocity-divergence forcing of amplitude
+    div_amp/dt (seeded)."""
+    nn = _grid(dim, n)
+    h = L_UNIT / nn[0]
+    centres = [[L_UNIT * v for v in c] for c in centres_unit]
+    radii = [L_UNIT * r for r in radii_unit]
+    C = bubble_fraction(dim, nn, h, centres, radii)
+
+    def unit(s):
+        f = smooth_field(dim, nn, seed + s)
+        m = np.abs(f).max()
+        return f / m if m > 0 else f
+
+    rho_l, e_l0 = REF_LIQUID
+    rho_g0, e_g0 = REF_GAS[gas_atm]
+    rho_g = rho_g0 * (1.0 + 0.05 * unit(1))
+    e_l = e_l0 * (1.0 + 1e-4 * unit(2))
+    e_g = e_g0 * (1.0 + 0.01 * unit(3))
+    m1 = C * rho_l
+    m2 = (1.0 - C) * rho_g
+    rho = m1 + m2
+    us = [u_amp * unit(4 + a) for a in range(dim)]
+    mom = [np.ascontiguousarray(rho * u) for u in us]
+    ke = 0.5 * rho * sum(u * u for u in us)
+    E = m1 * e_l + m2 * e_g + ke
+    dt = acoustic_dt(h)
+    rng = np.random.Generator(np.random.PCG64(seed + 10))
+    div = (div_amp / dt) * rng.uniform(-1.0, 1.0, size=C.shape) if div_amp else None
+    return Problem(name=name, dim=dim, n=nn, h=h, mode="state", C=C,
+                   liquid=LIQUID_NASG, gas=GAS_IDEAL, dt=dt, div_ustar=div,
+                   rtol=rtol, precision=precision, m1=np.ascontiguousarray(m1),
+                   m2=np.ascontiguousarray(m2), E=np.ascontiguousarray(E), mom=mom)
+
+
+def state2d(n: int = 1024) -> Problem:
+    """The 2-D bubble (radius 0.1, centred) given by its conserved state,
+    gas and liquid near 1 atm, velocity 1 m/s."""
+    return state_problem(f"state2d_{n}", 2, (n, n), [(0.5, 0.5)], [0.1], gas_atm=1)
+
+
+def state3d(n: int = 256, precision: str = "mixed") -> Problem:
+    """The near-wall 3-D bubble (radius 0.2 at (0.5, 0.5, 0.24)) given by
+    its conserved state, gas near 10 atm, velocity 1 m/s."""
+    return state_problem(f"state3d_{n}", 3, (n, n, n), [(0.5, 0.5, 0.24)], [0.2],
+                         gas_atm=10, precision=precision)
 
 
 # ---------------------------------------------------------------- serving mix
