@@ -4,7 +4,10 @@
 One step = one pass of the whole hot path over one synthetic input:
 re-assembly of the operator and hierarchy (pt_mg_update), the paper's
 right-hand side (pt_mg_paper_rhs) and the solve to tolerance
-(pt_mg_solve), with every input already resident in device memory.
+(pt_mg_solve), with every input already resident in device memory.  The
+state-mode workloads (state2d_1024, state3d_256) start one step earlier,
+from the advected conserved variables: the provisional pressure and
+temperature (pt_state_eval, Eqs. 20 and 23) feed the state-mode assembly.
 
 Prints one JSON line: cell-updates/s of the timed steps, the roofline of
 the dominant kernel (HIP-event durations of its launches inside the timed
@@ -35,6 +38,8 @@ WORKLOADS = {
     "bubble2d_1024": ("bubble2d", "fp64", 1e-12),
     "wall3d_256": ("wall3d", "mixed", 1e-12),
     "collapse3d_512": ("collapse3d", "mixed", 1e-12),
+    "state2d_1024": ("state2d", "fp64", 1e-12),
+    "state3d_256": ("state3d", "mixed", 1e-12),
 }
 
 
@@ -48,6 +53,10 @@ def make_problem(name):
         return W.wall3d(256)
     if name == "collapse3d_512":
         return W.collapse3d(512)
+    if name == "state2d_1024":
+        return W.state2d(1024)
+    if name == "state3d_256":
+        return W.state3d(256)
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -71,6 +80,21 @@ def traffic_from_profile(workload, kernel_class, launches_per_step):
     if rec.get("source_hash") != kernel_source_hash() or rec.get("kernel_class") != kernel_class:
         return None
     return rec.get("hbm_bytes_per_launch")
+
+
+def upstream_line(prob, state_ms):
+    """Achieved bandwidth of the provisional-state kernel (state mode):
+    per cell it reads C, m1, m2, E and dim momentum components and writes
+    p_adv, T_adv, all float64, once."""
+    if not state_ms:
+        return None
+    nbytes = prob.ncells * 8.0 * (4 + prob.dim + 2)
+    ms = sum(state_ms) / len(state_ms)
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    return {"kernel": "pt_state_eval", "bound": "hbm", "achieved": round(gbs, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+            "avg_launch_us": round(ms * 1e3, 2), "alg_bytes_per_launch": nbytes,
+            "launches": len(state_ms)}
 
 
 def oracle_updates(orc, prob, cycles):
@@ -322,9 +346,18 @@ def main():
         p = torch.empty(prob.ncells, dtype=torch.float64, device="cuda")
         T = torch.empty_like(p)
 
+        state = D.state_record(prob, tens) if prob.mode == "state" else None
+        state_ev = []    # (start, end) event pairs around the state kernel
+
         def step():
+            if state is not None:
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record(stream)
+                ptmg.state_eval(state, stream)
+                b.record(stream)
+                state_ev.append((a, b))
             h.update(s)
-            if prob.mode == "phases":
+            if prob.mode != "explicit":
                 b_p, b_T = h.paper_rhs(tens.get("p_adv"), tens.get("T_adv"), tens.get("div"))
             else:
                 b_p, b_T = tens["f_p"], tens["f_T"]
@@ -352,6 +385,7 @@ def main():
         stats = h.kernel_stats()
         timed = h.timed_stats()
         h.set_timing(False)
+        state_ms = [a.elapsed_time(b) for a, b in state_ev[args.warmup:]]
 
     dom = ROOFLINE_KERNEL
     st = timed[dom]
@@ -383,6 +417,7 @@ def main():
                    "step": "pt_mg_update + pt_mg_paper_rhs + pt_mg_solve",
                    "parallelism": "single GPU"},
         "roofline": roofline,
+        "upstream": upstream_line(prob, state_ms),
         "launches_per_step": {k: v["launches"] / args.steps for k, v in stats.items()},
         "relres_last": list(info["relres"]),
     }

@@ -70,15 +70,18 @@ typedef enum {
     PT_ERR_STATE = 6      /* call not valid for this handle (wrong mode, level, ...) */
 } pt_status;
 
-typedef enum { PT_COEF_EXPLICIT = 0, PT_COEF_PHASES = 1 } pt_coef_mode;
+typedef enum { PT_COEF_EXPLICIT = 0, PT_COEF_PHASES = 1, PT_COEF_STATE = 2 } pt_coef_mode;
 typedef enum { PT_PREC_FP64 = 0, PT_PREC_MIXED = 1 } pt_precision;
 
 /* Per-phase properties (SI).  beta <= 0: thermal dilation from Eq. (10),
  * beta = (Gamma-1) c_v / ((Gamma-1) c_v T + b (p + Pi)), evaluated at the
  * cell's (p_adv, T_adv); an ideal gas has Gamma = gamma, Pi = b = 0, which
- * gives 1/T.  gamma = c_p/c_v and the sound speed c enter l3 (Eq. 31). */
+ * gives 1/T.  gamma = c_p/c_v and the sound speed c enter l3 (Eq. 31).
+ * q is the energy offset of the NASG EoS (Eq. 9), used by pt_state_eval.
+ * In PT_COEF_STATE mode rho and c are not used: each cell's phase density
+ * comes from its conserved variables and the sound speed from Eq. (11). */
 typedef struct {
-    double rho, k, cp, cv, c, gamma, Gamma, Pi, b, beta;
+    double rho, k, cp, cv, c, gamma, Gamma, Pi, b, beta, q;
 } pt_phase;
 
 /* Problem description.  Unused fields are ignored; arrays are device
@@ -105,6 +108,15 @@ typedef struct {
      * constant of each component by a zero mean (the right-hand side is
      * projected to zero mean).  PT_ERR_ARG if set while B is not zero. */
     int mean_constraint;
+    /* PT_COEF_STATE: the paper form with the cell state of Sec. 3.  Uses C,
+     * liquid, gas, dt as PT_COEF_PHASES, the arrays p_adv and T_adv (both
+     * required, e.g. from pt_state_eval), and the phase masses per volume
+     * m1 = C rho_1, m2 = (1 - C) rho_2 [N]: each phase present in a cell
+     * (fraction > 0, mass > 0) has density m_i / C_i, the sound speed of
+     * Eq. (11) at that density and p_adv, and beta of Eq. (10); its block
+     * is weighted by its fraction as in PT_COEF_PHASES, a_p = 1/(m1 + m2),
+     * a_T = C k_1 + (1 - C) k_2. */
+    const double *m1, *m2;
 } pt_problem;
 
 typedef struct {
@@ -124,6 +136,35 @@ typedef struct {
     double t_solve_s;                  /* wall time of the call */
     int status;                        /* same as the return value */
 } pt_solve_info;
+
+/* Advected conserved variables of one grid (Sec. 3), for pt_state_eval.
+ * Device float64 arrays [n]. */
+typedef struct {
+    int dim;                 /* 2 or 3: momentum components read */
+    long long n;             /* cells, >= 1 */
+    const double *C;         /* liquid volume fraction C_1 */
+    const double *m1, *m2;   /* phase masses per volume C_1 rho_1, C_2 rho_2 */
+    const double *E;         /* total energy per volume of the cell (both phases) */
+    const double *mom[3];    /* averaged momentum per axis, or all NULL (at rest) */
+    pt_phase liquid, gas;    /* NASG records (Gamma, Pi, b, q, cp, cv); ideal gas:
+                              * Gamma = gamma, Pi = b = q = 0 */
+    double *p_adv, *T_adv;   /* outputs */
+} pt_state;
+
+/* Provisional pressure and temperature from the advected conserved
+ * variables through the EoS (Sec. 3): Eq. (20),
+ *   p = (E - 1/2 rho |u|^2 - bar(Gamma Pi (1 - rho b)/(Gamma - 1) + rho q))
+ *       / bar((1 - rho b)/(Gamma - 1)),
+ * with rho = m1 + m2, u = mom / rho, and Eq. (23),
+ *   T = (bar(1 - rho b) p + bar(Pi (1 - rho b))) / bar(rho (c_p - c_v)),
+ * where bar(phi) = C_1 phi(rho_1) + C_2 phi(rho_2), rho_i = m_i / C_i (the
+ * bars are formed as sums of C_i- and m_i-weighted terms, so a phase
+ * absent from a cell adds nothing and nothing is divided by C_i).
+ * Asynchronous on hip_stream (hipStream_t or NULL); no host
+ * synchronisation and no allocation.  Cells are not validated here
+ * (pt_mg_setup / pt_mg_update reject non-physical states).  PT_ERR_ARG
+ * for a NULL field, dim or n out of range, or Gamma <= 1. */
+int pt_state_eval(const pt_state *s, void *hip_stream);
 
 /* Device bytes that pt_mg_setup will allocate for this problem and
  * precision (the handle's hierarchy, coarse inverse and work buffers).
@@ -145,7 +186,7 @@ int pt_mg_update(pt_mg_t h, const pt_problem *prob);
 
 /* Right-hand side of the paper form, Eqs. (33)-(34):
  * b_T = l1 T_adv + l2 p_adv, b_p = l3 p_adv + div_ustar / dt, with the
- * cell coefficients of the handle (PT_COEF_PHASES only, else
+ * cell coefficients of the handle (PT_COEF_PHASES or PT_COEF_STATE, else
  * PT_ERR_STATE).  p_adv / T_adv NULL -> the constants given at setup;
  * div_ustar NULL -> zero.  Outputs b_p, b_T [N]. */
 int pt_mg_paper_rhs(pt_mg_t h, const double *p_adv, const double *T_adv,

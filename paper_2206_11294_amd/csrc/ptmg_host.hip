@@ -62,7 +62,22 @@ const char *plan_problem(const pt_problem *p, int prec, Plan &P)
         if (p->n[a] > (1 << 20)) return "grid too large";
     }
     if (!(p->h > 0.0) || !std::isfinite(p->h)) return "h must be positive";
-    if (p->mode != PT_COEF_EXPLICIT && p->mode != PT_COEF_PHASES) return "unknown mode";
+    if (p->mode != PT_COEF_EXPLICIT && p->mode != PT_COEF_PHASES && p->mode != PT_COEF_STATE)
+        return "unknown mode";
+    if (p->mode == PT_COEF_STATE) {
+        if (!p->C || !p->m1 || !p->m2 || !p->p_adv || !p->T_adv)
+            return "state mode needs C, m1, m2, p_adv and T_adv";
+        if (!(p->dt > 0.0) || !std::isfinite(p->dt)) return "dt must be positive";
+        if (p->mean_constraint) return "mean_constraint only applies to B = 0 (explicit mode)";
+        const pt_phase *ph[2] = {&p->liquid, &p->gas};
+        for (int q = 0; q < 2; q++) {
+            const pt_phase &f = *ph[q];
+            if (!(f.k >= 0) || !(f.cp > 0) || !(f.gamma > 0) || !(f.Gamma > 1.0) || !(f.b >= 0))
+                return "state-mode phase needs k >= 0, cp > 0, gamma > 0, Gamma > 1, b >= 0";
+            if (!(f.beta > 0) && !((f.Gamma - 1.0) * f.cv > 0))
+                return "phase needs beta > 0 or (Gamma-1) c_v > 0 for Eq. (10)";
+        }
+    }
     if (p->mode == PT_COEF_PHASES) {
         if (!p->C) return "phases mode needs C";
         if (!(p->dt > 0.0) || !std::isfinite(p->dt)) return "dt must be positive";
@@ -685,6 +700,8 @@ int assemble_enqueue(pt_mg_t h, const pt_problem *p)
     a.T_adv = p->T_adv;
     a.p_adv_const = p->p_adv_const;
     a.T_adv_const = p->T_adv_const;
+    a.m1 = p->m1;
+    a.m2 = p->m2;
     a.ac64 = h->ac64();
     a.B64 = h->B64();
     if (P.prec == PT_PREC_MIXED) {
@@ -785,6 +802,19 @@ double elapsed(std::chrono::steady_clock::time_point t0)
 // ================================================================== C ABI
 // (the declarations in pt_mg.h give these definitions C linkage)
 
+int pt_state_eval(const pt_state *st, void *hip_stream)
+{
+    if (!st) return fail(nullptr, PT_ERR_ARG, "state is NULL");
+    if (st->dim != 2 && st->dim != 3) return fail(nullptr, PT_ERR_ARG, "dim must be 2 or 3");
+    if (st->n < 1) return fail(nullptr, PT_ERR_ARG, "n must be >= 1");
+    if (!st->C || !st->m1 || !st->m2 || !st->E || !st->p_adv || !st->T_adv)
+        return fail(nullptr, PT_ERR_ARG, "NULL field");
+    if (!(st->liquid.Gamma > 1.0) || !(st->gas.Gamma > 1.0))
+        return fail(nullptr, PT_ERR_ARG, "Gamma must be > 1");
+    launch_state(*st, (hipStream_t)hip_stream);
+    return check_hip(nullptr, hipGetLastError(), "state kernel");
+}
+
 size_t pt_mg_footprint_bytes(const pt_problem *prob, int precision)
 {
     Plan P;
@@ -866,7 +896,8 @@ int handle_create(const pt_problem *prob, int precision, hipStream_t stream, cha
 int handle_paper_rhs_async(pt_mg_t h, const double *p_adv, const double *T_adv,
                            const double *div_ustar, double *b_p, double *b_T)
 {
-    if (h->prob.mode != PT_COEF_PHASES) return fail(h, PT_ERR_STATE, "paper_rhs needs phases mode");
+    if (h->prob.mode == PT_COEF_EXPLICIT)
+        return fail(h, PT_ERR_STATE, "paper_rhs needs phases or state mode");
     h->begin(PT_K_OTHER, 48.0 * h->P.N);
     launch_paper_rhs(h->P.N, h->B64(), p_adv, h->prob.p_adv_const, T_adv, h->prob.T_adv_const,
                      div_ustar, h->prob.dt, b_p, b_T, h->stream);
@@ -937,7 +968,8 @@ int pt_mg_paper_rhs(pt_mg_t h, const double *p_adv, const double *T_adv, const d
                     double *b_p, double *b_T)
 {
     if (!h || !h->ready) return fail(h, PT_ERR_STATE, "handle not ready");
-    if (h->prob.mode != PT_COEF_PHASES) return fail(h, PT_ERR_STATE, "paper_rhs needs phases mode");
+    if (h->prob.mode == PT_COEF_EXPLICIT)
+        return fail(h, PT_ERR_STATE, "paper_rhs needs phases or state mode");
     if (!b_p || !b_T) return fail(h, PT_ERR_ARG, "outputs are NULL");
     h->begin(PT_K_OTHER, 48.0 * h->P.N);
     launch_paper_rhs(h->P.N, h->B64(), p_adv, h->prob.p_adv_const, T_adv, h->prob.T_adv_const,
@@ -961,7 +993,7 @@ int outer(pt_mg_t h, const double *b_p, const double *b_T, const double *src_p,
     a.nz = P.n[2];
     a.N = P.N;
     a.inv_h2 = 1.0 / (h->prob.h * h->prob.h);
-    a.phases = h->prob.mode == PT_COEF_PHASES;
+    a.phases = h->prob.mode != PT_COEF_EXPLICIT;
     a.ac = h->ac64();
     a.B = h->B64();
     a.b_p = b_p;

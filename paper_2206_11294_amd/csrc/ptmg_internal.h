@@ -64,6 +64,8 @@ struct AsmArgs {
     double dt;
     const double *p_adv, *T_adv;
     double p_adv_const, T_adv_const;
+    // state
+    const double *m1, *m2;
     // outputs
     double2 *ac64;
     double4 *B64;
@@ -87,6 +89,9 @@ template <typename R> struct TailArgs {
     const double *Ainv;
     int ainv_off;   // LDS offset of a copy of Ainv, or -1 (read from global memory)
 };
+
+// Provisional state (Eqs. 20, 23) of n cells.
+void launch_state(const pt_state &st, hipStream_t s);
 
 // ---- launch wrappers (implemented in ptmg_kernels.hip) --------------------
 void launch_assemble(const AsmArgs &a, hipStream_t s);

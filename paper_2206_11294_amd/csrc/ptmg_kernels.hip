@@ -147,7 +147,37 @@ __global__ __launch_bounds__(kBlock) void k_assemble(AsmArgs a)
     double2 ac;
     double4 B;
     bool argbad = false;
-    if (a.mode == PT_COEF_PHASES) {
+    if (a.mode == PT_COEF_STATE) {
+        // each phase's block weighted by its fraction, written with the
+        // phase mass m_i = C_i rho_i so that nothing is divided by C_i:
+        // C_i Bpp = gamma (C_i - m_i b) / (Gamma (p + Pi) dt^2)  (Eq. 11 in
+        // gamma / (rho c^2)), C_i BpT = -C_i beta / dt^2, C_i BTp =
+        // -C_i beta T / dt, C_i BTT = m_i c_p / dt (Eqs. 29-32)
+        const double c = a.C[t], p = a.p_adv[t], T = a.T_adv[t];
+        const double frac[2] = {c, 1.0 - c}, mass[2] = {a.m1[t], a.m2[t]};
+        const pt_phase *ph[2] = {&a.liq, &a.gas};
+        argbad = !(c >= 0.0 && c <= 1.0) || !isfinite(p) || !(T > 0.0) || !isfinite(T);
+        B.x = B.y = B.z = B.w = 0.0;
+        const double idt = 1.0 / a.dt;
+        for (int q = 0; q < 2; q++) {
+            const pt_phase &f = *ph[q];
+            if (!(mass[q] >= 0.0)) argbad = true;
+            if (frac[q] <= 0.0) continue;
+            if (!(mass[q] > 0.0) || !(p + f.Pi > 0.0) || !(frac[q] - mass[q] * f.b > 0.0))
+                argbad = true;
+            double beta = f.beta;
+            if (!(beta > 0.0)) {
+                const double gcv = (f.Gamma - 1.0) * f.cv;
+                beta = gcv / (gcv * T + f.b * (p + f.Pi));
+            }
+            B.x += f.gamma * (frac[q] - mass[q] * f.b) / (f.Gamma * (p + f.Pi)) * idt * idt;
+            B.y += -frac[q] * beta * idt * idt;
+            B.z += -frac[q] * beta * T * idt;
+            B.w += mass[q] * f.cp * idt;
+        }
+        ac.x = 1.0 / (mass[0] + mass[1]);
+        ac.y = c * a.liq.k + (1.0 - c) * a.gas.k;
+    } else if (a.mode == PT_COEF_PHASES) {
         double c = a.C[t];
         double p = a.p_adv ? a.p_adv[t] : a.p_adv_const;
         double T = a.T_adv ? a.T_adv[t] : a.T_adv_const;
@@ -193,6 +223,43 @@ __global__ __launch_bounds__(kBlock) void k_assemble(AsmArgs a)
 void launch_assemble(const AsmArgs &a, hipStream_t s)
 {
     hipLaunchKernelGGL(k_assemble, dim3(nblk(a.N)), dim3(kBlock), 0, s, a);
+}
+
+// Provisional state (Eqs. 20, 23) from the advected conserved variables;
+// the phase averages are sums of fraction- and mass-weighted terms.
+__global__ __launch_bounds__(kBlock) void k_state(pt_state st)
+{
+    long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= st.n) return;
+    const double c = st.C[t];
+    const double frac[2] = {c, 1.0 - c}, mass[2] = {st.m1[t], st.m2[t]};
+    const pt_phase *ph[2] = {&st.liquid, &st.gas};
+    double e_static = 0.0, inv_gm1 = 0.0, vol = 0.0, vol_pi = 0.0, heat = 0.0;
+    for (int q = 0; q < 2; q++) {
+        const pt_phase &f = *ph[q];
+        const double free_vol = frac[q] - mass[q] * f.b;   // C_i (1 - rho_i b)
+        const double gpi = f.Gamma * f.Pi / (f.Gamma - 1.0);
+        e_static += gpi * free_vol + mass[q] * f.q;
+        inv_gm1 += free_vol / (f.Gamma - 1.0);
+        vol += free_vol;
+        vol_pi += f.Pi * free_vol;
+        heat += mass[q] * (f.cp - f.cv);
+    }
+    const double rho = mass[0] + mass[1];
+    double m2 = 0.0;
+    for (int d = 0; d < st.dim; d++) {
+        if (!st.mom[d]) continue;
+        const double m = st.mom[d][t];
+        m2 += m * m;
+    }
+    const double p = (st.E[t] - 0.5 * m2 / rho - e_static) / inv_gm1;
+    st.p_adv[t] = p;
+    st.T_adv[t] = (vol * p + vol_pi) / heat;
+}
+
+void launch_state(const pt_state &st, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_state, dim3(nblk(st.n)), dim3(kBlock), 0, s, st);
 }
 
 // Paper right-hand side (Eqs. 33-34) from the cell block:

@@ -269,7 +269,7 @@ int pt_server_submit(pt_server_t s, const pt_problem *prob, int precision, const
     const size_t hb = handle_plan_bytes(prob, precision);
     if (hb == 0) return sfail(s, PT_ERR_ARG, "invalid problem");
     if ((b_p == nullptr) != (b_T == nullptr)) return sfail(s, PT_ERR_ARG, "give both b_p and b_T or neither");
-    if (!b_p && prob->mode != PT_COEF_PHASES)
+    if (!b_p && prob->mode == PT_COEF_EXPLICIT)
         return sfail(s, PT_ERR_ARG, "explicit mode needs its right-hand side");
     Request r;
     r.id = s->next_id++;

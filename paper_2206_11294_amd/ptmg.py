@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libptmg.so")
 PT_OK, PT_ERR_ARG, PT_ERR_OOM, PT_ERR_SINGULAR, PT_ERR_NOCONV, PT_ERR_HIP, PT_ERR_STATE = range(7)
 STATUS_NAMES = {0: "PT_OK", 1: "PT_ERR_ARG", 2: "PT_ERR_OOM", 3: "PT_ERR_SINGULAR",
                 4: "PT_ERR_NOCONV", 5: "PT_ERR_HIP", 6: "PT_ERR_STATE"}
-PT_COEF_EXPLICIT, PT_COEF_PHASES = 0, 1
+PT_COEF_EXPLICIT, PT_COEF_PHASES, PT_COEF_STATE = 0, 1, 2
 PT_PREC_FP64, PT_PREC_MIXED = 0, 1
 PT_MAX_HIST = 64
 PT_OPT_GRAPHS, PT_OPT_TAIL, PT_OPT_FUSED, PT_OPT_TIMING_EVERY, PT_OPT_SPECULATE = 1, 2, 3, 4, 5
@@ -35,7 +35,7 @@ class PtMgError(RuntimeError):
 
 class pt_phase(ctypes.Structure):
     _fields_ = [(f, ctypes.c_double) for f in
-                ("rho", "k", "cp", "cv", "c", "gamma", "Gamma", "Pi", "b", "beta")]
+                ("rho", "k", "cp", "cv", "c", "gamma", "Gamma", "Pi", "b", "beta", "q")]
 
 
 _Dp = ctypes.c_void_p
@@ -52,6 +52,16 @@ class pt_problem(ctypes.Structure):
         ("p_adv", _Dp), ("T_adv", _Dp),
         ("p_adv_const", ctypes.c_double), ("T_adv_const", ctypes.c_double),
         ("mean_constraint", ctypes.c_int),
+        ("m1", _Dp), ("m2", _Dp),
+    ]
+
+
+class pt_state(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int), ("n", ctypes.c_longlong),
+        ("C", _Dp), ("m1", _Dp), ("m2", _Dp), ("E", _Dp), ("mom", _Dp * 3),
+        ("liquid", pt_phase), ("gas", pt_phase),
+        ("p_adv", _Dp), ("T_adv", _Dp),
     ]
 
 
@@ -82,6 +92,7 @@ def lib() -> ctypes.CDLL:
         P = ctypes.POINTER
         sig = {
             "pt_mg_footprint_bytes": (ctypes.c_size_t, [P(pt_problem), c_int]),
+            "pt_state_eval": (c_int, [P(pt_state), c_void]),
             "pt_mg_setup": (c_int, [P(pt_problem), c_int, c_void, P(c_void)]),
             "pt_mg_update": (c_int, [c_void, P(pt_problem)]),
             "pt_mg_paper_rhs": (c_int, [c_void] + [c_void] * 5),
@@ -120,7 +131,7 @@ def lib() -> ctypes.CDLL:
 def exported_symbols() -> Sequence[str]:
     """Names of the C-ABI functions the binding uses."""
     lib()
-    return ["pt_mg_footprint_bytes", "pt_mg_setup", "pt_mg_update", "pt_mg_paper_rhs",
+    return ["pt_state_eval", "pt_mg_footprint_bytes", "pt_mg_setup", "pt_mg_update", "pt_mg_paper_rhs",
             "pt_mg_solve", "pt_mg_residual", "pt_mg_destroy", "pt_mg_last_error",
             "pt_mg_num_levels", "pt_mg_level_dims", "pt_mg_get_operator", "pt_mg_smooth",
             "pt_mg_restrict_residual", "pt_mg_prolong_add", "pt_mg_coarse_solve",
@@ -149,6 +160,14 @@ def phase_struct(rho, k, cp, cv, c, gamma, Gamma, Pi, b, beta=0.0) -> pt_phase:
 
 def footprint_bytes(prob: pt_problem, precision: int) -> int:
     return int(lib().pt_mg_footprint_bytes(ctypes.byref(prob), precision))
+
+
+def state_eval(st: pt_state, stream=None) -> None:
+    """pt_state_eval: provisional (p, T) into st.p_adv, st.T_adv (device
+    tensors the caller keeps alive), asynchronous on `stream`."""
+    rc = lib().pt_state_eval(ctypes.byref(st), _stream_ptr(stream))
+    if rc:
+        raise PtMgError(rc, lib().pt_mg_last_error(None).decode())
 
 
 def copy_kernel(dst: torch.Tensor, src: torch.Tensor, nbytes: int, stream=None) -> None:

@@ -40,6 +40,25 @@ def to_device(prob: Problem, device="cuda") -> Tuple[ptmg.pt_problem, Dict[str, 
         s.mean_constraint = int(prob.mean_constraint)
         t["f_p"] = _dev(prob.f_p, device)
         t["f_T"] = _dev(prob.f_T, device)
+    elif prob.mode == "state":
+        # conserved variables in; p_adv, T_adv from the library's kernel
+        s.mode = ptmg.PT_COEF_STATE
+        for key in ("C", "m1", "m2", "E"):
+            t[key] = _dev(getattr(prob, key), device)
+        for a, m in enumerate(prob.mom or []):
+            t[f"mom{a}"] = _dev(m, device)
+        t["p_adv"] = torch.empty_like(t["C"])
+        t["T_adv"] = torch.empty_like(t["C"])
+        st = state_record(prob, t)
+        ptmg.state_eval(st, torch.cuda.current_stream())
+        torch.cuda.current_stream().synchronize()   # other streams may read p_adv, T_adv
+        s.C, s.m1, s.m2 = (t[k].data_ptr() for k in ("C", "m1", "m2"))
+        s.p_adv, s.T_adv = t["p_adv"].data_ptr(), t["T_adv"].data_ptr()
+        s.liquid = _ph(prob.liquid)
+        s.gas = _ph(prob.gas)
+        s.dt = prob.dt
+        if prob.div_ustar is not None:
+            t["div"] = _dev(prob.div_ustar, device)
     else:
         s.mode = ptmg.PT_COEF_PHASES
         t["C"] = _dev(prob.C, device)
@@ -58,6 +77,21 @@ def to_device(prob: Problem, device="cuda") -> Tuple[ptmg.pt_problem, Dict[str, 
         if prob.div_ustar is not None:
             t["div"] = _dev(prob.div_ustar, device)
     return s, t
+
+
+def state_record(prob: Problem, t: Dict[str, torch.Tensor]) -> ptmg.pt_state:
+    """pt_state record over the device tensors of a state-mode problem."""
+    st = ptmg.pt_state()
+    st.dim = prob.dim
+    st.n = prob.ncells
+    st.C, st.m1, st.m2, st.E = (t[k].data_ptr() for k in ("C", "m1", "m2", "E"))
+    for a in range(3):
+        key = f"mom{a}"
+        st.mom[a] = t[key].data_ptr() if key in t else None
+    st.liquid = _ph(prob.liquid)
+    st.gas = _ph(prob.gas)
+    st.p_adv, st.T_adv = t["p_adv"].data_ptr(), t["T_adv"].data_ptr()
+    return st
 
 
 def precision_code(prob: Problem) -> int:
