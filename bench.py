@@ -43,14 +43,16 @@ WORKLOADS = {
 }
 
 
-def make_problem(name):
+def make_problem(name, stiff=False):
     import workloads as W
+    if stiff and name not in ("bubble2d_1024", "wall3d_256"):
+        raise SystemExit("--stiff applies to bubble2d_1024 and wall3d_256")
     if name == "explicit_64":
         return W.explicit_const(64, 64)
     if name == "bubble2d_1024":
-        return W.bubble2d(1024)
+        return W.bubble2d(1024, stiff=stiff)
     if name == "wall3d_256":
-        return W.wall3d(256)
+        return W.wall3d(256, stiff=stiff)
     if name == "collapse3d_512":
         return W.collapse3d(512)
     if name == "state2d_1024":
@@ -292,6 +294,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="bubble2d_1024", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", choices=["fp64", "mixed"], default=None)
+    ap.add_argument("--method", choices=["defect", "bicgstab"], default="defect",
+                    help="outer iteration: the defect-correction loop of Sec. 3, or "
+                         "BiCGStab with the V-cycle as preconditioner")
+    ap.add_argument("--stiff", action="store_true",
+                    help="diffusive-CFL time step (bubble workloads)")
     ap.add_argument("--rtol", type=float, default=None)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -335,7 +342,8 @@ def main():
     prec_name = args.precision or prec_default
     rtol = args.rtol if args.rtol is not None else rtol_default
     prec = ptmg.PT_PREC_MIXED if prec_name == "mixed" else ptmg.PT_PREC_FP64
-    prob = make_problem(name)
+    prob = make_problem(name, args.stiff)
+    method = ptmg.PT_SOLVE_BICGSTAB if args.method == "bicgstab" else ptmg.PT_SOLVE_DEFECT
     print(f"# workload {name} grid {prob.n} precision {prec_name} rtol {rtol:g}",
           file=sys.stderr, flush=True)
 
@@ -361,7 +369,7 @@ def main():
                 b_p, b_T = h.paper_rhs(tens.get("p_adv"), tens.get("T_adv"), tens.get("div"))
             else:
                 b_p, b_T = tens["f_p"], tens["f_T"]
-            info = h.solve(b_p, b_T, p, T, rtol=rtol, max_cycles=50)
+            info = h.solve(b_p, b_T, p, T, rtol=rtol, max_cycles=120, method=method)
             return info, b_p, b_T
 
         for _ in range(args.warmup):
@@ -414,7 +422,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": name, "grid": list(prob.n[: prob.dim]), "precision": prec_name,
                    "rtol": rtol, "cycles_per_solve": float(np.mean(cycles)),
-                   "step": "pt_mg_update + pt_mg_paper_rhs + pt_mg_solve",
+                   "step": ("pt_state_eval + " if prob.mode == "state" else "")
+                   + "pt_mg_update + pt_mg_paper_rhs + pt_mg_solve",
+                   "method": args.method, "time_step": "diffusive" if args.stiff else "acoustic",
                    "parallelism": "single GPU"},
         "roofline": roofline,
         "upstream": upstream_line(prob, state_ms),

@@ -124,7 +124,20 @@ typedef struct {
     int max_cycles;          /* V-cycles at most (<= PT_MAX_HIST - 1 recorded) */
     int nu1, nu2;            /* pre/post red-black smoothing sweeps (0..8) */
     int zero_guess;          /* 1: start from zero, ignoring the contents of p, T */
+    /* PT_SOLVE_DEFECT (0): the defect-correction loop of Sec. 3 (residual,
+     * test, V-cycle on the correction, update).  PT_SOLVE_BICGSTAB (1):
+     * BiCGStab on the canonical system with the V-cycle as right
+     * preconditioner, for time steps far above the acoustic one where the
+     * plain loop contracts slowly; same stop test (paper row form, true
+     * FP64 residual every iteration), max_cycles counts V-cycles (two per
+     * iteration).  BiCGStab is synchronous (pt_mg_solve only), does not take
+     * the mean constraint, and its first use on a handle allocates 8 FP64
+     * work vectors of 2N doubles, kept until pt_mg_destroy. */
+    int method;
 } pt_solve_opts;
+
+#define PT_SOLVE_DEFECT 0
+#define PT_SOLVE_BICGSTAB 1
 
 #define PT_MAX_HIST 64
 

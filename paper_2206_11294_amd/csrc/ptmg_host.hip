@@ -176,6 +176,7 @@ struct pt_mg_s {
     int *flags_host = nullptr;      // pinned
     std::string err = "no error";
     double *Ainv = nullptr;
+    double *kry = nullptr;          // Krylov work vectors (allocated on first use)
     bool ready = false;
     bool owns_memory = true;        // false: device + pinned memory belong to a server arena
     hipEvent_t done_ev = nullptr;   // marks the end of the last enqueued step
@@ -955,6 +956,7 @@ void pt_mg_destroy(pt_mg_t h)
     for (auto ev : h->norm_ev)
         if (ev) (void)hipEventDestroy(ev);
     for (auto e : h->ev_all) (void)hipEventDestroy(e);
+    if (h->kry) (void)hipFree(h->kry);
     if (h->owns_memory) {
         if (h->base) (void)hipFree(h->base);
         if (h->norms_host) (void)hipHostFree(h->norms_host);
@@ -984,10 +986,13 @@ namespace {
 template <typename RV>
 int outer(pt_mg_t h, const double *b_p, const double *b_T, const double *src_p,
           const double *src_T, double *dst_p, double *dst_T, bool update, bool want_r,
-          double *res_p, double *res_T, const double *bshift)
+          double *res_p, double *res_T, const double *bshift, double *r64_p = nullptr,
+          double *r64_T = nullptr)
 {
     const Plan &P = h->P;
     OuterArgs<RV> a;
+    a.r64_p = r64_p;
+    a.r64_T = r64_T;
     a.nx = P.n[0];
     a.ny = P.n[1];
     a.nz = P.n[2];
@@ -1025,13 +1030,14 @@ int outer(pt_mg_t h, const double *b_p, const double *b_T, const double *src_p,
 
 int outer_any(pt_mg_t h, const double *b_p, const double *b_T, const double *src_p,
               const double *src_T, double *dst_p, double *dst_T, bool update, bool want_r,
-              double *res_p, double *res_T, const double *bshift)
+              double *res_p, double *res_T, const double *bshift, double *r64_p = nullptr,
+              double *r64_T = nullptr)
 {
     if (h->P.prec == PT_PREC_MIXED)
         return outer<float>(h, b_p, b_T, src_p, src_T, dst_p, dst_T, update, want_r, res_p, res_T,
-                            bshift);
+                            bshift, r64_p, r64_T);
     return outer<double>(h, b_p, b_T, src_p, src_T, dst_p, dst_T, update, want_r, res_p, res_T,
-                         bshift);
+                         bshift, r64_p, r64_T);
 }
 
 // Reduce the partial sums to 4 doubles written straight into pinned host
@@ -1137,11 +1143,13 @@ int solve_begin(pt_mg_t h, const double *b_p, const double *b_T, double *p, doub
 {
     if (!h || !h->ready) return fail(h, PT_ERR_STATE, "handle not ready");
     if (!b_p || !b_T || !p || !T) return fail(h, PT_ERR_ARG, "NULL field");
-    pt_solve_opts o = {1e-9, 50, 2, 2, 1};
+    pt_solve_opts o = {1e-9, 50, 2, 2, 1, PT_SOLVE_DEFECT};
     if (opts_in) o = *opts_in;
     if (!(o.rtol >= 0) || o.max_cycles < 0 || o.nu1 < 0 || o.nu2 < 0 || o.nu1 > 8 || o.nu2 > 8 ||
         o.nu1 + o.nu2 == 0)
         return fail(h, PT_ERR_ARG, "bad solve options");
+    if (o.method != PT_SOLVE_DEFECT)
+        return fail(h, PT_ERR_ARG, "only the defect-correction loop runs asynchronously");
     const Plan &P = h->P;
     auto &S = h->sv;
     S = pt_mg_s::Solve();
@@ -1265,9 +1273,22 @@ int solve_advance(pt_mg_t h, pt_solve_info *info)
 
 }  // namespace ptmg
 
+static int krylov_solve(pt_mg_t h, const double *b_p, const double *b_T, double *p, double *T,
+                        const pt_solve_opts &o, pt_solve_info *info);
+
 int pt_mg_solve(pt_mg_t h, const double *b_p, const double *b_T, double *p, double *T,
                 const pt_solve_opts *opts_in, pt_solve_info *info)
 {
+    if (opts_in && opts_in->method == PT_SOLVE_BICGSTAB) {
+        if (!h || !h->ready) return fail(h, PT_ERR_STATE, "handle not ready");
+        if (!b_p || !b_T || !p || !T) return fail(h, PT_ERR_ARG, "NULL field");
+        const pt_solve_opts &o = *opts_in;
+        if (!(o.rtol >= 0) || o.max_cycles < 0 || o.nu1 < 0 || o.nu2 < 0 || o.nu1 > 8 ||
+            o.nu2 > 8 || o.nu1 + o.nu2 == 0)
+            return fail(h, PT_ERR_ARG, "bad solve options");
+        return krylov_solve(h, b_p, b_T, p, T, o, info);
+    }
+    if (opts_in && opts_in->method != PT_SOLVE_DEFECT) return fail(h, PT_ERR_ARG, "unknown method");
     int rc = solve_begin(h, b_p, b_T, p, T, opts_in);
     if (rc != PT_OK) return rc;
     for (;;) {
@@ -1332,6 +1353,165 @@ template <typename R> void unpack_lv(pt_mg_t h, int l, bool f, double *x, double
         if ((h)->P.prec == PT_PREC_MIXED) { using R = float; CALL; } \
         else { using R = double; CALL; }                        \
     } while (0)
+
+// BiCGStab (van der Vorst) on the canonical system A x = f with the
+// V-cycle as right preconditioner.  The residual is recomputed from x in
+// FP64 every iteration (the outer-residual kernel, which also gives the
+// paper-row-form norms of the stop test).  Vectors are FP64 pairs (p, T)
+// in h->kry; "neg" vectors hold -A y, as the residual kernel returns them
+// for a zero right-hand side.  Dot products are fixed-order reductions.
+static int krylov_solve(pt_mg_t h, const double *b_p, const double *b_T, double *p, double *T,
+                        const pt_solve_opts &o, pt_solve_info *info)
+{
+    const Plan &P = h->P;
+    const long long N = P.N;
+    if (h->prob.mean_constraint)
+        return fail(h, PT_ERR_ARG, "BiCGStab does not take the mean constraint");
+    if (!h->owns_memory) return fail(h, PT_ERR_STATE, "BiCGStab needs a handle with its own memory");
+    if (!h->kry) {
+        hipError_t e = hipMalloc(&h->kry, sizeof(double) * 16 * (size_t)N);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            h->kry = nullptr;
+            return fail(h, PT_ERR_OOM, "BiCGStab work vectors");
+        }
+    }
+    enum { R = 0, RH, PV, VN, SV, TN, PH, SH };
+    auto vp = [&](int k) { return h->kry + 2 * N * k; };
+    auto vT = [&](int k) { return h->kry + 2 * N * k + N; };
+    const auto t0 = std::chrono::steady_clock::now();
+    pt_solve_info inf;
+    std::memset(&inf, 0, sizeof inf);
+    h->updates = 0;
+    hipStream_t st = h->stream;
+    if (o.zero_guess) {
+        launch_zero(p, 8 * (size_t)N, st);
+        launch_zero(T, 8 * (size_t)N, st);
+    }
+    int rc = PT_OK;
+    double rel[2] = {0, 0};
+    // r = f - A x in FP64 (canonical), paper-form relative norms
+    auto true_residual = [&]() {
+        int nb = outer_any(h, b_p, b_T, p, T, nullptr, nullptr, false, false, nullptr, nullptr,
+                           nullptr, vp(R), vT(R));
+        rc = enqueue_norms(h, nb, 0);
+        if (rc == PT_OK) rc = sync(h, "BiCGStab residual");
+        if (rc) return;
+        const double *s = h->norms_host;
+        rel[0] = s[2] > 0 ? std::sqrt(s[0] / s[2]) : std::sqrt(s[0]);
+        rel[1] = s[3] > 0 ? std::sqrt(s[1] / s[3]) : std::sqrt(s[1]);
+        if (inf.hist_len < PT_MAX_HIST) {
+            inf.relres_hist[2 * inf.hist_len] = rel[0];
+            inf.relres_hist[2 * inf.hist_len + 1] = rel[1];
+            inf.hist_len++;
+        }
+    };
+    double d[2];
+    auto dot2 = [&](int x, int y, int z, int w) {
+        h->begin(PT_K_OTHER, 8.0 * 4 * N * (z >= 0 ? 2 : 1));
+        int nb = launch_dot2(N, vp(x), vT(x), vp(y), vT(y), z >= 0 ? vp(z) : nullptr,
+                             z >= 0 ? vT(z) : nullptr, z >= 0 ? vp(w) : nullptr,
+                             z >= 0 ? vT(w) : nullptr, h->partials(), st);
+        launch_reduce4(h->partials(), nb, h->norms_devp + 8, st);
+        h->end();
+        rc = sync(h, "BiCGStab dot");
+        d[0] = h->norms_host[8];
+        d[1] = h->norms_host[9];
+    };
+    auto lin3 = [&](double *op, double *oT, double a, int x, double b, int y, double c, int z) {
+        h->begin(PT_K_OTHER, 8.0 * 2 * N * (z >= 0 ? 4 : 3));
+        launch_lin3(N, op, oT, a, vp(x), vT(x), b, vp(y), vT(y), c, z >= 0 ? vp(z) : nullptr,
+                    z >= 0 ? vT(z) : nullptr, st);
+        h->end();
+    };
+    auto precond = [&](int in, int out) {
+        PT_DISPATCH(h, {
+            pack_lv<R>(h, 0, true, vp(in), vT(in));
+            vcycle<R>(h, 0, o.nu1, o.nu2);
+            unpack_lv<R>(h, 0, false, vp(out), vT(out));
+        });
+        inf.cycles++;
+    };
+    auto matvec_neg = [&](int in, int out) {
+        (void)outer_any(h, nullptr, nullptr, vp(in), vT(in), nullptr, nullptr, false, false,
+                        nullptr, nullptr, nullptr, vp(out), vT(out));
+    };
+    auto done = [&]() {
+        return rel[0] <= o.rtol && rel[1] <= o.rtol;
+    };
+    int status = PT_ERR_NOCONV;
+    true_residual();
+    if (rc) return rc;
+    if (done()) status = PT_OK;
+    if (status != PT_OK && std::isfinite(rel[0]) && std::isfinite(rel[1])) {
+        lin3(vp(RH), vT(RH), 1.0, R, 0.0, R, 0.0, -1);
+        launch_zero(vp(PV), 16 * (size_t)N, st);
+        launch_zero(vp(VN), 16 * (size_t)N, st);
+        double rho = 1.0, alpha = 1.0, omega = 1.0;
+        for (;;) {
+            if (inf.cycles + 2 > o.max_cycles) {
+                h->err = "max_cycles reached";
+                break;
+            }
+            dot2(RH, R, -1, -1);
+            if (rc) return rc;
+            const double rho1 = d[0];
+            if (!(std::isfinite(rho1)) || rho1 == 0.0) {
+                h->err = "BiCGStab breakdown (rho)";
+                break;
+            }
+            const double beta = (rho1 / rho) * (alpha / omega);
+            // p = r + beta (p - omega A p^), A p^ = -VN
+            lin3(vp(PV), vT(PV), 1.0, R, beta, PV, beta * omega, VN);
+            precond(PV, PH);
+            matvec_neg(PH, VN);
+            dot2(RH, VN, -1, -1);
+            if (rc) return rc;
+            const double rAp = -d[0];
+            if (!(std::isfinite(rAp)) || rAp == 0.0) {
+                h->err = "BiCGStab breakdown (r^ . A p)";
+                break;
+            }
+            alpha = rho1 / rAp;
+            lin3(vp(SV), vT(SV), 1.0, R, alpha, VN, 0.0, -1);   // s = r - alpha A p^
+            precond(SV, SH);
+            matvec_neg(SH, TN);
+            dot2(TN, SV, TN, TN);
+            if (rc) return rc;
+            omega = d[1] > 0.0 ? -d[0] / d[1] : 0.0;             // (A s^ . s) / |A s^|^2
+            // x += alpha p^ + omega s^
+            h->begin(PT_K_OTHER, 8.0 * 2 * N * 4);
+            launch_lin3(N, p, T, 1.0, p, T, alpha, vp(PH), vT(PH), omega, vp(SH), vT(SH), st);
+            h->end();
+            true_residual();
+            if (rc) return rc;
+            if (!std::isfinite(rel[0]) || !std::isfinite(rel[1])) {
+                h->err = "residual norm is not finite";
+                break;
+            }
+            if (done()) {
+                status = PT_OK;
+                break;
+            }
+            if (omega == 0.0) {
+                h->err = "BiCGStab breakdown (omega)";
+                break;
+            }
+            rho = rho1;
+        }
+    } else if (status != PT_OK) {
+        h->err = "residual norm is not finite";
+    }
+    rc = sync(h, "BiCGStab");
+    if (rc) return rc;
+    h->last_updates = h->updates;
+    inf.relres[0] = rel[0];
+    inf.relres[1] = rel[1];
+    inf.t_solve_s = elapsed(t0);
+    inf.status = status;
+    if (info) *info = inf;
+    return status;
+}
 
 int pt_mg_smooth(pt_mg_t h, int level, const double *f_p, const double *f_T, double *u_p,
                  double *u_T, int sweeps)

@@ -38,7 +38,7 @@ template <typename RV> struct OuterArgs {
     int phases;                    // 1: paper form (b = (lp, lT)), 0: canonical
     const double2 *ac;             // FP64 cell coefficients
     const double4 *B;              // FP64 block
-    const double *b_p, *b_T;       // mode-native right-hand side
+    const double *b_p, *b_T;       // mode-native right-hand side (null: zero)
     const double *bshift;          // [2] sums of b (mean constraint) or null
     double bshift_scale;           // b -= bshift_scale * bshift (1/N: the mean)
     const double *src_p, *src_T;   // current iterate
@@ -46,6 +46,7 @@ template <typename RV> struct OuterArgs {
     const typename VT<RV>::v2 *du; // correction of the last V-cycle (update = 1)
     typename VT<RV>::v2 *r;        // canonical residual out (V-cycle RHS) or null
     double *res_p, *res_T;         // mode-native residual out or null
+    double *r64_p, *r64_T;         // canonical residual out in FP64 or null
     double *partials;              // [4 * gridDim.x]: sum res_p^2, res_T^2, b_p^2, b_T^2
     int update;
 };
@@ -92,6 +93,18 @@ template <typename R> struct TailArgs {
 
 // Provisional state (Eqs. 20, 23) of n cells.
 void launch_state(const pt_state &st, hipStream_t s);
+
+// Krylov vector kernels (FP64 pairs of arrays p, T of N cells).
+// out = a x + b y (+ c z when z_p is not null); out may alias x, y or z.
+void launch_lin3(long long N, double *out_p, double *out_T, double a, const double *x_p,
+                 const double *x_T, double b, const double *y_p, const double *y_T, double c,
+                 const double *z_p, const double *z_T, hipStream_t s);
+// Two dot products d0 = <x, y>, d1 = <z, w> over both components, as
+// fixed-order partial sums [4 per block] (d0, d1, 0, 0) for launch_reduce4;
+// z_p null: d1 = 0.  Returns the block count.
+int launch_dot2(long long N, const double *x_p, const double *x_T, const double *y_p,
+                const double *y_T, const double *z_p, const double *z_T, const double *w_p,
+                const double *w_T, double *partials, hipStream_t s);
 
 // ---- launch wrappers (implemented in ptmg_kernels.hip) --------------------
 void launch_assemble(const AsmArgs &a, hipStream_t s);

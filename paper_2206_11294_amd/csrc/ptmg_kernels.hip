@@ -262,6 +262,59 @@ void launch_state(const pt_state &st, hipStream_t s)
     hipLaunchKernelGGL(k_state, dim3(nblk(st.n)), dim3(kBlock), 0, s, st);
 }
 
+// ---------------------------------------------- Krylov vector kernels
+__global__ __launch_bounds__(kBlock) void k_lin3(long long N, double *op, double *oT, double a,
+                                                 const double *xp, const double *xT, double b,
+                                                 const double *yp, const double *yT, double c,
+                                                 const double *zp, const double *zT)
+{
+    long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= N) return;
+    double vp = a * xp[t] + b * yp[t];
+    double vT = a * xT[t] + b * yT[t];
+    if (zp) {
+        vp += c * zp[t];
+        vT += c * zT[t];
+    }
+    op[t] = vp;
+    oT[t] = vT;
+}
+
+void launch_lin3(long long N, double *out_p, double *out_T, double a, const double *x_p,
+                 const double *x_T, double b, const double *y_p, const double *y_T, double c,
+                 const double *z_p, const double *z_T, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_lin3, dim3(nblk(N)), dim3(kBlock), 0, s, N, out_p, out_T, a, x_p, x_T,
+                       b, y_p, y_T, c, z_p, z_T);
+}
+
+// Grid-strided over a fixed block count, so the partial sums (and the
+// fixed-order reduction after them) do not depend on timing.
+__global__ __launch_bounds__(kBlock) void k_dot2(long long N, const double *xp, const double *xT,
+                                                 const double *yp, const double *yT,
+                                                 const double *zp, const double *zT,
+                                                 const double *wp, const double *wT,
+                                                 double *partials)
+{
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    const long long stride = (long long)gridDim.x * kBlock;
+    for (long long t = (long long)blockIdx.x * kBlock + threadIdx.x; t < N; t += stride) {
+        v[0] += xp[t] * yp[t] + xT[t] * yT[t];
+        if (zp) v[1] += zp[t] * wp[t] + zT[t] * wT[t];
+    }
+    block_reduce_store(v, 4, partials + 4ll * blockIdx.x);
+}
+
+int launch_dot2(long long N, const double *x_p, const double *x_T, const double *y_p,
+                const double *y_T, const double *z_p, const double *z_T, const double *w_p,
+                const double *w_T, double *partials, hipStream_t s)
+{
+    const int nb = sum2_blocks(N);
+    hipLaunchKernelGGL(k_dot2, dim3(nb), dim3(kBlock), 0, s, N, x_p, x_T, y_p, y_T, z_p, z_T,
+                       w_p, w_T, partials);
+    return nb;
+}
+
 // Paper right-hand side (Eqs. 33-34) from the cell block:
 // l1 = -BTT, l2 = -BTp, l4 = BpT / l1, l3 = -Bpp + l4 l2.
 __global__ __launch_bounds__(kBlock) void k_paper_rhs(long long N, const double4 *B64,
@@ -2152,8 +2205,8 @@ __global__ __launch_bounds__(TX *TY) void k_outer_zm(OuterArgs<RV> a, int NX, in
             if (mine && z < z1) {
                 const long long g = gx + (long long)NX * gy + nxy * z;
                 Bn = a.B[g];
-                bpn = a.b_p[g];
-                bTn = a.b_T[g];
+                bpn = a.b_p ? a.b_p[g] : 0.0;
+                bTn = a.b_T ? a.b_T[g] : 0.0;
             }
         };
         fetch(z0 - 1);
@@ -2225,6 +2278,10 @@ __global__ __launch_bounds__(TX *TY) void k_outer_zm(OuterArgs<RV> a, int NX, in
                 }
                 if (a.res_p) a.res_p[g] = resp;
                 if (a.res_T) a.res_T[g] = resT;
+                if (a.r64_p) {
+                    a.r64_p[g] = rp;
+                    a.r64_T[g] = rT;
+                }
                 acc[0] += resp * resp;
                 acc[1] += resT * resT;
                 acc[2] += bp * bp;

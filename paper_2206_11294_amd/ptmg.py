@@ -67,7 +67,11 @@ class pt_state(ctypes.Structure):
 
 class pt_solve_opts(ctypes.Structure):
     _fields_ = [("rtol", ctypes.c_double), ("max_cycles", ctypes.c_int),
-                ("nu1", ctypes.c_int), ("nu2", ctypes.c_int), ("zero_guess", ctypes.c_int)]
+                ("nu1", ctypes.c_int), ("nu2", ctypes.c_int), ("zero_guess", ctypes.c_int),
+                ("method", ctypes.c_int)]
+
+
+PT_SOLVE_DEFECT, PT_SOLVE_BICGSTAB = 0, 1
 
 
 class pt_solve_info(ctypes.Structure):
@@ -222,8 +226,8 @@ class PtMg:
         return b_p, b_T
 
     def solve(self, b_p, b_T, p, T, rtol=1e-9, max_cycles=50, nu1=2, nu2=2,
-              zero_guess=True, raise_on_noconv=True) -> Dict:
-        opts = pt_solve_opts(rtol, max_cycles, nu1, nu2, int(zero_guess))
+              zero_guess=True, raise_on_noconv=True, method=PT_SOLVE_DEFECT) -> Dict:
+        opts = pt_solve_opts(rtol, max_cycles, nu1, nu2, int(zero_guess), int(method))
         info = pt_solve_info()
         rc = lib().pt_mg_solve(self._h, _ptr(b_p), _ptr(b_T), _ptr(p), _ptr(T),
                                ctypes.byref(opts), ctypes.byref(info))
