@@ -56,6 +56,7 @@ _D = ctypes.POINTER(ctypes.c_double)
 _I = ctypes.POINTER(ctypes.c_int)
 _L = ctypes.POINTER(ctypes.c_long)
 _P = ctypes.POINTER(_Phase)
+_PP = ctypes.POINTER(_D)
 
 
 def _declare(lib):
@@ -89,6 +90,11 @@ def _declare(lib):
         "orc_mg_solve": (c_int, [c_int, _I, c_double, _D, _D, _D, _D, _D, _D, _D, _D, _D,
                                  c_double, c_int, c_int, c_int, c_int, _D]),
         "orc_mg_levels": (c_int, [c_int, _I]),
+        "orc_divergence": (None, [c_int, _I, c_double, _PP, _D]),
+        "orc_project": (None, [c_int, _I, c_double, c_double, _D, _D, _PP, _PP, _PP, _PP]),
+        "orc_phase_pressures": (None, [c_long, _D, _D, _D, c_double, _D, _D]),
+        "orc_energy_update": (None, [c_int, _I, c_double, c_double, _D, _D, _D, _D, _D, _PP,
+                                     _D, _D, _D, _D]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -101,6 +107,15 @@ def _d(a: Optional[np.ndarray]):
         return ctypes.cast(None, _D)
     assert a.dtype == np.float64 and a.flags.c_contiguous
     return a.ctypes.data_as(_D)
+
+
+def _dp(arrays):
+    """Array of three double pointers (NULL where an axis is absent)."""
+    if arrays is None:
+        return ctypes.cast(None, _PP)
+    ptrs = [_d(a) if a is not None else ctypes.cast(None, _D) for a in arrays]
+    ptrs += [ctypes.cast(None, _D)] * (3 - len(ptrs))
+    return (_D * 3)(*ptrs)
 
 
 def _f64(a) -> np.ndarray:
@@ -245,6 +260,8 @@ def paper_rhs(op: Operator, prob) -> Tuple[np.ndarray, np.ndarray]:
     if op.p_adv is not None:
         p_adv, T_adv = op.p_adv, op.T_adv
     div = None if prob.div_ustar is None else _f64(prob.div_ustar)
+    if div is None and getattr(prob, "uf_star", None) is not None:
+        div = divergence(prob.dim, prob.n, prob.h, prob.uf_star)
     _load().orc_paper_rhs(N, _d(lam), _d(p_adv), prob.p_adv_const, _d(T_adv),
                           prob.T_adv_const, _d(div), prob.dt, _d(b_p), _d(b_T))
     return b_p, b_T
@@ -455,3 +472,66 @@ def solve(prob, rtol: float = 1e-13, max_cycles: int = 200, direct_max: int = 70
         if cyc < 0:
             raise RuntimeError("oracle multigrid did not converge")
     return op, b_p, b_T, p, T
+
+
+# ---------------------------------------------------------------------------
+# after the solve: velocity correction and phase energies (Sec. 3)
+# ---------------------------------------------------------------------------
+def face_shape(dim, n, a) -> Tuple[int, ...]:
+    """Array shape (x last) of the faces across axis a: n_a + 1 along a."""
+    m = [int(v) for v in n[:dim]]
+    m[a] += 1
+    return tuple(m[dim - 1 - b] for b in range(dim))
+
+
+def divergence(dim, n, h, U) -> np.ndarray:
+    """Discrete div of face velocities U[a] (the div u* of Eqs. 17, 34)."""
+    Us = [_f64(u) for u in U]
+    out = np.zeros(int(n[0]) * int(n[1]) * int(n[2]))
+    _load().orc_divergence(dim, _dims(n), h, _dp(Us), _d(out))
+    return out
+
+
+def project(op: Operator, dt: float, p, U_star, u_star=None):
+    """Eq. (unp1): face velocities (and, with u_star, cell velocities) after
+    the correction by the pressure gradient.  Returns (U, u or None)."""
+    Us = [_f64(u) for u in U_star]
+    U = [np.zeros_like(u) for u in Us]
+    cs = None if u_star is None else [_f64(u) for u in u_star]
+    c = None if cs is None else [np.zeros_like(u) for u in cs]
+    F, _ = _fb(op)
+    _load().orc_project(op.dim, _dims(op.n), op.h, dt, _d(F), _d(_f64(p)), _dp(Us), _dp(U),
+                        _dp(cs), _dp(c))
+    return U, c
+
+
+def phase_pressures(p, C, kappa=None, sigma: float = 0.0):
+    """Eqs. (37)-(38)."""
+    p, C = _f64(p), _f64(C)
+    p1, p2 = np.zeros_like(p), np.zeros_like(p)
+    _load().orc_phase_pressures(p.size, _d(p), _d(C), _d(None if kappa is None else _f64(kappa)),
+                                sigma, _d(p1), _d(p2))
+    return p1, p2
+
+
+def energy_update(op: Operator, dt: float, C, p1, p2, T, U, E1_adv, E2_adv):
+    """Eq. (39), inviscid.  Returns (E1, E2)."""
+    E1a, E2a = _f64(E1_adv), _f64(E2_adv)
+    E1, E2 = np.zeros_like(E1a), np.zeros_like(E2a)
+    F, _ = _fb(op)
+    Us = [_f64(u) for u in U]
+    _load().orc_energy_update(op.dim, _dims(op.n), op.h, dt, _d(F), _d(_f64(C)), _d(_f64(p1)),
+                              _d(_f64(p2)), _d(_f64(T)), _dp(Us), _d(E1a), _d(E2a), _d(E1),
+                              _d(E2))
+    return E1, E2
+
+
+def downstream(op: Operator, dt: float, p, T, C, U_star, E1_adv, E2_adv, u_star=None,
+               kappa=None, sigma: float = 0.0):
+    """The end of the step in the paper's order: velocity correction
+    (Eq. unp1), phase pressures (Eqs. 37-38), phase energies (Eq. 39).
+    Returns dict(U, u, p1, p2, E1, E2)."""
+    U, u = project(op, dt, p, U_star, u_star)
+    p1, p2 = phase_pressures(p, C, kappa, sigma)
+    E1, E2 = energy_update(op, dt, C, p1, p2, T, U, E1_adv, E2_adv)
+    return {"U": U, "u": u, "p1": p1, "p2": p2, "E1": E1, "E2": E2}

@@ -36,6 +36,11 @@
  * cites its multigrid; these choices change the speed, not the converged
  * result.  The step functions (red-black sweep, restriction, prolongation,
  * coarse operator) are exported for step-by-step comparisons.
+ *
+ * Also here: the provisional state from the advected conserved variables
+ * (Eqs. 20, 23) and the end of the step that consumes the solution: the
+ * velocity correction (Eq. unp1) on faces and at cell centres, the phase
+ * pressures (Eqs. 37-38) and the phase total energies (Eq. 39).
  */
 #include <math.h>
 #include <stdlib.h>
@@ -808,4 +813,150 @@ int orc_mg_levels(int dim, const int *n)
     int m[3] = {n[0], n[1], n[2]}, l = 1;
     while (can_coarsen(dim, m)) { int c[3]; coarse_dims(dim, m, c); memcpy(m, c, sizeof m); l++; }
     return l;
+}
+
+/* ------------------------------------------------------------------ */
+/* after the solve: velocity correction and phase energies (Sec. 3)    */
+/* ------------------------------------------------------------------ */
+
+/* Face velocities: U[a] holds the velocity component normal to the faces
+ * across axis a.  There are n_a + 1 faces along a (both walls included)
+ * and n_b along every other axis b; face (i,j,k) is the lower face of cell
+ * (i,j,k).  Index i + m0*(j + m1*k) with m_b = n_b + (b == a). */
+static long fidx(const int *n, int a, long i, long j, long k)
+{
+    long m0 = n[0] + (a == 0), m1 = n[1] + (a == 1);
+    return i + m0 * (j + m1 * k);
+}
+
+/* Discrete divergence of face velocities: the sum over axes of
+ * (U on the upper face - U on the lower face) / h.  This is the div u* of
+ * Eq. (17) and of lambda_p in Eq. (34). */
+void orc_divergence(int dim, const int *n, double h, const double *const *U, double *div)
+{
+    for (long k = 0; k < n[2]; k++)
+        for (long j = 0; j < n[1]; j++)
+            for (long i = 0; i < n[0]; i++) {
+                double s = 0.0;
+                for (int a = 0; a < dim; a++) {
+                    long up[3] = {i, j, k};
+                    up[a] += 1;
+                    s += (U[a][fidx(n, a, up[0], up[1], up[2])] - U[a][fidx(n, a, i, j, k)]) / h;
+                }
+                div[idx3(n, i, j, k)] = s;
+            }
+}
+
+/* (1/rho) dp/dn on face (i,j,k) across axis a: the p face coefficient of
+ * the solve (the face mean of 1/rho, F[a]) times the pressure difference
+ * between the upper and the lower cell over h.  Zero on the two walls,
+ * where the solve has no flux either. */
+static double face_accel(const int *n, int a, double h, const double *F, const double *p,
+                         long i, long j, long k)
+{
+    long ii[3] = {i, j, k};
+    if (ii[a] == 0 || ii[a] == n[a]) return 0.0;
+    long N = (long)n[0] * n[1] * n[2];
+    long R = idx3(n, i, j, k);
+    ii[a] -= 1;
+    long L = idx3(n, ii[0], ii[1], ii[2]);
+    return F[(long)a * N + R] * (p[R] - p[L]) / h;
+}
+
+/* Velocity correction, Eq. (unp1): u^{n+1} = u* - dt (1/rho) grad p^{n+1}.
+ * On faces, with the face coefficient of the solve, so that the divergence
+ * of the corrected face velocities is the one of Eq. (17) that the solve
+ * used.  At cell centres (us, u not NULL), (1/rho) grad p along each axis is
+ * the mean of its values on the cell's two faces across that axis. */
+void orc_project(int dim, const int *n, double h, double dt, const double *F,
+                 const double *p, const double *const *Us, double *const *U,
+                 const double *const *us, double *const *u)
+{
+    for (int a = 0; a < dim; a++) {
+        long m[3] = {n[0], n[1], n[2]};
+        m[a] += 1;
+        for (long k = 0; k < m[2]; k++)
+            for (long j = 0; j < m[1]; j++)
+                for (long i = 0; i < m[0]; i++) {
+                    long f = fidx(n, a, i, j, k);
+                    U[a][f] = Us[a][f] - dt * face_accel(n, a, h, F, p, i, j, k);
+                }
+    }
+    if (!us || !u) return;
+    for (long k = 0; k < n[2]; k++)
+        for (long j = 0; j < n[1]; j++)
+            for (long i = 0; i < n[0]; i++) {
+                long c = idx3(n, i, j, k);
+                for (int a = 0; a < dim; a++) {
+                    long up[3] = {i, j, k};
+                    up[a] += 1;
+                    double g_lo = face_accel(n, a, h, F, p, i, j, k);
+                    double g_hi = face_accel(n, a, h, F, p, up[0], up[1], up[2]);
+                    u[a][c] = us[a][c] - dt * 0.5 * (g_lo + g_hi);
+                }
+            }
+}
+
+/* Phase pressures from the one-fluid pressure, Eqs. (37)-(38):
+ * p1 = p + (1 - C) sigma kappa, p2 = p - C sigma kappa (kappa NULL: none). */
+void orc_phase_pressures(long N, const double *p, const double *C, const double *kappa,
+                         double sigma, double *p1, double *p2)
+{
+    for (long c = 0; c < N; c++) {
+        double sk = kappa ? sigma * kappa[c] : 0.0;
+        p1[c] = p[c] + (1.0 - C[c]) * sk;
+        p2[c] = p[c] - C[c] * sk;
+    }
+}
+
+/* Phase total energies at the end of the step, Eq. (39) without the viscous
+ * work (inviscid): for phase i, with C_1 = C and C_2 = 1 - C,
+ *   (C_i rho_i e_T,i)^{n+1} = (C_i rho_i e_T,i)^(adv)
+ *                             + dt C_i [ -div(p_i u) + div(k grad T) ],
+ * the heat flux -q_i = k grad T^{n+1} being the one of the T equation (face
+ * coefficient F[3 + a], zero through the walls).  The pressure-work flux on
+ * a face is the mean of the two cells' p_i times the face velocity; on a
+ * wall face the cell's own p_i (zero normal gradient, as in the solve). */
+void orc_energy_update(int dim, const int *n, double h, double dt, const double *F,
+                       const double *C, const double *p1, const double *p2, const double *T,
+                       const double *const *U, const double *E1a, const double *E2a,
+                       double *E1, double *E2)
+{
+    long N = (long)n[0] * n[1] * n[2];
+    for (long k = 0; k < n[2]; k++)
+        for (long j = 0; j < n[1]; j++)
+            for (long i = 0; i < n[0]; i++) {
+                long c = idx3(n, i, j, k);
+                double w1 = 0.0, w2 = 0.0, q = 0.0;   /* div(p1 u), div(p2 u), div(k grad T) */
+                for (int a = 0; a < dim; a++) {
+                    long ii[3] = {i, j, k};
+                    /* lower face */
+                    double u_lo = U[a][fidx(n, a, i, j, k)];
+                    double P1lo = p1[c], P2lo = p2[c], q_lo = 0.0;
+                    if (ii[a] > 0) {
+                        long t[3] = {i, j, k};
+                        t[a] -= 1;
+                        long L = idx3(n, t[0], t[1], t[2]);
+                        P1lo = 0.5 * (p1[L] + p1[c]);
+                        P2lo = 0.5 * (p2[L] + p2[c]);
+                        q_lo = F[(long)(3 + a) * N + c] * (T[c] - T[L]) / h;
+                    }
+                    /* upper face */
+                    long t[3] = {i, j, k};
+                    t[a] += 1;
+                    double u_hi = U[a][fidx(n, a, t[0], t[1], t[2])];
+                    double P1hi = p1[c], P2hi = p2[c], q_hi = 0.0;
+                    if (ii[a] < n[a] - 1) {
+                        long R = idx3(n, t[0], t[1], t[2]);
+                        P1hi = 0.5 * (p1[c] + p1[R]);
+                        P2hi = 0.5 * (p2[c] + p2[R]);
+                        q_hi = F[(long)(3 + a) * N + R] * (T[R] - T[c]) / h;
+                    }
+                    w1 += (P1hi * u_hi - P1lo * u_lo) / h;
+                    w2 += (P2hi * u_hi - P2lo * u_lo) / h;
+                    q += (q_hi - q_lo) / h;
+                }
+                E1[c] = E1a[c] + dt * C[c] * (-w1 + q);
+                E2[c] = E2a[c] + dt * (1.0 - C[c]) * (-w2 + q);
+            }
 }

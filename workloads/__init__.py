@@ -115,6 +115,15 @@ class Problem:
     m2: Optional[np.ndarray] = None         # (1 - C) rho_2
     E: Optional[np.ndarray] = None          # total energy per volume
     mom: Optional[List[np.ndarray]] = None  # averaged momentum, one array per axis
+    # face velocities u* (Eq. provel): one array per axis, n_a + 1 faces
+    # along a (walls included), x fastest; when given, div u* is computed
+    # from them and div_ustar is None
+    uf_star: Optional[List[np.ndarray]] = None
+    uc_star: Optional[List[np.ndarray]] = None  # u* at cell centres, one array per axis
+    E1: Optional[np.ndarray] = None         # C rho_1 e_T,1 after advection
+    E2: Optional[np.ndarray] = None         # (1 - C) rho_2 e_T,2 after advection
+    kappa: Optional[np.ndarray] = None      # interface curvature [1/m]
+    sigma: float = 0.0                      # surface tension [N/m]
 
     @property
     def ncells(self) -> int:
@@ -158,6 +167,53 @@ def bubble_fraction(dim: int, n: Sequence[int], h: float,
     C = np.clip(0.5 + s / h, 0.0, 1.0)
     return np.ascontiguousarray(np.broadcast_to(C, tuple(
         n[dim - 1 - a] for a in range(dim))), dtype=np.float64)
+
+
+def face_velocities(dim: int, n: Sequence[int], seed: int, amp: float,
+                    noise: float) -> List[np.ndarray]:
+    """Seeded face velocities inside closed walls: for each axis a, a few
+    smooth modes sin(pi k x_a) prod_b cos(pi m x_b) of amplitude `amp` on the
+    face centres (zero on the walls normal to a) plus uniform noise in
+    [-noise, noise] on the interior faces.  Array shapes are x last, with
+    n_a + 1 faces along a."""
+    nn = _grid(dim, n)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for a in range(dim):
+        m = list(nn[:dim])
+        m[a] += 1
+        shape = tuple(m[dim - 1 - b] for b in range(dim))
+        u = np.zeros(shape)
+        for _ in range(3):
+            term = np.full(shape, amp * rng.uniform(-1.0, 1.0))
+            for b in range(dim):
+                shp = [1] * dim
+                shp[dim - 1 - b] = m[b]
+                if b == a:
+                    x = np.arange(m[b]) / nn[b]
+                    term = term * np.sin(math.pi * int(rng.integers(1, 4)) * x).reshape(shp)
+                else:
+                    x = (np.arange(m[b]) + 0.5) / nn[b]
+                    term = term * np.cos(math.pi * int(rng.integers(0, 4)) * x).reshape(shp)
+            u += term
+        if noise:
+            u += noise * rng.uniform(-1.0, 1.0, size=shape)
+        wall = [slice(None)] * dim
+        wall[dim - 1 - a] = 0
+        u[tuple(wall)] = 0.0
+        wall[dim - 1 - a] = -1
+        u[tuple(wall)] = 0.0
+        out.append(np.ascontiguousarray(u))
+    return out
+
+
+def interface_curvature(dim: int, C: np.ndarray, radius: float) -> np.ndarray:
+    """(dim - 1)/R in cells cut by the interface (0 < C < 1), else 0: the
+    curvature of a sphere (circle) of radius R."""
+    return np.where((C > 0.0) & (C < 1.0), (dim - 1) / radius, 0.0)
+
+
+SIGMA_WATER = 0.072             # surface tension of water-air near 20 C [N/m]
 
 
 def acoustic_dt(h: float, c_liquid: float = LIQUID.c, cfl: float = 0.5) -> float:
@@ -255,9 +311,13 @@ def state_problem(name: str, dim: int, n: Sequence[int],
     and total energy E = C rho_l e_l + (1-C) rho_g e_g + 1/2 rho |u|^2
     from the reference states REF_LIQUID, REF_GAS[gas_atm] with seeded
     smooth relative variations (rho_g 5 %, e_l 1e-4, e_g 1 %); a smooth
-    velocity of amplitude u_amp [m/s] per axis (momentum = rho u); the
-    acoustic time step; velocity-divergence forcing of amplitude
-    div_amp/dt (seeded)."""
+    velocity of amplitude u_amp [m/s] per axis (momentum = rho u, phase
+    energies E_i = m_i (e_i + |u|^2/2)); the acoustic time step; provisional
+    face velocities u* of the same amplitude inside closed walls with seeded
+    noise of amplitude div_amp h/dt on the interior faces (so that div u* has
+    a rough part of order div_amp/dt); u* at the cell centres = u; the
+    curvature of the first bubble in the cut cells, water's surface
+    tension."""
     nn = _grid(dim, n)
     h = L_UNIT / nn[0]
     centres = [[L_UNIT * v for v in c] for c in centres_unit]
@@ -279,15 +339,19 @@ def state_problem(name: str, dim: int, n: Sequence[int],
     rho = m1 + m2
     us = [u_amp * unit(4 + a) for a in range(dim)]
     mom = [np.ascontiguousarray(rho * u) for u in us]
-    ke = 0.5 * rho * sum(u * u for u in us)
-    E = m1 * e_l + m2 * e_g + ke
+    k2 = 0.5 * sum(u * u for u in us)
+    E1 = m1 * (e_l + k2)
+    E2 = m2 * (e_g + k2)
+    E = E1 + E2
     dt = acoustic_dt(h)
-    rng = np.random.Generator(np.random.PCG64(seed + 10))
-    div = (div_amp / dt) * rng.uniform(-1.0, 1.0, size=C.shape) if div_amp else None
+    uf = face_velocities(dim, nn, seed + 10, u_amp, div_amp * h / dt)
     return Problem(name=name, dim=dim, n=nn, h=h, mode="state", C=C,
-                   liquid=LIQUID_NASG, gas=GAS_IDEAL, dt=dt, div_ustar=div,
+                   liquid=LIQUID_NASG, gas=GAS_IDEAL, dt=dt, div_ustar=None,
                    rtol=rtol, precision=precision, m1=np.ascontiguousarray(m1),
-                   m2=np.ascontiguousarray(m2), E=np.ascontiguousarray(E), mom=mom)
+                   m2=np.ascontiguousarray(m2), E=np.ascontiguousarray(E), mom=mom,
+                   uf_star=uf, uc_star=[np.ascontiguousarray(u) for u in us],
+                   E1=np.ascontiguousarray(E1), E2=np.ascontiguousarray(E2),
+                   kappa=interface_curvature(dim, C, radii[0]), sigma=SIGMA_WATER)
 
 
 def state2d(n: int = 1024) -> Problem:
