@@ -5,9 +5,13 @@ One step = one pass of the whole hot path over one synthetic input:
 re-assembly of the operator and hierarchy (pt_mg_update), the paper's
 right-hand side (pt_mg_paper_rhs) and the solve to tolerance
 (pt_mg_solve), with every input already resident in device memory.  The
-state-mode workloads (state2d_1024, state3d_256) start one step earlier,
-from the advected conserved variables: the provisional pressure and
-temperature (pt_state_eval, Eqs. 20 and 23) feed the state-mode assembly.
+state-mode workloads (state2d_1024, state3d_256) cover the implicit part
+of the time step from the advected conserved variables to the updated
+ones: the provisional pressure and temperature (pt_state_eval, Eqs. 20
+and 23) feed the state-mode assembly, div u* comes from the provisional
+face velocities (pt_mg_divergence), and after the solve the velocity
+correction and the phase energy update (pt_mg_downstream, Eqs. unp1,
+37-39) consume it.
 
 Prints one JSON line: cell-updates/s of the timed steps, the roofline of
 the dominant kernel (HIP-event durations of its launches inside the timed
@@ -99,6 +103,21 @@ def upstream_line(prob, state_ms):
             "launches": len(state_ms)}
 
 
+def downstream_line(timed):
+    """Achieved bandwidth of pt_mg_downstream from the library's HIP-event
+    timing (algorithmic bytes: every array it reads or writes, once)."""
+    st = timed.get("downstream")
+    if not st or not st["launches"]:
+        return None
+    ms = st["ms"] / st["launches"]
+    nbytes = st["bytes"] / st["launches"]
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    return {"kernel": "pt_mg_downstream", "bound": "hbm", "achieved": round(gbs, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+            "avg_launch_us": round(ms * 1e3, 2), "alg_bytes_per_launch": nbytes,
+            "launches": st["launches"]}
+
+
 def oracle_updates(orc, prob, cycles):
     """Cell-updates of the oracle's solve: per V-cycle 4 sweeps and one
     residual on every non-coarsest level, plus the two finest-grid
@@ -126,8 +145,11 @@ def cpu_baseline(prob, rtol, budget_s):
         t = time.perf_counter()
         op = orc.assemble(prob)
         b_p, b_T = orc.rhs(op, prob)
-        _, _, cyc, hist = orc.mg_solve(op, b_p, b_T, rtol=rtol, max_cycles=max_cycles,
+        p, T, cyc, hist = orc.mg_solve(op, b_p, b_T, rtol=rtol, max_cycles=max_cycles,
                                        pin_mean=prob.mean_constraint)
+        if prob.uf_star is not None:
+            orc.downstream(op, prob.dt, p, T, prob.C, prob.uf_star, prob.E1, prob.E2,
+                           prob.uc_star, prob.kappa, prob.sigma)
         done = max_cycles if cyc < 0 else cyc
         return time.perf_counter() - t, oracle_updates(orc, prob, done), done
 
@@ -142,8 +164,12 @@ def cpu_baseline(prob, rtol, budget_s):
             updates += up
             cycles += done
             reps += 1
-    sample = (f"{prob.name}: {reps} oracle step(s) of assembly + paper RHS + FP64 V(2,2) "
-              f"lexicographic multigrid ({cycles} V-cycles in all"
+    sample = (f"{prob.name}: {reps} oracle step(s) of "
+              + ("provisional state + div u* + " if prob.mode == "state" else "")
+              + "assembly + paper RHS + FP64 V(2,2) "
+              f"lexicographic multigrid"
+              + (" + velocity correction and phase energies" if prob.uf_star is not None else "")
+              + f" ({cycles} V-cycles in all"
               + (", capped at one V-cycle" if capped else f", rtol {rtol:g}")
               + f"), {total:.1f} s")
     return {"value": updates / total, "unit": "cell-updates/s", "cores": threads,
@@ -356,6 +382,13 @@ def main():
 
         state = D.state_record(prob, tens) if prob.mode == "state" else None
         state_ev = []    # (start, end) event pairs around the state kernel
+        faces = D.face_inputs(prob, tens) if prob.uf_star is not None else None
+        if faces is not None:
+            div = torch.empty_like(p)
+            U = [torch.empty_like(f) for f in faces]
+            us = [tens[f"us{a}"] for a in range(prob.dim)]
+            u = [torch.empty_like(x) for x in us]
+            E1, E2 = torch.empty_like(p), torch.empty_like(p)
 
         def step():
             if state is not None:
@@ -365,11 +398,17 @@ def main():
                 b.record(stream)
                 state_ev.append((a, b))
             h.update(s)
-            if prob.mode != "explicit":
+            if faces is not None:
+                h.divergence(faces, out=div)
+                b_p, b_T = h.paper_rhs(tens.get("p_adv"), tens.get("T_adv"), div)
+            elif prob.mode != "explicit":
                 b_p, b_T = h.paper_rhs(tens.get("p_adv"), tens.get("T_adv"), tens.get("div"))
             else:
                 b_p, b_T = tens["f_p"], tens["f_T"]
             info = h.solve(b_p, b_T, p, T, rtol=rtol, max_cycles=120, method=method)
+            if faces is not None:
+                h.downstream(p, T, tens["C"], faces, U, us, u, tens["E1"], tens["E2"], E1, E2,
+                             tens["kappa"], prob.sigma)
             return info, b_p, b_T
 
         for _ in range(args.warmup):
@@ -378,7 +417,8 @@ def main():
         # HIP events only around the finest-grid smoother (the kernel the
         # roofline reports), and only around one smoothing run in
         # `timing_every`, so that the timed steps carry little overhead
-        h.set_timing(True, classes=[ROOFLINE_KERNEL])
+        h.set_timing(True, classes=[ROOFLINE_KERNEL]
+                     + (["downstream"] if faces is not None else []))
         h.set_option(ptmg.PT_OPT_TIMING_EVERY, args.timing_every)
         h.reset_stats()
         updates = 0
@@ -423,11 +463,15 @@ def main():
         "config": {"workload": name, "grid": list(prob.n[: prob.dim]), "precision": prec_name,
                    "rtol": rtol, "cycles_per_solve": float(np.mean(cycles)),
                    "step": ("pt_state_eval + " if prob.mode == "state" else "")
-                   + "pt_mg_update + pt_mg_paper_rhs + pt_mg_solve",
+                   + "pt_mg_update + "
+                   + ("pt_mg_divergence + " if faces is not None else "")
+                   + "pt_mg_paper_rhs + pt_mg_solve"
+                   + (" + pt_mg_downstream" if faces is not None else ""),
                    "method": args.method, "time_step": "diffusive" if args.stiff else "acoustic",
                    "parallelism": "single GPU"},
         "roofline": roofline,
         "upstream": upstream_line(prob, state_ms),
+        "downstream": downstream_line(timed),
         "launches_per_step": {k: v["launches"] / args.steps for k, v in stats.items()},
         "relres_last": list(info["relres"]),
     }

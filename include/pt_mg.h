@@ -221,6 +221,62 @@ int pt_mg_solve(pt_mg_t h, const double *b_p, const double *b_T, double *p, doub
 int pt_mg_residual(pt_mg_t h, const double *b_p, const double *b_T, const double *p,
                    const double *T, double *r_p, double *r_T, double relres[2]);
 
+/* ---------------------------------------------------------------------
+ * The end of the step, after the solve (Sec. 3).
+ *
+ * Face velocities: U[a] (a < dim) holds the velocity component normal to
+ * the faces across axis a: n[a] + 1 faces along a (both walls included)
+ * and n[b] along every other axis b.  The face at (i,j,k) is the lower
+ * face of cell (i,j,k); its index is i + m0*(j + m1*k) with
+ * m_b = n[b] + (b == a).  Device float64 arrays, caller-owned.
+ * --------------------------------------------------------------------- */
+
+/* Divergence of face velocities per cell, the sum over axes of
+ * (U_a on the upper face - U_a on the lower face) / h: the div u* that
+ * Eq. (17) and lambda_p of Eq. (34) use (pass it to pt_mg_paper_rhs).
+ * U[0 .. dim-1] as above (U[dim..2] ignored), div [N] output.  Any mode.
+ * PT_ERR_ARG for a NULL array. */
+int pt_mg_divergence(pt_mg_t h, const double *const U[3], double *div);
+
+/* Fields of pt_mg_downstream.  Cell arrays [N]; U arrays as above. */
+typedef struct {
+    const double *p, *T;         /* the solution of pt_mg_solve */
+    const double *C;             /* liquid volume fraction C_1 (the assembly's) */
+    const double *kappa;         /* interface curvature, or NULL: no surface tension */
+    double sigma;                /* surface tension coefficient */
+    const double *U_star[3];     /* provisional face velocities u* (Eq. provel) */
+    double *U[3];                /* out: face velocities at the end of the step;
+                                  * must not overlap U_star */
+    const double *u_star[3];     /* provisional cell velocities, or all NULL */
+    double *u[3];                /* out: cell velocities (may be u_star), or all NULL */
+    const double *E1_adv, *E2_adv; /* phase total energies per volume after
+                                  * advection, C_i rho_i e_T,i; both NULL: no
+                                  * energy update */
+    double *E1, *E2;             /* out (may be E1_adv, E2_adv) */
+} pt_downstream;
+
+/* The step's end in one pass over the grid: the velocity correction of
+ * Eq. (unp1) and the phase energies of Eq. (39) with the phase pressures
+ * of Eqs. (37)-(38).
+ *  - Faces: U = U* - dt a_f (p_R - p_L)/h on interior faces, a_f the p
+ *    face coefficient of the assembly (harmonic mean of 1/rho), so that
+ *    div U is the one of Eq. (17) the solve used; wall faces keep U*.
+ *  - Cells: u = u* - dt g, g along each axis the mean of a_f (p_R - p_L)/h
+ *    on the cell's two faces across that axis (0 on a wall face).
+ *  - p_1 = p + (1 - C) sigma kappa, p_2 = p - C sigma kappa.
+ *  - E_i = E_i^adv + dt C_i [ -div(p_i U) + div(k grad T) ], C_1 = C,
+ *    C_2 = 1 - C; the pressure-work flux on a face is the mean of the two
+ *    cells' p_i times U (on a wall face the cell's own p_i); the heat flux
+ *    is k_f (T_R - T_L)/h with the T face coefficient of the assembly, zero
+ *    through the walls.  The viscous work of Eq. (39) is not included
+ *    (inviscid flow).
+ * dt, h, 1/rho and k are those of the last pt_mg_setup / pt_mg_update
+ * (PT_COEF_PHASES or PT_COEF_STATE; PT_ERR_STATE otherwise).  Returns when
+ * the outputs are written.  PT_ERR_ARG for a NULL p, T, C, U_star[a] or
+ * U[a] (a < dim), U[a] == U_star[a], only one of u_star / u given for an
+ * axis, or exactly one of E1_adv, E2_adv, E1, E2 missing. */
+int pt_mg_downstream(pt_mg_t h, const pt_downstream *d);
+
 void pt_mg_destroy(pt_mg_t h);
 
 /* Last error message of the handle, or of the calling thread when h is
@@ -287,7 +343,8 @@ typedef enum {
     PT_K_PROLONG = 4,         /* prolongation + correction, all levels */
     PT_K_COARSE_SOLVE = 5,    /* coarsest-grid solve */
     PT_K_OTHER = 6,           /* norm reduction, conversions, copies */
-    PT_K_COUNT = 7
+    PT_K_DOWNSTREAM = 7,      /* pt_mg_downstream (velocity correction + phase energies) */
+    PT_K_COUNT = 8
 } pt_kernel_class;
 
 /* HIP-event timing (off by default): on = 0 off, 1 every kernel class,

@@ -980,6 +980,96 @@ int pt_mg_paper_rhs(pt_mg_t h, const double *p_adv, const double *T_adv, const d
     return sync(h, "paper_rhs");
 }
 
+int pt_mg_divergence(pt_mg_t h, const double *const U[3], double *div)
+{
+    if (!h || !h->ready) return fail(h, PT_ERR_STATE, "handle not ready");
+    const Plan &P = h->P;
+    const int dim = h->prob.dim;
+    if (!U || !div) return fail(h, PT_ERR_ARG, "NULL array");
+    for (int a = 0; a < dim; a++)
+        if (!U[a]) return fail(h, PT_ERR_ARG, "NULL face velocity array");
+    double faces = 0.0;
+    for (int a = 0; a < dim; a++) faces += (double)P.N + (double)P.N / P.n[a];
+    h->begin(PT_K_OTHER, 8.0 * (faces + P.N));
+    launch_divergence(dim, P.n[0], P.n[1], P.n[2], 1.0 / h->prob.h, U[0], U[1],
+                      dim == 3 ? U[2] : nullptr, div, h->stream);
+    h->end();
+    return sync(h, "divergence");
+}
+
+int pt_mg_downstream(pt_mg_t h, const pt_downstream *d)
+{
+    if (!h || !h->ready) return fail(h, PT_ERR_STATE, "handle not ready");
+    if (h->prob.mode == PT_COEF_EXPLICIT)
+        return fail(h, PT_ERR_STATE, "downstream needs phases or state mode");
+    if (!d) return fail(h, PT_ERR_ARG, "NULL argument record");
+    const Plan &P = h->P;
+    const int dim = h->prob.dim;
+    if (!d->p || !d->T || !d->C) return fail(h, PT_ERR_ARG, "p, T and C are required");
+    int ncell = 0;
+    for (int a = 0; a < dim; a++) {
+        if (!d->U_star[a] || !d->U[a]) return fail(h, PT_ERR_ARG, "face velocities are required");
+        if (d->U[a] == d->U_star[a])
+            return fail(h, PT_ERR_ARG, "face velocities cannot be updated in place");
+        if (!d->u_star[a] != !d->u[a])
+            return fail(h, PT_ERR_ARG, "cell velocity needs both u_star and u");
+        ncell += d->u[a] != nullptr;
+    }
+    if (ncell != 0 && ncell != dim)
+        return fail(h, PT_ERR_ARG, "cell velocities for some axes only");
+    const int ne = (d->E1_adv != nullptr) + (d->E2_adv != nullptr) + (d->E1 != nullptr) +
+                   (d->E2 != nullptr);
+    if (ne != 0 && ne != 4) return fail(h, PT_ERR_ARG, "energy update needs E1_adv, E2_adv, E1, E2");
+    DownArgs a = {};
+    a.nx = P.n[0];
+    a.ny = P.n[1];
+    a.nz = P.n[2];
+    a.inv_h = 1.0 / h->prob.h;
+    a.dt = h->prob.dt;
+    a.sigma = d->sigma;
+    a.ac = h->ac64();
+    a.p = d->p;
+    a.T = d->T;
+    a.C = d->C;
+    a.kappa = d->kappa;
+    a.Ux = d->U_star[0];
+    a.Uy = d->U_star[1];
+    a.Vx = d->U[0];
+    a.Vy = d->U[1];
+    if (ncell) {
+        a.ux = d->u_star[0];
+        a.uy = d->u_star[1];
+        a.vx = d->u[0];
+        a.vy = d->u[1];
+    }
+    if (dim == 3) {
+        a.Uz = d->U_star[2];
+        a.Vz = d->U[2];
+        if (ncell) {
+            a.uz = d->u_star[2];
+            a.vz = d->u[2];
+        }
+    }
+    if (ne) {
+        a.E1a = d->E1_adv;
+        a.E2a = d->E2_adv;
+        a.E1 = d->E1;
+        a.E2 = d->E2;
+    }
+    // algorithmic bytes: every array read or written once
+    const double N = (double)P.N;
+    double faces = 0.0;
+    for (int q = 0; q < dim; q++) faces += N + N / P.n[q];
+    double bytes = 8.0 * (5.0 * N + 2.0 * faces);   // p, T, (1/rho, k), C; U*, U
+    if (d->kappa) bytes += 8.0 * N;
+    if (ncell) bytes += 16.0 * dim * N;
+    if (ne) bytes += 32.0 * N;
+    h->begin(PT_K_DOWNSTREAM, bytes);
+    launch_downstream(dim, a, h->stream);
+    h->end();
+    return sync(h, "downstream");
+}
+
 namespace {
 
 // Outer residual on the finest grid; returns blocks of partial sums.

@@ -106,6 +106,26 @@ int launch_dot2(long long N, const double *x_p, const double *x_T, const double 
                 const double *y_T, const double *z_p, const double *z_T, const double *w_p,
                 const double *w_T, double *partials, hipStream_t s);
 
+// End-of-step pass on the finest grid: face and cell velocity correction
+// and phase energies (pt_mg_downstream).  Face arrays per axis as in
+// pt_mg.h; the 3-D-only members are null in 2-D.
+struct DownArgs {
+    int nx, ny, nz;
+    double inv_h, dt, sigma;
+    const double2 *ac;                 // FP64 cell (1/rho, k)
+    const double *p, *T, *C, *kappa;   // kappa null: no surface tension
+    const double *Ux, *Uy, *Uz;        // provisional face velocities
+    double *Vx, *Vy, *Vz;              // corrected face velocities
+    const double *ux, *uy, *uz;        // provisional cell velocities (null: none)
+    double *vx, *vy, *vz;
+    const double *E1a, *E2a;           // null: no energy update
+    double *E1, *E2;
+};
+void launch_downstream(int dim, const DownArgs &a, hipStream_t s);
+// div = sum over axes of (U upper face - U lower face) * inv_h.
+void launch_divergence(int dim, int nx, int ny, int nz, double inv_h, const double *Ux,
+                       const double *Uy, const double *Uz, double *div, hipStream_t s);
+
 // ---- launch wrappers (implemented in ptmg_kernels.hip) --------------------
 void launch_assemble(const AsmArgs &a, hipStream_t s);
 void launch_paper_rhs(long long N, const double4 *B64, const double *p_adv, double p_const,

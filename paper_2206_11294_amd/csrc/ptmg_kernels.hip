@@ -2836,3 +2836,234 @@ template void tail_set_lds_limit<float>(int, size_t);
 template void tail_set_lds_limit<double>(int, size_t);
 
 }  // namespace ptmg
+
+namespace ptmg {
+
+// ------------------------------------------------ end of the step
+// Velocity correction and phase energies in one plane-marching pass: a
+// 4-slot LDS ring of planes (tile + a ring of one cell) holds (p, T),
+// (1/rho, k) and (C, sigma kappa), so every cell array is read from HBM
+// once; each cell recomputes the corrected velocity of its 2*DIM faces
+// (the expression is the same in both cells that share a face) and writes
+// the lower ones (and the upper wall face at the end of an axis).  A 2-D
+// grid marches along y with 1-row planes.
+template <int DIM, int TX, int TY>
+__global__ __launch_bounds__(TX *TY) void k_down_zm(DownArgs a, int NX, int NY, int NZ, int zc,
+                                                    int tiles_x, int tiles_y, int ntiles)
+{
+    constexpr bool FLAT = DIM == 2;
+    constexpr int NT = TX * TY;
+    constexpr int PX = TX + 2, PY = FLAT ? 1 : TY + 2, PS = PX * PY;
+    constexpr int NLD = (PS + NT - 1) / NT;
+    __shared__ double2 sq[4][PS];   // (p, T)
+    __shared__ double2 sa[4][PS];   // (1/rho, k)
+    __shared__ double2 sc[4][PS];   // (C, sigma kappa)
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    if (tile >= ntiles) return;     // whole block: no barrier is skipped by part of it
+    const int t = threadIdx.x;
+    const int txi = tile % tiles_x;
+    const int rr = tile / tiles_x;
+    const int x0 = txi * TX, y0 = (rr % tiles_y) * TY;
+    const int z0 = (rr / tiles_y) * zc, z1 = min(z0 + zc, NZ);
+    const long long nxy = (long long)NX * NY;
+    const int oy = FLAT ? 0 : 1;
+    const double *Um = FLAT ? a.Uy : a.Uz;   // faces across the marching axis
+    double *Vm = FLAT ? a.Vy : a.Vz;
+    const double *um = FLAT ? a.uy : a.uz;
+    double *vm = FLAT ? a.vy : a.vz;
+    const bool cellv = a.ux != nullptr;
+    const bool energy = a.E1a != nullptr;
+
+    double2 pq[NLD], pa[NLD], pc[NLD];
+    auto fetch = [&](int z) {
+#pragma unroll
+        for (int i = 0; i < NLD; i++) {
+            const int c = t + i * NT;
+            pq[i] = make_double2(0.0, 0.0);
+            pa[i] = make_double2(0.0, 0.0);
+            pc[i] = make_double2(0.0, 0.0);
+            const int gx = x0 + c % PX - 1, gy = y0 + c / PX - oy;
+            if (c < PS && z >= 0 && z < NZ && gx >= 0 && gx < NX && gy >= 0 && gy < NY) {
+                const long long g = gx + (long long)NX * gy + nxy * z;
+                pq[i] = make_double2(a.p[g], a.T[g]);
+                pa[i] = a.ac[g];
+                pc[i] = make_double2(a.C[g], a.kappa ? a.sigma * a.kappa[g] : 0.0);
+            }
+        }
+    };
+    auto store = [&](int z) {
+        const int s = z & 3;
+#pragma unroll
+        for (int i = 0; i < NLD; i++) {
+            const int c = t + i * NT;
+            if (c < PS) {
+                sq[s][c] = pq[i];
+                sa[s][c] = pa[i];
+                sc[s][c] = pc[i];
+            }
+        }
+    };
+    // this thread's cell column
+    const int lx = 1 + t % TX, ly = oy + t / TX;
+    const int gx = x0 + lx - 1, gy = y0 + ly - oy;
+    const bool mine = gx < NX && gy < NY;
+    const int c = ly * PX + lx;
+    // pointwise inputs of the next cell (prefetched one plane ahead)
+    struct CellIn {
+        double e1, e2, u0, u1, u2;   // energies, cell velocities (x, in-plane y, march)
+        double xl, xh, yl, yh, mh;   // provisional face velocities
+    };
+    CellIn nx_ = {}, cur;
+    auto fetch_cell = [&](int z) {
+        if (mine && z < z1) {
+            const long long g = gx + (long long)NX * gy + nxy * z;
+            if (energy) {
+                nx_.e1 = a.E1a[g];
+                nx_.e2 = a.E2a[g];
+            }
+            if (cellv) {
+                nx_.u0 = a.ux[g];
+                if (!FLAT) nx_.u1 = a.uy[g];
+                nx_.u2 = um[g];
+            }
+            const long long fx = gx + (long long)(NX + 1) * (gy + (long long)NY * z);
+            nx_.xl = a.Ux[fx];
+            nx_.xh = a.Ux[fx + 1];
+            if (!FLAT) {
+                const long long fy = gx + (long long)NX * (gy + (long long)(NY + 1) * z);
+                nx_.yl = a.Uy[fy];
+                nx_.yh = a.Uy[fy + NX];
+            }
+            nx_.mh = Um[g + nxy];
+        }
+    };
+    double ml = 0.0;   // provisional velocity on the lower face across the marching axis
+    if (mine) ml = Um[gx + (long long)NX * gy + nxy * z0];
+    fetch(z0 - 1);
+    store(z0 - 1);
+    fetch(z0);
+    store(z0);
+    fetch_cell(z0);
+    cur = nx_;
+    fetch(z0 + 1);
+    for (int k = z0; k < z1; k++) {
+        store(k + 1);
+        fetch(k + 2);
+        fetch_cell(k + 1);
+        __syncthreads();
+        if (mine) {
+            const int s = k & 3, sm = (k + 3) & 3, sp = (k + 1) & 3;
+            const double2 q = sq[s][c], am = sa[s][c], cm = sc[s][c];
+            const double p1c = q.x + (1.0 - cm.x) * cm.y, p2c = q.x - cm.x * cm.y;
+            // one face of this cell: corrected velocity, (1/rho) dp/dn, the
+            // phase pressures on the face and the heat flux k dT/dn
+            struct Face {
+                double U, g, P1, P2, q;
+            };
+            auto face = [&](int ss, int qi, bool inside, bool upper, double Us) {
+                Face f;
+                if (!inside) {
+                    f.U = Us;
+                    f.g = 0.0;
+                    f.P1 = p1c;
+                    f.P2 = p2c;
+                    f.q = 0.0;
+                    return f;
+                }
+                const double2 qn = sq[ss][qi], an = sa[ss][qi], cn = sc[ss][qi];
+                const double p1n = qn.x + (1.0 - cn.x) * cn.y, p2n = qn.x - cn.x * cn.y;
+                if (upper) {
+                    f.g = harm(am.x, an.x) * ((qn.x - q.x) * a.inv_h);
+                    f.q = harm(am.y, an.y) * ((qn.y - q.y) * a.inv_h);
+                    f.P1 = 0.5 * (p1c + p1n);
+                    f.P2 = 0.5 * (p2c + p2n);
+                } else {
+                    f.g = harm(an.x, am.x) * ((q.x - qn.x) * a.inv_h);
+                    f.q = harm(an.y, am.y) * ((q.y - qn.y) * a.inv_h);
+                    f.P1 = 0.5 * (p1n + p1c);
+                    f.P2 = 0.5 * (p2n + p2c);
+                }
+                f.U = Us - a.dt * f.g;
+                return f;
+            };
+            double w1 = 0.0, w2 = 0.0, qs = 0.0;
+            auto axis = [&](const Face &lo, const Face &hi) {
+                w1 += (hi.P1 * hi.U - lo.P1 * lo.U) * a.inv_h;
+                w2 += (hi.P2 * hi.U - lo.P2 * lo.U) * a.inv_h;
+                qs += (hi.q - lo.q) * a.inv_h;
+            };
+            const long long g = gx + (long long)NX * gy + nxy * k;
+            // x
+            const Face xlo = face(s, c - 1, gx > 0, false, cur.xl);
+            const Face xhi = face(s, c + 1, gx < NX - 1, true, cur.xh);
+            axis(xlo, xhi);
+            const long long fx = gx + (long long)(NX + 1) * (gy + (long long)NY * k);
+            a.Vx[fx] = xlo.U;
+            if (gx == NX - 1) a.Vx[fx + 1] = xhi.U;
+            if (cellv) a.vx[g] = cur.u0 - a.dt * (0.5 * (xlo.g + xhi.g));
+            // in-plane y (3-D)
+            if (!FLAT) {
+                const Face ylo = face(s, c - PX, gy > 0, false, cur.yl);
+                const Face yhi = face(s, c + PX, gy < NY - 1, true, cur.yh);
+                axis(ylo, yhi);
+                const long long fy = gx + (long long)NX * (gy + (long long)(NY + 1) * k);
+                a.Vy[fy] = ylo.U;
+                if (gy == NY - 1) a.Vy[fy + NX] = yhi.U;
+                if (cellv) a.vy[g] = cur.u1 - a.dt * (0.5 * (ylo.g + yhi.g));
+            }
+            // marching axis
+            const Face mlo = face(sm, c, k > 0, false, ml);
+            const Face mhi = face(sp, c, k < NZ - 1, true, cur.mh);
+            axis(mlo, mhi);
+            Vm[g] = mlo.U;
+            if (k == NZ - 1) Vm[g + nxy] = mhi.U;
+            if (cellv) vm[g] = cur.u2 - a.dt * (0.5 * (mlo.g + mhi.g));
+            if (energy) {
+                const double C = cm.x;
+                a.E1[g] = cur.e1 + a.dt * C * (-w1 + qs);
+                a.E2[g] = cur.e2 + a.dt * (1.0 - C) * (-w2 + qs);
+            }
+            ml = cur.mh;
+        }
+        cur = nx_;
+    }
+}
+
+void launch_downstream(int dim, const DownArgs &a, hipStream_t s)
+{
+    const ZmGeom g = outer_geom(dim, a.nx, a.ny, a.nz);
+    if (dim == 3)
+        hipLaunchKernelGGL((k_down_zm<3, 64, 4>), dim3(g.nt), dim3(256), 0, s, a, g.NX, g.NY,
+                           g.NZ, g.zc, g.tx, g.ty, g.nt);
+    else
+        hipLaunchKernelGGL((k_down_zm<2, 256, 1>), dim3(g.nt), dim3(256), 0, s, a, g.NX, g.NY,
+                           g.NZ, g.zc, g.tx, g.ty, g.nt);
+}
+
+__global__ __launch_bounds__(256) void k_divergence(int dim, int nx, int ny, int nz, double inv_h,
+                                                    const double *Ux, const double *Uy,
+                                                    const double *Uz, double *div)
+{
+    const long long N = (long long)nx * ny * nz;
+    for (long long t = blockIdx.x * 256ll + threadIdx.x; t < N; t += (long long)gridDim.x * 256) {
+        int i, j, k;
+        decode(t, nx, ny, i, j, k);
+        const long long fx = i + (long long)(nx + 1) * (j + (long long)ny * k);
+        const long long fy = i + (long long)nx * (j + (long long)(ny + 1) * k);
+        double d = (Ux[fx + 1] - Ux[fx]) * inv_h;
+        d += (Uy[fy + nx] - Uy[fy]) * inv_h;
+        if (dim == 3) d += (Uz[t + (long long)nx * ny] - Uz[t]) * inv_h;
+        div[t] = d;
+    }
+}
+
+void launch_divergence(int dim, int nx, int ny, int nz, double inv_h, const double *Ux,
+                       const double *Uy, const double *Uz, double *div, hipStream_t s)
+{
+    const long long N = (long long)nx * ny * nz;
+    const long long nb = std::min<long long>((N + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_divergence, dim3((unsigned)nb), dim3(256), 0, s, dim, nx, ny, nz, inv_h,
+                       Ux, Uy, Uz, div);
+}
+
+}  // namespace ptmg

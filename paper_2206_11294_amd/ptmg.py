@@ -23,7 +23,7 @@ PT_PREC_FP64, PT_PREC_MIXED = 0, 1
 PT_MAX_HIST = 64
 PT_OPT_GRAPHS, PT_OPT_TAIL, PT_OPT_FUSED, PT_OPT_TIMING_EVERY, PT_OPT_SPECULATE = 1, 2, 3, 4, 5
 KERNEL_CLASSES = ["outer_residual", "smooth_fine", "smooth_coarse", "restrict", "prolong",
-                  "coarse_solve", "other"]
+                  "coarse_solve", "other", "downstream"]
 
 
 class PtMgError(RuntimeError):
@@ -65,6 +65,14 @@ class pt_state(ctypes.Structure):
     ]
 
 
+class pt_downstream(ctypes.Structure):
+    _fields_ = [
+        ("p", _Dp), ("T", _Dp), ("C", _Dp), ("kappa", _Dp), ("sigma", ctypes.c_double),
+        ("U_star", _Dp * 3), ("U", _Dp * 3), ("u_star", _Dp * 3), ("u", _Dp * 3),
+        ("E1_adv", _Dp), ("E2_adv", _Dp), ("E1", _Dp), ("E2", _Dp),
+    ]
+
+
 class pt_solve_opts(ctypes.Structure):
     _fields_ = [("rtol", ctypes.c_double), ("max_cycles", ctypes.c_int),
                 ("nu1", ctypes.c_int), ("nu2", ctypes.c_int), ("zero_guess", ctypes.c_int),
@@ -100,6 +108,8 @@ def lib() -> ctypes.CDLL:
             "pt_mg_setup": (c_int, [P(pt_problem), c_int, c_void, P(c_void)]),
             "pt_mg_update": (c_int, [c_void, P(pt_problem)]),
             "pt_mg_paper_rhs": (c_int, [c_void] + [c_void] * 5),
+            "pt_mg_divergence": (c_int, [c_void, P(c_void), c_void]),
+            "pt_mg_downstream": (c_int, [c_void, P(pt_downstream)]),
             "pt_mg_solve": (c_int, [c_void, c_void, c_void, c_void, c_void,
                                     P(pt_solve_opts), P(pt_solve_info)]),
             "pt_mg_residual": (c_int, [c_void] + [c_void] * 6 + [P(c_double)]),
@@ -136,6 +146,7 @@ def exported_symbols() -> Sequence[str]:
     """Names of the C-ABI functions the binding uses."""
     lib()
     return ["pt_state_eval", "pt_mg_footprint_bytes", "pt_mg_setup", "pt_mg_update", "pt_mg_paper_rhs",
+            "pt_mg_divergence", "pt_mg_downstream",
             "pt_mg_solve", "pt_mg_residual", "pt_mg_destroy", "pt_mg_last_error",
             "pt_mg_num_levels", "pt_mg_level_dims", "pt_mg_get_operator", "pt_mg_smooth",
             "pt_mg_restrict_residual", "pt_mg_prolong_add", "pt_mg_coarse_solve",
@@ -224,6 +235,29 @@ class PtMg:
         self._check(lib().pt_mg_paper_rhs(self._h, _ptr(p_adv), _ptr(T_adv), _ptr(div_ustar),
                                           _ptr(b_p), _ptr(b_T)))
         return b_p, b_T
+
+    def divergence(self, U: Sequence[torch.Tensor], out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """pt_mg_divergence: div of the face velocities U[a] (one tensor per axis)."""
+        div = self._empty() if out is None else out
+        ptrs = (ctypes.c_void_p * 3)(*[_ptr(u) for u in U], *([None] * (3 - len(U))))
+        self._check(lib().pt_mg_divergence(self._h, ptrs, _ptr(div)))
+        return div
+
+    def downstream(self, p, T, C, U_star, U, u_star=None, u=None, E1_adv=None, E2_adv=None,
+                   E1=None, E2=None, kappa=None, sigma: float = 0.0) -> None:
+        """pt_mg_downstream: velocity correction and phase energies into the
+        given output tensors (U, u, E1, E2)."""
+        d = pt_downstream()
+        d.p, d.T, d.C, d.kappa = _ptr(p), _ptr(T), _ptr(C), _ptr(kappa)
+        d.sigma = sigma
+        for a in range(len(U_star)):
+            d.U_star[a] = _ptr(U_star[a])
+            d.U[a] = _ptr(U[a])
+            if u_star is not None:
+                d.u_star[a] = _ptr(u_star[a])
+                d.u[a] = _ptr(u[a])
+        d.E1_adv, d.E2_adv, d.E1, d.E2 = _ptr(E1_adv), _ptr(E2_adv), _ptr(E1), _ptr(E2)
+        self._check(lib().pt_mg_downstream(self._h, ctypes.byref(d)))
 
     def solve(self, b_p, b_T, p, T, rtol=1e-9, max_cycles=50, nu1=2, nu2=2,
               zero_guess=True, raise_on_noconv=True, method=PT_SOLVE_DEFECT) -> Dict:

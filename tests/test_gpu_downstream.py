@@ -1,0 +1,276 @@
+"""pt_mg_divergence and pt_mg_downstream against the oracle: element by
+element on the same seeded inputs, on grids that span several tiles and
+z-chunks with ragged edges, at the full 1024^2 and 256^3 sizes, with the
+increments isolated (zero provisional velocities and energies) so that
+they are compared at their own scale, plus the end-to-end chain from the
+conserved variables through the solve."""
+import numpy as np
+import pytest
+
+import oracle as orc
+import workloads as W
+from gpu_util import dev, host, rel_err
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _fields(prob, seed):
+    """Seeded (p, T) near the reference state with smooth and rough parts
+    (not a solve output: both sides take them as inputs)."""
+    rng = np.random.default_rng(seed)
+    N = prob.ncells
+    sm = W.smooth_field(prob.dim, prob.n, seed).reshape(-1)
+    p = W.P0 * (1.0 + 0.01 * sm + 1e-4 * rng.uniform(-1, 1, N))
+    T = W.T0 + 5.0 * sm + 0.05 * rng.uniform(-1, 1, N)
+    return p, T
+
+
+def _case(name):
+    if name == "state2d_257x5":
+        return W.state_problem(name, 2, (257, 5), [(0.5, 0.5)], [0.3], seed=31)
+    if name == "state2d_6x300":
+        return W.state_problem(name, 2, (6, 300), [(0.5, 0.5)], [0.4], seed=32)
+    if name == "state2d_200x136":
+        return W.state_problem(name, 2, (200, 136), [(0.45, 0.5)], [0.2], seed=33)
+    if name == "state3d_66x6x10":
+        return W.state_problem(name, 3, (66, 6, 10), [(0.5, 0.5, 0.5)], [0.3], seed=34)
+    if name == "state3d_40x24x56":
+        return W.state_problem(name, 3, (40, 24, 56), [(0.5, 0.4, 0.5)], [0.25], seed=35)
+    if name == "state3d_2x2x2":
+        return W.state_problem(name, 3, (2, 2, 2), [(0.5, 0.5, 0.5)], [0.4], seed=36)
+    if name == "bubble2d_132x68":
+        prob = W.bubble_problem(name, 2, (132, 68), [(0.4, 0.5)], [0.2], W.P0, 10 * W.P0)
+        return _with_end_of_step(prob, 37)
+    if name == "state2d_1024":
+        return W.state2d(1024)
+    if name == "state3d_256":
+        return W.state3d(256)
+    raise KeyError(name)
+
+
+def _with_end_of_step(prob, seed):
+    """End-of-step inputs for a phases-mode problem."""
+    import dataclasses
+    rng = np.random.default_rng(seed)
+    N = prob.ncells
+    uf = W.face_velocities(prob.dim, prob.n, seed, 1.0, 1e-2)
+    uc = [rng.uniform(-1, 1, N) for _ in range(prob.dim)]
+    return dataclasses.replace(prob, uf_star=uf, uc_star=uc,
+                               E1=prob.C.reshape(-1) * rng.uniform(8e7, 9e7, N),
+                               E2=(1 - prob.C.reshape(-1)) * rng.uniform(2e5, 3e5, N),
+                               kappa=W.interface_curvature(prob.dim, prob.C, 0.2e-3),
+                               sigma=W.SIGMA_WATER)
+
+
+def _handle(prob):
+    import workloads.device as D
+    from paper_2206_11294_amd import ptmg
+    s, t = D.to_device(prob)
+    h = ptmg.PtMg(s, ptmg.PT_PREC_FP64)
+    return h, t
+
+
+def _run(h, prob, t, p, T, Us, us, E1a, E2a, kappa=True, cells=True, energy=True):
+    Pd, Td = dev(p), dev(T)
+    Usd = [dev(u) for u in Us]
+    U = [torch.full_like(u, float("nan")) for u in Usd]
+    usd = [dev(u) for u in us] if cells else None
+    u = [torch.full_like(x, float("nan")) for x in usd] if cells else None
+    E1 = torch.full_like(Pd, float("nan")) if energy else None
+    E2 = torch.full_like(Pd, float("nan")) if energy else None
+    h.downstream(Pd, Td, t["C"], Usd, U, usd, u, dev(E1a) if energy else None,
+                 dev(E2a) if energy else None, E1, E2,
+                 t["kappa"] if kappa else None, prob.sigma if kappa else 0.0)
+    torch.cuda.synchronize()
+    return {"U": [host(x) for x in U], "u": [host(x) for x in u] if cells else None,
+            "E1": host(E1) if energy else None, "E2": host(E2) if energy else None}
+
+
+def _oracle(op, prob, p, T, Us, us, E1a, E2a, kappa=True):
+    return orc.downstream(op, prob.dt, p, T, prob.C, Us, E1a, E2a, us,
+                          prob.kappa if kappa else None, prob.sigma if kappa else 0.0)
+
+
+def _close(a, b, rtol):
+    """Element-wise: |a - b| <= rtol * max|b| (the scale of the field)."""
+    a, b = np.asarray(a).reshape(-1), np.asarray(b).reshape(-1)
+    scale = max(np.abs(b).max(), 1e-300)
+    err = np.abs(a - b).max() / scale
+    assert np.all(np.isfinite(a)), "non-finite output"
+    assert err <= rtol, f"max error {err:.3e} of scale {scale:.3e}"
+
+
+SMALL = ["state2d_257x5", "state2d_6x300", "state2d_200x136", "state3d_66x6x10",
+         "state3d_40x24x56", "state3d_2x2x2", "bubble2d_132x68"]
+
+
+@pytest.mark.parametrize("name", SMALL + ["state2d_1024"])
+def test_divergence_matches_oracle(name):
+    prob = _case(name)
+    print(f"divergence {name} {prob.n}", flush=True)
+    h, t = _handle(prob)
+    import workloads.device as D
+    d = host(h.divergence(D.face_inputs(prob, t)))
+    ref = orc.divergence(prob.dim, prob.n, prob.h, prob.uf_star)
+    scale = max(np.abs(u).max() for u in prob.uf_star) / prob.h
+    assert np.abs(d - ref).max() <= 1e-14 * scale
+
+
+@pytest.mark.parametrize("name", SMALL)
+def test_downstream_matches_oracle(name):
+    prob = _case(name)
+    print(f"downstream {name} {prob.n}", flush=True)
+    h, t = _handle(prob)
+    op = orc.assemble(prob)
+    p, T = _fields(prob, 7)
+    Us = [u.reshape(-1) for u in prob.uf_star]
+    us = [u.reshape(-1) for u in prob.uc_star]
+    E1a, E2a = prob.E1.reshape(-1), prob.E2.reshape(-1)
+    # full update against the oracle's
+    g = _run(h, prob, t, p, T, Us, us, E1a, E2a)
+    o = _oracle(op, prob, p, T, Us, us, E1a, E2a)
+    for a in range(prob.dim):
+        _close(g["U"][a], o["U"][a], 1e-14)
+        _close(g["u"][a], o["u"][a], 1e-14)
+    _close(g["E1"], o["E1"], 1e-14)
+    _close(g["E2"], o["E2"], 1e-14)
+    # the increments alone: zero provisional velocities and energies
+    zU = [np.zeros_like(u) for u in Us]
+    zu = [np.zeros_like(u) for u in us]
+    z = np.zeros(prob.ncells)
+    g = _run(h, prob, t, p, T, zU, zu, z, z)
+    o = _oracle(op, prob, p, T, zU, zu, z, z)
+    for a in range(prob.dim):
+        _close(g["U"][a], o["U"][a], 1e-12)
+        _close(g["u"][a], o["u"][a], 1e-12)
+    _close(g["E1"], o["E1"], 1e-11)
+    _close(g["E2"], o["E2"], 1e-11)
+    # velocity increments with the energies: pressure work of the corrected
+    # flow only, and without surface tension
+    g = _run(h, prob, t, p, T, Us, us, z, z, kappa=False)
+    o = _oracle(op, prob, p, T, Us, us, z, z, kappa=False)
+    _close(g["E1"], o["E1"], 1e-11)
+    _close(g["E2"], o["E2"], 1e-11)
+
+
+@pytest.mark.parametrize("name", ["state2d_200x136", "state3d_66x6x10"])
+def test_optional_outputs(name):
+    """Without cell velocities and without the energy update, the face
+    velocities are the same; the energies alone (no cell velocities) too."""
+    prob = _case(name)
+    h, t = _handle(prob)
+    p, T = _fields(prob, 8)
+    Us = [u.reshape(-1) for u in prob.uf_star]
+    us = [u.reshape(-1) for u in prob.uc_star]
+    E1a, E2a = prob.E1.reshape(-1), prob.E2.reshape(-1)
+    full = _run(h, prob, t, p, T, Us, us, E1a, E2a)
+    faces = _run(h, prob, t, p, T, Us, us, E1a, E2a, cells=False, energy=False)
+    en = _run(h, prob, t, p, T, Us, us, E1a, E2a, cells=False)
+    for a in range(prob.dim):
+        assert np.array_equal(full["U"][a], faces["U"][a])
+        assert np.array_equal(full["U"][a], en["U"][a])
+    assert np.array_equal(full["E1"], en["E1"]) and np.array_equal(full["E2"], en["E2"])
+
+
+@pytest.mark.parametrize("name", ["state2d_1024", "state3d_256"])
+def test_downstream_full_size(name):
+    """The benchmarked grids, element by element (the oracle's C loops
+    finish in seconds at these sizes)."""
+    prob = _case(name)
+    print(f"downstream full {name} {prob.n}", flush=True)
+    h, t = _handle(prob)
+    op = orc.assemble(prob)
+    p, T = _fields(prob, 9)
+    Us = [u.reshape(-1) for u in prob.uf_star]
+    us = [u.reshape(-1) for u in prob.uc_star]
+    z = np.zeros(prob.ncells)
+    g = _run(h, prob, t, p, T, Us, us, z, z)
+    o = _oracle(op, prob, p, T, Us, us, z, z)
+    for a in range(prob.dim):
+        _close(g["U"][a], o["U"][a], 1e-14)
+        _close(g["u"][a], o["u"][a], 1e-14)
+    _close(g["E1"], o["E1"], 1e-11)
+    _close(g["E2"], o["E2"], 1e-11)
+    h.destroy()
+
+
+@pytest.mark.parametrize("name", ["state2d_1024", "state3d_66x6x10"])
+def test_total_energy_conserved_on_gpu(name):
+    """sigma = 0 and closed walls: the GPU's phase increments sum to zero
+    over the grid to rounding (each face flux cancels between its cells)."""
+    prob = _case(name)
+    h, t = _handle(prob)
+    p, T = _fields(prob, 10)
+    Us = [u.reshape(-1) for u in prob.uf_star]
+    z = np.zeros(prob.ncells)
+    g = _run(h, prob, t, p, T, Us, [np.zeros(prob.ncells)] * prob.dim, z, z, kappa=False)
+    scale = np.abs(g["E1"]).sum() + np.abs(g["E2"]).sum()
+    assert abs((g["E1"] + g["E2"]).sum()) <= 1e-12 * scale
+
+
+@pytest.mark.parametrize("name", ["state2d_200x136", "state3d_40x24x56"])
+def test_end_of_step_after_the_solve(name):
+    """The chain from the conserved variables: provisional state, div u*,
+    right-hand side, solve, end of the step, each side on its own; the
+    corrected velocities and energy increments agree to the solve's
+    tolerance."""
+    import workloads.device as D
+    prob = _case(name)
+    h, b_p, b_T, t = D.setup(prob, 0)
+    p, T = torch.empty_like(b_p), torch.empty_like(b_T)
+    info = h.solve(b_p, b_T, p, T, rtol=1e-13, max_cycles=60)
+    assert info["status"] == 0
+    z = np.zeros(prob.ncells)
+    Us = [u.reshape(-1) for u in prob.uf_star]
+    us = [u.reshape(-1) for u in prob.uc_star]
+    g = _run(h, prob, t, host(p), host(T), Us, us, z, z)
+    op, ob_p, ob_T, op_, oT = orc.solve(prob, rtol=1e-14)
+    o = _oracle(op, prob, op_, oT, Us, us, z, z)
+    for a in range(prob.dim):
+        dg, do = g["U"][a] - Us[a], o["U"][a] - Us[a]
+        assert rel_err(dg, do) <= 1e-6
+    assert rel_err(g["E1"], o["E1"]) <= 1e-6 and rel_err(g["E2"], o["E2"]) <= 1e-6
+    # the corrected divergence (Eq. 17) from the library's own kernels
+    Ud = [dev(u) for u in g["U"]]
+    d_new = host(h.divergence(Ud))
+    d_ref = orc.divergence(prob.dim, prob.n, prob.h, o["U"])
+    assert rel_err(d_new, d_ref) <= 1e-6
+
+
+def test_downstream_errors():
+    from paper_2206_11294_amd import ptmg
+    import workloads.device as D
+    prob = _case("state2d_200x136")
+    h, t = _handle(prob)
+    p, T = _fields(prob, 11)
+    Pd, Td = dev(p), dev(T)
+    Us = D.face_inputs(prob, t)
+    U = [torch.empty_like(u) for u in Us]
+    with pytest.raises(ptmg.PtMgError) as e:
+        h.downstream(Pd, Td, t["C"], Us, Us)       # in place
+    assert e.value.status == ptmg.PT_ERR_ARG
+    with pytest.raises(ptmg.PtMgError) as e:
+        h.downstream(Pd, Td, t["C"], Us, U, E1_adv=t["E1"], E2_adv=t["E2"], E1=Pd.clone())
+    assert e.value.status == ptmg.PT_ERR_ARG
+    with pytest.raises(ptmg.PtMgError) as e:
+        h.downstream(None, Td, t["C"], Us, U)
+    assert e.value.status == ptmg.PT_ERR_ARG
+    h.downstream(Pd, Td, t["C"], Us, U)           # faces only: fine
+    ex = W.explicit_const(32, 32)
+    s2, t2 = D.to_device(ex)
+    h2 = ptmg.PtMg(s2, ptmg.PT_PREC_FP64)
+    Ue = [torch.zeros((32 + (a == 0)) * (32 + (a == 1)), dtype=torch.float64, device="cuda")
+          for a in range(2)]
+    z = torch.zeros(32 * 32, dtype=torch.float64, device="cuda")
+    with pytest.raises(ptmg.PtMgError) as e:
+        h2.downstream(z, z, z, Ue, [torch.empty_like(u) for u in Ue])
+    assert e.value.status == ptmg.PT_ERR_STATE
+    # the divergence works in any mode
+    assert torch.count_nonzero(h2.divergence(Ue)).item() == 0

@@ -59,6 +59,7 @@ def to_device(prob: Problem, device="cuda") -> Tuple[ptmg.pt_problem, Dict[str, 
         s.dt = prob.dt
         if prob.div_ustar is not None:
             t["div"] = _dev(prob.div_ustar, device)
+        _end_of_step_inputs(prob, t, device)
     else:
         s.mode = ptmg.PT_COEF_PHASES
         t["C"] = _dev(prob.C, device)
@@ -76,7 +77,27 @@ def to_device(prob: Problem, device="cuda") -> Tuple[ptmg.pt_problem, Dict[str, 
         s.T_adv_const = prob.T_adv_const
         if prob.div_ustar is not None:
             t["div"] = _dev(prob.div_ustar, device)
+        _end_of_step_inputs(prob, t, device)
     return s, t
+
+
+def _end_of_step_inputs(prob: Problem, t: Dict[str, torch.Tensor], device) -> None:
+    """Device copies of the inputs of the end of the step: face and cell
+    velocities u*, phase energies after advection, curvature."""
+    if prob.uf_star is not None:
+        for a, u in enumerate(prob.uf_star):
+            t[f"Us{a}"] = _dev(u, device)
+    if prob.uc_star is not None:
+        for a, u in enumerate(prob.uc_star):
+            t[f"us{a}"] = _dev(u, device)
+    for key in ("E1", "E2", "kappa"):
+        if getattr(prob, key) is not None:
+            t[key] = _dev(getattr(prob, key), device)
+
+
+def face_inputs(prob: Problem, t: Dict[str, torch.Tensor]):
+    """The provisional face velocity tensors, one per axis."""
+    return [t[f"Us{a}"] for a in range(prob.dim)]
 
 
 def state_record(prob: Problem, t: Dict[str, torch.Tensor]) -> ptmg.pt_state:
@@ -107,5 +128,7 @@ def setup(prob: Problem, precision: Optional[int] = None, device="cuda", stream=
     if prob.mode == "explicit":
         b_p, b_T = t["f_p"], t["f_T"]
     else:
+        if "div" not in t and "Us0" in t:
+            t["div"] = h.divergence(face_inputs(prob, t))
         b_p, b_T = h.paper_rhs(t.get("p_adv"), t.get("T_adv"), t.get("div"))
     return h, b_p, b_T, t
