@@ -76,24 +76,27 @@ def _declare(lib):
                                         _D, _D, _D]),
         "orc_canonical_rhs": (None, [c_long, _D, _D, _D, _D, _D]),
         "orc_faces_from_cells": (None, [c_int, _I, _D, _D, _D]),
-        "orc_apply": (None, [c_int, _I, c_double, _D, _D, _D, _D, _D, _D]),
-        "orc_residual": (None, [c_int, _I, c_double, _D, _D, _D, _D, _D, _D, _D, _D]),
-        "orc_paper_residual": (None, [c_int, _I, c_double, _D, _D, _D, _D, _D, _D, _D, _D]),
-        "orc_lex_sweep": (None, [c_int, _I, c_double, _D, _D, _D, _D, _D, _D]),
-        "orc_rb_sweep": (None, [c_int, _I, c_double, _D, _D, _D, _D, _D, _D]),
+        "orc_apply": (None, [c_int, _I, c_double, _D, c_int, _D, _D, _D, _D, _D]),
+        "orc_residual": (None, [c_int, _I, c_double, _D, c_int, _D, _D, _D, _D, _D, _D, _D]),
+        "orc_paper_residual": (None, [c_int, _I, c_double, _D, c_int, _D, _D, _D, _D, _D,
+                                      _D, _D]),
+        "orc_lex_sweep": (None, [c_int, _I, c_double, _D, c_int, _D, _D, _D, _D, _D]),
+        "orc_rb_sweep": (None, [c_int, _I, c_double, _D, c_int, _D, _D, _D, _D, _D]),
         "orc_coarse_operator": (None, [c_int, _I, _D, _D, _D, _D]),
         "orc_restrict": (None, [c_int, _I, _D, _D, _D, _D]),
         "orc_prolong_add": (None, [c_int, _I, _D, _D, _D, _D]),
-        "orc_dense_matrix": (None, [c_int, _I, c_double, _D, _D, c_int, _D]),
+        "orc_dense_matrix": (None, [c_int, _I, c_double, _D, c_int, _D, c_int, _D]),
         "orc_lu": (c_int, [c_long, _D, _L]),
         "orc_lu_solve": (None, [c_long, _D, _L, _D]),
-        "orc_mg_solve": (c_int, [c_int, _I, c_double, _D, _D, _D, _D, _D, _D, _D, _D, _D,
+        "orc_mg_solve": (c_int, [c_int, _I, c_double, _D, c_int, _D, _D, _D, _D, _D, _D, _D,
+                                 _D,
                                  c_double, c_int, c_int, c_int, c_int, _D]),
         "orc_mg_levels": (c_int, [c_int, _I]),
-        "orc_divergence": (None, [c_int, _I, c_double, _PP, _D]),
+        "orc_divergence": (None, [c_int, _I, c_double, c_int, _PP, _D]),
         "orc_project": (None, [c_int, _I, c_double, c_double, _D, _D, _PP, _PP, _PP, _PP]),
         "orc_phase_pressures": (None, [c_long, _D, _D, _D, c_double, _D, _D]),
-        "orc_energy_update": (None, [c_int, _I, c_double, c_double, _D, _D, _D, _D, _D, _PP,
+        "orc_energy_update": (None, [c_int, _I, c_double, c_double, _D, c_int, _D, _D, _D, _D,
+                                     _PP,
                                      _D, _D, _D, _D]),
     }
     for name, (res, args) in sig.items():
@@ -142,7 +145,8 @@ class Operator:
     B: block [4, N] in the order (pp, pT, Tp, TT),
     lam: paper coefficients [4, N] (l1, l2, l3, l4) in phases mode, else None;
     p_adv, T_adv: the provisional state the operator was assembled at, when
-    the problem gives it through conserved variables (state mode).
+    the problem gives it through conserved variables (state mode);
+    axi: 1 for the axisymmetric r-z metric (y the radius), else 0.
     """
     dim: int
     n: Tuple[int, int, int]
@@ -154,6 +158,7 @@ class Operator:
     a_T: Optional[np.ndarray] = None
     p_adv: Optional[np.ndarray] = None
     T_adv: Optional[np.ndarray] = None
+    axi: int = 0
 
     @property
     def N(self) -> int:
@@ -227,13 +232,14 @@ def assemble(prob) -> Operator:
             raise ValueError(f"{bad} cells with a non-positive block")
         F = faces_from_cells(prob.dim, prob.n, a_p, a_T)
         return Operator(prob.dim, prob.n, prob.h, F, B.reshape(4, N), lam.reshape(4, N),
-                        a_p, a_T, p_adv, T_adv)
+                        a_p, a_T, p_adv, T_adv, axi=_axi(prob))
     if prob.mode == "explicit":
         a_p = np.full(N, float(prob.alpha_p))
         a_T = np.full(N, float(prob.alpha_T))
         B = np.repeat(np.asarray(prob.B_const, dtype=np.float64)[:, None], N, axis=1)
         F = faces_from_cells(prob.dim, prob.n, a_p, a_T)
-        return Operator(prob.dim, prob.n, prob.h, F, np.ascontiguousarray(B), None, a_p, a_T)
+        return Operator(prob.dim, prob.n, prob.h, F, np.ascontiguousarray(B), None, a_p, a_T,
+                        axi=_axi(prob))
     C = _f64(prob.C)
     a_p, a_T = np.zeros(N), np.zeros(N)
     lam, B = np.zeros(4 * N), np.zeros(4 * N)
@@ -247,7 +253,15 @@ def assemble(prob) -> Operator:
         raise ValueError(f"{bad} cells with a non-positive block")
     F = faces_from_cells(prob.dim, prob.n, a_p, a_T)
     return Operator(prob.dim, prob.n, prob.h, F, B.reshape(4, N), lam.reshape(4, N),
-                    a_p, a_T)
+                    a_p, a_T, axi=_axi(prob))
+
+
+def _axi(prob) -> int:
+    """1 for an axisymmetric r-z problem (2-D only)."""
+    axi = int(bool(getattr(prob, "axisymmetric", False)))
+    if axi and prob.dim != 2:
+        raise ValueError("the axisymmetric metric needs a 2-D grid")
+    return axi
 
 
 def paper_rhs(op: Operator, prob) -> Tuple[np.ndarray, np.ndarray]:
@@ -261,7 +275,7 @@ def paper_rhs(op: Operator, prob) -> Tuple[np.ndarray, np.ndarray]:
         p_adv, T_adv = op.p_adv, op.T_adv
     div = None if prob.div_ustar is None else _f64(prob.div_ustar)
     if div is None and getattr(prob, "uf_star", None) is not None:
-        div = divergence(prob.dim, prob.n, prob.h, prob.uf_star)
+        div = divergence(prob.dim, prob.n, prob.h, prob.uf_star, op.axi)
     _load().orc_paper_rhs(N, _d(lam), _d(p_adv), prob.p_adv_const, _d(T_adv),
                           prob.T_adv_const, _d(div), prob.dt, _d(b_p), _d(b_T))
     return b_p, b_T
@@ -291,7 +305,7 @@ def _fb(op: Operator):
 def apply(op: Operator, p, T) -> Tuple[np.ndarray, np.ndarray]:
     F, B = _fb(op)
     Ap, AT = np.zeros(op.N), np.zeros(op.N)
-    _load().orc_apply(op.dim, _dims(op.n), op.h, _d(F), _d(B), _d(_f64(p)), _d(_f64(T)),
+    _load().orc_apply(op.dim, _dims(op.n), op.h, _d(F), op.axi, _d(B), _d(_f64(p)), _d(_f64(T)),
                       _d(Ap), _d(AT))
     return Ap, AT
 
@@ -299,7 +313,7 @@ def apply(op: Operator, p, T) -> Tuple[np.ndarray, np.ndarray]:
 def residual(op: Operator, f_p, f_T, p, T) -> Tuple[np.ndarray, np.ndarray]:
     F, B = _fb(op)
     rp, rT = np.zeros(op.N), np.zeros(op.N)
-    _load().orc_residual(op.dim, _dims(op.n), op.h, _d(F), _d(B), _d(_f64(f_p)),
+    _load().orc_residual(op.dim, _dims(op.n), op.h, _d(F), op.axi, _d(B), _d(_f64(f_p)),
                          _d(_f64(f_T)), _d(_f64(p)), _d(_f64(T)), _d(rp), _d(rT))
     return rp, rT
 
@@ -309,7 +323,7 @@ def paper_residual(op: Operator, b_p, b_T, p, T) -> Tuple[np.ndarray, np.ndarray
     F, _ = _fb(op)
     lam = np.ascontiguousarray(op.lam).reshape(-1)
     rp, rT = np.zeros(op.N), np.zeros(op.N)
-    _load().orc_paper_residual(op.dim, _dims(op.n), op.h, _d(F), _d(lam), _d(_f64(b_p)),
+    _load().orc_paper_residual(op.dim, _dims(op.n), op.h, _d(F), op.axi, _d(lam), _d(_f64(b_p)),
                                _d(_f64(b_T)), _d(_f64(p)), _d(_f64(T)), _d(rp), _d(rT))
     return rp, rT
 
@@ -332,7 +346,8 @@ def sweep(op: Operator, f_p, f_T, p, T, order: str = "rb"):
     F, B = _fb(op)
     fn = _load().orc_rb_sweep if order == "rb" else _load().orc_lex_sweep
     assert p.dtype == np.float64 and T.dtype == np.float64
-    fn(op.dim, _dims(op.n), op.h, _d(F), _d(B), _d(_f64(f_p)), _d(_f64(f_T)), _d(p), _d(T))
+    fn(op.dim, _dims(op.n), op.h, _d(F), op.axi, _d(B), _d(_f64(f_p)), _d(_f64(f_T)), _d(p),
+       _d(T))
 
 
 def coarse_dims(dim, n):
@@ -345,7 +360,7 @@ def coarse_operator(op: Operator) -> Operator:
     F, B = _fb(op)
     Fc, Bc = np.zeros(6 * Nc), np.zeros(4 * Nc)
     _load().orc_coarse_operator(op.dim, _dims(op.n), _d(F), _d(B), _d(Fc), _d(Bc))
-    return Operator(op.dim, nc, 2 * op.h, Fc.reshape(6, Nc), Bc.reshape(4, Nc))
+    return Operator(op.dim, nc, 2 * op.h, Fc.reshape(6, Nc), Bc.reshape(4, Nc), axi=op.axi)
 
 
 def restrict(dim, n, r_p, r_T):
@@ -365,7 +380,8 @@ def dense_matrix(op: Operator, pin_mean: bool = False) -> np.ndarray:
     F, B = _fb(op)
     m = 2 * op.N
     M = np.zeros(m * m)
-    _load().orc_dense_matrix(op.dim, _dims(op.n), op.h, _d(F), _d(B), int(pin_mean), _d(M))
+    _load().orc_dense_matrix(op.dim, _dims(op.n), op.h, _d(F), op.axi, _d(B), int(pin_mean),
+                             _d(M))
     return M.reshape(m, m)
 
 
@@ -405,7 +421,7 @@ def mg_solve(op: Operator, b_p, b_T, p0=None, T0=None, rtol: float = 1e-13,
     hist = np.zeros(2 * (max_cycles + 2))
     F, B = _fb(op)
     lam = None if op.lam is None else np.ascontiguousarray(op.lam).reshape(-1)
-    cyc = _load().orc_mg_solve(op.dim, _dims(op.n), op.h, _d(F), _d(B), _d(lam),
+    cyc = _load().orc_mg_solve(op.dim, _dims(op.n), op.h, _d(F), op.axi, _d(B), _d(lam),
                                _d(b_p), _d(b_T), _d(f_p), _d(f_T), _d(p), _d(T),
                                rtol, max_cycles, nu1, nu2, int(pin_mean), _d(hist))
     ncyc = max_cycles if cyc < 0 else cyc
@@ -432,12 +448,17 @@ def sparse_matrix(op: Operator):
             w = (Fa[tuple(sl_hi)] * inv_h2).reshape(-1)
             i_hi = idx[tuple(sl_hi)].reshape(-1)
             i_lo = idx[tuple(sl_lo)].reshape(-1)
+            w_hi, w_lo = w, w          # the face's weight in its upper / lower cell's row
+            if op.axi and a == 1:
+                jf = (i_hi // nx) % ny   # radius of the face, in units of h
+                w_hi = w * jf / (jf + 0.5)
+                w_lo = w * jf / (jf - 0.5)
             off = c * N
             rows += [i_hi + off, i_lo + off]
             cols += [i_lo + off, i_hi + off]
-            vals += [-w, -w]
-            np.add.at(diag, i_hi, w)
-            np.add.at(diag, i_lo, w)
+            vals += [-w_hi, -w_lo]
+            np.add.at(diag, i_hi, w_hi)
+            np.add.at(diag, i_lo, w_lo)
         rows.append(np.arange(N) + c * N)
         cols.append(np.arange(N) + c * N)
         vals.append(diag + op.B[0 if c == 0 else 3])
@@ -484,11 +505,11 @@ def face_shape(dim, n, a) -> Tuple[int, ...]:
     return tuple(m[dim - 1 - b] for b in range(dim))
 
 
-def divergence(dim, n, h, U) -> np.ndarray:
+def divergence(dim, n, h, U, axi: int = 0) -> np.ndarray:
     """Discrete div of face velocities U[a] (the div u* of Eqs. 17, 34)."""
     Us = [_f64(u) for u in U]
     out = np.zeros(int(n[0]) * int(n[1]) * int(n[2]))
-    _load().orc_divergence(dim, _dims(n), h, _dp(Us), _d(out))
+    _load().orc_divergence(dim, _dims(n), h, int(axi), _dp(Us), _d(out))
     return out
 
 
@@ -520,7 +541,7 @@ def energy_update(op: Operator, dt: float, C, p1, p2, T, U, E1_adv, E2_adv):
     E1, E2 = np.zeros_like(E1a), np.zeros_like(E2a)
     F, _ = _fb(op)
     Us = [_f64(u) for u in U]
-    _load().orc_energy_update(op.dim, _dims(op.n), op.h, dt, _d(F), _d(_f64(C)), _d(_f64(p1)),
+    _load().orc_energy_update(op.dim, _dims(op.n), op.h, dt, _d(F), op.axi, _d(_f64(C)), _d(_f64(p1)),
                               _d(_f64(p2)), _d(_f64(T)), _dp(Us), _d(E1a), _d(E2a), _d(E1),
                               _d(E2))
     return E1, E2

@@ -8,7 +8,7 @@
  * What it computes (Saade, Lohse & Fuster, "A multigrid solver for the
  * coupled pressure-temperature equations in an all-Mach solver with VoF"):
  *
- *   paper form (Eqs. 27-28), a = [T p]:
+ *   paper form (Eqs. 27-28), a = [T p], per unit volume:
  *     div(k grad T) + l1 T + l2 p            = lT
  *     div(grad p / rho) + l3 p + l4 div(k grad T) = lp
  *   with l1..l4, lT, lp of Eqs. 29-34 (l4 read as beta/(rho c_p dt), the
@@ -20,6 +20,10 @@
  *     -div(a_T grad T) + BTp p + BTT T = f_T,   a_T = k
  *     Bpp = -l3 + l4 l2, BpT = l4 l1, BTp = -l2, BTT = -l1,
  *     f_T = -lT, f_p = -lp + l4 lT.
+ *
+ * Geometry: Cartesian 2-D / 3-D, or axisymmetric r-z (2-D, y the radius
+ * from the axis on the lower y wall; every diffusion term and divergence
+ * then carries the face-area / cell-volume metric of axi_face).
  *
  * Discretisation: cell-centred finite volumes on a uniform grid of spacing h
  * (second order, as the paper states in Sec. 4.1), homogeneous Neumann
@@ -297,10 +301,23 @@ void orc_faces_from_cells(int dim, const int *n, const double *a_p,
         }
 }
 
+/* Axisymmetric (r-z) metric: y is the radius, measured from the axis on
+ * the lower y wall.  In units of the grid spacing the lower face of row j
+ * is at r = j and the cell centre at r = j + 1/2.  A finite volume's
+ * radial faces have areas proportional to their radius and its axial faces
+ * and volume to the centre radius, so per unit volume a radial face counts
+ * r_face / r_centre and an axial face 1 (the cylindrical divergence
+ * (1/r) d/dr (r a du/dr) + d/dz (a du/dz)). */
+static double axi_face(long j_face, long j_cell)
+{
+    return (double)j_face / ((double)j_cell + 0.5);
+}
+
 /* Diffusion part of the canonical operator at one cell, component c:
- * sum over faces of a_f (u_i - u_nbr) / h^2 (zero flux through the
- * boundary).  Also returns the sum of face coefficients / h^2. */
-static double diffusion_at(int dim, const int *n, double h, const double *F,
+ * sum over faces of m_f a_f (u_i - u_nbr) / h^2 (zero flux through the
+ * boundary), m_f = 1, or the r-z metric of axi_face on radial faces when
+ * axi.  Also returns the sum of the face weights. */
+static double diffusion_at(int dim, const int *n, double h, const double *F, int axi,
                            int c, const double *u, long i, long j, long k,
                            double *diag)
 {
@@ -316,6 +333,7 @@ static double diffusion_at(int dim, const int *n, double h, const double *F,
             t[a] -= 1;
             long lo = idx3(n, t[0], t[1], t[2]);
             double w = Fa[me] * inv_h2;
+            if (axi && a == 1) w *= axi_face(j, j);
             acc += w * (u[me] - u[lo]);
             dsum += w;
         }
@@ -324,6 +342,7 @@ static double diffusion_at(int dim, const int *n, double h, const double *F,
             t[a] += 1;
             long hi = idx3(n, t[0], t[1], t[2]);
             double w = Fa[hi] * inv_h2;
+            if (axi && a == 1) w *= axi_face(j + 1, j);
             acc += w * (u[me] - u[hi]);
             dsum += w;
         }
@@ -333,7 +352,7 @@ static double diffusion_at(int dim, const int *n, double h, const double *F,
 }
 
 /* A u in canonical form.  B is component-major [4n]. */
-void orc_apply(int dim, const int *n, double h, const double *F, const double *B,
+void orc_apply(int dim, const int *n, double h, const double *F, int axi, const double *B,
                const double *p, const double *T, double *Ap, double *AT)
 {
     long N = (long)n[0] * n[1] * n[2];
@@ -342,20 +361,20 @@ void orc_apply(int dim, const int *n, double h, const double *F, const double *B
         for (long j = 0; j < n[1]; j++)
             for (long i = 0; i < n[0]; i++) {
                 long me = idx3(n, i, j, k);
-                double dp = diffusion_at(dim, n, h, F, 0, p, i, j, k, NULL);
-                double dT = diffusion_at(dim, n, h, F, 1, T, i, j, k, NULL);
+                double dp = diffusion_at(dim, n, h, F, axi, 0, p, i, j, k, NULL);
+                double dT = diffusion_at(dim, n, h, F, axi, 1, T, i, j, k, NULL);
                 Ap[me] = dp + B[0 * N + me] * p[me] + B[1 * N + me] * T[me];
                 AT[me] = dT + B[2 * N + me] * p[me] + B[3 * N + me] * T[me];
             }
 }
 
 /* r = f - A u (canonical form). */
-void orc_residual(int dim, const int *n, double h, const double *F, const double *B,
+void orc_residual(int dim, const int *n, double h, const double *F, int axi, const double *B,
                   const double *f_p, const double *f_T, const double *p,
                   const double *T, double *r_p, double *r_T)
 {
     long N = (long)n[0] * n[1] * n[2];
-    orc_apply(dim, n, h, F, B, p, T, r_p, r_T);
+    orc_apply(dim, n, h, F, axi, B, p, T, r_p, r_T);
 #pragma omp parallel for schedule(static)
     for (long i = 0; i < N; i++) {
         r_p[i] = f_p[i] - r_p[i];
@@ -367,7 +386,7 @@ void orc_residual(int dim, const int *n, double h, const double *F, const double
  * res_T = bT - (div(k grad T) + l1 T + l2 p),
  * res_p = bp - (div(grad p/rho) + l3 p + l4 div(k grad T)).
  * Here div(a grad u) at a cell = -(diffusion_at). */
-void orc_paper_residual(int dim, const int *n, double h, const double *F,
+void orc_paper_residual(int dim, const int *n, double h, const double *F, int axi,
                         const double *lam, const double *b_p, const double *b_T,
                         const double *p, const double *T, double *res_p,
                         double *res_T)
@@ -378,8 +397,8 @@ void orc_paper_residual(int dim, const int *n, double h, const double *F,
         for (long j = 0; j < n[1]; j++)
             for (long i = 0; i < n[0]; i++) {
                 long me = idx3(n, i, j, k);
-                double divp = -diffusion_at(dim, n, h, F, 0, p, i, j, k, NULL);
-                double divT = -diffusion_at(dim, n, h, F, 1, T, i, j, k, NULL);
+                double divp = -diffusion_at(dim, n, h, F, axi, 0, p, i, j, k, NULL);
+                double divT = -diffusion_at(dim, n, h, F, axi, 1, T, i, j, k, NULL);
                 double l1 = lam[me], l2 = lam[N + me], l3 = lam[2 * N + me],
                        l4 = lam[3 * N + me];
                 res_T[me] = b_T[me] - (divT + l1 * T[me] + l2 * p[me]);
@@ -399,7 +418,7 @@ static double dot(long N, const double *x, const double *y)
 /* ------------------------------------------------------------------ */
 
 /* Solve the 2x2 block equations of one cell with its neighbours fixed. */
-static void block_update(int dim, const int *n, double h, const double *F,
+static void block_update(int dim, const int *n, double h, const double *F, int axi,
                          const double *B, const double *f_p, const double *f_T,
                          double *p, double *T, long i, long j, long k)
 {
@@ -408,8 +427,8 @@ static void block_update(int dim, const int *n, double h, const double *F,
     double sp, sT;
     /* diffusion_at(u) = S u_me - sum w u_nbr, so the neighbour sum is
      * S u_me - diffusion_at(u). */
-    double dp = diffusion_at(dim, n, h, F, 0, p, i, j, k, &sp);
-    double dT = diffusion_at(dim, n, h, F, 1, T, i, j, k, &sT);
+    double dp = diffusion_at(dim, n, h, F, axi, 0, p, i, j, k, &sp);
+    double dT = diffusion_at(dim, n, h, F, axi, 1, T, i, j, k, &sT);
     double gp = f_p[me] + (sp * p[me] - dp);
     double gT = f_T[me] + (sT * T[me] - dT);
     double a = B[0 * N + me] + sp, b = B[1 * N + me];
@@ -420,18 +439,18 @@ static void block_update(int dim, const int *n, double h, const double *F,
 }
 
 /* One lexicographic block Gauss-Seidel sweep (x fastest). */
-void orc_lex_sweep(int dim, const int *n, double h, const double *F, const double *B,
+void orc_lex_sweep(int dim, const int *n, double h, const double *F, int axi, const double *B,
                    const double *f_p, const double *f_T, double *p, double *T)
 {
     for (long k = 0; k < n[2]; k++)
         for (long j = 0; j < n[1]; j++)
             for (long i = 0; i < n[0]; i++)
-                block_update(dim, n, h, F, B, f_p, f_T, p, T, i, j, k);
+                block_update(dim, n, h, F, axi, B, f_p, f_T, p, T, i, j, k);
 }
 
 /* One red-black block Gauss-Seidel sweep: cells with (i+j+k) even first,
  * then the odd ones, each using the latest neighbour values. */
-void orc_rb_sweep(int dim, const int *n, double h, const double *F, const double *B,
+void orc_rb_sweep(int dim, const int *n, double h, const double *F, int axi, const double *B,
                   const double *f_p, const double *f_T, double *p, double *T)
 {
     for (int colour = 0; colour < 2; colour++)
@@ -439,7 +458,7 @@ void orc_rb_sweep(int dim, const int *n, double h, const double *F, const double
             for (long j = 0; j < n[1]; j++)
                 for (long i = 0; i < n[0]; i++)
                     if (((i + j + k) & 1) == colour)
-                        block_update(dim, n, h, F, B, f_p, f_T, p, T, i, j, k);
+                        block_update(dim, n, h, F, axi, B, f_p, f_T, p, T, i, j, k);
 }
 
 /* Coarse grid of n: every axis < dim halved. */
@@ -563,7 +582,7 @@ void orc_prolong_add(int dim, const int *n, const double *e_p, const double *e_T
  * `pin_mean`, the all-ones block (scaled by the mean diagonal) is added to
  * each component's diagonal block, which fixes the constant mode of a pure
  * Neumann Poisson problem to zero mean for a zero-mean right-hand side. */
-void orc_dense_matrix(int dim, const int *n, double h, const double *F,
+void orc_dense_matrix(int dim, const int *n, double h, const double *F, int axi,
                       const double *B, int pin_mean, double *M)
 {
     long N = (long)n[0] * n[1] * n[2];
@@ -575,8 +594,8 @@ void orc_dense_matrix(int dim, const int *n, double h, const double *F,
     for (long col = 0; col < M2; col++) {
         memset(e, 0, sizeof(double) * N);
         e[col % N] = 1.0;
-        if (col < N) orc_apply(dim, n, h, F, B, e, z, Ap, AT);
-        else orc_apply(dim, n, h, F, B, z, e, Ap, AT);
+        if (col < N) orc_apply(dim, n, h, F, axi, B, e, z, Ap, AT);
+        else orc_apply(dim, n, h, F, axi, B, z, e, Ap, AT);
         for (long r = 0; r < N; r++) {
             M[r * M2 + col] = Ap[r];
             M[(N + r) * M2 + col] = AT[r];
@@ -646,7 +665,7 @@ typedef struct {
 } orc_level;
 
 typedef struct {
-    int dim, nlev, pin_mean;
+    int dim, nlev, pin_mean, axi;
     orc_level L[ORC_MAX_LEVELS];
     double *LU;
     long *piv;
@@ -682,11 +701,12 @@ static int can_coarsen(int dim, const int *n)
     return 1;
 }
 
-static void mg_build(orc_mg *mg, int dim, const int *n, double h, const double *F0,
+static void mg_build(orc_mg *mg, int dim, const int *n, double h, const double *F0, int axi,
                      const double *B0, int pin_mean)
 {
     memset(mg, 0, sizeof(*mg));
     mg->dim = dim;
+    mg->axi = axi;
     mg->pin_mean = pin_mean;
     level_alloc(&mg->L[0], n, h);
     memcpy(mg->L[0].F, F0, sizeof(double) * 6 * mg->L[0].N);
@@ -705,7 +725,7 @@ static void mg_build(orc_mg *mg, int dim, const int *n, double h, const double *
     mg->m = 2 * c->N;
     mg->LU = malloc(sizeof(double) * mg->m * mg->m);
     mg->piv = malloc(sizeof(long) * mg->m);
-    orc_dense_matrix(dim, c->n, c->h, c->F, c->B, pin_mean, mg->LU);
+    orc_dense_matrix(dim, c->n, c->h, c->F, axi, c->B, pin_mean, mg->LU);
     orc_lu(mg->m, mg->LU, mg->piv);
 }
 
@@ -739,15 +759,17 @@ static void vcycle(orc_mg *mg, int l, int nu1, int nu2)
         return;
     }
     for (int s = 0; s < nu1; s++)
-        orc_lex_sweep(dim, lv->n, lv->h, lv->F, lv->B, lv->f_p, lv->f_T, lv->u_p, lv->u_T);
-    orc_residual(dim, lv->n, lv->h, lv->F, lv->B, lv->f_p, lv->f_T, lv->u_p, lv->u_T,
+        orc_lex_sweep(dim, lv->n, lv->h, lv->F, mg->axi, lv->B, lv->f_p, lv->f_T, lv->u_p,
+                      lv->u_T);
+    orc_residual(dim, lv->n, lv->h, lv->F, mg->axi, lv->B, lv->f_p, lv->f_T, lv->u_p, lv->u_T,
                  lv->r_p, lv->r_T);
     orc_level *cv = &mg->L[l + 1];
     orc_restrict(dim, lv->n, lv->r_p, lv->r_T, cv->f_p, cv->f_T);
     vcycle(mg, l + 1, nu1, nu2);
     orc_prolong_add(dim, lv->n, cv->u_p, cv->u_T, lv->u_p, lv->u_T);
     for (int s = 0; s < nu2; s++)
-        orc_lex_sweep(dim, lv->n, lv->h, lv->F, lv->B, lv->f_p, lv->f_T, lv->u_p, lv->u_T);
+        orc_lex_sweep(dim, lv->n, lv->h, lv->F, mg->axi, lv->B, lv->f_p, lv->f_T, lv->u_p,
+                      lv->u_T);
 }
 
 /*
@@ -762,14 +784,14 @@ static void vcycle(orc_mg *mg, int l, int nu1, int nu2)
  * hist (may be NULL) receives 2 numbers per residual evaluation.
  * Returns the number of V-cycles performed, or -1 if max_cycles was hit.
  */
-int orc_mg_solve(int dim, const int *n, double h, const double *F, const double *B,
+int orc_mg_solve(int dim, const int *n, double h, const double *F, int axi, const double *B,
                  const double *lam, const double *b_p, const double *b_T,
                  const double *f_p, const double *f_T, double *p, double *T,
                  double rtol, int max_cycles, int nu1, int nu2, int pin_mean,
                  double *hist)
 {
     orc_mg mg;
-    mg_build(&mg, dim, n, h, F, B, pin_mean);
+    mg_build(&mg, dim, n, h, F, axi, B, pin_mean);
     orc_level *l0 = &mg.L[0];
     long N = l0->N;
     memcpy(l0->f_p, f_p, sizeof(double) * N);
@@ -780,8 +802,8 @@ int orc_mg_solve(int dim, const int *n, double h, const double *F, const double 
     double *rfp = malloc(sizeof(double) * N), *rfT = malloc(sizeof(double) * N);
     int cycles = 0, done = 0;
     for (;;) {
-        if (lam) orc_paper_residual(dim, n, h, F, lam, b_p, b_T, p, T, rp, rT);
-        else orc_residual(dim, n, h, F, B, f_p, f_T, p, T, rp, rT);
+        if (lam) orc_paper_residual(dim, n, h, F, axi, lam, b_p, b_T, p, T, rp, rT);
+        else orc_residual(dim, n, h, F, axi, B, f_p, f_T, p, T, rp, rT);
         double rel[2];
         rel[0] = bn[0] > 0 ? sqrt(dot(N, rp, rp)) / bn[0] : sqrt(dot(N, rp, rp));
         rel[1] = bn[1] > 0 ? sqrt(dot(N, rT, rT)) / bn[1] : sqrt(dot(N, rT, rT));
@@ -789,7 +811,7 @@ int orc_mg_solve(int dim, const int *n, double h, const double *F, const double 
         if (rel[0] <= rtol && rel[1] <= rtol) { done = 1; break; }
         if (cycles >= max_cycles) break;
         /* correction equation in canonical form */
-        orc_residual(dim, n, h, l0->F, l0->B, f_p, f_T, p, T, rfp, rfT);
+        orc_residual(dim, n, h, l0->F, axi, l0->B, f_p, f_T, p, T, rfp, rfT);
         memcpy(l0->f_p, rfp, sizeof(double) * N);
         memcpy(l0->f_T, rfT, sizeof(double) * N);
         vcycle(&mg, 0, nu1, nu2);
@@ -830,9 +852,11 @@ static long fidx(const int *n, int a, long i, long j, long k)
 }
 
 /* Discrete divergence of face velocities: the sum over axes of
- * (U on the upper face - U on the lower face) / h.  This is the div u* of
- * Eq. (17) and of lambda_p in Eq. (34). */
-void orc_divergence(int dim, const int *n, double h, const double *const *U, double *div)
+ * (m_hi U on the upper face - m_lo U on the lower face) / h, m = 1 or the
+ * r-z metric of axi_face on radial faces.  This is the div u* of Eq. (17)
+ * and of lambda_p in Eq. (34). */
+void orc_divergence(int dim, const int *n, double h, int axi, const double *const *U,
+                    double *div)
 {
     for (long k = 0; k < n[2]; k++)
         for (long j = 0; j < n[1]; j++)
@@ -841,7 +865,10 @@ void orc_divergence(int dim, const int *n, double h, const double *const *U, dou
                 for (int a = 0; a < dim; a++) {
                     long up[3] = {i, j, k};
                     up[a] += 1;
-                    s += (U[a][fidx(n, a, up[0], up[1], up[2])] - U[a][fidx(n, a, i, j, k)]) / h;
+                    double m_lo = 1.0, m_hi = 1.0;
+                    if (axi && a == 1) { m_lo = axi_face(j, j); m_hi = axi_face(j + 1, j); }
+                    s += (m_hi * U[a][fidx(n, a, up[0], up[1], up[2])]
+                          - m_lo * U[a][fidx(n, a, i, j, k)]) / h;
                 }
                 div[idx3(n, i, j, k)] = s;
             }
@@ -916,8 +943,9 @@ void orc_phase_pressures(long N, const double *p, const double *C, const double 
  * the heat flux -q_i = k grad T^{n+1} being the one of the T equation (face
  * coefficient F[3 + a], zero through the walls).  The pressure-work flux on
  * a face is the mean of the two cells' p_i times the face velocity; on a
- * wall face the cell's own p_i (zero normal gradient, as in the solve). */
-void orc_energy_update(int dim, const int *n, double h, double dt, const double *F,
+ * wall face the cell's own p_i (zero normal gradient, as in the solve).
+ * With axi, the flux differences carry the r-z metric of the divergence. */
+void orc_energy_update(int dim, const int *n, double h, double dt, const double *F, int axi,
                        const double *C, const double *p1, const double *p2, const double *T,
                        const double *const *U, const double *E1a, const double *E2a,
                        double *E1, double *E2)
@@ -952,9 +980,11 @@ void orc_energy_update(int dim, const int *n, double h, double dt, const double 
                         P2hi = 0.5 * (p2[c] + p2[R]);
                         q_hi = F[(long)(3 + a) * N + R] * (T[R] - T[c]) / h;
                     }
-                    w1 += (P1hi * u_hi - P1lo * u_lo) / h;
-                    w2 += (P2hi * u_hi - P2lo * u_lo) / h;
-                    q += (q_hi - q_lo) / h;
+                    double m_lo = 1.0, m_hi = 1.0;
+                    if (axi && a == 1) { m_lo = axi_face(j, j); m_hi = axi_face(j + 1, j); }
+                    w1 += (m_hi * P1hi * u_hi - m_lo * P1lo * u_lo) / h;
+                    w2 += (m_hi * P2hi * u_hi - m_lo * P2lo * u_lo) / h;
+                    q += (m_hi * q_hi - m_lo * q_lo) / h;
                 }
                 E1[c] = E1a[c] + dt * C[c] * (-w1 + q);
                 E2[c] = E2a[c] + dt * (1.0 - C[c]) * (-w2 + q);

@@ -124,6 +124,9 @@ class Problem:
     E2: Optional[np.ndarray] = None         # (1 - C) rho_2 e_T,2 after advection
     kappa: Optional[np.ndarray] = None      # interface curvature [1/m]
     sigma: float = 0.0                      # surface tension [N/m]
+    # axisymmetric r-z grid (2-D): x is the axis direction, y the radius
+    # from the axis on the lower y wall
+    axisymmetric: bool = False
 
     @property
     def ncells(self) -> int:
