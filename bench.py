@@ -44,6 +44,7 @@ WORKLOADS = {
     "collapse3d_512": ("collapse3d", "mixed", 1e-12),
     "state2d_1024": ("state2d", "fp64", 1e-12),
     "state3d_256": ("state3d", "mixed", 1e-12),
+    "axi2d_1024": ("axi2d", "fp64", 1e-12),
 }
 
 
@@ -63,6 +64,8 @@ def make_problem(name, stiff=False):
         return W.state2d(1024)
     if name == "state3d_256":
         return W.state3d(256)
+    if name == "axi2d_1024":
+        return W.axi2d(1024)
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -461,6 +464,7 @@ def main():
         "dtype": "f64" if prec_name == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": {"workload": name, "grid": list(prob.n[: prob.dim]), "precision": prec_name,
+                   "geometry": "axisymmetric r-z" if prob.axisymmetric else "cartesian",
                    "rtol": rtol, "cycles_per_solve": float(np.mean(cycles)),
                    "step": ("pt_state_eval + " if prob.mode == "state" else "")
                    + "pt_mg_update + "

@@ -117,6 +117,17 @@ typedef struct {
      * is weighted by its fraction as in PT_COEF_PHASES, a_p = 1/(m1 + m2),
      * a_T = C k_1 + (1 - C) k_2. */
     const double *m1, *m2;
+    /* 1: axisymmetric r-z grid (2-D only, else PT_ERR_ARG), the geometry of
+     * the paper's bubble computations (Sec. 4): x is the axial and y the
+     * radial coordinate, the axis is the lower y boundary, and cell row j
+     * lies between the radii j h and (j + 1) h.  Every equation is per unit
+     * volume with the cylindrical divergence: a radial face between rows
+     * j - 1 and j counts, in the row-i equation, its coefficient times
+     * r_face / r_i (areas proportional to the radius, volumes to the
+     * centre radius), so no flux crosses the axis; axial faces are
+     * unchanged.  The same metric applies in pt_mg_divergence and
+     * pt_mg_downstream.  0: Cartesian. */
+    int axisymmetric;
 } pt_problem;
 
 typedef struct {

@@ -32,6 +32,7 @@ struct Plan {
     long long N = 0;
     LevelPlan lv[kMaxLevels];
     size_t o_ac64, o_B64, o_xp, o_xT, o_partials, o_flags, o_gj0, o_gj1;
+    size_t o_axm64 = (size_t)-1, o_axm32 = (size_t)-1;   // r-z metric per finest row
     size_t total = 0;
     size_t take(size_t bytes)
     {
@@ -62,6 +63,8 @@ const char *plan_problem(const pt_problem *p, int prec, Plan &P)
         if (p->n[a] > (1 << 20)) return "grid too large";
     }
     if (!(p->h > 0.0) || !std::isfinite(p->h)) return "h must be positive";
+    if (p->axisymmetric != 0 && p->axisymmetric != 1) return "axisymmetric must be 0 or 1";
+    if (p->axisymmetric && p->dim != 2) return "the axisymmetric metric needs a 2-D grid";
     if (p->mode != PT_COEF_EXPLICIT && p->mode != PT_COEF_PHASES && p->mode != PT_COEF_STATE)
         return "unknown mode";
     if (p->mode == PT_COEF_STATE) {
@@ -102,6 +105,10 @@ const char *plan_problem(const pt_problem *p, int prec, Plan &P)
     P.o_B64 = P.take(32 * P.N);
     P.o_xp = P.take(8 * P.N);
     P.o_xT = P.take(8 * P.N);
+    if (p->axisymmetric) {
+        P.o_axm64 = P.take(32ull * p->n[1]);
+        if (prec == PT_PREC_MIXED) P.o_axm32 = P.take(16ull * p->n[1]);
+    }
     // hierarchy
     int n[3] = {p->n[0], p->n[1], p->n[2]};
     double h = p->h;
@@ -255,8 +262,14 @@ struct pt_mg_s {
             o.ac = at<typename VT<R>::v2>(L.o_ac);
             o.B = at<typename VT<R>::v4>(L.o_B);
         }
+        o.axm = nullptr;
+        if (l == 0)
+            o.axm = (const typename VT<R>::v4 *)(sizeof(R) == 8 ? (void *)axm64()
+                                                                : (void *)at<float4>(P.o_axm32));
         return o;
     }
+    // r-z metric of the finest rows (null on Cartesian grids)
+    double4 *axm64() { return at<double4>(P.o_axm64); }
     // FP64 view of the finest-grid operator (coarsening source, exports).
     Lvl<double> level0_fp64()
     {
@@ -265,6 +278,7 @@ struct pt_mg_s {
         o.f = nullptr;
         o.ac = ac64();
         o.B = B64();
+        o.axm = axm64();
         return o;
     }
 
@@ -790,7 +804,8 @@ void plan_tail(pt_mg_t h)
 bool same_grid(const pt_problem *a, const pt_problem *b)
 {
     return a->dim == b->dim && a->n[0] == b->n[0] && a->n[1] == b->n[1] && a->n[2] == b->n[2] &&
-           a->h == b->h && a->mode == b->mode && a->mean_constraint == b->mean_constraint;
+           a->h == b->h && a->mode == b->mode && a->mean_constraint == b->mean_constraint &&
+           a->axisymmetric == b->axisymmetric;
 }
 
 double elapsed(std::chrono::steady_clock::time_point t0)
@@ -883,6 +898,8 @@ int handle_create(const pt_problem *prob, int precision, hipStream_t stream, cha
         return PT_ERR_HIP;
     }
     plan_tail(h);
+    if (prob->axisymmetric)
+        launch_axi_metric(P.n[1], h->axm64(), h->at<float4>(P.o_axm32), h->stream);
     int rc = assemble_enqueue(h, prob);
     if (rc != PT_OK) {
         *err = h->err;
@@ -992,7 +1009,7 @@ int pt_mg_divergence(pt_mg_t h, const double *const U[3], double *div)
     for (int a = 0; a < dim; a++) faces += (double)P.N + (double)P.N / P.n[a];
     h->begin(PT_K_OTHER, 8.0 * (faces + P.N));
     launch_divergence(dim, P.n[0], P.n[1], P.n[2], 1.0 / h->prob.h, U[0], U[1],
-                      dim == 3 ? U[2] : nullptr, div, h->stream);
+                      dim == 3 ? U[2] : nullptr, h->axm64(), div, h->stream);
     h->end();
     return sync(h, "divergence");
 }
@@ -1028,6 +1045,7 @@ int pt_mg_downstream(pt_mg_t h, const pt_downstream *d)
     a.dt = h->prob.dt;
     a.sigma = d->sigma;
     a.ac = h->ac64();
+    a.axm = h->axm64();
     a.p = d->p;
     a.T = d->T;
     a.C = d->C;
@@ -1088,6 +1106,7 @@ int outer(pt_mg_t h, const double *b_p, const double *b_T, const double *src_p,
     a.nz = P.n[2];
     a.N = P.N;
     a.inv_h2 = 1.0 / (h->prob.h * h->prob.h);
+    a.axm = h->axm64();
     a.phases = h->prob.mode != PT_COEF_EXPLICIT;
     a.ac = h->ac64();
     a.B = h->B64();

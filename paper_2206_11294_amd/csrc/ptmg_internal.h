@@ -28,6 +28,11 @@ template <typename R> struct Lvl {
     const typename VT<R>::v4 *B;               // block (pp, pT, Tp, TT)
     typename VT<R>::v2 *u;                     // unknowns (p, T)
     typename VT<R>::v2 *f;                     // right-hand side (p, T)
+    // axisymmetric r-z grids, level 0 only (null otherwise): per row j,
+    // (j/(j+1/2), (j+1)/(j+1/2), j+1/2, j), the radial face metric of the
+    // lower and upper face per unit volume, the cell radius and the lower
+    // face radius in units of h
+    const typename VT<R>::v4 *axm;
 };
 
 // Outer FP64 residual arguments (finest grid).
@@ -35,6 +40,7 @@ template <typename RV> struct OuterArgs {
     int nx, ny, nz;
     long long N;
     double inv_h2;
+    const double4 *axm;            // r-z metric per row (2-D) or null
     int phases;                    // 1: paper form (b = (lp, lT)), 0: canonical
     const double2 *ac;             // FP64 cell coefficients
     const double4 *B;              // FP64 block
@@ -120,11 +126,15 @@ struct DownArgs {
     double *vx, *vy, *vz;
     const double *E1a, *E2a;           // null: no energy update
     double *E1, *E2;
+    const double4 *axm;                // r-z metric per row (2-D) or null
 };
 void launch_downstream(int dim, const DownArgs &a, hipStream_t s);
 // div = sum over axes of (U upper face - U lower face) * inv_h.
 void launch_divergence(int dim, int nx, int ny, int nz, double inv_h, const double *Ux,
-                       const double *Uy, const double *Uz, double *div, hipStream_t s);
+                       const double *Uy, const double *Uz, const double4 *axm, double *div,
+                       hipStream_t s);
+// Fill the r-z metric table of ny rows in FP64 and, if m32 is not null, FP32.
+void launch_axi_metric(int ny, double4 *m64, float4 *m32, hipStream_t s);
 
 // ---- launch wrappers (implemented in ptmg_kernels.hip) --------------------
 void launch_assemble(const AsmArgs &a, hipStream_t s);

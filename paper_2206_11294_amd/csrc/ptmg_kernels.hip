@@ -27,6 +27,11 @@ template <> __device__ __forceinline__ float quot<float>(float a, float b)
     return a * __builtin_amdgcn_rcpf(b);
 }
 
+// Fused multiply-add written out, where two kernels must round alike
+// whatever the compiler contracts elsewhere.
+__device__ __forceinline__ float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 template <typename R>
 __device__ __forceinline__ R harm(R a, R b)
 {
@@ -63,6 +68,18 @@ __device__ __forceinline__ typename VT<R>::v2 face_coef(const Lvl<R> &L,
     return upper ? F[q] : F[me];
 }
 
+// Radial face coefficient per unit volume on an r-z grid: the face's
+// harmonic coefficient times r_face / r_cell (the row's metric m).  Every
+// level-0 kernel applies it the same way (before the 1/h^2 scaling), so
+// that the fused and the reference paths agree bit for bit.
+template <typename V2, typename V4>
+__device__ __forceinline__ void axi_face(V2 &w, const V4 &m, bool upper)
+{
+    const auto f = upper ? m.y : m.x;
+    w.x *= f;
+    w.y *= f;
+}
+
 // Sums over the faces of cell (i,j,k): S = sum w, nb = sum w u_nbr (when
 // USE_U), per component.  Face order: x-, x+, y-, y+, z-, z+.
 template <typename R, int DIM, bool CF, bool USE_U>
@@ -77,6 +94,7 @@ __device__ __forceinline__ void gather(const Lvl<R> &L, int i, int j, int k, lon
     const long long sx = 1, sy = L.nx, sz = (long long)L.nx * L.ny;
     auto acc = [&](long long q, int axis, bool upper) {
         V2 w = face_coef<R, CF>(L, am, me, q, axis, upper);
+        if (CF && axis == 1 && L.axm) axi_face(w, L.axm[j], upper);
         R wp = w.x * ih2, wT = w.y * ih2;
         Sp += wp;
         ST += wT;
@@ -815,16 +833,32 @@ __global__ __launch_bounds__(kBlock) void k_coarsen(Lvl<RIN> F, int cnx, int cny
                           DIM == 3 ? base[2] + ((m >> 2) & 1) : 0};
         const long long me = c[0] + (long long)F.nx * (c[1] + (long long)F.ny * c[2]);
         const V4 b = F.B[me];
-        b4[0] += (double)b.x;
-        b4[1] += (double)b.y;
-        b4[2] += (double)b.z;
-        b4[3] += (double)b.w;
+        if (CF && F.axm) {
+            // r-z: level 1 holds the volume-weighted equations (blocks
+            // times the cell radius, faces times the face area below)
+            const double rc = (double)F.axm[c[1]].z;
+            b4[0] += (double)b.x * rc;
+            b4[1] += (double)b.y * rc;
+            b4[2] += (double)b.z * rc;
+            b4[3] += (double)b.w * rc;
+        } else {
+            b4[0] += (double)b.x;
+            b4[1] += (double)b.y;
+            b4[2] += (double)b.z;
+            b4[3] += (double)b.w;
+        }
 #pragma unroll
         for (int a = 0; a < DIM; a++) {
             if (c[a] != base[a] || Ci[a] == 0) continue;
             V2 w;
             if (CF) {
                 w = harm2(F.ac[me], F.ac[me - st[a]]);
+                if (F.axm) {
+                    // axial faces: area ~ cell radius; radial: face radius
+                    const auto ar = a == 0 ? F.axm[c[1]].z : F.axm[c[1]].w;
+                    w.x *= ar;
+                    w.y *= ar;
+                }
             } else {
                 const V2 *Fa = a == 0 ? F.fx : (a == 1 ? F.fy : F.fz);
                 w = Fa[me];
@@ -908,6 +942,7 @@ __device__ double dense_row_diag(const Lvl<R> &L, long long cell, int c, double 
             if (up == 1 && ii[a] == nn[a] - 1) continue;
             const long long q = up ? cell + st[a] : cell - st[a];
             V2 w = face_coef<R, CF>(L, am, cell, q, a, up == 1);
+            if (CF && a == 1 && L.axm) axi_face(w, L.axm[j], up == 1);
             double wc = (double)(c == 0 ? w.x : w.y) * L.inv_h2;
             S += wc;
             if (row) row[2 * q + c] -= wc;
@@ -1491,7 +1526,7 @@ __global__ __launch_bounds__(TX *TY) void k_rb_tile2(Lvl<R> L, typename VT<R>::v
         }
     }
     __syncthreads();
-    auto update = [&](int c, long long g) {
+    auto update = [&](int c, long long g, int gy) {
         R gp = R(0), gT = R(0), Sp = R(0), ST = R(0);
         auto accw = [&](V2 w, int q) {
             const R wp = w.x * ih2, wT = w.y * ih2;
@@ -1508,10 +1543,16 @@ __global__ __launch_bounds__(TX *TY) void k_rb_tile2(Lvl<R> L, typename VT<R>::v
             accw(sfy[c + PX], c + PX);
         } else {
             const V2 am = sa[c];
+            V2 ym = harm2(am, sa[c - PX]), yp = harm2(am, sa[c + PX]);
+            if (L.axm) {
+                const V4 mt = L.axm[gy];
+                axi_face(ym, mt, false);
+                axi_face(yp, mt, true);
+            }
             accw(harm2(am, sa[c - 1]), c - 1);
             accw(harm2(am, sa[c + 1]), c + 1);
-            accw(harm2(am, sa[c - PX]), c - PX);
-            accw(harm2(am, sa[c + PX]), c + PX);
+            accw(ym, c - PX);
+            accw(yp, c + PX);
         }
         V2 o;
         block_solve<R>(L.f[g], L.B[g], gp, gT, Sp, ST, o);
@@ -1522,7 +1563,8 @@ __global__ __launch_bounds__(TX *TY) void k_rb_tile2(Lvl<R> L, typename VT<R>::v
         const int gy = y0 + ly - 2;
         const int lx = 1 + 2 * (t % RW) + ((x0 - 1 + gy) & 1);
         const int gx = x0 + lx - 2;
-        if (gx >= 0 && gx < L.nx && gy >= 0 && gy < L.ny) update(ly * PX + lx, gx + (long long)L.nx * gy);
+        if (gx >= 0 && gx < L.nx && gy >= 0 && gy < L.ny)
+            update(ly * PX + lx, gx + (long long)L.nx * gy, gy);
     }
     __syncthreads();
     if (t < BW * TY) {         // black cells of the tile
@@ -1530,7 +1572,7 @@ __global__ __launch_bounds__(TX *TY) void k_rb_tile2(Lvl<R> L, typename VT<R>::v
         const int gy = y0 + ly - 2;
         const int lx = 2 + 2 * (t % BW) + (1 - ((x0 + gy) & 1));
         const int gx = x0 + lx - 2;
-        if (gx < L.nx && gy < L.ny) update(ly * PX + lx, gx + (long long)L.nx * gy);
+        if (gx < L.nx && gy < L.ny) update(ly * PX + lx, gx + (long long)L.nx * gy, gy);
     }
     __syncthreads();
     {
@@ -1657,8 +1699,15 @@ __global__ __launch_bounds__(TX *TY) void k_rb_tile2x(Lvl<R> L, Lvl<R> C,
         // the y- face of c + PX: written into their slots
         ((V2 *)&sw[c + 1])[0] = wxp;
         ((V2 *)&sw[c + PX])[1] = wyp;
-        if (gx >= 0 && gx < L.nx && gy >= 0 && gy < L.ny)
-            solve(c, gx + (long long)L.nx * gy, wxm, wxp, wym, wyp);
+        if (gx >= 0 && gx < L.nx && gy >= 0 && gy < L.ny) {
+            V2 ym = wym, yp = wyp;
+            if (L.axm) {
+                const V4 mt = L.axm[gy];
+                axi_face(ym, mt, false);
+                axi_face(yp, mt, true);
+            }
+            solve(c, gx + (long long)L.nx * gy, wxm, wxp, ym, yp);
+        }
     }
     __syncthreads();
     if (t < RWB * RYB) {
@@ -1671,6 +1720,11 @@ __global__ __launch_bounds__(TX *TY) void k_rb_tile2x(Lvl<R> L, Lvl<R> C,
         if (gx >= 0 && gx < L.nx && gy >= 0 && gy < L.ny) {
             V2 wxm, wxp, wym, wyp;
             wget(c, wxm, wxp, wym, wyp);
+            if (L.axm) {
+                const V4 mt = L.axm[gy];
+                axi_face(wym, mt, false);
+                axi_face(wyp, mt, true);
+            }
             solve(c, gx + (long long)L.nx * gy, wxm, wxp, wym, wyp);
         }
     }
@@ -1690,6 +1744,11 @@ __global__ __launch_bounds__(TX *TY) void k_rb_tile2x(Lvl<R> L, Lvl<R> C,
         R nbp = R(0), nbT = R(0), Sp = R(0), ST = R(0);
         V2 wxm, wxp, wym, wyp;
         wget(c, wxm, wxp, wym, wyp);
+        if (L.axm) {
+            const V4 mt = L.axm[gy];
+            axi_face(wym, mt, false);
+            axi_face(wyp, mt, true);
+        }
         auto nb = [&](V2 w, int q) {
             const R wp = w.x * ih2, wT = w.y * ih2;
             const V2 uq = su[q];
@@ -1717,12 +1776,22 @@ __global__ __launch_bounds__(TX *TY) void k_rb_tile2x(Lvl<R> L, Lvl<R> C,
         if (I < C.nx && J < C.ny) {
             const int b0 = 2 * cj * TX + 2 * ci;
             const V2 r00 = sr[b0], r10 = sr[b0 + 1], r01 = sr[b0 + TX], r11 = sr[b0 + TX + 1];
-            // row pairs first, as the plane-marching restriction sums them
+            // row pairs first, as the plane-marching restriction sums them;
+            // on an r-z grid each row's pair is weighted by its cell radius
+            // (level 1 holds the volume-weighted equations)
             R accp = R(0), accT = R(0);
-            accp += r00.x + r10.x;
-            accT += r00.y + r10.y;
-            accp += r01.x + r11.x;
-            accT += r01.y + r11.y;
+            if (L.axm) {
+                const R rc0 = L.axm[2 * J].z, rc1 = L.axm[2 * J + 1].z;
+                accp = fmadd(r00.x + r10.x, rc0, accp);
+                accT = fmadd(r00.y + r10.y, rc0, accT);
+                accp = fmadd(r01.x + r11.x, rc1, accp);
+                accT = fmadd(r01.y + r11.y, rc1, accT);
+            } else {
+                accp += r00.x + r10.x;
+                accT += r00.y + r10.y;
+                accp += r01.x + r11.x;
+                accT += r01.y + r11.y;
+            }
             const R sc = R(0.25);
             V2 o;
             o.x = accp * sc;
@@ -2227,8 +2296,10 @@ __global__ __launch_bounds__(TX *TY) void k_outer_zm(OuterArgs<RV> a, int NX, in
                 const double2 um = su[s][c];
                 const double2 am = sa[s][c];
                 double nbp = 0.0, nbT = 0.0, Sp = 0.0, ST = 0.0;
-                auto nb = [&](int ss, int q) {
+                // mr: the r-z metric of a radial (marching-axis, 2-D) face
+                auto nb = [&](int ss, int q, int mr = -1) {
                     double2 w = harm2(am, sa[ss][q]);
+                    if (FLAT && mr >= 0 && a.axm) axi_face(w, a.axm[k], mr == 1);
                     w.x *= a.inv_h2;
                     w.y *= a.inv_h2;
                     const double2 uq = su[ss][q];
@@ -2243,8 +2314,8 @@ __global__ __launch_bounds__(TX *TY) void k_outer_zm(OuterArgs<RV> a, int NX, in
                     nb(s, c - PX);
                     nb(s, c + PX);
                 }
-                nb(sm, c);
-                nb(sp, c);
+                nb(sm, c, 0);
+                nb(sp, c, 1);
                 const double Lp = Sp * um.x - nbp;   // -div(a_p grad p)
                 const double LT = ST * um.y - nbT;   // -div(a_T grad T)
                 double bp = bp0, bT = bT0;
@@ -2432,8 +2503,10 @@ __global__ __launch_bounds__(TX *TY) void k_restrict_zm(Lvl<R> F, Lvl<R> C, int 
             const V2 um = su[s][c];
             const V2 am = sa[s][c];
             R nbp = R(0), nbT = R(0), Sp = R(0), ST = R(0);
-            auto nb = [&](int ss, int q) {
+            // mr: the r-z metric of a radial (marching-axis, 2-D) face
+            auto nb = [&](int ss, int q, int mr) {
                 V2 w = harm2(am, sa[ss][q]);
+                if (FLAT && mr >= 0 && F.axm) axi_face(w, F.axm[k], mr == 1);
                 const R wp = w.x * ih2, wT = w.y * ih2;
                 const V2 uq = su[ss][q];
                 Sp += wp;
@@ -2441,14 +2514,14 @@ __global__ __launch_bounds__(TX *TY) void k_restrict_zm(Lvl<R> F, Lvl<R> C, int 
                 nbp += wp * uq.x;
                 nbT += wT * uq.y;
             };
-            nb(s, c - 1);
-            nb(s, c + 1);
+            nb(s, c - 1, -1);
+            nb(s, c + 1, -1);
             if (!FLAT) {
-                nb(s, c - PX);
-                nb(s, c + PX);
+                nb(s, c - PX, -1);
+                nb(s, c + PX, -1);
             }
-            nb(sm, c);
-            nb(sp, c);
+            nb(sm, c, 0);
+            nb(sp, c, 1);
             const R Ap = Sp * um.x - nbp + B.x * um.x + B.y * um.y;
             const R AT = ST * um.y - nbT + B.z * um.x + B.w * um.y;
             r.x = f.x - Ap;
@@ -2460,14 +2533,21 @@ __global__ __launch_bounds__(TX *TY) void k_restrict_zm(Lvl<R> F, Lvl<R> C, int 
             // children (2 cxl + a, 2 cyl + b) of the tile, in x then y order
             const int base = 2 * cyl * TX + 2 * cxl;
             const V2 r00 = sr[base], r10 = sr[base + 1];
-            R sp_ = r00.x + r10.x, sT_ = r00.y + r10.y;
-            if (!FLAT) {
-                const V2 r01 = sr[base + TX], r11 = sr[base + TX + 1];
-                sp_ += r01.x + r11.x;
-                sT_ += r01.y + r11.y;
+            if (FLAT && F.axm) {
+                // r-z: the row's pair weighted by its cell radius
+                const R rc = F.axm[k].z;
+                accp = fmadd(r00.x + r10.x, rc, accp);
+                accT = fmadd(r00.y + r10.y, rc, accT);
+            } else {
+                R sp_ = r00.x + r10.x, sT_ = r00.y + r10.y;
+                if (!FLAT) {
+                    const V2 r01 = sr[base + TX], r11 = sr[base + TX + 1];
+                    sp_ += r01.x + r11.x;
+                    sT_ += r01.y + r11.y;
+                }
+                accp += sp_;
+                accT += sT_;
             }
-            accp += sp_;
-            accT += sT_;
             if (k & 1) {
                 const R sc = FLAT ? R(0.25) : R(0.125);
                 V2 o;
@@ -3014,7 +3094,15 @@ __global__ __launch_bounds__(TX *TY) void k_down_zm(DownArgs a, int NX, int NY, 
             // marching axis
             const Face mlo = face(sm, c, k > 0, false, ml);
             const Face mhi = face(sp, c, k < NZ - 1, true, cur.mh);
-            axis(mlo, mhi);
+            if (FLAT && a.axm) {
+                // r-z: radial flux differences per unit volume
+                const double4 mt = a.axm[k];
+                w1 += (mt.y * mhi.P1 * mhi.U - mt.x * mlo.P1 * mlo.U) * a.inv_h;
+                w2 += (mt.y * mhi.P2 * mhi.U - mt.x * mlo.P2 * mlo.U) * a.inv_h;
+                qs += (mt.y * mhi.q - mt.x * mlo.q) * a.inv_h;
+            } else {
+                axis(mlo, mhi);
+            }
             Vm[g] = mlo.U;
             if (k == NZ - 1) Vm[g + nxy] = mhi.U;
             if (cellv) vm[g] = cur.u2 - a.dt * (0.5 * (mlo.g + mhi.g));
@@ -3042,7 +3130,8 @@ void launch_downstream(int dim, const DownArgs &a, hipStream_t s)
 
 __global__ __launch_bounds__(256) void k_divergence(int dim, int nx, int ny, int nz, double inv_h,
                                                     const double *Ux, const double *Uy,
-                                                    const double *Uz, double *div)
+                                                    const double *Uz, const double4 *axm,
+                                                    double *div)
 {
     const long long N = (long long)nx * ny * nz;
     for (long long t = blockIdx.x * 256ll + threadIdx.x; t < N; t += (long long)gridDim.x * 256) {
@@ -3051,19 +3140,46 @@ __global__ __launch_bounds__(256) void k_divergence(int dim, int nx, int ny, int
         const long long fx = i + (long long)(nx + 1) * (j + (long long)ny * k);
         const long long fy = i + (long long)nx * (j + (long long)(ny + 1) * k);
         double d = (Ux[fx + 1] - Ux[fx]) * inv_h;
-        d += (Uy[fy + nx] - Uy[fy]) * inv_h;
+        if (axm) {
+            const double4 m = axm[j];
+            d += (m.y * Uy[fy + nx] - m.x * Uy[fy]) * inv_h;
+        } else {
+            d += (Uy[fy + nx] - Uy[fy]) * inv_h;
+        }
         if (dim == 3) d += (Uz[t + (long long)nx * ny] - Uz[t]) * inv_h;
         div[t] = d;
     }
 }
 
 void launch_divergence(int dim, int nx, int ny, int nz, double inv_h, const double *Ux,
-                       const double *Uy, const double *Uz, double *div, hipStream_t s)
+                       const double *Uy, const double *Uz, const double4 *axm, double *div,
+                       hipStream_t s)
 {
     const long long N = (long long)nx * ny * nz;
     const long long nb = std::min<long long>((N + 255) / 256, 65536);
     hipLaunchKernelGGL(k_divergence, dim3((unsigned)nb), dim3(256), 0, s, dim, nx, ny, nz, inv_h,
-                       Ux, Uy, Uz, div);
+                       Ux, Uy, Uz, axm, div);
+}
+
+// The r-z metric per row j of the finest grid, in units of h: radial faces
+// at r = j (lower) and j + 1 (upper), the cell centre at j + 1/2.
+__global__ __launch_bounds__(256) void k_axi_metric(int ny, double4 *m64, float4 *m32)
+{
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= ny) return;
+    const double rc = (double)j + 0.5;
+    double4 m;
+    m.x = (double)j / rc;
+    m.y = ((double)j + 1.0) / rc;
+    m.z = rc;
+    m.w = (double)j;
+    m64[j] = m;
+    if (m32) m32[j] = make_float4((float)m.x, (float)m.y, (float)m.z, (float)m.w);
+}
+
+void launch_axi_metric(int ny, double4 *m64, float4 *m32, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_axi_metric, dim3((ny + 255) / 256), dim3(256), 0, s, ny, m64, m32);
 }
 
 }  // namespace ptmg

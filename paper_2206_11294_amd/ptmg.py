@@ -52,7 +52,7 @@ class pt_problem(ctypes.Structure):
         ("p_adv", _Dp), ("T_adv", _Dp),
         ("p_adv_const", ctypes.c_double), ("T_adv_const", ctypes.c_double),
         ("mean_constraint", ctypes.c_int),
-        ("m1", _Dp), ("m2", _Dp),
+        ("m1", _Dp), ("m2", _Dp), ("axisymmetric", ctypes.c_int),
     ]
 
 

@@ -1,0 +1,224 @@
+"""Axisymmetric (r-z) grids on the GPU against the oracle: solves in both
+precisions (phases and state mode, multi-level and single-level grids),
+the level-0 steps that carry the metric (outer residual, sweep,
+restriction into the volume-weighted level 1, level-1 operator), the
+bit-for-bit agreement of the fused / tail / graph paths with the
+reference launches, the end of the step, and the argument checks."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import oracle as orc
+import workloads as W
+from gpu_util import dev, host, rel_err
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _axi(prob):
+    return dataclasses.replace(prob, axisymmetric=True)
+
+
+def _cases():
+    return {
+        # a bubble on the axis near the wall z = 0 (x is the axis direction)
+        "wall_200x136": _axi(W.bubble_problem("aw", 2, (200, 136), [(0.3, 0.0)], [0.25],
+                                              W.P0, 10 * W.P0, div_amp=1e-6, div_seed=21)),
+        "twobubble_132x68": _axi(W.bubble_problem("at", 2, (132, 68), [(0.3, 0.0), (0.7, 0.3)],
+                                                  [0.15, 0.1], W.P0, 3 * W.P0, div_amp=1e-6,
+                                                  div_seed=22)),
+        "single_5x6": _axi(W.bubble_problem("as", 2, (5, 6), [(0.5, 0.0)], [0.6], W.P0,
+                                            2 * W.P0, div_amp=1e-6, div_seed=23)),
+        "state_96x80": _axi(W.state_problem("ast", 2, (96, 80), [(0.4, 0.0)], [0.3], seed=24)),
+    }
+
+
+def _radii(n):
+    """Per finest row j: cell radius j + 1/2 and lower-face radius j (units of h)."""
+    j = np.arange(n[1], dtype=np.float64)
+    return j + 0.5, j
+
+
+@pytest.mark.parametrize("name", list(_cases()))
+@pytest.mark.parametrize("prec", [0, 1])
+def test_axi_solve_matches_oracle(name, prec):
+    import workloads.device as D
+    prob = _cases()[name]
+    print(f"axi solve {name} prec {prec}", flush=True)
+    h, b_p, b_T, _ = D.setup(prob, prec)
+    if name == "single_5x6":
+        assert h.num_levels() == 1
+    p, T = torch.empty_like(b_p), torch.empty_like(b_T)
+    info = h.solve(b_p, b_T, p, T, rtol=1e-12, max_cycles=60)
+    assert info["status"] == 0, info
+    op, ob_p, ob_T, p_ref, T_ref = orc.solve(prob, rtol=1e-14)
+    assert op.axi == 1
+    assert rel_err(host(b_p), ob_p) <= 1e-13 and rel_err(host(b_T), ob_T) <= 1e-13
+    P, TT = host(p), host(T)
+    assert rel_err(P, p_ref) <= 1e-8 and rel_err(TT, T_ref) <= 1e-8
+    assert max(orc.relres(op, ob_p, ob_T, P, TT)) <= 2e-12
+    # the Cartesian operator does not have this solution
+    op0 = dataclasses.replace(op, axi=0)
+    assert max(orc.relres(op0, ob_p, ob_T, P, TT)) > 1e-8
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_axi_level0_steps(prec):
+    """Outer residual, one level-0 sweep, the level-0 residual restricted
+    with the cell radii, and the level-1 operator (faces times their area,
+    blocks times the cell radius, averaged over the children)."""
+    import workloads.device as D
+    prob = _cases()["wall_200x136"]
+    h, b_p, b_T, _ = D.setup(prob, prec)
+    op = orc.assemble(prob)
+    N = op.N
+    rng = np.random.default_rng(31)
+    # outer residual (FP64 in both precisions)
+    p = prob.p_adv.reshape(-1) * (1 + 1e-3 * rng.standard_normal(N))
+    T = W.T0 * (1 + 1e-4 * rng.standard_normal(N))
+    bp, bT = host(b_p), host(b_T)
+    r_p, r_T, rel = h.residual(b_p, b_T, dev(p), dev(T))
+    o_rp, o_rT = orc.paper_residual(op, bp, bT, p, T)
+    scale = lambda a: max(np.abs(a).max(), 1e-300)
+    assert np.abs(host(r_p) - o_rp).max() <= 1e-11 * scale(o_rp)
+    assert np.abs(host(r_T) - o_rT).max() <= 1e-11 * scale(o_rT)
+    # one sweep on level 0 (canonical form, per unit volume)
+    tol = 1e-12 if prec == 0 else 3e-5
+    f_p, f_T = rng.uniform(-1, 1, N), rng.uniform(-1, 1, N)
+    u_p = rng.uniform(-1, 1, N) / np.abs(op.B[0]).max()
+    u_T = rng.uniform(-1, 1, N) / np.abs(op.B[3]).max()
+    gp, gT = dev(u_p), dev(u_T)
+    h.smooth(0, dev(f_p), dev(f_T), gp, gT, sweeps=1)
+    rp, rT = u_p.copy(), u_T.copy()
+    orc.sweep(op, f_p, f_T, rp, rT, "rb")
+    assert np.abs(host(gp) - rp).max() <= tol * scale(rp)
+    assert np.abs(host(gT) - rT).max() <= tol * scale(rT)
+    # restriction: the coarse right-hand side is the mean of r_c * residual
+    fc_p, fc_T = h.restrict_residual(0, dev(f_p), dev(f_T), dev(u_p), dev(u_T))
+    res_p, res_T = orc.residual(op, f_p, f_T, u_p, u_T)
+    rc, rf = _radii(prob.n)
+    wrow = np.repeat(rc[:, None], prob.n[0], axis=1).reshape(-1)
+    ref_p, ref_T = orc.restrict(2, prob.n, wrow * res_p, wrow * res_T)
+    assert np.abs(host(fc_p) - ref_p).max() <= tol * scale(ref_p)
+    assert np.abs(host(fc_T) - ref_T).max() <= tol * scale(ref_T)
+    # level-1 operator
+    nx, ny = prob.n[0], prob.n[1]
+    F1, B1 = h.get_operator(1)
+    F1, B1 = host(F1), host(B1)
+    ctol = 1e-14 if prec == 0 else 2e-7
+    Bw = op.B.reshape(4, ny, nx) * rc[None, :, None]
+    Bc = Bw.reshape(4, ny // 2, 2, nx // 2, 2).mean(axis=(2, 4)).reshape(4, -1)
+    for q in range(4):
+        assert np.abs(B1[q] - Bc[q]).max() <= ctol * scale(Bc[q])
+    for c in range(2):
+        Fx = op.F[c * 3 + 0].reshape(ny, nx) * rc[:, None]
+        Fy = op.F[c * 3 + 1].reshape(ny, nx) * rf[:, None]
+        cx = Fx[:, 0::2].reshape(ny // 2, 2, nx // 2).mean(axis=1)
+        cy = Fy[0::2, :].reshape(ny // 2, nx // 2, 2).mean(axis=2)
+        cx[:, 0] = 0.0
+        cy[0, :] = 0.0
+        assert np.abs(F1[c * 3 + 0] - cx.reshape(-1)).max() <= ctol * scale(cx)
+        assert np.abs(F1[c * 3 + 1] - cy.reshape(-1)).max() <= ctol * scale(cy)
+
+
+@pytest.mark.parametrize("name", ["wall_200x136", "state_96x80"])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_axi_fused_paths_match_reference(name, prec):
+    """With the metric, the fused sweeps and transfers, the tail and the
+    graph replay still equal the plain launches bit for bit."""
+    import workloads.device as D
+    from paper_2206_11294_amd import ptmg
+    prob = _cases()[name]
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        h, b_p, b_T, _ = D.setup(prob, prec, stream=stream)
+        rng = np.random.default_rng(7)
+        f_p, f_T = dev(rng.uniform(-1, 1, h.N)), dev(rng.uniform(-1, 1, h.N))
+        out = {}
+        for opts in ((1, 1, 1), (0, 0, 0)):
+            h.set_option(ptmg.PT_OPT_GRAPHS, opts[0])
+            h.set_option(ptmg.PT_OPT_TAIL, opts[1])
+            h.set_option(ptmg.PT_OPT_FUSED, opts[2])
+            p, T = torch.empty_like(b_p), torch.empty_like(b_T)
+            h.solve(b_p, b_T, p, T, rtol=1e-12)
+            e = h.vcycle(f_p, f_T)
+            torch.cuda.synchronize()
+            out[opts] = (p.clone(), T.clone(), e[0].clone(), e[1].clone())
+    for a, b in zip(out[(1, 1, 1)], out[(0, 0, 0)]):
+        assert torch.equal(a, b), (a - b).abs().max().item()
+
+
+def test_axi_end_of_step():
+    """Divergence and pt_mg_downstream with the r-z metric against the
+    oracle, element by element; the increments alone at their own scale."""
+    import workloads.device as D
+    prob = _cases()["state_96x80"]
+    s, t = D.to_device(prob)
+    from paper_2206_11294_amd import ptmg
+    h = ptmg.PtMg(s, ptmg.PT_PREC_FP64)
+    op = orc.assemble(prob)
+    d = host(h.divergence(D.face_inputs(prob, t)))
+    ref = orc.divergence(2, prob.n, prob.h, prob.uf_star, axi=1)
+    assert np.abs(d - ref).max() <= 1e-14 * max(np.abs(u).max() for u in prob.uf_star) / prob.h
+    rng = np.random.default_rng(9)
+    N = prob.ncells
+    sm = W.smooth_field(2, prob.n, 3).reshape(-1)
+    p = W.P0 * (1 + 0.01 * sm + 1e-4 * rng.uniform(-1, 1, N))
+    T = W.T0 + 5 * sm + 0.05 * rng.uniform(-1, 1, N)
+    Us = [u.reshape(-1) for u in prob.uf_star]
+    us = [u.reshape(-1) for u in prob.uc_star]
+    z = np.zeros(N)
+    U = [torch.empty_like(dev(u)) for u in Us]
+    u = [torch.empty_like(dev(x)) for x in us]
+    E1, E2 = torch.empty_like(dev(z)), torch.empty_like(dev(z))
+    h.downstream(dev(p), dev(T), t["C"], [dev(x) for x in Us], U, [dev(x) for x in us], u,
+                 dev(z), dev(z), E1, E2, t["kappa"], prob.sigma)
+    torch.cuda.synchronize()
+    o = orc.downstream(op, prob.dt, p, T, prob.C, Us, z, z, us, prob.kappa, prob.sigma)
+
+    def close(a, b, tol):
+        b = np.asarray(b).reshape(-1)
+        assert np.abs(host(a) - b).max() <= tol * max(np.abs(b).max(), 1e-300)
+    for a in range(2):
+        close(U[a], o["U"][a], 1e-14)
+        close(u[a], o["u"][a], 1e-14)
+    close(E1, o["E1"], 1e-11)
+    close(E2, o["E2"], 1e-11)
+    # total energy weighted by the cell volumes is conserved without
+    # surface tension (closed walls)
+    h.downstream(dev(p), dev(T), t["C"], [dev(x) for x in Us], U, None, None,
+                 dev(z), dev(z), E1, E2)
+    torch.cuda.synchronize()
+    rc, _ = _radii(prob.n)
+    V = np.repeat(rc[:, None], prob.n[0], axis=1).reshape(-1)
+    tot = V * (host(E1) + host(E2))
+    assert abs(tot.sum()) <= 1e-12 * np.abs(tot).sum()
+
+
+def test_axi_errors():
+    import workloads.device as D
+    from paper_2206_11294_amd import ptmg
+    p3 = _axi(W.bubble_problem("a3", 3, (8, 8, 8), [(0.5, 0.5, 0.5)], [0.3], W.P0, W.P0))
+    s, _ = D.to_device(p3)
+    with pytest.raises(ptmg.PtMgError) as e:
+        ptmg.PtMg(s, ptmg.PT_PREC_FP64)
+    assert e.value.status == ptmg.PT_ERR_ARG
+    prob = _cases()["twobubble_132x68"]
+    s, t = D.to_device(prob)
+    h = ptmg.PtMg(s, ptmg.PT_PREC_FP64)
+    s.axisymmetric = 0
+    with pytest.raises(ptmg.PtMgError) as e:
+        h.update(s)
+    assert e.value.status == ptmg.PT_ERR_STATE
+    s.axisymmetric = 2
+    with pytest.raises(ptmg.PtMgError) as e:
+        ptmg.PtMg(s, ptmg.PT_PREC_FP64)
+    assert e.value.status == ptmg.PT_ERR_ARG

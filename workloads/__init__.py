@@ -304,6 +304,16 @@ def collapse3d(n: int = 512, precision: str = "mixed") -> Problem:
                           precision=precision)
 
 
+def axi2d(n: int = 1024) -> Problem:
+    """Axisymmetric r-z bubble near a rigid wall: radius 0.1 on the axis at
+    axial distance 0.2 from the wall z = 0 (stand-off 2), gas at p0/20 in
+    liquid at p0, forcing by a seeded velocity divergence of amplitude
+    1e-6/dt (seed 2); x is the axial and y the radial coordinate."""
+    prob = bubble_problem(f"axi2d_{n}", 2, (n, n), [(0.2, 0.0)], [0.1], P0, P0 / 20,
+                          div_amp=1e-6, div_seed=2)
+    return dataclasses.replace(prob, axisymmetric=True)
+
+
 def state_problem(name: str, dim: int, n: Sequence[int],
                   centres_unit: Sequence[Sequence[float]], radii_unit: Sequence[float],
                   gas_atm: int = 1, u_amp: float = 1.0, seed: int = 12,

@@ -31,6 +31,7 @@ def to_device(prob: Problem, device="cuda") -> Tuple[ptmg.pt_problem, Dict[str, 
     s.dim = prob.dim
     s.n[0], s.n[1], s.n[2] = prob.n
     s.h = prob.h
+    s.axisymmetric = int(prob.axisymmetric)
     if prob.mode == "explicit":
         s.mode = ptmg.PT_COEF_EXPLICIT
         s.alpha_p_const = prob.alpha_p
