@@ -848,7 +848,6 @@ int handle_create(const pt_problem *prob, int precision, hipStream_t stream, cha
                   size_t bytes, void *pinned, pt_mg_t *out, std::string *err)
 {
     *out = nullptr;
-    static const bool graphs_env = !getenv("PTMG_NO_GRAPHS");
     Plan P;
     if (const char *why = plan_problem(prob, precision, P)) {
         *err = why;
@@ -857,7 +856,6 @@ int handle_create(const pt_problem *prob, int precision, hipStream_t stream, cha
     pt_mg_t h = new pt_mg_s();
     h->P = P;
     h->stream = stream;
-    h->use_graphs = graphs_env;
     h->owns_memory = dev_mem == nullptr;
     if (h->owns_memory) {
         hipError_t e = hipMalloc(&h->base, P.total);

@@ -1229,19 +1229,6 @@ namespace ptmg {
 // XCD (and its L2) a contiguous run of tiles whose halos overlap.  With
 // q = nb / 8 and r = nb % 8, XCD x has q + (x < r) blocks, so the map is a
 // bijection of [0, nb).
-// Streaming store of a (p, T) pair that the kernel never reads back.
-__device__ __forceinline__ void store_nt(float2 *p, float2 v)
-{
-    typedef float f2v __attribute__((ext_vector_type(2)));
-    f2v w = {v.x, v.y};
-    __builtin_nontemporal_store(w, (f2v *)p);
-}
-__device__ __forceinline__ void store_nt(double2 *p, double2 v)
-{
-    typedef double d2v __attribute__((ext_vector_type(2)));
-    d2v w = {v.x, v.y};
-    __builtin_nontemporal_store(w, (d2v *)p);
-}
 
 __device__ __forceinline__ int xcd_tile(int b, int nb)
 {
@@ -1262,8 +1249,7 @@ __device__ __forceinline__ void block_solve(typename VT<R>::v2 f, typename VT<R>
 
 template <typename R, int TX, int TY, bool ZG, bool FACES>
 __global__ __launch_bounds__(TX *TY) void k_rb_fused3(Lvl<R> L, typename VT<R>::v2 *__restrict__ uo,
-                                                      int zc, int tiles_x, int tiles_y, int ntiles,
-                                                      int nt_store)
+                                                      int zc, int tiles_x, int tiles_y, int ntiles)
 {
     // FACES: a coarse level with stored lower-face coefficients (fx, fy,
     // fz) instead of cell coefficients; faces of plane z are needed while
@@ -1409,9 +1395,7 @@ __global__ __launch_bounds__(TX *TY) void k_rb_fused3(Lvl<R> L, typename VT<R>::
         const int lx = 2 + t % TX, ly = 2 + t / TX;
         const int gx = x0 + lx - 2, gy = y0 + ly - 2;
         if (gx < L.nx && gy < L.ny) {
-            V2 *dst = uo + gx + (long long)L.nx * gy + nxy * z;
-            if (nt_store) store_nt(dst, su[s][ly * PX + lx]);
-            else *dst = su[s][ly * PX + lx];
+            uo[gx + (long long)L.nx * gy + nxy * z] = su[s][ly * PX + lx];
         }
     };
 
@@ -2085,33 +2069,25 @@ void launch_rb_fused(int dim, const Lvl<R> &L, typename VT<R>::v2 *uo, int zero_
                      hipStream_t s)
 {
     if (dim == 3) {
-        // tile 64 x TY: TY = 8 on the finest grid by default (16: FP32 only,
-        // 4: through PTMG_TILE_Y); 4 on coarse levels (their LDS rings are
-        // larger)
-        static const int ty_env = [] {
-            const char *e = getenv("PTMG_TILE_Y");
-            return e ? atoi(e) : 8;
-        }();
+        // tile 64 x TY.  The FP32 finest grid takes 64 x 16 tiles (1024
+        // threads, one block per CU with its 109 KB of LDS rings): the
+        // two-cell y halo of the iterate and coefficients is re-read 1.33x
+        // instead of 1.59x at 64 x 8, and 256 blocks (one per CU) keep the
+        // z chunks long, so the four ring planes each chunk re-reads stay a
+        // small share.  FP64 cells take twice the LDS, so the FP64 finest
+        // grid keeps 64 x 8 (two blocks per CU, 512 blocks); coarse levels
+        // with stored faces hold three more rings and take 64 x 4.
         constexpr int TX = 64;
-        const int TY = faces ? 4 : ((ty_env == 16 && sizeof(R) == 4) ? 16 : (ty_env == 4 ? 4 : 8));
+        const int TY = faces ? 4 : (sizeof(R) == 4 ? 16 : 8);
         const int tx = (L.nx + TX - 1) / TX, ty = (L.ny + TY - 1) / TY;
-        // chunk the z walk so that the grid has enough blocks to fill the chip
-        static const int want_env = [] {
-            const char *e = getenv("PTMG_FUSED_BLOCKS");
-            return e ? atoi(e) : 0;
-        }();
-        static const int nt_env = [] {
-            const char *e = getenv("PTMG_NT_STORE");
-            return e ? atoi(e) : 0;
-        }();
-        const long long want = want_env > 0 ? want_env : (TY == 4 ? 2048 : 512);
+        const long long want = TY == 4 ? 2048 : (TY == 16 ? 256 : 512);
         int zc = L.nz;
         while (zc > 16 && (long long)tx * ty * ((L.nz + zc - 1) / zc) < want) zc = (zc + 1) / 2;
         const int tz = (L.nz + zc - 1) / zc;
         const int nt = tx * ty * tz;
 #define PTMG_FUSED3(TYC, ZGC, FC)                                                              \
     hipLaunchKernelGGL((k_rb_fused3<R, TX, TYC, ZGC, FC>), dim3(nt), dim3(TX * TYC), 0, s, L, uo, \
-                       zc, tx, ty, nt, nt_env)
+                       zc, tx, ty, nt)
         if (faces) {
             if (zero_guess) PTMG_FUSED3(4, true, true);
             else PTMG_FUSED3(4, false, true);
