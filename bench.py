@@ -2,9 +2,10 @@
 """Benchmark of the coupled pressure-temperature multigrid solve on one GPU.
 
 One step = one pass of the whole hot path over one synthetic input:
-re-assembly of the operator and hierarchy (pt_mg_update), the paper's
-right-hand side (pt_mg_paper_rhs) and the solve to tolerance
-(pt_mg_solve), with every input already resident in device memory.  The
+re-assembly of the operator and hierarchy, the paper's right-hand side
+and the solve to tolerance (one pt_mg_step call; pt_mg_update +
+pt_mg_solve for the explicit case), with every input already resident in
+device memory.  The
 state-mode workloads (state2d_1024, state3d_256) cover the implicit part
 of the time step from the advected conserved variables to the updated
 ones: the provisional pressure and temperature (pt_state_eval, Eqs. 20
@@ -382,6 +383,7 @@ def main():
         h = ptmg.PtMg(s, prec, stream=stream)
         p = torch.empty(prob.ncells, dtype=torch.float64, device="cuda")
         T = torch.empty_like(p)
+        rhs_p, rhs_T = torch.empty_like(p), torch.empty_like(p)
 
         state = D.state_record(prob, tens) if prob.mode == "state" else None
         state_ev = []    # (start, end) event pairs around the state kernel
@@ -400,15 +402,17 @@ def main():
                 ptmg.state_eval(state, stream)
                 b.record(stream)
                 state_ev.append((a, b))
-            h.update(s)
-            if faces is not None:
-                h.divergence(faces, out=div)
-                b_p, b_T = h.paper_rhs(tens.get("p_adv"), tens.get("T_adv"), div)
-            elif prob.mode != "explicit":
-                b_p, b_T = h.paper_rhs(tens.get("p_adv"), tens.get("T_adv"), tens.get("div"))
-            else:
+            if prob.mode == "explicit":
+                h.update(s)
                 b_p, b_T = tens["f_p"], tens["f_T"]
-            info = h.solve(b_p, b_T, p, T, rtol=rtol, max_cycles=120, method=method)
+                info = h.solve(b_p, b_T, p, T, rtol=rtol, max_cycles=120, method=method)
+            else:
+                # update + paper right-hand side + solve in one call
+                if faces is not None:
+                    h.divergence(faces, out=div)
+                info = h.step(s, div if faces is not None else tens.get("div"), rhs_p, rhs_T,
+                              p, T, rtol=rtol, max_cycles=120, method=method)
+                b_p, b_T = rhs_p, rhs_T
             if faces is not None:
                 h.downstream(p, T, tens["C"], faces, U, us, u, tens["E1"], tens["E2"], E1, E2,
                              tens["kappa"], prob.sigma)
@@ -467,9 +471,9 @@ def main():
                    "geometry": "axisymmetric r-z" if prob.axisymmetric else "cartesian",
                    "rtol": rtol, "cycles_per_solve": float(np.mean(cycles)),
                    "step": ("pt_state_eval + " if prob.mode == "state" else "")
-                   + "pt_mg_update + "
                    + ("pt_mg_divergence + " if faces is not None else "")
-                   + "pt_mg_paper_rhs + pt_mg_solve"
+                   + ("pt_mg_update + pt_mg_solve" if prob.mode == "explicit" else
+                      "pt_mg_step (update + paper RHS + solve)")
                    + (" + pt_mg_downstream" if faces is not None else ""),
                    "method": args.method, "time_step": "diffusive" if args.stiff else "acoustic",
                    "parallelism": "single GPU"},
@@ -478,6 +482,7 @@ def main():
         "downstream": downstream_line(timed),
         "launches_per_step": {k: v["launches"] / args.steps for k, v in stats.items()},
         "relres_last": list(info["relres"]),
+        "relres_hist_last": [[float("%.3g" % x) for x in pair] for pair in info["hist"]],
     }
     if not args.no_oracle_check and prob.ncells <= 2_500_000:
         import oracle as orc

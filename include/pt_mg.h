@@ -225,6 +225,20 @@ int pt_mg_paper_rhs(pt_mg_t h, const double *p_adv, const double *T_adv,
 int pt_mg_solve(pt_mg_t h, const double *b_p, const double *b_T, double *p, double *T,
                 const pt_solve_opts *opts, pt_solve_info *info);
 
+/* One implicit step in one call: pt_mg_update(prob), the paper right-hand
+ * side of Eqs. (33)-(34) from prob->p_adv, prob->T_adv and div_ustar into
+ * b_p, b_T (as pt_mg_paper_rhs), and pt_mg_solve(b, p, T, opts, info), the
+ * work of Algorithm 1's implicit p-T solve.  Everything is enqueued on the
+ * handle's stream with the host waiting only where the solve reads its
+ * norms; the assembly checks of pt_mg_update are read with the first
+ * norms.  Results, outputs and errors are those of the three calls in
+ * sequence (an assembly error leaves the handle not ready and b, p, T
+ * unspecified).  PT_COEF_PHASES or PT_COEF_STATE only (PT_ERR_STATE
+ * otherwise); b_p, b_T, p, T [N] are caller-owned device arrays. */
+int pt_mg_step(pt_mg_t h, const pt_problem *prob, const double *div_ustar, double *b_p,
+               double *b_T, double *p, double *T, const pt_solve_opts *opts,
+               pt_solve_info *info);
+
 /* Residual in FP64, mode-native form: res = b - L(a) of Eqs. (27)-(28)
  * (PT_COEF_PHASES) or f - A u (PT_COEF_EXPLICIT).  r_p, r_T [N] may be
  * NULL.  relres (may be NULL) receives ||res_c||_2 / ||b_c||_2 for
@@ -397,7 +411,7 @@ long long pt_mg_last_cell_updates(pt_mg_t h);
  *  PT_OPT_SPECULATE: enqueue the next outer iteration (V-cycle, FP64
  *    update, residual and norms) before the host has read the current
  *    norms, whenever the contraction seen so far predicts that the
- *    current iterate misses the tolerance by a factor of 30 or more (and,
+ *    current iterate misses the tolerance by a factor of 3 or more (and,
  *    from a zero guess, the first cycle at once).  The solution, cycles
  *    and history are those of the step-by-step loop; a wrong guess costs
  *    one V-cycle of device time.  Default 1. */

@@ -208,6 +208,7 @@ struct pt_mg_s {
         bool have_prev = false;
         double prev[2] = {0, 0};
         long long upd[2] = {0, 0};  // cell-updates enqueued up to outer k (slot k & 1)
+        bool check_asm = false;     // the assembly of this step is checked with the first norms
         pt_solve_info inf;
         std::chrono::steady_clock::time_point t0;
     } sv;
@@ -228,6 +229,10 @@ struct pt_mg_s {
     double ms[PT_K_COUNT] = {0};
     long long updates = 0, last_updates = 0;
     std::vector<CoarseGraph> graphs;
+    // the hierarchy build (coarsening chain, coarsest matrix and inverse)
+    // as one graph, captured at the first assembly on a non-null stream
+    hipGraph_t hier_graph = nullptr;
+    hipGraphExec_t hier_exec = nullptr;
     bool use_graphs = true;
     // single-block tail cycle over levels tail_lt .. nlev-1 (0: not used)
     int tail_lt = 0;
@@ -692,6 +697,34 @@ template <typename R> void build_hierarchy(pt_mg_t h)
     }
 }
 
+// The hierarchy build replayed from a graph: its kernels read and write
+// only the handle's memory, so one capture serves every update.  Direct
+// launches on the null stream or if the capture fails.
+template <typename R> void hierarchy(pt_mg_t h)
+{
+    if (!h->use_graphs || !h->stream) {
+        build_hierarchy<R>(h);
+        return;
+    }
+    if (!h->hier_exec) {
+        bool ok = hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
+        if (ok) {
+            build_hierarchy<R>(h);
+            ok = hipStreamEndCapture(h->stream, &h->hier_graph) == hipSuccess && h->hier_graph;
+        }
+        if (ok) ok = hipGraphInstantiate(&h->hier_exec, h->hier_graph, nullptr, nullptr, 0) == hipSuccess;
+        if (!ok) {
+            (void)hipGetLastError();
+            if (h->hier_graph) (void)hipGraphDestroy(h->hier_graph);
+            h->hier_graph = nullptr;
+            h->hier_exec = nullptr;
+            build_hierarchy<R>(h);
+            return;
+        }
+    }
+    (void)hipGraphLaunch(h->hier_exec, h->stream);
+}
+
 // Enqueue assembly, hierarchy, coarsest inverse and the flag read-back on
 // the handle's stream; done_ev marks the end.
 int assemble_enqueue(pt_mg_t h, const pt_problem *p)
@@ -730,10 +763,11 @@ int assemble_enqueue(pt_mg_t h, const pt_problem *p)
     h->prob.alpha_p = h->prob.alpha_T = h->prob.B = h->prob.C = h->prob.p_adv = h->prob.T_adv = nullptr;
     launch_zero(h->flags(), sizeof(int) * NFLAGS, h->stream);
     launch_assemble(a, h->stream);
-    if (P.prec == PT_PREC_MIXED) build_hierarchy<float>(h);
-    else build_hierarchy<double>(h);
-    hipError_t e = hipMemcpyAsync(h->flags_host, h->flags(), sizeof(int) * NFLAGS,
-                                  hipMemcpyDeviceToHost, h->stream);
+    if (P.prec == PT_PREC_MIXED) hierarchy<float>(h);
+    else hierarchy<double>(h);
+    // the flags go straight into the pinned host copy (its device address)
+    launch_flags_out(h->flags(), (int *)(h->norms_devp + 16), NFLAGS, h->stream);
+    hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipEventRecord(h->done_ev, h->stream);
     return check_hip(h, e, "setup enqueue");
 }
@@ -971,6 +1005,12 @@ void pt_mg_destroy(pt_mg_t h)
     for (auto ev : h->norm_ev)
         if (ev) (void)hipEventDestroy(ev);
     for (auto e : h->ev_all) (void)hipEventDestroy(e);
+    for (auto &c : h->graphs) {
+        if (c.exec) (void)hipGraphExecDestroy(c.exec);
+        if (c.graph) (void)hipGraphDestroy(c.graph);
+    }
+    if (h->hier_exec) (void)hipGraphExecDestroy(h->hier_exec);
+    if (h->hier_graph) (void)hipGraphDestroy(h->hier_graph);
     if (h->kry) (void)hipFree(h->kry);
     if (h->owns_memory) {
         if (h->base) (void)hipFree(h->base);
@@ -1270,8 +1310,7 @@ int solve_begin(pt_mg_t h, const double *b_p, const double *b_T, double *p, doub
     h->updates = 0;
     if (o.zero_guess) {
         h->begin(PT_K_OTHER, 16.0 * P.N);
-        launch_zero(p, 8 * (size_t)P.N, h->stream);
-        launch_zero(T, 8 * (size_t)P.N, h->stream);
+        launch_zero2(p, T, 8 * (size_t)P.N, h->stream);
         h->end();
     }
     // mean constraint: the right-hand side is used with its mean removed
@@ -1293,6 +1332,18 @@ int solve_advance(pt_mg_t h, pt_solve_info *info)
     const Plan &P = h->P;
     hipError_t e;
     h->flush_timing();
+    if (S.phase == 1 && S.check_asm) {
+        // pt_mg_step: the assembly flags were copied before the first
+        // residual, so they are in host memory now
+        S.check_asm = false;
+        h->ready = false;
+        const int rc = assemble_check(h);   // ready again on success
+        if (rc != PT_OK) {
+            (void)hipStreamSynchronize(h->stream);   // let the enqueued cycles drain
+            S.phase = 0;
+            return rc;
+        }
+    }
     if (S.phase == 1) {
         const int k = S.k_wait;
         const double *s = h->norms_host + 4 * (k & 1);
@@ -1321,12 +1372,15 @@ int solve_advance(pt_mg_t h, pt_solve_info *info)
         if (!finish) {
             int rc = PT_OK;
             if (S.k_enq == k) rc = enqueue_outer(h, k + 1);
-            // Outer k+2 ahead of the norms of k+1 when, at the contraction
-            // seen so far (0.1 before any), u_{k+1} still misses the
-            // tolerance by a wide margin; a wrong guess costs one cycle of
-            // device time, never a different result.
+            // Outer k+2 ahead of the norms of k+1 when, at the last
+            // contraction seen (0.1 before any), u_{k+1} still misses the
+            // tolerance by a factor of 3.  The multigrid contracts at a
+            // steady rate after its first cycle, which contracts far more
+            // from a zero guess (so its rate under-predicts the next
+            // residual and errs on the side of waiting); a wrong guess
+            // costs one cycle of device time, never a different result.
             if (rc == PT_OK && h->speculate && S.k_enq == k + 1 && k + 2 <= S.o.max_cycles) {
-                constexpr double kMargin = 30.0;
+                constexpr double kMargin = 3.0;
                 bool ahead = false;
                 for (int c = 0; c < 2; c++) {
                     double rate = S.have_prev && S.prev[c] > 0 ? rel[c] / S.prev[c] : 0.1;
@@ -1403,6 +1457,56 @@ int pt_mg_solve(pt_mg_t h, const double *b_p, const double *b_T, double *p, doub
         if (rc == PT_OK) rc = check_hip(h, hipGetLastError(), "solve");
         if (rc != PT_OK) {
             h->sv.phase = 0;
+            return rc;
+        }
+        rc = solve_advance(h, info);
+        if (rc != PT_RUNNING) return rc;
+    }
+}
+
+int pt_mg_step(pt_mg_t h, const pt_problem *prob, const double *div_ustar, double *b_p,
+               double *b_T, double *p, double *T, const pt_solve_opts *opts_in,
+               pt_solve_info *info)
+{
+    if (!h) return fail(nullptr, PT_ERR_ARG, "handle is NULL");
+    if (!prob) return fail(h, PT_ERR_ARG, "problem is NULL");
+    if (prob->mode == PT_COEF_EXPLICIT)
+        return fail(h, PT_ERR_STATE, "step needs phases or state mode");
+    if (!b_p || !b_T || !p || !T) return fail(h, PT_ERR_ARG, "NULL field");
+    if (opts_in && opts_in->method != PT_SOLVE_DEFECT) {
+        // the Krylov loop waits on every reduction anyway
+        int rc = pt_mg_update(h, prob);
+        if (rc == PT_OK) rc = pt_mg_paper_rhs(h, prob->p_adv, prob->T_adv, div_ustar, b_p, b_T);
+        if (rc == PT_OK) rc = pt_mg_solve(h, b_p, b_T, p, T, opts_in, info);
+        return rc;
+    }
+    Plan P;
+    if (const char *why = plan_problem(prob, h->P.prec, P)) return fail(h, PT_ERR_ARG, why);
+    if (!same_grid(prob, &h->prob))
+        return fail(h, PT_ERR_STATE, "update must keep dim, n, h, mode and mean_constraint");
+    if (P.total != h->P.total) return fail(h, PT_ERR_STATE, "update changes the memory plan");
+    int rc = assemble_enqueue(h, prob);
+    if (rc == PT_OK)
+        rc = handle_paper_rhs_async(h, prob->p_adv, prob->T_adv, div_ustar, b_p, b_T);
+    if (rc != PT_OK) {
+        (void)hipStreamSynchronize(h->stream);
+        return rc;
+    }
+    h->ready = true;   // provisionally: the flags are checked with the first norms
+    rc = solve_begin(h, b_p, b_T, p, T, opts_in);
+    if (rc != PT_OK) {
+        (void)hipStreamSynchronize(h->stream);
+        h->ready = false;
+        const int arc = assemble_check(h);
+        return arc != PT_OK ? arc : rc;
+    }
+    h->sv.check_asm = true;
+    for (;;) {
+        rc = check_hip(h, hipEventSynchronize(handle_event(h)), "step");
+        if (rc == PT_OK) rc = check_hip(h, hipGetLastError(), "step");
+        if (rc != PT_OK) {
+            h->sv.phase = 0;
+            h->ready = false;
             return rc;
         }
         rc = solve_advance(h, info);

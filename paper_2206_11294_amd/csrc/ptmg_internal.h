@@ -206,6 +206,8 @@ template <typename RIN, typename ROUT>
 void launch_convert(long long n, const RIN *in, ROUT *out, hipStream_t s);
 void launch_copy(void *dst, const void *src, size_t bytes, hipStream_t s);
 void launch_zero(void *p, size_t bytes, hipStream_t s);
+void launch_zero2(void *p, void *q, size_t bytes, hipStream_t s);   // both arrays
+void launch_flags_out(const int *src, int *dst, int n, hipStream_t s);   // n <= 64
 
 // ---- handle internals used by the serving engine (ptmg_host.hip) ---------
 constexpr int PT_RUNNING = -1;

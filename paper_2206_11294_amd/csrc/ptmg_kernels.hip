@@ -1194,6 +1194,46 @@ __global__ __launch_bounds__(kBlock) void k_zero(uint4 *p, long long nvec, unsig
     if (t < ntail) tail[t] = 0;
 }
 
+// Two zero fills in one launch (the zero initial guess of p and T).
+__global__ __launch_bounds__(kBlock) void k_zero2(uint4 *p, uint4 *q, long long nvec,
+                                                  unsigned char *tp, unsigned char *tq, int ntail)
+{
+    long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
+    const long long stride = (long long)gridDim.x * kBlock;
+    for (long long i = t; i < nvec; i += stride) {
+        p[i] = make_uint4(0, 0, 0, 0);
+        q[i] = make_uint4(0, 0, 0, 0);
+    }
+    if (t < ntail) {
+        tp[t] = 0;
+        tq[t] = 0;
+    }
+}
+
+void launch_zero2(void *p, void *q, size_t bytes, hipStream_t s)
+{
+    const long long nvec = (long long)(bytes / 16);
+    const int ntail = (int)(bytes % 16);
+    long long blocks = (nvec + kBlock - 1) / kBlock;
+    if (blocks > 8192) blocks = 8192;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_zero2, dim3((unsigned)blocks), dim3(kBlock), 0, s, (uint4 *)p,
+                       (uint4 *)q, nvec, (unsigned char *)p + nvec * 16,
+                       (unsigned char *)q + nvec * 16, ntail);
+}
+
+// The assembly's error flags into the host's pinned copy (through its
+// device address), ordered on the stream like any kernel.
+__global__ void k_flags_out(const int *src, int *dst, int n)
+{
+    if ((int)threadIdx.x < n) dst[threadIdx.x] = src[threadIdx.x];
+}
+
+void launch_flags_out(const int *src, int *dst, int n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_flags_out, dim3(1), dim3(64), 0, s, src, dst, n);
+}
+
 void launch_zero(void *p, size_t bytes, hipStream_t s)
 {
     const long long nvec = (long long)(bytes / 16);

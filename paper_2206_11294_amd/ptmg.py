@@ -109,6 +109,8 @@ def lib() -> ctypes.CDLL:
             "pt_mg_update": (c_int, [c_void, P(pt_problem)]),
             "pt_mg_paper_rhs": (c_int, [c_void] + [c_void] * 5),
             "pt_mg_divergence": (c_int, [c_void, P(c_void), c_void]),
+            "pt_mg_step": (c_int, [c_void, P(pt_problem)] + [c_void] * 5 + [P(pt_solve_opts),
+                                                                           P(pt_solve_info)]),
             "pt_mg_downstream": (c_int, [c_void, P(pt_downstream)]),
             "pt_mg_solve": (c_int, [c_void, c_void, c_void, c_void, c_void,
                                     P(pt_solve_opts), P(pt_solve_info)]),
@@ -146,7 +148,7 @@ def exported_symbols() -> Sequence[str]:
     """Names of the C-ABI functions the binding uses."""
     lib()
     return ["pt_state_eval", "pt_mg_footprint_bytes", "pt_mg_setup", "pt_mg_update", "pt_mg_paper_rhs",
-            "pt_mg_divergence", "pt_mg_downstream",
+            "pt_mg_divergence", "pt_mg_downstream", "pt_mg_step",
             "pt_mg_solve", "pt_mg_residual", "pt_mg_destroy", "pt_mg_last_error",
             "pt_mg_num_levels", "pt_mg_level_dims", "pt_mg_get_operator", "pt_mg_smooth",
             "pt_mg_restrict_residual", "pt_mg_prolong_add", "pt_mg_coarse_solve",
@@ -235,6 +237,21 @@ class PtMg:
         self._check(lib().pt_mg_paper_rhs(self._h, _ptr(p_adv), _ptr(T_adv), _ptr(div_ustar),
                                           _ptr(b_p), _ptr(b_T)))
         return b_p, b_T
+
+    def step(self, prob: pt_problem, div_ustar, b_p, b_T, p, T, rtol=1e-9, max_cycles=50,
+             nu1=2, nu2=2, zero_guess=True, raise_on_noconv=True,
+             method=PT_SOLVE_DEFECT) -> Dict:
+        """pt_mg_step: update + paper right-hand side (into b_p, b_T) + solve."""
+        opts = pt_solve_opts(rtol, max_cycles, nu1, nu2, int(zero_guess), int(method))
+        info = pt_solve_info()
+        rc = lib().pt_mg_step(self._h, ctypes.byref(prob), _ptr(div_ustar), _ptr(b_p), _ptr(b_T),
+                              _ptr(p), _ptr(T), ctypes.byref(opts), ctypes.byref(info))
+        if rc and (rc != PT_ERR_NOCONV or raise_on_noconv):
+            self._check(rc)
+        n = info.hist_len
+        return {"status": rc, "cycles": info.cycles, "relres": (info.relres[0], info.relres[1]),
+                "hist": [(info.relres_hist[2 * q], info.relres_hist[2 * q + 1]) for q in range(n)],
+                "t_solve_s": info.t_solve_s}
 
     def divergence(self, U: Sequence[torch.Tensor], out: Optional[torch.Tensor] = None) -> torch.Tensor:
         """pt_mg_divergence: div of the face velocities U[a] (one tensor per axis)."""

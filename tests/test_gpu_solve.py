@@ -377,3 +377,63 @@ def test_bicgstab_matches_oracle_and_helps_stiff(prec):
     assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1])
     with pytest.raises(ptmg.PtMgError):
         h.solve(gb_p, gb_T, p, T, method=7)
+
+
+@pytest.mark.parametrize("kind", ["phases", "state"])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_step_equals_update_rhs_solve(kind, prec):
+    """pt_mg_step (update + paper right-hand side + solve with one wait)
+    gives the right-hand side, solution, cycle count and history of the
+    three separate calls, bit for bit; an invalid field through the step
+    is the update's error and leaves the handle not ready until a valid
+    step."""
+    import dataclasses
+    import workloads.device as D
+    from paper_2206_11294_amd import ptmg
+    if kind == "phases":
+        first = step_problems()["bubble2d_200x136"]
+        second = W.bubble_problem("b2b", 2, (200, 136), [(0.55, 0.4)], [0.15], W.P0, 5 * W.P0,
+                                  div_amp=1e-6, div_seed=8)
+    else:
+        first = W.state_problem("st1", 2, (200, 136), [(0.45, 0.5)], [0.2], seed=41)
+        second = W.state_problem("st2", 2, (200, 136), [(0.5, 0.45)], [0.25], seed=42)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        h, _, _, _ = D.setup(first, prec, stream=stream)
+        s2, t2 = D.to_device(second)
+        div = t2.get("div")
+        if div is None and "Us0" in t2:
+            div = h.divergence(D.face_inputs(second, t2))
+        # separate calls
+        h.update(s2)
+        b_p, b_T = h.paper_rhs(t2.get("p_adv"), t2.get("T_adv"), div)
+        p1, T1 = torch.empty_like(b_p), torch.empty_like(b_T)
+        i1 = h.solve(b_p, b_T, p1, T1, rtol=1e-12)
+        # one call (the handle starts from the first problem again)
+        s1, t1 = D.to_device(first)
+        h.update(s1)
+        c_p, c_T = torch.empty_like(b_p), torch.empty_like(b_T)
+        p2, T2 = torch.empty_like(b_p), torch.empty_like(b_T)
+        i2 = h.step(s2, div, c_p, c_T, p2, T2, rtol=1e-12)
+        torch.cuda.synchronize()
+        assert i1["cycles"] == i2["cycles"] and i1["hist"] == i2["hist"]
+        for a, b in ((b_p, c_p), (b_T, c_T), (p1, p2), (T1, T2)):
+            assert torch.equal(a, b)
+        # an invalid volume fraction: the update's error, then not ready
+        bad = dataclasses.replace(second, C=np.where(second.C > 0.5, 1.5, second.C))
+        sb, tb = D.to_device(bad) if kind == "phases" else (None, None)
+        if kind == "phases":
+            with pytest.raises(ptmg.PtMgError) as e:
+                h.step(sb, div, c_p, c_T, p2, T2, rtol=1e-12)
+            assert e.value.status == ptmg.PT_ERR_ARG
+            with pytest.raises(ptmg.PtMgError) as e:
+                h.solve(b_p, b_T, p2, T2)
+            assert e.value.status == ptmg.PT_ERR_STATE
+            i3 = h.step(s2, div, c_p, c_T, p2, T2, rtol=1e-12)
+            torch.cuda.synchronize()
+            assert i3["cycles"] == i1["cycles"] and torch.equal(p1, p2)
+        ex = W.explicit_const(32, 32)
+        se, _ = D.to_device(ex)
+        with pytest.raises(ptmg.PtMgError) as e:
+            h.step(se, None, c_p, c_T, p2, T2)
+        assert e.value.status == ptmg.PT_ERR_STATE
