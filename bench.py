@@ -334,6 +334,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-oracle-check", action="store_true")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="BYTES")
+    ap.add_argument("--tail-cells", type=int, default=None,
+                    help="largest level of the single-block tail (PT_OPT_TAIL_CELLS)")
     ap.add_argument("--timing-every", type=int, default=7,
                     help="time one finest-grid smoothing run in this many")
     ap.add_argument("--serve", action="store_true", help="the serving mix instead of a workload")
@@ -381,6 +383,8 @@ def main():
     with torch.cuda.stream(stream):
         s, tens = D.to_device(prob)
         h = ptmg.PtMg(s, prec, stream=stream)
+        if args.tail_cells is not None:
+            h.set_option(ptmg.PT_OPT_TAIL_CELLS, args.tail_cells)
         p = torch.empty(prob.ncells, dtype=torch.float64, device="cuda")
         T = torch.empty_like(p)
         rhs_p, rhs_T = torch.empty_like(p), torch.empty_like(p)
@@ -476,6 +480,7 @@ def main():
                       "pt_mg_step (update + paper RHS + solve)")
                    + (" + pt_mg_downstream" if faces is not None else ""),
                    "method": args.method, "time_step": "diffusive" if args.stiff else "acoustic",
+                   "tail_levels": h.get_option(ptmg.PT_OPT_TAIL),
                    "parallelism": "single GPU"},
         "roofline": roofline,
         "upstream": upstream_line(prob, state_ms),

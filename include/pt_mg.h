@@ -414,13 +414,17 @@ long long pt_mg_last_cell_updates(pt_mg_t h);
  *    current iterate misses the tolerance by a factor of 3 or more (and,
  *    from a zero guess, the first cycle at once).  The solution, cycles
  *    and history are those of the step-by-step loop; a wrong guess costs
- *    one V-cycle of device time.  Default 1. */
+ *    one V-cycle of device time.  Default 1.
+ *  PT_OPT_TAIL_CELLS: the largest level (in cells) the single-block tail
+ *    may hold; 0 (default): as many coarse levels as fit its LDS.  The
+ *    levels above it run as grid kernels with the same arithmetic. */
 typedef enum {
     PT_OPT_GRAPHS = 1,
     PT_OPT_TAIL = 2,
     PT_OPT_FUSED = 3,
     PT_OPT_TIMING_EVERY = 4,
-    PT_OPT_SPECULATE = 5
+    PT_OPT_SPECULATE = 5,
+    PT_OPT_TAIL_CELLS = 6
 } pt_option;
 int pt_mg_set_option(pt_mg_t h, int option, int value);
 int pt_mg_get_option(pt_mg_t h, int option);

@@ -239,6 +239,7 @@ struct pt_mg_s {
     size_t tail_lds = 0;
     int tail_ainv_off = -1;
     bool use_tail = true;
+    long long tail_max_cells = 0;   // largest level the tail may hold (0: LDS-limited only)
 
     template <typename T> T *at(size_t off) { return off == (size_t)-1 ? nullptr : (T *)(base + off); }
     double2 *ac64() { return at<double2>(P.o_ac64); }
@@ -521,7 +522,8 @@ template <typename R> void coarse_cycle(pt_mg_t h, int nu1, int nu2)
         vcycle<R>(h, 1, nu1, nu2);
         return;
     }
-    const int key = nu1 * 16 + nu2 + (h->use_fused ? 256 : 0) + (h->use_tail ? 512 : 0);
+    const int key = nu1 * 16 + nu2 + (h->use_fused ? 256 : 0) + (h->use_tail ? 512 : 0) +
+                    (h->tail_lt << 10);
     const unsigned state = h->u_cur & ~1u;
     CoarseGraph *g = nullptr;
     for (auto &c : h->graphs)
@@ -818,6 +820,7 @@ void plan_tail(pt_mg_t h)
     int lt = P.nlev - 1;
     for (int l = P.nlev - 2; l >= 1; l--) {
         if (total + need(l) > budget || P.nlev - l > kMaxTail) break;
+        if (h->tail_max_cells > 0 && P.lv[l].N > h->tail_max_cells) break;
         total += need(l);
         lt = l;
     }
@@ -1848,6 +1851,11 @@ int pt_mg_set_option(pt_mg_t h, int option, int value)
     else if (option == PT_OPT_TAIL) h->use_tail = value != 0;
     else if (option == PT_OPT_FUSED) h->use_fused = value != 0;
     else if (option == PT_OPT_SPECULATE) h->speculate = value != 0;
+    else if (option == PT_OPT_TAIL_CELLS) {
+        if (value < 0) return fail(h, PT_ERR_ARG, "PT_OPT_TAIL_CELLS must be >= 0");
+        h->tail_max_cells = value;
+        plan_tail(h);
+    }
     else if (option == PT_OPT_TIMING_EVERY) {
         if (value < 1) return fail(h, PT_ERR_ARG, "PT_OPT_TIMING_EVERY must be >= 1");
         h->timing_every = value;
@@ -1863,6 +1871,7 @@ int pt_mg_get_option(pt_mg_t h, int option)
     if (option == PT_OPT_TIMING_EVERY) return h->timing_every;
     if (option == PT_OPT_SPECULATE) return h->speculate ? 1 : 0;
     if (option == PT_OPT_TAIL) return (h->use_tail && h->tail_lt > 0) ? h->P.nlev - h->tail_lt : 0;
+    if (option == PT_OPT_TAIL_CELLS) return (int)h->tail_max_cells;
     return -1;
 }
 

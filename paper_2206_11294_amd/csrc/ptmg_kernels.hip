@@ -12,6 +12,8 @@
 #include <algorithm>
 #include <cstdlib>
 
+#include <mutex>
+
 #include "ptmg_internal.h"
 
 namespace ptmg {
@@ -2921,6 +2923,14 @@ template bool launch_tail<double>(int, const TailArgs<double> &, size_t, hipStre
 template <typename R>
 void tail_set_lds_limit(int dim, size_t bytes)
 {
+    // the limit belongs to the kernel, shared by every handle of the
+    // process: it only grows, so no handle's tail is left without its LDS
+    static std::mutex mu;
+    static size_t granted[2] = {0, 0};
+    std::lock_guard<std::mutex> lock(mu);
+    size_t &g = granted[dim == 3 ? 1 : 0];
+    if (bytes <= g) return;
+    g = bytes;
     if (dim == 3)
         (void)hipFuncSetAttribute((const void *)k_tail<R, 3>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);

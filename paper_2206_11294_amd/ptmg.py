@@ -22,6 +22,7 @@ PT_COEF_EXPLICIT, PT_COEF_PHASES, PT_COEF_STATE = 0, 1, 2
 PT_PREC_FP64, PT_PREC_MIXED = 0, 1
 PT_MAX_HIST = 64
 PT_OPT_GRAPHS, PT_OPT_TAIL, PT_OPT_FUSED, PT_OPT_TIMING_EVERY, PT_OPT_SPECULATE = 1, 2, 3, 4, 5
+PT_OPT_TAIL_CELLS = 6
 KERNEL_CLASSES = ["outer_residual", "smooth_fine", "smooth_coarse", "restrict", "prolong",
                   "coarse_solve", "other", "downstream"]
 

@@ -437,3 +437,35 @@ def test_step_equals_update_rhs_solve(kind, prec):
         with pytest.raises(ptmg.PtMgError) as e:
             h.step(se, None, c_p, c_T, p2, T2)
         assert e.value.status == ptmg.PT_ERR_STATE
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_tail_cap_changes_no_result(prec):
+    """Capping the single-block tail moves its upper levels to the grid
+    kernels: fewer tail levels, the same solution and V-cycle bit for bit."""
+    import workloads.device as D
+    from paper_2206_11294_amd import ptmg
+    # levels of 122880, 30720, 7680, 1920, 480, 120 and 30 cells
+    prob = W.bubble_problem("b6", 2, (384, 320), [(0.4, 0.45)], [0.2], W.P0, 10 * W.P0,
+                            div_amp=1e-6, div_seed=12)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        h, b_p, b_T, _ = D.setup(prob, prec, stream=stream)
+        rng = np.random.default_rng(12)
+        f_p, f_T = dev(rng.uniform(-1, 1, h.N)), dev(rng.uniform(-1, 1, h.N))
+        out, levels = {}, {}
+        for cap in (0, 480, 120, 16):
+            h.set_option(ptmg.PT_OPT_TAIL_CELLS, cap)
+            assert h.get_option(ptmg.PT_OPT_TAIL_CELLS) == cap
+            levels[cap] = h.get_option(ptmg.PT_OPT_TAIL)
+            p, T = torch.empty_like(b_p), torch.empty_like(b_T)
+            h.solve(b_p, b_T, p, T, rtol=1e-12)
+            e = h.vcycle(f_p, f_T)
+            torch.cuda.synchronize()
+            out[cap] = (p.clone(), T.clone(), e[0].clone(), e[1].clone())
+        with pytest.raises(ptmg.PtMgError):
+            h.set_option(ptmg.PT_OPT_TAIL_CELLS, -1)
+    assert levels[0] >= levels[480] == 3 and levels[120] == 2 and levels[16] == 0
+    for cap in (480, 120, 16):
+        for a, b in zip(out[0], out[cap]):
+            assert torch.equal(a, b), (a - b).abs().max().item()
