@@ -146,3 +146,31 @@ def test_served_results_match_oracle():
         op, b_p, b_T, p_ref, T_ref = orc.solve(prob, rtol=1e-14, direct_max=0)
         assert rel_err(host(p), p_ref) <= 1e-8 and rel_err(host(T), T_ref) <= 1e-8
     srv.destroy()
+
+
+def test_rz_and_state_requests_in_the_mix():
+    """Axisymmetric and state-mode requests ride the same engine: each
+    result is the same bits as the request solved alone."""
+    import dataclasses
+    from paper_2206_11294_amd import serve
+    rng = np.random.default_rng(3)
+    probs = _requests(range(40, 44))
+    rz = [dataclasses.replace(W.serve_request(i, SIZES2D, [32]), axisymmetric=True)
+          for i in range(50, 60)]
+    probs += [p for p in rz if p.dim == 2][:2]
+    st = W.state_problem("srv_state", 2, (128, 96), [(0.5, 0.5)], [0.2], seed=44)
+    st = dataclasses.replace(st, uf_star=None,
+                             div_ustar=(1e-6 / st.dt) * rng.uniform(-1, 1, st.C.shape))
+    probs.append(st)
+    assert sum(p.axisymmetric for p in probs) == 2
+    alone = [_alone(p, 1e-10) for p in probs]
+    srv = serve.Server(hbm_budget=8 << 30, max_active=6)
+    reqs = _submit_all(srv, probs, 1e-10)
+    srv.run_until_idle()
+    torch.cuda.synchronize()
+    for (rid, p, T, prob), (pa, Ta, ia) in zip(reqs, alone):
+        info = srv.request(rid)
+        assert info["status"] == 0, (prob.name, info)
+        assert info["cycles"] == ia["cycles"]
+        assert torch.equal(p, pa) and torch.equal(T, Ta), prob.name
+    srv.destroy()
