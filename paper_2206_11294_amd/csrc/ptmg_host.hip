@@ -145,8 +145,7 @@ const char *plan_problem(const pt_problem *p, int prec, Plan &P)
     P.m = (int)(2 * Nc);
     P.o_gj0 = P.take(8ull * P.m * P.m);
     P.o_gj1 = P.take(8ull * P.m * P.m);
-    P.nblocks = std::max(std::max(outer_blocks(P.N), sum2_blocks(P.N)),
-                         outer_zm_blocks(p->dim, p->n[0], p->n[1], p->n[2]));
+    P.nblocks = std::max(sum2_blocks(P.N), outer_zm_blocks(p->dim, p->n[0], p->n[1], p->n[2]));
     P.o_partials = P.take(8ull * (4 * ((size_t)P.nblocks + reduce_scratch(P.nblocks)) + 16));
     P.o_flags = P.take(sizeof(int) * NFLAGS);
     return nullptr;

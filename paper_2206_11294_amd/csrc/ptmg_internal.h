@@ -143,11 +143,8 @@ void launch_paper_rhs(long long N, const double4 *B64, const double *p_adv, doub
                       double *b_p, double *b_T, hipStream_t s);
 
 template <typename RV>
-int launch_outer(int dim, const OuterArgs<RV> &a, hipStream_t s);   // returns #blocks
-template <typename RV>
 int launch_outer_zm(int dim, const OuterArgs<RV> &a, hipStream_t s);   // returns #blocks
 int outer_zm_blocks(int dim, int nx, int ny, int nz);
-int outer_blocks(long long N);
 int reduce_scratch(int nblocks);   // extra partial slots launch_reduce4 needs
 void launch_reduce4(const double *partials, int nblocks, double *out4, hipStream_t s);
 void launch_sum2(long long N, const double *x, const double *y, double *partials, int nblocks,

@@ -362,108 +362,7 @@ void launch_paper_rhs(long long N, const double4 *B64, const double *p_adv, doub
                        T_adv, T_const, div, dt, b_p, b_T);
 }
 
-// ---------------------------------------------------- outer FP64 residual
-// u_new = u + du (when update), residual of the mode-native form (paper
-// form Eqs. 27-28 in phases mode, computed directly so that its rounding
-// does not depend on the size of b), the canonical residual for the
-// V-cycle (r_T = -res_T, r_p = -res_p + l4 res_T), and per-block sums of
-// res_p^2, res_T^2, b_p^2, b_T^2.
-template <int DIM, typename RV>
-__global__ __launch_bounds__(kBlock) void k_outer(OuterArgs<RV> a)
-{
-    using V2 = typename VT<RV>::v2;
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    const long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
-    if (t < a.N) {
-        int i, j, k;
-        decode(t, a.nx, a.ny, i, j, k);
-        const long long me = t;
-        auto U = [&](long long q) {
-            double2 v = make_double2(a.src_p[q], a.src_T[q]);
-            if (a.update) {
-                V2 d = a.du[q];
-                v.x += (double)d.x;
-                v.y += (double)d.y;
-            }
-            return v;
-        };
-        double2 um = U(me);
-        double2 am = a.ac[me];
-        double nbp = 0.0, nbT = 0.0, Sp = 0.0, ST = 0.0;
-        auto acc_nb = [&](long long q) {
-            double2 w = harm2(am, a.ac[q]);
-            w.x *= a.inv_h2;
-            w.y *= a.inv_h2;
-            double2 uq = U(q);
-            Sp += w.x;
-            ST += w.y;
-            nbp += w.x * uq.x;
-            nbT += w.y * uq.y;
-        };
-        const long long sy = a.nx, sz = (long long)a.nx * a.ny;
-        if (i > 0) acc_nb(me - 1);
-        if (i < a.nx - 1) acc_nb(me + 1);
-        if (j > 0) acc_nb(me - sy);
-        if (j < a.ny - 1) acc_nb(me + sy);
-        if (DIM == 3) {
-            if (k > 0) acc_nb(me - sz);
-            if (k < a.nz - 1) acc_nb(me + sz);
-        }
-        const double Lp = Sp * um.x - nbp;   // -div(a_p grad p)
-        const double LT = ST * um.y - nbT;   // -div(a_T grad T)
-        const double4 B = a.B[me];
-        double bp = a.b_p[me], bT = a.b_T[me];
-        if (a.bshift) {
-            bp -= a.bshift_scale * a.bshift[0];
-            bT -= a.bshift_scale * a.bshift[1];
-        }
-        double resp, resT, rp, rT;
-        if (a.phases) {
-            const double l1 = -B.w, l2 = -B.z, l4 = B.y / l1, l3 = -B.x + l4 * l2;
-            resT = bT - (-LT + l1 * um.y + l2 * um.x);
-            resp = bp - (-Lp + l3 * um.x + l4 * (-LT));
-            rT = -resT;
-            rp = -resp + l4 * resT;
-        } else {
-            rp = bp - (Lp + B.x * um.x + B.y * um.y);
-            rT = bT - (LT + B.z * um.x + B.w * um.y);
-            resp = rp;
-            resT = rT;
-        }
-        if (a.update) {
-            a.dst_p[me] = um.x;
-            a.dst_T[me] = um.y;
-        }
-        if (a.r) {
-            V2 o;
-            o.x = (RV)rp;
-            o.y = (RV)rT;
-            a.r[me] = o;
-        }
-        if (a.res_p) a.res_p[me] = resp;
-        if (a.res_T) a.res_T[me] = resT;
-        acc[0] += resp * resp;
-        acc[1] += resT * resT;
-        acc[2] += bp * bp;
-        acc[3] += bT * bT;
-    }
-    block_reduce_store(acc, 4, a.partials + 4ll * blockIdx.x);
-}
 
-int outer_blocks(long long N) { return (int)nblk(N); }
-
-template <typename RV>
-int launch_outer(int dim, const OuterArgs<RV> &a, hipStream_t s)
-{
-    unsigned nb = (unsigned)outer_blocks(a.N);
-    if (dim == 3)
-        hipLaunchKernelGGL((k_outer<3, RV>), dim3(nb), dim3(kBlock), 0, s, a);
-    else
-        hipLaunchKernelGGL((k_outer<2, RV>), dim3(nb), dim3(kBlock), 0, s, a);
-    return (int)nb;
-}
-template int launch_outer<float>(int, const OuterArgs<float> &, hipStream_t);
-template int launch_outer<double>(int, const OuterArgs<double> &, hipStream_t);
 
 // Fixed-order reduction of per-block partial sums (`width` per block).
 __global__ __launch_bounds__(kBlock) void k_reduce(const double *partials, int nblocks, int width,
@@ -2220,6 +2119,12 @@ bool launch_gj_lds(const double *A, double *Ainv, int m, int *flags, hipStream_t
 namespace ptmg {
 
 // -------------------------------------------- plane-marching stencils
+// The FP64 outer residual: u_new = u + du (when update), the residual of
+// the mode-native form (paper form Eqs. 27-28 in phases and state mode,
+// computed directly so that its rounding does not depend on the size of
+// b), the canonical residual for the V-cycle (r_T = -res_T,
+// r_p = -res_p + l4 res_T), and per-block sums of res_p^2, res_T^2, b_p^2,
+// b_T^2 for the fixed-order norm reduction.
 // The FP64 outer residual and the finest-grid residual + restriction as
 // z-marching tiles: a 4-slot LDS ring of planes (tile + a ring of one
 // cell) so that every array element is read from HBM once, with the next
