@@ -492,8 +492,8 @@ def main():
     if not args.no_oracle_check and prob.ncells <= 2_500_000:
         import oracle as orc
         op = orc.assemble(prob)
+        bp, bT = orc.rhs(op, prob)   # the oracle's own right-hand side
         P, TT = p.cpu().numpy(), T.cpu().numpy()
-        bp, bT = b_p.cpu().numpy(), b_T.cpu().numpy()
         out["oracle_relres_of_gpu_solution"] = [float(x) for x in orc.relres(op, bp, bT, P, TT)]
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, rtol, args.cpu_seconds)

@@ -84,8 +84,8 @@ def test_axi_level0_steps(prec):
     # outer residual (FP64 in both precisions)
     p = prob.p_adv.reshape(-1) * (1 + 1e-3 * rng.standard_normal(N))
     T = W.T0 * (1 + 1e-4 * rng.standard_normal(N))
-    bp, bT = host(b_p), host(b_T)
-    r_p, r_T, rel = h.residual(b_p, b_T, dev(p), dev(T))
+    bp, bT = orc.rhs(op, prob)   # the oracle's right-hand side, input of both
+    r_p, r_T, rel = h.residual(dev(bp), dev(bT), dev(p), dev(T))
     o_rp, o_rT = orc.paper_residual(op, bp, bT, p, T)
     scale = lambda a: max(np.abs(a).max(), 1e-300)
     assert np.abs(host(r_p) - o_rp).max() <= 1e-11 * scale(o_rp)

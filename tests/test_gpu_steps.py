@@ -34,7 +34,22 @@ def case(request):
     for l in range(1, out["fp64"][0].num_levels()):
         ops.append(orc.coarse_operator(ops[-1]))
     out["ops"] = ops
+    # the FP32 hierarchy of the mixed-precision V-cycle, built on the oracle
+    # side: each coarse level is the averaging of the level above (summed in
+    # FP64) rounded to FP32, level 1 from the FP64 finest operator
+    ops32 = [None]
+    src = op
+    for l in range(1, out["fp64"][0].num_levels()):
+        c = orc.coarse_operator(src)
+        c = orc.Operator(c.dim, c.n, c.h, _f32(c.F), _f32(c.B))
+        ops32.append(c)
+        src = c
+    out["ops32"] = ops32
     return out
+
+
+def _f32(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float32), dtype=np.float64)
 
 
 def _close(a, b, rtol_scale, label):
@@ -94,8 +109,9 @@ def test_outer_residual(case, prec):
         T = prob.T_adv_const * (1 + 1e-4 * rng.standard_normal(N))
     else:
         p, T = rng.standard_normal(N), rng.standard_normal(N)
-    bp, bT = host(b_p), host(b_T)
-    r_p, r_T, rel = h.residual(b_p, b_T, dev(p), dev(T))
+    # both sides take the oracle's right-hand side as the input
+    bp, bT = orc.rhs(op, prob)
+    r_p, r_T, rel = h.residual(dev(bp), dev(bT), dev(p), dev(T))
     if prob.mode == "phases":
         op_rp, op_rT = orc.paper_residual(op, bp, bT, p, T)
     else:
@@ -124,8 +140,7 @@ def test_smoother_matches_red_black_sweep(case, prec):
     tol = 1e-12 if prec == "fp64" else 3e-5
     for l, op in enumerate(case["ops"]):
         if prec == "mixed" and l > 0:
-            F, B = h.get_operator(l)      # the FP32 operator the V-cycle uses
-            op = orc.Operator(op.dim, op.n, op.h, host(F), host(B))
+            op = case["ops32"][l]         # the FP32 operator the V-cycle uses
         f_p, f_T, u_p, u_T = _level_fields(op, 100 + l)
         gp, gT = dev(u_p), dev(u_T)
         h.smooth(l, dev(f_p), dev(f_T), gp, gT, sweeps=1)
@@ -144,8 +159,7 @@ def test_restrict_residual(case, prec):
     for l in range(len(ops) - 1):
         op = ops[l]
         if prec == "mixed" and l > 0:
-            F, B = h.get_operator(l)
-            op = orc.Operator(op.dim, op.n, op.h, host(F), host(B))
+            op = case["ops32"][l]
         f_p, f_T, u_p, u_T = _level_fields(op, 200 + l)
         fc_p, fc_T = h.restrict_residual(l, dev(f_p), dev(f_T), dev(u_p), dev(u_T))
         r_p, r_T = orc.residual(op, f_p, f_T, u_p, u_T)
@@ -178,9 +192,9 @@ def test_coarse_solve(case, prec):
     against LU of the same operator."""
     h = case[prec][0]
     L = h.num_levels() - 1
-    F, B = h.get_operator(L)
     op = case["ops"][L]
-    opg = orc.Operator(op.dim, op.n, op.h, host(F), host(B))
+    # the coarsest operator the library inverts, built on the oracle side
+    opg = op if (prec == "fp64" or L == 0) else case["ops32"][L]
     rng = np.random.default_rng(4)
     f_p, f_T = rng.uniform(-1, 1, op.N), rng.uniform(-1, 1, op.N)
     if prec == "mixed":   # the V-cycle hands FP32 values to the coarse solve
