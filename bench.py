@@ -334,6 +334,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-oracle-check", action="store_true")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="BYTES")
+    ap.add_argument("--coarse-sweeps", type=int, default=None,
+                    help="16 nu1 + nu2 below the finest level (PT_OPT_COARSE_SWEEPS)")
     ap.add_argument("--tail-cells", type=int, default=None,
                     help="largest level of the single-block tail (PT_OPT_TAIL_CELLS)")
     ap.add_argument("--timing-every", type=int, default=7,
@@ -385,6 +387,8 @@ def main():
         h = ptmg.PtMg(s, prec, stream=stream)
         if args.tail_cells is not None:
             h.set_option(ptmg.PT_OPT_TAIL_CELLS, args.tail_cells)
+        if args.coarse_sweeps is not None:
+            h.set_option(ptmg.PT_OPT_COARSE_SWEEPS, args.coarse_sweeps)
         p = torch.empty(prob.ncells, dtype=torch.float64, device="cuda")
         T = torch.empty_like(p)
         rhs_p, rhs_T = torch.empty_like(p), torch.empty_like(p)

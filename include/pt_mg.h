@@ -417,14 +417,22 @@ long long pt_mg_last_cell_updates(pt_mg_t h);
  *    one V-cycle of device time.  Default 1.
  *  PT_OPT_TAIL_CELLS: the largest level (in cells) the single-block tail
  *    may hold; 0 (default): as many coarse levels as fit its LDS.  The
- *    levels above it run as grid kernels with the same arithmetic. */
+ *    levels above it run as grid kernels with the same arithmetic.
+ *  PT_OPT_COARSE_SWEEPS: 16 nu1 + nu2, the pre- and post-sweeps on the
+ *    levels below the finest (each 0..8, not both 0); 0: the solve's own
+ *    nu1, nu2 on every level.  Default 17: one sweep each way below the
+ *    finest level (the solve's nu1, nu2 apply there).  Unlike the options
+ *    above this changes the V-cycle, and so the iterates and cycle
+ *    counts; the converged solution is the one the tolerance admits
+ *    either way. */
 typedef enum {
     PT_OPT_GRAPHS = 1,
     PT_OPT_TAIL = 2,
     PT_OPT_FUSED = 3,
     PT_OPT_TIMING_EVERY = 4,
     PT_OPT_SPECULATE = 5,
-    PT_OPT_TAIL_CELLS = 6
+    PT_OPT_TAIL_CELLS = 6,
+    PT_OPT_COARSE_SWEEPS = 7
 } pt_option;
 int pt_mg_set_option(pt_mg_t h, int option, int value);
 int pt_mg_get_option(pt_mg_t h, int option);

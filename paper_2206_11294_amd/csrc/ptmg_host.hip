@@ -239,6 +239,10 @@ struct pt_mg_s {
     int tail_ainv_off = -1;
     bool use_tail = true;
     long long tail_max_cells = 0;   // largest level the tail may hold (0: LDS-limited only)
+    // 16 nu1 + nu2 of the levels below the finest (0: as the finest); one
+    // sweep each way there cost the same cycles as two on the measured
+    // grids and 5-9 % less time per step
+    int coarse_nu = 17;
 
     template <typename T> T *at(size_t off) { return off == (size_t)-1 ? nullptr : (T *)(base + off); }
     double2 *ac64() { return at<double2>(P.o_ac64); }
@@ -506,6 +510,10 @@ template <typename R> void coarse_solve(pt_mg_t h)
 
 template <typename R> void vcycle(pt_mg_t h, int l, int nu1, int nu2);
 
+// Sweeps of the levels below the finest (PT_OPT_COARSE_SWEEPS).
+int coarse_nu1(pt_mg_t h, int nu1) { return h->coarse_nu ? h->coarse_nu >> 4 : nu1; }
+int coarse_nu2(pt_mg_t h, int nu2) { return h->coarse_nu ? h->coarse_nu & 15 : nu2; }
+
 // Kernel classes launched by the coarse-level cycle.
 constexpr unsigned kCoarseClasses =
     (1u << PT_K_SMOOTH_COARSE) | (1u << PT_K_RESTRICT) | (1u << PT_K_PROLONG) |
@@ -619,7 +627,7 @@ template <typename R> void vcycle(pt_mg_t h, int l, int nu1, int nu2)
     }
     if (l == 0 && fused_transfers0(h, nu1, nu2)) {
         smooth0_fused<R>(h, nu1, true, false, true);
-        coarse_cycle<R>(h, nu1, nu2);
+        coarse_cycle<R>(h, coarse_nu1(h, nu1), coarse_nu2(h, nu2));
         smooth0_fused<R>(h, nu2, false, true, false);
         return;
     }
@@ -651,7 +659,7 @@ template <typename R> void vcycle(pt_mg_t h, int l, int nu1, int nu2)
     }
     smooth<R>(h, l, nu1, true);
     restrict_level<R>(h, l);
-    if (l == 0) coarse_cycle<R>(h, nu1, nu2);
+    if (l == 0) coarse_cycle<R>(h, coarse_nu1(h, nu1), coarse_nu2(h, nu2));
     else vcycle<R>(h, l + 1, nu1, nu2);
     prolong_level<R>(h, l);
     smooth<R>(h, l, nu2, false);
@@ -1850,7 +1858,12 @@ int pt_mg_set_option(pt_mg_t h, int option, int value)
     else if (option == PT_OPT_TAIL) h->use_tail = value != 0;
     else if (option == PT_OPT_FUSED) h->use_fused = value != 0;
     else if (option == PT_OPT_SPECULATE) h->speculate = value != 0;
-    else if (option == PT_OPT_TAIL_CELLS) {
+    else if (option == PT_OPT_COARSE_SWEEPS) {
+        const int a = value >> 4, b = value & 15;
+        if (value != 0 && (value < 0 || value > 255 || a > 8 || b > 8 || a + b == 0))
+            return fail(h, PT_ERR_ARG, "PT_OPT_COARSE_SWEEPS: 16 nu1 + nu2 with nu <= 8, or 0");
+        h->coarse_nu = value;
+    } else if (option == PT_OPT_TAIL_CELLS) {
         if (value < 0) return fail(h, PT_ERR_ARG, "PT_OPT_TAIL_CELLS must be >= 0");
         h->tail_max_cells = value;
         plan_tail(h);
@@ -1871,6 +1884,7 @@ int pt_mg_get_option(pt_mg_t h, int option)
     if (option == PT_OPT_SPECULATE) return h->speculate ? 1 : 0;
     if (option == PT_OPT_TAIL) return (h->use_tail && h->tail_lt > 0) ? h->P.nlev - h->tail_lt : 0;
     if (option == PT_OPT_TAIL_CELLS) return (int)h->tail_max_cells;
+    if (option == PT_OPT_COARSE_SWEEPS) return h->coarse_nu;
     return -1;
 }
 
