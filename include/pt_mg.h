@@ -420,8 +420,10 @@ long long pt_mg_last_cell_updates(pt_mg_t h);
  *    levels above it run as grid kernels with the same arithmetic.
  *  PT_OPT_COARSE_SWEEPS: 16 nu1 + nu2, the pre- and post-sweeps on the
  *    levels below the finest (each 0..8, not both 0); 0: the solve's own
- *    nu1, nu2 on every level.  Default 17: one sweep each way below the
- *    finest level (the solve's nu1, nu2 apply there).  Unlike the options
+ *    nu1, nu2 on every level (the default).  Steps whose coarse
+ *    levels are dominated by the acoustic block term converge as fast with
+ *    17 (one sweep each way) for less time; diffusion-dominated steps need
+ *    the full counts there.  Unlike the options
  *    above this changes the V-cycle, and so the iterates and cycle
  *    counts; the converged solution is the one the tolerance admits
  *    either way. */

@@ -239,10 +239,10 @@ struct pt_mg_s {
     int tail_ainv_off = -1;
     bool use_tail = true;
     long long tail_max_cells = 0;   // largest level the tail may hold (0: LDS-limited only)
-    // 16 nu1 + nu2 of the levels below the finest (0: as the finest); one
-    // sweep each way there cost the same cycles as two on the measured
-    // grids and 5-9 % less time per step
-    int coarse_nu = 17;
+    // 16 nu1 + nu2 of the levels below the finest (0: as the finest).  One
+    // sweep each way there saves time on acoustic steps but costs cycles on
+    // diffusion-dominated ones, so the default keeps the solve's own counts.
+    int coarse_nu = 0;
 
     template <typename T> T *at(size_t off) { return off == (size_t)-1 ? nullptr : (T *)(base + off); }
     double2 *ac64() { return at<double2>(P.o_ac64); }

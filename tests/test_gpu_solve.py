@@ -283,8 +283,7 @@ def test_coarse_half_cycles_match_reference(nu, prec):
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         h, b_p, b_T, _ = D.setup(prob, prec, stream=stream)
-        # the coarse levels take the pair under test (not the default one
-        # sweep each way below the finest level)
+        # the coarse levels take the pair under test, whatever the default
         h.set_option(ptmg.PT_OPT_COARSE_SWEEPS, 0)
         rng = np.random.default_rng(5)
         f_p, f_T = dev(rng.uniform(-1, 1, h.N)), dev(rng.uniform(-1, 1, h.N))
@@ -475,7 +474,7 @@ def test_tail_cap_changes_no_result(prec):
 
 
 def test_coarse_sweeps_option():
-    """PT_OPT_COARSE_SWEEPS: default one sweep each way below the finest
+    """PT_OPT_COARSE_SWEEPS: by default the solve's own counts on every
     level; other settings change the V-cycle but the solve still meets the
     tolerance against the oracle; invalid values are refused."""
     import workloads.device as D
@@ -483,9 +482,9 @@ def test_coarse_sweeps_option():
     prob = step_problems()["bubble2d_200x136"]
     op, b_p, b_T, p_ref, T_ref = orc.solve(prob)
     h, gb_p, gb_T, _ = D.setup(prob, 0)
-    assert h.get_option(ptmg.PT_OPT_COARSE_SWEEPS) == 17
+    assert h.get_option(ptmg.PT_OPT_COARSE_SWEEPS) == 0
     hists = {}
-    for v in (17, 0, 33, 16 * 2 + 1):
+    for v in (0, 17, 33, 16 * 2 + 1):
         h.set_option(ptmg.PT_OPT_COARSE_SWEEPS, v)
         p, T = torch.empty_like(gb_p), torch.empty_like(gb_T)
         info = h.solve(gb_p, gb_T, p, T, rtol=1e-12)
