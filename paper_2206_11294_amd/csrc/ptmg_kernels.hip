@@ -1196,11 +1196,13 @@ __global__ __launch_bounds__(TX *TY) void k_rb_fused3(Lvl<R> L, typename VT<R>::
     // fz) instead of cell coefficients; faces of plane z are needed while
     // planes z-1 .. z+1 update, so they live in a 4-slot ring.
     // Software-pipelined walk over a 5-plane LDS ring: while plane step k
-    // computes, the global loads of step k+1 (plane k+3 and the f, B of
-    // the next red and black cells) are in flight in registers.  Five
-    // slots let the store of plane k+2 overwrite plane k-3, whose last
-    // reader finished before the previous barrier, so each step needs
-    // two barriers.
+    // computes, the global loads of steps k+1 and k+2 (planes k+3, k+4 and
+    // the f, B of their red and black cells) are in flight in registers,
+    // three register sets taken in turn (the loop is unrolled by three, so
+    // no set is copied while its loads are outstanding).  Five slots let
+    // the store of plane k+2 overwrite plane k-3, whose last reader
+    // finished before the previous barrier, so each step needs two
+    // barriers.
     using V2 = typename VT<R>::v2;
     using V4 = typename VT<R>::v4;
     constexpr int NT = TX * TY;
@@ -1227,49 +1229,56 @@ __global__ __launch_bounds__(TX *TY) void k_rb_fused3(Lvl<R> L, typename VT<R>::
     auto slot = [](int z) { return (z + 10) % 5; };   // z >= -2
     auto fslot = [](int z) { return (z + 8) & 3; };
 
-    // ---- per-thread pieces of a plane step
-    V2 pu[NLD], pa[NLD], pfx[NLF], pfy[NLF], pfz[NLF];
-    auto fetch_plane = [&](int z) {
+    // ---- per-thread pieces of a plane step: the global loads of step k
+    // (plane k+2, f and B of the red cell on plane k+1 and of the black
+    // cell on plane k) in registers
+    struct Step {
+        V2 pu[NLD], pa[NLD], pfx[NLF], pfy[NLF], pfz[NLF];
+        int rc, bc;
+        V2 rf, bf;
+        V4 rB, bB;
+    };
+    auto fetch_plane = [&](int z, Step &S) {
 #pragma unroll
         for (int i = 0; i < NLD; i++) {
             const int c = t + i * NT;
-            pu[i].x = pu[i].y = R(0);
-            pa[i].x = pa[i].y = R(0);
+            S.pu[i].x = S.pu[i].y = R(0);
+            S.pa[i].x = S.pa[i].y = R(0);
             if (FACES) {
-                pfx[i].x = pfx[i].y = R(0);
-                pfy[i].x = pfy[i].y = R(0);
-                pfz[i].x = pfz[i].y = R(0);
+                S.pfx[i].x = S.pfx[i].y = R(0);
+                S.pfy[i].x = S.pfy[i].y = R(0);
+                S.pfz[i].x = S.pfz[i].y = R(0);
             }
             if (c < PS) {
                 const int gx = x0 + c % PX - 2, gy = y0 + c / PX - 2;
                 if (z >= 0 && z < L.nz && gx >= 0 && gx < L.nx && gy >= 0 && gy < L.ny) {
                     const long long g = gx + (long long)L.nx * gy + nxy * z;
                     if (FACES) {
-                        pfx[i] = L.fx[g];
-                        pfy[i] = L.fy[g];
-                        pfz[i] = L.fz[g];
+                        S.pfx[i] = L.fx[g];
+                        S.pfy[i] = L.fy[g];
+                        S.pfz[i] = L.fz[g];
                     } else {
-                        pa[i] = L.ac[g];
+                        S.pa[i] = L.ac[g];
                     }
-                    if (!ZG) pu[i] = L.u[g];
+                    if (!ZG) S.pu[i] = L.u[g];
                 }
             }
         }
     };
-    auto store_plane = [&](int z) {
+    auto store_plane = [&](int z, const Step &S) {
         const int s = slot(z);
 #pragma unroll
         for (int i = 0; i < NLD; i++) {
             const int c = t + i * NT;
             if (c < PS) {
-                su[s][c] = pu[i];
+                su[s][c] = S.pu[i];
                 if (FACES) {
                     const int fs = fslot(z);
-                    sfx[fs][c] = pfx[i];
-                    sfy[fs][c] = pfy[i];
-                    sfz[fs][c] = pfz[i];
+                    sfx[fs][c] = S.pfx[i];
+                    sfy[fs][c] = S.pfy[i];
+                    sfz[fs][c] = S.pfz[i];
                 } else {
-                    sa[s][c] = pa[i];
+                    sa[s][c] = S.pa[i];
                 }
             }
         }
@@ -1340,10 +1349,41 @@ __global__ __launch_bounds__(TX *TY) void k_rb_fused3(Lvl<R> L, typename VT<R>::
         }
     };
 
+    // the global loads of step k (none past the chunk's last step)
+    auto load_step = [&](int k, Step &S) {
+        S.rc = S.bc = -1;
+        if (k >= z1) return;
+        long long g;
+        fetch_plane(k + 2, S);
+        red_cell(k + 1, S.rc, g);
+        if (S.rc >= 0) {
+            S.rf = L.f[g];
+            S.rB = L.B[g];
+        }
+        black_cell(k, S.bc, g);
+        if (S.bc >= 0) {
+            S.bf = L.f[g];
+            S.bB = L.B[g];
+        }
+    };
+    // plane step k from the set `cur`; the loads of step k+2 go to `ahead`
+    auto body = [&](int k, const Step &cur, Step &ahead) {
+        store_plane(k + 2, cur);
+        load_step(k + 2, ahead);
+        __syncthreads();
+        write_plane(k - 1);
+        if (cur.rc >= 0) update(k + 1, cur.rc, cur.rf, cur.rB);
+        __syncthreads();
+        if (cur.bc >= 0) update(k, cur.bc, cur.bf, cur.bB);
+    };
+
     // ---- prologue: planes z0-2 .. z0+1, red on z0-1 and z0
-    for (int z = z0 - 2; z <= z0 + 1; z++) {
-        fetch_plane(z);
-        store_plane(z);
+    {
+        Step S;
+        for (int z = z0 - 2; z <= z0 + 1; z++) {
+            fetch_plane(z, S);
+            store_plane(z, S);
+        }
     }
     __syncthreads();
     for (int z = z0 - 1; z <= z0; z++) {
@@ -1353,53 +1393,16 @@ __global__ __launch_bounds__(TX *TY) void k_rb_fused3(Lvl<R> L, typename VT<R>::
         if (c >= 0) update(z, c, L.f[g], L.B[g]);
         __syncthreads();
     }
-    // in flight for step z0: plane z0+2, red of z0+1, black of z0
-    int rc, bc;
-    long long rg, bg;
-    V2 rf, bf;
-    V4 rB, bB;
-    fetch_plane(z0 + 2);
-    red_cell(z0 + 1, rc, rg);
-    if (rc >= 0) {
-        rf = L.f[rg];
-        rB = L.B[rg];
-    }
-    black_cell(z0, bc, bg);
-    if (bc >= 0) {
-        bf = L.f[bg];
-        bB = L.B[bg];
-    }
-    for (int k = z0; k < z1; k++) {
-        store_plane(k + 2);
-        // issue the loads of step k+1
-        int rcn, bcn;
-        long long rgn, bgn;
-        V2 rfn, bfn;
-        V4 rBn, bBn;
-        fetch_plane(k + 3);
-        red_cell(k + 2, rcn, rgn);
-        if (rcn >= 0) {
-            rfn = L.f[rgn];
-            rBn = L.B[rgn];
-        }
-        black_cell(k + 1, bcn, bgn);
-        if (bcn >= 0 && k + 1 < z1) {
-            bfn = L.f[bgn];
-            bBn = L.B[bgn];
-        }
-        __syncthreads();
-        write_plane(k - 1);
-        if (rc >= 0) update(k + 1, rc, rf, rB);
-        __syncthreads();
-        if (bc >= 0) update(k, bc, bf, bB);
-        rc = rcn;
-        rg = rgn;
-        rf = rfn;
-        rB = rBn;
-        bc = (k + 1 < z1) ? bcn : -1;
-        bg = bgn;
-        bf = bfn;
-        bB = bBn;
+    // in flight for steps z0 and z0+1
+    Step A, B, C;
+    load_step(z0, A);
+    load_step(z0 + 1, B);
+    for (int k = z0; k < z1; k += 3) {
+        body(k, A, C);
+        if (k + 1 >= z1) break;
+        body(k + 1, B, A);
+        if (k + 2 >= z1) break;
+        body(k + 2, C, B);
     }
     __syncthreads();
     write_plane(z1 - 1);
@@ -2648,7 +2651,45 @@ __global__ __launch_bounds__(DIM == 3 ? 512 : 1024) void k_tail(TailArgs<R> A)
     if (A.ainv_off >= 0)
         for (int e = t + NT; e < A.m * A.m; e += NT)
             ((double *)(lds + A.ainv_off))[e] = A.Ainv[e];
+    // Sizes and LDS offsets of every level, staged in LDS so that the level
+    // loops below run over a dynamic level index with one copy of each
+    // phase's code.  Unrolled over the levels, the kernel grows past the
+    // instruction cache, and the single block then stalls on instruction
+    // fetches at every phase.
+    __shared__ int smeta[kMaxTail][10];
+    __shared__ double sih2[kMaxTail];
+    if (t == 0) {
+#pragma unroll
+        for (int q = 0; q < kMaxTail; q++) {
+            smeta[q][0] = A.g[q].nx;
+            smeta[q][1] = A.g[q].ny;
+            smeta[q][2] = A.g[q].nz;
+            smeta[q][3] = (int)A.g[q].N;
+#pragma unroll
+            for (int i = 0; i < 6; i++) smeta[q][4 + i] = A.off[q][i];
+            sih2[q] = A.g[q].inv_h2;
+        }
+    }
     __syncthreads();
+    // the LDS view of level q (face levels: no cell coefficients, no r-z
+    // metric)
+    auto lview = [&](int q) {
+        Lvl<R> v;
+        v.nx = smeta[q][0];
+        v.ny = smeta[q][1];
+        v.nz = smeta[q][2];
+        v.N = smeta[q][3];
+        v.inv_h2 = sih2[q];
+        v.ac = nullptr;
+        v.axm = nullptr;
+        v.u = (V2 *)(lds + smeta[q][4]);
+        v.f = (V2 *)(lds + smeta[q][5]);
+        v.fx = (const V2 *)(lds + smeta[q][6]);
+        v.fy = (const V2 *)(lds + smeta[q][7]);
+        v.fz = DIM == 3 ? (const V2 *)(lds + smeta[q][8]) : nullptr;
+        v.B = (const V4 *)(lds + smeta[q][9]);
+        return v;
+    };
     // Levels of at most 64 cells run in wavefront 0 alone: its lanes
     // exchange values through LDS in program order, so a wavefront-scope
     // fence replaces the block barrier between phases.
@@ -2692,7 +2733,7 @@ __global__ __launch_bounds__(DIM == 3 ? 512 : 1024) void k_tail(TailArgs<R> A)
     };
     // down on level q: smoothing from a zero guess, residual restricted
     auto down = [&](int q, bool wave) {
-        const Lvl<R> V = view(q), C = view(q + 1);
+        const Lvl<R> V = lview(q), C = lview(q + 1);
         const int stride = wave ? 64 : NT;
         if (A.nu1 == 0) {
             for (int e = t; e < (int)V.N; e += stride) {
@@ -2715,7 +2756,7 @@ __global__ __launch_bounds__(DIM == 3 ? 512 : 1024) void k_tail(TailArgs<R> A)
     };
     // up on level q: prolongation + correction, then smoothing
     auto up = [&](int q, bool wave) {
-        const Lvl<R> V = view(q), C = view(q + 1);
+        const Lvl<R> V = lview(q), C = lview(q + 1);
         const int stride = wave ? 64 : NT;
         for (int e = t; e < (int)V.N; e += stride) {
             int i, j, k;
@@ -2734,7 +2775,7 @@ __global__ __launch_bounds__(DIM == 3 ? 512 : 1024) void k_tail(TailArgs<R> A)
     // lanes, 64 / G rows at a time, and the butterfly's first steps, which
     // only add zeros, are skipped.
     auto coarsest = [&](int q, bool wave) {
-        const Lvl<R> C = view(q);
+        const Lvl<R> C = lview(q);
         const R *f = (const R *)C.f;
         R *u = (R *)C.u;
         const int lane = t & 63, wv = t >> 6;
@@ -2768,34 +2809,25 @@ __global__ __launch_bounds__(DIM == 3 ? 512 : 1024) void k_tail(TailArgs<R> A)
         }
         sync(wave);
     };
-    // block part, down
-#pragma unroll
-    for (int q = 0; q + 1 < kMaxTail; q++)
-        if (q + 1 < nl && q < w0) down(q, false);
-    if (w0 >= nl - 1) {   // no wavefront part: the coarsest grid block-wide
-#pragma unroll
-        for (int q = 1; q < kMaxTail; q++)
-            if (q == nl - 1) coarsest(q, false);
-    }
-    // wavefront part: down, coarsest, up
-    if (w0 < nl - 1) {
+    // levels 0 .. wb-1 run block-wide on the way down and up, levels
+    // wb .. nl-2 in the wavefront part; the coarsest is level nl-1
+    const int wb = min(w0, nl - 1);
+#pragma unroll 1
+    for (int q = 0; q < wb; q++) down(q, false);
+    if (wb == nl - 1) {
+        coarsest(nl - 1, false);   // no wavefront part: the coarsest block-wide
+    } else {
         if (t < 64) {
-#pragma unroll
-            for (int q = 0; q + 1 < kMaxTail; q++)
-                if (q + 1 < nl && q >= w0) down(q, true);
-#pragma unroll
-            for (int q = 1; q < kMaxTail; q++)
-                if (q == nl - 1) coarsest(q, true);
-#pragma unroll
-            for (int q = kMaxTail - 2; q >= 0; q--)
-                if (q + 1 < nl && q >= w0) up(q, true);
+#pragma unroll 1
+            for (int q = wb; q < nl - 1; q++) down(q, true);
+            coarsest(nl - 1, true);
+#pragma unroll 1
+            for (int q = nl - 2; q >= wb; q--) up(q, true);
         }
         __syncthreads();
     }
-    // block part, up
-#pragma unroll
-    for (int q = kMaxTail - 2; q >= 0; q--)
-        if (q + 1 < nl && q < w0) up(q, false);
+#pragma unroll 1
+    for (int q = wb - 1; q >= 0; q--) up(q, false);
     {
         const Lvl<R> V = view(0);
         for (int e = t; e < (int)V.N; e += NT) A.g[0].u[e] = V.u[e];
