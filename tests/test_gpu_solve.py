@@ -269,6 +269,37 @@ def test_tail_and_graph_paths_agree(name, prec):
         assert torch.equal(a, b), (a - b).abs().max().item()
 
 
+@pytest.mark.parametrize("nu", [(2, 2), (3, 2), (2, 1), (4, 3), (1, 2)])
+@pytest.mark.parametrize("name", ["bubble2d_200x136", "explicit_64", "twobubble2d_96x80"])
+def test_fused_solve_matches_reference_per_sweep_count(name, nu):
+    """2-D FP64 solves with the fused finest-level sweeps and transfers at
+    several (nu1, nu2): solution, cycles and every residual norm equal
+    those of the separate kernels (PT_OPT_FUSED off) bit for bit, on a grid
+    whose width is no multiple of the 256-column tiles and with the mean
+    constraint (explicit_64); the solve meets the tolerance against the
+    oracle's own right-hand side."""
+    import workloads.device as D
+    from paper_2206_11294_amd import ptmg
+    prob = step_problems()[name]
+    op = orc.assemble(prob)
+    b_p, b_T = orc.rhs(op, prob)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        h, gb_p, gb_T, _ = D.setup(prob, 0, stream=stream)
+        out = {}
+        for fused in (1, 0):
+            h.set_option(ptmg.PT_OPT_FUSED, fused)
+            p, T = torch.empty_like(gb_p), torch.empty_like(gb_T)
+            info = h.solve(gb_p, gb_T, p, T, rtol=1e-11, nu1=nu[0], nu2=nu[1], max_cycles=60)
+            torch.cuda.synchronize()
+            out[fused] = (p.clone(), T.clone(), info)
+    (p1, T1, i1), (p0, T0, i0) = out[1], out[0]
+    assert i1["status"] == i0["status"] == 0
+    assert i1["cycles"] == i0["cycles"] and i1["hist"] == i0["hist"]
+    assert torch.equal(p1, p0) and torch.equal(T1, T0)
+    assert max(orc.relres(op, b_p, b_T, host(p1), host(T1))) <= 2e-11
+
+
 @pytest.mark.parametrize("nu", [(1, 1), (2, 1), (1, 2), (2, 2), (3, 2), (0, 2)])
 @pytest.mark.parametrize("prec", [0, 1])
 def test_coarse_half_cycles_match_reference(nu, prec):
