@@ -412,7 +412,9 @@ long long pt_mg_last_cell_updates(pt_mg_t h);
  *    update, residual and norms) before the host has read the current
  *    norms, whenever the contraction seen so far predicts that the
  *    current iterate misses the tolerance by a factor of 3 or more (and,
- *    from a zero guess, the first cycle at once).  The solution, cycles
+ *    from a zero guess, the first cycle at once; the contraction of that
+ *    first cycle is taken no smaller than the last one of the handle's
+ *    previous solve).  The solution, cycles
  *    and history are those of the step-by-step loop; a wrong guess costs
  *    one V-cycle of device time.  Default 1.
  *  PT_OPT_TAIL_CELLS: the largest level (in cells) the single-block tail

@@ -189,8 +189,10 @@ struct pt_mg_s {
     // asynchronous solve (pt_mg_solve drives it to the end; a server polls it)
     // Outer iteration k computes u_k (k >= 1: after V-cycle k-1) and the
     // norms of its residual into pinned slot k & 1, marked by norm_ev[k & 1].
-    // u_k lives in the caller's (p, T) for even k and in the handle's
-    // second FP64 pair for odd k.  The host reads the norms of k_wait while
+    // u_k lives in the caller's (p, T) when k + parity is even and in the
+    // handle's second FP64 pair otherwise; a zero-guess solve takes the
+    // parity of the previous solve's last k, so that its answer most often
+    // lands in (p, T) with no copy.  The host reads the norms of k_wait while
     // outer k_wait + 1 (and, when the contraction so far predicts that k_wait
     // + 1 cannot meet the tolerance, outer k_wait + 2) is already enqueued,
     // so the device does not idle while the host decides.
@@ -208,10 +210,15 @@ struct pt_mg_s {
         double prev[2] = {0, 0};
         long long upd[2] = {0, 0};  // cell-updates enqueued up to outer k (slot k & 1)
         bool check_asm = false;     // the assembly of this step is checked with the first norms
+        int parity = 0;             // u_k is in (p, T) when k + parity is even
         pt_solve_info inf;
         std::chrono::steady_clock::time_point t0;
     } sv;
     bool speculate = true;
+    // from the last finished solve: the parity of its final k, and its last
+    // contraction per component (the steady rate of later cycles)
+    int hint_parity = 0;
+    double rate_hint[2] = {0.0, 0.0};
     unsigned u_cur = 0;             // bit l: level l's current iterate is in its second buffer
     bool use_fused = true;          // false: two colour passes per sweep (reference path)
     // measurement
@@ -1253,7 +1260,7 @@ namespace {
 // Where u_k lives (see pt_mg_s::Solve).
 void iterate_at(pt_mg_t h, int k, double **p, double **T)
 {
-    if (k % 2 == 0) {
+    if ((k + h->sv.parity) % 2 == 0) {
         *p = h->sv.p;
         *T = h->sv.T;
     } else {
@@ -1269,7 +1276,9 @@ int enqueue_outer(pt_mg_t h, int k)
     auto &S = h->sv;
     int nb;
     if (k == 0) {
-        nb = outer_any(h, S.b_p, S.b_T, S.p, S.T, nullptr, nullptr, false, true, nullptr, nullptr,
+        double *sp, *sT;
+        iterate_at(h, 0, &sp, &sT);
+        nb = outer_any(h, S.b_p, S.b_T, sp, sT, nullptr, nullptr, false, true, nullptr, nullptr,
                        S.bshift);
     } else {
         vcycle_any(h, S.o.nu1, S.o.nu2);
@@ -1319,8 +1328,11 @@ int solve_begin(pt_mg_t h, const double *b_p, const double *b_T, double *p, doub
     std::memset(&S.inf, 0, sizeof S.inf);
     h->updates = 0;
     if (o.zero_guess) {
+        S.parity = h->hint_parity;
+        double *u0p, *u0T;
+        iterate_at(h, 0, &u0p, &u0T);
         h->begin(PT_K_OTHER, 16.0 * P.N);
-        launch_zero2(p, T, 8 * (size_t)P.N, h->stream);
+        launch_zero2(u0p, u0T, 8 * (size_t)P.N, h->stream);
         h->end();
     }
     // mean constraint: the right-hand side is used with its mean removed
@@ -1394,6 +1406,10 @@ int solve_advance(pt_mg_t h, pt_solve_info *info)
                 bool ahead = false;
                 for (int c = 0; c < 2; c++) {
                     double rate = S.have_prev && S.prev[c] > 0 ? rel[c] / S.prev[c] : 0.1;
+                    // the first cycle from a zero guess contracts far more
+                    // than the later ones: the previous solve's last rate
+                    // predicts the next better
+                    if (k == 1 && S.o.zero_guess) rate = std::max(rate, h->rate_hint[c]);
                     rate = std::min(rate, 1.0);
                     if (rel[c] * rate > kMargin * S.o.rtol) ahead = true;
                 }
@@ -1412,7 +1428,13 @@ int solve_advance(pt_mg_t h, pt_solve_info *info)
         // u_k is the answer; later speculative outers wrote only the other
         // buffer pair, and the copy below is ordered after them.
         S.k_wait = k;
-        if (k % 2 == 1) {
+        if (S.o.zero_guess) h->hint_parity = k % 2;
+        if (inf.hist_len >= 3) {
+            const double *hh = inf.relres_hist + 2 * (inf.hist_len - 2);
+            for (int c = 0; c < 2; c++)
+                h->rate_hint[c] = hh[c] > 0 && std::isfinite(hh[c + 2]) ? hh[c + 2] / hh[c] : 0.0;
+        }
+        if ((k + S.parity) % 2 == 1) {
             double *xp, *xT;
             iterate_at(h, k, &xp, &xT);
             h->begin(PT_K_OTHER, 32.0 * P.N);

@@ -269,6 +269,38 @@ def test_tail_and_graph_paths_agree(name, prec):
         assert torch.equal(a, b), (a - b).abs().max().item()
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_solution_parity_and_rate_hints(prec):
+    """A zero-guess solve keeps its odd or even iterates in the caller's
+    arrays as the previous solve on the handle ended, and predicts its
+    second cycle from the previous solve's last contraction: on one handle,
+    solves that end after 3, 2, 2, 1, 4 and 3 cycles (and one that
+    converges) equal, bit for bit, the same solves each on a fresh handle."""
+    import workloads.device as D
+    prob = step_problems()["bubble2d_200x136"]
+    op = orc.assemble(prob)
+    b_p, b_T = orc.rhs(op, prob)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        h, gb_p, gb_T, _ = D.setup(prob, prec, stream=stream)
+        for m in (3, 2, 2, 1, 4, 3, None):
+            kw = dict(rtol=1e-12, max_cycles=40) if m is None else \
+                dict(rtol=1e-30, max_cycles=m, raise_on_noconv=False)
+            p, T = torch.full_like(gb_p, 7.0), torch.full_like(gb_T, 7.0)
+            i1 = h.solve(gb_p, gb_T, p, T, **kw)
+            h2, gb_p2, gb_T2, _ = D.setup(prob, prec, stream=stream)
+            p2, T2 = torch.full_like(gb_p, -3.0), torch.full_like(gb_T, -3.0)
+            i2 = h2.solve(gb_p2, gb_T2, p2, T2, **kw)
+            torch.cuda.synchronize()
+            h2.destroy()
+            assert i1["cycles"] == i2["cycles"] and i1["hist"] == i2["hist"]
+            assert i1["status"] == i2["status"]
+            if m is not None:
+                assert i1["cycles"] == m
+            assert torch.equal(p, p2) and torch.equal(T, T2)
+        assert max(orc.relres(op, b_p, b_T, host(p), host(T))) <= 2e-12
+
+
 @pytest.mark.parametrize("nu", [(2, 2), (3, 2), (2, 1), (4, 3), (1, 2)])
 @pytest.mark.parametrize("name", ["bubble2d_200x136", "explicit_64", "twobubble2d_96x80"])
 def test_fused_solve_matches_reference_per_sweep_count(name, nu):
