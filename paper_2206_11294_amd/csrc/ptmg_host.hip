@@ -239,7 +239,9 @@ struct pt_mg_s {
     // as one graph, captured at the first assembly on a non-null stream
     hipGraph_t hier_graph = nullptr;
     hipGraphExec_t hier_exec = nullptr;
-    bool use_graphs = true;
+    // off by default: with one kernel per coarse visit and the tail, a graph
+    // replaces few launches, and its end costs more than they do
+    bool use_graphs = false;
     // single-block tail cycle over levels tail_lt .. nlev-1 (0: not used)
     int tail_lt = 0;
     size_t tail_lds = 0;

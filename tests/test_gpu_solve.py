@@ -211,10 +211,13 @@ def test_timing_and_counters():
 
 @pytest.mark.parametrize("name", ["bubble2d_200x136", "bubble3d_40x24x56"])
 def test_graph_replay_matches_direct_launches(name):
-    """On a non-null stream the coarse-level V-cycle is replayed from a HIP
-    graph (several replays per solve, host synchronisations in between);
-    every solve must equal the one with direct launches bit for bit."""
+    """With PT_OPT_GRAPHS on a non-null stream the coarse-level V-cycle is
+    replayed from a HIP graph (several replays per solve, host
+    synchronisations in between) and the hierarchy build after an assembly
+    from another; every solve must equal the one with direct launches bit
+    for bit."""
     import workloads.device as D
+    from paper_2206_11294_amd import ptmg
     prob = step_problems()[name]
     outs = {}
     for mode in ("direct", "graph"):
@@ -223,6 +226,12 @@ def test_graph_replay_matches_direct_launches(name):
             torch.cuda.current_stream())
         with ctx:
             h, b_p, b_T, _ = D.setup(prob, 1, stream=stream)
+            assert h.get_option(ptmg.PT_OPT_GRAPHS) == 0
+            if mode == "graph":
+                h.set_option(ptmg.PT_OPT_GRAPHS, 1)
+                s2, t2 = D.to_device(prob)
+                for _ in range(2):   # hierarchy build captured, then replayed
+                    h.update(s2, keepalive=t2)
             res = []
             for _ in range(3):
                 p, T = torch.empty_like(b_p), torch.empty_like(b_T)
