@@ -1182,7 +1182,7 @@ int outer(pt_mg_t h, const double *b_p, const double *b_T, const double *src_p,
     a.partials = h->partials();
     a.update = update ? 1 : 0;
     const double Rb = sizeof(RV);
-    double nbytes = (double)P.N * (16 + 16 + 32 + 16);
+    double nbytes = (double)P.N * ((src_p ? 16 : 0) + 16 + 32 + 16);
     if (update) nbytes += (double)P.N * (2 * Rb + 16);
     if (want_r) nbytes += (double)P.N * 2 * Rb;
     if (res_p) nbytes += 8.0 * P.N;
@@ -1277,15 +1277,17 @@ int enqueue_outer(pt_mg_t h, int k)
 {
     auto &S = h->sv;
     int nb;
+    // from a zero guess u_0 = 0 is never stored: outers 0 and 1 read no
+    // source iterate
     if (k == 0) {
-        double *sp, *sT;
-        iterate_at(h, 0, &sp, &sT);
+        double *sp = nullptr, *sT = nullptr;
+        if (!S.o.zero_guess) iterate_at(h, 0, &sp, &sT);
         nb = outer_any(h, S.b_p, S.b_T, sp, sT, nullptr, nullptr, false, true, nullptr, nullptr,
                        S.bshift);
     } else {
         vcycle_any(h, S.o.nu1, S.o.nu2);
-        double *sp, *sT, *dp, *dT;
-        iterate_at(h, k - 1, &sp, &sT);
+        double *sp = nullptr, *sT = nullptr, *dp, *dT;
+        if (k > 1 || !S.o.zero_guess) iterate_at(h, k - 1, &sp, &sT);
         iterate_at(h, k, &dp, &dT);
         nb = outer_any(h, S.b_p, S.b_T, sp, sT, dp, dT, true, true, nullptr, nullptr, S.bshift);
     }
@@ -1318,7 +1320,6 @@ int solve_begin(pt_mg_t h, const double *b_p, const double *b_T, double *p, doub
         return fail(h, PT_ERR_ARG, "bad solve options");
     if (o.method != PT_SOLVE_DEFECT)
         return fail(h, PT_ERR_ARG, "only the defect-correction loop runs asynchronously");
-    const Plan &P = h->P;
     auto &S = h->sv;
     S = pt_mg_s::Solve();
     S.t0 = std::chrono::steady_clock::now();
@@ -1329,14 +1330,7 @@ int solve_begin(pt_mg_t h, const double *b_p, const double *b_T, double *p, doub
     S.T = T;
     std::memset(&S.inf, 0, sizeof S.inf);
     h->updates = 0;
-    if (o.zero_guess) {
-        S.parity = h->hint_parity;
-        double *u0p, *u0T;
-        iterate_at(h, 0, &u0p, &u0T);
-        h->begin(PT_K_OTHER, 16.0 * P.N);
-        launch_zero2(u0p, u0T, 8 * (size_t)P.N, h->stream);
-        h->end();
-    }
+    if (o.zero_guess) S.parity = h->hint_parity;
     // mean constraint: the right-hand side is used with its mean removed
     S.bshift = h->prob.mean_constraint ? grid_sums(h, b_p, b_T, 0) : nullptr;
     int rc = enqueue_outer(h, 0);
@@ -1436,7 +1430,12 @@ int solve_advance(pt_mg_t h, pt_solve_info *info)
             for (int c = 0; c < 2; c++)
                 h->rate_hint[c] = hh[c] > 0 && std::isfinite(hh[c + 2]) ? hh[c + 2] / hh[c] : 0.0;
         }
-        if ((k + S.parity) % 2 == 1) {
+        if (k == 0 && S.o.zero_guess) {
+            // the answer is the zero guess itself, never stored
+            h->begin(PT_K_OTHER, 16.0 * P.N);
+            launch_zero2(S.p, S.T, 8 * (size_t)P.N, h->stream);
+            h->end();
+        } else if ((k + S.parity) % 2 == 1) {
             double *xp, *xT;
             iterate_at(h, k, &xp, &xT);
             h->begin(PT_K_OTHER, 32.0 * P.N);

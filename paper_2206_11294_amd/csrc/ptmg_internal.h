@@ -47,7 +47,7 @@ template <typename RV> struct OuterArgs {
     const double *b_p, *b_T;       // mode-native right-hand side (null: zero)
     const double *bshift;          // [2] sums of b (mean constraint) or null
     double bshift_scale;           // b -= bshift_scale * bshift (1/N: the mean)
-    const double *src_p, *src_T;   // current iterate
+    const double *src_p, *src_T;   // current iterate (null: zero)
     double *dst_p, *dst_T;         // updated iterate (update = 1)
     const typename VT<RV>::v2 *du; // correction of the last V-cycle (update = 1)
     typename VT<RV>::v2 *r;        // canonical residual out (V-cycle RHS) or null

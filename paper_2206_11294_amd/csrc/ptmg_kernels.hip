@@ -2167,7 +2167,8 @@ __global__ __launch_bounds__(TX *TY) void k_outer_zm(OuterArgs<RV> a, int NX, in
                 const int gx = x0 + c % PX - 1, gy = y0 + c / PX - oy;
                 if (c < PS && z >= 0 && z < NZ && gx >= 0 && gx < NX && gy >= 0 && gy < NY) {
                     const long long g = gx + (long long)NX * gy + nxy * z;
-                    double2 v = make_double2(a.src_p[g], a.src_T[g]);
+                    double2 v = a.src_p ? make_double2(a.src_p[g], a.src_T[g])
+                                        : make_double2(0.0, 0.0);
                     if (a.update) {
                         const V2 d = a.du[g];
                         v.x += (double)d.x;

@@ -93,3 +93,26 @@ def test_uniform_state_is_exact(prec):
     info = h.solve(b_p, b_T, p, T, rtol=1e-12, max_cycles=60, zero_guess=False)
     assert info["status"] == 0 and info["cycles"] == 0, info
     assert np.all(host(p) == W.P0) and np.all(host(T) == W.T0)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_zero_rhs_stops_at_cycle_zero_with_zeros(prec):
+    """b = 0 from a zero guess: the solve stops at cycle 0 and writes zeros
+    into (p, T) whatever they held, on a fresh handle and after a solve
+    that ended on an odd cycle (whose parity the next solve takes for its
+    iterates); the zero guess itself is never stored, so this final write
+    is the only one."""
+    import workloads.device as D
+    prob = W.bubble_problem("z", 2, (64, 48), [(0.5, 0.5)], [0.2], W.P0, 5 * W.P0,
+                            div_amp=1e-6, div_seed=3)
+    h, b_p, b_T, _ = D.setup(prob, prec)
+    z = torch.zeros_like(b_p)
+    for before in (None, 3):
+        if before is not None:
+            p, T = torch.empty_like(b_p), torch.empty_like(b_T)
+            info = h.solve(b_p, b_T, p, T, rtol=1e-30, max_cycles=before, raise_on_noconv=False)
+            assert info["cycles"] == before
+        p, T = torch.full_like(b_p, 5.0), torch.full_like(b_T, -5.0)
+        info = h.solve(z, z, p, T, rtol=1e-12)
+        assert info["status"] == 0 and info["cycles"] == 0, info
+        assert torch.all(p == 0) and torch.all(T == 0)
