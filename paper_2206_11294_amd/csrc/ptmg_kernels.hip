@@ -50,6 +50,18 @@ __device__ __forceinline__ V2 harm2(V2 a, V2 b)
     return o;
 }
 
+// Block-to-work mapping that is XCD-aware: the hardware deals
+// consecutive block ids to the 8 XCDs in turn, so XCD x runs blocks
+// b = x, x + 8, ...; block b takes logical index (blocks of XCDs before x)
+// + b / 8, which gives each XCD (and its L2) a contiguous run of work
+// whose halos overlap.  With q = nb / 8 and r = nb % 8, XCD x has
+// q + (x < r) blocks, so the map is a bijection of [0, nb).
+__device__ __forceinline__ int xcd_tile(int b, int nb)
+{
+    const int x = b & 7, q = nb >> 3, r = nb & 7;
+    return x * q + min(x, r) + (b >> 3);
+}
+
 __device__ __forceinline__ void decode(long long t, int nx, int ny, int &i, int &j, int &k)
 {
     i = (int)(t % nx);
@@ -618,7 +630,8 @@ template void launch_rb_pass<double>(int, int, const Lvl<double> &, int, int, hi
 template <typename R, int DIM, bool CF>
 __global__ __launch_bounds__(kBlock) void k_restrict(Lvl<R> F, Lvl<R> C)
 {
-    long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
+    // neighbouring coarse cells share the fine halo: runs of them per XCD
+    long long t = (long long)xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     if (t >= C.N) return;
     int I, J, K;
     decode(t, C.nx, C.ny, I, J, K);
@@ -718,7 +731,9 @@ __global__ __launch_bounds__(kBlock) void k_coarsen(Lvl<RIN> F, int cnx, int cny
     using V4 = typename VT<RIN>::v4;
     using O2 = typename VT<ROUT>::v2;
     using O4 = typename VT<ROUT>::v4;
-    long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
+    // the lower faces read the neighbours' children: runs of coarse cells
+    // per XCD, so that those reads hit its L2
+    long long t = (long long)xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     const long long CN = (long long)cnx * cny * cnz;
     if (t >= CN) return;
     int I, J, K;
@@ -1162,20 +1177,8 @@ namespace ptmg {
 //   one cell (reads old black on planes k..k+2), updates black on plane k
 //   over the tile (reads new red on planes k-1..k+1), writes plane k.
 // Cells outside the grid get zero coefficients, so the harmonic-mean face
-// weight to them is zero (no flux through the boundary).
-//
-// Block-to-tile mapping is XCD-aware: the hardware deals consecutive block
-// ids to the 8 XCDs in turn, so XCD x runs blocks b = x, x + 8, ...; block
-// b takes logical tile (tiles of XCDs before x) + b / 8, which gives each
-// XCD (and its L2) a contiguous run of tiles whose halos overlap.  With
-// q = nb / 8 and r = nb % 8, XCD x has q + (x < r) blocks, so the map is a
-// bijection of [0, nb).
-
-__device__ __forceinline__ int xcd_tile(int b, int nb)
-{
-    const int x = b & 7, q = nb >> 3, r = nb & 7;
-    return x * q + min(x, r) + (b >> 3);
-}
+// weight to them is zero (no flux through the boundary).  Tiles are
+// assigned XCD-aware (xcd_tile).
 
 template <typename R>
 __device__ __forceinline__ void block_solve(typename VT<R>::v2 f, typename VT<R>::v4 b, R gp_nb,
