@@ -404,14 +404,6 @@ double bytes_sweep_half(const Plan &P, int l, bool zero_guess)
     return N * (0.5 * (zero_guess ? 0 : 2 * R) + 0.5 * 2 * R + 0.5 * 4 * R + coef + 0.5 * 2 * R);
 }
 
-// Algorithmic bytes of one fused sweep: u, f, cell coefficients and block
-// read once (u not at all from a zero guess), u written once.
-double bytes_sweep_fused(const Plan &P, bool zero_guess)
-{
-    const double R = P.prec == PT_PREC_MIXED ? 4 : 8;
-    return (double)P.lv[0].N * R * (zero_guess ? 10 : 12);
-}
-
 // One pass over memory per sweep pays off where a level has enough
 // work for the whole chip: every 2-D level (independent tiles), 3-D
 // levels of at least 2^20 cells (the plane-marching kernel).

@@ -280,7 +280,7 @@ int pt_server_submit(pt_server_t s, const pt_problem *prob, int precision, const
     r.div = div_ustar;
     r.p = p;
     r.T = T;
-    r.opts = opts ? *opts : pt_solve_opts{1e-9, 50, 2, 2, 1};
+    r.opts = opts ? *opts : pt_solve_opts{1e-9, 50, 2, 2, 1, PT_SOLVE_DEFECT};
     const long long N = (long long)prob->n[0] * prob->n[1] * prob->n[2];
     r.handle_bytes = (hb + kAlign - 1) & ~(kAlign - 1);
     r.bytes = r.handle_bytes + (b_p ? 0 : (size_t)16 * N);
@@ -299,12 +299,11 @@ int pt_server_progress(pt_server_t s, double until, int *n_done)
     if (!s) return sfail(nullptr, PT_ERR_ARG, "server is NULL");
     const long long f0 = s->finished;
     for (;;) {
-        bool moved = false;
-        while (admit_one(s)) moved = true;
+        while (admit_one(s)) {
+        }
         for (auto &sl : s->slots) {
             if (sl.req < 0) continue;
-            Request &r = s->reqs[sl.req];
-            if (poll_one(s, r)) moved = true;
+            (void)poll_one(s, s->reqs[sl.req]);
         }
         const double t = now_s();
         if (t >= until) break;
