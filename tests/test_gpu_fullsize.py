@@ -1,6 +1,6 @@
 """Parity at the benchmarked sizes, in the launch configuration bench.py
-times (a non-null stream: graph replay of the coarse levels, fused
-finest-grid kernels, single-block tail).
+times: a non-null stream, the fused finest-grid kernels, the single-block
+tail, and bench.py's smoothing for the workload (its SWEEPS table).
 
   * 1024^2 bubble, FP64: the oracle's own multigrid solution is cheap
     enough to compare element by element.
@@ -10,12 +10,18 @@ finest-grid kernels, single-block tail).
     and a manufactured solution u* (b = L(u*) formed by the oracle) is
     recovered (P8).
 """
+import os
+import sys
+
 import numpy as np
 import pytest
 
 import oracle as orc
 import workloads as W
 from gpu_util import dev, host, rel_err
+
+sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+import bench  # noqa: E402  (the per-workload smoothing table)
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -27,20 +33,21 @@ def _gpu():
         pytest.skip("no GPU")
 
 
-def _solve(prob, prec, rtol, b=None):
+def _solve(prob, prec, rtol, workload, b=None):
     import workloads.device as D
     from paper_2206_11294_amd import ptmg
+    nu1, nu2, coarse = bench.SWEEPS[workload]
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
-        s, t = D.to_device(prob)
-        h = ptmg.PtMg(s, prec, stream=stream)
-        if b is None:
-            b_p, b_T = h.paper_rhs(t.get("p_adv"), t.get("T_adv"), t.get("div"))
-        else:
+        # the handle and the paper right-hand side as bench.py builds them
+        # (div u* from the face velocities where the workload has them)
+        h, b_p, b_T, t = D.setup(prob, prec, stream=stream)
+        h.set_option(ptmg.PT_OPT_COARSE_SWEEPS, coarse)
+        if b is not None:
             b_p, b_T = dev(b[0]), dev(b[1])
         p = torch.empty(prob.ncells, dtype=torch.float64, device="cuda")
         T = torch.empty_like(p)
-        info = h.solve(b_p, b_T, p, T, rtol=rtol, max_cycles=40)
+        info = h.solve(b_p, b_T, p, T, rtol=rtol, max_cycles=40, nu1=nu1, nu2=nu2)
         torch.cuda.synchronize()
         out = (host(p), host(T), host(b_p), host(b_T), info)
         h.destroy()
@@ -62,7 +69,7 @@ def _manufactured(prob, op):
 
 def test_bubble2d_1024_fp64_matches_oracle():
     prob = W.bubble2d(1024)
-    P, T, bp, bT, info = _solve(prob, 0, 1e-12)
+    P, T, bp, bT, info = _solve(prob, 0, 1e-12, "bubble2d_1024")
     assert info["status"] == 0 and info["cycles"] <= 6, info
     op = orc.assemble(prob)
     ob_p, ob_T = orc.paper_rhs(op, prob)
@@ -83,7 +90,7 @@ def test_wall3d_256_certified_by_oracle_residual():
     ob_p, ob_T = orc.paper_rhs(op, prob)
     sols = {}
     for prec in (0, 1):
-        P, T, bp, bT, info = _solve(prob, prec, 1e-12)
+        P, T, bp, bT, info = _solve(prob, prec, 1e-12, "wall3d_256")
         assert info["status"] == 0 and info["cycles"] <= 8, info
         rel = orc.relres(op, ob_p, ob_T, P, T)
         assert rel.max() <= 2e-12, (prec, rel)
@@ -96,7 +103,7 @@ def test_wall3d_256_manufactured_solution():
     prob = W.wall3d(256)
     op = orc.assemble(prob)
     p_star, T_star, b_p, b_T = _manufactured(prob, op)
-    P, T, _, _, info = _solve(prob, 1, 1e-13, b=(b_p, b_T))
+    P, T, _, _, info = _solve(prob, 1, 1e-13, "wall3d_256", b=(b_p, b_T))
     assert info["status"] == 0, info
     assert rel_err(P, p_star) <= 1e-8 and rel_err(T, T_star) <= 1e-8
     assert rel_err(T - prob.T_adv_const, T_star - prob.T_adv_const) <= 1e-6
@@ -104,7 +111,7 @@ def test_wall3d_256_manufactured_solution():
 
 def test_collapse3d_512_mixed_certified_and_manufactured():
     prob = W.collapse3d(512)
-    P, T, bp, bT, info = _solve(prob, 1, 1e-12)
+    P, T, bp, bT, info = _solve(prob, 1, 1e-12, "collapse3d_512")
     assert info["status"] == 0 and info["cycles"] <= 8, info
     op = orc.assemble(prob)
     ob_p, ob_T = orc.paper_rhs(op, prob)
@@ -112,6 +119,39 @@ def test_collapse3d_512_mixed_certified_and_manufactured():
     assert rel.max() <= 2e-12, rel
     del P, T
     p_star, T_star, b_p, b_T = _manufactured(prob, op)
-    P, T, _, _, info = _solve(prob, 1, 1e-13, b=(b_p, b_T))
+    P, T, _, _, info = _solve(prob, 1, 1e-13, "collapse3d_512", b=(b_p, b_T))
     assert info["status"] == 0, info
     assert rel_err(P, p_star) <= 1e-8 and rel_err(T, T_star) <= 1e-8
+
+
+def test_axi2d_1024_fp64_matches_oracle():
+    """The r-z bubble near the wall at the benchmarked size and smoothing:
+    the oracle's r-z residual certifies the GPU solution, which matches the
+    oracle's own multigrid solution."""
+    prob = W.axi2d(1024)
+    P, T, bp, bT, info = _solve(prob, 0, 1e-12, "axi2d_1024")
+    assert info["status"] == 0 and info["cycles"] <= 6, info
+    op = orc.assemble(prob)
+    assert op.axi == 1
+    ob_p, ob_T = orc.paper_rhs(op, prob)
+    assert rel_err(bp, ob_p) <= 1e-13 and rel_err(bT, ob_T) <= 1e-14
+    rel = orc.relres(op, ob_p, ob_T, P, T)
+    assert rel.max() <= 2e-12, rel
+    p_ref, T_ref, cyc, _ = orc.mg_solve(op, ob_p, ob_T, rtol=1e-14)
+    assert cyc > 0
+    assert rel_err(P, p_ref) <= 1e-8 and rel_err(T, T_ref) <= 1e-8
+
+
+def test_state2d_1024_certified_by_oracle_residual():
+    """The state-mode step at the benchmarked size and smoothing: the GPU's
+    own provisional state, div u* of the face velocities and operator; the
+    oracle's residual of the GPU solution, with the oracle's right-hand
+    side."""
+    prob = W.state2d(1024)
+    P, T, bp, bT, info = _solve(prob, 0, 1e-12, "state2d_1024")
+    assert info["status"] == 0 and info["cycles"] <= 6, info
+    op = orc.assemble(prob)
+    ob_p, ob_T = orc.paper_rhs(op, prob)
+    assert rel_err(bp, ob_p) <= 1e-10
+    rel = orc.relres(op, ob_p, ob_T, P, T)
+    assert rel.max() <= 1e-11, rel
