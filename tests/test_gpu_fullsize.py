@@ -33,10 +33,11 @@ def _gpu():
         pytest.skip("no GPU")
 
 
-def _solve(prob, prec, rtol, workload, b=None):
+def _solve(prob, prec, rtol, workload, b=None, stiff=False):
     import workloads.device as D
     from paper_2206_11294_amd import ptmg
-    nu1, nu2, coarse = bench.SWEEPS[workload]
+    # bench.py: the workload's smoothing; diffusive steps the library's V(2,2)
+    nu1, nu2, coarse = (2, 2, 0) if stiff else bench.SWEEPS[workload]
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         # the handle and the paper right-hand side as bench.py builds them
@@ -155,3 +156,28 @@ def test_state2d_1024_certified_by_oracle_residual():
     assert rel_err(bp, ob_p) <= 1e-10
     rel = orc.relres(op, ob_p, ob_T, P, T)
     assert rel.max() <= 1e-11, rel
+
+
+def test_state3d_256_mixed_certified_by_oracle_residual():
+    """The 3-D state-mode step in mixed precision at the benchmarked size
+    and smoothing, certified by the oracle's residual."""
+    prob = W.state3d(256)
+    P, T, bp, bT, info = _solve(prob, 1, 1e-12, "state3d_256")
+    assert info["status"] == 0 and info["cycles"] <= 8, info
+    op = orc.assemble(prob)
+    ob_p, ob_T = orc.paper_rhs(op, prob)
+    assert rel_err(bp, ob_p) <= 1e-10
+    rel = orc.relres(op, ob_p, ob_T, P, T)
+    assert rel.max() <= 1e-11, rel
+
+
+def test_stiff_bubble2d_1024_certified_by_oracle_residual():
+    """The diffusive-CFL step at 1024^2 (bench.py --stiff, defect loop with
+    the library's V(2,2)), certified by the oracle's residual."""
+    prob = W.bubble2d(1024, stiff=True)
+    P, T, bp, bT, info = _solve(prob, 0, 1e-12, "bubble2d_1024", stiff=True)
+    assert info["status"] == 0 and 8 <= info["cycles"] <= 40, info
+    op = orc.assemble(prob)
+    ob_p, ob_T = orc.paper_rhs(op, prob)
+    rel = orc.relres(op, ob_p, ob_T, P, T)
+    assert rel.max() <= 2e-12, rel
