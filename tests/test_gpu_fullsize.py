@@ -181,3 +181,28 @@ def test_stiff_bubble2d_1024_certified_by_oracle_residual():
     ob_p, ob_T = orc.paper_rhs(op, prob)
     rel = orc.relres(op, ob_p, ob_T, P, T)
     assert rel.max() <= 2e-12, rel
+
+
+def test_explicit_64_matches_oracle():
+    """The 64^2 constant-coefficient case (mean constraint, rtol 1e-10) at
+    bench.py's smoothing, against the oracle's sparse direct solution."""
+    prob = W.explicit_const(64, 64)
+    P, T, bp, bT, info = _solve(prob, 0, 1e-10, "explicit_64")
+    assert info["status"] == 0 and info["cycles"] <= 12, info
+    op, ob_p, ob_T, p_ref, T_ref = orc.solve(prob)
+    assert rel_err(bp, ob_p) == 0.0 and rel_err(bT, ob_T) == 0.0
+    rel = orc.relres(op, ob_p, ob_T, P, T)
+    assert rel.max() <= 2e-10, rel
+    assert rel_err(P, p_ref) <= 1e-8 and rel_err(T, T_ref) <= 1e-8
+
+
+def test_stiff_wall3d_256_certified_by_oracle_residual():
+    """The diffusive-CFL 256^3 step in mixed precision (bench.py --stiff,
+    V(2,2)), certified by the oracle's residual."""
+    prob = W.wall3d(256, stiff=True)
+    P, T, bp, bT, info = _solve(prob, 1, 1e-12, "wall3d_256", stiff=True)
+    assert info["status"] == 0, info
+    op = orc.assemble(prob)
+    ob_p, ob_T = orc.paper_rhs(op, prob)
+    rel = orc.relres(op, ob_p, ob_T, P, T)
+    assert rel.max() <= 2e-12, rel
