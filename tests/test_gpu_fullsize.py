@@ -33,7 +33,7 @@ def _gpu():
         pytest.skip("no GPU")
 
 
-def _solve(prob, prec, rtol, workload, b=None, stiff=False):
+def _solve(prob, prec, rtol, workload, b=None, stiff=False, method=None):
     import workloads.device as D
     from paper_2206_11294_amd import ptmg
     # bench.py: the workload's smoothing; diffusive steps the library's V(2,2)
@@ -48,7 +48,8 @@ def _solve(prob, prec, rtol, workload, b=None, stiff=False):
             b_p, b_T = dev(b[0]), dev(b[1])
         p = torch.empty(prob.ncells, dtype=torch.float64, device="cuda")
         T = torch.empty_like(p)
-        info = h.solve(b_p, b_T, p, T, rtol=rtol, max_cycles=40, nu1=nu1, nu2=nu2)
+        kw = {} if method is None else {"method": getattr(ptmg, method)}
+        info = h.solve(b_p, b_T, p, T, rtol=rtol, max_cycles=40, nu1=nu1, nu2=nu2, **kw)
         torch.cuda.synchronize()
         out = (host(p), host(T), host(b_p), host(b_T), info)
         h.destroy()
@@ -206,3 +207,19 @@ def test_stiff_wall3d_256_certified_by_oracle_residual():
     ob_p, ob_T = orc.paper_rhs(op, prob)
     rel = orc.relres(op, ob_p, ob_T, P, T)
     assert rel.max() <= 2e-12, rel
+
+
+def test_stiff_bubble2d_1024_bicgstab_certified_by_oracle_residual():
+    """bench.py --stiff --method bicgstab at 1024^2: BiCGStab with the
+    V-cycle as preconditioner, certified by the oracle's residual, in fewer
+    V-cycles than the defect loop."""
+    prob = W.bubble2d(1024, stiff=True)
+    P, T, bp, bT, info = _solve(prob, 0, 1e-12, "bubble2d_1024", stiff=True,
+                                method="PT_SOLVE_BICGSTAB")
+    assert info["status"] == 0, info
+    op = orc.assemble(prob)
+    ob_p, ob_T = orc.paper_rhs(op, prob)
+    rel = orc.relres(op, ob_p, ob_T, P, T)
+    assert rel.max() <= 2e-12, rel
+    _, _, _, _, idef = _solve(prob, 0, 1e-12, "bubble2d_1024", stiff=True)
+    assert info["cycles"] < idef["cycles"], (info["cycles"], idef["cycles"])
