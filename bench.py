@@ -300,7 +300,9 @@ def serve_bench(args):
 
 def stream_probe():
     """Attainable HBM bandwidth: plain copies of 2 GiB timed with HIP
-    events (the library's copy kernel and torch's copy_)."""
+    events (the library's copy kernel and torch's copy_), and the library's
+    copy kernel on sizes that fit the 256 MB Infinity Cache (median of 20
+    back-to-back launches, each timed on its own)."""
     import torch
     from paper_2206_11294_amd import ptmg
     nbytes = 2 << 30
@@ -320,7 +322,23 @@ def stream_probe():
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / 10
         res[name] = {"GB_per_s": round(2 * nbytes / (ms * 1e-3) / 1e9, 1), "ms": round(ms, 4)}
-    print(json.dumps({"stream_probe_bytes_moved": 2 * nbytes, **res}), flush=True)
+    sizes = []
+    for mb in (32, 64, 128, 256, 512):
+        nb = mb << 20
+        for _ in range(5):
+            ptmg.copy_kernel(dst, src, nb)
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(21)]
+        for i in range(20):
+            ev[i].record()
+            ptmg.copy_kernel(dst, src, nb)
+        ev[20].record()
+        torch.cuda.synchronize()
+        med = sorted(ev[i].elapsed_time(ev[i + 1]) for i in range(20))[10]
+        sizes.append({"MB_copied": mb, "median_us": round(med * 1e3, 2),
+                      "GB_per_s": round(2 * nb / (med * 1e-3) / 1e9, 1)})
+    print(json.dumps({"stream_probe_bytes_moved": 2 * nbytes, **res,
+                      "pt_copy_kernel_by_size": sizes}), flush=True)
 
 
 def copy_calibration(nbytes):
