@@ -673,15 +673,47 @@ void vcycle_any(pt_mg_t h, int nu1, int nu2)
 }
 
 // ---- assembly + hierarchy + coarsest inverse --------------------------
+// Levels of at most this many cells are built, with the coarsest inverse,
+// by one single-block kernel (launch_hier_small) on the fused path.
+constexpr long long kHierSmallCells = 1024;
+
 template <typename R> void build_hierarchy(pt_mg_t h)
 {
     const Plan &P = h->P;
+    double *M0 = h->at<double>(P.o_gj0), *M1 = h->at<double>(P.o_gj1);
+    const int pin = h->prob.mean_constraint ? 1 : 0;
+    // b0: the first level the single-block kernel builds (its parent, a
+    // face level, is the finest it reads)
+    int b0 = P.nlev - 1;
+    while (b0 - 1 >= 2 && P.lv[b0 - 1].N <= kHierSmallCells && P.nlev - b0 + 2 <= kMaxTail) b0--;
+    const bool small = h->use_fused && P.nlev >= 3 && b0 >= 2 && P.m <= 128;
     if (P.nlev > 1) {
         Lvl<R> c1 = h->level<R>(1);
         launch_coarsen<double, R>(P.dim, 1, h->level0_fp64(), (typename VT<R>::v2 *)c1.fx,
                                   (typename VT<R>::v2 *)c1.fy, (typename VT<R>::v2 *)c1.fz,
                                   (typename VT<R>::v4 *)c1.B, h->stream);
-        for (int l = 1; l + 1 < P.nlev; l++) {
+        for (int l = 1; l + 1 < (small ? b0 : P.nlev); l++) {
+            Lvl<R> f = h->level<R>(l), c = h->level<R>(l + 1);
+            launch_coarsen<R, R>(P.dim, 0, f, (typename VT<R>::v2 *)c.fx,
+                                 (typename VT<R>::v2 *)c.fy, (typename VT<R>::v2 *)c.fz,
+                                 (typename VT<R>::v4 *)c.B, h->stream);
+        }
+    }
+    if (small) {
+        HierSmallArgs<R> a;
+        std::memset(&a, 0, sizeof a);
+        a.nl = P.nlev - b0 + 1;
+        a.pin = pin;
+        a.m = P.m;
+        for (int q = 0; q < a.nl; q++) a.g[q] = h->level<R>(b0 - 1 + q);
+        a.M0 = M0;
+        a.Ainv = M1;
+        a.flags = h->flags();
+        if (launch_hier_small<R>(P.dim, a, h->stream)) {
+            h->Ainv = M1;
+            return;
+        }
+        for (int l = b0 - 1; l + 1 < P.nlev; l++) {
             Lvl<R> f = h->level<R>(l), c = h->level<R>(l + 1);
             launch_coarsen<R, R>(P.dim, 0, f, (typename VT<R>::v2 *)c.fx,
                                  (typename VT<R>::v2 *)c.fy, (typename VT<R>::v2 *)c.fz,
@@ -689,8 +721,6 @@ template <typename R> void build_hierarchy(pt_mg_t h)
         }
     }
     // dense coarsest matrix, inverted by Gauss-Jordan
-    double *M0 = h->at<double>(P.o_gj0), *M1 = h->at<double>(P.o_gj1);
-    const int pin = h->prob.mean_constraint ? 1 : 0;
     if (P.nlev == 1)
         launch_coarse_dense<double>(P.dim, 1, h->level0_fp64(), pin, M0, h->stream);
     else

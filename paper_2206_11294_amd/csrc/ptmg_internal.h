@@ -89,6 +89,19 @@ constexpr int kMaxTail = 8;
 
 // Arguments of the single-block tail cycle: global views of its levels and
 // the LDS byte offsets of each level's u, f, fx, fy, fz, B.
+// The small end of the hierarchy build (launch_hier_small): coarsen
+// g[0] -> ... -> g[nl-1], then the dense matrix of g[nl-1] (pin: mean
+// constraint) into M0 and its Gauss-Jordan inverse (m x m) into Ainv.
+template <typename R> struct HierSmallArgs {
+    int nl, pin, m;
+    Lvl<R> g[kMaxTail];
+    double *M0, *Ainv;
+    int *flags;
+};
+// false (nothing launched) when m exceeds the LDS inverse or nl is not 2..kMaxTail
+template <typename R>
+bool launch_hier_small(int dim, const HierSmallArgs<R> &a, hipStream_t s);
+
 template <typename R> struct TailArgs {
     int nl, m, nu1, nu2;
     Lvl<R> g[kMaxTail];

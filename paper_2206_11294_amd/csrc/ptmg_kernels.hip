@@ -720,22 +720,18 @@ template void launch_prolong<double>(int, const Lvl<double> &, const Lvl<double>
 // ------------------------------------------------------ coarse operator
 // Coarse face coefficient = mean of the 2^(DIM-1) fine faces that make up
 // the coarse face; coarse block = mean of the 2^DIM children's blocks.
+// Coarse cell t of a cnx x cny x cnz level from the fine level F.
 template <typename RIN, typename ROUT, int DIM, bool CF>
-__global__ __launch_bounds__(kBlock) void k_coarsen(Lvl<RIN> F, int cnx, int cny, int cnz,
-                                                    typename VT<ROUT>::v2 *fx,
-                                                    typename VT<ROUT>::v2 *fy,
-                                                    typename VT<ROUT>::v2 *fz,
-                                                    typename VT<ROUT>::v4 *Bo)
+__device__ __forceinline__ void coarsen_cell(const Lvl<RIN> &F, int cnx, int cny, int cnz,
+                                             typename VT<ROUT>::v2 *fx,
+                                             typename VT<ROUT>::v2 *fy,
+                                             typename VT<ROUT>::v2 *fz,
+                                             typename VT<ROUT>::v4 *Bo, long long t)
 {
     using V2 = typename VT<RIN>::v2;
     using V4 = typename VT<RIN>::v4;
     using O2 = typename VT<ROUT>::v2;
     using O4 = typename VT<ROUT>::v4;
-    // the lower faces read the neighbours' children: runs of coarse cells
-    // per XCD, so that those reads hit its L2
-    long long t = (long long)xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-    const long long CN = (long long)cnx * cny * cnz;
-    if (t >= CN) return;
     int I, J, K;
     decode(t, cnx, cny, I, J, K);
     const int base[3] = {2 * I, 2 * J, DIM == 3 ? 2 * K : 0};
@@ -804,6 +800,21 @@ __global__ __launch_bounds__(kBlock) void k_coarsen(Lvl<RIN> F, int cnx, int cny
     }
 }
 
+template <typename RIN, typename ROUT, int DIM, bool CF>
+__global__ __launch_bounds__(kBlock) void k_coarsen(Lvl<RIN> F, int cnx, int cny, int cnz,
+                                                    typename VT<ROUT>::v2 *fx,
+                                                    typename VT<ROUT>::v2 *fy,
+                                                    typename VT<ROUT>::v2 *fz,
+                                                    typename VT<ROUT>::v4 *Bo)
+{
+    // the lower faces read the neighbours' children: runs of coarse cells
+    // per XCD, so that those reads hit its L2
+    long long t = (long long)xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    const long long CN = (long long)cnx * cny * cnz;
+    if (t >= CN) return;
+    coarsen_cell<RIN, ROUT, DIM, CF>(F, cnx, cny, cnz, fx, fy, fz, Bo, t);
+}
+
 template <typename RIN, typename ROUT>
 void launch_coarsen(int dim, int level0, const Lvl<RIN> &F, typename VT<ROUT>::v2 *fx,
                     typename VT<ROUT>::v2 *fy, typename VT<ROUT>::v2 *fz,
@@ -868,13 +879,12 @@ __device__ double dense_row_diag(const Lvl<R> &L, long long cell, int c, double 
     return S + (double)(c == 0 ? b.x : b.w);
 }
 
+// Row r of the dense matrix.
 template <typename R, int DIM, bool CF>
-__global__ __launch_bounds__(kBlock) void k_coarse_dense(Lvl<R> L, int pin_mean, double *M)
+__device__ __forceinline__ void dense_row(const Lvl<R> &L, int pin_mean, double *M, long long r)
 {
     using V4 = typename VT<R>::v4;
-    long long r = (long long)blockIdx.x * kBlock + threadIdx.x;
     const long long m = 2 * L.N;
-    if (r >= m) return;
     const long long cell = r >> 1;
     const int c = (int)(r & 1);
     double *row = M + r * m;
@@ -889,6 +899,14 @@ __global__ __launch_bounds__(kBlock) void k_coarse_dense(Lvl<R> L, int pin_mean,
         const double sh = d0 / (double)L.N;
         for (long long q = 0; q < L.N; q++) row[2 * q + c] += sh;
     }
+}
+
+template <typename R, int DIM, bool CF>
+__global__ __launch_bounds__(kBlock) void k_coarse_dense(Lvl<R> L, int pin_mean, double *M)
+{
+    long long r = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (r >= 2 * L.N) return;
+    dense_row<R, DIM, CF>(L, pin_mean, M, r);
 }
 
 template <typename R>
@@ -2078,38 +2096,92 @@ namespace ptmg {
 // one block, the matrix resident in LDS: the same elimination as k_gj_step,
 // with the pivot row and column copied aside before each update.
 constexpr int kGJLdsMax = 128;
-__global__ __launch_bounds__(1024) void k_gj_lds(const double *A, double *Ainv, int m, int *flags)
+// The elimination by the first nt threads of the block (nt a multiple of m;
+// every thread of the block reaches the barriers).
+__device__ __forceinline__ void gj_lds_body(const double *A, double *Ainv, int m, int *flags,
+                                            double *M, double *rowk, double *colk, int nt)
 {
-    __shared__ double M[kGJLdsMax * kGJLdsMax];
-    __shared__ double rowk[kGJLdsMax], colk[kGJLdsMax];
-    const int nt = blockDim.x;
     const int mm = m * m;
-    for (int e = threadIdx.x; e < mm; e += nt) M[e] = A[e];
+    const bool act = (int)threadIdx.x < nt;
+    for (int e = threadIdx.x; e < mm; e += blockDim.x) M[e] = A[e];
     __syncthreads();
     for (int k = 0; k < m; k++) {
         const double p = M[k * m + k];
         const double q = 1.0 / p;
         // scaled pivot row and the pivot column, as in k_gj_step
-        for (int e = threadIdx.x; e < m; e += nt) {
+        for (int e = threadIdx.x; e < m; e += blockDim.x) {
             rowk[e] = M[k * m + e] * q;
             colk[e] = M[e * m + k];
         }
         if (threadIdx.x == 0 && (!(p > 0.0) || !isfinite(p))) atomicOr(&flags[FLAG_PIVOT], 1);
         __syncthreads();
-        for (int i = threadIdx.x / m; i < m; i += nt / m) {
-            const int j = threadIdx.x % m;
-            const int e = i * m + j;
-            double v;
-            if (i == k && j == k) v = q;
-            else if (i == k) v = rowk[j];
-            else if (j == k) v = -colk[i] * q;
-            else v = M[e] - colk[i] * rowk[j];
-            M[e] = v;
+        if (act) {
+            for (int i = threadIdx.x / m; i < m; i += nt / m) {
+                const int j = threadIdx.x % m;
+                const int e = i * m + j;
+                double v;
+                if (i == k && j == k) v = q;
+                else if (i == k) v = rowk[j];
+                else if (j == k) v = -colk[i] * q;
+                else v = M[e] - colk[i] * rowk[j];
+                M[e] = v;
+            }
         }
         __syncthreads();
     }
-    for (int e = threadIdx.x; e < mm; e += nt) Ainv[e] = M[e];
+    for (int e = threadIdx.x; e < mm; e += blockDim.x) Ainv[e] = M[e];
 }
+
+__global__ __launch_bounds__(1024) void k_gj_lds(const double *A, double *Ainv, int m, int *flags)
+{
+    __shared__ double M[kGJLdsMax * kGJLdsMax];
+    __shared__ double rowk[kGJLdsMax], colk[kGJLdsMax];
+    gj_lds_body(A, Ainv, m, flags, M, rowk, colk, (int)blockDim.x);
+}
+
+// The small end of the hierarchy build in one block: the coarsening of
+// levels g[0] -> g[1] -> ... -> g[nl-1] (at most a few thousand cells
+// each), the dense matrix of the coarsest and its Gauss-Jordan inverse,
+// with the arithmetic of k_coarsen, k_coarse_dense and k_gj_lds; as
+// separate kernels each of these steps is a launch.  The level views are
+// staged in LDS and read with a dynamic index, so every step has one copy
+// of its code.
+template <typename R, int DIM>
+__global__ __launch_bounds__(1024) void k_hier_small(HierSmallArgs<R> A)
+{
+    using O2 = typename VT<R>::v2;
+    using O4 = typename VT<R>::v4;
+    __shared__ Lvl<R> sl[kMaxTail];
+    __shared__ double M[kGJLdsMax * kGJLdsMax];
+    __shared__ double rowk[kGJLdsMax], colk[kGJLdsMax];
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int q = 0; q < kMaxTail; q++)
+        if (t == q && q < A.nl) sl[q] = A.g[q];
+    __syncthreads();
+    for (int q = 0; q + 1 < A.nl; q++) {
+        const Lvl<R> F = sl[q], C = sl[q + 1];
+        for (long long c = t; c < C.N; c += blockDim.x)
+            coarsen_cell<R, R, DIM, false>(F, C.nx, C.ny, C.nz, (O2 *)C.fx, (O2 *)C.fy,
+                                           (O2 *)C.fz, (O4 *)C.B, c);
+        __syncthreads();
+    }
+    const Lvl<R> L = sl[A.nl - 1];
+    for (long long r = t; r < 2 * L.N; r += blockDim.x) dense_row<R, DIM, false>(L, A.pin, A.M0, r);
+    __syncthreads();
+    gj_lds_body(A.M0, A.Ainv, A.m, A.flags, M, rowk, colk, (int)(blockDim.x / A.m) * A.m);
+}
+
+template <typename R>
+bool launch_hier_small(int dim, const HierSmallArgs<R> &a, hipStream_t s)
+{
+    if (a.m > kGJLdsMax || a.nl < 2 || a.nl > kMaxTail) return false;
+    if (dim == 3) hipLaunchKernelGGL((k_hier_small<R, 3>), dim3(1), dim3(1024), 0, s, a);
+    else hipLaunchKernelGGL((k_hier_small<R, 2>), dim3(1), dim3(1024), 0, s, a);
+    return true;
+}
+template bool launch_hier_small<float>(int, const HierSmallArgs<float> &, hipStream_t);
+template bool launch_hier_small<double>(int, const HierSmallArgs<double> &, hipStream_t);
 
 bool launch_gj_lds(const double *A, double *Ainv, int m, int *flags, hipStream_t s)
 {

@@ -567,3 +567,36 @@ def test_coarse_sweeps_option():
     for bad in (-1, 9 * 16, 9, 256):
         with pytest.raises(ptmg.PtMgError):
             h.set_option(ptmg.PT_OPT_COARSE_SWEEPS, bad)
+
+
+@pytest.mark.parametrize("name", ["bubble2d_200x136", "bubble3d_40x24x56", "explicit_64",
+                                  "twobubble2d_96x80"])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_small_hierarchy_kernel_matches_reference(name, prec):
+    """The small end of the hierarchy (levels of at most 1024 cells, the
+    coarsest matrix and its inverse) built by one single-block kernel on
+    the fused path equals the separate kernels (PT_OPT_FUSED off) bit for
+    bit: every level's operator and a whole solve."""
+    import workloads.device as D
+    from paper_2206_11294_amd import ptmg
+    prob = step_problems()[name]
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        h, b_p, b_T, t = D.setup(prob, prec, stream=stream)
+        s2, t2 = D.to_device(prob)
+        nl = h.num_levels()
+        out = {}
+        for fused in (1, 0):
+            h.set_option(ptmg.PT_OPT_FUSED, fused)
+            h.update(s2, keepalive=t2)      # the hierarchy rebuilt on this path
+            ops = [tuple(x.clone() for x in h.get_operator(l)) for l in range(1, nl)]
+            p, T = torch.empty_like(b_p), torch.empty_like(b_T)
+            h.set_option(ptmg.PT_OPT_FUSED, 1)
+            info = h.solve(b_p, b_T, p, T, rtol=1e-12)
+            torch.cuda.synchronize()
+            assert info["status"] == 0
+            out[fused] = (ops, p.clone(), T.clone(), info["hist"])
+    (o1, p1, T1, h1), (o0, p0, T0, h0) = out[1], out[0]
+    for l, (a, b) in enumerate(zip(o1, o0), start=1):
+        assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1]), l
+    assert torch.equal(p1, p0) and torch.equal(T1, T0) and h1 == h0
