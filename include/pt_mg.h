@@ -406,8 +406,11 @@ long long pt_mg_last_cell_updates(pt_mg_t h);
  *  PT_OPT_TAIL: run the coarsest levels that fit in one block's LDS as a
  *    single-block kernel; default 1.  pt_mg_get_option returns, for
  *    PT_OPT_TAIL, the number of levels the tail covers (0 if none).
- *  PT_OPT_FUSED: each red-black sweep as one fused pass over memory;
- *    0: two colour passes (the reference path); default 1.
+ *  PT_OPT_FUSED: each red-black sweep as one fused pass over memory, the
+ *    finest level's transfers inside its sweeps, and (from the next
+ *    pt_mg_update) the levels of at most 1024 cells and the coarsest
+ *    inverse built by one single-block kernel; 0: two colour passes and
+ *    separate kernels (the reference path, equal bit for bit); default 1.
  *  PT_OPT_TIMING_EVERY: with timing on, time one run in every n of each
  *    class (n >= 1, default 1; PT_ERR_ARG otherwise).
  *  PT_OPT_SPECULATE: enqueue the next outer iteration (V-cycle, FP64
