@@ -12,9 +12,12 @@ certified by its own residual.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes
 import os
+import shutil
 import subprocess
+import tempfile
 from dataclasses import dataclass
 from typing import Optional, Tuple
 
@@ -26,16 +29,41 @@ _LIB = os.path.join(_HERE, "libptorc.so")
 _lib = None
 
 
+def _compile(out: str, plant: int = 0) -> None:
+    subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared",
+                           "-ffp-contract=off", "-std=c99", f"-DORC_PLANT={int(plant)}",
+                           "-o", out, _SRC, "-lm"])
+
+
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc (FP64, no FMA contraction, OpenMP)."""
     stale = (not os.path.exists(_LIB)
              or os.path.getmtime(_LIB) < os.path.getmtime(_SRC))
     if force or stale:
         tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared",
-                               "-ffp-contract=off", "-std=c99", "-o", tmp, _SRC, "-lm"])
+        _compile(tmp)
         os.replace(tmp, _LIB)
     return _LIB
+
+
+@contextlib.contextmanager
+def planted(k: int):
+    """Mutation checks of the pin tests: inside the block every oracle
+    call goes to a private build with planted mistake k (ORC_PLANT in
+    ptorc.c); the correct library is restored on exit."""
+    global _lib
+    saved = _load()
+    d = tempfile.mkdtemp(prefix="ptorc_plant")
+    try:
+        path = os.path.join(d, f"libptorc_plant{int(k)}.so")
+        _compile(path, k)
+        lib = ctypes.CDLL(path)
+        _declare(lib)
+        _lib = lib
+        yield
+    finally:
+        _lib = saved
+        shutil.rmtree(d, ignore_errors=True)
 
 
 def _load():

@@ -50,6 +50,16 @@
 #include <stdlib.h>
 #include <string.h>
 
+/* Planted mistakes, for the mutation checks of the pin tests only: the
+ * tests compile a private copy of this file with ORC_PLANT = k and check
+ * that the pins reject it.  Every other build uses 0 (no mistake).
+ *   1: face coefficient = arithmetic instead of harmonic mean
+ *   2: cell a_p = C/rho_l + (1-C)/rho_g instead of 1/(C rho_l + (1-C) rho_g)
+ *   3: cell a_T = 1/(C/k_l + (1-C)/k_g) instead of C k_l + (1-C) k_g */
+#ifndef ORC_PLANT
+#define ORC_PLANT 0
+#endif
+
 typedef struct {
     double rho, k, cp, cv, c, gamma, Gamma, Pi, b, beta, q;
 } orc_phase;
@@ -124,8 +134,16 @@ long orc_assemble_phases(long n, const double *C, const orc_phase *liq,
         double T = T_adv ? T_adv[i] : T_const;
         double l[4], b[4];
         orc_cell_lambdas(c, liq, gas, p, T, dt, l, b);
+#if ORC_PLANT == 2
+        a_p[i] = c / liq->rho + (1.0 - c) / gas->rho;
+#else
         a_p[i] = 1.0 / (c * liq->rho + (1.0 - c) * gas->rho);
+#endif
+#if ORC_PLANT == 3
+        a_T[i] = 1.0 / (c / liq->k + (1.0 - c) / gas->k);
+#else
         a_T[i] = c * liq->k + (1.0 - c) * gas->k;
+#endif
         for (int q = 0; q < 4; q++) {
             lam[q * n + i] = l[q];
             B[q * n + i] = b[q];
@@ -296,7 +314,11 @@ void orc_faces_from_cells(int dim, const int *n, const double *a_p,
                         long lo = idx3(n, ii[0], ii[1], ii[2]);
                         double L = cell[c][lo], R = cell[c][me];
                         /* a zero coefficient on either side closes the face */
+#if ORC_PLANT == 1
+                        Fa[me] = 0.5 * (L + R);
+#else
                         Fa[me] = (L + R > 0.0) ? 2.0 * L * R / (L + R) : 0.0;
+#endif
                     }
         }
 }

@@ -461,3 +461,100 @@ def test_rb_and_lex_sweeps_reduce_error(orc):
         for _ in range(3):
             orc.sweep(op, f_p, f_T, p, T, order)
         assert np.linalg.norm(p - pd) < 0.5 * e0
+
+
+# ------------------------------ P13 face and cell coefficients of the mixture
+# Sec. 3's averaging rule makes the mixture density and conductivity of a
+# cell the C-weighted means of the phase values, and Eqs. 27-28 divide the
+# pressure gradient by that density.  Two exact facts pin how the oracle
+# turns them into coefficients, without re-typing its formulas:
+#  * a column of two layers with a jump of the coefficient at one face
+#    carries, in steady state without sources, the same flux through every
+#    face; the continuous solution is piecewise linear, and a cell-centred
+#    scheme reproduces that flux on every face only with the harmonic face
+#    mean of the cell coefficients (a series of two half-cell resistances);
+#  * in a uniform mixture the velocity correction of Eq. unp1 is the
+#    pressure gradient divided by the mixture density.
+LAYERS = [(1.0, 0.0), (0.0, 1.0), (0.3, 0.8), (0.95, 0.1)]
+
+
+def _layered_column(nx, m, cL, cR, C_extra=None):
+    """Phases-mode column of nx x 3 cells: liquid fraction cL in cells
+    i < m and cR in cells i >= m (the jump lies on the face x = m h)."""
+    h = W.L_UNIT / nx
+    C = np.where(np.arange(nx) < m, cL, cR)[None, :].repeat(3, axis=0)
+    return W.Problem(name="layers", dim=2, n=(nx, 3, 1), h=h, mode="phases",
+                     C=np.ascontiguousarray(C, dtype=np.float64), dt=W.acoustic_dt(h))
+
+
+def _piecewise_linear(x, xm, aL, aR, q, u0):
+    """Steady solution of -(a u')' = 0 with constant flux q = -a u' and
+    u(0) = u0, for a = aL left of xm and aR right of it."""
+    left = u0 - q * x / aL
+    right = u0 - q * xm / aL - q * (x - xm) / aR
+    return np.where(x < xm, left, right)
+
+
+def _layer_rows(orc, cL, cR, nx=24, m=11):
+    """Largest interior row of the oracle's diffusion operator (B = 0)
+    applied to the exact two-layer solution, over the flux scale q/h,
+    for the p and the T component."""
+    prob = _layered_column(nx, m, cL, cR)
+    op = orc.assemble(prob)
+    N = prob.ncells
+    op0 = orc.Operator(2, prob.n, prob.h, op.F, np.zeros((4, N)))
+    liq, gas = W.LIQUID, W.GAS
+    rho = lambda c: c * liq.rho + (1 - c) * gas.rho        # mixture density
+    kap = lambda c: c * liq.k + (1 - c) * gas.k            # mixture conductivity
+    x = np.tile((np.arange(nx) + 0.5) * prob.h, 3)
+    xm = m * prob.h
+    # fluxes that change u by one unit per cell in the left layer (the
+    # operator is linear: the offset and the scale of u are immaterial)
+    qp, qT = 1 / rho(cL) / prob.h, kap(cL) / prob.h
+    p = _piecewise_linear(x, xm, 1 / rho(cL), 1 / rho(cR), qp, 0.0)
+    T = _piecewise_linear(x, xm, kap(cL), kap(cR), qT, 0.0)
+    Ap, AT = orc.apply(op0, p, T)
+    inner = np.tile((np.arange(nx) > 0) & (np.arange(nx) < nx - 1), 3)
+    return (np.abs(Ap[inner]).max() / (qp / prob.h),
+            np.abs(AT[inner]).max() / (qT / prob.h))
+
+
+@pytest.mark.parametrize("cL,cR", LAYERS)
+def test_P13_two_layers_exact_flux(orc, cL, cR):
+    rp, rT = _layer_rows(orc, cL, cR)
+    assert rp <= 1e-9 and rT <= 1e-9, (rp, rT)
+
+
+def _uniform_mixture_correction(orc, c):
+    """rho_bar (U - U*) / (-dt dp/dx) on the interior x faces of a uniform
+    mixture column with a linear pressure (Eq. unp1); 1 when a_p = 1/rho_bar."""
+    nx = 12
+    prob = _layered_column(nx, 0, c, c)
+    op = orc.assemble(prob)
+    slope = 3.0e5                                  # Pa/m
+    x = np.tile((np.arange(nx) + 0.5) * prob.h, 3)
+    p = W.P0 + slope * x
+    U_star = [np.zeros(orc.face_shape(2, prob.n, a)) for a in range(2)]
+    U, _ = orc.project(op, prob.dt, p, U_star)
+    Ux = U[0].reshape(3, nx + 1)[:, 1:nx]
+    rho_bar = c * W.LIQUID.rho + (1 - c) * W.GAS.rho
+    return rho_bar * Ux / (-prob.dt * slope)
+
+
+@pytest.mark.parametrize("c", [0.3, 0.75, 1.0, 0.0])
+def test_P13_uniform_mixture_velocity_correction(orc, c):
+    np.testing.assert_allclose(_uniform_mixture_correction(orc, c), 1.0, rtol=1e-12)
+
+
+def test_P13_pins_reject_planted_means(orc):
+    """Each planted mistake of a mixture coefficient fails a P13 pin."""
+    with orc.planted(1):      # arithmetic face mean
+        assert max(_layer_rows(orc, 1.0, 0.0)) > 1e-2
+        assert max(_layer_rows(orc, 0.3, 0.8)) > 1e-2
+    with orc.planted(2):      # a_p as the C-weighted mean of 1/rho
+        assert _layer_rows(orc, 0.3, 0.8)[0] > 1e-2
+        assert np.abs(_uniform_mixture_correction(orc, 0.3) - 1).max() > 1e-2
+    with orc.planted(3):      # a_T as the harmonic C-weighted mean of k
+        assert _layer_rows(orc, 0.3, 0.8)[1] > 1e-2
+    # and the correct oracle is back
+    assert max(_layer_rows(orc, 0.3, 0.8)) <= 1e-9
