@@ -14,11 +14,17 @@ face velocities (pt_mg_divergence), and after the solve the velocity
 correction and the phase energy update (pt_mg_downstream, Eqs. unp1,
 37-39) consume it.
 
+The default workload is the largest single-GPU one: the 512^3 collapse-
+like field (a sphere of radius 0.25 with gas at 0.01 p0 in liquid at
+100 p0), solved with the FP32 V-cycle under FP64 iterative refinement.
+For the mixed-precision workloads the same steps are then timed with the
+plain FP64 V-cycle at the same size and tolerance, and reported beside.
+
 Prints one JSON line: cell-updates/s of the timed steps, the roofline of
 the dominant kernel (HIP-event durations of its launches inside the timed
-region, algorithmic bytes per launch), and the CPU leg: the FP64 oracle
-timed on the host on a bounded sample of the same workload, and the
-oracle's own residual of the last GPU solution.
+region, algorithmic bytes per launch), the FP64 comparison, and the CPU
+leg: the FP64 oracle timed on the host on a bounded sample of the same
+workload, and the oracle's own residual of the last GPU solution.
 
   python bench.py [--steps K] [--warmup W] [--workload NAME] [--precision fp64|mixed]
   python bench.py --copy-calib BYTES    # plain copy kernel (counter calibration)
@@ -154,12 +160,27 @@ def oracle_updates(orc, prob, cycles):
     return cycles * per_cycle + sizes[0]
 
 
+def cpu_model():
+    """The host CPU's model name (Linux), or the platform's processor."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
 def cpu_baseline(prob, rtol, budget_s):
     """The oracle as it stands, on the host cores, on a bounded sample of
     the same workload: whole steps (assembly, right-hand side, multigrid
     solve to the same tolerance) repeated until the budget is used; when
     one V-cycle already takes a large share of the budget, a single step
-    capped at one V-cycle."""
+    capped at one V-cycle.  The oracle's assembly and operator applications
+    are OpenMP loops over the host threads; its lexicographic Gauss-Seidel
+    sweeps, restrictions and prolongations run on one thread."""
     import oracle as orc
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
 
@@ -195,7 +216,8 @@ def cpu_baseline(prob, rtol, budget_s):
               + (", capped at one V-cycle" if capped else f", rtol {rtol:g}")
               + f"), {total:.1f} s")
     return {"value": updates / total, "unit": "cell-updates/s", "cores": threads,
-            "kind": "oracle", "sample": sample}
+            "kind": "oracle", "sample": sample, "cpu_model": cpu_model(),
+            "threads": {"assembly_and_residuals": threads, "vcycle_sweeps_and_transfers": 1}}
 
 
 def _make_serve_request(rid):
@@ -358,7 +380,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="bubble2d_1024", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="collapse3d_512", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", choices=["fp64", "mixed"], default=None)
     ap.add_argument("--method", choices=["defect", "bicgstab"], default="defect",
                     help="outer iteration: the defect-correction loop of Sec. 3, or "
@@ -368,6 +390,8 @@ def main():
     ap.add_argument("--rtol", type=float, default=None)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64-compare", action="store_true",
+                    help="mixed-precision workloads: skip the FP64 steps timed beside")
     ap.add_argument("--no-oracle-check", action="store_true",
                     help="in the CPU leg, skip the oracle's residual of the GPU solution")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="BYTES")
@@ -427,6 +451,99 @@ def main():
     print(f"# workload {name} grid {prob.n} precision {prec_name} rtol {rtol:g}",
           file=sys.stderr, flush=True)
 
+    run = timed_steps(prob, prec, rtol, method, args)
+    h, info, p, T = run["h"], run["info"], run["p"], run["T"]
+    stats, timed = run["stats"], run["timed"]
+    elapsed, updates, cycles = run["elapsed"], run["updates"], run["cycles"]
+
+    dom = ROOFLINE_KERNEL
+    st = timed[dom]
+    avg_ms = st["ms"] / max(st["launches"], 1)
+    bytes_per_launch = st["bytes"] / max(st["launches"], 1)
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    traffic = traffic_from_profile(name, dom, stats[dom]["launches"] / args.steps)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": dom, "avg_launch_us": round(avg_ms * 1e3, 2),
+                "alg_bytes_per_launch": bytes_per_launch, "timed_launches": st["launches"],
+                "timed_every": args.timing_every}
+
+    out = {
+        "metric": "coupled p-T cell-updates/s",
+        "value": updates / elapsed,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec_name == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": name, "grid": list(prob.n[: prob.dim]), "precision": prec_name,
+                   "geometry": "axisymmetric r-z" if prob.axisymmetric else "cartesian",
+                   "rtol": rtol, "cycles_per_solve": float(np.mean(cycles)),
+                   "step": ("pt_state_eval + " if prob.mode == "state" else "")
+                   + ("pt_mg_divergence + " if run["faces"] else "")
+                   + ("pt_mg_update + pt_mg_solve" if prob.mode == "explicit" else
+                      "pt_mg_step (update + paper RHS + solve)")
+                   + (" + pt_mg_downstream" if run["faces"] else ""),
+                   "method": args.method, "time_step": "diffusive" if args.stiff else "acoustic",
+                   "tail_levels": run["tail_levels"],
+                   "sweeps": {"finest": [args.nu1, args.nu2],
+                              "coarse": (list(divmod(args.coarse_sweeps, 16))
+                                         if args.coarse_sweeps else [args.nu1, args.nu2])},
+                   "footprint_bytes": run["footprint"],
+                   "parallelism": "single GPU"},
+        "roofline": roofline,
+        "upstream": upstream_line(prob, run["state_ms"]),
+        "downstream": downstream_line(timed),
+        "launches_per_step": {k: v["launches"] / args.steps for k, v in stats.items()},
+        "relres_last": list(info["relres"]),
+        "relres_hist_last": [[float("%.3g" % x) for x in pair] for pair in info["hist"]],
+    }
+    P, TT = p.cpu().numpy(), T.cpu().numpy()
+    h.destroy()
+    del run, h, p, T
+    torch.cuda.empty_cache()
+
+    if prec == ptmg.PT_PREC_MIXED and not args.no_fp64_compare:
+        # the same steps with the plain FP64 V-cycle, same size and tolerance
+        print("# the same steps with the FP64 V-cycle", file=sys.stderr, flush=True)
+        ref = timed_steps(prob, ptmg.PT_PREC_FP64, rtol, method, args, roofline_timing=False)
+        fp64_ms = 1e3 * ref["elapsed"] / args.steps
+        out["fp64_same_steps"] = {
+            "precision": "fp64", "rtol": rtol, "ms_per_step": fp64_ms,
+            "cycles_per_solve": float(np.mean(ref["cycles"])),
+            "cell_updates_per_s": ref["updates"] / ref["elapsed"],
+            "relres_last": list(ref["info"]["relres"]),
+            "mixed_speedup": fp64_ms / out["ms_per_step"]}
+        ref["h"].destroy()
+        del ref
+        torch.cuda.empty_cache()
+
+    if not args.no_cpu_baseline:
+        # the CPU leg: the oracle timed on the host cores, and (grids it
+        # assembles in seconds) its own residual of the last GPU solution
+        out["cpu_baseline"] = cpu_baseline(prob, rtol, args.cpu_seconds)
+        if not args.no_oracle_check and prob.ncells <= 150_000_000:
+            import oracle as orc
+            op = orc.assemble(prob)
+            bp, bT = orc.rhs(op, prob)   # the oracle's own right-hand side
+            out["oracle_relres_of_gpu_solution"] = [float(x)
+                                                    for x in orc.relres(op, bp, bT, P, TT)]
+    print(json.dumps(out), flush=True)
+
+
+def timed_steps(prob, prec, rtol, method, args, roofline_timing=True):
+    """W untimed and K timed steps of the workload on a handle of the
+    given precision; the handle is returned alive with the last solution."""
+    import torch
+
+    import workloads.device as D
+    from paper_2206_11294_amd import ptmg
+
     stream = torch.cuda.Stream()   # the library's stream (default priority)
     with torch.cuda.stream(stream):
         s, tens = D.to_device(prob)
@@ -467,27 +584,27 @@ def main():
                 info = h.step(s, div if faces is not None else tens.get("div"), rhs_p, rhs_T,
                               p, T, rtol=rtol, max_cycles=120, nu1=args.nu1, nu2=args.nu2,
                               method=method)
-                b_p, b_T = rhs_p, rhs_T
             if faces is not None:
                 h.downstream(p, T, tens["C"], faces, U, us, u, tens["E1"], tens["E2"], E1, E2,
                              tens["kappa"], prob.sigma)
-            return info, b_p, b_T
+            return info
 
         for _ in range(args.warmup):
             step()
         torch.cuda.synchronize()
-        # HIP events only around the finest-grid smoother (the kernel the
-        # roofline reports), and only around one smoothing run in
-        # `timing_every`, so that the timed steps carry little overhead
-        h.set_timing(True, classes=[ROOFLINE_KERNEL]
-                     + (["downstream"] if faces is not None else []))
-        h.set_option(ptmg.PT_OPT_TIMING_EVERY, args.timing_every)
+        if roofline_timing:
+            # HIP events only around the finest-grid smoother (the kernel
+            # the roofline reports), and only around one smoothing run in
+            # `timing_every`, so that the timed steps carry little overhead
+            h.set_timing(True, classes=[ROOFLINE_KERNEL]
+                         + (["downstream"] if faces is not None else []))
+            h.set_option(ptmg.PT_OPT_TIMING_EVERY, args.timing_every)
         h.reset_stats()
         updates = 0
         cycles = []
         t0 = time.perf_counter()
         for _ in range(args.steps):
-            info, b_p, b_T = step()
+            info = step()
             updates += h.last_cell_updates()
             cycles.append(info["cycles"])
         torch.cuda.synchronize()
@@ -496,65 +613,10 @@ def main():
         timed = h.timed_stats()
         h.set_timing(False)
         state_ms = [a.elapsed_time(b) for a, b in state_ev[args.warmup:]]
-
-    dom = ROOFLINE_KERNEL
-    st = timed[dom]
-    avg_ms = st["ms"] / max(st["launches"], 1)
-    bytes_per_launch = st["bytes"] / max(st["launches"], 1)
-    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    traffic = traffic_from_profile(name, dom, stats[dom]["launches"] / args.steps)
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": dom, "avg_launch_us": round(avg_ms * 1e3, 2),
-                "alg_bytes_per_launch": bytes_per_launch, "timed_launches": st["launches"],
-                "timed_every": args.timing_every}
-
-    out = {
-        "metric": "coupled p-T cell-updates/s",
-        "value": updates / elapsed,
-        "unit": "cell-updates/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": 1e3 * elapsed / args.steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64" if prec_name == "fp64" else "f32+f64",
-        "data": "synthetic",
-        "config": {"workload": name, "grid": list(prob.n[: prob.dim]), "precision": prec_name,
-                   "geometry": "axisymmetric r-z" if prob.axisymmetric else "cartesian",
-                   "rtol": rtol, "cycles_per_solve": float(np.mean(cycles)),
-                   "step": ("pt_state_eval + " if prob.mode == "state" else "")
-                   + ("pt_mg_divergence + " if faces is not None else "")
-                   + ("pt_mg_update + pt_mg_solve" if prob.mode == "explicit" else
-                      "pt_mg_step (update + paper RHS + solve)")
-                   + (" + pt_mg_downstream" if faces is not None else ""),
-                   "method": args.method, "time_step": "diffusive" if args.stiff else "acoustic",
-                   "tail_levels": h.get_option(ptmg.PT_OPT_TAIL),
-                   "sweeps": {"finest": [args.nu1, args.nu2],
-                              "coarse": (list(divmod(args.coarse_sweeps, 16))
-                                         if args.coarse_sweeps else [args.nu1, args.nu2])},
-                   "parallelism": "single GPU"},
-        "roofline": roofline,
-        "upstream": upstream_line(prob, state_ms),
-        "downstream": downstream_line(timed),
-        "launches_per_step": {k: v["launches"] / args.steps for k, v in stats.items()},
-        "relres_last": list(info["relres"]),
-        "relres_hist_last": [[float("%.3g" % x) for x in pair] for pair in info["hist"]],
-    }
-    if not args.no_cpu_baseline:
-        # the CPU leg: the oracle timed on the host cores, and (grids it
-        # assembles in seconds) its own residual of the last GPU solution
-        out["cpu_baseline"] = cpu_baseline(prob, rtol, args.cpu_seconds)
-        if not args.no_oracle_check and prob.ncells <= 2_500_000:
-            import oracle as orc
-            op = orc.assemble(prob)
-            bp, bT = orc.rhs(op, prob)   # the oracle's own right-hand side
-            P, TT = p.cpu().numpy(), T.cpu().numpy()
-            out["oracle_relres_of_gpu_solution"] = [float(x)
-                                                    for x in orc.relres(op, bp, bT, P, TT)]
-    print(json.dumps(out), flush=True)
+    return {"h": h, "info": info, "p": p, "T": T, "stats": stats, "timed": timed,
+            "elapsed": elapsed, "updates": updates, "cycles": cycles, "state_ms": state_ms,
+            "faces": faces is not None, "tail_levels": h.get_option(ptmg.PT_OPT_TAIL),
+            "footprint": ptmg.footprint_bytes(s, prec)}
 
 
 if __name__ == "__main__":
