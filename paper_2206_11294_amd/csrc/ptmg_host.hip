@@ -239,6 +239,7 @@ struct pt_mg_s {
     // as one graph, captured at the first assembly on a non-null stream
     hipGraph_t hier_graph = nullptr;
     hipGraphExec_t hier_exec = nullptr;
+    bool hier_fused = true;         // use_fused when hier_graph was captured
     // off by default: with one kernel per coarse visit and the tail, a graph
     // replaces few launches, and its end costs more than they do
     bool use_graphs = false;
@@ -746,7 +747,16 @@ template <typename R> void hierarchy(pt_mg_t h)
         build_hierarchy<R>(h);
         return;
     }
+    if (h->hier_exec && h->hier_fused != h->use_fused) {
+        // PT_OPT_FUSED changed since the capture: the graph holds the other
+        // kernels, so capture again
+        (void)hipGraphExecDestroy(h->hier_exec);
+        (void)hipGraphDestroy(h->hier_graph);
+        h->hier_exec = nullptr;
+        h->hier_graph = nullptr;
+    }
     if (!h->hier_exec) {
+        h->hier_fused = h->use_fused;
         bool ok = hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
         if (ok) {
             build_hierarchy<R>(h);

@@ -246,6 +246,39 @@ def test_graph_replay_matches_direct_launches(name):
     assert torch.equal(outs["direct"][1], outs["graph"][1])
 
 
+@pytest.mark.parametrize("name", ["bubble2d_200x136", "bubble3d_40x24x56"])
+def test_hierarchy_graph_follows_fused_toggle(name):
+    """PT_OPT_FUSED switched between two updates of a handle that replays
+    its hierarchy build from a graph: the build is captured again with the
+    other kernels, and every level's operator and the solve equal those of
+    a handle with direct launches bit for bit."""
+    import workloads.device as D
+    from paper_2206_11294_amd import ptmg
+    prob = step_problems()[name]
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        hg, b_p, b_T, _ = D.setup(prob, 1, stream=stream)
+        hd, _, _, _ = D.setup(prob, 1, stream=stream)
+        hg.set_option(ptmg.PT_OPT_GRAPHS, 1)
+        s2, t2 = D.to_device(prob)
+        for fused in (1, 1, 0, 0, 1):
+            for h in (hg, hd):
+                h.set_option(ptmg.PT_OPT_FUSED, fused)
+                h.update(s2, keepalive=t2)
+            for lv in range(hg.num_levels()):
+                Fg, Bg = hg.get_operator(lv)
+                Fd, Bd = hd.get_operator(lv)
+                assert torch.equal(Fg, Fd) and torch.equal(Bg, Bd), (fused, lv)
+            sol = []
+            for h in (hg, hd):
+                p, T = torch.empty_like(b_p), torch.empty_like(b_T)
+                info = h.solve(b_p, b_T, p, T, rtol=1e-12)
+                assert info["status"] == 0
+                sol.append((p, T))
+            torch.cuda.synchronize()
+            assert torch.equal(sol[0][0], sol[1][0]) and torch.equal(sol[0][1], sol[1][1])
+
+
 @pytest.mark.parametrize("name", ["bubble2d_200x136", "bubble3d_40x24x56", "explicit_64",
                                   "twobubble2d_96x80"])
 @pytest.mark.parametrize("prec", [0, 1])
