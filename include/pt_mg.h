@@ -225,6 +225,27 @@ int pt_mg_paper_rhs(pt_mg_t h, const double *p_adv, const double *T_adv,
 int pt_mg_solve(pt_mg_t h, const double *b_p, const double *b_T, double *p, double *T,
                 const pt_solve_opts *opts, pt_solve_info *info);
 
+/* For callers that cannot allocate device memory: code that runs between
+ * HIP graph captures, serving loops and harnesses that forbid hipMalloc.
+ * pt_mg_solve with the same arguments, results, errors and info, except
+ * that no call allocates device or host memory: with opts->method =
+ * PT_SOLVE_BICGSTAB the eight FP64 work vectors (128 bytes per cell, which
+ * pt_mg_solve allocates on its first BiCGStab call on a handle) live in the
+ * library's static device scratch of PT_SCRATCH_BYTES (128 MiB, held on
+ * each GPU the library runs on until the process ends), so grids of at
+ * most PT_SCRATCH_MAX_CELLS = 2^20 cells; a larger grid fails with
+ * PT_ERR_ARG before anything is enqueued.  The defect method needs no work
+ * memory beyond the handle's and runs exactly as pt_mg_solve.  The scratch
+ * is shared by every call on one GPU and keeps the last call's contents
+ * (the vectors that must start at zero are cleared by each call): calls
+ * that overlap on one GPU (from two host threads, or on two handles whose
+ * streams run concurrently) race.  Timing (pt_mg_set_timing) creates its
+ * HIP events on first use; leave it off where nothing may be created. */
+#define PT_SCRATCH_MAX_CELLS (1ll << 20)
+#define PT_SCRATCH_BYTES (16ll * 8 * PT_SCRATCH_MAX_CELLS)
+int pt_mg_solve_noalloc(pt_mg_t h, const double *b_p, const double *b_T, double *p, double *T,
+                        const pt_solve_opts *opts, pt_solve_info *info);
+
 /* One implicit step in one call: pt_mg_update(prob), the paper right-hand
  * side of Eqs. (33)-(34) from prob->p_adv, prob->T_adv and div_ustar into
  * b_p, b_T (as pt_mg_paper_rhs), and pt_mg_solve(b, p, T, opts, info), the

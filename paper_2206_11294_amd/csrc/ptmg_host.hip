@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -185,6 +186,7 @@ struct pt_mg_s {
     double *kry = nullptr;          // Krylov work vectors (allocated on first use)
     bool ready = false;
     bool owns_memory = true;        // false: device + pinned memory belong to a server arena
+    int device = 0;                 // the GPU current at setup (its static scratch)
     hipEvent_t done_ev = nullptr;   // marks the end of the last enqueued step
     // asynchronous solve (pt_mg_solve drives it to the end; a server polls it)
     // Outer iteration k computes u_k (k >= 1: after V-cycle k-1) and the
@@ -378,6 +380,48 @@ int fail(pt_mg_t h, int code, const std::string &msg)
     if (h) h->err = msg;
     else g_thread_err = msg;
     return code;
+}
+
+// ------------------------------------------------------- static scratch
+// Work memory of pt_mg_solve_noalloc (BiCGStab's eight FP64 vector pairs):
+// one array per GPU, loaded with the library's code object, so that no
+// call allocates.  In host code the name `scratch` only stands in for the
+// device symbol: its address on each GPU comes from hipGetSymbolAddress,
+// taken once per device with that device current, and only that address
+// is passed to kernels.
+static __device__ __align__(256) double scratch[16 * (size_t)PT_SCRATCH_MAX_CELLS];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_dev[kMaxDevices] = {};
+
+// Device address of `scratch` on GPU dev (looked up on first use).
+int scratch_address(pt_mg_t h, int dev, double **out)
+{
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (dev < 0 || dev >= kMaxDevices) return fail(h, PT_ERR_HIP, "device index out of range");
+    if (!g_scratch_dev[dev]) {
+        int cur = -1;
+        if (hipGetDevice(&cur) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(h, PT_ERR_HIP, "hipGetDevice failed");
+        }
+        if (cur != dev && hipSetDevice(dev) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(h, PT_ERR_HIP, "hipSetDevice failed");
+        }
+        void *ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (cur != dev) (void)hipSetDevice(cur);
+        if (e != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return fail(h, PT_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") +
+                                           hipGetErrorString(e));
+        }
+        g_scratch_dev[dev] = (double *)ptr;
+    }
+    *out = g_scratch_dev[dev];
+    return PT_OK;
 }
 
 int check_hip(pt_mg_t h, hipError_t e, const char *what)
@@ -941,6 +985,19 @@ int handle_create(const pt_problem *prob, int precision, hipStream_t stream, cha
     pt_mg_t h = new pt_mg_s();
     h->P = P;
     h->stream = stream;
+    if (hipGetDevice(&h->device) != hipSuccess) {
+        (void)hipGetLastError();
+        delete h;
+        *err = "hipGetDevice failed";
+        return PT_ERR_HIP;
+    }
+    {
+        // the static scratch's address on this GPU, taken at set-up so that
+        // pt_mg_solve_noalloc's first call loads and looks up nothing (a
+        // failure here is reported by that call, which retries)
+        double *w = nullptr;
+        if (scratch_address(nullptr, h->device, &w) != PT_OK) (void)hipGetLastError();
+    }
     h->owns_memory = dev_mem == nullptr;
     if (h->owns_memory) {
         hipError_t e = hipMalloc(&h->base, P.total);
@@ -1500,19 +1557,45 @@ int solve_advance(pt_mg_t h, pt_solve_info *info)
 }  // namespace ptmg
 
 static int krylov_solve(pt_mg_t h, const double *b_p, const double *b_T, double *p, double *T,
-                        const pt_solve_opts &o, pt_solve_info *info);
+                        const pt_solve_opts &o, pt_solve_info *info, double *work);
+
+// Argument checks of a BiCGStab solve.
+static int krylov_check(pt_mg_t h, const double *b_p, const double *b_T, double *p, double *T,
+                        const pt_solve_opts &o)
+{
+    if (!h || !h->ready) return fail(h, PT_ERR_STATE, "handle not ready");
+    if (!b_p || !b_T || !p || !T) return fail(h, PT_ERR_ARG, "NULL field");
+    if (!(o.rtol >= 0) || o.max_cycles < 0 || o.nu1 < 0 || o.nu2 < 0 || o.nu1 > 8 ||
+        o.nu2 > 8 || o.nu1 + o.nu2 == 0)
+        return fail(h, PT_ERR_ARG, "bad solve options");
+    return PT_OK;
+}
+
+int pt_mg_solve_noalloc(pt_mg_t h, const double *b_p, const double *b_T, double *p, double *T,
+                        const pt_solve_opts *opts_in, pt_solve_info *info)
+{
+    if (!opts_in || opts_in->method != PT_SOLVE_BICGSTAB)
+        return pt_mg_solve(h, b_p, b_T, p, T, opts_in, info);   // allocates nothing
+    int rc = krylov_check(h, b_p, b_T, p, T, *opts_in);
+    if (rc != PT_OK) return rc;
+    if (h->P.N > PT_SCRATCH_MAX_CELLS)
+        return fail(h, PT_ERR_ARG, "grid of " + std::to_string(h->P.N) +
+                                       " cells exceeds the static scratch (" +
+                                       std::to_string((long long)PT_SCRATCH_MAX_CELLS) +
+                                       " cells)");
+    double *work = nullptr;
+    rc = scratch_address(h, h->device, &work);
+    if (rc != PT_OK) return rc;
+    return krylov_solve(h, b_p, b_T, p, T, *opts_in, info, work);
+}
 
 int pt_mg_solve(pt_mg_t h, const double *b_p, const double *b_T, double *p, double *T,
                 const pt_solve_opts *opts_in, pt_solve_info *info)
 {
     if (opts_in && opts_in->method == PT_SOLVE_BICGSTAB) {
-        if (!h || !h->ready) return fail(h, PT_ERR_STATE, "handle not ready");
-        if (!b_p || !b_T || !p || !T) return fail(h, PT_ERR_ARG, "NULL field");
-        const pt_solve_opts &o = *opts_in;
-        if (!(o.rtol >= 0) || o.max_cycles < 0 || o.nu1 < 0 || o.nu2 < 0 || o.nu1 > 8 ||
-            o.nu2 > 8 || o.nu1 + o.nu2 == 0)
-            return fail(h, PT_ERR_ARG, "bad solve options");
-        return krylov_solve(h, b_p, b_T, p, T, o, info);
+        int rc = krylov_check(h, b_p, b_T, p, T, *opts_in);
+        if (rc != PT_OK) return rc;
+        return krylov_solve(h, b_p, b_T, p, T, *opts_in, info, nullptr);
     }
     if (opts_in && opts_in->method != PT_SOLVE_DEFECT) return fail(h, PT_ERR_ARG, "unknown method");
     int rc = solve_begin(h, b_p, b_T, p, T, opts_in);
@@ -1634,27 +1717,34 @@ template <typename R> void unpack_lv(pt_mg_t h, int l, bool f, double *x, double
 // V-cycle as right preconditioner.  The residual is recomputed from x in
 // FP64 every iteration (the outer-residual kernel, which also gives the
 // paper-row-form norms of the stop test).  Vectors are FP64 pairs (p, T)
-// in h->kry; "neg" vectors hold -A y, as the residual kernel returns them
-// for a zero right-hand side.  Dot products are fixed-order reductions.
+// in `work` (16 N doubles; null: h->kry, allocated on first use); "neg"
+// vectors hold -A y, as the residual kernel returns them for a zero
+// right-hand side.  Every vector is written before it is read except PV
+// and VN, which are cleared, so stale work contents never matter.  Dot
+// products are fixed-order reductions.
 static int krylov_solve(pt_mg_t h, const double *b_p, const double *b_T, double *p, double *T,
-                        const pt_solve_opts &o, pt_solve_info *info)
+                        const pt_solve_opts &o, pt_solve_info *info, double *work)
 {
     const Plan &P = h->P;
     const long long N = P.N;
     if (h->prob.mean_constraint)
         return fail(h, PT_ERR_ARG, "BiCGStab does not take the mean constraint");
-    if (!h->owns_memory) return fail(h, PT_ERR_STATE, "BiCGStab needs a handle with its own memory");
-    if (!h->kry) {
-        hipError_t e = hipMalloc(&h->kry, sizeof(double) * 16 * (size_t)N);
-        if (e != hipSuccess) {
-            (void)hipGetLastError();
-            h->kry = nullptr;
-            return fail(h, PT_ERR_OOM, "BiCGStab work vectors");
+    if (!work) {
+        if (!h->owns_memory)
+            return fail(h, PT_ERR_STATE, "BiCGStab needs a handle with its own memory");
+        if (!h->kry) {
+            hipError_t e = hipMalloc(&h->kry, sizeof(double) * 16 * (size_t)N);
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                h->kry = nullptr;
+                return fail(h, PT_ERR_OOM, "BiCGStab work vectors");
+            }
         }
+        work = h->kry;
     }
     enum { R = 0, RH, PV, VN, SV, TN, PH, SH };
-    auto vp = [&](int k) { return h->kry + 2 * N * k; };
-    auto vT = [&](int k) { return h->kry + 2 * N * k + N; };
+    auto vp = [&](int k) { return work + 2 * N * k; };
+    auto vT = [&](int k) { return work + 2 * N * k + N; };
     const auto t0 = std::chrono::steady_clock::now();
     pt_solve_info inf;
     std::memset(&inf, 0, sizeof inf);

@@ -82,6 +82,7 @@ class pt_solve_opts(ctypes.Structure):
 
 
 PT_SOLVE_DEFECT, PT_SOLVE_BICGSTAB = 0, 1
+PT_SCRATCH_MAX_CELLS = 1 << 20   # pt_mg_solve_noalloc: largest BiCGStab grid
 
 
 class pt_solve_info(ctypes.Structure):
@@ -116,6 +117,8 @@ def lib() -> ctypes.CDLL:
             "pt_mg_downstream": (c_int, [c_void, P(pt_downstream)]),
             "pt_mg_solve": (c_int, [c_void, c_void, c_void, c_void, c_void,
                                     P(pt_solve_opts), P(pt_solve_info)]),
+            "pt_mg_solve_noalloc": (c_int, [c_void, c_void, c_void, c_void, c_void,
+                                            P(pt_solve_opts), P(pt_solve_info)]),
             "pt_mg_residual": (c_int, [c_void] + [c_void] * 6 + [P(c_double)]),
             "pt_mg_destroy": (None, [c_void]),
             "pt_mg_last_error": (ctypes.c_char_p, [c_void]),
@@ -151,7 +154,7 @@ def exported_symbols() -> Sequence[str]:
     lib()
     return ["pt_state_eval", "pt_mg_footprint_bytes", "pt_mg_setup", "pt_mg_update", "pt_mg_paper_rhs",
             "pt_mg_divergence", "pt_mg_downstream", "pt_mg_step",
-            "pt_mg_solve", "pt_mg_residual", "pt_mg_destroy", "pt_mg_last_error",
+            "pt_mg_solve", "pt_mg_solve_noalloc", "pt_mg_residual", "pt_mg_destroy", "pt_mg_last_error",
             "pt_mg_num_levels", "pt_mg_level_dims", "pt_mg_get_operator", "pt_mg_smooth",
             "pt_mg_restrict_residual", "pt_mg_prolong_add", "pt_mg_coarse_solve",
             "pt_mg_vcycle", "pt_mg_set_timing", "pt_mg_kernel_stats", "pt_mg_timed_stats", "pt_mg_reset_stats",
@@ -279,11 +282,14 @@ class PtMg:
         self._check(lib().pt_mg_downstream(self._h, ctypes.byref(d)))
 
     def solve(self, b_p, b_T, p, T, rtol=1e-9, max_cycles=50, nu1=2, nu2=2,
-              zero_guess=True, raise_on_noconv=True, method=PT_SOLVE_DEFECT) -> Dict:
+              zero_guess=True, raise_on_noconv=True, method=PT_SOLVE_DEFECT,
+              noalloc=False) -> Dict:
+        """pt_mg_solve, or pt_mg_solve_noalloc with noalloc=True."""
         opts = pt_solve_opts(rtol, max_cycles, nu1, nu2, int(zero_guess), int(method))
         info = pt_solve_info()
-        rc = lib().pt_mg_solve(self._h, _ptr(b_p), _ptr(b_T), _ptr(p), _ptr(T),
-                               ctypes.byref(opts), ctypes.byref(info))
+        fn = lib().pt_mg_solve_noalloc if noalloc else lib().pt_mg_solve
+        rc = fn(self._h, _ptr(b_p), _ptr(b_T), _ptr(p), _ptr(T),
+                ctypes.byref(opts), ctypes.byref(info))
         if rc and (rc != PT_ERR_NOCONV or raise_on_noconv):
             self._check(rc)
         n = info.hist_len
