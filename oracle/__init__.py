@@ -125,7 +125,9 @@ def _declare(lib):
         "orc_phase_pressures": (None, [c_long, _D, _D, _D, c_double, _D, _D]),
         "orc_energy_update": (None, [c_int, _I, c_double, c_double, _D, c_int, _D, _D, _D, _D,
                                      _PP,
-                                     _D, _D, _D, _D]),
+                                     _D, _D, _D, _D, _D]),
+        "orc_viscous_work": (None, [c_int, _I, c_double, c_int, _D, c_double, c_double, _PP, _PP,
+                                    _D]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -158,8 +160,10 @@ def _dims(n) -> ctypes.Array:
 
 
 def phase(ph) -> _Phase:
-    """ctypes phase record from a workloads.Phase."""
-    return _Phase(*ph.as_tuple())
+    """ctypes phase record from a workloads.Phase (the viscosity enters
+    through viscous_work, not the record)."""
+    return _Phase(ph.rho, ph.k, ph.cp, ph.cv, ph.c, ph.gamma, ph.Gamma, ph.Pi, ph.b, ph.beta,
+                  ph.q)
 
 
 # ---------------------------------------------------------------------------
@@ -563,24 +567,43 @@ def phase_pressures(p, C, kappa=None, sigma: float = 0.0):
     return p1, p2
 
 
-def energy_update(op: Operator, dt: float, C, p1, p2, T, U, E1_adv, E2_adv):
-    """Eq. (39), inviscid.  Returns (E1, E2)."""
+def viscous_work(op: Operator, C, mu, U, u) -> np.ndarray:
+    """One-fluid viscous work div(mu (grad u + grad u^T) . u) of Eq. (39)
+    per cell, mu = (mu_1, mu_2), face velocities U and cell velocities u."""
+    Us = [_f64(x) for x in U]
+    us = [_f64(x) for x in u]
+    W = np.zeros(op.N)
+    _load().orc_viscous_work(op.dim, _dims(op.n), op.h, op.axi, _d(_f64(C)), float(mu[0]),
+                             float(mu[1]), _dp(Us), _dp(us), _d(W))
+    return W
+
+
+def energy_update(op: Operator, dt: float, C, p1, p2, T, U, E1_adv, E2_adv, W=None):
+    """Eq. (39) with the one-fluid viscous work W (None: inviscid).
+    Returns (E1, E2)."""
     E1a, E2a = _f64(E1_adv), _f64(E2_adv)
     E1, E2 = np.zeros_like(E1a), np.zeros_like(E2a)
     F, _ = _fb(op)
     Us = [_f64(u) for u in U]
     _load().orc_energy_update(op.dim, _dims(op.n), op.h, dt, _d(F), op.axi, _d(_f64(C)), _d(_f64(p1)),
-                              _d(_f64(p2)), _d(_f64(T)), _dp(Us), _d(E1a), _d(E2a), _d(E1),
-                              _d(E2))
+                              _d(_f64(p2)), _d(_f64(T)), _dp(Us), _d(E1a), _d(E2a),
+                              _d(None if W is None else _f64(W)), _d(E1), _d(E2))
     return E1, E2
 
 
 def downstream(op: Operator, dt: float, p, T, C, U_star, E1_adv, E2_adv, u_star=None,
-               kappa=None, sigma: float = 0.0):
+               kappa=None, sigma: float = 0.0, mu=None):
     """The end of the step in the paper's order: velocity correction
-    (Eq. unp1), phase pressures (Eqs. 37-38), phase energies (Eq. 39).
-    Returns dict(U, u, p1, p2, E1, E2)."""
+    (Eq. unp1), phase pressures (Eqs. 37-38), phase energies (Eq. 39), the
+    latter with the viscous work of the corrected velocities when
+    mu = (mu_1, mu_2) is given (needs u_star).
+    Returns dict(U, u, p1, p2, E1, E2, W)."""
     U, u = project(op, dt, p, U_star, u_star)
     p1, p2 = phase_pressures(p, C, kappa, sigma)
-    E1, E2 = energy_update(op, dt, C, p1, p2, T, U, E1_adv, E2_adv)
-    return {"U": U, "u": u, "p1": p1, "p2": p2, "E1": E1, "E2": E2}
+    W = None
+    if mu is not None and (mu[0] > 0 or mu[1] > 0):
+        if u is None:
+            raise ValueError("the viscous work needs the cell velocities")
+        W = viscous_work(op, C, mu, U, u)
+    E1, E2 = energy_update(op, dt, C, p1, p2, T, U, E1_adv, E2_adv, W)
+    return {"U": U, "u": u, "p1": p1, "p2": p2, "E1": E1, "E2": E2, "W": W}

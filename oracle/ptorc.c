@@ -55,7 +55,9 @@
  * that the pins reject it.  Every other build uses 0 (no mistake).
  *   1: face coefficient = arithmetic instead of harmonic mean
  *   2: cell a_p = C/rho_l + (1-C)/rho_g instead of 1/(C rho_l + (1-C) rho_g)
- *   3: cell a_T = 1/(C/k_l + (1-C)/k_g) instead of C k_l + (1-C) k_g */
+ *   3: cell a_T = 1/(C/k_l + (1-C)/k_g) instead of C k_l + (1-C) k_g
+ *   4: viscous stress mu grad u instead of mu (grad u + grad u^T)
+ *   5: viscous stress without the tangential-gradient term (g_ba) */
 #ifndef ORC_PLANT
 #define ORC_PLANT 0
 #endif
@@ -967,10 +969,109 @@ void orc_phase_pressures(long N, const double *p, const double *C, const double 
  * a face is the mean of the two cells' p_i times the face velocity; on a
  * wall face the cell's own p_i (zero normal gradient, as in the solve).
  * With axi, the flux differences carry the r-z metric of the divergence. */
+/* Viscous work of Eq. (39), one-fluid, per unit volume:
+ *     W = div( mu (grad u + grad u^T) . u )
+ * for the end-of-step velocity u^{n+1}, written as the sum over the faces
+ * of a cell of the normal flux (tau . u)_a on the faces across axis a.  On
+ * the face between the cells L and R across axis a:
+ *   - velocity: the normal component is the face velocity U_a, every
+ *     other component the mean of the two cells' velocities;
+ *   - stress (Stokes' hypothesis, no bulk viscosity):
+ *       tau_aa = 2 mu_f (u_a(R) - u_a(L)) / h,
+ *       tau_ab = mu_f [ (u_b(R) - u_b(L)) / h + (g_ba(L) + g_ba(R)) / 2 ],  b != a,
+ *     g_ba(c) the centred difference of u_a along b at cell c, with the
+ *     value mirrored across a wall (zero gradient);
+ *   - mu_f: the mean of the two cells' mu_bar = C mu_1 + (1 - C) mu_2.
+ * No flux crosses a wall (no penetration, free slip).  r-z: radial faces
+ * carry the metric of axi_face, as the other fluxes.  u[b] are the cell
+ * velocities per axis, U[a] the face velocities. */
+static double cell_vel(const int *n, const double *const *u, int b, long i, long j, long k)
+{
+    return u[b][idx3(n, i, j, k)];
+}
+
+/* centred difference of u_a along b at cell (i,j,k), mirrored at walls */
+static double grad_c(const int *n, double h, const double *const *u, int a, int b,
+                     long i, long j, long k)
+{
+    long lo[3] = {i, j, k}, hi[3] = {i, j, k};
+    if (lo[b] > 0) lo[b] -= 1;
+    if (hi[b] < n[b] - 1) hi[b] += 1;
+    return (cell_vel(n, u, a, hi[0], hi[1], hi[2]) - cell_vel(n, u, a, lo[0], lo[1], lo[2]))
+           / (2.0 * h);
+}
+
+/* normal viscous work flux (tau . u)_a on the interior face between L = me - e_a and R = me */
+static double visc_flux(int dim, const int *n, double h, const double *C, double mu1,
+                        double mu2, const double *const *U, const double *const *u, int a,
+                        long i, long j, long k)
+{
+    long L[3] = {i, j, k};
+    L[a] -= 1;
+    long cL = idx3(n, L[0], L[1], L[2]), cR = idx3(n, i, j, k);
+    double muL = C[cL] * mu1 + (1.0 - C[cL]) * mu2;
+    double muR = C[cR] * mu1 + (1.0 - C[cR]) * mu2;
+    double mu_f = 0.5 * (muL + muR);
+    double flux = 0.0;
+    for (int b = 0; b < dim; b++) {
+        double ub_f, tau;
+        double duR = cell_vel(n, u, b, i, j, k), duL = cell_vel(n, u, b, L[0], L[1], L[2]);
+        if (b == a) {
+            ub_f = U[a][fidx(n, a, i, j, k)];
+#if ORC_PLANT == 4
+            tau = mu_f * (duR - duL) / h;
+#else
+            tau = 2.0 * mu_f * (duR - duL) / h;
+#endif
+        } else {
+            ub_f = 0.5 * (duL + duR);
+            double gL = grad_c(n, h, u, a, b, L[0], L[1], L[2]);
+            double gR = grad_c(n, h, u, a, b, i, j, k);
+#if ORC_PLANT == 4 || ORC_PLANT == 5
+            (void)gL;
+            (void)gR;
+            tau = mu_f * (duR - duL) / h;
+#else
+            tau = mu_f * ((duR - duL) / h + 0.5 * (gL + gR));
+#endif
+        }
+        flux += tau * ub_f;
+    }
+    return flux;
+}
+
+void orc_viscous_work(int dim, const int *n, double h, int axi, const double *C, double mu1,
+                      double mu2, const double *const *U, const double *const *u, double *W)
+{
+    for (long k = 0; k < n[2]; k++)
+        for (long j = 0; j < n[1]; j++)
+            for (long i = 0; i < n[0]; i++) {
+                long c = idx3(n, i, j, k);
+                double w = 0.0;
+                for (int a = 0; a < dim; a++) {
+                    long ii[3] = {i, j, k};
+                    double f_lo = 0.0, f_hi = 0.0;
+                    if (ii[a] > 0) f_lo = visc_flux(dim, n, h, C, mu1, mu2, U, u, a, i, j, k);
+                    if (ii[a] < n[a] - 1) {
+                        long t[3] = {i, j, k};
+                        t[a] += 1;
+                        f_hi = visc_flux(dim, n, h, C, mu1, mu2, U, u, a, t[0], t[1], t[2]);
+                    }
+                    double m_lo = 1.0, m_hi = 1.0;
+                    if (axi && a == 1) { m_lo = axi_face(j, j); m_hi = axi_face(j + 1, j); }
+                    w += (m_hi * f_hi - m_lo * f_lo) / h;
+                }
+                W[c] = w;
+            }
+}
+
+/* Phase energies of Eq. (39): pressure work, viscous work W (one-fluid,
+ * from orc_viscous_work, or NULL: inviscid) and heat flux, each phase
+ * taking its volume fraction of the one-fluid terms. */
 void orc_energy_update(int dim, const int *n, double h, double dt, const double *F, int axi,
                        const double *C, const double *p1, const double *p2, const double *T,
                        const double *const *U, const double *E1a, const double *E2a,
-                       double *E1, double *E2)
+                       const double *Wv, double *E1, double *E2)
 {
     long N = (long)n[0] * n[1] * n[2];
     for (long k = 0; k < n[2]; k++)
@@ -1008,7 +1109,8 @@ void orc_energy_update(int dim, const int *n, double h, double dt, const double 
                     w2 += (m_hi * P2hi * u_hi - m_lo * P2lo * u_lo) / h;
                     q += (m_hi * q_hi - m_lo * q_lo) / h;
                 }
-                E1[c] = E1a[c] + dt * C[c] * (-w1 + q);
-                E2[c] = E2a[c] + dt * (1.0 - C[c]) * (-w2 + q);
+                double wv = Wv ? Wv[c] : 0.0;
+                E1[c] = E1a[c] + dt * C[c] * (-w1 + wv + q);
+                E2[c] = E2a[c] + dt * (1.0 - C[c]) * (-w2 + wv + q);
             }
 }

@@ -227,3 +227,162 @@ def test_corrected_divergence_follows_eq17_and_the_solve(dim, n):
     scale = np.linalg.norm(dU) + np.linalg.norm(dstar)
     assert np.linalg.norm(dU - want) <= 1e-6 * scale
     assert np.linalg.norm(dU - dstar) > 1e-3 * scale     # the correction acts
+
+
+# ----------------------------------------------- viscous work of Eq. (39)
+# W = div(mu (grad u + grad u^T) . u) for the end-of-step velocity: closed
+# forms on linear fields (interior cells, where the discrete fluxes of a
+# linear field are exact), telescoping fluxes, second order on a smooth
+# field with free-slip walls, and planted mistakes.
+MU = (1.0e-3, 1.8e-5)          # water and air viscosities [Pa s]
+
+
+def _vel_fields(dim, n, h, fn):
+    """Cell velocities u_b = fn(b, x) and face velocities U_a = fn(a, x_face),
+    except that wall faces carry zero normal velocity (closed walls)."""
+    xc = [_coords(dim, n, h, a) for a in range(dim)]
+    u = [fn(b, xc).reshape(-1) for b in range(dim)]
+    U = []
+    for a in range(dim):
+        xf = [_coords(dim, n, h, b, faces_of=a) for b in range(dim)]
+        Ua = fn(a, xf)
+        sl = [slice(None)] * dim
+        sl[dim - 1 - a] = 0
+        Ua[tuple(sl)] = 0.0
+        sl[dim - 1 - a] = -1
+        Ua[tuple(sl)] = 0.0
+        U.append(Ua.reshape(-1))
+    return U, u
+
+
+def _interior(dim, n, depth):
+    """Mask of cells at least `depth` cells from every wall."""
+    m = np.ones(tuple(n[dim - 1 - b] for b in range(dim)), bool)
+    for a in range(dim):
+        sl = [slice(None)] * dim
+        ax = dim - 1 - a
+        idx = np.arange(n[a])
+        keep = (idx >= depth) & (idx < n[a] - depth)
+        shp = [1] * dim
+        shp[ax] = n[a]
+        m &= keep.reshape(shp)
+    return m.reshape(-1)
+
+
+def _mix(C):
+    return C * MU[0] + (1 - C) * MU[1]
+
+
+@pytest.mark.parametrize("dim,n", [(2, (10, 9, 1)), (3, (7, 8, 6))])
+@pytest.mark.parametrize("c", [1.0, 0.35])
+def test_viscous_simple_shear(dim, n, c):
+    """u = (gamma y, 0, 0): the stress is mu gamma on the shear faces and
+    div(tau . u) = mu gamma^2 in every cell off the walls."""
+    h, g = 0.2, 3.0
+    op = _op(dim, n, h, 1.0, 1.0)
+    C = np.full(op.N, c)
+    U, u = _vel_fields(dim, n, h, lambda b, x: g * x[1] if b == 0 else 0.0 * x[0])
+    Wv = orc.viscous_work(op, C, MU, U, u)
+    inner = _interior(dim, n, 1)
+    np.testing.assert_allclose(Wv[inner], _mix(c) * g * g, rtol=1e-12)
+
+
+@pytest.mark.parametrize("dim,n", [(2, (10, 9, 1)), (3, (7, 8, 6))])
+def test_viscous_planar_extension(dim, n):
+    """u = eps (x, -y) in 2-D: tau = 2 mu eps diag(1, -1), div(tau . u) =
+    4 mu eps^2; in 3-D u = eps (x, y, -2z): 12 mu eps^2, off the walls."""
+    h, e = 0.2, 0.7
+    op = _op(dim, n, h, 1.0, 1.0)
+    C = np.full(op.N, 0.6)
+    coef = (1.0, -1.0) if dim == 2 else (1.0, 1.0, -2.0)
+    U, u = _vel_fields(dim, n, h, lambda b, x: e * coef[b] * x[b])
+    Wv = orc.viscous_work(op, C, MU, U, u)
+    inner = _interior(dim, n, 1)
+    expect = (4.0 if dim == 2 else 12.0) * _mix(0.6) * e * e
+    np.testing.assert_allclose(Wv[inner], expect, rtol=1e-12)
+
+
+@pytest.mark.parametrize("dim,n", [(2, (10, 9, 1)), (3, (7, 8, 6))])
+def test_viscous_rigid_translation_is_zero(dim, n):
+    h = 0.2
+    op = _op(dim, n, h, 1.0, 1.0)
+    rng = np.random.default_rng(3)
+    C = rng.uniform(0, 1, op.N)
+    vel = [2.0, -1.5, 0.5][:dim]
+    U, u = _vel_fields(dim, n, h, lambda b, x: vel[b] + 0.0 * x[0])
+    assert np.abs(orc.viscous_work(op, C, MU, U, u)).max() == 0.0
+
+
+@pytest.mark.parametrize("dim,n,axi", [(2, (10, 9, 1), 0), (3, (7, 8, 6), 0), (2, (10, 9, 1), 1)])
+def test_viscous_fluxes_telescope(dim, n, axi):
+    """Random velocities and fractions, closed walls: the face fluxes cancel
+    in pairs, so the volume integral of the viscous work is zero (r-z: with
+    the cell volumes proportional to the radius)."""
+    h = 0.2
+    op = _op(dim, n, h, 1.0, 1.0)
+    op = orc.Operator(op.dim, op.n, op.h, op.F, op.B, axi=axi)
+    rng = np.random.default_rng(4)
+    C = rng.uniform(0, 1, op.N)
+    U, u = _vel_fields(dim, n, h, lambda b, x: rng.standard_normal(x[0].shape))
+    Wv = orc.viscous_work(op, C, MU, U, u)
+    vol = np.ones(op.N)
+    if axi:
+        vol = np.repeat(np.arange(n[1]) + 0.5, n[0])
+    scale = np.abs(Wv * vol).sum()
+    assert scale > 0 and abs((Wv * vol).sum()) <= 1e-13 * scale
+
+
+def _smooth_case(n, plant=None):
+    """u = (a sin(pi x) cos(pi y), b cos(pi x) sin(pi y)) on the unit square
+    (free slip on every wall), uniform mu: error of W against the analytic
+    div(mu (grad u + grad u^T) . u) on the cells two or more from a wall."""
+    a, b = 1.0, 0.4
+    h = 1.0 / n
+    op = _op(2, (n, n, 1), h, 1.0, 1.0)
+    C = np.ones(op.N)
+    pi = np.pi
+
+    def f(comp, x):
+        X, Y = x[0], x[1]
+        if comp == 0:
+            return a * np.sin(pi * X) * np.cos(pi * Y)
+        return b * np.cos(pi * X) * np.sin(pi * Y)
+
+    U, u = _vel_fields(2, (n, n, 1), h, f)
+    Wv = orc.viscous_work(op, C, MU, U, u)
+    X, Y = _coords(2, (n, n, 1), h, 0).reshape(-1), _coords(2, (n, n, 1), h, 1).reshape(-1)
+    # analytic: tau_xx = 2 mu u_x, tau_yy = 2 mu v_y, tau_xy = mu (u_y + v_x);
+    # W = d/dx(tau_xx u + tau_xy v) + d/dy(tau_xy u + tau_yy v)
+    s, c = np.sin, np.cos
+    u_ = a * s(pi * X) * c(pi * Y); v_ = b * c(pi * X) * s(pi * Y)
+    ux = a * pi * c(pi * X) * c(pi * Y); uy = -a * pi * s(pi * X) * s(pi * Y)
+    vx = -b * pi * s(pi * X) * s(pi * Y); vy = b * pi * c(pi * X) * c(pi * Y)
+    uxx = -a * pi * pi * s(pi * X) * c(pi * Y); uyy = -a * pi * pi * s(pi * X) * c(pi * Y)
+    uxy = -a * pi * pi * c(pi * X) * s(pi * Y)
+    vxx = -b * pi * pi * c(pi * X) * s(pi * Y); vyy = -b * pi * pi * c(pi * X) * s(pi * Y)
+    vxy = -b * pi * pi * s(pi * X) * c(pi * Y)
+    mu = MU[0]
+    txx, tyy, txy = 2 * mu * ux, 2 * mu * vy, mu * (uy + vx)
+    dtxx_dx, dtyy_dy = 2 * mu * uxx, 2 * mu * vyy
+    dtxy_dx, dtxy_dy = mu * (uxy + vxx), mu * (uyy + vxy)
+    W_exact = (dtxx_dx * u_ + txx * ux + dtxy_dx * v_ + txy * vx
+               + dtxy_dy * u_ + txy * uy + dtyy_dy * v_ + tyy * vy)
+    inner = _interior(2, (n, n, 1), 2)
+    return np.abs(Wv - W_exact)[inner].max() / np.abs(W_exact).max()
+
+
+def test_viscous_second_order():
+    errs = [_smooth_case(n) for n in (16, 32, 64)]
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert 3.5 < r1 < 4.6 and 3.5 < r2 < 4.6, errs
+
+
+def test_viscous_pins_reject_planted_mistakes():
+    """grad u alone, or the stress without its tangential-gradient term,
+    fail the closed forms or the convergence pin."""
+    with orc.planted(4):       # mu grad u instead of mu (grad u + grad u^T)
+        with pytest.raises(AssertionError):
+            test_viscous_planar_extension(2, (10, 9, 1))
+    with orc.planted(5):       # no tangential-gradient term in tau_ab
+        assert _smooth_case(32) > 0.05
+    assert _smooth_case(32) < 0.02

@@ -49,10 +49,11 @@ class Phase:
     b: float
     beta: float = 0.0
     q: float = 0.0          # NASG energy offset of Eq. (9) (state mode)
+    mu: float = 0.0         # dynamic viscosity (viscous work of Eq. 39)
 
     def as_tuple(self) -> Tuple[float, ...]:
         return (self.rho, self.k, self.cp, self.cv, self.c, self.gamma,
-                self.Gamma, self.Pi, self.b, self.beta, self.q)
+                self.Gamma, self.Pi, self.b, self.beta, self.q, self.mu)
 
 
 LIQUID = Phase(rho=1000.0, k=0.6, cp=4000.0, cv=3610.0, c=1500.0,
@@ -68,6 +69,11 @@ LIQUID_NASG = Phase(rho=1055.9, k=0.6, cp=4285.0, cv=3610.0, c=1500.0,
                     q=-1177788.0)
 GAS_IDEAL = Phase(rho=1.2, k=0.6 / 23.0, cp=1000.0, cv=1000.0 / 1.4, c=340.0,
                   gamma=1.4, Gamma=1.4, Pi=0.0, b=0.0)
+
+# Dynamic viscosities [Pa s] of water and air near 293 K, for the viscous
+# work of the phase energies (Eq. 39) in the state-mode workloads.
+MU_WATER = 1.0e-3
+MU_AIR = 1.8e-5
 
 # Reference conserved state of the state-mode workloads: phase densities
 # and specific internal energies near (1 atm, 293 K) for the two records
@@ -318,7 +324,7 @@ def state_problem(name: str, dim: int, n: Sequence[int],
                   centres_unit: Sequence[Sequence[float]], radii_unit: Sequence[float],
                   gas_atm: int = 1, u_amp: float = 1.0, seed: int = 12,
                   div_amp: float = 1e-6, precision: str = "fp64",
-                  rtol: float = 1e-9) -> Problem:
+                  rtol: float = 1e-9, viscous: bool = True) -> Problem:
     """Bubbles in liquid given by advected conserved variables (Sec. 3):
     C from the bubble geometry; phase masses m1 = C rho_l, m2 = (1-C) rho_g
     and total energy E = C rho_l e_l + (1-C) rho_g e_g + 1/2 rho |u|^2
@@ -330,7 +336,7 @@ def state_problem(name: str, dim: int, n: Sequence[int],
     noise of amplitude div_amp h/dt on the interior faces (so that div u* has
     a rough part of order div_amp/dt); u* at the cell centres = u; the
     curvature of the first bubble in the cut cells, water's surface
-    tension."""
+    tension; water's and air's viscosities (none if not viscous)."""
     nn = _grid(dim, n)
     h = L_UNIT / nn[0]
     centres = [[L_UNIT * v for v in c] for c in centres_unit]
@@ -358,8 +364,10 @@ def state_problem(name: str, dim: int, n: Sequence[int],
     E = E1 + E2
     dt = acoustic_dt(h)
     uf = face_velocities(dim, nn, seed + 10, u_amp, div_amp * h / dt)
+    liquid = dataclasses.replace(LIQUID_NASG, mu=MU_WATER if viscous else 0.0)
+    gas = dataclasses.replace(GAS_IDEAL, mu=MU_AIR if viscous else 0.0)
     return Problem(name=name, dim=dim, n=nn, h=h, mode="state", C=C,
-                   liquid=LIQUID_NASG, gas=GAS_IDEAL, dt=dt, div_ustar=None,
+                   liquid=liquid, gas=gas, dt=dt, div_ustar=None,
                    rtol=rtol, precision=precision, m1=np.ascontiguousarray(m1),
                    m2=np.ascontiguousarray(m2), E=np.ascontiguousarray(E), mom=mom,
                    uf_star=uf, uc_star=[np.ascontiguousarray(u) for u in us],
