@@ -192,7 +192,8 @@ def cpu_baseline(prob, rtol, budget_s):
                                        pin_mean=prob.mean_constraint)
         if prob.uf_star is not None:
             orc.downstream(op, prob.dt, p, T, prob.C, prob.uf_star, prob.E1, prob.E2,
-                           prob.uc_star, prob.kappa, prob.sigma)
+                           prob.uc_star, prob.kappa, prob.sigma,
+                           mu=(prob.liquid.mu, prob.gas.mu))
         done = max_cycles if cyc < 0 else cyc
         return time.perf_counter() - t, oracle_updates(orc, prob, done), done
 
@@ -228,9 +229,11 @@ def _make_serve_request(rid):
 def serve_bench(args):
     """The serving mix: Poisson arrivals at `rate`/s of requests drawn
     from a pool of distinct seeded requests (2-D 128^2..2048^2 and 3-D
-    64^3..192^3, 1-4 bubbles, mixed precision), through the continuous-
-    batching engine.  Reports solves/s and p50/p99 latency (arrival to
-    result ready) over the arrivals after the warm-up."""
+    64^3..192^3, 1-4 bubbles, mixed precision to 1e-9) whose inputs are
+    resident on the device, through the continuous-batching engine.
+    Reports solves/s and p50/p99 latency (arrival to result ready) over the
+    arrivals after the warm-up: one JSON line for the open-loop run at
+    --serve-rate, then (--serve-sweep) one per rate of a saturation sweep."""
     import multiprocessing as mp
 
     import numpy as np
@@ -250,74 +253,92 @@ def serve_bench(args):
         p = torch.empty(pr.ncells, dtype=torch.float64, device="cuda")
         entries.append({"prob": pr, "s": s, "t": t, "p": p, "T": torch.empty_like(p),
                         "busy": None})
+    del probs
     torch.cuda.synchronize()
-    srv = serve.Server(hbm_budget=int(args.serve_budget_gb * (1 << 30)),
-                       max_active=args.serve_slots, use_graphs=False)
-    arrivals = W.poisson_arrivals(args.serve_rate, args.serve_seconds, seed=4)
     rtol = args.rtol if args.rtol is not None else 1e-9
-    t0 = serve.now() + 0.05
-    submitted = []   # (rid, arrival time, entry index)
-    nxt = 0
-    for k, ta in enumerate(arrivals):
-        srv.progress(t0 + ta)
-        for e in entries:   # release entries whose request finished
-            if e["busy"] is not None and srv.request(e["busy"])["status"] not in (-2, -3):
-                e["busy"] = None
-        # the next free pool entry (outputs of an entry are in use while busy)
-        for _ in range(pool_n):
-            e = entries[nxt % pool_n]
-            nxt += 1
-            if e["busy"] is None:
-                break
-        else:
-            srv.progress(float("inf"))
+
+    def window(rate, seconds, warmup):
+        srv = serve.Server(hbm_budget=int(args.serve_budget_gb * (1 << 30)),
+                           max_active=args.serve_slots, use_graphs=False)
+        arrivals = W.poisson_arrivals(rate, seconds, seed=4)
+        t0 = serve.now() + 0.05
+        submitted = []   # (rid, arrival time, problem)
+        busy = []        # entries whose outputs are in use
+        nxt = 0
+        for ta in arrivals:
+            srv.progress(t0 + ta)
+            still = []
+            for e in busy:   # release entries whose request finished
+                if srv.request(e["busy"])["status"] in (-2, -3):
+                    still.append(e)
+                else:
+                    e["busy"] = None
+            busy = still
+            # the next free pool entry (outputs of an entry are in use while busy)
+            for _ in range(pool_n):
+                e = entries[nxt % pool_n]
+                nxt += 1
+                if e["busy"] is None:
+                    break
+            else:
+                srv.progress(float("inf"))
+                for b in busy:
+                    b["busy"] = None
+                busy = []
+            rid = srv.submit(e["s"], ptmg.PT_PREC_MIXED, e["p"], e["T"], div=e["t"].get("div"),
+                             rtol=rtol, t_arrival=t0 + ta, keepalive=e["t"])
+            e["busy"] = rid
+            busy.append(e)
+            submitted.append((rid, ta, e["prob"]))
+        srv.run_until_idle()
+        torch.cuda.synchronize()
+        for e in busy:
             e["busy"] = None
-        rid = srv.submit(e["s"], ptmg.PT_PREC_MIXED, e["p"], e["T"], div=e["t"].get("div"),
-                         rtol=rtol, t_arrival=t0 + ta, keepalive=e["t"])
-        e["busy"] = rid
-        submitted.append((rid, ta, e["prob"]))
-    srv.run_until_idle()
-    torch.cuda.synchronize()
-    lat, done_t, cycles, cells, status = [], [], [], [], []
-    for rid, ta, pr in submitted:
-        info = srv.request(rid)
-        status.append(info["status"])
-        if ta < args.serve_warmup:
-            continue
-        lat.append(info["t_done"] - info["t_arrival"])
-        done_t.append(info["t_done"] - t0)
-        cycles.append(info["cycles"])
-        cells.append(pr.ncells)
-    srv.destroy()
-    lat = np.array(lat)
-    window = max(done_t) - args.serve_warmup
-    out = {
-        "metric": "coupled p-T solves/s at p99 latency (serving mix)",
-        "value": len(lat) / window,
-        "unit": "solves/s",
-        "n_gpus": 1,
-        "steps": len(lat),
-        "warmup": int(sum(1 for _, ta, _ in submitted if ta < args.serve_warmup)),
-        "ms_per_step": 1e3 * float(np.mean(lat)),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32+f64",
-        "data": "synthetic",
-        "config": {"workload": "serving_mix", "rate_per_s": args.serve_rate,
-                   "seconds": args.serve_seconds, "pool": pool_n, "slots": args.serve_slots,
-                   "hbm_budget_gb": args.serve_budget_gb, "rtol": rtol,
-                   "sizes_2d": [W.SERVE_SIZES_2D[0], W.SERVE_SIZES_2D[-1]],
-                   "sizes_3d": [W.SERVE_SIZES_3D[0], W.SERVE_SIZES_3D[-1]]},
-        "latency_ms": {"p50": 1e3 * float(np.percentile(lat, 50)),
-                       "p90": 1e3 * float(np.percentile(lat, 90)),
-                       "p99": 1e3 * float(np.percentile(lat, 99)),
-                       "max": 1e3 * float(lat.max())},
-        "mean_cycles": float(np.mean(cycles)),
-        "mean_cells": float(np.mean(cells)),
-        "failed": int(sum(1 for s in status if s != 0)),
-    }
-    print(json.dumps(out), flush=True)
+        lat, done_t, cycles, cells, status = [], [], [], [], []
+        for rid, ta, pr in submitted:
+            info = srv.request(rid)
+            status.append(info["status"])
+            if ta < warmup:
+                continue
+            lat.append(info["t_done"] - info["t_arrival"])
+            done_t.append(info["t_done"] - t0)
+            cycles.append(info["cycles"])
+            cells.append(pr.ncells)
+        srv.destroy()
+        lat = np.array(lat)
+        span = max(done_t) - warmup
+        return {
+            "metric": "coupled p-T solves/s at p99 latency (serving mix)",
+            "value": len(lat) / span,
+            "unit": "solves/s",
+            "n_gpus": 1,
+            "steps": len(lat),
+            "warmup": int(sum(1 for _, ta, _ in submitted if ta < warmup)),
+            "ms_per_step": 1e3 * float(np.mean(lat)),
+            "higher_is_better": True,
+            "scaling": "weak",
+            "vs_baseline": None,
+            "dtype": "f32+f64",
+            "data": "synthetic",
+            "config": {"workload": "serving_mix", "rate_per_s": rate,
+                       "seconds": seconds, "warmup_s": warmup, "pool": pool_n,
+                       "slots": args.serve_slots, "hbm_budget_gb": args.serve_budget_gb,
+                       "rtol": rtol,
+                       "sizes_2d": [W.SERVE_SIZES_2D[0], W.SERVE_SIZES_2D[-1]],
+                       "sizes_3d": [W.SERVE_SIZES_3D[0], W.SERVE_SIZES_3D[-1]]},
+            "latency_ms": {"p50": 1e3 * float(np.percentile(lat, 50)),
+                           "p90": 1e3 * float(np.percentile(lat, 90)),
+                           "p99": 1e3 * float(np.percentile(lat, 99)),
+                           "max": 1e3 * float(lat.max())},
+            "mean_cycles": float(np.mean(cycles)),
+            "mean_cells": float(np.mean(cells)),
+            "failed": int(sum(1 for s_ in status if s_ != 0)),
+        }
+
+    print(json.dumps(window(args.serve_rate, args.serve_seconds, args.serve_warmup)),
+          flush=True)
+    for rate in ([float(r) for r in args.serve_sweep.split(",")] if args.serve_sweep else []):
+        print(json.dumps(window(rate, args.serve_sweep_seconds, 5.0)), flush=True)
 
 
 def stream_probe():
@@ -409,9 +430,14 @@ def main():
     ap.add_argument("--serve", action="store_true", help="the serving mix instead of a workload")
     ap.add_argument("--stream-probe", action="store_true", help="copy bandwidth, then exit")
     ap.add_argument("--serve-rate", type=float, default=50.0)
-    ap.add_argument("--serve-seconds", type=float, default=40.0)
-    ap.add_argument("--serve-warmup", type=float, default=5.0)
-    ap.add_argument("--serve-pool", type=int, default=48)
+    ap.add_argument("--serve-seconds", type=float, default=130.0,
+                    help="open-loop run length, warm-up included")
+    ap.add_argument("--serve-warmup", type=float, default=10.0)
+    ap.add_argument("--serve-pool", type=int, default=256,
+                    help="distinct seeded requests resident on the device")
+    ap.add_argument("--serve-sweep", default="",
+                    help="comma-separated arrival rates of a saturation sweep after the run")
+    ap.add_argument("--serve-sweep-seconds", type=float, default=35.0)
     ap.add_argument("--serve-slots", type=int, default=8)
     ap.add_argument("--serve-budget-gb", type=float, default=64.0)
     args = ap.parse_args()

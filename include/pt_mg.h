@@ -78,10 +78,12 @@ typedef enum { PT_PREC_FP64 = 0, PT_PREC_MIXED = 1 } pt_precision;
  * cell's (p_adv, T_adv); an ideal gas has Gamma = gamma, Pi = b = 0, which
  * gives 1/T.  gamma = c_p/c_v and the sound speed c enter l3 (Eq. 31).
  * q is the energy offset of the NASG EoS (Eq. 9), used by pt_state_eval.
+ * mu is the dynamic viscosity (Pa s) of the viscous work in the phase
+ * energies of Eq. (39) (pt_mg_downstream); 0 for an inviscid phase.
  * In PT_COEF_STATE mode rho and c are not used: each cell's phase density
  * comes from its conserved variables and the sound speed from Eq. (11). */
 typedef struct {
-    double rho, k, cp, cv, c, gamma, Gamma, Pi, b, beta, q;
+    double rho, k, cp, cv, c, gamma, Gamma, Pi, b, beta, q, mu;
 } pt_phase;
 
 /* Problem description.  Unused fields are ignored; arrays are device
@@ -310,17 +312,26 @@ typedef struct {
  *  - Cells: u = u* - dt g, g along each axis the mean of a_f (p_R - p_L)/h
  *    on the cell's two faces across that axis (0 on a wall face).
  *  - p_1 = p + (1 - C) sigma kappa, p_2 = p - C sigma kappa.
- *  - E_i = E_i^adv + dt C_i [ -div(p_i U) + div(k grad T) ], C_1 = C,
+ *  - E_i = E_i^adv + dt C_i [ -div(p_i U) + W + div(k grad T) ], C_1 = C,
  *    C_2 = 1 - C; the pressure-work flux on a face is the mean of the two
  *    cells' p_i times U (on a wall face the cell's own p_i); the heat flux
  *    is k_f (T_R - T_L)/h with the T face coefficient of the assembly, zero
- *    through the walls.  The viscous work of Eq. (39) is not included
- *    (inviscid flow).
- * dt, h, 1/rho and k are those of the last pt_mg_setup / pt_mg_update
- * (PT_COEF_PHASES or PT_COEF_STATE; PT_ERR_STATE otherwise).  Returns when
- * the outputs are written.  PT_ERR_ARG for a NULL p, T, C, U_star[a] or
- * U[a] (a < dim), U[a] == U_star[a], only one of u_star / u given for an
- * axis, or exactly one of E1_adv, E2_adv, E1, E2 missing. */
+ *    through the walls.
+ *  - W = div(mu (grad u + grad u^T) . u), the viscous work of Eq. (39) for
+ *    the corrected velocities, when a phase has mu > 0 (needs u_star and u):
+ *    the flux through the face between cells L and R across axis a is
+ *    sum_b tau_ab u_b with u_a the face velocity U and u_b (b != a) the mean
+ *    of the two cells' u_b; tau_aa = 2 mu_f (u_a,R - u_a,L)/h and tau_ab =
+ *    mu_f ((u_b,R - u_b,L)/h + the mean over L, R of the centred difference
+ *    of u_a along b, mirrored at a wall); mu_f the mean of the two cells'
+ *    C mu_1 + (1 - C) mu_2; no flux through the walls.  It runs as a
+ *    second pass over the grid.
+ * dt, h, 1/rho, k and the viscosities are those of the last pt_mg_setup /
+ * pt_mg_update (PT_COEF_PHASES or PT_COEF_STATE; PT_ERR_STATE otherwise).
+ * Returns when the outputs are written.  PT_ERR_ARG for a NULL p, T, C,
+ * U_star[a] or U[a] (a < dim), U[a] == U_star[a], only one of u_star / u
+ * given for an axis, exactly one of E1_adv, E2_adv, E1, E2 missing, or a
+ * viscous phase without cell velocities. */
 int pt_mg_downstream(pt_mg_t h, const pt_downstream *d);
 
 void pt_mg_destroy(pt_mg_t h);

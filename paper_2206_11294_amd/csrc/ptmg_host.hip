@@ -465,23 +465,37 @@ bool half_level(pt_mg_t h, int l, int nu1, int nu2)
            nu2 >= 1 && nu2 <= 2;
 }
 
-template <typename R> void smooth(pt_mg_t h, int l, int sweeps, bool zero_guess)
+// 3-D finest level in FP32: the last pre-smoothing sweep also forms the
+// residual and restricts it to level 1 (one pass instead of two).
+bool fused_restrict3(pt_mg_t h, int l, int nu1)
+{
+    return h->use_fused && h->P.dim == 3 && l == 0 && h->P.prec == PT_PREC_MIXED &&
+           h->P.nlev > 1 && nu1 >= 1;
+}
+
+// `sweeps` sweeps on level l; with res (fused_restrict3) the last one also
+// writes the restricted residual into level l+1's right-hand side.
+template <typename R> void smooth(pt_mg_t h, int l, int sweeps, bool zero_guess, bool res = false)
 {
     if (fused_level(h, l)) {
         // fused red-black sweeps (one pass over memory each), ping-ponging
         // the iterate between the level's two buffers
         const double Rb = sizeof(R);
         for (int s = 0; s < sweeps; s++) {
-            const bool zg = zero_guess && s == 0;
+            const bool zg = zero_guess && s == 0, r = res && s == sweeps - 1;
             Lvl<R> L = h->level<R>(l);
             h->u_cur ^= 1u << l;
             typename VT<R>::v2 *uo = h->level<R>(l).u;
             const double coef = (l == 0 ? 2 : 2 * h->P.dim) * Rb;   // cell or face coefficients
-            const double nb = (double)L.N * ((zg ? 0 : 2 * Rb) + 2 * Rb + coef + 4 * Rb + 2 * Rb);
+            double nb = (double)L.N * ((zg ? 0 : 2 * Rb) + 2 * Rb + coef + 4 * Rb + 2 * Rb);
+            if (r) nb += (double)h->P.lv[l + 1].N * 2 * Rb;            // coarse f written
             h->begin(l == 0 ? PT_K_SMOOTH_FINE : PT_K_SMOOTH_COARSE, nb, s == 0);
-            launch_rb_fused<R>(h->P.dim, L, uo, zg ? 1 : 0, l == 0 ? 0 : 1, h->stream);
+            if (r)
+                launch_rb_fused3r<R>(L, h->level<R>(l + 1), uo, zg ? 1 : 0, h->stream);
+            else
+                launch_rb_fused<R>(h->P.dim, L, uo, zg ? 1 : 0, l == 0 ? 0 : 1, h->stream);
             h->end(s == sweeps - 1);
-            h->updates += L.N;
+            h->updates += L.N * (r ? 2 : 1);
         }
         return;
     }
@@ -703,8 +717,9 @@ template <typename R> void vcycle(pt_mg_t h, int l, int nu1, int nu2)
         launch_zero(L.u, (size_t)L.N * 2 * sizeof(R), h->stream);
         h->end();
     }
-    smooth<R>(h, l, nu1, true);
-    restrict_level<R>(h, l);
+    const bool res = fused_restrict3(h, l, nu1);
+    smooth<R>(h, l, nu1, true, res);
+    if (!res) restrict_level<R>(h, l);
     if (l == 0) coarse_cycle<R>(h, coarse_nu1(h, nu1), coarse_nu2(h, nu2));
     else vcycle<R>(h, l + 1, nu1, nu2);
     prolong_level<R>(h, l);
@@ -1183,6 +1198,10 @@ int pt_mg_downstream(pt_mg_t h, const pt_downstream *d)
     const int ne = (d->E1_adv != nullptr) + (d->E2_adv != nullptr) + (d->E1 != nullptr) +
                    (d->E2 != nullptr);
     if (ne != 0 && ne != 4) return fail(h, PT_ERR_ARG, "energy update needs E1_adv, E2_adv, E1, E2");
+    const double mu1 = h->prob.liquid.mu, mu2 = h->prob.gas.mu;
+    const bool viscous = ne && (mu1 != 0.0 || mu2 != 0.0);
+    if (viscous && !ncell)
+        return fail(h, PT_ERR_ARG, "the viscous work needs the cell velocities u_star and u");
     DownArgs a = {};
     a.nx = P.n[0];
     a.ny = P.n[1];
@@ -1228,8 +1247,32 @@ int pt_mg_downstream(pt_mg_t h, const pt_downstream *d)
     if (d->kappa) bytes += 8.0 * N;
     if (ncell) bytes += 16.0 * dim * N;
     if (ne) bytes += 32.0 * N;
+    // the viscous pass: C, u, U read, E1 and E2 read and written
+    if (viscous) bytes += 8.0 * (N + dim * N + faces + 4.0 * N);
     h->begin(PT_K_DOWNSTREAM, bytes);
     launch_downstream(dim, a, h->stream);
+    if (viscous) {
+        // second pass: needs the corrected velocities of the neighbours
+        ViscArgs v = {};
+        v.nx = a.nx;
+        v.ny = a.ny;
+        v.nz = a.nz;
+        v.inv_h = a.inv_h;
+        v.dt = a.dt;
+        v.mu1 = mu1;
+        v.mu2 = mu2;
+        v.C = d->C;
+        v.Ux = d->U[0];
+        v.Uy = d->U[1];
+        v.Uz = dim == 3 ? d->U[2] : nullptr;
+        v.ux = d->u[0];
+        v.uy = d->u[1];
+        v.uz = dim == 3 ? d->u[2] : nullptr;
+        v.axm = h->axm64();
+        v.E1 = d->E1;
+        v.E2 = d->E2;
+        launch_viscous(dim, v, h->stream);
+    }
     h->end();
     return sync(h, "downstream");
 }

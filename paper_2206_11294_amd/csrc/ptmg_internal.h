@@ -142,6 +142,19 @@ struct DownArgs {
     const double4 *axm;                // r-z metric per row (2-D) or null
 };
 void launch_downstream(int dim, const DownArgs &a, hipStream_t s);
+// Viscous work of Eq. (39) added to the phase energies E1, E2 in place,
+// from the end-of-step face velocities U and cell velocities u (every axis
+// < dim non-null).
+struct ViscArgs {
+    int nx, ny, nz;
+    double inv_h, dt, mu1, mu2;
+    const double *C;
+    const double *Ux, *Uy, *Uz;        // face velocities
+    const double *ux, *uy, *uz;        // cell velocities
+    const double4 *axm;                // r-z metric per row (2-D) or null
+    double *E1, *E2;
+};
+void launch_viscous(int dim, const ViscArgs &a, hipStream_t s);
 // div = sum over axes of (U upper face - U lower face) * inv_h.
 void launch_divergence(int dim, int nx, int ny, int nz, double inv_h, const double *Ux,
                        const double *Uy, const double *Uz, const double4 *axm, double *div,
@@ -182,6 +195,11 @@ void launch_half2(bool up, int nu, const Lvl<R> &L, const Lvl<R> &C, typename VT
 template <typename R>
 void launch_rb_fused(int dim, const Lvl<R> &L, typename VT<R>::v2 *uo, int zero_guess, int faces,
                      hipStream_t s);
+// 3-D finest level, FP32: one sweep with the residual restricted into C.f
+// (the last pre-smoothing sweep); a no-op for FP64 (LDS-bound).
+template <typename R>
+void launch_rb_fused3r(const Lvl<R> &L, const Lvl<R> &C, typename VT<R>::v2 *uo, int zero_guess,
+                       hipStream_t s);
 template <typename R>
 void launch_restrict(int dim, int level0, const Lvl<R> &F, const Lvl<R> &C, hipStream_t s);
 template <typename R>

@@ -19,14 +19,28 @@
 namespace ptmg {
 
 // ---------------------------------------------------------------- helpers
-// Quotient of the smoother and transfer arithmetic: correctly rounded in
-// FP64; in FP32 (the mixed-precision V-cycle, a preconditioner under FP64
-// refinement) the hardware reciprocal (1 ulp) times the numerator, a
-// third of the instructions of a rounded division.
-template <typename R> __device__ __forceinline__ R quot(R a, R b) { return a / b; }
+// Quotient of the V-cycle arithmetic (smoothers, transfers, coarse
+// operators): the V-cycle approximates the correction and the FP64 outer
+// residual decides the answer, so its quotients need not be correctly
+// rounded.  FP32: the hardware reciprocal (1 ulp) times the numerator.
+// FP64: the hardware reciprocal seed refined by two Newton steps
+// (x <- x + x (1 - b x); the relative error squares at each step), times
+// the numerator: half the instructions of a rounded division, which bounds
+// the FP64 sweeps.  The outer residual and the end-of-step pass divide
+// exactly (harm_exact).
+template <typename R> __device__ __forceinline__ R quot(R a, R b);
 template <> __device__ __forceinline__ float quot<float>(float a, float b)
 {
     return a * __builtin_amdgcn_rcpf(b);
+}
+template <> __device__ __forceinline__ double quot<double>(double a, double b)
+{
+    double x = __builtin_amdgcn_rcp(b);
+    double e = __builtin_fma(-b, x, 1.0);
+    x = __builtin_fma(x, e, x);
+    e = __builtin_fma(-b, x, 1.0);
+    x = __builtin_fma(x, e, x);
+    return a * x;
 }
 
 // Fused multiply-add written out, where two kernels must round alike
@@ -48,6 +62,18 @@ __device__ __forceinline__ V2 harm2(V2 a, V2 b)
     o.x = harm(a.x, b.x);
     o.y = harm(a.y, b.y);
     return o;
+}
+
+// The harmonic mean with a correctly rounded division (FP64 operator of
+// record: outer residual, end of the step).
+__device__ __forceinline__ double harm_exact(double a, double b)
+{
+    const double s = a + b;
+    return s > 0.0 ? 2.0 * a * b / s : 0.0;
+}
+__device__ __forceinline__ double2 harm2_exact(double2 a, double2 b)
+{
+    return make_double2(harm_exact(a.x, b.x), harm_exact(a.y, b.y));
 }
 
 // Block-to-work mapping that is XCD-aware: the hardware deals
@@ -1429,6 +1455,548 @@ __global__ __launch_bounds__(TX *TY) void k_rb_fused3(Lvl<R> L, typename VT<R>::
     write_plane(z1 - 1);
 }
 
+// The finest 3-D sweep with every harmonic face coefficient computed once.
+// Same walk as k_rb_fused3 (cell coefficients, a ring of two cells, red on
+// plane k+1 over the tile and a ring of one, black on plane k over the
+// tile), but the threads own columns: the thread that updates black at
+// (x, y, k) also updates red at (x, y, k+1), one step earlier red at
+// (x, y, k-1), so the two z faces of its black cell are faces its own red
+// updates computed (kept in registers), and the red update writes its four
+// in-plane faces to LDS (two plane slots), where the black update reads
+// them.  Every face borders one red and one black cell, so a red-black
+// sweep evaluates each face once (ring cells aside) instead of once per
+// colour; the harmonic mean is symmetric in its arguments bit for bit, so
+// the black update sums the same values in the same order.  Black no longer
+// reads the cell coefficients, which then need three plane slots instead of
+// five.  Threads BW*TY onwards take the red cells of the ring.
+template <typename R, int TX, int TY, bool ZG>
+__global__ __launch_bounds__(TX *TY) void k_rb_fused3c(Lvl<R> L, typename VT<R>::v2 *__restrict__ uo,
+                                                       int zc, int tiles_x, int tiles_y, int ntiles)
+{
+    using V2 = typename VT<R>::v2;
+    using V4 = typename VT<R>::v4;
+    constexpr int NT = TX * TY;
+    constexpr int PX = TX + 4, PY = TY + 4, PS = PX * PY;
+    constexpr int NLD = (PS + NT - 1) / NT;
+    constexpr int BW = TX / 2;                  // black cells per tile row
+    constexpr int NCOL = BW * TY;               // column-owning threads
+    constexpr int NRING = TX + TY + 2;          // red cells of the ring, per plane
+    static_assert(NCOL + NRING <= NT && TX % 2 == 0 && TY % 2 == 0, "thread mapping");
+    __shared__ V2 su[5][PS];
+    __shared__ V2 sa[3][PS];
+    __shared__ V2 sfx[2][PS], sfy[2][PS];       // lower x / y face of each cell
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    if (tile >= ntiles) return;
+    const int txi = tile % tiles_x;
+    const int rr = tile / tiles_x;
+    const int tyi = rr % tiles_y;
+    const int tzi = rr / tiles_y;
+    const int x0 = txi * TX, y0 = tyi * TY;
+    const int z0 = tzi * zc, z1 = min(z0 + zc, L.nz);
+    const R ih2 = (R)L.inv_h2;
+    const long long nxy = (long long)L.nx * L.ny;
+    const int t = threadIdx.x;
+    auto slot = [](int z) { return (z + 10) % 5; };   // z >= -2
+    auto aslot = [](int z) { return (z + 9) % 3; };
+    auto fslot = [](int z) { return z & 1; };
+
+    struct Step {
+        V2 pu[NLD], pa[NLD];
+        int rc, bc;
+        V2 rf, bf;
+        V4 rB, bB;
+    };
+    auto fetch_plane = [&](int z, Step &S) {
+#pragma unroll
+        for (int i = 0; i < NLD; i++) {
+            const int c = t + i * NT;
+            S.pu[i].x = S.pu[i].y = R(0);
+            S.pa[i].x = S.pa[i].y = R(0);
+            if (c < PS) {
+                const int gx = x0 + c % PX - 2, gy = y0 + c / PX - 2;
+                if (z >= 0 && z < L.nz && gx >= 0 && gx < L.nx && gy >= 0 && gy < L.ny) {
+                    const long long g = gx + (long long)L.nx * gy + nxy * z;
+                    S.pa[i] = L.ac[g];
+                    if (!ZG) S.pu[i] = L.u[g];
+                }
+            }
+        }
+    };
+    auto store_plane = [&](int z, const Step &S) {
+        const int s = slot(z), sa_ = aslot(z);
+#pragma unroll
+        for (int i = 0; i < NLD; i++) {
+            const int c = t + i * NT;
+            if (c < PS) {
+                su[s][c] = S.pu[i];
+                sa[sa_][c] = S.pa[i];
+            }
+        }
+    };
+    // red cell of this thread on plane z: a tile column (t < NCOL), the
+    // column of its black cell on plane z - 1, or a red cell of the ring
+    auto red_cell = [&](int z, int &c, long long &g) {
+        c = -1;
+        if (z < 0 || z >= L.nz || t >= NCOL + NRING) return;
+        int lx, ly;
+        if (t < NCOL) {
+            ly = 2 + t / BW;
+            lx = 2 + 2 * (t % BW) + ((x0 + y0 + ly + z) & 1);
+        } else {
+            const int q = t - NCOL;
+            constexpr int HX = (TX + 2) / 2, HY = TY / 2;
+            if (q < HX) {                       // row below the tile
+                ly = 1;
+                lx = 1 + 2 * q + ((x0 + y0 + z) & 1);
+            } else if (q < 2 * HX) {            // row above the tile
+                ly = TY + 2;
+                lx = 1 + 2 * (q - HX) + ((x0 + y0 + z + 1) & 1);
+            } else if (q < 2 * HX + HY) {       // column left of the tile
+                lx = 1;
+                ly = 2 + 2 * (q - 2 * HX) + ((x0 + y0 + z + 1) & 1);
+            } else {                            // column right of the tile
+                lx = TX + 2;
+                ly = 2 + 2 * (q - 2 * HX - HY) + ((x0 + y0 + z) & 1);
+            }
+        }
+        const int gx = x0 + lx - 2, gy = y0 + ly - 2;
+        if (gx < 0 || gx >= L.nx || gy < 0 || gy >= L.ny) return;
+        c = ly * PX + lx;
+        g = gx + (long long)L.nx * gy + nxy * z;
+    };
+    // black cell of this thread on plane z (t < NCOL): a tile cell
+    auto black_cell = [&](int z, int &c, long long &g) {
+        c = -1;
+        if (z < 0 || z >= L.nz || t >= NCOL) return;
+        const int ly = 2 + t / BW;
+        const int lx = 2 + 2 * (t % BW) + ((x0 + y0 + ly + z + 1) & 1);
+        const int gx = x0 + lx - 2, gy = y0 + ly - 2;
+        if (gx >= L.nx || gy >= L.ny) return;
+        c = ly * PX + lx;
+        g = gx + (long long)L.nx * gy + nxy * z;
+    };
+    auto accw = [&](R &gp, R &gT, R &Sp, R &ST, V2 w, int ss, int q) {
+        const R wp = w.x * ih2, wT = w.y * ih2;
+        const V2 uq = su[ss][q];
+        Sp += wp;
+        ST += wT;
+        gp += wp * uq.x;
+        gT += wT * uq.y;
+    };
+    // red update on plane z: computes its six faces, writes the four in
+    // the plane to LDS, returns the two z faces
+    auto update_red = [&](int z, int c, V2 f, V4 b, V2 &wzm, V2 &wzp) {
+        const int s = slot(z), sm = slot(z - 1), sp = slot(z + 1);
+        const int a0 = aslot(z), fs = fslot(z);
+        R gp = R(0), gT = R(0), Sp = R(0), ST = R(0);
+        const V2 am = sa[a0][c];
+        const V2 wxm = harm2(am, sa[a0][c - 1]), wxp = harm2(am, sa[a0][c + 1]);
+        const V2 wym = harm2(am, sa[a0][c - PX]), wyp = harm2(am, sa[a0][c + PX]);
+        wzm = harm2(am, sa[aslot(z - 1)][c]);
+        wzp = harm2(am, sa[aslot(z + 1)][c]);
+        sfx[fs][c] = wxm;
+        sfx[fs][c + 1] = wxp;
+        sfy[fs][c] = wym;
+        sfy[fs][c + PX] = wyp;
+        accw(gp, gT, Sp, ST, wxm, s, c - 1);
+        accw(gp, gT, Sp, ST, wxp, s, c + 1);
+        accw(gp, gT, Sp, ST, wym, s, c - PX);
+        accw(gp, gT, Sp, ST, wyp, s, c + PX);
+        accw(gp, gT, Sp, ST, wzm, sm, c);
+        accw(gp, gT, Sp, ST, wzp, sp, c);
+        V2 o;
+        block_solve<R>(f, b, gp, gT, Sp, ST, o);
+        su[s][c] = o;
+    };
+    // black update on plane z with the faces of its red neighbours
+    auto update_black = [&](int z, int c, V2 f, V4 b, V2 wzm, V2 wzp) {
+        const int s = slot(z), sm = slot(z - 1), sp = slot(z + 1), fs = fslot(z);
+        R gp = R(0), gT = R(0), Sp = R(0), ST = R(0);
+        accw(gp, gT, Sp, ST, sfx[fs][c], s, c - 1);
+        accw(gp, gT, Sp, ST, sfx[fs][c + 1], s, c + 1);
+        accw(gp, gT, Sp, ST, sfy[fs][c], s, c - PX);
+        accw(gp, gT, Sp, ST, sfy[fs][c + PX], s, c + PX);
+        accw(gp, gT, Sp, ST, wzm, sm, c);
+        accw(gp, gT, Sp, ST, wzp, sp, c);
+        V2 o;
+        block_solve<R>(f, b, gp, gT, Sp, ST, o);
+        su[s][c] = o;
+    };
+    auto write_plane = [&](int z) {
+        if (z < z0 || z >= z1) return;
+        const int s = slot(z);
+        const int lx = 2 + t % TX, ly = 2 + t / TX;
+        const int gx = x0 + lx - 2, gy = y0 + ly - 2;
+        if (gx < L.nx && gy < L.ny) {
+            uo[gx + (long long)L.nx * gy + nxy * z] = su[s][ly * PX + lx];
+        }
+    };
+    auto load_step = [&](int k, Step &S) {
+        S.rc = S.bc = -1;
+        if (k >= z1) return;
+        long long g;
+        fetch_plane(k + 2, S);
+        red_cell(k + 1, S.rc, g);
+        if (S.rc >= 0) {
+            S.rf = L.f[g];
+            S.rB = L.B[g];
+        }
+        black_cell(k, S.bc, g);
+        if (S.bc >= 0) {
+            S.bf = L.f[g];
+            S.bB = L.B[g];
+        }
+    };
+    // z faces of this thread's column: zq0 is the lower face of its black
+    // cell at the current step (the upper face of its red cell two steps
+    // back), zq1 the one for the next step
+    V2 zq0, zq1;
+    zq0.x = zq0.y = zq1.x = zq1.y = R(0);
+    auto body = [&](int k, const Step &cur, Step &ahead) {
+        store_plane(k + 2, cur);
+        load_step(k + 2, ahead);
+        __syncthreads();
+        write_plane(k - 1);
+        V2 wzm, wzp;
+        wzm.x = wzm.y = wzp.x = wzp.y = R(0);
+        if (cur.rc >= 0) update_red(k + 1, cur.rc, cur.rf, cur.rB, wzm, wzp);
+        __syncthreads();
+        if (cur.bc >= 0) update_black(k, cur.bc, cur.bf, cur.bB, zq0, wzm);
+        zq0 = zq1;
+        zq1 = wzp;
+    };
+
+    // a face whose red cell lies outside the grid is never written: zero
+    // (no flux), and it stays zero, as a cell has the same colour on every
+    // plane that uses the same face slot
+    for (int c = t; c < PS; c += NT) {
+        sfx[0][c].x = sfx[0][c].y = sfx[1][c].x = sfx[1][c].y = R(0);
+        sfy[0][c].x = sfy[0][c].y = sfy[1][c].x = sfy[1][c].y = R(0);
+    }
+    // ---- prologue: planes z0-2 .. z0 (three coefficient slots), red on
+    // z0-1, plane z0+1, red on z0
+    {
+        Step S;
+        for (int z = z0 - 2; z <= z0; z++) {
+            fetch_plane(z, S);
+            store_plane(z, S);
+        }
+        __syncthreads();
+        int c;
+        long long g;
+        V2 wzm, wzp;
+        red_cell(z0 - 1, c, g);
+        if (c >= 0) update_red(z0 - 1, c, L.f[g], L.B[g], wzm, wzp);
+        if (c >= 0 && t < NCOL) zq0 = wzp;
+        fetch_plane(z0 + 1, S);
+        __syncthreads();
+        store_plane(z0 + 1, S);
+        __syncthreads();
+        red_cell(z0, c, g);
+        if (c >= 0) update_red(z0, c, L.f[g], L.B[g], wzm, wzp);
+        if (c >= 0 && t < NCOL) zq1 = wzp;
+        __syncthreads();
+    }
+    Step A, B, C;
+    load_step(z0, A);
+    load_step(z0 + 1, B);
+    for (int k = z0; k < z1; k += 3) {
+        body(k, A, C);
+        if (k + 1 >= z1) break;
+        body(k + 1, B, A);
+        if (k + 2 >= z1) break;
+        body(k + 2, C, B);
+    }
+    __syncthreads();
+    write_plane(z1 - 1);
+}
+
+// The finest 3-D sweep with the residual and its restriction fused in
+// (the last pre-smoothing sweep of a V-cycle).  The sweep is k_rb_fused3's
+// (same per-cell arithmetic, same order), with a ring of three cells so
+// that the block also finishes black on a ring of one and red on a ring of
+// two: after the sweep every neighbour of a tile cell then holds its final
+// value in LDS, and the residual f - A u of the tile can be formed without
+// reading another block's output.  The chunk's black planes extend one
+// plane below and above it for the same reason (only the chunk's own
+// planes are written).  At plane step k (red on k+1, black on k) the
+// residual of plane k-2, whose planes k-3 .. k-1 are final, is formed by
+// one thread per tile cell (its own column's plane k-3 kept in registers,
+// as the 5-slot ring no longer holds it) with the arithmetic and summation
+// order of k_restrict_zm, and the 2 x 2 x 2 child means go to the coarse
+// right-hand side.  One plane step ahead is loaded while a step computes
+// (two register sets), to keep the registers of 1024 threads within one
+// block per CU.  FP32 only: FP64 rings of three cells exceed the LDS.
+template <typename R, int TX, int TY, bool ZG>
+__global__ __launch_bounds__(TX *TY) void k_rb_fused3r(Lvl<R> L, Lvl<R> C,
+                                                       typename VT<R>::v2 *__restrict__ uo, int zc,
+                                                       int tiles_x, int tiles_y, int ntiles)
+{
+    using V2 = typename VT<R>::v2;
+    using V4 = typename VT<R>::v4;
+    constexpr int G = 3;                         // loaded ring around the tile
+    constexpr int NT = TX * TY;
+    constexpr int PX = TX + 2 * G, PY = TY + 2 * G, PS = PX * PY;
+    constexpr int NLD = (PS + NT - 1) / NT;      // plane cells loaded per thread
+    constexpr int RW = (TX + 4) / 2, RH = TY + 4;   // red: tile and two rings
+    constexpr int BW = (TX + 2) / 2, BH = TY + 2;   // black: tile and one ring
+    constexpr int CX = TX / 2, CY = TY / 2;
+    static_assert(RW * RH <= NT && BW * BH <= NT && TX % 2 == 0 && TY % 2 == 0,
+                  "thread mapping");
+    __shared__ V2 su[5][PS];
+    __shared__ V2 sa[5][PS];
+    __shared__ V2 sr[NT];
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    if (tile >= ntiles) return;
+    const int txi = tile % tiles_x;
+    const int rr = tile / tiles_x;
+    const int tyi = rr % tiles_y;
+    const int tzi = rr / tiles_y;
+    const int x0 = txi * TX, y0 = tyi * TY;
+    const int z0 = tzi * zc, z1 = min(z0 + zc, L.nz);
+    const R ih2 = (R)L.inv_h2;
+    const long long nxy = (long long)L.nx * L.ny;
+    const int t = threadIdx.x;
+    auto slot = [](int z) { return (z + 10) % 5; };   // z >= -3
+
+    struct Step {
+        V2 pu[NLD], pa[NLD];
+        int rc, bc;
+        V2 rf, bf;
+        V4 rB, bB;
+    };
+    auto fetch_plane = [&](int z, Step &S) {
+#pragma unroll
+        for (int i = 0; i < NLD; i++) {
+            const int c = t + i * NT;
+            S.pu[i].x = S.pu[i].y = R(0);
+            S.pa[i].x = S.pa[i].y = R(0);
+            if (c < PS) {
+                const int gx = x0 + c % PX - G, gy = y0 + c / PX - G;
+                if (z >= 0 && z < L.nz && gx >= 0 && gx < L.nx && gy >= 0 && gy < L.ny) {
+                    const long long g = gx + (long long)L.nx * gy + nxy * z;
+                    S.pa[i] = L.ac[g];
+                    if (!ZG) S.pu[i] = L.u[g];
+                }
+            }
+        }
+    };
+    auto store_plane = [&](int z, const Step &S) {
+        const int s = slot(z);
+#pragma unroll
+        for (int i = 0; i < NLD; i++) {
+            const int c = t + i * NT;
+            if (c < PS) {
+                su[s][c] = S.pu[i];
+                sa[s][c] = S.pa[i];
+            }
+        }
+    };
+    // red cell of this thread on plane z: region [1, TX+5) x [1, TY+5)
+    auto red_cell = [&](int z, int &c, long long &g) {
+        c = -1;
+        if (z < 0 || z >= L.nz || t >= RW * RH) return;
+        const int ly = 1 + t / RW;
+        const int gy = y0 + ly - G;
+        const int lx = 1 + 2 * (t % RW) + ((x0 + 1 - G + gy + z) & 1);
+        const int gx = x0 + lx - G;
+        if (gx < 0 || gx >= L.nx || gy < 0 || gy >= L.ny) return;
+        c = ly * PX + lx;
+        g = gx + (long long)L.nx * gy + nxy * z;
+    };
+    // black cell of this thread on plane z: region [2, TX+4) x [2, TY+4)
+    auto black_cell = [&](int z, int &c, long long &g) {
+        c = -1;
+        if (z < 0 || z >= L.nz || t >= BW * BH) return;
+        const int ly = 2 + t / BW;
+        const int gy = y0 + ly - G;
+        const int lx = 2 + 2 * (t % BW) + ((x0 + 3 - G + gy + z) & 1);
+        const int gx = x0 + lx - G;
+        if (gx < 0 || gx >= L.nx || gy < 0 || gy >= L.ny) return;
+        c = ly * PX + lx;
+        g = gx + (long long)L.nx * gy + nxy * z;
+    };
+    // the red-black update of k_rb_fused3 (cell coefficients)
+    auto update = [&](int z, int c, V2 f, V4 b) {
+        const int s = slot(z), sm = slot(z - 1), sp = slot(z + 1);
+        R gp = R(0), gT = R(0), Sp = R(0), ST = R(0);
+        auto accw = [&](V2 w, int ss, int q) {
+            const R wp = w.x * ih2, wT = w.y * ih2;
+            const V2 uq = su[ss][q];
+            Sp += wp;
+            ST += wT;
+            gp += wp * uq.x;
+            gT += wT * uq.y;
+        };
+        const V2 am = sa[s][c];
+        accw(harm2(am, sa[s][c - 1]), s, c - 1);
+        accw(harm2(am, sa[s][c + 1]), s, c + 1);
+        accw(harm2(am, sa[s][c - PX]), s, c - PX);
+        accw(harm2(am, sa[s][c + PX]), s, c + PX);
+        accw(harm2(am, sa[sm][c]), sm, c);
+        accw(harm2(am, sa[sp][c]), sp, c);
+        V2 o;
+        block_solve<R>(f, b, gp, gT, Sp, ST, o);
+        su[s][c] = o;
+    };
+    // this thread's tile cell (residual) and coarse cell (restriction)
+    const int lxr = G + t % TX, lyr = G + t / TX;
+    const int gxr = x0 + lxr - G, gyr = y0 + lyr - G;
+    const bool rmine = gxr < L.nx && gyr < L.ny;
+    const int cr = lyr * PX + lxr;
+    const int cxl = t % CX, cyl = t / CX;
+    const int gcx = x0 / 2 + cxl, gcy = y0 / 2 + cyl;
+    const bool cmine = t < CX * CY && gcx < C.nx && gcy < C.ny;
+    V2 um_prev, am_prev;     // the thread's own cell on the plane below the residual's
+    um_prev.x = um_prev.y = am_prev.x = am_prev.y = R(0);
+    R accp = R(0), accT = R(0);
+    // residual of plane q at the thread's tile cell, into sr; the own
+    // cell of plane q becomes the z- neighbour of the next residual
+    auto residual = [&](int q, bool want) {
+        V2 r;
+        r.x = r.y = R(0);
+        const int s = slot(q), sp = slot(q + 1);
+        const V2 um = su[s][cr], am = sa[s][cr];
+        if (want && rmine) {
+            const long long g = gxr + (long long)L.nx * gyr + nxy * q;
+            const V2 f = L.f[g];
+            const V4 B = L.B[g];
+            R nbp = R(0), nbT = R(0), Sp = R(0), ST = R(0);
+            auto nb = [&](V2 aq, V2 uq) {
+                V2 w = harm2(am, aq);
+                const R wp = w.x * ih2, wT = w.y * ih2;
+                Sp += wp;
+                ST += wT;
+                nbp += wp * uq.x;
+                nbT += wT * uq.y;
+            };
+            nb(sa[s][cr - 1], su[s][cr - 1]);
+            nb(sa[s][cr + 1], su[s][cr + 1]);
+            nb(sa[s][cr - PX], su[s][cr - PX]);
+            nb(sa[s][cr + PX], su[s][cr + PX]);
+            nb(am_prev, um_prev);
+            nb(sa[sp][cr], su[sp][cr]);
+            const R Ap = Sp * um.x - nbp + B.x * um.x + B.y * um.y;
+            const R AT = ST * um.y - nbT + B.z * um.x + B.w * um.y;
+            r.x = f.x - Ap;
+            r.y = f.y - AT;
+        }
+        sr[t] = r;
+        um_prev = um;
+        am_prev = am;
+    };
+    // the 2 x 2 children of this thread's coarse cell on plane q (after a
+    // barrier), summed as k_restrict_zm sums them; the coarse plane is
+    // written after its odd fine plane
+    auto restrict_plane = [&](int q) {
+        if (!cmine) return;
+        const int base = 2 * cyl * TX + 2 * cxl;
+        const V2 r00 = sr[base], r10 = sr[base + 1];
+        const V2 r01 = sr[base + TX], r11 = sr[base + TX + 1];
+        R sp_ = r00.x + r10.x, sT_ = r00.y + r10.y;
+        sp_ += r01.x + r11.x;
+        sT_ += r01.y + r11.y;
+        accp += sp_;
+        accT += sT_;
+        if (q & 1) {
+            V2 o;
+            o.x = accp * R(0.125);
+            o.y = accT * R(0.125);
+            C.f[gcx + (long long)C.nx * gcy + (long long)C.nx * C.ny * (q >> 1)] = o;
+            accp = accT = R(0);
+        }
+    };
+    auto write_plane = [&](int z) {
+        if (z < z0 || z >= z1 || !rmine) return;
+        uo[gxr + (long long)L.nx * gyr + nxy * z] = su[slot(z)][cr];
+    };
+    // the global loads of step k: plane k+2, f and B of the red cell on
+    // plane k+1 and of the black cell on plane k (none past step z1)
+    auto load_step = [&](int k, Step &S) {
+        S.rc = S.bc = -1;
+        if (k > z1) return;
+        long long g;
+        fetch_plane(k + 2, S);
+        red_cell(k + 1, S.rc, g);
+        if (S.rc >= 0) {
+            S.rf = L.f[g];
+            S.rB = L.B[g];
+        }
+        black_cell(k, S.bc, g);
+        if (S.bc >= 0) {
+            S.bf = L.f[g];
+            S.bB = L.B[g];
+        }
+    };
+    // plane step k from `cur`; the loads of step k+1 go to `ahead`
+    auto body = [&](int k, const Step &cur, Step &ahead) {
+        store_plane(k + 2, cur);
+        load_step(k + 1, ahead);
+        __syncthreads();
+        write_plane(k - 1);
+        if (cur.rc >= 0) update(k + 1, cur.rc, cur.rf, cur.rB);
+        if (k - 2 >= z0 - 1) residual(k - 2, k - 2 >= z0);
+        __syncthreads();
+        if (cur.bc >= 0) update(k, cur.bc, cur.bf, cur.bB);
+        if (k - 2 >= z0) restrict_plane(k - 2);
+    };
+
+    // ---- prologue: planes z0-3 .. z0, red on z0-2 and z0-1
+    {
+        Step S;
+        for (int z = z0 - 3; z <= z0; z++) {
+            fetch_plane(z, S);
+            store_plane(z, S);
+        }
+    }
+    __syncthreads();
+    for (int z = z0 - 2; z <= z0 - 1; z++) {
+        int c;
+        long long g;
+        red_cell(z, c, g);
+        if (c >= 0) update(z, c, L.f[g], L.B[g]);
+        __syncthreads();
+    }
+    // steps z0-1 .. z1: black on z0-1 .. z1, red on z0 .. z1+1
+    Step A, B;
+    load_step(z0 - 1, A);
+    for (int k = z0 - 1; k <= z1; k += 2) {
+        body(k, A, B);
+        if (k + 1 > z1) break;
+        body(k + 1, B, A);
+    }
+    // the last residual plane, z1 - 1 (plane z1 finished by the last step)
+    __syncthreads();
+    residual(z1 - 1, true);
+    __syncthreads();
+    restrict_plane(z1 - 1);
+}
+
+template <typename R>
+void launch_rb_fused3r(const Lvl<R> &L, const Lvl<R> &C, typename VT<R>::v2 *uo, int zero_guess,
+                       hipStream_t s)
+{
+    if constexpr (sizeof(R) == 4) {
+        constexpr int TX = 64, TY = 16;
+        const int tx = (L.nx + TX - 1) / TX, ty = (L.ny + TY - 1) / TY;
+        // chunks of an even number of planes (a coarse plane takes two)
+        int zc = L.nz;
+        while (zc > 16 && (long long)tx * ty * ((L.nz + zc - 1) / zc) < 256)
+            zc = ((zc + 1) / 2 + 1) & ~1;
+        const int nt = tx * ty * ((L.nz + zc - 1) / zc);
+        if (zero_guess)
+            hipLaunchKernelGGL((k_rb_fused3r<R, TX, TY, true>), dim3(nt), dim3(TX * TY), 0, s, L, C,
+                               uo, zc, tx, ty, nt);
+        else
+            hipLaunchKernelGGL((k_rb_fused3r<R, TX, TY, false>), dim3(nt), dim3(TX * TY), 0, s, L,
+                               C, uo, zc, tx, ty, nt);
+    }
+}
+template void launch_rb_fused3r<float>(const Lvl<float> &, const Lvl<float> &, float2 *, int,
+                                       hipStream_t);
+template void launch_rb_fused3r<double>(const Lvl<double> &, const Lvl<double> &, double2 *, int,
+                                        hipStream_t);
+
 // 2-D: one whole red-black sweep per TX x TY tile, not marching: the tile
 // and a ring of 2 cells (u and the cell coefficients, or the stored faces)
 // in LDS, red over the tile and a ring of one, then black over the tile.
@@ -2062,8 +2630,16 @@ void launch_rb_fused(int dim, const Lvl<R> &L, typename VT<R>::v2 *uo, int zero_
                 else PTMG_FUSED3(16, false, false);
             }
         } else if (TY == 8) {
-            if (zero_guess) PTMG_FUSED3(8, true, false);
-            else PTMG_FUSED3(8, false, false);
+            // FP64: each face coefficient once per sweep (its divisions
+            // bound the FP64 sweep)
+            if constexpr (sizeof(R) == 8) {
+                if (zero_guess)
+                    hipLaunchKernelGGL((k_rb_fused3c<R, TX, 8, true>), dim3(nt), dim3(TX * 8), 0, s,
+                                       L, uo, zc, tx, ty, nt);
+                else
+                    hipLaunchKernelGGL((k_rb_fused3c<R, TX, 8, false>), dim3(nt), dim3(TX * 8), 0, s,
+                                       L, uo, zc, tx, ty, nt);
+            }
         } else {
             if (zero_guess) PTMG_FUSED3(4, true, false);
             else PTMG_FUSED3(4, false, false);
@@ -2300,7 +2876,7 @@ __global__ __launch_bounds__(TX *TY) void k_outer_zm(OuterArgs<RV> a, int NX, in
                 double nbp = 0.0, nbT = 0.0, Sp = 0.0, ST = 0.0;
                 // mr: the r-z metric of a radial (marching-axis, 2-D) face
                 auto nb = [&](int ss, int q, int mr = -1) {
-                    double2 w = harm2(am, sa[ss][q]);
+                    double2 w = harm2_exact(am, sa[ss][q]);
                     if (FLAT && mr >= 0 && a.axm) axi_face(w, a.axm[k], mr == 1);
                     w.x *= a.inv_h2;
                     w.y *= a.inv_h2;
@@ -3092,13 +3668,13 @@ __global__ __launch_bounds__(TX *TY) void k_down_zm(DownArgs a, int NX, int NY, 
                 const double2 qn = sq[ss][qi], an = sa[ss][qi], cn = sc[ss][qi];
                 const double p1n = qn.x + (1.0 - cn.x) * cn.y, p2n = qn.x - cn.x * cn.y;
                 if (upper) {
-                    f.g = harm(am.x, an.x) * ((qn.x - q.x) * a.inv_h);
-                    f.q = harm(am.y, an.y) * ((qn.y - q.y) * a.inv_h);
+                    f.g = harm_exact(am.x, an.x) * ((qn.x - q.x) * a.inv_h);
+                    f.q = harm_exact(am.y, an.y) * ((qn.y - q.y) * a.inv_h);
                     f.P1 = 0.5 * (p1c + p1n);
                     f.P2 = 0.5 * (p2c + p2n);
                 } else {
-                    f.g = harm(an.x, am.x) * ((q.x - qn.x) * a.inv_h);
-                    f.q = harm(an.y, am.y) * ((q.y - qn.y) * a.inv_h);
+                    f.g = harm_exact(an.x, am.x) * ((q.x - qn.x) * a.inv_h);
+                    f.q = harm_exact(an.y, am.y) * ((q.y - qn.y) * a.inv_h);
                     f.P1 = 0.5 * (p1n + p1c);
                     f.P2 = 0.5 * (p2n + p2c);
                 }
@@ -3165,6 +3741,89 @@ void launch_downstream(int dim, const DownArgs &a, hipStream_t s)
     else
         hipLaunchKernelGGL((k_down_zm<2, 256, 1>), dim3(g.nt), dim3(256), 0, s, a, g.NX, g.NY,
                            g.NZ, g.zc, g.tx, g.ty, g.nt);
+}
+
+// Viscous work of the phase energies (Eq. 39): W = div(mu (grad u + grad u^T)
+// . u) of the end-of-step velocity, one value per cell, and E_i += dt C_i W
+// (the phases share the one-fluid flux, so the total is conservative).
+// The normal flux (tau . u)_a on the face between cells L and R across
+// axis a takes the face velocity as the normal component and the mean of
+// the two cells' velocities for the others; tau_aa = 2 mu (u_a,R -
+// u_a,L)/h, tau_ab = mu ((u_b,R - u_b,L)/h + mean over L, R of the centred
+// difference of u_a along b, mirrored at a wall); mu the mean of the two
+// cells' C mu_1 + (1 - C) mu_2.  Wall faces carry no flux; r-z radial faces
+// the metric.  One thread per cell; every face flux is evaluated by the
+// same function from the face's own data, so both cells of a face take
+// the same value and the fluxes cancel exactly in the sum over the grid.
+template <int DIM>
+__device__ __forceinline__ double visc_flux(const ViscArgs &a, int ax, int i, int j, int k)
+{
+    const long long sx = 1, sy = a.nx, sz = (long long)a.nx * a.ny;
+    const long long st[3] = {sx, sy, sz};
+    const int idx[3] = {i, j, k};
+    const int n[3] = {a.nx, a.ny, a.nz};
+    const long long R = i + sy * j + sz * k, L = R - st[ax];
+    const double *u[3] = {a.ux, a.uy, a.uz};
+    const double muL = a.C[L] * a.mu1 + (1.0 - a.C[L]) * a.mu2;
+    const double muR = a.C[R] * a.mu1 + (1.0 - a.C[R]) * a.mu2;
+    const double mu = 0.5 * (muL + muR);
+    double flux = 0.0;
+#pragma unroll
+    for (int b = 0; b < DIM; b++) {
+        const double vR = u[b][R], vL = u[b][L];
+        if (b == ax) {
+            const double *U = ax == 0 ? a.Ux : (ax == 1 ? a.Uy : a.Uz);
+            const long long f = i + (long long)(a.nx + (ax == 0)) *
+                                        (j + (long long)(a.ny + (ax == 1)) * k);
+            flux += 2.0 * mu * (vR - vL) * a.inv_h * U[f];
+        } else {
+            // centred differences of u_ax along b at L and R (mirrored at walls)
+            const long long lo = idx[b] > 0 ? st[b] : 0, hi = idx[b] < n[b] - 1 ? st[b] : 0;
+            const double *w = u[ax];
+            const double gR = (w[R + hi] - w[R - lo]) * (0.5 * a.inv_h);
+            const double gL = (w[L + hi] - w[L - lo]) * (0.5 * a.inv_h);
+            const double tau = mu * ((vR - vL) * a.inv_h + 0.5 * (gL + gR));
+            flux += tau * (0.5 * (vL + vR));
+        }
+    }
+    return flux;
+}
+
+template <int DIM>
+__global__ __launch_bounds__(256) void k_viscous(ViscArgs a)
+{
+    const long long N = (long long)a.nx * a.ny * a.nz;
+    for (long long t = blockIdx.x * 256ll + threadIdx.x; t < N; t += (long long)gridDim.x * 256) {
+        int i, j, k;
+        decode(t, a.nx, a.ny, i, j, k);
+        const int idx[3] = {i, j, k};
+        const int n[3] = {a.nx, a.ny, a.nz};
+        double W = 0.0;
+#pragma unroll
+        for (int ax = 0; ax < DIM; ax++) {
+            const double lo = idx[ax] > 0 ? visc_flux<DIM>(a, ax, i, j, k) : 0.0;
+            double hi = 0.0;
+            if (idx[ax] < n[ax] - 1)
+                hi = visc_flux<DIM>(a, ax, i + (ax == 0), j + (ax == 1), k + (ax == 2));
+            if (DIM == 2 && ax == 1 && a.axm) {
+                const double4 m = a.axm[j];
+                W += (m.y * hi - m.x * lo) * a.inv_h;
+            } else {
+                W += (hi - lo) * a.inv_h;
+            }
+        }
+        const double c = a.C[t];
+        a.E1[t] += a.dt * c * W;
+        a.E2[t] += a.dt * (1.0 - c) * W;
+    }
+}
+
+void launch_viscous(int dim, const ViscArgs &a, hipStream_t s)
+{
+    const long long N = (long long)a.nx * a.ny * a.nz;
+    const unsigned nb = (unsigned)std::min<long long>((N + 255) / 256, 1 << 20);
+    if (dim == 3) hipLaunchKernelGGL(k_viscous<3>, dim3(nb), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(k_viscous<2>, dim3(nb), dim3(256), 0, s, a);
 }
 
 __global__ __launch_bounds__(256) void k_divergence(int dim, int nx, int ny, int nz, double inv_h,

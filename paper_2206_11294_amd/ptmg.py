@@ -37,7 +37,7 @@ class PtMgError(RuntimeError):
 
 class pt_phase(ctypes.Structure):
     _fields_ = [(f, ctypes.c_double) for f in
-                ("rho", "k", "cp", "cv", "c", "gamma", "Gamma", "Pi", "b", "beta", "q")]
+                ("rho", "k", "cp", "cv", "c", "gamma", "Gamma", "Pi", "b", "beta", "q", "mu")]
 
 
 _Dp = ctypes.c_void_p
@@ -176,8 +176,8 @@ def _stream_ptr(stream) -> Optional[int]:
     return stream.cuda_stream or None
 
 
-def phase_struct(rho, k, cp, cv, c, gamma, Gamma, Pi, b, beta=0.0) -> pt_phase:
-    return pt_phase(rho, k, cp, cv, c, gamma, Gamma, Pi, b, beta)
+def phase_struct(rho, k, cp, cv, c, gamma, Gamma, Pi, b, beta=0.0, q=0.0, mu=0.0) -> pt_phase:
+    return pt_phase(rho, k, cp, cv, c, gamma, Gamma, Pi, b, beta, q, mu)
 
 
 def footprint_bytes(prob: pt_problem, precision: int) -> int:

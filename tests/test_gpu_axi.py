@@ -182,7 +182,8 @@ def test_axi_end_of_step():
     h.downstream(dev(p), dev(T), t["C"], [dev(x) for x in Us], U, [dev(x) for x in us], u,
                  dev(z), dev(z), E1, E2, t["kappa"], prob.sigma)
     torch.cuda.synchronize()
-    o = orc.downstream(op, prob.dt, p, T, prob.C, Us, z, z, us, prob.kappa, prob.sigma)
+    o = orc.downstream(op, prob.dt, p, T, prob.C, Us, z, z, us, prob.kappa, prob.sigma,
+                       mu=(prob.liquid.mu, prob.gas.mu))
 
     def close(a, b, tol):
         b = np.asarray(b).reshape(-1)
@@ -193,8 +194,8 @@ def test_axi_end_of_step():
     close(E1, o["E1"], 1e-11)
     close(E2, o["E2"], 1e-11)
     # total energy weighted by the cell volumes is conserved without
-    # surface tension (closed walls)
-    h.downstream(dev(p), dev(T), t["C"], [dev(x) for x in Us], U, None, None,
+    # surface tension (closed walls), viscous work included
+    h.downstream(dev(p), dev(T), t["C"], [dev(x) for x in Us], U, [dev(x) for x in us], u,
                  dev(z), dev(z), E1, E2)
     torch.cuda.synchronize()
     rc, _ = _radii(prob.n)

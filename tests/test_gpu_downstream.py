@@ -95,7 +95,8 @@ def _run(h, prob, t, p, T, Us, us, E1a, E2a, kappa=True, cells=True, energy=True
 
 def _oracle(op, prob, p, T, Us, us, E1a, E2a, kappa=True):
     return orc.downstream(op, prob.dt, p, T, prob.C, Us, E1a, E2a, us,
-                          prob.kappa if kappa else None, prob.sigma if kappa else 0.0)
+                          prob.kappa if kappa else None, prob.sigma if kappa else 0.0,
+                          mu=(prob.liquid.mu, prob.gas.mu))
 
 
 def _close(a, b, rtol):
@@ -163,8 +164,21 @@ def test_downstream_matches_oracle(name):
 @pytest.mark.parametrize("name", ["state2d_200x136", "state3d_66x6x10"])
 def test_optional_outputs(name):
     """Without cell velocities and without the energy update, the face
-    velocities are the same; the energies alone (no cell velocities) too."""
-    prob = _case(name)
+    velocities are the same; the energies alone (no cell velocities) too,
+    for inviscid phases.  Viscous phases need the cell velocities."""
+    import dataclasses
+    from paper_2206_11294_amd import ptmg
+    vprob = _case(name)
+    assert vprob.liquid.mu > 0 and vprob.gas.mu > 0
+    hv, tv = _handle(vprob)
+    p, T = _fields(vprob, 8)
+    Us = [u.reshape(-1) for u in vprob.uf_star]
+    with pytest.raises(ptmg.PtMgError) as e:
+        _run(hv, vprob, tv, p, T, Us, [], vprob.E1.reshape(-1), vprob.E2.reshape(-1),
+             cells=False)
+    assert e.value.status == ptmg.PT_ERR_ARG
+    prob = dataclasses.replace(vprob, liquid=dataclasses.replace(vprob.liquid, mu=0.0),
+                               gas=dataclasses.replace(vprob.gas, mu=0.0))
     h, t = _handle(prob)
     p, T = _fields(prob, 8)
     Us = [u.reshape(-1) for u in prob.uf_star]
@@ -210,7 +224,9 @@ def test_total_energy_conserved_on_gpu(name):
     p, T = _fields(prob, 10)
     Us = [u.reshape(-1) for u in prob.uf_star]
     z = np.zeros(prob.ncells)
-    g = _run(h, prob, t, p, T, Us, [np.zeros(prob.ncells)] * prob.dim, z, z, kappa=False)
+    rng = np.random.default_rng(11)
+    us = [rng.uniform(-1, 1, prob.ncells) for _ in range(prob.dim)]   # viscous work too
+    g = _run(h, prob, t, p, T, Us, us, z, z, kappa=False)
     scale = np.abs(g["E1"]).sum() + np.abs(g["E2"]).sum()
     assert abs((g["E1"] + g["E2"]).sum()) <= 1e-12 * scale
 
@@ -274,3 +290,34 @@ def test_downstream_errors():
     assert e.value.status == ptmg.PT_ERR_STATE
     # the divergence works in any mode
     assert torch.count_nonzero(h2.divergence(Ue)).item() == 0
+
+
+@pytest.mark.parametrize("name", SMALL[:-1] + ["state2d_1024", "state3d_256", "axi_state2d_96x80"])
+def test_viscous_work_matches_oracle(name):
+    """The viscous work of Eq. (39) alone: p = 0 and a uniform T remove the
+    pressure work and the heat flux, no surface tension, so the energy
+    increments are dt C_i W of the corrected velocities (here u* itself);
+    element by element against the oracle, seeded random cell velocities,
+    at its own scale; Cartesian and r-z grids."""
+    import dataclasses
+    if name == "axi_state2d_96x80":
+        prob = W.state_problem(name, 2, (96, 80), [(0.4, 0.0)], [0.3], seed=38)
+        prob = dataclasses.replace(prob, axisymmetric=True)
+    else:
+        prob = _case(name)
+    print(f"viscous {name} {prob.n}", flush=True)
+    assert prob.liquid.mu > 0 and prob.gas.mu > 0
+    h, t = _handle(prob)
+    op = orc.assemble(prob)
+    rng = np.random.default_rng(12)
+    N = prob.ncells
+    p, T = np.zeros(N), np.full(N, W.T0)
+    Us = [u.reshape(-1) for u in prob.uf_star]
+    us = [rng.uniform(-1, 1, N) for _ in range(prob.dim)]
+    z = np.zeros(N)
+    g = _run(h, prob, t, p, T, Us, us, z, z, kappa=False)
+    o = _oracle(op, prob, p, T, Us, us, z, z, kappa=False)
+    assert np.abs(o["E1"]).max() > 0
+    _close(g["E1"], o["E1"], 1e-12)
+    _close(g["E2"], o["E2"], 1e-12)
+    h.destroy()

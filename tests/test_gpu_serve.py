@@ -47,10 +47,25 @@ def _submit_all(srv, probs, rtol, t0=None):
     return out
 
 
+def _largest():
+    """Requests of the serving mix's largest sizes, 2048^2 and 192^3: the
+    first ids of each dimension drawn with only those sizes allowed."""
+    out = {}
+    rid = 100
+    while len(out) < 2:
+        pr = W.serve_request(rid, [2048], [192])
+        out.setdefault(pr.dim, pr)
+        rid += 1
+    return [out[2], out[3]]
+
+
 def test_results_identical_alone_and_in_the_mix():
+    """Twelve small requests and the mix's largest two (2048^2, 192^3)."""
     from paper_2206_11294_amd import serve
-    probs = _requests(range(12))
+    probs = _requests(range(6)) + _largest() + _requests(range(6, 12))
     assert {p.dim for p in probs} == {2, 3}
+    assert max(p.ncells for p in probs if p.dim == 2) == 2048 ** 2
+    assert max(p.ncells for p in probs if p.dim == 3) == 192 ** 3
     alone = [_alone(p, 1e-10) for p in probs]
     srv = serve.Server(hbm_budget=8 << 30, max_active=6)
     reqs = _submit_all(srv, probs, 1e-10)

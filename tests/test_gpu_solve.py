@@ -279,6 +279,40 @@ def test_hierarchy_graph_follows_fused_toggle(name):
             assert torch.equal(sol[0][0], sol[1][0]) and torch.equal(sol[0][1], sol[1][1])
 
 
+@pytest.mark.parametrize("n", [(136, 40, 48), (68, 36, 36)])
+def test_fused_restriction_3d_equals_reference(n):
+    """The 3-D FP32 finest sweep that also restricts its residual (the last
+    pre-sweep of each V-cycle) against the separate sweep and restriction
+    kernels (PT_OPT_FUSED off): V-cycles with one to three pre-sweeps (one:
+    the fused sweep starts from zero) and a whole solve agree bit for bit,
+    on grids of several tiles and z chunks with ragged edges."""
+    import workloads.device as D
+    from paper_2206_11294_amd import ptmg
+    prob = W.bubble_problem("fr", 3, n, [(0.45, 0.5, 0.4)], [0.3], 100 * W.P0, 0.01 * W.P0,
+                            div_amp=1e-7, div_seed=6)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        h, b_p, b_T, _ = D.setup(prob, 1, stream=stream)
+        rng = np.random.default_rng(3)
+        f_p, f_T = dev(rng.uniform(-1, 1, h.N)), dev(rng.uniform(-1, 1, h.N))
+        out = {}
+        for fused in (1, 0):
+            h.set_option(ptmg.PT_OPT_FUSED, fused)
+            res = []
+            for nu1 in (1, 2, 3):
+                e = h.vcycle(f_p, f_T, nu1=nu1, nu2=1)
+                res += [e[0].clone(), e[1].clone()]
+            p, T = torch.empty_like(b_p), torch.empty_like(b_T)
+            info = h.solve(b_p, b_T, p, T, rtol=1e-12, nu1=3, nu2=2)
+            torch.cuda.synchronize()
+            assert info["status"] == 0
+            res += [p.clone(), T.clone()]
+            out[fused] = (res, info["cycles"], info["hist"])
+    for a, b in zip(out[1][0], out[0][0]):
+        assert torch.equal(a, b), (a - b).abs().max().item()
+    assert out[1][1] == out[0][1] and out[1][2] == out[0][2]
+
+
 @pytest.mark.parametrize("name", ["bubble2d_200x136", "bubble3d_40x24x56", "explicit_64",
                                   "twobubble2d_96x80"])
 @pytest.mark.parametrize("prec", [0, 1])
@@ -633,3 +667,29 @@ def test_small_hierarchy_kernel_matches_reference(name, prec):
     for l, (a, b) in enumerate(zip(o1, o0), start=1):
         assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1]), l
     assert torch.equal(p1, p0) and torch.equal(T1, T0) and h1 == h0
+
+
+def test_vcycle_h_independent_on_constant_family():
+    """The 2-D constant-coefficient case (alpha_p = 1, alpha_T = 0.1,
+    B = [[1, 0.3], [0.2, 1]]/dt, seeded f) at N = 64 ... 1024: the V(2,2)
+    cycle's contraction per cycle stays bounded and the cycles to 1e-10
+    stay within two of each other as h halves four times (multigrid's
+    h-independence; the paper prints no iteration counts, so the bound is
+    this library's own record)."""
+    import workloads.device as D
+    rec = []
+    for n in (64, 128, 256, 512, 1024):
+        prob = W.explicit_const(n, n)
+        h, b_p, b_T, _ = D.setup(prob, 0)
+        p, T = torch.empty_like(b_p), torch.empty_like(b_T)
+        info = h.solve(b_p, b_T, p, T, rtol=1e-10, max_cycles=40)
+        assert info["status"] == 0, n
+        hist = np.array(info["hist"]).max(axis=1)
+        rates = hist[2:] / hist[1:-1]       # steady contraction after the first cycle
+        rec.append((n, info["cycles"], float(rates.max()) if rates.size else 0.0))
+        print(f"# constant family N={n}: cycles {info['cycles']}, "
+              f"contraction {rec[-1][2]:.2e}", flush=True)
+        h.destroy()
+    cycles = [c for _, c, _ in rec]
+    assert max(cycles) - min(cycles) <= 2, rec
+    assert max(r for _, _, r in rec) <= 0.1, rec
