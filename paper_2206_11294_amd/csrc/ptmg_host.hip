@@ -33,6 +33,9 @@ struct Plan {
     long long N = 0;
     LevelPlan lv[kMaxLevels];
     size_t o_ac64, o_B64, o_xp, o_xT, o_partials, o_flags, o_gj0, o_gj1;
+    // phases mode: the finest block is kept compact, (C, bb) and T
+    bool compact = false;
+    size_t o_cb64 = (size_t)-1, o_T64 = (size_t)-1, o_cb32 = (size_t)-1, o_T32 = (size_t)-1;
     size_t o_axm64 = (size_t)-1, o_axm32 = (size_t)-1;   // r-z metric per finest row
     size_t total = 0;
     size_t take(size_t bytes)
@@ -101,9 +104,21 @@ const char *plan_problem(const pt_problem *p, int prec, Plan &P)
     for (int a = 0; a < 3; a++) P.n[a] = p->n[a];
     P.N = (long long)p->n[0] * p->n[1] * p->n[2];
     const size_t R = prec == PT_PREC_MIXED ? 4 : 8;
-    // finest grid FP64 operator, FP64 ping-pong iterate
+    // finest grid FP64 operator: cell coefficients and the block (phases
+    // mode in mixed precision: compact, (C, bb) and T, in both precisions;
+    // the FP64 sweeps of an FP64 V-cycle are faster with the stored block),
+    // FP64 ping-pong iterate
+    P.compact = p->mode == PT_COEF_PHASES && prec == PT_PREC_MIXED;
     P.o_ac64 = P.take(16 * P.N);
-    P.o_B64 = P.take(32 * P.N);
+    P.o_B64 = (size_t)-1;
+    if (P.compact) {
+        P.o_cb64 = P.take(16 * P.N);
+        P.o_T64 = P.take(8 * P.N);
+        P.o_cb32 = P.take(8 * P.N);
+        P.o_T32 = P.take(4 * P.N);
+    } else {
+        P.o_B64 = P.take(32 * P.N);
+    }
     P.o_xp = P.take(8 * P.N);
     P.o_xT = P.take(8 * P.N);
     if (p->axisymmetric) {
@@ -126,7 +141,7 @@ const char *plan_problem(const pt_problem *p, int prec, Plan &P)
         if (l == 0) {
             if (prec == PT_PREC_MIXED) {
                 L.o_ac = P.take(2 * R * L.N);
-                L.o_B = P.take(4 * R * L.N);
+                if (!P.compact) L.o_B = P.take(4 * R * L.N);
             }
         } else {
             L.o_fx = P.take(2 * R * L.N);
@@ -186,6 +201,9 @@ struct pt_mg_s {
     double *kry = nullptr;          // Krylov work vectors (allocated on first use)
     bool ready = false;
     bool owns_memory = true;        // false: device + pinned memory belong to a server arena
+    bool p_field = false, T_field = false;   // phases mode: p_adv / T_adv given per cell
+    CBK<double> cbk64 = {};         // compact block: the constants of the last assembly
+    CBK<float> cbk32 = {};
     int device = 0;                 // the GPU current at setup (its static scratch)
     hipEvent_t done_ev = nullptr;   // marks the end of the last enqueued step
     // asynchronous solve (pt_mg_solve drives it to the end; a server polls it)
@@ -242,6 +260,7 @@ struct pt_mg_s {
     hipGraph_t hier_graph = nullptr;
     hipGraphExec_t hier_exec = nullptr;
     bool hier_fused = true;         // use_fused when hier_graph was captured
+    int hier_fields = 0;            // p_field + 2 T_field when hier_graph was captured
     // off by default: with one kernel per coarse visit and the tail, a graph
     // replaces few launches, and its end costs more than they do
     bool use_graphs = false;
@@ -261,6 +280,23 @@ struct pt_mg_s {
     double4 *B64() { return at<double4>(P.o_B64); }
     double *partials() { return at<double>(P.o_partials); }
     int *flags() { return at<int>(P.o_flags); }
+
+    // the compact block, its T and constants (null: stored block)
+    template <typename R>
+    void compact_view(const typename VT<R>::v2 *&cb, const R *&T, long long &tmask, CBK<R> &k)
+    {
+        cb = nullptr;
+        T = nullptr;
+        tmask = 0;
+        std::memset(&k, 0, sizeof k);
+        if (!P.compact) return;
+        const bool f32 = sizeof(R) == 4;
+        cb = at<typename VT<R>::v2>(f32 ? P.o_cb32 : P.o_cb64);
+        T = at<R>(f32 ? P.o_T32 : P.o_T64);
+        tmask = T_field ? -1ll : 0ll;
+        if constexpr (sizeof(R) == 4) k = cbk32;
+        else k = cbk64;
+    }
 
     template <typename R> Lvl<R> level(int l)
     {
@@ -284,9 +320,15 @@ struct pt_mg_s {
             o.B = at<typename VT<R>::v4>(L.o_B);
         }
         o.axm = nullptr;
-        if (l == 0)
+        o.cb = nullptr;
+        o.T0 = nullptr;
+        o.tmask = 0;
+        std::memset(&o.k, 0, sizeof o.k);
+        if (l == 0) {
             o.axm = (const typename VT<R>::v4 *)(sizeof(R) == 8 ? (void *)axm64()
                                                                 : (void *)at<float4>(P.o_axm32));
+            compact_view<R>(o.cb, o.T0, o.tmask, o.k);
+        }
         return o;
     }
     // r-z metric of the finest rows (null on Cartesian grids)
@@ -300,6 +342,7 @@ struct pt_mg_s {
         o.ac = ac64();
         o.B = B64();
         o.axm = axm64();
+        compact_view<double>(o.cb, o.T0, o.tmask, o.k);
         return o;
     }
 
@@ -439,14 +482,25 @@ int sync(pt_mg_t h, const char *what)
 }
 
 // Algorithmic bytes of one kernel launch (each array read or written once).
-double bytes_sweep_half(const Plan &P, int l, bool zero_guess)
+// The operator of level l per cell: cell (finest) or face coefficients and
+// the block, stored or compact ((C, bb), and T where given per cell).
+double op_bytes(pt_mg_t h, int l, double R)
 {
-    const double R = P.prec == PT_PREC_MIXED ? 4 : 8;
-    const double N = (double)P.lv[l].N;
-    const double coef = (l == 0 ? 2 : 2 * P.dim) * R;     // cell or face coefficients
-    // one colour: reads the other colour's u, its own f and B, all coefficients
-    // (harmonic means need the neighbours'), writes its own u
-    return N * (0.5 * (zero_guess ? 0 : 2 * R) + 0.5 * 2 * R + 0.5 * 4 * R + coef + 0.5 * 2 * R);
+    if (l == 0 && h->P.compact) return R * (2 + 2 + h->T_field);
+    return ((l == 0 ? 2 : 2 * h->P.dim) + 4) * R;
+}
+
+double bytes_sweep_half(pt_mg_t h, int l, bool zero_guess)
+{
+    const double R = h->P.prec == PT_PREC_MIXED ? 4 : 8;
+    const double N = (double)h->P.lv[l].N;
+    // one colour: reads the other colour's u, its own f and block, all
+    // coefficients (harmonic means need the neighbours'), writes its own u;
+    // compact block: (C, bb) and T (where given per cell) of its own
+    const double op = (l == 0 && h->P.compact)
+                          ? R * (2 + 0.5 * (2 + h->T_field))
+                          : 0.5 * 4 * R + (l == 0 ? 2 : 2 * h->P.dim) * R;
+    return N * (0.5 * (zero_guess ? 0 : 2 * R) + 0.5 * 2 * R + op + 0.5 * 2 * R);
 }
 
 // One pass over memory per sweep pays off where a level has enough
@@ -486,8 +540,7 @@ template <typename R> void smooth(pt_mg_t h, int l, int sweeps, bool zero_guess,
             Lvl<R> L = h->level<R>(l);
             h->u_cur ^= 1u << l;
             typename VT<R>::v2 *uo = h->level<R>(l).u;
-            const double coef = (l == 0 ? 2 : 2 * h->P.dim) * Rb;   // cell or face coefficients
-            double nb = (double)L.N * ((zg ? 0 : 2 * Rb) + 2 * Rb + coef + 4 * Rb + 2 * Rb);
+            double nb = (double)L.N * ((zg ? 0 : 2 * Rb) + 2 * Rb + op_bytes(h, l, Rb) + 2 * Rb);
             if (r) nb += (double)h->P.lv[l + 1].N * 2 * Rb;            // coarse f written
             h->begin(l == 0 ? PT_K_SMOOTH_FINE : PT_K_SMOOTH_COARSE, nb, s == 0);
             if (r)
@@ -503,10 +556,10 @@ template <typename R> void smooth(pt_mg_t h, int l, int sweeps, bool zero_guess,
     const int cls = l == 0 ? PT_K_SMOOTH_FINE : PT_K_SMOOTH_COARSE;
     for (int s = 0; s < sweeps; s++) {
         const bool zg = zero_guess && s == 0;
-        h->begin(cls, bytes_sweep_half(h->P, l, zg));
+        h->begin(cls, bytes_sweep_half(h, l, zg));
         launch_rb_pass<R>(h->P.dim, l == 0, L, 0, zg ? 1 : 0, h->stream);
         h->end();
-        h->begin(cls, bytes_sweep_half(h->P, l, false));
+        h->begin(cls, bytes_sweep_half(h, l, false));
         launch_rb_pass<R>(h->P.dim, l == 0, L, 1, 0, h->stream);
         h->end();
         h->updates += L.N;
@@ -529,7 +582,7 @@ template <typename R> void smooth0_fused(pt_mg_t h, int sweeps, bool zero_guess,
         Lvl<R> L = h->level<R>(0), C = h->level<R>(1);
         h->u_cur ^= 1u;
         typename VT<R>::v2 *uo = h->level<R>(0).u;
-        double nb = (double)L.N * ((zg ? 0 : 2 * Rb) + 2 * Rb + 2 * Rb + 4 * Rb + 2 * Rb);
+        double nb = (double)L.N * ((zg ? 0 : 2 * Rb) + 2 * Rb + op_bytes(h, 0, Rb) + 2 * Rb);
         if (p || r) nb += (double)C.N * 2 * Rb;   // coarse u read, or coarse f written
         h->begin(PT_K_SMOOTH_FINE, nb, s == 0);
         launch_tile2x<R>(L, C, uo, zg ? 1 : 0, p ? 1 : 0, r ? 1 : 0, h->stream);
@@ -542,8 +595,8 @@ template <typename R> void restrict_level(pt_mg_t h, int l)
 {
     Lvl<R> F = h->level<R>(l), C = h->level<R>(l + 1);
     const double Rb = sizeof(R);
-    const double coef = (l == 0 ? 2 : 2 * h->P.dim) * Rb;
-    h->begin(PT_K_RESTRICT, (double)F.N * (8 * Rb + coef) + (double)C.N * 2 * Rb);
+    // u, f, the operator read; coarse f written
+    h->begin(PT_K_RESTRICT, (double)F.N * (4 * Rb + op_bytes(h, l, Rb)) + (double)C.N * 2 * Rb);
     if (l == 0) launch_restrict_zm<R>(h->P.dim, F, C, h->stream);
     else launch_restrict<R>(h->P.dim, 0, F, C, h->stream);
     h->end();
@@ -806,9 +859,11 @@ template <typename R> void hierarchy(pt_mg_t h)
         build_hierarchy<R>(h);
         return;
     }
-    if (h->hier_exec && h->hier_fused != h->use_fused) {
-        // PT_OPT_FUSED changed since the capture: the graph holds the other
-        // kernels, so capture again
+    const int fields = (int)h->p_field + 2 * (int)h->T_field;
+    if (h->hier_exec && (h->hier_fused != h->use_fused || h->hier_fields != fields)) {
+        // PT_OPT_FUSED, or which provisional fields are given per cell,
+        // changed since the capture: the graph holds other kernels or
+        // arguments, so capture again
         (void)hipGraphExecDestroy(h->hier_exec);
         (void)hipGraphDestroy(h->hier_graph);
         h->hier_exec = nullptr;
@@ -816,6 +871,7 @@ template <typename R> void hierarchy(pt_mg_t h)
     }
     if (!h->hier_exec) {
         h->hier_fused = h->use_fused;
+        h->hier_fields = fields;
         bool ok = hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
         if (ok) {
             build_hierarchy<R>(h);
@@ -864,6 +920,51 @@ int assemble_enqueue(pt_mg_t h, const pt_problem *p)
     if (P.prec == PT_PREC_MIXED) {
         a.ac32 = h->at<float2>(P.lv[0].o_ac);
         a.B32 = h->at<float4>(P.lv[0].o_B);
+    }
+    if (p->mode == PT_COEF_PHASES) {
+        // the constants of this assembly (dt and the phases may change),
+        // and where the block is kept compact, its arrays
+        h->p_field = p->p_adv != nullptr;
+        h->T_field = p->T_adv != nullptr;
+        if (P.compact) {
+            a.cb64 = h->at<double2>(P.o_cb64);
+            a.T64 = h->at<double>(P.o_T64);
+            a.cb32 = h->at<float2>(P.o_cb32);
+            a.T32 = h->at<float>(P.o_T32);
+            a.T_cells = h->T_field;
+        }
+        OpK k64;
+        std::memset(&k64, 0, sizeof k64);
+        const pt_phase *ph[2] = {&p->liquid, &p->gas};
+        for (int q = 0; q < 2; q++) {
+            const pt_phase &f = *ph[q];
+            k64.rho[q] = f.rho;
+            k64.k[q] = f.k;
+            k64.blk.K1[q] = f.gamma / (f.rho * f.c * f.c) / (p->dt * p->dt);
+            k64.blk.K2[q] = f.rho * f.cp / p->dt;
+            k64.gcv[q] = (f.Gamma - 1.0) * f.cv;
+            k64.b[q] = f.b;
+            k64.Pi[q] = f.Pi;
+            if (f.beta > 0.0) {
+                k64.beta[q] = f.beta;
+            } else if (f.b == 0.0 && !h->T_field) {
+                // Eq. (10) without the covolume at the uniform T: as the kernels
+                // would form it (gcv T + 0 is exact)
+                k64.beta[q] = k64.gcv[q] / (k64.gcv[q] * p->T_adv_const);
+            }
+        }
+        k64.blk.idt = 1.0 / p->dt;
+        k64.blk.idt2 = 1.0 / (p->dt * p->dt);
+        CBK<float> k32;
+        for (int q = 0; q < 2; q++) {
+            k32.K1[q] = (float)k64.blk.K1[q];
+            k32.K2[q] = (float)k64.blk.K2[q];
+        }
+        k32.idt = (float)k64.blk.idt;
+        k32.idt2 = (float)k64.blk.idt2;
+        h->cbk64 = k64.blk;
+        h->cbk32 = k32;
+        a.k64 = k64;
     }
     a.flags = h->flags();
     h->ready = false;
@@ -1072,7 +1173,7 @@ int handle_paper_rhs_async(pt_mg_t h, const double *p_adv, const double *T_adv,
     if (h->prob.mode == PT_COEF_EXPLICIT)
         return fail(h, PT_ERR_STATE, "paper_rhs needs phases or state mode");
     h->begin(PT_K_OTHER, 48.0 * h->P.N);
-    launch_paper_rhs(h->P.N, h->B64(), p_adv, h->prob.p_adv_const, T_adv, h->prob.T_adv_const,
+    launch_paper_rhs(h->level0_fp64(), p_adv, h->prob.p_adv_const, T_adv, h->prob.T_adv_const,
                      div_ustar, h->prob.dt, b_p, b_T, h->stream);
     h->end();
     return PT_OK;
@@ -1152,7 +1253,7 @@ int pt_mg_paper_rhs(pt_mg_t h, const double *p_adv, const double *T_adv, const d
         return fail(h, PT_ERR_STATE, "paper_rhs needs phases or state mode");
     if (!b_p || !b_T) return fail(h, PT_ERR_ARG, "outputs are NULL");
     h->begin(PT_K_OTHER, 48.0 * h->P.N);
-    launch_paper_rhs(h->P.N, h->B64(), p_adv, h->prob.p_adv_const, T_adv, h->prob.T_adv_const,
+    launch_paper_rhs(h->level0_fp64(), p_adv, h->prob.p_adv_const, T_adv, h->prob.T_adv_const,
                      div_ustar, h->prob.dt, b_p, b_T, h->stream);
     h->end();
     return sync(h, "paper_rhs");
@@ -1299,6 +1400,7 @@ int outer(pt_mg_t h, const double *b_p, const double *b_T, const double *src_p,
     a.phases = h->prob.mode != PT_COEF_EXPLICIT;
     a.ac = h->ac64();
     a.B = h->B64();
+    h->compact_view<double>(a.cb, a.T0, a.tmask, a.k);
     a.b_p = b_p;
     a.b_T = b_T;
     a.bshift = bshift;
@@ -1314,7 +1416,8 @@ int outer(pt_mg_t h, const double *b_p, const double *b_T, const double *src_p,
     a.partials = h->partials();
     a.update = update ? 1 : 0;
     const double Rb = sizeof(RV);
-    double nbytes = (double)P.N * ((src_p ? 16 : 0) + 16 + 32 + 16);
+    // iterate (unless zero), operator (a, block), b
+    double nbytes = (double)P.N * ((src_p ? 16 : 0) + op_bytes(h, 0, 8) + 16);
     if (update) nbytes += (double)P.N * (2 * Rb + 16);
     if (want_r) nbytes += (double)P.N * 2 * Rb;
     if (res_p) nbytes += 8.0 * P.N;

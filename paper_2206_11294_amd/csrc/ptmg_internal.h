@@ -15,17 +15,40 @@ template <typename R> struct VT;
 template <> struct VT<float> { using v2 = float2; using v4 = float4; };
 template <> struct VT<double> { using v2 = double2; using v4 = double4; };
 
-// One grid level as the kernels see it.  Level 0 stores cell coefficients
-// (faces are their harmonic means); coarser levels store face coefficients
-// (lower face of each cell, 0 on the boundary).  Coefficients are
-// unscaled; kernels multiply by inv_h2.
+// Constants of the finest-grid operator of phases mode.  Per phase i
+// (0 liquid, 1 gas) the canonical block of Eqs. 29-32 is
+//   [[K1, -beta/dt^2], [-beta T/dt, K2]],  K1 = gamma/(rho c^2 dt^2),
+//   K2 = rho c_p/dt,
+// (Bpp = -l3 + l4 l2 and BpT = l4 l1 with l4 = beta/(rho c_p dt): the
+// beta^2 terms of l3 and l4 l2 cancel), with beta fixed or from Eq. (10)
+// at (p, T); the cell block is the C-average of the two,
+//   [[C K1_1 + (1-C) K1_2, -bb/dt^2], [-bb T/dt, C K2_1 + (1-C) K2_2]],
+// bb = C beta_1 + (1-C) beta_2, so a cell's block is kept as the pair
+// (C, bb) and T (compact block), and the cell coefficients are
+// a_p = 1/(C rho_1 + (1-C) rho_2), a_T = C k_1 + (1-C) k_2.
+template <typename R> struct CBK {
+    R K1[2], K2[2];
+    R idt, idt2;            // 1/dt, 1/dt^2
+};
+struct OpK {
+    double rho[2], k[2];
+    double beta[2];              // > 0: fixed; 0: Eq. (10)
+    double gcv[2], b[2], Pi[2];  // Eq. (10): beta = gcv / (gcv T + b (p + Pi))
+    CBK<double> blk;
+};
+
+// One grid level as the kernels see it.  Level 0 has cell coefficients
+// (faces are their harmonic means) and its block stored, or in phases mode
+// the compact block (cb, T0 and the constants k); coarser levels store
+// face coefficients (lower face of each cell, 0 on the boundary).
+// Coefficients are unscaled; kernels multiply by inv_h2.
 template <typename R> struct Lvl {
     int nx, ny, nz;
     long long N;
     double inv_h2;
-    const typename VT<R>::v2 *ac;              // cell (a_p, a_T), level 0 only
+    const typename VT<R>::v2 *ac;              // cell (a_p, a_T), level 0 stored only
     const typename VT<R>::v2 *fx, *fy, *fz;    // faces, coarse levels only
-    const typename VT<R>::v4 *B;               // block (pp, pT, Tp, TT)
+    const typename VT<R>::v4 *B;               // block (pp, pT, Tp, TT), unless cb
     typename VT<R>::v2 *u;                     // unknowns (p, T)
     typename VT<R>::v2 *f;                     // right-hand side (p, T)
     // axisymmetric r-z grids, level 0 only (null otherwise): per row j,
@@ -33,6 +56,12 @@ template <typename R> struct Lvl {
     // lower and upper face per unit volume, the cell radius and the lower
     // face radius in units of h
     const typename VT<R>::v4 *axm;
+    // level 0, compact block (cb non-null): (C, bb) per cell, T at
+    // T0[g & tmask] (tmask 0: one T for every cell), and the constants
+    const typename VT<R>::v2 *cb;
+    const R *T0;
+    long long tmask;
+    CBK<R> k;
 };
 
 // Outer FP64 residual arguments (finest grid).
@@ -43,7 +72,11 @@ template <typename RV> struct OuterArgs {
     const double4 *axm;            // r-z metric per row (2-D) or null
     int phases;                    // 1: paper form (b = (lp, lT)), 0: canonical
     const double2 *ac;             // FP64 cell coefficients
-    const double4 *B;              // FP64 block
+    const double4 *B;              // FP64 block, or
+    const double2 *cb;             // the compact block (non-null) as in Lvl
+    const double *T0;
+    long long tmask;
+    CBK<double> k;
     const double *b_p, *b_T;       // mode-native right-hand side (null: zero)
     const double *bshift;          // [2] sums of b (mean constraint) or null
     double bshift_scale;           // b -= bshift_scale * bshift (1/N: the mean)
@@ -73,11 +106,20 @@ struct AsmArgs {
     double p_adv_const, T_adv_const;
     // state
     const double *m1, *m2;
-    // outputs
+    // outputs: the cell coefficients and the stored block (B64 null: the
+    // block is kept compact) ...
     double2 *ac64;
     double4 *B64;
     float2 *ac32;   // may be null
     float4 *B32;    // may be null
+    // ... or, phases mode in mixed precision, the compact block with its T
+    // (T_cells 0: the one T in element 0); k64: the phases' constants
+    double2 *cb64;  // null: not compact
+    double *T64;
+    float2 *cb32;
+    float *T32;
+    int T_cells;
+    OpK k64;
     int *flags;     // [0] argument errors, [1] singular blocks, [2] nonzero B
 };
 
@@ -164,7 +206,8 @@ void launch_axi_metric(int ny, double4 *m64, float4 *m32, hipStream_t s);
 
 // ---- launch wrappers (implemented in ptmg_kernels.hip) --------------------
 void launch_assemble(const AsmArgs &a, hipStream_t s);
-void launch_paper_rhs(long long N, const double4 *B64, const double *p_adv, double p_const,
+// Eqs. (33)-(34) with the finest FP64 operator L (stored or derived).
+void launch_paper_rhs(const Lvl<double> &L, const double *p_adv, double p_const,
                       const double *T_adv, double T_const, const double *div, double dt,
                       double *b_p, double *b_T, hipStream_t s);
 

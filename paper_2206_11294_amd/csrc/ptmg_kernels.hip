@@ -76,6 +76,109 @@ __device__ __forceinline__ double2 harm2_exact(double2 a, double2 b)
     return make_double2(harm_exact(a.x, b.x), harm_exact(a.y, b.y));
 }
 
+// ------------------------------------------------ finest-grid operator
+// Phases mode (the assembly, FP64): cell coefficients a_p = 1/(C rho_1 +
+// (1-C) rho_2), a_T = C k_1 + (1-C) k_2, thermal dilations of Eq. (10) at
+// (p, T) (or fixed), and their C-average bb.  Divisions are correctly
+// rounded; every multiply-add is written out (fmadd) or kept as a
+// separate product, so that each kernel computes the same bits.
+__device__ __forceinline__ double2 phases_ac(const OpK &k, double C)
+{
+    const double g = 1.0 - C;
+    return make_double2(1.0 / fmadd(C, k.rho[0], g * k.rho[1]), fmadd(C, k.k[0], g * k.k[1]));
+}
+__device__ __forceinline__ double phases_beta(const OpK &k, int q, double p, double T)
+{
+    if (k.beta[q] > 0.0) return k.beta[q];
+    return k.gcv[q] / fmadd(k.gcv[q], T, k.b[q] * (p + k.Pi[q]));
+}
+
+// The block of a cell from its compact form (C, bb) and T.
+template <typename R>
+__device__ __forceinline__ typename VT<R>::v4 compact_B(const CBK<R> &k, R C, R bb, R T)
+{
+    const R g = R(1) - C;
+    typename VT<R>::v4 B;
+    B.x = fmadd(C, k.K1[0], g * k.K1[1]);
+    B.y = -bb * k.idt2;
+    B.z = -(bb * T) * k.idt;
+    B.w = fmadd(C, k.K2[0], g * k.K2[1]);
+    return B;
+}
+
+// The finest level's block at cell g, stored or compact (coarse levels:
+// the stored block).
+template <typename R>
+__device__ __forceinline__ typename VT<R>::v4 cell_B(const Lvl<R> &L, long long g)
+{
+    if (!L.cb) return L.B[g];
+    const typename VT<R>::v2 c = L.cb[g];
+    return compact_B(L.k, c.x, c.y, L.T0[g & L.tmask]);
+}
+template <typename R>
+__device__ __forceinline__ typename VT<R>::v2 cell_ac(const Lvl<R> &L, long long g)
+{
+    return L.ac[g];
+}
+
+// Two-stage access for the kernels that load planes ahead of their use:
+// the raw load (the stored block, or the compact block with T) and the
+// arithmetic that finishes it where it is used, so that the loads stay in
+// flight meanwhile.
+template <typename R>
+__device__ __forceinline__ typename VT<R>::v4 cell_B_raw(const Lvl<R> &L, long long g)
+{
+    if (!L.cb) return L.B[g];
+    const typename VT<R>::v2 c = L.cb[g];
+    typename VT<R>::v4 r;
+    r.x = c.x;
+    r.y = c.y;
+    r.z = L.T0[g & L.tmask];
+    r.w = R(0);
+    return r;
+}
+template <typename R>
+__device__ __forceinline__ typename VT<R>::v4 cell_B_fin(const Lvl<R> &L, typename VT<R>::v4 r)
+{
+    if (!L.cb) return r;
+    return compact_B(L.k, r.x, r.y, r.z);
+}
+
+// The smoothers' and the V-cycle's restriction's access: the block is
+// compact only on the finest level of an FP32 V-cycle, so an FP64 V-cycle's
+// kernels read the stored block and carry no compact path.
+template <typename R>
+__device__ __forceinline__ typename VT<R>::v4 sweep_B(const Lvl<R> &L, long long g)
+{
+    if constexpr (sizeof(R) == 8) return L.B[g];
+    else return cell_B(L, g);
+}
+template <typename R>
+__device__ __forceinline__ typename VT<R>::v4 sweep_B_raw(const Lvl<R> &L, long long g)
+{
+    if constexpr (sizeof(R) == 8) return L.B[g];
+    else return cell_B_raw(L, g);
+}
+template <typename R>
+__device__ __forceinline__ typename VT<R>::v4 sweep_B_fin(const Lvl<R> &L, typename VT<R>::v4 r)
+{
+    if constexpr (sizeof(R) == 8) return r;
+    else return cell_B_fin(L, r);
+}
+
+// The same for the FP64 outer residual (OuterArgs).
+template <typename A> __device__ __forceinline__ double4 op_B64_raw(const A &a, long long g)
+{
+    if (!a.cb) return a.B[g];
+    const double2 c = a.cb[g];
+    return make_double4(c.x, c.y, a.T0[g & a.tmask], 0.0);
+}
+template <typename A> __device__ __forceinline__ double4 op_B64_fin(const A &a, double4 r)
+{
+    if (!a.cb) return r;
+    return compact_B(a.k, r.x, r.y, r.z);
+}
+
 // Block-to-work mapping that is XCD-aware: the hardware deals
 // consecutive block ids to the 8 XCDs in turn, so XCD x runs blocks
 // b = x, x + 8, ...; block b takes logical index (blocks of XCDs before x)
@@ -103,7 +206,7 @@ __device__ __forceinline__ typename VT<R>::v2 face_coef(const Lvl<R> &L,
                                                         typename VT<R>::v2 am, long long me,
                                                         long long q, int axis, bool upper)
 {
-    if (CF) return harm2(am, L.ac[q]);
+    if (CF) return harm2(am, cell_ac(L, q));
     const typename VT<R>::v2 *F = axis == 0 ? L.fx : (axis == 1 ? L.fy : L.fz);
     return upper ? F[q] : F[me];
 }
@@ -130,7 +233,7 @@ __device__ __forceinline__ void gather(const Lvl<R> &L, int i, int j, int k, lon
     const R ih2 = (R)L.inv_h2;
     nbp = nbT = Sp = ST = R(0);
     V2 am;
-    if (CF) am = L.ac[me];
+    if (CF) am = cell_ac(L, me);
     const long long sx = 1, sy = L.nx, sz = (long long)L.nx * L.ny;
     auto acc = [&](long long q, int axis, bool upper) {
         V2 w = face_coef<R, CF>(L, am, me, q, axis, upper);
@@ -173,31 +276,13 @@ __device__ __forceinline__ void block_reduce_store(double *v, int width, double 
 static inline unsigned nblk(long long n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
 // ---------------------------------------------------------------- assembly
-// Per cell: thermal dilation (Eq. 10), the phase coefficients l1..l4
-// (Eqs. 29-32, l4 = beta/(rho c_p dt)), each phase's canonical block
-// (Bpp = -l3 + l4 l2, BpT = l4 l1, BTp = -l2, BTT = -l1), averaged with the
-// liquid fraction C (Sec. 3 averaging rule), and the cell coefficients
-// a_p = 1/(C rho_1 + (1-C) rho_2), a_T = C k_1 + (1-C) k_2.
-__device__ __forceinline__ double4 phase_block(const pt_phase &ph, double p, double T, double dt)
-{
-    double beta = ph.beta;
-    if (!(beta > 0.0)) {
-        double gcv = (ph.Gamma - 1.0) * ph.cv;
-        beta = gcv / (gcv * T + ph.b * (p + ph.Pi));
-    }
-    double rcp = ph.rho * ph.cp;
-    double l1 = -rcp / dt;
-    double l2 = beta * T / dt;
-    double l3 = -(ph.gamma / (ph.rho * ph.c * ph.c) - beta * beta * T / rcp) / (dt * dt);
-    double l4 = beta / (rcp * dt);
-    double4 B;
-    B.x = -l3 + l4 * l2;
-    B.y = l4 * l1;
-    B.z = -l2;
-    B.w = -l1;
-    return B;
-}
-
+// Per cell, the canonical block and the cell coefficients.  Phases mode:
+// per phase Eqs. 29-32 with l4 = beta/(rho c_p dt), which give
+// Bpp = -l3 + l4 l2 = gamma/(rho c^2 dt^2), BpT = l4 l1 = -beta/dt^2,
+// BTp = -l2 = -beta T/dt, BTT = -l1 = rho c_p/dt, averaged with the liquid
+// fraction C (the averaging rule of Sec. 3) and kept compact.  State mode:
+// each phase's block weighted by its fraction from its own density;
+// explicit mode: the given coefficients.
 __global__ __launch_bounds__(kBlock) void k_assemble(AsmArgs a)
 {
     long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
@@ -236,19 +321,24 @@ __global__ __launch_bounds__(kBlock) void k_assemble(AsmArgs a)
         ac.x = 1.0 / (mass[0] + mass[1]);
         ac.y = c * a.liq.k + (1.0 - c) * a.gas.k;
     } else if (a.mode == PT_COEF_PHASES) {
+        // cell coefficients, and the block kept compact: (C, bb) with
+        // bb = C beta_1 + (1 - C) beta_2, and T where it varies per cell
         double c = a.C[t];
         double p = a.p_adv ? a.p_adv[t] : a.p_adv_const;
         double T = a.T_adv ? a.T_adv[t] : a.T_adv_const;
         argbad = !(c >= 0.0 && c <= 1.0) || !isfinite(p) || !(T > 0.0) || !isfinite(T);
-        double4 B1 = phase_block(a.liq, p, T, a.dt);
-        double4 B2 = phase_block(a.gas, p, T, a.dt);
-        double g = 1.0 - c;
-        B.x = c * B1.x + g * B2.x;
-        B.y = c * B1.y + g * B2.y;
-        B.z = c * B1.z + g * B2.z;
-        B.w = c * B1.w + g * B2.w;
-        ac.x = 1.0 / (c * a.liq.rho + g * a.gas.rho);
-        ac.y = c * a.liq.k + g * a.gas.k;
+        const double bb = fmadd(c, phases_beta(a.k64, 0, p, T), (1.0 - c) * phases_beta(a.k64, 1, p, T));
+        B = compact_B(a.k64.blk, c, bb, T);
+        ac = phases_ac(a.k64, c);
+        if (a.cb64) {
+            const bool wT = a.T_cells || t == 0;
+            a.cb64[t] = make_double2(c, bb);
+            a.cb32[t] = make_float2((float)c, (float)bb);
+            if (wT) {
+                a.T64[t] = T;
+                a.T32[t] = (float)T;
+            }
+        }
     } else {
         ac.x = a.alpha_p ? a.alpha_p[t] : a.alpha_p_const;
         ac.y = a.alpha_T ? a.alpha_T[t] : a.alpha_T_const;
@@ -271,11 +361,9 @@ __global__ __launch_bounds__(kBlock) void k_assemble(AsmArgs a)
     if (argbad) atomicOr(&a.flags[FLAG_ARG], 1);
     if (sing) atomicOr(&a.flags[FLAG_SINGULAR], 1);
     a.ac64[t] = ac;
-    a.B64[t] = B;
-    if (a.ac32) {
-        a.ac32[t] = make_float2((float)ac.x, (float)ac.y);
-        a.B32[t] = make_float4((float)B.x, (float)B.y, (float)B.z, (float)B.w);
-    }
+    if (a.B64) a.B64[t] = B;
+    if (a.ac32) a.ac32[t] = make_float2((float)ac.x, (float)ac.y);
+    if (a.B32) a.B32[t] = make_float4((float)B.x, (float)B.y, (float)B.z, (float)B.w);
 }
 
 void launch_assemble(const AsmArgs &a, hipStream_t s)
@@ -375,15 +463,14 @@ int launch_dot2(long long N, const double *x_p, const double *x_T, const double 
 
 // Paper right-hand side (Eqs. 33-34) from the cell block:
 // l1 = -BTT, l2 = -BTp, l4 = BpT / l1, l3 = -Bpp + l4 l2.
-__global__ __launch_bounds__(kBlock) void k_paper_rhs(long long N, const double4 *B64,
-                                                      const double *p_adv, double p_const,
-                                                      const double *T_adv, double T_const,
-                                                      const double *div, double dt,
+__global__ __launch_bounds__(kBlock) void k_paper_rhs(Lvl<double> L, const double *p_adv,
+                                                      double p_const, const double *T_adv,
+                                                      double T_const, const double *div, double dt,
                                                       double *b_p, double *b_T)
 {
     long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
-    if (t >= N) return;
-    double4 B = B64[t];
+    if (t >= L.N) return;
+    double4 B = cell_B(L, t);
     double l1 = -B.w, l2 = -B.z, l4 = B.y / l1, l3 = -B.x + l4 * l2;
     double p = p_adv ? p_adv[t] : p_const;
     double T = T_adv ? T_adv[t] : T_const;
@@ -392,11 +479,11 @@ __global__ __launch_bounds__(kBlock) void k_paper_rhs(long long N, const double4
     b_p[t] = l3 * p + d / dt;
 }
 
-void launch_paper_rhs(long long N, const double4 *B64, const double *p_adv, double p_const,
+void launch_paper_rhs(const Lvl<double> &L, const double *p_adv, double p_const,
                       const double *T_adv, double T_const, const double *div, double dt,
                       double *b_p, double *b_T, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_paper_rhs, dim3(nblk(N)), dim3(kBlock), 0, s, N, B64, p_adv, p_const,
+    hipLaunchKernelGGL(k_paper_rhs, dim3(nblk(L.N)), dim3(kBlock), 0, s, L, p_adv, p_const,
                        T_adv, T_const, div, dt, b_p, b_T);
 }
 
@@ -496,7 +583,7 @@ __device__ __forceinline__ void rb_cell(const Lvl<R> &L, int i, int j, int k, lo
     R nbp, nbT, Sp, ST;
     gather<R, DIM, CF, USE_U>(L, i, j, k, me, nbp, nbT, Sp, ST);
     const V2 f = L.f[me];
-    const V4 b = L.B[me];
+    const V4 b = sweep_B(L, me);
     const R gp = f.x + nbp, gT = f.y + nbT;
     const R a = b.x + Sp, d = b.w + ST;
     const R inv = quot(R(1), a * d - b.y * b.z);
@@ -517,7 +604,7 @@ __device__ __forceinline__ typename VT<R>::v2 residual_cell(const Lvl<R> &F, int
     gather<R, DIM, CF, true>(F, i, j, k, me, nbp, nbT, Sp, ST);
     const V2 u = F.u[me];
     const V2 f = F.f[me];
-    const V4 b = F.B[me];
+    const V4 b = sweep_B(F, me);
     const R Ap = Sp * u.x - nbp + b.x * u.x + b.y * u.y;
     const R AT = ST * u.y - nbT + b.z * u.x + b.w * u.y;
     V2 r;
@@ -770,7 +857,7 @@ __device__ __forceinline__ void coarsen_cell(const Lvl<RIN> &F, int cnx, int cny
         const int c[3] = {base[0] + (m & 1), base[1] + ((m >> 1) & 1),
                           DIM == 3 ? base[2] + ((m >> 2) & 1) : 0};
         const long long me = c[0] + (long long)F.nx * (c[1] + (long long)F.ny * c[2]);
-        const V4 b = F.B[me];
+        const V4 b = cell_B(F, me);
         if (CF && F.axm) {
             // r-z: level 1 holds the volume-weighted equations (blocks
             // times the cell radius, faces times the face area below)
@@ -790,7 +877,7 @@ __device__ __forceinline__ void coarsen_cell(const Lvl<RIN> &F, int cnx, int cny
             if (c[a] != base[a] || Ci[a] == 0) continue;
             V2 w;
             if (CF) {
-                w = harm2(F.ac[me], F.ac[me - st[a]]);
+                w = harm2(cell_ac(F, me), cell_ac(F, me - st[a]));
                 if (F.axm) {
                     // axial faces: area ~ cell radius; radial: face radius
                     const auto ar = a == 0 ? F.axm[c[1]].z : F.axm[c[1]].w;
@@ -884,7 +971,7 @@ __device__ double dense_row_diag(const Lvl<R> &L, long long cell, int c, double 
     int i, j, k;
     decode(cell, L.nx, L.ny, i, j, k);
     V2 am;
-    if (CF) am = L.ac[cell];
+    if (CF) am = cell_ac(L, cell);
     const long long st[3] = {1, L.nx, (long long)L.nx * L.ny};
     const int ii[3] = {i, j, k};
     const int nn[3] = {L.nx, L.ny, L.nz};
@@ -901,7 +988,7 @@ __device__ double dense_row_diag(const Lvl<R> &L, long long cell, int c, double 
             if (row) row[2 * q + c] -= wc;
         }
     }
-    const typename VT<R>::v4 b = L.B[cell];
+    const typename VT<R>::v4 b = cell_B(L, cell);
     return S + (double)(c == 0 ? b.x : b.w);
 }
 
@@ -916,7 +1003,7 @@ __device__ __forceinline__ void dense_row(const Lvl<R> &L, int pin_mean, double 
     double *row = M + r * m;
     for (long long q = 0; q < m; q++) row[q] = 0.0;
     const double D = dense_row_diag<R, DIM, CF>(L, cell, c, row);
-    const V4 b = L.B[cell];
+    const V4 b = cell_B(L, cell);
     row[r] += D;
     row[2 * cell + (1 - c)] += (double)(c == 0 ? b.y : b.z);
     if (pin_mean) {
@@ -1024,7 +1111,7 @@ __global__ __launch_bounds__(kBlock) void k_export_op(Lvl<R> L, double *faces, d
     const int ii[3] = {i, j, k};
     const long long st[3] = {1, L.nx, (long long)L.nx * L.ny};
     V2 am;
-    if (CF) am = L.ac[t];
+    if (CF) am = cell_ac(L, t);
     for (int a = 0; a < 3; a++) {
         double wp = 0.0, wT = 0.0;
         if (a < DIM && ii[a] > 0) {
@@ -1035,7 +1122,7 @@ __global__ __launch_bounds__(kBlock) void k_export_op(Lvl<R> L, double *faces, d
         faces[(0 * 3 + a) * L.N + t] = wp;
         faces[(1 * 3 + a) * L.N + t] = wT;
     }
-    const typename VT<R>::v4 b = L.B[t];
+    const typename VT<R>::v4 b = cell_B(L, t);
     Bout[t] = (double)b.x;
     Bout[L.N + t] = (double)b.y;
     Bout[2 * L.N + t] = (double)b.z;
@@ -1305,7 +1392,7 @@ __global__ __launch_bounds__(TX *TY) void k_rb_fused3(Lvl<R> L, typename VT<R>::
                         S.pfy[i] = L.fy[g];
                         S.pfz[i] = L.fz[g];
                     } else {
-                        S.pa[i] = L.ac[g];
+                        S.pa[i] = cell_ac(L, g);
                     }
                     if (!ZG) S.pu[i] = L.u[g];
                 }
@@ -1405,12 +1492,12 @@ __global__ __launch_bounds__(TX *TY) void k_rb_fused3(Lvl<R> L, typename VT<R>::
         red_cell(k + 1, S.rc, g);
         if (S.rc >= 0) {
             S.rf = L.f[g];
-            S.rB = L.B[g];
+            S.rB = sweep_B_raw(L, g);
         }
         black_cell(k, S.bc, g);
         if (S.bc >= 0) {
             S.bf = L.f[g];
-            S.bB = L.B[g];
+            S.bB = sweep_B_raw(L, g);
         }
     };
     // plane step k from the set `cur`; the loads of step k+2 go to `ahead`
@@ -1419,9 +1506,9 @@ __global__ __launch_bounds__(TX *TY) void k_rb_fused3(Lvl<R> L, typename VT<R>::
         load_step(k + 2, ahead);
         __syncthreads();
         write_plane(k - 1);
-        if (cur.rc >= 0) update(k + 1, cur.rc, cur.rf, cur.rB);
+        if (cur.rc >= 0) update(k + 1, cur.rc, cur.rf, sweep_B_fin(L, cur.rB));
         __syncthreads();
-        if (cur.bc >= 0) update(k, cur.bc, cur.bf, cur.bB);
+        if (cur.bc >= 0) update(k, cur.bc, cur.bf, sweep_B_fin(L, cur.bB));
     };
 
     // ---- prologue: planes z0-2 .. z0+1, red on z0-1 and z0
@@ -1437,7 +1524,7 @@ __global__ __launch_bounds__(TX *TY) void k_rb_fused3(Lvl<R> L, typename VT<R>::
         int c;
         long long g;
         red_cell(z, c, g);
-        if (c >= 0) update(z, c, L.f[g], L.B[g]);
+        if (c >= 0) update(z, c, L.f[g], sweep_B(L, g));
         __syncthreads();
     }
     // in flight for steps z0 and z0+1
@@ -1516,7 +1603,7 @@ __global__ __launch_bounds__(TX *TY) void k_rb_fused3c(Lvl<R> L, typename VT<R>:
                 const int gx = x0 + c % PX - 2, gy = y0 + c / PX - 2;
                 if (z >= 0 && z < L.nz && gx >= 0 && gx < L.nx && gy >= 0 && gy < L.ny) {
                     const long long g = gx + (long long)L.nx * gy + nxy * z;
-                    S.pa[i] = L.ac[g];
+                    S.pa[i] = cell_ac(L, g);
                     if (!ZG) S.pu[i] = L.u[g];
                 }
             }
@@ -1639,12 +1726,12 @@ __global__ __launch_bounds__(TX *TY) void k_rb_fused3c(Lvl<R> L, typename VT<R>:
         red_cell(k + 1, S.rc, g);
         if (S.rc >= 0) {
             S.rf = L.f[g];
-            S.rB = L.B[g];
+            S.rB = sweep_B_raw(L, g);
         }
         black_cell(k, S.bc, g);
         if (S.bc >= 0) {
             S.bf = L.f[g];
-            S.bB = L.B[g];
+            S.bB = sweep_B_raw(L, g);
         }
     };
     // z faces of this thread's column: zq0 is the lower face of its black
@@ -1659,9 +1746,9 @@ __global__ __launch_bounds__(TX *TY) void k_rb_fused3c(Lvl<R> L, typename VT<R>:
         write_plane(k - 1);
         V2 wzm, wzp;
         wzm.x = wzm.y = wzp.x = wzp.y = R(0);
-        if (cur.rc >= 0) update_red(k + 1, cur.rc, cur.rf, cur.rB, wzm, wzp);
+        if (cur.rc >= 0) update_red(k + 1, cur.rc, cur.rf, sweep_B_fin(L, cur.rB), wzm, wzp);
         __syncthreads();
-        if (cur.bc >= 0) update_black(k, cur.bc, cur.bf, cur.bB, zq0, wzm);
+        if (cur.bc >= 0) update_black(k, cur.bc, cur.bf, sweep_B_fin(L, cur.bB), zq0, wzm);
         zq0 = zq1;
         zq1 = wzp;
     };
@@ -1686,14 +1773,14 @@ __global__ __launch_bounds__(TX *TY) void k_rb_fused3c(Lvl<R> L, typename VT<R>:
         long long g;
         V2 wzm, wzp;
         red_cell(z0 - 1, c, g);
-        if (c >= 0) update_red(z0 - 1, c, L.f[g], L.B[g], wzm, wzp);
+        if (c >= 0) update_red(z0 - 1, c, L.f[g], sweep_B(L, g), wzm, wzp);
         if (c >= 0 && t < NCOL) zq0 = wzp;
         fetch_plane(z0 + 1, S);
         __syncthreads();
         store_plane(z0 + 1, S);
         __syncthreads();
         red_cell(z0, c, g);
-        if (c >= 0) update_red(z0, c, L.f[g], L.B[g], wzm, wzp);
+        if (c >= 0) update_red(z0, c, L.f[g], sweep_B(L, g), wzm, wzp);
         if (c >= 0 && t < NCOL) zq1 = wzp;
         __syncthreads();
     }
@@ -1775,7 +1862,7 @@ __global__ __launch_bounds__(TX *TY) void k_rb_fused3r(Lvl<R> L, Lvl<R> C,
                 const int gx = x0 + c % PX - G, gy = y0 + c / PX - G;
                 if (z >= 0 && z < L.nz && gx >= 0 && gx < L.nx && gy >= 0 && gy < L.ny) {
                     const long long g = gx + (long long)L.nx * gy + nxy * z;
-                    S.pa[i] = L.ac[g];
+                    S.pa[i] = cell_ac(L, g);
                     if (!ZG) S.pu[i] = L.u[g];
                 }
             }
@@ -1860,7 +1947,7 @@ __global__ __launch_bounds__(TX *TY) void k_rb_fused3r(Lvl<R> L, Lvl<R> C,
         if (want && rmine) {
             const long long g = gxr + (long long)L.nx * gyr + nxy * q;
             const V2 f = L.f[g];
-            const V4 B = L.B[g];
+            const V4 B = sweep_B(L, g);
             R nbp = R(0), nbT = R(0), Sp = R(0), ST = R(0);
             auto nb = [&](V2 aq, V2 uq) {
                 V2 w = harm2(am, aq);
@@ -1920,12 +2007,12 @@ __global__ __launch_bounds__(TX *TY) void k_rb_fused3r(Lvl<R> L, Lvl<R> C,
         red_cell(k + 1, S.rc, g);
         if (S.rc >= 0) {
             S.rf = L.f[g];
-            S.rB = L.B[g];
+            S.rB = sweep_B_raw(L, g);
         }
         black_cell(k, S.bc, g);
         if (S.bc >= 0) {
             S.bf = L.f[g];
-            S.bB = L.B[g];
+            S.bB = sweep_B_raw(L, g);
         }
     };
     // plane step k from `cur`; the loads of step k+1 go to `ahead`
@@ -1934,10 +2021,10 @@ __global__ __launch_bounds__(TX *TY) void k_rb_fused3r(Lvl<R> L, Lvl<R> C,
         load_step(k + 1, ahead);
         __syncthreads();
         write_plane(k - 1);
-        if (cur.rc >= 0) update(k + 1, cur.rc, cur.rf, cur.rB);
+        if (cur.rc >= 0) update(k + 1, cur.rc, cur.rf, sweep_B_fin(L, cur.rB));
         if (k - 2 >= z0 - 1) residual(k - 2, k - 2 >= z0);
         __syncthreads();
-        if (cur.bc >= 0) update(k, cur.bc, cur.bf, cur.bB);
+        if (cur.bc >= 0) update(k, cur.bc, cur.bf, sweep_B_fin(L, cur.bB));
         if (k - 2 >= z0) restrict_plane(k - 2);
     };
 
@@ -1954,7 +2041,7 @@ __global__ __launch_bounds__(TX *TY) void k_rb_fused3r(Lvl<R> L, Lvl<R> C,
         int c;
         long long g;
         red_cell(z, c, g);
-        if (c >= 0) update(z, c, L.f[g], L.B[g]);
+        if (c >= 0) update(z, c, L.f[g], sweep_B(L, g));
         __syncthreads();
     }
     // steps z0-1 .. z1: black on z0-1 .. z1, red on z0 .. z1+1
@@ -2030,7 +2117,7 @@ __global__ __launch_bounds__(TX *TY) void k_rb_tile2(Lvl<R> L, typename VT<R>::v
                 fx = L.fx[g];
                 fy = L.fy[g];
             } else {
-                a = L.ac[g];
+                a = cell_ac(L, g);
             }
             if (!ZG) u = L.u[g];
         }
@@ -2072,7 +2159,7 @@ __global__ __launch_bounds__(TX *TY) void k_rb_tile2(Lvl<R> L, typename VT<R>::v
             accw(yp, c + PX);
         }
         V2 o;
-        block_solve<R>(L.f[g], L.B[g], gp, gT, Sp, ST, o);
+        block_solve<R>(L.f[g], sweep_B(L, g), gp, gT, Sp, ST, o);
         su[c] = o;
     };
     if (t < RW * (TY + 2)) {   // red cells ((x+y) even) of the tile and a ring of one
@@ -2145,7 +2232,7 @@ __global__ __launch_bounds__(TX *TY) void k_rb_tile2x(Lvl<R> L, Lvl<R> C,
         u.x = u.y = a.x = a.y = R(0);
         if (gx >= 0 && gx < L.nx && gy >= 0 && gy < L.ny) {
             const long long g = gx + (long long)L.nx * gy;
-            a = L.ac[g];
+            a = cell_ac(L, g);
             if (!ZG) {
                 u = L.u[g];
                 if (PRO) {
@@ -2176,7 +2263,7 @@ __global__ __launch_bounds__(TX *TY) void k_rb_tile2x(Lvl<R> L, Lvl<R> C,
         accw(wym, c - PX);
         accw(wyp, c + PX);
         V2 o;
-        block_solve<R>(L.f[g], L.B[g], gp, gT, Sp, ST, o);
+        block_solve<R>(L.f[g], sweep_B(L, g), gp, gT, Sp, ST, o);
         su[c] = o;
     };
     auto weight = [&](V2 am, int q) { return harm2(am, sa[q]); };
@@ -2279,7 +2366,7 @@ __global__ __launch_bounds__(TX *TY) void k_rb_tile2x(Lvl<R> L, Lvl<R> C,
         nb(wym, c - PX);
         nb(wyp, c + PX);
         const V2 f = L.f[g];
-        const V4 B = L.B[g];
+        const V4 B = sweep_B(L, g);
         const R Ap = Sp * um.x - nbp + B.x * um.x + B.y * um.y;
         const R AT = ST * um.y - nbT + B.z * um.x + B.w * um.y;
         r.x = f.x - Ap;
@@ -2439,7 +2526,7 @@ __device__ __forceinline__ void half_cycle2(const Lvl<R> &L, const Lvl<R> &C,
                 if (in_ring(lx, ly, DMAX) && inside(gx, gy)) {
                     const long long g = gx + (long long)L.nx * gy;
                     f[q][k] = L.f[g];
-                    B[q][k] = L.B[g];
+                    B[q][k] = sweep_B(L, g);
                 }
             }
         }
@@ -2851,7 +2938,7 @@ __global__ __launch_bounds__(TX *TY) void k_outer_zm(OuterArgs<RV> a, int NX, in
         auto fetch_cell = [&](int z) {
             if (mine && z < z1) {
                 const long long g = gx + (long long)NX * gy + nxy * z;
-                Bn = a.B[g];
+                Bn = op_B64_raw(a, g);
                 bpn = a.b_p ? a.b_p[g] : 0.0;
                 bTn = a.b_T ? a.b_T[g] : 0.0;
             }
@@ -2861,7 +2948,7 @@ __global__ __launch_bounds__(TX *TY) void k_outer_zm(OuterArgs<RV> a, int NX, in
         fetch(z0);
         store(z0);
         fetch_cell(z0);
-        double4 B = Bn;
+        double4 B = op_B64_fin(a, Bn);
         double bp0 = bpn, bT0 = bTn;
         fetch(z0 + 1);
         for (int k = z0; k < z1; k++) {
@@ -2936,7 +3023,7 @@ __global__ __launch_bounds__(TX *TY) void k_outer_zm(OuterArgs<RV> a, int NX, in
                 acc[2] += bp * bp;
                 acc[3] += bT * bT;
             }
-            B = Bn;
+            B = op_B64_fin(a, Bn);
             bp0 = bpn;
             bT0 = bTn;
         }
@@ -3026,7 +3113,7 @@ __global__ __launch_bounds__(TX *TY) void k_restrict_zm(Lvl<R> F, Lvl<R> C, int 
             if (c < PS && z >= 0 && z < NZ && gx >= 0 && gx < NX && gy >= 0 && gy < NY) {
                 const long long g = gx + (long long)NX * gy + nxy * z;
                 pu[i] = F.u[g];
-                pa[i] = F.ac[g];
+                pa[i] = cell_ac(F, g);
             }
         }
     };
@@ -3051,7 +3138,7 @@ __global__ __launch_bounds__(TX *TY) void k_restrict_zm(Lvl<R> F, Lvl<R> C, int 
         if (mine && z < z1) {
             const long long g = gx + (long long)NX * gy + nxy * z;
             fn = F.f[g];
-            Bn = F.B[g];
+            Bn = sweep_B_raw(F, g);
         }
     };
     // coarse cell of this thread (t < CX * CY)
@@ -3067,7 +3154,7 @@ __global__ __launch_bounds__(TX *TY) void k_restrict_zm(Lvl<R> F, Lvl<R> C, int 
     store(z0);
     fetch_cell(z0);
     V2 f = fn;
-    V4 B = Bn;
+    V4 B = sweep_B_fin(F, Bn);
     fetch(z0 + 1);
     for (int k = z0; k < z1; k++) {
         store(k + 1);
@@ -3136,7 +3223,7 @@ __global__ __launch_bounds__(TX *TY) void k_restrict_zm(Lvl<R> F, Lvl<R> C, int 
             }
         }
         f = fn;
-        B = Bn;
+        B = sweep_B_fin(F, Bn);
     }
 }
 
@@ -3334,6 +3421,9 @@ __global__ __launch_bounds__(DIM == 3 ? 512 : 1024) void k_tail(TailArgs<R> A)
         v.inv_h2 = sih2[q];
         v.ac = nullptr;
         v.axm = nullptr;
+        v.cb = nullptr;                 // stored faces and block
+        v.T0 = nullptr;
+        v.tmask = 0;
         v.u = (V2 *)(lds + smeta[q][4]);
         v.f = (V2 *)(lds + smeta[q][5]);
         v.fx = (const V2 *)(lds + smeta[q][6]);
