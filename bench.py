@@ -423,6 +423,9 @@ def main():
     ap.add_argument("--coarse-sweeps", type=int, default=None,
                     help="16 nu1 + nu2 below the finest level (PT_OPT_COARSE_SWEEPS; "
                          "default: the workload's)")
+    ap.add_argument("--w-levels", type=int, default=None,
+                    help="levels below the finest visited as a W-cycle (PT_OPT_W_LEVELS; "
+                         "default: 2 for diffusive 3-D steps, else 0, the V-cycle)")
     ap.add_argument("--tail-cells", type=int, default=None,
                     help="largest level of the single-block tail (PT_OPT_TAIL_CELLS)")
     ap.add_argument("--timing-every", type=int, default=7,
@@ -473,6 +476,12 @@ def main():
     args.nu1 = nu1 if args.nu1 is None else args.nu1
     args.nu2 = nu2 if args.nu2 is None else args.nu2
     args.coarse_sweeps = coarse if args.coarse_sweeps is None else args.coarse_sweeps
+    if args.w_levels is None:
+        # diffusive 3-D steps: two coarse corrections per visit on levels 1
+        # and 2 (17 instead of 37 cycles at 256^3, 33 % less time); the
+        # acoustic steps and 2-D keep the V-cycle (in 2-D the coarse levels
+        # cost too much to visit twice)
+        args.w_levels = 2 if (args.stiff and prob.dim == 3) else 0
     method = ptmg.PT_SOLVE_BICGSTAB if args.method == "bicgstab" else ptmg.PT_SOLVE_DEFECT
     print(f"# workload {name} grid {prob.n} precision {prec_name} rtol {rtol:g}",
           file=sys.stderr, flush=True)
@@ -516,7 +525,7 @@ def main():
                       "pt_mg_step (update + paper RHS + solve)")
                    + (" + pt_mg_downstream" if run["faces"] else ""),
                    "method": args.method, "time_step": "diffusive" if args.stiff else "acoustic",
-                   "tail_levels": run["tail_levels"],
+                   "tail_levels": run["tail_levels"], "w_levels": args.w_levels,
                    "sweeps": {"finest": [args.nu1, args.nu2],
                               "coarse": (list(divmod(args.coarse_sweeps, 16))
                                          if args.coarse_sweeps else [args.nu1, args.nu2])},
@@ -577,6 +586,7 @@ def timed_steps(prob, prec, rtol, method, args, roofline_timing=True):
         if args.tail_cells is not None:
             h.set_option(ptmg.PT_OPT_TAIL_CELLS, args.tail_cells)
         h.set_option(ptmg.PT_OPT_COARSE_SWEEPS, args.coarse_sweeps)
+        h.set_option(ptmg.PT_OPT_W_LEVELS, args.w_levels)
         p = torch.empty(prob.ncells, dtype=torch.float64, device="cuda")
         T = torch.empty_like(p)
         rhs_p, rhs_T = torch.empty_like(p), torch.empty_like(p)

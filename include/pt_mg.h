@@ -465,7 +465,18 @@ long long pt_mg_last_cell_updates(pt_mg_t h);
  *    the full counts there.  Unlike the options
  *    above this changes the V-cycle, and so the iterates and cycle
  *    counts; the converged solution is the one the tolerance admits
- *    either way. */
+ *    either way.
+ *  PT_OPT_W_LEVELS: w >= 0; each visit of levels 1 .. w (those above the
+ *    single-block tail) corrects twice on its coarse level (a second pass
+ *    of sweeps, residual, coarse cycle, prolongation and sweeps from the
+ *    iterate the first left), a W-cycle there; the finest level and the
+ *    tail stay V.  0 (default): the V-cycle.  On time steps far above the
+ *    acoustic one (diffusion-dominated, with the 1000:1 density jump)
+ *    the V-cycle's coarse levels lose accuracy level by level and the
+ *    cycle contracts ever more slowly as the grid grows; the W-cycle's
+ *    contraction stays near the two-grid one, for more coarse-level work
+ *    per cycle.  Like PT_OPT_COARSE_SWEEPS this changes the iterates and
+ *    cycle counts, not the converged solution. */
 typedef enum {
     PT_OPT_GRAPHS = 1,
     PT_OPT_TAIL = 2,
@@ -473,7 +484,8 @@ typedef enum {
     PT_OPT_TIMING_EVERY = 4,
     PT_OPT_SPECULATE = 5,
     PT_OPT_TAIL_CELLS = 6,
-    PT_OPT_COARSE_SWEEPS = 7
+    PT_OPT_COARSE_SWEEPS = 7,
+    PT_OPT_W_LEVELS = 8
 } pt_option;
 int pt_mg_set_option(pt_mg_t h, int option, int value);
 int pt_mg_get_option(pt_mg_t h, int option);

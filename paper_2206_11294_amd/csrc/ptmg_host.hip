@@ -274,6 +274,9 @@ struct pt_mg_s {
     // sweep each way there saves time on acoustic steps but costs cycles on
     // diffusion-dominated ones, so the default keeps the solve's own counts.
     int coarse_nu = 0;
+    // levels 1 .. w_levels (above the single-block tail) visit their coarse
+    // level twice per visit (W-cycle there); 0: V-cycle
+    int w_levels = 0;
 
     template <typename T> T *at(size_t off) { return off == (size_t)-1 ? nullptr : (T *)(base + off); }
     double2 *ac64() { return at<double2>(P.o_ac64); }
@@ -643,7 +646,7 @@ template <typename R> void coarse_cycle(pt_mg_t h, int nu1, int nu2)
         return;
     }
     const int key = nu1 * 16 + nu2 + (h->use_fused ? 256 : 0) + (h->use_tail ? 512 : 0) +
-                    (h->tail_lt << 10);
+                    (h->tail_lt << 10) + (std::min(h->w_levels, 63) << 16);
     const unsigned state = h->u_cur & ~1u;
     CoarseGraph *g = nullptr;
     for (auto &c : h->graphs)
@@ -727,8 +730,32 @@ template <typename R> void tail_cycle(pt_mg_t h, int nu1, int nu2)
     h->end();
 }
 
-// V(nu1, nu2) cycle on level l for A e = f_l, e in u_l, from a zero guess.
+template <typename R> void vcycle_visit(pt_mg_t h, int l, int nu1, int nu2);
+
+// The second coarse correction of a W visit of level l (from the iterate
+// its first one left): sweeps, residual and restriction, the coarse cycle,
+// prolongation, sweeps.  Separate kernels, with the arithmetic of the
+// fused ones.
+template <typename R> void w_repeat(pt_mg_t h, int l, int nu1, int nu2)
+{
+    smooth<R>(h, l, nu1, false);
+    restrict_level<R>(h, l);
+    vcycle<R>(h, l + 1, nu1, nu2);
+    prolong_level<R>(h, l);
+    smooth<R>(h, l, nu2, false);
+}
+
+// Multigrid cycle on level l for A e = f_l, e in u_l, from a zero guess:
+// a V(nu1, nu2) cycle, with two coarse corrections per visit on levels
+// 1 .. w_levels above the tail (PT_OPT_W_LEVELS).
 template <typename R> void vcycle(pt_mg_t h, int l, int nu1, int nu2)
+{
+    vcycle_visit<R>(h, l, nu1, nu2);
+    const bool tail = h->use_tail && h->tail_lt > 0 && l >= h->tail_lt;
+    if (l >= 1 && l <= h->w_levels && !tail && l < h->P.nlev - 1) w_repeat<R>(h, l, nu1, nu2);
+}
+
+template <typename R> void vcycle_visit(pt_mg_t h, int l, int nu1, int nu2)
 {
     if (h->use_tail && h->tail_lt > 0 && l == h->tail_lt) {
         tail_cycle<R>(h, nu1, nu2);
@@ -2162,6 +2189,9 @@ int pt_mg_set_option(pt_mg_t h, int option, int value)
     else if (option == PT_OPT_TIMING_EVERY) {
         if (value < 1) return fail(h, PT_ERR_ARG, "PT_OPT_TIMING_EVERY must be >= 1");
         h->timing_every = value;
+    } else if (option == PT_OPT_W_LEVELS) {
+        if (value < 0) return fail(h, PT_ERR_ARG, "PT_OPT_W_LEVELS must be >= 0");
+        h->w_levels = value;
     } else return fail(h, PT_ERR_ARG, "unknown option");
     return PT_OK;
 }
@@ -2176,6 +2206,7 @@ int pt_mg_get_option(pt_mg_t h, int option)
     if (option == PT_OPT_TAIL) return (h->use_tail && h->tail_lt > 0) ? h->P.nlev - h->tail_lt : 0;
     if (option == PT_OPT_TAIL_CELLS) return (int)h->tail_max_cells;
     if (option == PT_OPT_COARSE_SWEEPS) return h->coarse_nu;
+    if (option == PT_OPT_W_LEVELS) return h->w_levels;
     return -1;
 }
 

@@ -24,6 +24,7 @@ PT_MAX_HIST = 64
 PT_OPT_GRAPHS, PT_OPT_TAIL, PT_OPT_FUSED, PT_OPT_TIMING_EVERY, PT_OPT_SPECULATE = 1, 2, 3, 4, 5
 PT_OPT_TAIL_CELLS = 6
 PT_OPT_COARSE_SWEEPS = 7
+PT_OPT_W_LEVELS = 8
 KERNEL_CLASSES = ["outer_residual", "smooth_fine", "smooth_coarse", "restrict", "prolong",
                   "coarse_solve", "other", "downstream"]
 

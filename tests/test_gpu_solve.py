@@ -636,6 +636,60 @@ def test_coarse_sweeps_option():
             h.set_option(ptmg.PT_OPT_COARSE_SWEEPS, bad)
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_w_levels_match_oracle_and_help_stiff(prec):
+    """PT_OPT_W_LEVELS: two coarse corrections per visit on the levels above
+    the tail.  On stiff (diffusive-CFL) 2-D and 3-D steps the solve gives
+    the oracle's answer in fewer cycles than the V-cycle; the fused and the
+    separate kernels, and graph replay and direct launches, give the same
+    bits; negative values are refused."""
+    import workloads.device as D
+    from paper_2206_11294_amd import ptmg
+    # (problem, rtol, largest tail level): the 3-D grid keeps its tail to
+    # 3^3 cells so that two levels run as a W-cycle; with the diffusive
+    # step the 3-D paper-form residual has a rounding floor near 3e-11
+    cases = [
+        (W.bubble_problem("w2", 2, (256, 256), [(0.5, 0.5)], [0.1], W.P0, W.P0,
+                          div_amp=1e-6, div_seed=2, stiff=True), 1e-11, 0),
+        (W.bubble_problem("w3", 3, (24, 24, 24), [(0.5, 0.5, 0.3)], [0.25], W.P0, 10 * W.P0,
+                          div_amp=1e-6, div_seed=4, stiff=True), 1e-10, 27),
+    ]
+    for prob, rtol, tail_cells in cases:
+        op, b_p, b_T, p_ref, T_ref = orc.solve(prob, direct_max=70000)
+        stream = torch.cuda.Stream()
+        with torch.cuda.stream(stream):
+            h, gb_p, gb_T, _ = D.setup(prob, prec, stream=stream)
+            h.set_option(ptmg.PT_OPT_TAIL_CELLS, tail_cells)
+            assert h.get_option(ptmg.PT_OPT_W_LEVELS) == 0
+            cyc = {}
+            for w in (0, 8):
+                h.set_option(ptmg.PT_OPT_W_LEVELS, w)
+                p, T = torch.empty_like(gb_p), torch.empty_like(gb_T)
+                info = h.solve(gb_p, gb_T, p, T, rtol=rtol, max_cycles=200)
+                assert info["status"] == 0, (prob.name, w, info["status"])
+                P, Tt = host(p), host(T)
+                assert rel_err(P, p_ref) <= 1e-8 and rel_err(Tt, T_ref) <= 1e-8, (prob.name, w)
+                assert orc.relres(op, b_p, b_T, P, Tt).max() <= 2 * rtol, (prob.name, w)
+                cyc[w] = info["cycles"]
+            assert cyc[8] < cyc[0], (prob.name, cyc)
+            # the same W-cycle through the other paths
+            ref = None
+            for fused, graphs in ((1, 0), (0, 0), (1, 1)):
+                h.set_option(ptmg.PT_OPT_FUSED, fused)
+                h.set_option(ptmg.PT_OPT_GRAPHS, graphs)
+                p, T = torch.empty_like(gb_p), torch.empty_like(gb_T)
+                info = h.solve(gb_p, gb_T, p, T, rtol=rtol, max_cycles=200)
+                torch.cuda.synchronize()
+                out = (p.clone(), T.clone(), info["cycles"])
+                if ref is None:
+                    ref = out
+                else:
+                    assert out[2] == ref[2] and torch.equal(out[0], ref[0]) and \
+                        torch.equal(out[1], ref[1]), (prob.name, fused, graphs)
+            with pytest.raises(ptmg.PtMgError):
+                h.set_option(ptmg.PT_OPT_W_LEVELS, -1)
+
+
 @pytest.mark.parametrize("name", ["bubble2d_200x136", "bubble3d_40x24x56", "explicit_64",
                                   "twobubble2d_96x80"])
 @pytest.mark.parametrize("prec", [0, 1])
