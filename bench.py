@@ -66,9 +66,9 @@ SWEEPS = {
     "explicit_64": (3, 2, 34),
     "bubble2d_1024": (3, 2, 17),
     "wall3d_256": (3, 2, 17),
-    "collapse3d_512": (3, 2, 17),
+    "collapse3d_512": (4, 3, 17),
     "state2d_1024": (3, 3, 17),
-    "state3d_256": (3, 2, 17),
+    "state3d_256": (4, 3, 17),
     "axi2d_1024": (3, 3, 17),
 }
 
