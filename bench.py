@@ -131,6 +131,22 @@ def upstream_line(prob, state_ms):
             "launches": len(state_ms)}
 
 
+def transfer_sweep_line(timed):
+    """The finest-grid sweep that also restricts its residual (or adds the
+    prolonged correction), timed apart from the plain sweeps: algorithmic
+    bytes are the sweep's plus the coarse level's f written (u read)."""
+    st = timed.get("smooth_fine_transfer")
+    if not st or not st["launches"]:
+        return None
+    ms = st["ms"] / st["launches"]
+    nbytes = st["bytes"] / st["launches"]
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    return {"kernel": "smooth_fine_transfer", "bound": "hbm", "achieved": round(gbs, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+            "avg_launch_us": round(ms * 1e3, 2), "alg_bytes_per_launch": nbytes,
+            "launches": st["launches"]}
+
+
 def downstream_line(timed):
     """Achieved bandwidth of pt_mg_downstream from the library's HIP-event
     timing (algorithmic bytes: every array it reads or writes, once)."""
@@ -532,6 +548,7 @@ def main():
                    "footprint_bytes": run["footprint"],
                    "parallelism": "single GPU"},
         "roofline": roofline,
+        "transfer_sweep": transfer_sweep_line(timed),
         "upstream": upstream_line(prob, run["state_ms"]),
         "downstream": downstream_line(timed),
         "launches_per_step": {k: v["launches"] / args.steps for k, v in stats.items()},
@@ -632,7 +649,7 @@ def timed_steps(prob, prec, rtol, method, args, roofline_timing=True):
             # HIP events only around the finest-grid smoother (the kernel
             # the roofline reports), and only around one smoothing run in
             # `timing_every`, so that the timed steps carry little overhead
-            h.set_timing(True, classes=[ROOFLINE_KERNEL]
+            h.set_timing(True, classes=[ROOFLINE_KERNEL, "smooth_fine_transfer"]
                          + (["downstream"] if faces is not None else []))
             h.set_option(ptmg.PT_OPT_TIMING_EVERY, args.timing_every)
         h.reset_stats()

@@ -401,7 +401,9 @@ typedef enum {
     PT_K_COARSE_SOLVE = 5,    /* coarsest-grid solve */
     PT_K_OTHER = 6,           /* norm reduction, conversions, copies */
     PT_K_DOWNSTREAM = 7,      /* pt_mg_downstream (velocity correction + phase energies) */
-    PT_K_COUNT = 8
+    PT_K_SMOOTH_FINE_T = 8,   /* finest-grid sweep with a transfer inside: the restriction
+                                 of its residual, or the prolonged correction added */
+    PT_K_COUNT = 9
 } pt_kernel_class;
 
 /* HIP-event timing (off by default): on = 0 off, 1 every kernel class,

@@ -538,6 +538,7 @@ template <typename R> void smooth(pt_mg_t h, int l, int sweeps, bool zero_guess,
         // fused red-black sweeps (one pass over memory each), ping-ponging
         // the iterate between the level's two buffers
         const double Rb = sizeof(R);
+        const int cls = l == 0 ? PT_K_SMOOTH_FINE : PT_K_SMOOTH_COARSE;
         for (int s = 0; s < sweeps; s++) {
             const bool zg = zero_guess && s == 0, r = res && s == sweeps - 1;
             Lvl<R> L = h->level<R>(l);
@@ -545,12 +546,15 @@ template <typename R> void smooth(pt_mg_t h, int l, int sweeps, bool zero_guess,
             typename VT<R>::v2 *uo = h->level<R>(l).u;
             double nb = (double)L.N * ((zg ? 0 : 2 * Rb) + 2 * Rb + op_bytes(h, l, Rb) + 2 * Rb);
             if (r) nb += (double)h->P.lv[l + 1].N * 2 * Rb;            // coarse f written
-            h->begin(l == 0 ? PT_K_SMOOTH_FINE : PT_K_SMOOTH_COARSE, nb, s == 0);
+            // the sweep that also restricts is a class of its own
+            const bool next_r = res && s + 1 == sweeps - 1;
+            if (r) h->begin(PT_K_SMOOTH_FINE_T, nb);
+            else h->begin(cls, nb, s == 0);
             if (r)
                 launch_rb_fused3r<R>(L, h->level<R>(l + 1), uo, zg ? 1 : 0, h->stream);
             else
                 launch_rb_fused<R>(h->P.dim, L, uo, zg ? 1 : 0, l == 0 ? 0 : 1, h->stream);
-            h->end(s == sweeps - 1);
+            h->end(r || next_r || s == sweeps - 1);
             h->updates += L.N * (r ? 2 : 1);
         }
         return;
@@ -587,9 +591,13 @@ template <typename R> void smooth0_fused(pt_mg_t h, int sweeps, bool zero_guess,
         typename VT<R>::v2 *uo = h->level<R>(0).u;
         double nb = (double)L.N * ((zg ? 0 : 2 * Rb) + 2 * Rb + op_bytes(h, 0, Rb) + 2 * Rb);
         if (p || r) nb += (double)C.N * 2 * Rb;   // coarse u read, or coarse f written
-        h->begin(PT_K_SMOOTH_FINE, nb, s == 0);
+        // a sweep with a transfer is a class of its own; the plain sweeps
+        // between share one run
+        const bool tr = p || r;
+        const bool next_tr = s + 1 < sweeps && ((pro && s + 1 == 0) || (res && s + 1 == sweeps - 1));
+        h->begin(tr ? PT_K_SMOOTH_FINE_T : PT_K_SMOOTH_FINE, nb, tr || s == 0 || (pro && s == 1));
         launch_tile2x<R>(L, C, uo, zg ? 1 : 0, p ? 1 : 0, r ? 1 : 0, h->stream);
-        h->end(s == sweeps - 1);
+        h->end(tr || next_tr || s == sweeps - 1);
         h->updates += L.N * (r ? 2 : 1);
     }
 }

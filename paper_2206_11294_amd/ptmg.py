@@ -26,7 +26,7 @@ PT_OPT_TAIL_CELLS = 6
 PT_OPT_COARSE_SWEEPS = 7
 PT_OPT_W_LEVELS = 8
 KERNEL_CLASSES = ["outer_residual", "smooth_fine", "smooth_coarse", "restrict", "prolong",
-                  "coarse_solve", "other", "downstream"]
+                  "coarse_solve", "other", "downstream", "smooth_fine_transfer"]
 
 
 class PtMgError(RuntimeError):

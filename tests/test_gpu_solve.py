@@ -187,14 +187,19 @@ def test_timing_and_counters():
     h.reset_stats()
     info = h.solve(b_p, b_T, p, T, rtol=1e-9)
     st = h.kernel_stats()
-    assert st["smooth_fine"]["launches"] == 4 * info["cycles"]   # one fused launch per sweep
+    # one fused launch per sweep; V(2,2) in 3-D FP32: the second pre-sweep
+    # also restricts its residual (a class of its own)
+    assert st["smooth_fine"]["launches"] == 3 * info["cycles"]
+    assert st["smooth_fine_transfer"]["launches"] == info["cycles"]
     assert st["outer_residual"]["launches"] == info["cycles"] + 1
     assert st["smooth_fine"]["ms"] > 0 and st["smooth_fine"]["bytes"] > 0
+    assert st["smooth_fine_transfer"]["ms"] > 0
     assert h.last_cell_updates() > 0
     ts = h.timed_stats()
     for c in st:      # every run timed: the timed launches are all launches
         assert ts[c]["launches"] == st[c]["launches"] and ts[c]["bytes"] == st[c]["bytes"], c
-    # one run in three of the finest-grid smoother: two runs per cycle
+    # one run in three of the finest-grid smoother: two runs per cycle, of
+    # one launch (before the restricting sweep) and two (after the cycle)
     h.set_timing(True, classes=["smooth_fine"])
     h.set_option(ptmg.PT_OPT_TIMING_EVERY, 3)
     assert h.get_option(ptmg.PT_OPT_TIMING_EVERY) == 3
@@ -202,9 +207,11 @@ def test_timing_and_counters():
     info = h.solve(b_p, b_T, p, T, rtol=1e-9)
     st, ts = h.kernel_stats(), h.timed_stats()
     runs = 2 * info["cycles"]
-    assert ts["smooth_fine"]["launches"] == 2 * ((runs + 2) // 3)
+    want = sum(1 if r % 2 == 0 else 2 for r in range(runs) if r % 3 == 0)
+    assert ts["smooth_fine"]["launches"] == want
     assert ts["smooth_fine"]["ms"] > 0 and ts["outer_residual"]["launches"] == 0
-    assert st["smooth_fine"]["launches"] == 4 * info["cycles"]
+    assert ts["smooth_fine_transfer"]["launches"] == 0
+    assert st["smooth_fine"]["launches"] == 3 * info["cycles"]
     with pytest.raises(ptmg.PtMgError):
         h.set_option(ptmg.PT_OPT_TIMING_EVERY, 0)
 
