@@ -147,6 +147,22 @@ typedef struct {
      * the mean constraint, and its first use on a handle allocates 8 FP64
      * work vectors of 2N doubles, kept until pt_mg_destroy. */
     int method;
+    /* 1: stream-ordered (pt_mg_solve, defect-correction loop only).  The
+     * call enqueues every outer iteration up to max_cycles (<= PT_MAX_HIST
+     * - 1) on the handle's stream and returns PT_OK at once; nothing waits
+     * on the host.  After each residual a one-thread kernel takes the stop
+     * test of Sec. 3 on the device, and once it is met every later launch
+     * of the solve returns at entry.  p, T and *info are valid once the
+     * stream has passed the solve (a stream or device synchronisation):
+     * the stream writes *info through a host function, so `info` must stay
+     * valid until then; info->status carries the outcome (PT_OK or
+     * PT_ERR_NOCONV).  Results are those of the blocking solve, bit for
+     * bit.  Costs: the launches after the stop still run as no-ops (a few
+     * microseconds each), so max_cycles should not be far above the cycles
+     * needed; the first use allocates a small pinned record (kept until
+     * pt_mg_destroy), so pt_mg_solve_noalloc refuses it; pt_mg_step and
+     * BiCGStab refuse it too; pt_mg_last_cell_updates reads 0 after it. */
+    int async;
 } pt_solve_opts;
 
 #define PT_SOLVE_DEFECT 0

@@ -35,6 +35,7 @@ struct Plan {
     size_t o_ac64, o_B64, o_xp, o_xT, o_partials, o_flags, o_gj0, o_gj1;
     // phases mode: the finest block is kept compact, (C, bb) and T
     bool compact = false;
+    size_t o_gate = (size_t)-1;
     size_t o_cb64 = (size_t)-1, o_T64 = (size_t)-1, o_cb32 = (size_t)-1, o_T32 = (size_t)-1;
     size_t o_axm64 = (size_t)-1, o_axm32 = (size_t)-1;   // r-z metric per finest row
     size_t total = 0;
@@ -121,6 +122,7 @@ const char *plan_problem(const pt_problem *p, int prec, Plan &P)
     }
     P.o_xp = P.take(8 * P.N);
     P.o_xT = P.take(8 * P.N);
+    P.o_gate = P.take(256);   // stream-ordered solve: stop flag, final k
     if (p->axisymmetric) {
         P.o_axm64 = P.take(32ull * p->n[1]);
         if (prec == PT_PREC_MIXED) P.o_axm32 = P.take(16ull * p->n[1]);
@@ -277,6 +279,10 @@ struct pt_mg_s {
     // levels 1 .. w_levels (above the single-block tail) visit their coarse
     // level twice per visit (W-cycle there); 0: V-cycle
     int w_levels = 0;
+    // stream-ordered solve: the stop flag every launch of it checks (null
+    // otherwise), and its record in pinned host memory (made on first use)
+    const int *gate_active = nullptr;
+    AsyncInfo *async_host = nullptr, *async_devp = nullptr;
 
     template <typename T> T *at(size_t off) { return off == (size_t)-1 ? nullptr : (T *)(base + off); }
     double2 *ac64() { return at<double2>(P.o_ac64); }
@@ -327,6 +333,7 @@ struct pt_mg_s {
         o.T0 = nullptr;
         o.tmask = 0;
         std::memset(&o.k, 0, sizeof o.k);
+        o.gate = gate_active;
         if (l == 0) {
             o.axm = (const typename VT<R>::v4 *)(sizeof(R) == 8 ? (void *)axm64()
                                                                 : (void *)at<float4>(P.o_axm32));
@@ -346,6 +353,7 @@ struct pt_mg_s {
         o.B = B64();
         o.axm = axm64();
         compact_view<double>(o.cb, o.T0, o.tmask, o.k);
+        o.gate = nullptr;
         return o;
     }
 
@@ -628,7 +636,7 @@ template <typename R> void coarse_solve(pt_mg_t h)
     Lvl<R> L = h->level<R>(h->P.nlev - 1);
     const int m = h->P.m;
     h->begin(PT_K_COARSE_SOLVE, 8.0 * m * m + 2.0 * m * sizeof(R));
-    launch_coarse_apply<R>(h->Ainv, m, (const R *)L.f, (R *)L.u, h->stream);
+    launch_coarse_apply<R>(h->Ainv, m, (const R *)L.f, (R *)L.u, h->stream, h->gate_active);
     h->end();
 }
 
@@ -649,7 +657,7 @@ constexpr unsigned kCoarseClasses =
 // the null stream (it cannot be captured) or a coarse class is being timed.
 template <typename R> void coarse_cycle(pt_mg_t h, int nu1, int nu2)
 {
-    if (!h->use_graphs || !h->stream || (h->timing & kCoarseClasses)) {
+    if (!h->use_graphs || !h->stream || (h->timing & kCoarseClasses) || h->gate_active) {
         vcycle<R>(h, 1, nu1, nu2);
         return;
     }
@@ -802,7 +810,7 @@ template <typename R> void vcycle_visit(pt_mg_t h, int l, int nu1, int nu2)
     Lvl<R> L = h->level<R>(l);
     if (nu1 == 0) {
         h->begin(PT_K_OTHER, (double)L.N * 2 * sizeof(R));
-        launch_zero(L.u, (size_t)L.N * 2 * sizeof(R), h->stream);
+        launch_zero(L.u, (size_t)L.N * 2 * sizeof(R), h->stream, h->gate_active);
         h->end();
     }
     const bool res = fused_restrict3(h, l, nu1);
@@ -1271,6 +1279,7 @@ void pt_mg_destroy(pt_mg_t h)
     if (h->hier_exec) (void)hipGraphExecDestroy(h->hier_exec);
     if (h->hier_graph) (void)hipGraphDestroy(h->hier_graph);
     if (h->kry) (void)hipFree(h->kry);
+    if (h->async_host) (void)hipHostFree(h->async_host);
     if (h->owns_memory) {
         if (h->base) (void)hipFree(h->base);
         if (h->norms_host) (void)hipHostFree(h->norms_host);
@@ -1450,6 +1459,7 @@ int outer(pt_mg_t h, const double *b_p, const double *b_T, const double *src_p,
     a.res_T = res_T;
     a.partials = h->partials();
     a.update = update ? 1 : 0;
+    a.gate = h->gate_active;
     const double Rb = sizeof(RV);
     // iterate (unless zero), operator (a, block), b
     double nbytes = (double)P.N * ((src_p ? 16 : 0) + op_bytes(h, 0, 8) + 16);
@@ -1481,7 +1491,7 @@ int outer_any(pt_mg_t h, const double *b_p, const double *b_T, const double *src
 int enqueue_norms(pt_mg_t h, int nb, int slot)
 {
     h->begin(PT_K_OTHER, 32.0 * nb);
-    launch_reduce4(h->partials(), nb, h->norms_devp + 4 * slot, h->stream);
+    launch_reduce4(h->partials(), nb, h->norms_devp + 4 * slot, h->stream, h->gate_active);
     h->end();
     return check_hip(h, hipEventRecord(h->norm_ev[slot], h->stream), "norm event");
 }
@@ -1755,6 +1765,8 @@ static int krylov_check(pt_mg_t h, const double *b_p, const double *b_T, double 
 int pt_mg_solve_noalloc(pt_mg_t h, const double *b_p, const double *b_T, double *p, double *T,
                         const pt_solve_opts *opts_in, pt_solve_info *info)
 {
+    if (opts_in && opts_in->async)
+        return fail(h, PT_ERR_ARG, "the stream-ordered mode allocates; call pt_mg_solve");
     if (!opts_in || opts_in->method != PT_SOLVE_BICGSTAB)
         return pt_mg_solve(h, b_p, b_T, p, T, opts_in, info);   // allocates nothing
     int rc = krylov_check(h, b_p, b_T, p, T, *opts_in);
@@ -1770,9 +1782,115 @@ int pt_mg_solve_noalloc(pt_mg_t h, const double *b_p, const double *b_T, double 
     return krylov_solve(h, b_p, b_T, p, T, *opts_in, info, work);
 }
 
+namespace {
+
+// The end of a stream-ordered solve, run by the stream after its last
+// launch: the record the stop tests wrote, into the caller's info.
+struct AsyncDone {
+    const AsyncInfo *rec;
+    pt_solve_info *info;
+    std::chrono::steady_clock::time_point t0;
+};
+
+void async_done(void *user)
+{
+    AsyncDone *d = (AsyncDone *)user;
+    if (d->info) {
+        const AsyncInfo &a = *d->rec;
+        pt_solve_info o;
+        std::memset(&o, 0, sizeof o);
+        o.cycles = a.cycles;
+        o.relres[0] = a.relres[0];
+        o.relres[1] = a.relres[1];
+        o.hist_len = a.hist_len;
+        for (int q = 0; q < 2 * a.hist_len && q < 2 * PT_MAX_HIST; q++) o.relres_hist[q] = a.hist[q];
+        o.status = a.status;
+        o.t_solve_s = elapsed(d->t0);
+        *d->info = o;
+    }
+    delete d;
+}
+
+// The defect-correction loop with every outer iteration up to max_cycles
+// enqueued at once: after each residual a one-thread launch takes the stop
+// test on the device and, once it is met, sets the flag that turns every
+// later launch of the solve into a no-op; a last launch moves u_k into
+// (p, T), and a host function fills `info`.  Nothing waits on the host.
+int solve_async(pt_mg_t h, const double *b_p, const double *b_T, double *p, double *T,
+                const pt_solve_opts &o, pt_solve_info *info)
+{
+    if (!h || !h->ready) return fail(h, PT_ERR_STATE, "handle not ready");
+    if (!b_p || !b_T || !p || !T) return fail(h, PT_ERR_ARG, "NULL field");
+    if (!(o.rtol >= 0) || o.max_cycles < 0 || o.nu1 < 0 || o.nu2 < 0 || o.nu1 > 8 || o.nu2 > 8 ||
+        o.nu1 + o.nu2 == 0)
+        return fail(h, PT_ERR_ARG, "bad solve options");
+    if (o.method != PT_SOLVE_DEFECT)
+        return fail(h, PT_ERR_ARG, "the stream-ordered solve runs the defect-correction loop");
+    if (o.max_cycles > PT_MAX_HIST - 1)
+        return fail(h, PT_ERR_ARG, "stream-ordered solve: max_cycles <= PT_MAX_HIST - 1");
+    const Plan &P = h->P;
+    if (!h->async_host) {
+        void *mem = nullptr;
+        hipError_t e = hipHostMalloc(&mem, sizeof(AsyncInfo), hipHostMallocDefault);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(h, PT_ERR_OOM, "pinned host allocation failed");
+        }
+        h->async_host = (AsyncInfo *)mem;
+        e = hipHostGetDevicePointer((void **)&h->async_devp, mem, 0);
+        if (e != hipSuccess) return check_hip(h, e, "pinned mapping");
+    }
+    int *gate = h->at<int>(P.o_gate);
+    auto &S = h->sv;
+    S = pt_mg_s::Solve();
+    S.t0 = std::chrono::steady_clock::now();
+    S.o = o;
+    S.b_p = b_p;
+    S.b_T = b_T;
+    S.p = p;
+    S.T = T;
+    h->updates = 0;
+    if (o.zero_guess) S.parity = h->hint_parity;
+    launch_gate_reset(gate, h->async_devp, h->stream);
+    S.bshift = h->prob.mean_constraint ? grid_sums(h, b_p, b_T, 0) : nullptr;
+    int rc = PT_OK;
+    h->gate_active = gate;
+    for (int k = 0; k <= o.max_cycles && rc == PT_OK; k++) {
+        rc = enqueue_outer(h, k);
+        if (rc == PT_OK)
+            launch_async_decide(h->norms_devp + 4 * (k & 1), k, o.rtol, o.max_cycles, gate,
+                                h->async_devp, h->stream);
+    }
+    h->gate_active = nullptr;
+    if (rc != PT_OK) {
+        (void)hipStreamSynchronize(h->stream);
+        return rc;
+    }
+    h->begin(PT_K_OTHER, 32.0 * P.N);
+    launch_async_final(gate, S.parity, o.zero_guess, h->at<double>(P.o_xp),
+                       h->at<double>(P.o_xT), p, T, P.N, h->stream);
+    h->end();
+    if (h->prob.mean_constraint) {
+        double *us = grid_sums(h, p, T, 1);
+        launch_shift2(P.N, p, T, us, 1.0 / (double)P.N, h->stream);
+    }
+    AsyncDone *d = new AsyncDone{h->async_host, info, S.t0};
+    hipError_t e = hipLaunchHostFunc(h->stream, async_done, d);
+    if (e != hipSuccess) {
+        delete d;
+        return check_hip(h, e, "stream-ordered solve");
+    }
+    h->last_updates = 0;   // not known on the host
+    S.phase = 0;
+    return check_hip(h, hipGetLastError(), "stream-ordered solve");
+}
+
+}  // namespace
+
 int pt_mg_solve(pt_mg_t h, const double *b_p, const double *b_T, double *p, double *T,
                 const pt_solve_opts *opts_in, pt_solve_info *info)
 {
+    if (opts_in && opts_in->async) return solve_async(h, b_p, b_T, p, T, *opts_in, info);
     if (opts_in && opts_in->method == PT_SOLVE_BICGSTAB) {
         int rc = krylov_check(h, b_p, b_T, p, T, *opts_in);
         if (rc != PT_OK) return rc;
@@ -1802,6 +1920,8 @@ int pt_mg_step(pt_mg_t h, const pt_problem *prob, const double *div_ustar, doubl
     if (prob->mode == PT_COEF_EXPLICIT)
         return fail(h, PT_ERR_STATE, "step needs phases or state mode");
     if (!b_p || !b_T || !p || !T) return fail(h, PT_ERR_ARG, "NULL field");
+    if (opts_in && opts_in->async)
+        return fail(h, PT_ERR_ARG, "the stream-ordered mode applies to pt_mg_solve");
     if (opts_in && opts_in->method != PT_SOLVE_DEFECT) {
         // the Krylov loop waits on every reduction anyway
         int rc = pt_mg_update(h, prob);

@@ -62,6 +62,9 @@ template <typename R> struct Lvl {
     const R *T0;
     long long tmask;
     CBK<R> k;
+    // non-null: the launch does nothing once *gate != 0 (the stream-ordered
+    // solve has decided to stop)
+    const int *gate;
 };
 
 // Outer FP64 residual arguments (finest grid).
@@ -88,6 +91,19 @@ template <typename RV> struct OuterArgs {
     double *r64_p, *r64_T;         // canonical residual out in FP64 or null
     double *partials;              // [4 * gridDim.x]: sum res_p^2, res_T^2, b_p^2, b_T^2
     int update;
+    const int *gate;               // as in Lvl
+};
+
+// Stream-ordered solve: what the stop test writes after each residual
+// (pinned host memory), and the device words the launches read: gate[0]
+// != 0 once the solve has stopped, gate[1] the final outer iteration k.
+struct AsyncInfo {
+    int status;           // PT_OK, PT_ERR_NOCONV, or -1 while running
+    int cycles;
+    int hist_len;
+    int nonfinite;
+    double relres[2];
+    double hist[2 * PT_MAX_HIST];
 };
 
 struct AsmArgs {
@@ -213,9 +229,18 @@ void launch_paper_rhs(const Lvl<double> &L, const double *p_adv, double p_const,
 
 template <typename RV>
 int launch_outer_zm(int dim, const OuterArgs<RV> &a, hipStream_t s);   // returns #blocks
+// the stop test of outer iteration k on the norms of its residual
+void launch_async_decide(const double *norms, int k, double rtol, int max_cycles, int *gate,
+                         AsyncInfo *info, hipStream_t s);
+// the answer u_k into (p, T): from (xp, xT) when k + parity is odd, zero
+// when k = 0 from a zero guess, else already there
+void launch_async_final(const int *gate, int parity, int zero_guess, const double *xp,
+                        const double *xT, double *p, double *T, long long N, hipStream_t s);
+void launch_gate_reset(int *gate, AsyncInfo *info, hipStream_t s);
 int outer_zm_blocks(int dim, int nx, int ny, int nz);
 int reduce_scratch(int nblocks);   // extra partial slots launch_reduce4 needs
-void launch_reduce4(const double *partials, int nblocks, double *out4, hipStream_t s);
+void launch_reduce4(const double *partials, int nblocks, double *out4, hipStream_t s,
+                    const int *gate = nullptr);
 void launch_sum2(long long N, const double *x, const double *y, double *partials, int nblocks,
                  double *out2, hipStream_t s);   // out2 = (sum x, sum y), fixed order
 int sum2_blocks(long long N);
@@ -263,7 +288,8 @@ void launch_coarse_dense(int dim, int level0, const Lvl<R> &L, int pin_mean, dou
 void launch_gj_step(const double *A, double *Bm, int m, int k, int *flags, hipStream_t s);
 bool launch_gj_lds(const double *A, double *Ainv, int m, int *flags, hipStream_t s);  // m <= 128
 template <typename R>
-void launch_coarse_apply(const double *Ainv, int m, const R *f, R *u, hipStream_t s);
+void launch_coarse_apply(const double *Ainv, int m, const R *f, R *u, hipStream_t s,
+                         const int *gate = nullptr);
 template <typename R>
 void launch_export_op(int dim, int level0, const Lvl<R> &L, double *faces, double *B,
                       hipStream_t s);
@@ -276,7 +302,7 @@ void launch_unpack(long long N, const typename VT<R>::v2 *in, double *p, double 
 template <typename RIN, typename ROUT>
 void launch_convert(long long n, const RIN *in, ROUT *out, hipStream_t s);
 void launch_copy(void *dst, const void *src, size_t bytes, hipStream_t s);
-void launch_zero(void *p, size_t bytes, hipStream_t s);
+void launch_zero(void *p, size_t bytes, hipStream_t s, const int *gate = nullptr);
 void launch_zero2(void *p, void *q, size_t bytes, hipStream_t s);   // both arrays
 void launch_flags_out(const int *src, int *dst, int n, hipStream_t s);   // n <= 64
 

@@ -71,6 +71,10 @@ __device__ __forceinline__ double harm_exact(double a, double b)
     const double s = a + b;
     return s > 0.0 ? 2.0 * a * b / s : 0.0;
 }
+// A launch of a stream-ordered solve does nothing once the solve has
+// stopped (the flag is written by an earlier launch on the same stream).
+__device__ __forceinline__ bool gated(const int *gate) { return gate && *gate != 0; }
+
 __device__ __forceinline__ double2 harm2_exact(double2 a, double2 b)
 {
     return make_double2(harm_exact(a.x, b.x), harm_exact(a.y, b.y));
@@ -491,8 +495,9 @@ void launch_paper_rhs(const Lvl<double> &L, const double *p_adv, double p_const,
 
 // Fixed-order reduction of per-block partial sums (`width` per block).
 __global__ __launch_bounds__(kBlock) void k_reduce(const double *partials, int nblocks, int width,
-                                                   double *out)
+                                                   double *out, const int *gate)
 {
+    if (gated(gate)) return;
     double v[4] = {0.0, 0.0, 0.0, 0.0};
     for (int b = threadIdx.x; b < nblocks; b += kBlock)
         for (int q = 0; q < width; q++) v[q] += partials[(long long)b * width + q];
@@ -503,8 +508,9 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const double *partials, int n
 // partials [b*kChunk, (b+1)*kChunk) (width doubles each).
 constexpr int kChunk = 1024;
 __global__ __launch_bounds__(kBlock) void k_reduce_stage(const double *partials, int nblocks,
-                                                         int width, double *out)
+                                                         int width, double *out, const int *gate)
 {
+    if (gated(gate)) return;
     double v[4] = {0.0, 0.0, 0.0, 0.0};
     const int b0 = blockIdx.x * kChunk;
     const int b1 = min(b0 + kChunk, nblocks);
@@ -517,16 +523,18 @@ int reduce_scratch(int nblocks) { return nblocks > kChunk ? (nblocks + kChunk - 
 
 // partials[0 .. 4*nblocks) -> out4; uses partials[4*nblocks ..
 // 4*(nblocks + reduce_scratch(nblocks))) as scratch.
-void launch_reduce4(const double *partials, int nblocks, double *out4, hipStream_t s)
+void launch_reduce4(const double *partials, int nblocks, double *out4, hipStream_t s,
+                    const int *gate)
 {
     const int g2 = reduce_scratch(nblocks);
     if (g2 == 0) {
-        hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, s, partials, nblocks, 4, out4);
+        hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, s, partials, nblocks, 4, out4, gate);
         return;
     }
     double *mid = const_cast<double *>(partials) + 4ll * nblocks;
-    hipLaunchKernelGGL(k_reduce_stage, dim3(g2), dim3(kBlock), 0, s, partials, nblocks, 4, mid);
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, s, mid, g2, 4, out4);
+    hipLaunchKernelGGL(k_reduce_stage, dim3(g2), dim3(kBlock), 0, s, partials, nblocks, 4, mid,
+                       gate);
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, s, mid, g2, 4, out4, gate);
 }
 
 // Grid-strided over at most kSumBlocks blocks (used once per solve).
@@ -549,7 +557,8 @@ void launch_sum2(long long N, const double *x, const double *y, double *partials
                  double *out2, hipStream_t s)
 {
     hipLaunchKernelGGL(k_sum2, dim3(sum2_blocks(N)), dim3(kBlock), 0, s, N, x, y, partials);
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, s, partials, nblocks, 2, out2);
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, s, partials, nblocks, 2, out2,
+                       (const int *)nullptr);
 }
 
 __global__ __launch_bounds__(kBlock) void k_shift2(long long N, double *x, double *y,
@@ -708,6 +717,7 @@ __device__ __forceinline__ void prolong_cell(const Lvl<R> &F, const Lvl<R> &C, i
 template <typename R, int DIM, bool CF>
 __global__ __launch_bounds__(kBlock) void k_rb_pass(Lvl<R> L, int color, int zero_guess)
 {
+    if (gated(L.gate)) return;
     long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
     const int nxh = (L.nx + 1) >> 1;
     const long long tot = (long long)nxh * L.ny * L.nz;
@@ -743,6 +753,7 @@ template void launch_rb_pass<double>(int, int, const Lvl<double> &, int, int, hi
 template <typename R, int DIM, bool CF>
 __global__ __launch_bounds__(kBlock) void k_restrict(Lvl<R> F, Lvl<R> C)
 {
+    if (gated(F.gate)) return;
     // neighbouring coarse cells share the fine halo: runs of them per XCD
     long long t = (long long)xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     if (t >= C.N) return;
@@ -771,6 +782,7 @@ template void launch_restrict<double>(int, int, const Lvl<double> &, const Lvl<d
 template <typename R, int DIM>
 __global__ __launch_bounds__(kBlock) void k_prolong(Lvl<R> F, Lvl<R> C)
 {
+    if (gated(F.gate)) return;
     long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
     if (t >= F.N) return;
     int i, j, k;
@@ -784,6 +796,7 @@ __global__ __launch_bounds__(kBlock) void k_prolong(Lvl<R> F, Lvl<R> C)
 template <typename R>
 __global__ __launch_bounds__(1024) void k_prolong3t(Lvl<R> F, Lvl<R> C, int tiles_x, int tiles_y)
 {
+    if (gated(F.gate)) return;
     using V2 = typename VT<R>::v2;
     constexpr int TX = 32, TY = 8, TZ = 4;
     constexpr int CX = TX / 2 + 2, CY = TY / 2 + 2, CZ = TZ / 2 + 2;
@@ -1076,8 +1089,9 @@ void launch_gj_step(const double *A, double *Bm, int m, int k, int *flags, hipSt
 // u = Ainv f on the coarsest grid, FP64 accumulation; one wave per row.
 template <typename R>
 __global__ __launch_bounds__(kBlock) void k_coarse_apply(const double *Ainv, int m, const R *f,
-                                                         R *u)
+                                                         R *u, const int *gate)
 {
+    if (gated(gate)) return;
     const int row = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (row >= m) return;
@@ -1089,15 +1103,17 @@ __global__ __launch_bounds__(kBlock) void k_coarse_apply(const double *Ainv, int
 }
 
 template <typename R>
-void launch_coarse_apply(const double *Ainv, int m, const R *f, R *u, hipStream_t s)
+void launch_coarse_apply(const double *Ainv, int m, const R *f, R *u, hipStream_t s,
+                         const int *gate)
 {
     const int rows_per_block = kBlock / 64;
     hipLaunchKernelGGL((k_coarse_apply<R>), dim3((m + rows_per_block - 1) / rows_per_block),
-                       dim3(kBlock), 0, s, Ainv, m, f, u);
+                       dim3(kBlock), 0, s, Ainv, m, f, u, gate);
 }
-template void launch_coarse_apply<float>(const double *, int, const float *, float *, hipStream_t);
+template void launch_coarse_apply<float>(const double *, int, const float *, float *, hipStream_t,
+                                         const int *);
 template void launch_coarse_apply<double>(const double *, int, const double *, double *,
-                                          hipStream_t);
+                                          hipStream_t, const int *);
 
 // ------------------------------------------------------ export / convert
 template <typename R, int DIM, bool CF>
@@ -1233,8 +1249,9 @@ namespace ptmg {
 // Zero fill with vector stores (kept out of hipMemsetAsync so that the
 // work can be captured in a graph).
 __global__ __launch_bounds__(kBlock) void k_zero(uint4 *p, long long nvec, unsigned char *tail,
-                                                 int ntail)
+                                                 int ntail, const int *gate)
 {
+    if (gated(gate)) return;
     long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
     const long long stride = (long long)gridDim.x * kBlock;
     for (long long q = t; q < nvec; q += stride) p[q] = make_uint4(0, 0, 0, 0);
@@ -1281,7 +1298,92 @@ void launch_flags_out(const int *src, int *dst, int n, hipStream_t s)
     hipLaunchKernelGGL(k_flags_out, dim3(1), dim3(64), 0, s, src, dst, n);
 }
 
-void launch_zero(void *p, size_t bytes, hipStream_t s)
+// ------------------------------------------------ stream-ordered solve
+// The stop test of outer iteration k (the host loop's, on the device): the
+// paper-form relative residual of each component from the norms of its
+// residual, recorded in the history; the solve stops when both meet rtol,
+// when a norm is not finite, or at max_cycles.
+__global__ void k_async_decide(const double *norms, int k, double rtol, int max_cycles, int *gate,
+                               AsyncInfo *info)
+{
+    if (threadIdx.x != 0 || gate[0] != 0) return;
+    const double rel0 = norms[2] > 0 ? sqrt(norms[0] / norms[2]) : sqrt(norms[0]);
+    const double rel1 = norms[3] > 0 ? sqrt(norms[1] / norms[3]) : sqrt(norms[1]);
+    if (info->hist_len < PT_MAX_HIST) {
+        info->hist[2 * info->hist_len] = rel0;
+        info->hist[2 * info->hist_len + 1] = rel1;
+        info->hist_len++;
+    }
+    info->relres[0] = rel0;
+    info->relres[1] = rel1;
+    int status = -1;
+    if (!isfinite(rel0) || !isfinite(rel1)) {
+        status = PT_ERR_NOCONV;
+        info->nonfinite = 1;
+    } else if (rel0 <= rtol && rel1 <= rtol) {
+        status = PT_OK;
+    } else if (k >= max_cycles) {
+        status = PT_ERR_NOCONV;
+    }
+    if (status != -1) {
+        info->status = status;
+        info->cycles = k;
+        gate[1] = k;
+        gate[0] = 1;
+    }
+}
+
+void launch_async_decide(const double *norms, int k, double rtol, int max_cycles, int *gate,
+                         AsyncInfo *info, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_async_decide, dim3(1), dim3(64), 0, s, norms, k, rtol, max_cycles, gate,
+                       info);
+}
+
+// Where u_k lives after the solve: the caller's arrays when k + parity is
+// even, else (xp, xT); from a zero guess u_0 is never stored.
+__global__ __launch_bounds__(kBlock) void k_async_final(const int *gate, int parity, int zero_guess,
+                                                        const double *xp, const double *xT,
+                                                        double *p, double *T, long long N)
+{
+    const int k = gate[1];
+    const bool zero = k == 0 && zero_guess;
+    if (!zero && (k + parity) % 2 == 0) return;
+    const long long stride = (long long)gridDim.x * kBlock;
+    for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < N; i += stride) {
+        p[i] = zero ? 0.0 : xp[i];
+        T[i] = zero ? 0.0 : xT[i];
+    }
+}
+
+void launch_async_final(const int *gate, int parity, int zero_guess, const double *xp,
+                        const double *xT, double *p, double *T, long long N, hipStream_t s)
+{
+    long long blocks = (N + kBlock - 1) / kBlock;
+    if (blocks > 8192) blocks = 8192;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_async_final, dim3((unsigned)blocks), dim3(kBlock), 0, s, gate, parity,
+                       zero_guess, xp, xT, p, T, N);
+}
+
+__global__ void k_gate_reset(int *gate, AsyncInfo *info)
+{
+    if (threadIdx.x != 0) return;
+    gate[0] = 0;
+    gate[1] = 0;
+    info->status = -1;
+    info->cycles = 0;
+    info->hist_len = 0;
+    info->nonfinite = 0;
+    info->relres[0] = info->relres[1] = 0.0;
+}
+
+void launch_gate_reset(int *gate, AsyncInfo *info, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_gate_reset, dim3(1), dim3(64), 0, s, gate, info);
+}
+
+void launch_zero(void *p, size_t bytes, hipStream_t s, const int *gate)
 {
     const long long nvec = (long long)(bytes / 16);
     const int ntail = (int)(bytes % 16);
@@ -1289,7 +1391,7 @@ void launch_zero(void *p, size_t bytes, hipStream_t s)
     if (blocks > 8192) blocks = 8192;
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(k_zero, dim3((unsigned)blocks), dim3(kBlock), 0, s, (uint4 *)p, nvec,
-                       (unsigned char *)p + nvec * 16, ntail);
+                       (unsigned char *)p + nvec * 16, ntail, gate);
 }
 
 }  // namespace ptmg
@@ -1326,6 +1428,7 @@ template <typename R, int TX, int TY, bool ZG, bool FACES>
 __global__ __launch_bounds__(TX *TY) void k_rb_fused3(Lvl<R> L, typename VT<R>::v2 *__restrict__ uo,
                                                       int zc, int tiles_x, int tiles_y, int ntiles)
 {
+    if (gated(L.gate)) return;
     // FACES: a coarse level with stored lower-face coefficients (fx, fy,
     // fz) instead of cell coefficients; faces of plane z are needed while
     // planes z-1 .. z+1 update, so they live in a 4-slot ring.
@@ -1560,6 +1663,7 @@ template <typename R, int TX, int TY, bool ZG>
 __global__ __launch_bounds__(TX *TY) void k_rb_fused3c(Lvl<R> L, typename VT<R>::v2 *__restrict__ uo,
                                                        int zc, int tiles_x, int tiles_y, int ntiles)
 {
+    if (gated(L.gate)) return;
     using V2 = typename VT<R>::v2;
     using V4 = typename VT<R>::v4;
     constexpr int NT = TX * TY;
@@ -1819,6 +1923,7 @@ __global__ __launch_bounds__(TX *TY) void k_rb_fused3r(Lvl<R> L, Lvl<R> C,
                                                        typename VT<R>::v2 *__restrict__ uo, int zc,
                                                        int tiles_x, int tiles_y, int ntiles)
 {
+    if (gated(L.gate)) return;
     using V2 = typename VT<R>::v2;
     using V4 = typename VT<R>::v4;
     constexpr int G = 3;                         // loaded ring around the tile
@@ -2093,6 +2198,7 @@ template <typename R, int TX, int TY, bool ZG, bool FACES>
 __global__ __launch_bounds__(TX *TY) void k_rb_tile2(Lvl<R> L, typename VT<R>::v2 *__restrict__ uo,
                                                      int tiles_x, int ntiles)
 {
+    if (gated(L.gate)) return;
     using V2 = typename VT<R>::v2;
     using V4 = typename VT<R>::v4;
     constexpr int NT = TX * TY;
@@ -2201,6 +2307,7 @@ __global__ __launch_bounds__(TX *TY) void k_rb_tile2x(Lvl<R> L, Lvl<R> C,
                                                       typename VT<R>::v2 *__restrict__ uo,
                                                       int tiles_x, int ntiles)
 {
+    if (gated(L.gate)) return;
     using V2 = typename VT<R>::v2;
     using V4 = typename VT<R>::v4;
     constexpr int NT = TX * TY;
@@ -2646,6 +2753,7 @@ __device__ __forceinline__ void half_cycle2(const Lvl<R> &L, const Lvl<R> &C,
 template <typename R, int TX, int TY, int NU>
 __global__ __launch_bounds__(TX *TY) void k_down2(Lvl<R> L, Lvl<R> C, int tiles_x, int ntiles)
 {
+    if (gated(L.gate)) return;
     half_cycle2<R, TX, TY, NU, false>(L, C, nullptr, tiles_x, ntiles);
 }
 
@@ -2654,6 +2762,7 @@ __global__ __launch_bounds__(TX *TY) void k_up2(Lvl<R> L, Lvl<R> C,
                                                 typename VT<R>::v2 *__restrict__ uo, int tiles_x,
                                                 int ntiles)
 {
+    if (gated(L.gate)) return;
     half_cycle2<R, TX, TY, NU, true>(L, C, uo, tiles_x, ntiles);
 }
 
@@ -2878,6 +2987,7 @@ template <int DIM, typename RV, int TX, int TY>
 __global__ __launch_bounds__(TX *TY) void k_outer_zm(OuterArgs<RV> a, int NX, int NY, int NZ,
                                                      int zc, int tiles_x, int tiles_y, int ntiles)
 {
+    if (gated(a.gate)) return;
     using V2 = typename VT<RV>::v2;
     constexpr bool FLAT = Flat<TY>::v;
     constexpr int NT = TX * TY;
@@ -3082,6 +3192,7 @@ __global__ __launch_bounds__(TX *TY) void k_restrict_zm(Lvl<R> F, Lvl<R> C, int 
                                                         int zc, int tiles_x, int tiles_y,
                                                         int ntiles)
 {
+    if (gated(F.gate)) return;
     using V2 = typename VT<R>::v2;
     using V4 = typename VT<R>::v4;
     constexpr bool FLAT = Flat<TY>::v;
@@ -3285,6 +3396,7 @@ __device__ __forceinline__ void decode32(int e, int nx, int ny, int &i, int &j, 
 template <typename R, int DIM>
 __global__ __launch_bounds__(DIM == 3 ? 512 : 1024) void k_tail(TailArgs<R> A)
 {
+    if (gated(A.g[0].gate)) return;
     using V2 = typename VT<R>::v2;
     using V4 = typename VT<R>::v4;
     extern __shared__ __align__(16) unsigned char lds[];

@@ -79,11 +79,30 @@ class pt_downstream(ctypes.Structure):
 class pt_solve_opts(ctypes.Structure):
     _fields_ = [("rtol", ctypes.c_double), ("max_cycles", ctypes.c_int),
                 ("nu1", ctypes.c_int), ("nu2", ctypes.c_int), ("zero_guess", ctypes.c_int),
-                ("method", ctypes.c_int)]
+                ("method", ctypes.c_int), ("async_", ctypes.c_int)]   # C field `async`
 
 
 PT_SOLVE_DEFECT, PT_SOLVE_BICGSTAB = 0, 1
 PT_SCRATCH_MAX_CELLS = 1 << 20   # pt_mg_solve_noalloc: largest BiCGStab grid
+
+
+class AsyncSolve:
+    """A stream-ordered solve in flight: result() after a stream sync."""
+
+    def __init__(self, info, owner):
+        self._info = info
+        self._owner = owner
+
+    def result(self) -> Dict:
+        info = self._info
+        n = info.hist_len
+        out = {"status": info.status, "cycles": info.cycles,
+               "relres": (info.relres[0], info.relres[1]),
+               "hist": [(info.relres_hist[2 * q], info.relres_hist[2 * q + 1]) for q in range(n)],
+               "t_solve_s": info.t_solve_s}
+        if self in self._owner._pending:
+            self._owner._pending.remove(self)
+        return out
 
 
 class pt_solve_info(ctypes.Structure):
@@ -206,6 +225,7 @@ class PtMg:
     def __init__(self, prob: pt_problem, precision: int = PT_PREC_FP64, stream=None,
                  keepalive=None):
         self._h = ctypes.c_void_p()
+        self._pending = []   # stream-ordered solves whose record the stream writes later
         self.precision = precision
         self.N = prob.n[0] * prob.n[1] * prob.n[2]
         self.device = torch.device("cuda", torch.cuda.current_device())
@@ -297,6 +317,18 @@ class PtMg:
         return {"status": rc, "cycles": info.cycles, "relres": (info.relres[0], info.relres[1]),
                 "hist": [(info.relres_hist[2 * q], info.relres_hist[2 * q + 1]) for q in range(n)],
                 "t_solve_s": info.t_solve_s}
+
+    def solve_async(self, b_p, b_T, p, T, rtol=1e-9, max_cycles=12, nu1=2, nu2=2,
+                    zero_guess=True) -> "AsyncSolve":
+        """pt_mg_solve in the stream-ordered mode: returns at once; the
+        result (p, T and the record) is valid after the stream is synchronised."""
+        opts = pt_solve_opts(rtol, max_cycles, nu1, nu2, int(zero_guess), PT_SOLVE_DEFECT, 1)
+        info = pt_solve_info()
+        self._check(lib().pt_mg_solve(self._h, _ptr(b_p), _ptr(b_T), _ptr(p), _ptr(T),
+                                      ctypes.byref(opts), ctypes.byref(info)))
+        pend = AsyncSolve(info, self)
+        self._pending.append(pend)   # the stream writes `info` later: keep it alive
+        return pend
 
     def residual(self, b_p, b_T, p, T, want_fields=True):
         r_p = self._empty() if want_fields else None

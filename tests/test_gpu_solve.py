@@ -754,3 +754,90 @@ def test_vcycle_h_independent_on_constant_family():
     cycles = [c for _, c, _ in rec]
     assert max(cycles) - min(cycles) <= 2, rec
     assert max(r for _, _, r in rec) <= 0.1, rec
+
+
+def _blocking_and_async(h, b_p, b_T, rtol, max_cycles, zero_guess=True, p0=None, T0=None):
+    """The blocking solve and the stream-ordered one on the same handle, from
+    the same start; returns both (p, T, info)."""
+    out = []
+    for mode in ("block", "async"):
+        p = torch.empty_like(b_p) if p0 is None else p0.clone()
+        T = torch.empty_like(b_T) if T0 is None else T0.clone()
+        if mode == "block":
+            info = h.solve(b_p, b_T, p, T, rtol=rtol, max_cycles=max_cycles,
+                           zero_guess=zero_guess, raise_on_noconv=False)
+        else:
+            pend = h.solve_async(b_p, b_T, p, T, rtol=rtol, max_cycles=max_cycles,
+                                 zero_guess=zero_guess)
+            torch.cuda.synchronize()
+            info = pend.result()
+        out.append((p, T, info))
+    return out
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_async_solve_equals_blocking(prec):
+    """The stream-ordered solve (opts.async): the stop test on the device,
+    every later launch a no-op, the answer moved into (p, T) by the stream,
+    the record written by a host function.  Same bits, cycles, history and
+    status as the blocking solve: 2-D and 3-D, a warm start, the mean
+    constraint, max_cycles reached, and three solves enqueued back to back
+    before one synchronisation."""
+    import workloads.device as D
+    from paper_2206_11294_amd import ptmg
+    for name in ("bubble2d_200x136", "bubble3d_40x24x56"):
+        prob = step_problems()[name]
+        h, b_p, b_T, _ = D.setup(prob, prec)
+        (p1, T1, i1), (p2, T2, i2) = _blocking_and_async(h, b_p, b_T, 1e-11, 12)
+        assert i1["status"] == 0 and i2["status"] == 0, (name, i1["status"], i2["status"])
+        assert i2["cycles"] == i1["cycles"] and i2["hist"] == i1["hist"], name
+        assert torch.equal(p1, p2) and torch.equal(T1, T2), name
+        # warm start from a perturbed answer; and a cap below the cycles needed
+        (p1, T1, i1), (p2, T2, i2) = _blocking_and_async(
+            h, b_p, b_T, 1e-12, 12, zero_guess=False, p0=p1 * (1 + 1e-9), T0=T1)
+        assert i2["cycles"] == i1["cycles"] and torch.equal(p1, p2) and torch.equal(T1, T2)
+        (p1, T1, i1), (p2, T2, i2) = _blocking_and_async(h, b_p, b_T, 1e-14, 1)
+        assert i1["status"] == ptmg.PT_ERR_NOCONV and i2["status"] == ptmg.PT_ERR_NOCONV
+        assert i2["cycles"] == i1["cycles"] == 1 and i2["hist"] == i1["hist"]
+        assert torch.equal(p1, p2) and torch.equal(T1, T2)
+        # three right-hand sides enqueued back to back, one synchronisation
+        rhs = [(b_p * s, b_T * s) for s in (1.0, 0.5, 2.0)]
+        ref = []
+        for bp, bT in rhs:
+            p, T = torch.empty_like(b_p), torch.empty_like(b_T)
+            ref.append((p, T, h.solve(bp, bT, p, T, rtol=1e-11, max_cycles=12)))
+        outs, pends = [], []
+        for bp, bT in rhs:
+            p, T = torch.empty_like(b_p), torch.empty_like(b_T)
+            pends.append(h.solve_async(bp, bT, p, T, rtol=1e-11, max_cycles=12))
+            outs.append((p, T))
+        torch.cuda.synchronize()
+        for (p, T), pend, (pr, Tr, ir) in zip(outs, pends, ref):
+            inf = pend.result()
+            assert inf["cycles"] == ir["cycles"] and inf["hist"] == ir["hist"]
+            assert torch.equal(p, pr) and torch.equal(T, Tr)
+    # the mean constraint (pure Neumann Poisson): the final shift is stream-ordered too
+    n = (80, 48)
+    N = n[0] * n[1]
+    rng = np.random.default_rng(1)
+    prob = W.Problem(name="poisson", dim=2, n=(80, 48, 1), h=1.0 / 80, mode="explicit",
+                     alpha_p=1.0, alpha_T=0.25, B_const=(0.0, 0.0, 0.0, 0.0),
+                     f_p=rng.uniform(-1, 1, N), f_T=rng.uniform(-1, 1, N), mean_constraint=True)
+    h, b_p, b_T, _ = D.setup(prob, prec)
+    (p1, T1, i1), (p2, T2, i2) = _blocking_and_async(h, b_p, b_T, 1e-11, 60)
+    assert i1["status"] == 0 and i2["status"] == 0
+    assert torch.equal(p1, p2) and torch.equal(T1, T2)
+    # refused where it does not apply
+    p, T = torch.empty_like(b_p), torch.empty_like(b_T)
+    for kw in ({"max_cycles": ptmg.PT_MAX_HIST}, ):
+        with pytest.raises(ptmg.PtMgError):
+            h.solve_async(b_p, b_T, p, T, **kw)
+    opts = ptmg.pt_solve_opts(1e-9, 10, 2, 2, 1, ptmg.PT_SOLVE_BICGSTAB, 1)
+    info = ptmg.pt_solve_info()
+    rc = ptmg.lib().pt_mg_solve(h._h, ptmg._ptr(b_p), ptmg._ptr(b_T), ptmg._ptr(p),
+                                ptmg._ptr(T), ctypes.byref(opts), ctypes.byref(info))
+    assert rc == ptmg.PT_ERR_ARG
+    opts.method = ptmg.PT_SOLVE_DEFECT
+    rc = ptmg.lib().pt_mg_solve_noalloc(h._h, ptmg._ptr(b_p), ptmg._ptr(b_T), ptmg._ptr(p),
+                                        ptmg._ptr(T), ctypes.byref(opts), ctypes.byref(info))
+    assert rc == ptmg.PT_ERR_ARG
