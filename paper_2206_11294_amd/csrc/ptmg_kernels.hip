@@ -3005,24 +3005,23 @@ __global__ __launch_bounds__(TX *TY) void k_outer_zm(OuterArgs<RV> a, int NX, in
         const int z0 = (rr / tiles_y) * zc, z1 = min(z0 + zc, NZ);
         const long long nxy = (long long)NX * NY;
         const int oy = FLAT ? 0 : 1;
+        // the loads of a plane stay raw in registers until the plane is
+        // stored a step later (the update u + du is formed there), so that
+        // they are in flight while the step between computes
         double2 pu[NLD], pa[NLD];
+        V2 pd[NLD];
         auto fetch = [&](int z) {
 #pragma unroll
             for (int i = 0; i < NLD; i++) {
                 const int c = t + i * NT;
                 pu[i] = make_double2(0.0, 0.0);
                 pa[i] = make_double2(0.0, 0.0);
+                pd[i].x = pd[i].y = RV(0);
                 const int gx = x0 + c % PX - 1, gy = y0 + c / PX - oy;
                 if (c < PS && z >= 0 && z < NZ && gx >= 0 && gx < NX && gy >= 0 && gy < NY) {
                     const long long g = gx + (long long)NX * gy + nxy * z;
-                    double2 v = a.src_p ? make_double2(a.src_p[g], a.src_T[g])
-                                        : make_double2(0.0, 0.0);
-                    if (a.update) {
-                        const V2 d = a.du[g];
-                        v.x += (double)d.x;
-                        v.y += (double)d.y;
-                    }
-                    pu[i] = v;
+                    if (a.src_p) pu[i] = make_double2(a.src_p[g], a.src_T[g]);
+                    if (a.update) pd[i] = a.du[g];
                     pa[i] = a.ac[g];
                 }
             }
@@ -3033,7 +3032,12 @@ __global__ __launch_bounds__(TX *TY) void k_outer_zm(OuterArgs<RV> a, int NX, in
             for (int i = 0; i < NLD; i++) {
                 const int c = t + i * NT;
                 if (c < PS) {
-                    su[s][c] = pu[i];
+                    double2 v = pu[i];
+                    if (a.update) {
+                        v.x += (double)pd[i].x;
+                        v.y += (double)pd[i].y;
+                    }
+                    su[s][c] = v;
                     sa[s][c] = pa[i];
                 }
             }
