@@ -1447,9 +1447,12 @@ __global__ __launch_bounds__(TX *TY) void k_rb_fused3(Lvl<R> L, typename VT<R>::
     constexpr int NLD = (PS + NT - 1) / NT;     // plane cells loaded per thread
     constexpr int RW = (TX + 2) / 2;            // red cells per row of the ring region
     constexpr int BW = TX / 2;                  // black cells per tile row
-    constexpr int NA = FACES ? 1 : 5, PA = FACES ? 1 : PS;
+    // ring slots: 5 with stored faces; 7 with cell coefficients, whose
+    // walk takes one barrier per plane step (below)
+    constexpr int NS = FACES ? 5 : 7;
+    constexpr int NA = FACES ? 1 : NS, PA = FACES ? 1 : PS;
     constexpr int NF = FACES ? 4 : 1, PF = FACES ? PS : 1, NLF = FACES ? NLD : 1;
-    __shared__ V2 su[5][PS];
+    __shared__ V2 su[NS][PS];
     __shared__ V2 sa[NA][PA];
     __shared__ V2 sfx[NF][PF], sfy[NF][PF], sfz[NF][PF];
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
@@ -1463,7 +1466,7 @@ __global__ __launch_bounds__(TX *TY) void k_rb_fused3(Lvl<R> L, typename VT<R>::
     const R ih2 = (R)L.inv_h2;
     const long long nxy = (long long)L.nx * L.ny;
     const int t = threadIdx.x;
-    auto slot = [](int z) { return (z + 10) % 5; };   // z >= -2
+    auto slot = [](int z) { return FACES ? (z + 10) % 5 : (z + 14) % 7; };   // z >= -3
     auto fslot = [](int z) { return (z + 8) & 3; };
 
     // ---- per-thread pieces of a plane step: the global loads of step k
@@ -1586,38 +1589,57 @@ __global__ __launch_bounds__(TX *TY) void k_rb_fused3(Lvl<R> L, typename VT<R>::
         }
     };
 
-    // the global loads of step k (none past the chunk's last step)
+    // the global loads of step k (none past the chunk's last step): with
+    // stored faces plane k+2, red on k+1, black on k; with cell
+    // coefficients plane k+3, red on k+1, black on k-1
     auto load_step = [&](int k, Step &S) {
         S.rc = S.bc = -1;
-        if (k >= z1) return;
+        if (FACES ? k >= z1 : k > z1 + 1) return;
         long long g;
-        fetch_plane(k + 2, S);
-        red_cell(k + 1, S.rc, g);
+        fetch_plane(FACES ? k + 2 : k + 3, S);
+        if (FACES || k + 1 <= z1) red_cell(k + 1, S.rc, g);
         if (S.rc >= 0) {
             S.rf = L.f[g];
             S.rB = sweep_B_raw(L, g);
         }
-        black_cell(k, S.bc, g);
+        const int kb = FACES ? k : k - 1;
+        if (kb >= z0 && kb < z1) black_cell(kb, S.bc, g);
         if (S.bc >= 0) {
             S.bf = L.f[g];
             S.bB = sweep_B_raw(L, g);
         }
     };
-    // plane step k from the set `cur`; the loads of step k+2 go to `ahead`
+    // plane step k from the set `cur`; the loads of step k+2 go to `ahead`.
+    // Stored faces: red on k+1, a barrier, black on k.  Cell coefficients:
+    // red on k+1 and black on k-1 in one barrier phase (red on k+1 reads
+    // black on planes k..k+2, all still old; black on k-1 reads red on
+    // k-2..k, all final since the previous steps), so each step needs one
+    // barrier; the store of plane k+3 overwrites plane k-4, last read two
+    // steps before.
     auto body = [&](int k, const Step &cur, Step &ahead) {
-        store_plane(k + 2, cur);
-        load_step(k + 2, ahead);
-        __syncthreads();
-        write_plane(k - 1);
-        if (cur.rc >= 0) update(k + 1, cur.rc, cur.rf, sweep_B_fin(L, cur.rB));
-        __syncthreads();
-        if (cur.bc >= 0) update(k, cur.bc, cur.bf, sweep_B_fin(L, cur.bB));
+        if constexpr (FACES) {
+            store_plane(k + 2, cur);
+            load_step(k + 2, ahead);
+            __syncthreads();
+            write_plane(k - 1);
+            if (cur.rc >= 0) update(k + 1, cur.rc, cur.rf, sweep_B_fin(L, cur.rB));
+            __syncthreads();
+            if (cur.bc >= 0) update(k, cur.bc, cur.bf, sweep_B_fin(L, cur.bB));
+        } else {
+            store_plane(k + 3, cur);
+            load_step(k + 2, ahead);
+            __syncthreads();
+            write_plane(k - 2);
+            if (cur.rc >= 0) update(k + 1, cur.rc, cur.rf, sweep_B_fin(L, cur.rB));
+            if (cur.bc >= 0) update(k - 1, cur.bc, cur.bf, sweep_B_fin(L, cur.bB));
+        }
     };
 
-    // ---- prologue: planes z0-2 .. z0+1, red on z0-1 and z0
+    // ---- prologue: planes z0-2 .. z0+1 (stored faces) or z0+2 (cell
+    // coefficients), red on z0-1 and z0
     {
         Step S;
-        for (int z = z0 - 2; z <= z0 + 1; z++) {
+        for (int z = z0 - 2; z <= z0 + (FACES ? 1 : 2); z++) {
             fetch_plane(z, S);
             store_plane(z, S);
         }
@@ -1628,21 +1650,26 @@ __global__ __launch_bounds__(TX *TY) void k_rb_fused3(Lvl<R> L, typename VT<R>::
         long long g;
         red_cell(z, c, g);
         if (c >= 0) update(z, c, L.f[g], sweep_B(L, g));
-        __syncthreads();
+        if (FACES) __syncthreads();
     }
     // in flight for steps z0 and z0+1
     Step A, B, C;
     load_step(z0, A);
     load_step(z0 + 1, B);
-    for (int k = z0; k < z1; k += 3) {
+    // stored faces: steps z0 .. z1-1 and a last write; cell coefficients:
+    // steps z0 .. z1+1 (the last two finish black and the writes)
+    const int kend = FACES ? z1 : z1 + 2;
+    for (int k = z0; k < kend; k += 3) {
         body(k, A, C);
-        if (k + 1 >= z1) break;
+        if (k + 1 >= kend) break;
         body(k + 1, B, A);
-        if (k + 2 >= z1) break;
+        if (k + 2 >= kend) break;
         body(k + 2, C, B);
     }
-    __syncthreads();
-    write_plane(z1 - 1);
+    if constexpr (FACES) {
+        __syncthreads();
+        write_plane(z1 - 1);
+    }
 }
 
 // The finest 3-D sweep with every harmonic face coefficient computed once.
