@@ -48,11 +48,16 @@ template <> __device__ __forceinline__ double quot<double>(double a, double b)
 __device__ __forceinline__ float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
+// The harmonic mean 2ab/(a+b) of two non-negative coefficients, zero when
+// both are zero: the sum is taken no smaller than the least normal number,
+// so a zero pair gives 0 * (finite reciprocal) = 0 without a select, and
+// every normal sum gives the plain quotient.
 template <typename R>
 __device__ __forceinline__ R harm(R a, R b)
 {
-    R s = a + b;
-    return s > R(0) ? quot(R(2) * a * b, s) : R(0);
+    constexpr R tiny = sizeof(R) == 4 ? R(1.17549435e-38f) : R(2.2250738585072014e-308);
+    const R s = fmax(a + b, tiny);
+    return quot(R(2) * a * b, s);
 }
 
 template <typename V2>
