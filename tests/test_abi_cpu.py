@@ -83,3 +83,39 @@ def test_serving_sizes_coarsen(L):
         assert ptmg.footprint_bytes(_prob(2, (n, n, 1)), 1) > 0, n
     for n in W.SERVE_SIZES_3D:
         assert ptmg.footprint_bytes(_prob(3, (n, n, n)), 1) > 0, n
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """Every structure the Python binding passes through the C ABI has the
+    size and field offsets of the header's declaration (a host C program
+    compiled against include/ prints them)."""
+    import ctypes
+    import shutil
+    import subprocess
+    from paper_2206_11294_amd import ptmg, serve
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    structs = [ptmg.pt_phase, ptmg.pt_problem, ptmg.pt_state, ptmg.pt_downstream,
+               ptmg.pt_solve_opts, ptmg.pt_solve_info, serve.pt_server_config,
+               serve.pt_request_info]
+    cname = {"async_": "async"}     # Python keyword on the binding side
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "pt_mg.h"',
+             '#include "pt_serve.h"', 'int main(void) {']
+    want = []
+    for st in structs:
+        lines.append(f'  printf("%zu\\n", sizeof({st.__name__}));')
+        want.append(ctypes.sizeof(st))
+        for f in st._fields_:
+            name = f[0]
+            lines.append(f'  printf("%zu\\n", offsetof({st.__name__}, {cname.get(name, name)}));')
+            want.append(getattr(st, name).offset)
+    lines += ['  return 0;', '}']
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c99", "-I", os.path.join(ROOT, "include"), "-o", str(exe),
+                    str(src)], check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True,
+                                          check=True).stdout.split()]
+    assert got == want
