@@ -3572,6 +3572,7 @@ __global__ __launch_bounds__(DIM == 3 ? 512 : 1024) void k_tail(TailArgs<R> A)
         v.cb = nullptr;                 // stored faces and block
         v.T0 = nullptr;
         v.tmask = 0;
+        v.gate = nullptr;               // the launch checked it at entry
         v.u = (V2 *)(lds + smeta[q][4]);
         v.f = (V2 *)(lds + smeta[q][5]);
         v.fx = (const V2 *)(lds + smeta[q][6]);
