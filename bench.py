@@ -56,20 +56,31 @@ WORKLOADS = {
 }
 
 # Smoothing per acoustic workload: (nu1, nu2) on the finest level and
-# 16 nu1 + nu2 below it (PT_OPT_COARSE_SWEEPS), each the setting that
-# reached the tolerance in the least time per step when measured.  Whether
-# a solve takes 3 or 4 V-cycles sits on a threshold of the contraction, so
-# the best pair moves between workloads.  Diffusive (--stiff) steps use the
-# library's default V(2,2) on every level: one coarse sweep each way costs
-# them cycles.
+# 16 nu1 + nu2 below it (PT_OPT_COARSE_SWEEPS), and the over-relaxation of
+# the finest level's sweeps (PT_OPT_OMEGA, in thousandths), each the setting
+# that reached the tolerance in the least time per step when measured.
+# Over-relaxed by 1.1 the finest sweeps take the solves from three cycles to
+# two (the 3-D state step: from four to three).  Whether a solve takes one
+# cycle more or less sits on a threshold of the contraction, so the best
+# setting moves between workloads.  Diffusive (--stiff) steps use the
+# library's default V(2,2) on every level and omega = 1: one coarse sweep
+# each way costs them cycles.
 SWEEPS = {
     "explicit_64": (3, 2, 34),
-    "bubble2d_1024": (3, 2, 17),
-    "wall3d_256": (3, 2, 17),
-    "collapse3d_512": (4, 3, 17),
-    "state2d_1024": (3, 3, 17),
-    "state3d_256": (4, 3, 17),
-    "axi2d_1024": (3, 3, 17),
+    "bubble2d_1024": (4, 3, 17),
+    "wall3d_256": (4, 3, 17),
+    "collapse3d_512": (5, 3, 17),
+    "state2d_1024": (4, 3, 17),
+    "state3d_256": (3, 3, 17),
+    "axi2d_1024": (5, 3, 17),
+}
+OMEGA = {
+    "bubble2d_1024": 1100,
+    "wall3d_256": 1100,
+    "collapse3d_512": 1100,
+    "state2d_1024": 1100,
+    "state3d_256": 1100,
+    "axi2d_1024": 1100,
 }
 
 
@@ -439,6 +450,9 @@ def main():
     ap.add_argument("--coarse-sweeps", type=int, default=None,
                     help="16 nu1 + nu2 below the finest level (PT_OPT_COARSE_SWEEPS; "
                          "default: the workload's)")
+    ap.add_argument("--omega", type=int, default=None,
+                    help="1000 x the finest level's over-relaxation (PT_OPT_OMEGA; "
+                         "default: the workload's)")
     ap.add_argument("--w-levels", type=int, default=None,
                     help="levels below the finest visited as a W-cycle (PT_OPT_W_LEVELS; "
                          "default: 2 for diffusive 3-D steps, else 0, the V-cycle)")
@@ -489,6 +503,8 @@ def main():
     prec = ptmg.PT_PREC_MIXED if prec_name == "mixed" else ptmg.PT_PREC_FP64
     prob = make_problem(name, args.stiff)
     nu1, nu2, coarse = (2, 2, 0) if args.stiff else SWEEPS[name]
+    omega = 1000 if args.stiff else OMEGA.get(name, 1000)
+    args.omega = omega if args.omega is None else args.omega
     args.nu1 = nu1 if args.nu1 is None else args.nu1
     args.nu2 = nu2 if args.nu2 is None else args.nu2
     args.coarse_sweeps = coarse if args.coarse_sweeps is None else args.coarse_sweeps
@@ -542,6 +558,7 @@ def main():
                    + (" + pt_mg_downstream" if run["faces"] else ""),
                    "method": args.method, "time_step": "diffusive" if args.stiff else "acoustic",
                    "tail_levels": run["tail_levels"], "w_levels": args.w_levels,
+                   "omega": args.omega / 1000.0,
                    "sweeps": {"finest": [args.nu1, args.nu2],
                               "coarse": (list(divmod(args.coarse_sweeps, 16))
                                          if args.coarse_sweeps else [args.nu1, args.nu2])},
@@ -604,6 +621,7 @@ def timed_steps(prob, prec, rtol, method, args, roofline_timing=True):
             h.set_option(ptmg.PT_OPT_TAIL_CELLS, args.tail_cells)
         h.set_option(ptmg.PT_OPT_COARSE_SWEEPS, args.coarse_sweeps)
         h.set_option(ptmg.PT_OPT_W_LEVELS, args.w_levels)
+        h.set_option(ptmg.PT_OPT_OMEGA, args.omega)
         p = torch.empty(prob.ncells, dtype=torch.float64, device="cuda")
         T = torch.empty_like(p)
         rhs_p, rhs_T = torch.empty_like(p), torch.empty_like(p)

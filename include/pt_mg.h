@@ -494,7 +494,13 @@ long long pt_mg_last_cell_updates(pt_mg_t h);
  *    cycle contracts ever more slowly as the grid grows; the W-cycle's
  *    contraction stays near the two-grid one, for more coarse-level work
  *    per cycle.  Like PT_OPT_COARSE_SWEEPS this changes the iterates and
- *    cycle counts, not the converged solution. */
+ *    cycle counts, not the converged solution.
+ *  PT_OPT_OMEGA: 1000 omega, 1..1999; the finest level's red-black block
+ *    Gauss-Seidel updates become u + omega (u_GS - u) (over-relaxation;
+ *    coarser levels keep omega = 1).  1000 (default): the plain update.
+ *    With 1100 the 512^3 collapse step of the mixed-precision solve
+ *    reaches 1e-12 in two cycles of V(4,4) instead of three of V(4,3).
+ *    Changes the iterates and cycle counts, not the converged solution. */
 typedef enum {
     PT_OPT_GRAPHS = 1,
     PT_OPT_TAIL = 2,
@@ -503,7 +509,8 @@ typedef enum {
     PT_OPT_SPECULATE = 5,
     PT_OPT_TAIL_CELLS = 6,
     PT_OPT_COARSE_SWEEPS = 7,
-    PT_OPT_W_LEVELS = 8
+    PT_OPT_W_LEVELS = 8,
+    PT_OPT_OMEGA = 9
 } pt_option;
 int pt_mg_set_option(pt_mg_t h, int option, int value);
 int pt_mg_get_option(pt_mg_t h, int option);

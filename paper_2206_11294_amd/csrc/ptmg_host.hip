@@ -279,6 +279,9 @@ struct pt_mg_s {
     // levels 1 .. w_levels (above the single-block tail) visit their coarse
     // level twice per visit (W-cycle there); 0: V-cycle
     int w_levels = 0;
+    // over-relaxation of the finest level's block Gauss-Seidel sweeps, in
+    // thousandths (1000: the plain update)
+    int omega_milli = 1000;
     // stream-ordered solve: the stop flag every launch of it checks (null
     // otherwise), and its record in pinned host memory (made on first use)
     const int *gate_active = nullptr;
@@ -334,7 +337,9 @@ struct pt_mg_s {
         o.tmask = 0;
         std::memset(&o.k, 0, sizeof o.k);
         o.gate = gate_active;
+        o.omega = R(1);
         if (l == 0) {
+            o.omega = (R)(omega_milli / 1000.0);
             o.axm = (const typename VT<R>::v4 *)(sizeof(R) == 8 ? (void *)axm64()
                                                                 : (void *)at<float4>(P.o_axm32));
             compact_view<R>(o.cb, o.T0, o.tmask, o.k);
@@ -575,7 +580,7 @@ template <typename R> void smooth(pt_mg_t h, int l, int sweeps, bool zero_guess,
         launch_rb_pass<R>(h->P.dim, l == 0, L, 0, zg ? 1 : 0, h->stream);
         h->end();
         h->begin(cls, bytes_sweep_half(h, l, false));
-        launch_rb_pass<R>(h->P.dim, l == 0, L, 1, 0, h->stream);
+        launch_rb_pass<R>(h->P.dim, l == 0, L, 1, zg ? 2 : 0, h->stream);
         h->end();
         h->updates += L.N;
     }
@@ -2320,6 +2325,9 @@ int pt_mg_set_option(pt_mg_t h, int option, int value)
     } else if (option == PT_OPT_W_LEVELS) {
         if (value < 0) return fail(h, PT_ERR_ARG, "PT_OPT_W_LEVELS must be >= 0");
         h->w_levels = value;
+    } else if (option == PT_OPT_OMEGA) {
+        if (value < 1 || value > 1999) return fail(h, PT_ERR_ARG, "PT_OPT_OMEGA must be in 1..1999");
+        h->omega_milli = value;
     } else return fail(h, PT_ERR_ARG, "unknown option");
     return PT_OK;
 }
@@ -2335,6 +2343,7 @@ int pt_mg_get_option(pt_mg_t h, int option)
     if (option == PT_OPT_TAIL_CELLS) return (int)h->tail_max_cells;
     if (option == PT_OPT_COARSE_SWEEPS) return h->coarse_nu;
     if (option == PT_OPT_W_LEVELS) return h->w_levels;
+    if (option == PT_OPT_OMEGA) return h->omega_milli;
     return -1;
 }
 

@@ -65,6 +65,7 @@ template <typename R> struct Lvl {
     // non-null: the launch does nothing once *gate != 0 (the stream-ordered
     // solve has decided to stop)
     const int *gate;
+    R omega;
 };
 
 // Outer FP64 residual arguments (finest grid).

@@ -48,6 +48,28 @@ template <> __device__ __forceinline__ double quot<double>(double a, double b)
 __device__ __forceinline__ float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
+// Over-relaxation of a block Gauss-Seidel update: old + omega (new - old);
+// omega = 1 leaves the plain update (coarse levels always, the finest
+// level unless PT_OPT_OMEGA says otherwise).
+// The update enters as a value the compiler cannot see into (an empty
+// asm statement holds it in a register), so that no kernel contracts the
+// difference with the product that formed the update and every kernel
+// rounds alike.
+template <typename T> __device__ __forceinline__ T opaque(T v)
+{
+    asm volatile("" : "+v"(v));
+    return v;
+}
+template <typename R, typename V2>
+__device__ __forceinline__ V2 relax(R omega, V2 o, V2 old)
+{
+    if (omega != R(1)) {
+        o.x = fmadd(omega, opaque(o.x) - old.x, old.x);
+        o.y = fmadd(omega, opaque(o.y) - old.y, old.y);
+    }
+    return o;
+}
+
 // The harmonic mean 2ab/(a+b) of two non-negative coefficients, zero when
 // both are zero: the sum is taken no smaller than the least normal number,
 // so a zero pair gives 0 * (finite reciprocal) = 0 without a select, and
@@ -590,7 +612,8 @@ void launch_shift2(long long N, double *x, double *y, const double *sum2, double
 // The block Gauss-Seidel update of one cell (shared by the grid kernels
 // and the single-block tail cycle, whose arrays live in LDS).
 template <typename R, int DIM, bool CF, bool USE_U>
-__device__ __forceinline__ void rb_cell(const Lvl<R> &L, int i, int j, int k, long long me)
+__device__ __forceinline__ void rb_cell(const Lvl<R> &L, int i, int j, int k, long long me,
+                                        bool old_zero = false)
 {
     using V2 = typename VT<R>::v2;
     using V4 = typename VT<R>::v4;
@@ -604,6 +627,12 @@ __device__ __forceinline__ void rb_cell(const Lvl<R> &L, int i, int j, int k, lo
     V2 o;
     o.x = (d * gp - b.y * gT) * inv;
     o.y = (a * gT - b.z * gp) * inv;
+    if (L.omega != R(1)) {
+        V2 old;
+        old.x = old.y = R(0);
+        if (USE_U && !old_zero) old = L.u[me];
+        o = relax(L.omega, o, old);
+    }
     L.u[me] = o;
 }
 
@@ -732,8 +761,11 @@ __global__ __launch_bounds__(kBlock) void k_rb_pass(Lvl<R> L, int color, int zer
     const int i = 2 * ti + ((j + k + color) & 1);
     if (i >= L.nx) return;
     const long long me = i + (long long)L.nx * (j + (long long)L.ny * k);
-    if (zero_guess) rb_cell<R, DIM, CF, false>(L, i, j, k, me);
-    else rb_cell<R, DIM, CF, true>(L, i, j, k, me);
+    // zero_guess 1: the iterate is zero (first colour of a sweep from a zero
+    // guess); 2: the other colour's new values are read, the cell's own old
+    // value is zero (second colour of that sweep)
+    if (zero_guess == 1) rb_cell<R, DIM, CF, false>(L, i, j, k, me);
+    else rb_cell<R, DIM, CF, true>(L, i, j, k, me, zero_guess == 2);
 }
 
 template <typename R>
@@ -1582,7 +1614,7 @@ __global__ __launch_bounds__(TX *TY) void k_rb_fused3(Lvl<R> L, typename VT<R>::
         }
         V2 o;
         block_solve<R>(f, b, gp, gT, Sp, ST, o);
-        su[s][c] = o;
+        su[s][c] = relax(L.omega, o, su[s][c]);
     };
     auto write_plane = [&](int z) {
         if (z < z0 || z >= z1) return;
@@ -1829,7 +1861,7 @@ __global__ __launch_bounds__(TX *TY) void k_rb_fused3c(Lvl<R> L, typename VT<R>:
         accw(gp, gT, Sp, ST, wzp, sp, c);
         V2 o;
         block_solve<R>(f, b, gp, gT, Sp, ST, o);
-        su[s][c] = o;
+        su[s][c] = relax(L.omega, o, su[s][c]);
     };
     // black update on plane z with the faces of its red neighbours
     auto update_black = [&](int z, int c, V2 f, V4 b, V2 wzm, V2 wzp) {
@@ -1843,7 +1875,7 @@ __global__ __launch_bounds__(TX *TY) void k_rb_fused3c(Lvl<R> L, typename VT<R>:
         accw(gp, gT, Sp, ST, wzp, sp, c);
         V2 o;
         block_solve<R>(f, b, gp, gT, Sp, ST, o);
-        su[s][c] = o;
+        su[s][c] = relax(L.omega, o, su[s][c]);
     };
     auto write_plane = [&](int z) {
         if (z < z0 || z >= z1) return;
@@ -2061,7 +2093,7 @@ __global__ __launch_bounds__(TX *TY) void k_rb_fused3r(Lvl<R> L, Lvl<R> C,
         accw(harm2(am, sa[sp][c]), sp, c);
         V2 o;
         block_solve<R>(f, b, gp, gT, Sp, ST, o);
-        su[s][c] = o;
+        su[s][c] = relax(L.omega, o, su[s][c]);
     };
     // this thread's tile cell (residual) and coarse cell (restriction)
     const int lxr = G + t % TX, lyr = G + t / TX;
@@ -2298,7 +2330,7 @@ __global__ __launch_bounds__(TX *TY) void k_rb_tile2(Lvl<R> L, typename VT<R>::v
         }
         V2 o;
         block_solve<R>(L.f[g], sweep_B(L, g), gp, gT, Sp, ST, o);
-        su[c] = o;
+        su[c] = relax(L.omega, o, su[c]);
     };
     if (t < RW * (TY + 2)) {   // red cells ((x+y) even) of the tile and a ring of one
         const int ly = 1 + t / RW;
@@ -2403,7 +2435,7 @@ __global__ __launch_bounds__(TX *TY) void k_rb_tile2x(Lvl<R> L, Lvl<R> C,
         accw(wyp, c + PX);
         V2 o;
         block_solve<R>(L.f[g], sweep_B(L, g), gp, gT, Sp, ST, o);
-        su[c] = o;
+        su[c] = relax(L.omega, o, su[c]);
     };
     auto weight = [&](V2 am, int q) { return harm2(am, sa[q]); };
     auto wget = [&](int c, V2 &wxm, V2 &wxp, V2 &wym, V2 &wyp) {
@@ -3573,6 +3605,7 @@ __global__ __launch_bounds__(DIM == 3 ? 512 : 1024) void k_tail(TailArgs<R> A)
         v.T0 = nullptr;
         v.tmask = 0;
         v.gate = nullptr;               // the launch checked it at entry
+        v.omega = R(1);
         v.u = (V2 *)(lds + smeta[q][4]);
         v.f = (V2 *)(lds + smeta[q][5]);
         v.fx = (const V2 *)(lds + smeta[q][6]);

@@ -25,6 +25,7 @@ PT_OPT_GRAPHS, PT_OPT_TAIL, PT_OPT_FUSED, PT_OPT_TIMING_EVERY, PT_OPT_SPECULATE 
 PT_OPT_TAIL_CELLS = 6
 PT_OPT_COARSE_SWEEPS = 7
 PT_OPT_W_LEVELS = 8
+PT_OPT_OMEGA = 9
 KERNEL_CLASSES = ["outer_residual", "smooth_fine", "smooth_coarse", "restrict", "prolong",
                   "coarse_solve", "other", "downstream", "smooth_fine_transfer"]
 

@@ -841,3 +841,48 @@ def test_async_solve_equals_blocking(prec):
     rc = ptmg.lib().pt_mg_solve_noalloc(h._h, ptmg._ptr(b_p), ptmg._ptr(b_T), ptmg._ptr(p),
                                         ptmg._ptr(T), ctypes.byref(opts), ctypes.byref(info))
     assert rc == ptmg.PT_ERR_ARG
+
+
+@pytest.mark.parametrize("name", ["bubble2d_200x136", "bubble3d_40x24x56", "explicit_64"])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_over_relaxation_fused_equals_reference(name, prec):
+    """PT_OPT_OMEGA (over-relaxed finest-level sweeps): the fused sweeps and
+    transfers give the separate kernels' solution, cycles and residual
+    history bit for bit (PT_OPT_FUSED off), at V(3,2) and V(4,4) and from a
+    zero guess (whose first sweep reads no iterate); the solve meets the
+    tolerance against the oracle's own right-hand side; omega = 1 is the
+    plain update; values outside 1..1999 are refused."""
+    import workloads.device as D
+    from paper_2206_11294_amd import ptmg
+    prob = step_problems()[name]
+    op = orc.assemble(prob)
+    b_p, b_T = orc.rhs(op, prob)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        h, gb_p, gb_T, _ = D.setup(prob, prec, stream=stream)
+        assert h.get_option(ptmg.PT_OPT_OMEGA) == 1000
+        plain = h.solve(gb_p, gb_T, torch.empty_like(gb_p), torch.empty_like(gb_T),
+                        rtol=1e-11, max_cycles=60)
+        h.set_option(ptmg.PT_OPT_OMEGA, 1000)
+        again = h.solve(gb_p, gb_T, torch.empty_like(gb_p), torch.empty_like(gb_T),
+                        rtol=1e-11, max_cycles=60)
+        assert again["hist"] == plain["hist"]
+        h.set_option(ptmg.PT_OPT_OMEGA, 1100)
+        for nu in ((3, 2), (4, 4)):
+            out = {}
+            for fused in (1, 0):
+                h.set_option(ptmg.PT_OPT_FUSED, fused)
+                p, T = torch.empty_like(gb_p), torch.empty_like(gb_T)
+                info = h.solve(gb_p, gb_T, p, T, rtol=1e-11, nu1=nu[0], nu2=nu[1],
+                               max_cycles=60)
+                torch.cuda.synchronize()
+                out[fused] = (p.clone(), T.clone(), info)
+            (p1, T1, i1), (p0, T0, i0) = out[1], out[0]
+            assert i1["status"] == i0["status"] == 0, (nu, i1["status"], i0["status"])
+            assert i1["cycles"] == i0["cycles"] and i1["hist"] == i0["hist"], nu
+            assert torch.equal(p1, p0) and torch.equal(T1, T0), nu
+            assert max(orc.relres(op, b_p, b_T, host(p1), host(T1))) <= 2e-11
+            assert i1["hist"] != plain["hist"]
+        for bad in (0, 2000, -5):
+            with pytest.raises(ptmg.PtMgError):
+                h.set_option(ptmg.PT_OPT_OMEGA, bad)
