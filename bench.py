@@ -503,7 +503,9 @@ def main():
     prec = ptmg.PT_PREC_MIXED if prec_name == "mixed" else ptmg.PT_PREC_FP64
     prob = make_problem(name, args.stiff)
     nu1, nu2, coarse = (2, 2, 0) if args.stiff else SWEEPS[name]
-    omega = 1000 if args.stiff else OMEGA.get(name, 1000)
+    # diffusive 3-D steps: over-relaxed by 1.2 with the W-cycle below, 15
+    # instead of 17 cycles at 256^3; 2-D diffusive steps gain nothing from it
+    omega = (1200 if prob.dim == 3 else 1000) if args.stiff else OMEGA.get(name, 1000)
     args.omega = omega if args.omega is None else args.omega
     args.nu1 = nu1 if args.nu1 is None else args.nu1
     args.nu2 = nu2 if args.nu2 is None else args.nu2
