@@ -286,7 +286,8 @@ def serve_bench(args):
 
     def window(rate, seconds, warmup):
         srv = serve.Server(hbm_budget=int(args.serve_budget_gb * (1 << 30)),
-                           max_active=args.serve_slots, use_graphs=False)
+                           max_active=args.serve_slots, use_graphs=False,
+                           omega_milli=args.serve_omega, coarse_sweeps=args.serve_coarse)
         arrivals = W.poisson_arrivals(rate, seconds, seed=4)
         t0 = serve.now() + 0.05
         submitted = []   # (rid, arrival time, problem)
@@ -313,7 +314,8 @@ def serve_bench(args):
                     b["busy"] = None
                 busy = []
             rid = srv.submit(e["s"], ptmg.PT_PREC_MIXED, e["p"], e["T"], div=e["t"].get("div"),
-                             rtol=rtol, t_arrival=t0 + ta, keepalive=e["t"])
+                             rtol=rtol, nu1=args.serve_nu[0], nu2=args.serve_nu[1],
+                             t_arrival=t0 + ta, keepalive=e["t"])
             e["busy"] = rid
             busy.append(e)
             submitted.append((rid, ta, e["prob"]))
@@ -350,6 +352,8 @@ def serve_bench(args):
             "config": {"workload": "serving_mix", "rate_per_s": rate,
                        "seconds": seconds, "warmup_s": warmup, "pool": pool_n,
                        "slots": args.serve_slots, "hbm_budget_gb": args.serve_budget_gb,
+                       "sweeps": list(args.serve_nu), "omega_milli": args.serve_omega,
+                       "coarse_sweeps": args.serve_coarse,
                        "rtol": rtol,
                        "sizes_2d": [W.SERVE_SIZES_2D[0], W.SERVE_SIZES_2D[-1]],
                        "sizes_3d": [W.SERVE_SIZES_3D[0], W.SERVE_SIZES_3D[-1]]},
@@ -472,6 +476,15 @@ def main():
                     help="comma-separated arrival rates of a saturation sweep after the run")
     ap.add_argument("--serve-sweep-seconds", type=float, default=35.0)
     ap.add_argument("--serve-slots", type=int, default=8)
+    # the serving mix's smoothing, measured fastest: V(3,2) on the finest
+    # level over-relaxed by 1.1, one sweep each way below (two cycles
+    # instead of 2.5 on average; the engine keeps up to above 1200/s)
+    ap.add_argument("--serve-omega", type=int, default=1100,
+                    help="PT_OPT_OMEGA of every request (0: the library default)")
+    ap.add_argument("--serve-coarse", type=int, default=17,
+                    help="PT_OPT_COARSE_SWEEPS of every request (0: the library default)")
+    ap.add_argument("--serve-nu", type=int, nargs=2, default=[3, 2],
+                    help="finest-level pre- and post-sweeps of every request")
     ap.add_argument("--serve-budget-gb", type=float, default=64.0)
     args = ap.parse_args()
 

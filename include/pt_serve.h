@@ -40,6 +40,8 @@ typedef struct {
     size_t hbm_budget;   /* bytes of the device arena holding admitted requests */
     int max_active;      /* slots: requests on the device at once, 1..64 */
     int use_graphs;      /* replay each request's coarse-level cycle from a HIP graph */
+    int omega_milli;     /* PT_OPT_OMEGA of every request's handle (0: the default) */
+    int coarse_sweeps;   /* PT_OPT_COARSE_SWEEPS of every request's handle (0: the default) */
 } pt_server_config;
 
 /* Request states reported before the solve's own pt_status. */

@@ -177,6 +177,8 @@ bool admit_one(pt_server_t s)
         return true;
     }
     pt_mg_set_option(r.h, PT_OPT_GRAPHS, s->cfg.use_graphs);
+    if (s->cfg.omega_milli) pt_mg_set_option(r.h, PT_OPT_OMEGA, s->cfg.omega_milli);
+    if (s->cfg.coarse_sweeps) pt_mg_set_option(r.h, PT_OPT_COARSE_SWEEPS, s->cfg.coarse_sweeps);
     if (!r.b_p) r.own_b = (double *)(mem + r.handle_bytes);
     return true;
 }
@@ -229,7 +231,10 @@ int pt_server_create(const pt_server_config *cfg, pt_server_t *out)
 {
     if (!out) return sfail(nullptr, PT_ERR_ARG, "out is NULL");
     *out = nullptr;
-    if (!cfg || cfg->max_active < 1 || cfg->max_active > 64 || cfg->hbm_budget < kAlign)
+    if (!cfg || cfg->max_active < 1 || cfg->max_active > 64 || cfg->hbm_budget < kAlign ||
+        cfg->omega_milli < 0 || cfg->omega_milli > 1999 || cfg->coarse_sweeps < 0 ||
+        cfg->coarse_sweeps > 255 || (cfg->coarse_sweeps && ((cfg->coarse_sweeps >> 4) > 8 ||
+                                                            (cfg->coarse_sweeps & 15) > 8)))
         return sfail(nullptr, PT_ERR_ARG, "bad server config");
     pt_server_t s = new pt_server_s();
     s->cfg = *cfg;

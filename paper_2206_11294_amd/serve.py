@@ -18,7 +18,8 @@ PT_SERVE_QUEUED, PT_SERVE_ACTIVE = -3, -2
 
 class pt_server_config(ctypes.Structure):
     _fields_ = [("hbm_budget", ctypes.c_size_t), ("max_active", ctypes.c_int),
-                ("use_graphs", ctypes.c_int)]
+                ("use_graphs", ctypes.c_int), ("omega_milli", ctypes.c_int),
+                ("coarse_sweeps", ctypes.c_int)]
 
 
 class pt_request_info(ctypes.Structure):
@@ -68,9 +69,11 @@ def now() -> float:
 
 
 class Server:
-    def __init__(self, hbm_budget: int, max_active: int = 8, use_graphs: bool = False):
+    def __init__(self, hbm_budget: int, max_active: int = 8, use_graphs: bool = False,
+                 omega_milli: int = 0, coarse_sweeps: int = 0):
         self._s = ctypes.c_void_p()
-        cfg = pt_server_config(int(hbm_budget), int(max_active), int(use_graphs))
+        cfg = pt_server_config(int(hbm_budget), int(max_active), int(use_graphs),
+                               int(omega_milli), int(coarse_sweeps))
         rc = _lib().pt_server_create(ctypes.byref(cfg), ctypes.byref(self._s))
         if rc:
             raise ptmg.PtMgError(rc, _lib().pt_server_last_error(None).decode())
