@@ -850,9 +850,11 @@ template <typename R> void build_hierarchy(pt_mg_t h)
     const bool small = h->use_fused && P.nlev >= 3 && b0 >= 2 && P.m <= 128;
     if (P.nlev > 1) {
         Lvl<R> c1 = h->level<R>(1);
-        launch_coarsen<double, R>(P.dim, 1, h->level0_fp64(), (typename VT<R>::v2 *)c1.fx,
-                                  (typename VT<R>::v2 *)c1.fy, (typename VT<R>::v2 *)c1.fz,
-                                  (typename VT<R>::v4 *)c1.B, h->stream);
+        // level 1 from the finest operator in the V-cycle's precision (the
+        // FP32 copies in mixed precision: half the bytes of the FP64 one)
+        launch_coarsen<R, R>(P.dim, 1, h->level<R>(0), (typename VT<R>::v2 *)c1.fx,
+                             (typename VT<R>::v2 *)c1.fy, (typename VT<R>::v2 *)c1.fz,
+                             (typename VT<R>::v4 *)c1.B, h->stream);
         for (int l = 1; l + 1 < (small ? b0 : P.nlev); l++) {
             Lvl<R> f = h->level<R>(l), c = h->level<R>(l + 1);
             launch_coarsen<R, R>(P.dim, 0, f, (typename VT<R>::v2 *)c.fx,
