@@ -205,6 +205,7 @@ struct pt_mg_s {
     bool owns_memory = true;        // false: device + pinned memory belong to a server arena
     bool p_field = false, T_field = false;   // phases mode: p_adv / T_adv given per cell
     CBK<double> cbk64 = {};         // compact block: the constants of the last assembly
+    double ac_rho[2] = {}, ac_k[2] = {};  // phase densities and conductivities of the last assembly
     CBK<float> cbk32 = {};
     int device = 0;                 // the GPU current at setup (its static scratch)
     hipEvent_t done_ev = nullptr;   // marks the end of the last enqueued step
@@ -1013,6 +1014,10 @@ int assemble_enqueue(pt_mg_t h, const pt_problem *p)
         k32.idt = (float)k64.blk.idt;
         k32.idt2 = (float)k64.blk.idt2;
         h->cbk64 = k64.blk;
+        for (int q = 0; q < 2; q++) {
+            h->ac_rho[q] = k64.rho[q];
+            h->ac_k[q] = k64.k[q];
+        }
         h->cbk32 = k32;
         a.k64 = k64;
     }
@@ -1452,6 +1457,10 @@ int outer(pt_mg_t h, const double *b_p, const double *b_T, const double *src_p,
     a.ac = h->ac64();
     a.B = h->B64();
     h->compact_view<double>(a.cb, a.T0, a.tmask, a.k);
+    for (int q = 0; q < 2; q++) {
+        a.rho[q] = h->ac_rho[q];
+        a.kc[q] = h->ac_k[q];
+    }
     a.b_p = b_p;
     a.b_T = b_T;
     a.bshift = bshift;
@@ -1468,8 +1477,10 @@ int outer(pt_mg_t h, const double *b_p, const double *b_T, const double *src_p,
     a.update = update ? 1 : 0;
     a.gate = h->gate_active;
     const double Rb = sizeof(RV);
-    // iterate (unless zero), operator (a, block), b
-    double nbytes = (double)P.N * ((src_p ? 16 : 0) + op_bytes(h, 0, 8) + 16);
+    // iterate (unless zero), operator (a, block; the compact block alone,
+    // a formed from its C), b
+    const double opb = P.compact ? 8.0 * (2 + h->T_field) : op_bytes(h, 0, 8);
+    double nbytes = (double)P.N * ((src_p ? 16 : 0) + opb + 16);
     if (update) nbytes += (double)P.N * (2 * Rb + 16);
     if (want_r) nbytes += (double)P.N * 2 * Rb;
     if (res_p) nbytes += 8.0 * P.N;

@@ -75,12 +75,14 @@ template <typename RV> struct OuterArgs {
     double inv_h2;
     const double4 *axm;            // r-z metric per row (2-D) or null
     int phases;                    // 1: paper form (b = (lp, lT)), 0: canonical
-    const double2 *ac;             // FP64 cell coefficients
+    const double2 *ac;             // FP64 cell coefficients (unread with the compact block)
     const double4 *B;              // FP64 block, or
     const double2 *cb;             // the compact block (non-null) as in Lvl
     const double *T0;
     long long tmask;
     CBK<double> k;
+    double rho[2], kc[2];          // compact block: a_p = 1/(C rho_1 + (1-C) rho_2),
+                                   // a_T = C k_1 + (1-C) k_2 formed from C
     const double *b_p, *b_T;       // mode-native right-hand side (null: zero)
     const double *bshift;          // [2] sums of b (mean constraint) or null
     double bshift_scale;           // b -= bshift_scale * bshift (1/N: the mean)

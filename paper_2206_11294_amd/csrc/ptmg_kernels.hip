@@ -113,10 +113,11 @@ __device__ __forceinline__ double2 harm2_exact(double2 a, double2 b)
 // (p, T) (or fixed), and their C-average bb.  Divisions are correctly
 // rounded; every multiply-add is written out (fmadd) or kept as a
 // separate product, so that each kernel computes the same bits.
-__device__ __forceinline__ double2 phases_ac(const OpK &k, double C)
+__device__ __forceinline__ double2 phases_ac(const double (&rho)[2], const double (&kc)[2],
+                                             double C)
 {
     const double g = 1.0 - C;
-    return make_double2(1.0 / fmadd(C, k.rho[0], g * k.rho[1]), fmadd(C, k.k[0], g * k.k[1]));
+    return make_double2(1.0 / fmadd(C, rho[0], g * rho[1]), fmadd(C, kc[0], g * kc[1]));
 }
 __device__ __forceinline__ double phases_beta(const OpK &k, int q, double p, double T)
 {
@@ -360,7 +361,7 @@ __global__ __launch_bounds__(kBlock) void k_assemble(AsmArgs a)
         argbad = !(c >= 0.0 && c <= 1.0) || !isfinite(p) || !(T > 0.0) || !isfinite(T);
         const double bb = fmadd(c, phases_beta(a.k64, 0, p, T), (1.0 - c) * phases_beta(a.k64, 1, p, T));
         B = compact_B(a.k64.blk, c, bb, T);
-        ac = phases_ac(a.k64, c);
+        ac = phases_ac(a.k64.rho, a.k64.k, c);
         if (a.cb64) {
             const bool wT = a.T_cells || t == 0;
             a.cb64[t] = make_double2(c, bb);
@@ -3072,9 +3073,14 @@ __global__ __launch_bounds__(TX *TY) void k_outer_zm(OuterArgs<RV> a, int NX, in
         // the loads of a plane stay raw in registers until the plane is
         // stored a step later (the update u + du is formed there), so that
         // they are in flight while the step between computes
+        // with the compact block, pa holds (C, bb) of the cell and the cell
+        // coefficients are formed from C when the plane is stored (bit i of
+        // inb: cell i of the ring lies in the grid)
         double2 pu[NLD], pa[NLD];
         V2 pd[NLD];
+        unsigned inb = 0u;
         auto fetch = [&](int z) {
+            inb = 0u;
 #pragma unroll
             for (int i = 0; i < NLD; i++) {
                 const int c = t + i * NT;
@@ -3086,7 +3092,8 @@ __global__ __launch_bounds__(TX *TY) void k_outer_zm(OuterArgs<RV> a, int NX, in
                     const long long g = gx + (long long)NX * gy + nxy * z;
                     if (a.src_p) pu[i] = make_double2(a.src_p[g], a.src_T[g]);
                     if (a.update) pd[i] = a.du[g];
-                    pa[i] = a.ac[g];
+                    pa[i] = a.cb ? a.cb[g] : a.ac[g];
+                    inb |= 1u << i;
                 }
             }
         };
@@ -3102,7 +3109,9 @@ __global__ __launch_bounds__(TX *TY) void k_outer_zm(OuterArgs<RV> a, int NX, in
                         v.y += (double)pd[i].y;
                     }
                     su[s][c] = v;
-                    sa[s][c] = pa[i];
+                    double2 w = pa[i];
+                    if (a.cb) w = ((inb >> i) & 1u) ? phases_ac(a.rho, a.kc, w.x) : make_double2(0.0, 0.0);
+                    sa[s][c] = w;
                 }
             }
         };
