@@ -942,8 +942,11 @@ template <typename R> void hierarchy(pt_mg_t h)
 }
 
 // Enqueue assembly, hierarchy, coarsest inverse and the flag read-back on
-// the handle's stream; done_ev marks the end.
-int assemble_enqueue(pt_mg_t h, const pt_problem *p)
+// the handle's stream; done_ev marks the end.  With b_p, b_T (phases and
+// state mode) the assembly also writes the paper right-hand side, as
+// pt_mg_paper_rhs would with these p_adv, T_adv and div.
+int assemble_enqueue(pt_mg_t h, const pt_problem *p, const double *div = nullptr,
+                     double *b_p = nullptr, double *b_T = nullptr)
 {
     const Plan &P = h->P;
     AsmArgs a;
@@ -1020,6 +1023,11 @@ int assemble_enqueue(pt_mg_t h, const pt_problem *p)
         }
         h->cbk32 = k32;
         a.k64 = k64;
+    }
+    if (b_p && p->mode != PT_COEF_EXPLICIT) {
+        a.div = div;
+        a.b_p = b_p;
+        a.b_T = b_T;
     }
     a.flags = h->flags();
     h->ready = false;
@@ -1952,9 +1960,8 @@ int pt_mg_step(pt_mg_t h, const pt_problem *prob, const double *div_ustar, doubl
     if (!same_grid(prob, &h->prob))
         return fail(h, PT_ERR_STATE, "update must keep dim, n, h, mode and mean_constraint");
     if (P.total != h->P.total) return fail(h, PT_ERR_STATE, "update changes the memory plan");
-    int rc = assemble_enqueue(h, prob);
-    if (rc == PT_OK)
-        rc = handle_paper_rhs_async(h, prob->p_adv, prob->T_adv, div_ustar, b_p, b_T);
+    // the assembly forms the paper right-hand side with the block
+    int rc = assemble_enqueue(h, prob, div_ustar, b_p, b_T);
     if (rc != PT_OK) {
         (void)hipStreamSynchronize(h->stream);
         return rc;

@@ -139,6 +139,10 @@ struct AsmArgs {
     float *T32;
     int T_cells;
     OpK k64;
+    // phases and state mode: the paper right-hand side (Eqs. 33-34) formed
+    // with the block, into b_p, b_T (null: not formed); div null: zero
+    const double *div;
+    double *b_p, *b_T;
     int *flags;     // [0] argument errors, [1] singular blocks, [2] nonzero B
 };
 

@@ -315,12 +315,26 @@ static inline unsigned nblk(long long n) { return (unsigned)((n + kBlock - 1) / 
 // fraction C (the averaging rule of Sec. 3) and kept compact.  State mode:
 // each phase's block weighted by its fraction from its own density;
 // explicit mode: the given coefficients.
+// The paper right-hand side of one cell (Eqs. 33-34) from its block (the
+// lambdas as the block holds them: l1 = -B_TT, l2 = -B_Tp, l4 = B_pT / l1,
+// l3 = -B_pp + l4 l2), its provisional p, T and div u*.  Every product and
+// sum is written out, so the assembly (which forms it with the block) and
+// k_paper_rhs round it the same way.
+__device__ __forceinline__ void paper_rhs_cell(double4 B, double p, double T, double d, double dt,
+                                               double &bp, double &bT)
+{
+    const double l1 = -B.w, l2 = -B.z, l4 = B.y / l1, l3 = fmadd(l4, l2, -B.x);
+    bT = fmadd(l1, T, opaque(l2 * p));
+    bp = fmadd(l3, p, d / dt);
+}
+
 __global__ __launch_bounds__(kBlock) void k_assemble(AsmArgs a)
 {
     long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
     if (t >= a.N) return;
     double2 ac;
     double4 B;
+    double rp = 0.0, rT = 0.0;   // p, T of the paper right-hand side
     bool argbad = false;
     if (a.mode == PT_COEF_STATE) {
         // each phase's block weighted by its fraction, written with the
@@ -329,6 +343,8 @@ __global__ __launch_bounds__(kBlock) void k_assemble(AsmArgs a)
         // gamma / (rho c^2)), C_i BpT = -C_i beta / dt^2, C_i BTp =
         // -C_i beta T / dt, C_i BTT = m_i c_p / dt (Eqs. 29-32)
         const double c = a.C[t], p = a.p_adv[t], T = a.T_adv[t];
+        rp = p;
+        rT = T;
         const double frac[2] = {c, 1.0 - c}, mass[2] = {a.m1[t], a.m2[t]};
         const pt_phase *ph[2] = {&a.liq, &a.gas};
         argbad = !(c >= 0.0 && c <= 1.0) || !isfinite(p) || !(T > 0.0) || !isfinite(T);
@@ -358,6 +374,8 @@ __global__ __launch_bounds__(kBlock) void k_assemble(AsmArgs a)
         double c = a.C[t];
         double p = a.p_adv ? a.p_adv[t] : a.p_adv_const;
         double T = a.T_adv ? a.T_adv[t] : a.T_adv_const;
+        rp = p;
+        rT = T;
         argbad = !(c >= 0.0 && c <= 1.0) || !isfinite(p) || !(T > 0.0) || !isfinite(T);
         const double bb = fmadd(c, phases_beta(a.k64, 0, p, T), (1.0 - c) * phases_beta(a.k64, 1, p, T));
         B = compact_B(a.k64.blk, c, bb, T);
@@ -392,6 +410,7 @@ __global__ __launch_bounds__(kBlock) void k_assemble(AsmArgs a)
     bool sing = !(B.x > 0.0 && B.w > 0.0 && B.x * B.w - B.y * B.z > 0.0);
     if (argbad) atomicOr(&a.flags[FLAG_ARG], 1);
     if (sing) atomicOr(&a.flags[FLAG_SINGULAR], 1);
+    if (a.b_p) paper_rhs_cell(B, rp, rT, a.div ? a.div[t] : 0.0, a.dt, a.b_p[t], a.b_T[t]);
     a.ac64[t] = ac;
     if (a.B64) a.B64[t] = B;
     if (a.ac32) a.ac32[t] = make_float2((float)ac.x, (float)ac.y);
@@ -502,13 +521,9 @@ __global__ __launch_bounds__(kBlock) void k_paper_rhs(Lvl<double> L, const doubl
 {
     long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
     if (t >= L.N) return;
-    double4 B = cell_B(L, t);
-    double l1 = -B.w, l2 = -B.z, l4 = B.y / l1, l3 = -B.x + l4 * l2;
-    double p = p_adv ? p_adv[t] : p_const;
-    double T = T_adv ? T_adv[t] : T_const;
-    double d = div ? div[t] : 0.0;
-    b_T[t] = l1 * T + l2 * p;
-    b_p[t] = l3 * p + d / dt;
+    const double p = p_adv ? p_adv[t] : p_const;
+    const double T = T_adv ? T_adv[t] : T_const;
+    paper_rhs_cell(cell_B(L, t), p, T, div ? div[t] : 0.0, dt, b_p[t], b_T[t]);
 }
 
 void launch_paper_rhs(const Lvl<double> &L, const double *p_adv, double p_const,
