@@ -279,9 +279,12 @@ int pt_mg_step(pt_mg_t h, const pt_problem *prob, const double *div_ustar, doubl
                pt_solve_info *info);
 
 /* Residual in FP64, mode-native form: res = b - L(a) of Eqs. (27)-(28)
- * (PT_COEF_PHASES) or f - A u (PT_COEF_EXPLICIT).  r_p, r_T [N] may be
- * NULL.  relres (may be NULL) receives ||res_c||_2 / ||b_c||_2 for
- * c = p, T, reduced in a fixed order (bitwise reproducible). */
+ * (PT_COEF_PHASES) or f - A u (PT_COEF_EXPLICIT).  p, T [N] are the
+ * iterate, or both NULL for a zero iterate (res = b, the first residual
+ * of a solve from a zero guess; the same values and norms as with zero
+ * arrays).  r_p, r_T [N] may be NULL.  relres (may be NULL) receives
+ * ||res_c||_2 / ||b_c||_2 for c = p, T, reduced in a fixed order (bitwise
+ * reproducible). */
 int pt_mg_residual(pt_mg_t h, const double *b_p, const double *b_T, const double *p,
                    const double *T, double *r_p, double *r_T, double relres[2]);
 

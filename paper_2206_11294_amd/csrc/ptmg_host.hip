@@ -1487,7 +1487,11 @@ int outer(pt_mg_t h, const double *b_p, const double *b_T, const double *src_p,
     const double Rb = sizeof(RV);
     // iterate (unless zero), operator (a, block; the compact block alone,
     // a formed from its C), b
-    const double opb = P.compact ? 8.0 * (2 + h->T_field) : op_bytes(h, 0, 8);
+    double opb = P.compact ? 8.0 * (2 + h->T_field) : op_bytes(h, 0, 8);
+    // a zero iterate: the residual is b, the block enters through l4 alone
+    // ((C, bb) of the compact block, else the stored block; none without
+    // the paper form)
+    if (!src_p && !update) opb = !a.phases ? 0.0 : (P.compact ? 16.0 : 32.0);
     double nbytes = (double)P.N * ((src_p ? 16 : 0) + opb + 16);
     if (update) nbytes += (double)P.N * (2 * Rb + 16);
     if (want_r) nbytes += (double)P.N * 2 * Rb;
@@ -1551,7 +1555,7 @@ int pt_mg_residual(pt_mg_t h, const double *b_p, const double *b_T, const double
                    double *r_p, double *r_T, double relres[2])
 {
     if (!h || !h->ready) return fail(h, PT_ERR_STATE, "handle not ready");
-    if (!b_p || !b_T || !p || !T) return fail(h, PT_ERR_ARG, "NULL field");
+    if (!b_p || !b_T || !p != !T) return fail(h, PT_ERR_ARG, "NULL field");
     int nb = outer_any(h, b_p, b_T, p, T, nullptr, nullptr, false, false, r_p, r_T, nullptr);
     double s[4];
     int rc = read_norms(h, nb, s);

@@ -3063,6 +3063,41 @@ namespace ptmg {
 // flat 3-D one (ny = 1, planes = rows, TY = 1, no y neighbours).
 template <int TY> struct Flat { static constexpr bool v = TY == 1; };
 
+// The right-hand side with the mean constraint's shift.
+template <typename RV>
+__device__ __forceinline__ void outer_b(const OuterArgs<RV> &a, double &bp, double &bT)
+{
+    if (a.bshift) {
+        bp -= a.bshift_scale * a.bshift[0];
+        bT -= a.bshift_scale * a.bshift[1];
+    }
+}
+// The outputs of one cell of the outer residual and its terms of the
+// norms (every sum written out, so the residual of a zero iterate below
+// sums exactly as the stencil kernel does).
+template <typename RV>
+__device__ __forceinline__ void outer_out(const OuterArgs<RV> &a, long long g, double resp,
+                                          double resT, double rp, double rT, double bp,
+                                          double bT, double *acc)
+{
+    if (a.r) {
+        typename VT<RV>::v2 o;
+        o.x = (RV)rp;
+        o.y = (RV)rT;
+        a.r[g] = o;
+    }
+    if (a.res_p) a.res_p[g] = resp;
+    if (a.res_T) a.res_T[g] = resT;
+    if (a.r64_p) {
+        a.r64_p[g] = rp;
+        a.r64_T[g] = rT;
+    }
+    acc[0] = fmadd(resp, resp, acc[0]);
+    acc[1] = fmadd(resT, resT, acc[1]);
+    acc[2] = fmadd(bp, bp, acc[2]);
+    acc[3] = fmadd(bT, bT, acc[3]);
+}
+
 template <int DIM, typename RV, int TX, int TY>
 __global__ __launch_bounds__(TX *TY) void k_outer_zm(OuterArgs<RV> a, int NX, int NY, int NZ,
                                                      int zc, int tiles_x, int tiles_y, int ntiles)
@@ -3186,17 +3221,14 @@ __global__ __launch_bounds__(TX *TY) void k_outer_zm(OuterArgs<RV> a, int NX, in
                 const double Lp = Sp * um.x - nbp;   // -div(a_p grad p)
                 const double LT = ST * um.y - nbT;   // -div(a_T grad T)
                 double bp = bp0, bT = bT0;
-                if (a.bshift) {
-                    bp -= a.bshift_scale * a.bshift[0];
-                    bT -= a.bshift_scale * a.bshift[1];
-                }
+                outer_b(a, bp, bT);
                 double resp, resT, rp, rT;
                 if (a.phases) {
                     const double l1 = -B.w, l2 = -B.z, l4 = B.y / l1, l3 = -B.x + l4 * l2;
                     resT = bT - (-LT + l1 * um.y + l2 * um.x);
                     resp = bp - (-Lp + l3 * um.x + l4 * (-LT));
                     rT = -resT;
-                    rp = -resp + l4 * resT;
+                    rp = fmadd(l4, resT, -resp);
                 } else {
                     rp = bp - (Lp + B.x * um.x + B.y * um.y);
                     rT = bT - (LT + B.z * um.x + B.w * um.y);
@@ -3208,26 +3240,75 @@ __global__ __launch_bounds__(TX *TY) void k_outer_zm(OuterArgs<RV> a, int NX, in
                     a.dst_p[g] = um.x;
                     a.dst_T[g] = um.y;
                 }
-                if (a.r) {
-                    V2 o;
-                    o.x = (RV)rp;
-                    o.y = (RV)rT;
-                    a.r[g] = o;
-                }
-                if (a.res_p) a.res_p[g] = resp;
-                if (a.res_T) a.res_T[g] = resT;
-                if (a.r64_p) {
-                    a.r64_p[g] = rp;
-                    a.r64_T[g] = rT;
-                }
-                acc[0] += resp * resp;
-                acc[1] += resT * resT;
-                acc[2] += bp * bp;
-                acc[3] += bT * bT;
+                outer_out(a, g, resp, resT, rp, rT, bp, bT, acc);
             }
             B = op_B64_fin(a, Bn);
             bp0 = bpn;
             bT0 = bTn;
+        }
+    }
+    block_reduce_store(acc, 4, a.partials + 4ll * blockIdx.x);
+}
+
+// The outer residual of a zero iterate (the first of a solve from a zero
+// guess): the residual is b itself, so no stencil is applied; each thread
+// walks the column of cells that is its own in k_outer_zm (the same
+// blocks, tiles and z order), so that the partial sums, and with them the
+// norms, are those of k_outer_zm bit for bit.  The block enters through
+// l4 = B_pT / (-B_TT) alone (compact block: (C, bb) without T).
+template <int DIM, typename RV, int TX, int TY>
+__global__ __launch_bounds__(TX *TY) void k_outer_zg(OuterArgs<RV> a, int NX, int NY, int NZ,
+                                                     int zc, int tiles_x, int tiles_y, int ntiles)
+{
+    if (gated(a.gate)) return;
+    constexpr int U = 4;   // cells whose loads are in flight together
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int t = threadIdx.x;
+    if (tile < ntiles) {
+        const int txi = tile % tiles_x;
+        const int rr = tile / tiles_x;
+        const int x0 = txi * TX, y0 = (rr % tiles_y) * TY;
+        const int z0 = (rr / tiles_y) * zc, z1 = min(z0 + zc, NZ);
+        const long long nxy = (long long)NX * NY;
+        const int gx = x0 + t % TX, gy = y0 + t / TX;
+        if (gx < NX && gy < NY) {
+            const long long g0 = gx + (long long)NX * gy;
+            for (int kb = z0; kb < z1; kb += U) {
+                double2 cb[U];
+                double4 Bs[U];
+                double bps[U], bTs[U];
+#pragma unroll
+                for (int u = 0; u < U; u++) {
+                    if (kb + u < z1) {
+                        const long long g = g0 + nxy * (kb + u);
+                        if (a.phases) {
+                            if (a.cb) cb[u] = a.cb[g];
+                            else Bs[u] = a.B[g];
+                        }
+                        bps[u] = a.b_p ? a.b_p[g] : 0.0;
+                        bTs[u] = a.b_T ? a.b_T[g] : 0.0;
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < U; u++) {
+                    if (kb + u < z1) {
+                        double bp = bps[u], bT = bTs[u];
+                        outer_b(a, bp, bT);
+                        double rp, rT;
+                        if (a.phases) {
+                            const double4 B = a.cb ? compact_B(a.k, cb[u].x, cb[u].y, 0.0) : Bs[u];
+                            const double l1 = -B.w, l4 = B.y / l1;
+                            rT = -bT;
+                            rp = fmadd(l4, bT, -bp);
+                        } else {
+                            rp = bp;
+                            rT = bT;
+                        }
+                        outer_out(a, g0 + nxy * (kb + u), bp, bT, rp, rT, bp, bT, acc);
+                    }
+                }
+            }
         }
     }
     block_reduce_store(acc, 4, a.partials + 4ll * blockIdx.x);
@@ -3264,6 +3345,16 @@ template <typename RV>
 int launch_outer_zm(int dim, const OuterArgs<RV> &a, hipStream_t s)
 {
     const ZmGeom g = outer_geom(dim, a.nx, a.ny, a.nz);
+    if (!a.src_p && !a.update) {
+        // a zero iterate: the residual is b (same blocks and partials)
+        if (dim == 3)
+            hipLaunchKernelGGL((k_outer_zg<3, RV, 64, 4>), dim3(g.nt), dim3(256), 0, s, a, g.NX,
+                               g.NY, g.NZ, g.zc, g.tx, g.ty, g.nt);
+        else
+            hipLaunchKernelGGL((k_outer_zg<2, RV, 256, 1>), dim3(g.nt), dim3(256), 0, s, a, g.NX,
+                               g.NY, g.NZ, g.zc, g.tx, g.ty, g.nt);
+        return g.nt;
+    }
     if (dim == 3)
         hipLaunchKernelGGL((k_outer_zm<3, RV, 64, 4>), dim3(g.nt), dim3(256), 0, s, a, g.NX, g.NY,
                            g.NZ, g.zc, g.tx, g.ty, g.nt);

@@ -123,6 +123,24 @@ def test_outer_residual(case, prec):
     np.testing.assert_allclose(rel, ref_rel, rtol=1e-10)
 
 
+@pytest.mark.parametrize("prec", PRECS)
+def test_outer_residual_zero_iterate(case, prec):
+    """a4: the residual of a zero iterate (the first of every solve from a
+    zero guess, a pointwise pass) equals the stencil residual of zero
+    arrays bit for bit, norms included, and is b itself."""
+    import torch
+    prob, op = case["prob"], case["op"]
+    h = case[prec][0]
+    bp, bT = orc.rhs(op, prob)
+    db_p, db_T = dev(bp), dev(bT)
+    zero = torch.zeros_like(db_p)
+    r_p, r_T, rel = h.residual(db_p, db_T, zero, zero)
+    z_p, z_T, zrel = h.residual(db_p, db_T, None, None)
+    assert torch.equal(r_p, z_p) and torch.equal(r_T, z_T)
+    assert rel == zrel and all(x in (0.0, 1.0) for x in zrel)
+    assert torch.equal(z_p, db_p) and torch.equal(z_T, db_T)
+
+
 def _level_fields(op, seed, scale_u=True):
     rng = np.random.default_rng(seed)
     N = op.N
