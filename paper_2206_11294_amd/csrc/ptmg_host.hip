@@ -528,6 +528,13 @@ bool fused_level(pt_mg_t h, int l)
     return h->use_fused && (h->P.dim == 2 || l == 0 || h->P.lv[l].N >= (1ll << 20));
 }
 
+// 3-D coarse levels of at least 2^20 cells restrict their residual with
+// the plane-marching kernel (bitwise the gather kernel's result).
+bool restrict_zm_level(pt_mg_t h, int l)
+{
+    return h->use_fused && h->P.dim == 3 && l >= 1 && h->P.lv[l].N >= (1ll << 20);
+}
+
 // 2-D coarse levels (not the coarsest) with nu1, nu2 in {1, 2}: each
 // visit of the level in a V-cycle is a single kernel.
 bool half_level(pt_mg_t h, int l, int nu1, int nu2)
@@ -623,6 +630,7 @@ template <typename R> void restrict_level(pt_mg_t h, int l)
     // u, f, the operator read; coarse f written
     h->begin(PT_K_RESTRICT, (double)F.N * (4 * Rb + op_bytes(h, l, Rb)) + (double)C.N * 2 * Rb);
     if (l == 0) launch_restrict_zm<R>(h->P.dim, F, C, h->stream);
+    else if (restrict_zm_level(h, l)) launch_restrict_zm<R>(h->P.dim, F, C, h->stream, true);
     else launch_restrict<R>(h->P.dim, 0, F, C, h->stream);
     h->end();
     h->updates += F.N;

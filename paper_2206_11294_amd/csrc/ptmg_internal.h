@@ -278,7 +278,8 @@ void launch_rb_fused3r(const Lvl<R> &L, const Lvl<R> &C, typename VT<R>::v2 *uo,
 template <typename R>
 void launch_restrict(int dim, int level0, const Lvl<R> &F, const Lvl<R> &C, hipStream_t s);
 template <typename R>
-void launch_restrict_zm(int dim, const Lvl<R> &F, const Lvl<R> &C, hipStream_t s);  // finest grid
+void launch_restrict_zm(int dim, const Lvl<R> &F, const Lvl<R> &C, hipStream_t s,
+                        bool faces = false);  // finest grid, or (faces) a 3-D coarse level
 template <typename R> size_t tail_level_lds(int dim, long long N);
 template <typename R>
 bool launch_tail(int dim, const TailArgs<R> &a, size_t lds_bytes, hipStream_t s);

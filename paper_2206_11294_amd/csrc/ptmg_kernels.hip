@@ -843,22 +843,33 @@ __global__ __launch_bounds__(kBlock) void k_prolong(Lvl<R> F, Lvl<R> C)
     prolong_cell<R, DIM>(F, C, i, j, k, t);
 }
 
-// 3-D: a 32 x 8 x 4 fine tile per block, its coarse parents and their
-// neighbours (18 x 6 x 4) staged in LDS once instead of eight global reads
+// 3-D: a 32 x 8 x 8 fine tile per block, its coarse parents and their
+// neighbours (18 x 6 x 6) staged in LDS once instead of eight global reads
 // per fine cell; the arithmetic of prolong_cell.
 template <typename R>
 __global__ __launch_bounds__(1024) void k_prolong3t(Lvl<R> F, Lvl<R> C, int tiles_x, int tiles_y)
 {
     if (gated(F.gate)) return;
     using V2 = typename VT<R>::v2;
-    constexpr int TX = 32, TY = 8, TZ = 4;
+    // a 32 x 8 x 8 fine tile: each thread adds the correction to the cells
+    // of planes k and k + 4, whose values are loaded with the coarse
+    // tile's, before the barrier
+    constexpr int TX = 32, TY = 8, TZ = 8, ZH = TZ / 2;
     constexpr int CX = TX / 2 + 2, CY = TY / 2 + 2, CZ = TZ / 2 + 2;
+    static_assert(CX * CY * CZ <= 1024, "one coarse cell per thread");
     __shared__ V2 sc[CX * CY * CZ];
     const int b = blockIdx.x;
     const int x0 = (b % tiles_x) * TX, y0 = ((b / tiles_x) % tiles_y) * TY;
     const int z0 = (b / tiles_x / tiles_y) * TZ;
     const int cx0 = x0 / 2 - 1, cy0 = y0 / 2 - 1, cz0 = z0 / 2 - 1;
     const int t = threadIdx.x;
+    const int i = x0 + t % TX, j = y0 + (t / TX) % TY, k = z0 + t / (TX * TY);
+    const bool in = i < F.nx && j < F.ny;
+    const long long g = i + (long long)F.nx * (j + (long long)F.ny * k);
+    const long long gh = g + (long long)F.nx * F.ny * ZH;
+    V2 u0, u1;
+    if (in && k < F.nz) u0 = F.u[g];
+    if (in && k + ZH < F.nz) u1 = F.u[gh];
     if (t < CX * CY * CZ) {
         const int ci = cx0 + t % CX, cj = cy0 + (t / CX) % CY, ck = cz0 + t / (CX * CY);
         V2 v;
@@ -868,18 +879,23 @@ __global__ __launch_bounds__(1024) void k_prolong3t(Lvl<R> F, Lvl<R> C, int tile
         sc[t] = v;
     }
     __syncthreads();
-    const int i = x0 + t % TX, j = y0 + (t / TX) % TY, k = z0 + t / (TX * TY);
-    if (i >= F.nx || j >= F.ny || k >= F.nz) return;
+    if (!in) return;
     auto get = [&](int a, int bb, int c) {
         return sc[(a - cx0) + CX * ((bb - cy0) + CY * (c - cz0))];
     };
     R vp, vT;
-    prolong_delta_from<R, 3>(i, j, k, C.nx, C.ny, C.nz, get, vp, vT);
-    const long long g = i + (long long)F.nx * (j + (long long)F.ny * k);
-    V2 u = F.u[g];
-    u.x += vp;
-    u.y += vT;
-    F.u[g] = u;
+    if (k < F.nz) {
+        prolong_delta_from<R, 3>(i, j, k, C.nx, C.ny, C.nz, get, vp, vT);
+        u0.x += vp;
+        u0.y += vT;
+        F.u[g] = u0;
+    }
+    if (k + ZH < F.nz) {
+        prolong_delta_from<R, 3>(i, j, k + ZH, C.nx, C.ny, C.nz, get, vp, vT);
+        u1.x += vp;
+        u1.y += vT;
+        F.u[gh] = u1;
+    }
 }
 
 template <typename R>
@@ -887,7 +903,7 @@ void launch_prolong(int dim, const Lvl<R> &F, const Lvl<R> &C, hipStream_t s)
 {
     dim3 g(nblk(F.N)), b(kBlock);
     if (dim == 3) {
-        const int tx = (F.nx + 31) / 32, ty = (F.ny + 7) / 8, tz = (F.nz + 3) / 4;
+        const int tx = (F.nx + 31) / 32, ty = (F.ny + 7) / 8, tz = (F.nz + 7) / 8;
         hipLaunchKernelGGL((k_prolong3t<R>), dim3(tx * ty * tz), dim3(1024), 0, s, F, C, tx, ty);
         return;
     }
@@ -3366,11 +3382,16 @@ int launch_outer_zm(int dim, const OuterArgs<RV> &a, hipStream_t s)
 template int launch_outer_zm<float>(int, const OuterArgs<float> &, hipStream_t);
 template int launch_outer_zm<double>(int, const OuterArgs<double> &, hipStream_t);
 
-// Finest-grid residual f - A u and its restriction (mean of the 2^d
-// children) to the coarse right-hand side, plane-marching like k_outer_zm.
-// Coarse plane K collects fine planes 2K and 2K+1, so chunks start on even
-// planes; the 2x2 (2-D: 2) in-plane sums go through LDS.
-template <typename R, int TX, int TY>
+// Residual f - A u and its restriction (mean of the 2^d children) to the
+// coarse right-hand side, plane-marching like k_outer_zm: the finest grid
+// (cell coefficients in the ring) or, FACES, a coarse level (each cell's
+// six stored faces read with its f and block).  Coarse plane K collects
+// fine planes 2K and 2K+1, so chunks start on even planes; the 2x2 (2-D:
+// 2) in-plane sums go through LDS.  Faces and children are summed in the
+// order of restrict_cell (zero faces and zero neighbours past the
+// boundary add nothing), so the coarse levels' result is k_restrict's bit
+// for bit.
+template <typename R, int TX, int TY, bool FACES>
 __global__ __launch_bounds__(TX *TY) void k_restrict_zm(Lvl<R> F, Lvl<R> C, int NX, int NY, int NZ,
                                                         int zc, int tiles_x, int tiles_y,
                                                         int ntiles)
@@ -3384,7 +3405,7 @@ __global__ __launch_bounds__(TX *TY) void k_restrict_zm(Lvl<R> F, Lvl<R> C, int 
     constexpr int NLD = (PS + NT - 1) / NT;
     constexpr int CX = TX / 2, CY = FLAT ? 1 : TY / 2;
     __shared__ V2 su[4][PS];
-    __shared__ V2 sa[4][PS];
+    __shared__ V2 sa[FACES ? 1 : 4][FACES ? 1 : PS];
     __shared__ V2 sr[NT];
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     if (tile >= ntiles) return;
@@ -3407,7 +3428,7 @@ __global__ __launch_bounds__(TX *TY) void k_restrict_zm(Lvl<R> F, Lvl<R> C, int 
             if (c < PS && z >= 0 && z < NZ && gx >= 0 && gx < NX && gy >= 0 && gy < NY) {
                 const long long g = gx + (long long)NX * gy + nxy * z;
                 pu[i] = F.u[g];
-                pa[i] = cell_ac(F, g);
+                if (!FACES) pa[i] = cell_ac(F, g);
             }
         }
     };
@@ -3418,7 +3439,7 @@ __global__ __launch_bounds__(TX *TY) void k_restrict_zm(Lvl<R> F, Lvl<R> C, int 
             const int c = t + i * NT;
             if (c < PS) {
                 su[s][c] = pu[i];
-                sa[s][c] = pa[i];
+                if (!FACES) sa[s][c] = pa[i];
             }
         }
     };
@@ -3428,11 +3449,22 @@ __global__ __launch_bounds__(TX *TY) void k_restrict_zm(Lvl<R> F, Lvl<R> C, int 
     const int c = ly * PX + lx;
     V2 fn;
     V4 Bn;
+    V2 wn[6], w6[6];   // FACES: the cell's faces x-, x+, y-, y+, z-, z+
     auto fetch_cell = [&](int z) {
         if (mine && z < z1) {
             const long long g = gx + (long long)NX * gy + nxy * z;
             fn = F.f[g];
             Bn = sweep_B_raw(F, g);
+            if (FACES) {
+#pragma unroll
+                for (int q = 0; q < 6; q++) wn[q].x = wn[q].y = R(0);
+                wn[0] = F.fx[g];
+                if (gx + 1 < NX) wn[1] = F.fx[g + 1];
+                wn[2] = F.fy[g];
+                if (gy + 1 < NY) wn[3] = F.fy[g + NX];
+                wn[4] = F.fz[g];
+                if (z + 1 < NZ) wn[5] = F.fz[g + nxy];
+            }
         }
     };
     // coarse cell of this thread (t < CX * CY)
@@ -3449,6 +3481,10 @@ __global__ __launch_bounds__(TX *TY) void k_restrict_zm(Lvl<R> F, Lvl<R> C, int 
     fetch_cell(z0);
     V2 f = fn;
     V4 B = sweep_B_fin(F, Bn);
+    if (FACES) {
+#pragma unroll
+        for (int q = 0; q < 6; q++) w6[q] = wn[q];
+    }
     fetch(z0 + 1);
     for (int k = z0; k < z1; k++) {
         store(k + 1);
@@ -3460,11 +3496,15 @@ __global__ __launch_bounds__(TX *TY) void k_restrict_zm(Lvl<R> F, Lvl<R> C, int 
         if (mine) {
             const int s = k & 3, sm = (k + 3) & 3, sp = (k + 1) & 3;
             const V2 um = su[s][c];
-            const V2 am = sa[s][c];
+            V2 am;
+            if constexpr (!FACES) am = sa[s][c];
             R nbp = R(0), nbT = R(0), Sp = R(0), ST = R(0);
             // mr: the r-z metric of a radial (marching-axis, 2-D) face
+            int nf = 0;
             auto nb = [&](int ss, int q, int mr) {
-                V2 w = harm2(am, sa[ss][q]);
+                V2 w;
+                if constexpr (FACES) w = w6[nf++];
+                else w = harm2(am, sa[ss][q]);
                 if (FLAT && mr >= 0 && F.axm) axi_face(w, F.axm[k], mr == 1);
                 const R wp = w.x * ih2, wT = w.y * ih2;
                 const V2 uq = su[ss][q];
@@ -3497,6 +3537,17 @@ __global__ __launch_bounds__(TX *TY) void k_restrict_zm(Lvl<R> F, Lvl<R> C, int 
                 const R rc = F.axm[k].z;
                 accp = fmadd(r00.x + r10.x, rc, accp);
                 accT = fmadd(r00.y + r10.y, rc, accT);
+            } else if (FACES) {
+                // one child after the other, as restrict_cell
+                const V2 r01 = sr[base + TX], r11 = sr[base + TX + 1];
+                accp = accp + r00.x;
+                accp = accp + r10.x;
+                accp = accp + r01.x;
+                accp = accp + r11.x;
+                accT = accT + r00.y;
+                accT = accT + r10.y;
+                accT = accT + r01.y;
+                accT = accT + r11.y;
             } else {
                 R sp_ = r00.x + r10.x, sT_ = r00.y + r10.y;
                 if (!FLAT) {
@@ -3508,7 +3559,7 @@ __global__ __launch_bounds__(TX *TY) void k_restrict_zm(Lvl<R> F, Lvl<R> C, int 
                 accT += sT_;
             }
             if (k & 1) {
-                const R sc = FLAT ? R(0.25) : R(0.125);
+                const R sc = FACES ? R(1) / R(8) : (FLAT ? R(0.25) : R(0.125));
                 V2 o;
                 o.x = accp * sc;
                 o.y = accT * sc;
@@ -3518,11 +3569,16 @@ __global__ __launch_bounds__(TX *TY) void k_restrict_zm(Lvl<R> F, Lvl<R> C, int 
         }
         f = fn;
         B = sweep_B_fin(F, Bn);
+        if (FACES) {
+#pragma unroll
+            for (int q = 0; q < 6; q++) w6[q] = wn[q];
+        }
     }
 }
 
+// faces: a 3-D coarse level (stored faces)
 template <typename R>
-void launch_restrict_zm(int dim, const Lvl<R> &F, const Lvl<R> &C, hipStream_t s)
+void launch_restrict_zm(int dim, const Lvl<R> &F, const Lvl<R> &C, hipStream_t s, bool faces)
 {
     int NX, NY, NZ, tx, ty;
     if (dim == 3) {
@@ -3537,15 +3593,20 @@ void launch_restrict_zm(int dim, const Lvl<R> &F, const Lvl<R> &C, hipStream_t s
     int zc = NZ;   // even (the grid coarsens), kept even below
     while (zc > 8 && (long long)tx * ty * ((NZ + zc - 1) / zc) < 2048) zc = ((zc + 1) / 2 + 1) & ~1;
     const int nt = tx * ty * ((NZ + zc - 1) / zc);
-    if (dim == 3)
-        hipLaunchKernelGGL((k_restrict_zm<R, 64, 4>), dim3(nt), dim3(256), 0, s, F, C, NX, NY, NZ,
-                           zc, tx, ty, nt);
+    if (dim == 3 && faces)
+        hipLaunchKernelGGL((k_restrict_zm<R, 64, 4, true>), dim3(nt), dim3(256), 0, s, F, C, NX, NY,
+                           NZ, zc, tx, ty, nt);
+    else if (dim == 3)
+        hipLaunchKernelGGL((k_restrict_zm<R, 64, 4, false>), dim3(nt), dim3(256), 0, s, F, C, NX, NY,
+                           NZ, zc, tx, ty, nt);
     else
-        hipLaunchKernelGGL((k_restrict_zm<R, 256, 1>), dim3(nt), dim3(256), 0, s, F, C, NX, NY, NZ,
-                           zc, tx, ty, nt);
+        hipLaunchKernelGGL((k_restrict_zm<R, 256, 1, false>), dim3(nt), dim3(256), 0, s, F, C, NX,
+                           NY, NZ, zc, tx, ty, nt);
 }
-template void launch_restrict_zm<float>(int, const Lvl<float> &, const Lvl<float> &, hipStream_t);
-template void launch_restrict_zm<double>(int, const Lvl<double> &, const Lvl<double> &, hipStream_t);
+template void launch_restrict_zm<float>(int, const Lvl<float> &, const Lvl<float> &, hipStream_t,
+                                        bool);
+template void launch_restrict_zm<double>(int, const Lvl<double> &, const Lvl<double> &, hipStream_t,
+                                         bool);
 
 }  // namespace ptmg
 

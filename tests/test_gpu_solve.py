@@ -415,6 +415,37 @@ def test_fused_solve_matches_reference_per_sweep_count(name, nu):
     assert max(orc.relres(op, b_p, b_T, host(p1), host(T1))) <= 2e-11
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_coarse_restriction_3d_matches_reference(prec):
+    """3-D coarse levels of at least 2^20 cells restrict their residual with
+    the plane-marching kernel: equal to the gather kernel (PT_OPT_FUSED off)
+    bit for bit, on a level of ragged 64-column tiles (160 x 96 x 96), and
+    the V-cycle and solve with it too."""
+    import workloads.device as D
+    from paper_2206_11294_amd import ptmg
+    prob = W.bubble_problem("b3r", 3, (320, 192, 192), [(0.45, 0.5, 0.55)], [0.2], W.P0,
+                            10 * W.P0, div_amp=1e-6, div_seed=13)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        h, b_p, b_T, _ = D.setup(prob, prec, stream=stream)
+        assert h.level_dims(1)[0] == (160, 96, 96)
+        N1 = 160 * 96 * 96
+        rng = np.random.default_rng(17)
+        f_p, f_T = dev(rng.uniform(-1, 1, N1)), dev(rng.uniform(-1, 1, N1))
+        u_p, u_T = dev(rng.uniform(-1e-9, 1e-9, N1)), dev(rng.uniform(-1e-3, 1e-3, N1))
+        out = {}
+        for fused in (1, 0):
+            h.set_option(ptmg.PT_OPT_FUSED, fused)
+            fc = h.restrict_residual(1, f_p, f_T, u_p, u_T)
+            p, T = torch.empty_like(b_p), torch.empty_like(b_T)
+            info = h.solve(b_p, b_T, p, T, rtol=1e-11)
+            torch.cuda.synchronize()
+            out[fused] = (fc[0].clone(), fc[1].clone(), p, T, info["cycles"], info["hist"])
+    assert out[1][4] == out[0][4] and out[1][5] == out[0][5]
+    for a, b in zip(out[1][:4], out[0][:4]):
+        assert torch.equal(a, b), (a - b).abs().max().item()
+
+
 @pytest.mark.parametrize("nu", [(1, 1), (2, 1), (1, 2), (2, 2), (3, 2), (0, 2)])
 @pytest.mark.parametrize("prec", [0, 1])
 def test_coarse_half_cycles_match_reference(nu, prec):
