@@ -206,6 +206,10 @@ struct pt_mg_s {
     bool p_field = false, T_field = false;   // phases mode: p_adv / T_adv given per cell
     CBK<double> cbk64 = {};         // compact block: the constants of the last assembly
     double ac_rho[2] = {}, ac_k[2] = {};  // phase densities and conductivities of the last assembly
+    // the last assembly left the FP64 cell coefficients unwritten (the
+    // compact block's C forms them where they are read); ensure_ac64 writes
+    // them for the kernels that read the array
+    bool ac64_lazy = false;
     CBK<float> cbk32 = {};
     int device = 0;                 // the GPU current at setup (its static scratch)
     hipEvent_t done_ev = nullptr;   // marks the end of the last enqueued step
@@ -979,6 +983,7 @@ int assemble_enqueue(pt_mg_t h, const pt_problem *p, const double *div = nullptr
     a.m2 = p->m2;
     a.ac64 = h->ac64();
     a.B64 = h->B64();
+    h->ac64_lazy = false;
     if (P.prec == PT_PREC_MIXED) {
         a.ac32 = h->at<float2>(P.lv[0].o_ac);
         a.B32 = h->at<float4>(P.lv[0].o_B);
@@ -1031,6 +1036,13 @@ int assemble_enqueue(pt_mg_t h, const pt_problem *p, const double *div = nullptr
         }
         h->cbk32 = k32;
         a.k64 = k64;
+        if (P.compact && P.nlev > 1) {
+            // the V-cycle, the outer residual and the right-hand side read
+            // the compact block alone (a single-level grid's coarsest
+            // matrix reads the array)
+            a.ac64 = nullptr;
+            h->ac64_lazy = true;
+        }
     }
     if (b_p && p->mode != PT_COEF_EXPLICIT) {
         a.div = div;
@@ -1051,6 +1063,17 @@ int assemble_enqueue(pt_mg_t h, const pt_problem *p, const double *div = nullptr
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipEventRecord(h->done_ev, h->stream);
     return check_hip(h, e, "setup enqueue");
+}
+
+// The FP64 cell coefficients of an assembly that left them to the
+// compact block, written from its C (the assembly's arithmetic).
+void ensure_ac64(pt_mg_t h)
+{
+    if (!h->ac64_lazy) return;
+    h->begin(PT_K_OTHER, 32.0 * h->P.N);
+    launch_fill_ac64(h->P.N, h->at<double2>(h->P.o_cb64), h->ac_rho, h->ac_k, h->ac64(), h->stream);
+    h->end();
+    h->ac64_lazy = false;
 }
 
 // After done_ev: interpret the flags of the assembly.
@@ -1375,6 +1398,7 @@ int pt_mg_downstream(pt_mg_t h, const pt_downstream *d)
     const bool viscous = ne && (mu1 != 0.0 || mu2 != 0.0);
     if (viscous && !ncell)
         return fail(h, PT_ERR_ARG, "the viscous work needs the cell velocities u_star and u");
+    ensure_ac64(h);
     DownArgs a = {};
     a.nx = P.n[0];
     a.ny = P.n[1];
@@ -2015,6 +2039,7 @@ int pt_mg_level_dims(pt_mg_t h, int level, int n[3], double *hl)
 namespace {
 template <typename R> void export_level(pt_mg_t h, int level, double *faces, double *B)
 {
+    ensure_ac64(h);
     if (level == 0)
         launch_export_op<double>(h->P.dim, 1, h->level0_fp64(), faces, B, h->stream);
     else

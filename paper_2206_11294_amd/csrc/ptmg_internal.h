@@ -229,6 +229,8 @@ void launch_axi_metric(int ny, double4 *m64, float4 *m32, hipStream_t s);
 
 // ---- launch wrappers (implemented in ptmg_kernels.hip) --------------------
 void launch_assemble(const AsmArgs &a, hipStream_t s);
+void launch_fill_ac64(long long N, const double2 *cb, const double rho[2], const double kc[2],
+                      double2 *ac, hipStream_t s);
 // Eqs. (33)-(34) with the finest FP64 operator L (stored or derived).
 void launch_paper_rhs(const Lvl<double> &L, const double *p_adv, double p_const,
                       const double *T_adv, double T_const, const double *div, double dt,

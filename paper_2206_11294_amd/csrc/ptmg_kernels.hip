@@ -411,7 +411,7 @@ __global__ __launch_bounds__(kBlock) void k_assemble(AsmArgs a)
     if (argbad) atomicOr(&a.flags[FLAG_ARG], 1);
     if (sing) atomicOr(&a.flags[FLAG_SINGULAR], 1);
     if (a.b_p) paper_rhs_cell(B, rp, rT, a.div ? a.div[t] : 0.0, a.dt, a.b_p[t], a.b_T[t]);
-    a.ac64[t] = ac;
+    if (a.ac64) a.ac64[t] = ac;
     if (a.B64) a.B64[t] = B;
     if (a.ac32) a.ac32[t] = make_float2((float)ac.x, (float)ac.y);
     if (a.B32) a.B32[t] = make_float4((float)B.x, (float)B.y, (float)B.z, (float)B.w);
@@ -420,6 +420,30 @@ __global__ __launch_bounds__(kBlock) void k_assemble(AsmArgs a)
 void launch_assemble(const AsmArgs &a, hipStream_t s)
 {
     hipLaunchKernelGGL(k_assemble, dim3(nblk(a.N)), dim3(kBlock), 0, s, a);
+}
+
+// Phases mode: the FP64 cell coefficients from the compact block's C, as
+// the assembly forms them.
+struct AcK {
+    double rho[2], kc[2];
+};
+__global__ __launch_bounds__(kBlock) void k_fill_ac64(long long N, const double2 *cb, AcK k,
+                                                      double2 *ac)
+{
+    long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= N) return;
+    ac[t] = phases_ac(k.rho, k.kc, cb[t].x);
+}
+
+void launch_fill_ac64(long long N, const double2 *cb, const double rho[2], const double kc[2],
+                      double2 *ac, hipStream_t s)
+{
+    AcK k;
+    for (int q = 0; q < 2; q++) {
+        k.rho[q] = rho[q];
+        k.kc[q] = kc[q];
+    }
+    hipLaunchKernelGGL(k_fill_ac64, dim3(nblk(N)), dim3(kBlock), 0, s, N, cb, k, ac);
 }
 
 // Provisional state (Eqs. 20, 23) from the advected conserved variables;
