@@ -1481,10 +1481,12 @@ template <typename RV>
 int outer(pt_mg_t h, const double *b_p, const double *b_T, const double *src_p,
           const double *src_T, double *dst_p, double *dst_T, bool update, bool want_r,
           double *res_p, double *res_T, const double *bshift, double *r64_p = nullptr,
-          double *r64_T = nullptr)
+          double *r64_T = nullptr, const void *src32 = nullptr, void *dst32 = nullptr)
 {
     const Plan &P = h->P;
     OuterArgs<RV> a;
+    a.src32 = (const typename VT<RV>::v2 *)src32;
+    a.dst32 = (typename VT<RV>::v2 *)dst32;
     a.r64_p = r64_p;
     a.r64_T = r64_T;
     a.nx = P.n[0];
@@ -1524,8 +1526,8 @@ int outer(pt_mg_t h, const double *b_p, const double *b_T, const double *src_p,
     // ((C, bb) of the compact block, else the stored block; none without
     // the paper form)
     if (!src_p && !update) opb = !a.phases ? 0.0 : (P.compact ? 16.0 : 32.0);
-    double nbytes = (double)P.N * ((src_p ? 16 : 0) + opb + 16);
-    if (update) nbytes += (double)P.N * (2 * Rb + 16);
+    double nbytes = (double)P.N * ((src_p ? 16 : (src32 ? 2 * Rb : 0)) + opb + 16);
+    if (update) nbytes += (double)P.N * (2 * Rb + (dst32 ? 2 * Rb : 16));
     if (want_r) nbytes += (double)P.N * 2 * Rb;
     if (res_p) nbytes += 8.0 * P.N;
     if (res_T) nbytes += 8.0 * P.N;
@@ -1539,13 +1541,13 @@ int outer(pt_mg_t h, const double *b_p, const double *b_T, const double *src_p,
 int outer_any(pt_mg_t h, const double *b_p, const double *b_T, const double *src_p,
               const double *src_T, double *dst_p, double *dst_T, bool update, bool want_r,
               double *res_p, double *res_T, const double *bshift, double *r64_p = nullptr,
-              double *r64_T = nullptr)
+              double *r64_T = nullptr, const void *src32 = nullptr, void *dst32 = nullptr)
 {
     if (h->P.prec == PT_PREC_MIXED)
         return outer<float>(h, b_p, b_T, src_p, src_T, dst_p, dst_T, update, want_r, res_p, res_T,
-                            bshift, r64_p, r64_T);
+                            bshift, r64_p, r64_T, src32, dst32);
     return outer<double>(h, b_p, b_T, src_p, src_T, dst_p, dst_T, update, want_r, res_p, res_T,
-                         bshift, r64_p, r64_T);
+                         bshift, r64_p, r64_T, src32, dst32);
 }
 
 // Reduce the partial sums to 4 doubles written straight into pinned host
@@ -1613,6 +1615,19 @@ void iterate_at(pt_mg_t h, int k, double **p, double **T)
     }
 }
 
+// From a zero guess in mixed precision the first iterate u_1 = du_1 is the
+// FP32 correction itself: outer 1 keeps it as FP32 (p, T) pairs in the
+// memory of its own iterate buffer's p array (8 bytes per cell, which the
+// pairs fill), and outer 2 reads them from there and writes the other
+// buffer pair; null where the iterate stays FP64.
+void *first_pairs(pt_mg_t h)
+{
+    if (!h->sv.o.zero_guess || h->P.prec != PT_PREC_MIXED) return nullptr;
+    double *p1, *T1;
+    iterate_at(h, 1, &p1, &T1);
+    return p1;
+}
+
 // Enqueue outer iteration k: V-cycle k-1 on r_{k-1} and the FP64 update
 // u_k = u_{k-1} + du (k >= 1), the residual of u_k and its norms.
 int enqueue_outer(pt_mg_t h, int k)
@@ -1629,9 +1644,18 @@ int enqueue_outer(pt_mg_t h, int k)
     } else {
         vcycle_any(h, S.o.nu1, S.o.nu2);
         double *sp = nullptr, *sT = nullptr, *dp, *dT;
+        void *k1 = first_pairs(h);
         if (k > 1 || !S.o.zero_guess) iterate_at(h, k - 1, &sp, &sT);
         iterate_at(h, k, &dp, &dT);
-        nb = outer_any(h, S.b_p, S.b_T, sp, sT, dp, dT, true, true, nullptr, nullptr, S.bshift);
+        if (k1 && k == 1)   // u_1 = du_1: kept as FP32 pairs
+            nb = outer_any(h, S.b_p, S.b_T, nullptr, nullptr, nullptr, nullptr, true, true,
+                           nullptr, nullptr, S.bshift, nullptr, nullptr, nullptr, k1);
+        else if (k1 && k == 2)
+            nb = outer_any(h, S.b_p, S.b_T, nullptr, nullptr, dp, dT, true, true, nullptr,
+                           nullptr, S.bshift, nullptr, nullptr, k1, nullptr);
+        else
+            nb = outer_any(h, S.b_p, S.b_T, sp, sT, dp, dT, true, true, nullptr, nullptr,
+                           S.bshift);
     }
     S.k_enq = k;
     S.upd[k & 1] = h->updates;
@@ -1776,6 +1800,11 @@ int solve_advance(pt_mg_t h, pt_solve_info *info)
             // the answer is the zero guess itself, never stored
             h->begin(PT_K_OTHER, 16.0 * P.N);
             launch_zero2(S.p, S.T, 8 * (size_t)P.N, h->stream);
+            h->end();
+        } else if (k == 1 && first_pairs(h)) {
+            // u_1 as FP32 pairs (possibly in S.p's own memory)
+            h->begin(PT_K_OTHER, 24.0 * P.N);
+            launch_pairs_to_fp64((const float2 *)first_pairs(h), S.p, S.T, P.N, h->stream);
             h->end();
         } else if ((k + S.parity) % 2 == 1) {
             double *xp, *xT;
@@ -1930,7 +1959,8 @@ int solve_async(pt_mg_t h, const double *b_p, const double *b_T, double *p, doub
     }
     h->begin(PT_K_OTHER, 32.0 * P.N);
     launch_async_final(gate, S.parity, o.zero_guess, h->at<double>(P.o_xp),
-                       h->at<double>(P.o_xT), p, T, P.N, h->stream);
+                       h->at<double>(P.o_xT), (const float2 *)first_pairs(h), p, T, P.N,
+                       h->stream);
     h->end();
     if (h->prob.mean_constraint) {
         double *us = grid_sums(h, p, T, 1);

@@ -88,6 +88,11 @@ template <typename RV> struct OuterArgs {
     double bshift_scale;           // b -= bshift_scale * bshift (1/N: the mean)
     const double *src_p, *src_T;   // current iterate (null: zero)
     double *dst_p, *dst_T;         // updated iterate (update = 1)
+    // the iterate as (p, T) pairs in the V-cycle's precision where that
+    // holds it exactly (the first from a zero guess is the correction
+    // itself): read instead of src_p, src_T; written instead of dst_p, dst_T
+    const typename VT<RV>::v2 *src32;
+    typename VT<RV>::v2 *dst32;
     const typename VT<RV>::v2 *du; // correction of the last V-cycle (update = 1)
     typename VT<RV>::v2 *r;        // canonical residual out (V-cycle RHS) or null
     double *res_p, *res_T;         // mode-native residual out or null
@@ -242,9 +247,13 @@ int launch_outer_zm(int dim, const OuterArgs<RV> &a, hipStream_t s);   // return
 void launch_async_decide(const double *norms, int k, double rtol, int max_cycles, int *gate,
                          AsyncInfo *info, hipStream_t s);
 // the answer u_k into (p, T): from (xp, xT) when k + parity is odd, zero
-// when k = 0 from a zero guess, else already there
+// when k = 0 from a zero guess, from the FP32 pairs k1 when k = 1 and k1
+// is given, else already there
 void launch_async_final(const int *gate, int parity, int zero_guess, const double *xp,
-                        const double *xT, double *p, double *T, long long N, hipStream_t s);
+                        const double *xT, const float2 *k1, double *p, double *T, long long N,
+                        hipStream_t s);
+// FP32 (p, T) pairs into FP64 p, T (k1 may alias p)
+void launch_pairs_to_fp64(const float2 *k1, double *p, double *T, long long N, hipStream_t s);
 void launch_gate_reset(int *gate, AsyncInfo *info, hipStream_t s);
 int outer_zm_blocks(int dim, int nx, int ny, int nz);
 int reduce_scratch(int nblocks);   // extra partial slots launch_reduce4 needs

@@ -1435,28 +1435,60 @@ void launch_async_decide(const double *norms, int k, double rtol, int max_cycles
 
 // Where u_k lives after the solve: the caller's arrays when k + parity is
 // even, else (xp, xT); from a zero guess u_0 is never stored.
+// k1 (non-null): where outer 1 keeps its iterate as FP32 pairs (it may be
+// p's own memory: each element is read before it is written)
 __global__ __launch_bounds__(kBlock) void k_async_final(const int *gate, int parity, int zero_guess,
                                                         const double *xp, const double *xT,
-                                                        double *p, double *T, long long N)
+                                                        const float2 *k1, double *p, double *T,
+                                                        long long N)
 {
     const int k = gate[1];
     const bool zero = k == 0 && zero_guess;
-    if (!zero && (k + parity) % 2 == 0) return;
+    const bool one = k == 1 && k1;
+    if (!zero && !one && (k + parity) % 2 == 0) return;
     const long long stride = (long long)gridDim.x * kBlock;
     for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < N; i += stride) {
-        p[i] = zero ? 0.0 : xp[i];
-        T[i] = zero ? 0.0 : xT[i];
+        if (one) {
+            const float2 v = k1[i];
+            p[i] = (double)v.x;
+            T[i] = (double)v.y;
+        } else {
+            p[i] = zero ? 0.0 : xp[i];
+            T[i] = zero ? 0.0 : xT[i];
+        }
     }
 }
 
 void launch_async_final(const int *gate, int parity, int zero_guess, const double *xp,
-                        const double *xT, double *p, double *T, long long N, hipStream_t s)
+                        const double *xT, const float2 *k1, double *p, double *T, long long N,
+                        hipStream_t s)
 {
     long long blocks = (N + kBlock - 1) / kBlock;
     if (blocks > 8192) blocks = 8192;
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(k_async_final, dim3((unsigned)blocks), dim3(kBlock), 0, s, gate, parity,
-                       zero_guess, xp, xT, p, T, N);
+                       zero_guess, xp, xT, k1, p, T, N);
+}
+
+// The FP32 pairs of outer 1's iterate as FP64 p, T (k1 may be p's own
+// memory: each element is read before it is written).
+__global__ __launch_bounds__(kBlock) void k_pairs_to_fp64(const float2 *k1, double *p, double *T,
+                                                          long long N)
+{
+    const long long stride = (long long)gridDim.x * kBlock;
+    for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < N; i += stride) {
+        const float2 v = k1[i];
+        p[i] = (double)v.x;
+        T[i] = (double)v.y;
+    }
+}
+
+void launch_pairs_to_fp64(const float2 *k1, double *p, double *T, long long N, hipStream_t s)
+{
+    long long blocks = (N + kBlock - 1) / kBlock;
+    if (blocks > 8192) blocks = 8192;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_pairs_to_fp64, dim3((unsigned)blocks), dim3(kBlock), 0, s, k1, p, T, N);
 }
 
 __global__ void k_gate_reset(int *gate, AsyncInfo *info)
@@ -3167,7 +3199,7 @@ __global__ __launch_bounds__(TX *TY) void k_outer_zm(OuterArgs<RV> a, int NX, in
         // coefficients are formed from C when the plane is stored (bit i of
         // inb: cell i of the ring lies in the grid)
         double2 pu[NLD], pa[NLD];
-        V2 pd[NLD];
+        V2 pd[NLD], ps[NLD];
         unsigned inb = 0u;
         auto fetch = [&](int z) {
             inb = 0u;
@@ -3177,10 +3209,12 @@ __global__ __launch_bounds__(TX *TY) void k_outer_zm(OuterArgs<RV> a, int NX, in
                 pu[i] = make_double2(0.0, 0.0);
                 pa[i] = make_double2(0.0, 0.0);
                 pd[i].x = pd[i].y = RV(0);
+                ps[i].x = ps[i].y = RV(0);
                 const int gx = x0 + c % PX - 1, gy = y0 + c / PX - oy;
                 if (c < PS && z >= 0 && z < NZ && gx >= 0 && gx < NX && gy >= 0 && gy < NY) {
                     const long long g = gx + (long long)NX * gy + nxy * z;
                     if (a.src_p) pu[i] = make_double2(a.src_p[g], a.src_T[g]);
+                    if (a.src32) ps[i] = a.src32[g];
                     if (a.update) pd[i] = a.du[g];
                     pa[i] = a.cb ? a.cb[g] : a.ac[g];
                     inb |= 1u << i;
@@ -3194,6 +3228,7 @@ __global__ __launch_bounds__(TX *TY) void k_outer_zm(OuterArgs<RV> a, int NX, in
                 const int c = t + i * NT;
                 if (c < PS) {
                     double2 v = pu[i];
+                    if (a.src32) v = make_double2((double)ps[i].x, (double)ps[i].y);
                     if (a.update) {
                         v.x += (double)pd[i].x;
                         v.y += (double)pd[i].y;
@@ -3277,8 +3312,15 @@ __global__ __launch_bounds__(TX *TY) void k_outer_zm(OuterArgs<RV> a, int NX, in
                 }
                 const long long g = gx + (long long)NX * gy + nxy * k;
                 if (a.update) {
-                    a.dst_p[g] = um.x;
-                    a.dst_T[g] = um.y;
+                    if (a.dst32) {
+                        V2 o;   // exact: the iterate is the correction itself
+                        o.x = (RV)um.x;
+                        o.y = (RV)um.y;
+                        a.dst32[g] = o;
+                    } else {
+                        a.dst_p[g] = um.x;
+                        a.dst_T[g] = um.y;
+                    }
                 }
                 outer_out(a, g, resp, resT, rp, rT, bp, bT, acc);
             }
@@ -3385,7 +3427,7 @@ template <typename RV>
 int launch_outer_zm(int dim, const OuterArgs<RV> &a, hipStream_t s)
 {
     const ZmGeom g = outer_geom(dim, a.nx, a.ny, a.nz);
-    if (!a.src_p && !a.update) {
+    if (!a.src_p && !a.src32 && !a.update) {
         // a zero iterate: the residual is b (same blocks and partials)
         if (dim == 3)
             hipLaunchKernelGGL((k_outer_zg<3, RV, 64, 4>), dim3(g.nt), dim3(256), 0, s, a, g.NX,

@@ -806,6 +806,29 @@ def _blocking_and_async(h, b_p, b_T, rtol, max_cycles, zero_guess=True, p0=None,
     return out
 
 
+@pytest.mark.parametrize("name", ["bubble2d_200x136", "bubble3d_40x24x56"])
+def test_answer_residual_is_the_reported_one(name):
+    """Mixed precision from a zero guess keeps the first iterate (the FP32
+    correction itself) as FP32 pairs in its buffer's memory: whether a
+    solve stops after one cycle (the pairs in the caller's own p array or
+    in the handle's buffer, by the parity the last solve left) or two, the
+    residual of the returned answer is the one the solve reported, bit for
+    bit, blocking and stream-ordered."""
+    import workloads.device as D
+    prob = step_problems()[name]
+    h, b_p, b_T, _ = D.setup(prob, 1)
+    p, T = torch.empty_like(b_p), torch.empty_like(b_T)
+    tight = h.solve(b_p, b_T, p, T, rtol=1e-12)
+    assert tight["cycles"] >= 2
+    loose = 2.0 * max(tight["hist"][1])   # met after the first cycle
+    for rtol, cycles in ((loose, 1), (loose, 1), (1e-12, tight["cycles"]), (loose, 1)):
+        for (pa, Ta, info) in _blocking_and_async(h, b_p, b_T, rtol, 20):
+            torch.cuda.synchronize()
+            assert info["status"] == 0 and info["cycles"] == cycles
+            _, _, rel = h.residual(b_p, b_T, pa, Ta, want_fields=False)
+            assert rel == tuple(info["relres"]), (rtol, rel, info["relres"])
+
+
 @pytest.mark.parametrize("prec", [0, 1])
 def test_async_solve_equals_blocking(prec):
     """The stream-ordered solve (opts.async): the stop test on the device,
