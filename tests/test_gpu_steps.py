@@ -36,7 +36,9 @@ def case(request):
     out["ops"] = ops
     # the FP32 hierarchy of the mixed-precision V-cycle, built on the oracle
     # side: each coarse level is the averaging of the level above (summed in
-    # FP64) rounded to FP32, level 1 from the FP64 finest operator
+    # FP64) rounded to FP32, level 1 from the FP64 finest operator (the
+    # library coarsens level 1 from the finest operator's FP32 copy; the
+    # two agree within the FP32 tolerances below)
     ops32 = [None]
     src = op
     for l in range(1, out["fp64"][0].num_levels()):
