@@ -446,6 +446,45 @@ def test_coarse_restriction_3d_matches_reference(prec):
         assert torch.equal(a, b), (a - b).abs().max().item()
 
 
+@pytest.mark.parametrize("big", [False, True])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_coarse_single_sweep_3d_matches_reference(big, prec):
+    """3-D coarse levels with one sweep on the way down only (or up only,
+    PT_OPT_COARSE_SWEEPS 16 and 1) under an over-relaxed V(5,3) on the
+    finest level: the fused kernels (plane-marching sweeps with stored
+    faces on levels of 2^20+ cells when big) give the separate kernels'
+    solution, cycles and history bit for bit, and the solve meets the
+    tolerance against the oracle."""
+    import workloads.device as D
+    from paper_2206_11294_amd import ptmg
+    if big:
+        prob = W.bubble_problem("b3s", 3, (320, 192, 192), [(0.45, 0.5, 0.55)], [0.2], W.P0,
+                                10 * W.P0, div_amp=1e-6, div_seed=14)
+    else:
+        prob = step_problems()["bubble3d_40x24x56"]
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        h, gb_p, gb_T, _ = D.setup(prob, prec, stream=stream)
+        h.set_option(ptmg.PT_OPT_OMEGA, 1100)
+        for cs in (16, 1):
+            h.set_option(ptmg.PT_OPT_COARSE_SWEEPS, cs)
+            out = {}
+            for fused in (1, 0):
+                h.set_option(ptmg.PT_OPT_FUSED, fused)
+                p, T = torch.empty_like(gb_p), torch.empty_like(gb_T)
+                info = h.solve(gb_p, gb_T, p, T, rtol=1e-11, nu1=5, nu2=3, max_cycles=30)
+                torch.cuda.synchronize()
+                out[fused] = (p, T, info)
+            (p1, T1, i1), (p0, T0, i0) = out[1], out[0]
+            assert i1["status"] == i0["status"] == 0, (cs, i1["status"], i0["status"])
+            assert i1["cycles"] == i0["cycles"] and i1["hist"] == i0["hist"], cs
+            assert torch.equal(p1, p0) and torch.equal(T1, T0), cs
+            if not big:
+                op = orc.assemble(prob)
+                b_p, b_T = orc.rhs(op, prob)
+                assert max(orc.relres(op, b_p, b_T, host(p1), host(T1))) <= 2e-11
+
+
 @pytest.mark.parametrize("nu", [(1, 1), (2, 1), (1, 2), (2, 2), (3, 2), (0, 2)])
 @pytest.mark.parametrize("prec", [0, 1])
 def test_coarse_half_cycles_match_reference(nu, prec):
