@@ -268,6 +268,8 @@ struct pt_mg_s {
     hipGraphExec_t hier_exec = nullptr;
     bool hier_fused = true;         // use_fused when hier_graph was captured
     int hier_fields = 0;            // p_field + 2 T_field when hier_graph was captured
+    CBK<double> hier_cbk64 = {};    // the compact block's constants when hier_graph was
+    CBK<float> hier_cbk32 = {};     // captured (the graph holds them as kernel arguments)
     // off by default: with one kernel per coarse visit and the tail, a graph
     // replaces few launches, and its end costs more than they do
     bool use_graphs = false;
@@ -923,10 +925,13 @@ template <typename R> void hierarchy(pt_mg_t h)
         return;
     }
     const int fields = (int)h->p_field + 2 * (int)h->T_field;
-    if (h->hier_exec && (h->hier_fused != h->use_fused || h->hier_fields != fields)) {
-        // PT_OPT_FUSED, or which provisional fields are given per cell,
-        // changed since the capture: the graph holds other kernels or
-        // arguments, so capture again
+    const bool same_k = std::memcmp(&h->hier_cbk64, &h->cbk64, sizeof h->cbk64) == 0 &&
+                        std::memcmp(&h->hier_cbk32, &h->cbk32, sizeof h->cbk32) == 0;
+    if (h->hier_exec && (h->hier_fused != h->use_fused || h->hier_fields != fields || !same_k)) {
+        // PT_OPT_FUSED, which provisional fields are given per cell, or the
+        // compact block's constants (dt, the phases) changed since the
+        // capture: the graph holds other kernels or arguments, so capture
+        // again
         (void)hipGraphExecDestroy(h->hier_exec);
         (void)hipGraphDestroy(h->hier_graph);
         h->hier_exec = nullptr;
@@ -935,6 +940,8 @@ template <typename R> void hierarchy(pt_mg_t h)
     if (!h->hier_exec) {
         h->hier_fused = h->use_fused;
         h->hier_fields = fields;
+        h->hier_cbk64 = h->cbk64;
+        h->hier_cbk32 = h->cbk32;
         bool ok = hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
         if (ok) {
             build_hierarchy<R>(h);

@@ -286,6 +286,41 @@ def test_hierarchy_graph_follows_fused_toggle(name):
             assert torch.equal(sol[0][0], sol[1][0]) and torch.equal(sol[0][1], sol[1][1])
 
 
+@pytest.mark.parametrize("name", ["bubble2d_200x136", "bubble3d_40x24x56"])
+def test_hierarchy_graph_follows_time_step(name):
+    """A mixed-precision phases handle keeps its finest block compact, with
+    constants of dt and the phases that the hierarchy graph holds as kernel
+    arguments: updates with another dt (and back) capture it again, and
+    every level's operator and the solve equal those of a handle with
+    direct launches bit for bit."""
+    import dataclasses
+    import workloads.device as D
+    from paper_2206_11294_amd import ptmg
+    prob = step_problems()[name]
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        hg, b_p, b_T, _ = D.setup(prob, 1, stream=stream)
+        hd, _, _, _ = D.setup(prob, 1, stream=stream)
+        hg.set_option(ptmg.PT_OPT_GRAPHS, 1)
+        for dt in (prob.dt, 0.5 * prob.dt, 0.5 * prob.dt, prob.dt):
+            pr = dataclasses.replace(prob, dt=dt)
+            s2, t2 = D.to_device(pr)
+            for h in (hg, hd):
+                h.update(s2, keepalive=t2)
+            for lv in range(hg.num_levels()):
+                Fg, Bg = hg.get_operator(lv)
+                Fd, Bd = hd.get_operator(lv)
+                assert torch.equal(Fg, Fd) and torch.equal(Bg, Bd), (dt, lv)
+            sol = []
+            for h in (hg, hd):
+                p, T = torch.empty_like(b_p), torch.empty_like(b_T)
+                info = h.solve(b_p, b_T, p, T, rtol=1e-12)
+                assert info["status"] == 0
+                sol.append((p, T))
+            torch.cuda.synchronize()
+            assert torch.equal(sol[0][0], sol[1][0]) and torch.equal(sol[0][1], sol[1][1])
+
+
 @pytest.mark.parametrize("n", [(136, 40, 48), (68, 36, 36)])
 def test_fused_restriction_3d_equals_reference(n):
     """The 3-D FP32 finest sweep that also restricts its residual (the last
