@@ -869,7 +869,7 @@ template <typename R> void build_hierarchy(pt_mg_t h)
         // FP32 copies in mixed precision: half the bytes of the FP64 one)
         launch_coarsen<R, R>(P.dim, 1, h->level<R>(0), (typename VT<R>::v2 *)c1.fx,
                              (typename VT<R>::v2 *)c1.fy, (typename VT<R>::v2 *)c1.fz,
-                             (typename VT<R>::v4 *)c1.B, h->stream);
+                             (typename VT<R>::v4 *)c1.B, h->stream, h->use_fused);
         for (int l = 1; l + 1 < (small ? b0 : P.nlev); l++) {
             Lvl<R> f = h->level<R>(l), c = h->level<R>(l + 1);
             launch_coarsen<R, R>(P.dim, 0, f, (typename VT<R>::v2 *)c.fx,

@@ -297,10 +297,12 @@ bool launch_tail(int dim, const TailArgs<R> &a, size_t lds_bytes, hipStream_t s)
 template <typename R> void tail_set_lds_limit(int dim, size_t bytes);
 template <typename R>
 void launch_prolong(int dim, const Lvl<R> &F, const Lvl<R> &C, hipStream_t s);
+// zm: a 3-D finest level coarsens with the plane-marching kernel (bitwise
+// the gather kernel's result)
 template <typename RIN, typename ROUT>
 void launch_coarsen(int dim, int level0, const Lvl<RIN> &F, typename VT<ROUT>::v2 *fx,
                     typename VT<ROUT>::v2 *fy, typename VT<ROUT>::v2 *fz,
-                    typename VT<ROUT>::v4 *B, hipStream_t s);
+                    typename VT<ROUT>::v4 *B, hipStream_t s, bool zm = false);
 template <typename R>
 void launch_coarse_dense(int dim, int level0, const Lvl<R> &L, int pin_mean, double *M,
                          hipStream_t s);

@@ -1034,13 +1034,172 @@ __global__ __launch_bounds__(kBlock) void k_coarsen(Lvl<RIN> F, int cnx, int cny
     coarsen_cell<RIN, ROUT, DIM, CF>(F, cnx, cny, cnz, fx, fy, fz, Bo, t);
 }
 
+// Level 1 from a 3-D finest level (cell coefficients), plane-marching: a
+// block takes a 64 x 4 tile of fine cells (32 x 2 coarse cells) down a
+// chunk of plane pairs, one coarse plane per step, with the next pair's
+// loads in flight while a pair computes.  Each thread forms its two fine
+// cells' blocks and the lower faces on which a cell is a lower child (the
+// harmonic mean with the neighbour below along that axis: in-plane from
+// the pair's coefficients staged in LDS with a lower halo, along z from
+// the cell below); the coarse cells' threads then sum their eight
+// children in the order of coarsen_cell (the block over all eight, each
+// face over the children on it), so the result is k_coarsen's bit for bit.
+template <typename RIN, typename ROUT>
+__global__ __launch_bounds__(256) void k_coarsen0_zm(Lvl<RIN> F, int zc, int tiles_x, int tiles_y,
+                                                     int ntiles, typename VT<ROUT>::v2 *fx,
+                                                     typename VT<ROUT>::v2 *fy,
+                                                     typename VT<ROUT>::v2 *fz,
+                                                     typename VT<ROUT>::v4 *Bo)
+{
+    using V2 = typename VT<RIN>::v2;
+    using V4 = typename VT<RIN>::v4;
+    using O2 = typename VT<ROUT>::v2;
+    using O4 = typename VT<ROUT>::v4;
+    constexpr int TX = 64, TY = 4, NT = TX * TY;
+    constexpr int PX = TX + 1, PY = TY + 1, PS = PX * PY;   // the tile and its lower halo
+    constexpr int NLD = (PS + NT - 1) / NT;
+    constexpr int CX = TX / 2, CY = TY / 2;
+    __shared__ V2 sac[2][PS];
+    __shared__ V4 sB[2][NT];
+    __shared__ V2 sf[2][3][NT];   // [plane of the pair][axis][cell]
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    if (tile >= ntiles) return;
+    const int t = threadIdx.x;
+    const int txi = tile % tiles_x;
+    const int rr = tile / tiles_x;
+    const int x0 = txi * TX, y0 = (rr % tiles_y) * TY;
+    const int z0 = (rr / tiles_y) * zc, z1 = min(z0 + zc, F.nz);   // z0, z1 even
+    const long long nxy = (long long)F.nx * F.ny;
+    const int lx = t % TX, ly = t / TX;
+    const int gx = x0 + lx, gy = y0 + ly;
+    const bool mine = gx < F.nx && gy < F.ny;
+    const long long g0 = gx + (long long)F.nx * gy;
+    const int cnx = F.nx / 2, cny = F.ny / 2;
+    const int cxl = t % CX, cyl = t / CX;
+    const int gcx = x0 / 2 + cxl, gcy = y0 / 2 + cyl;
+    const bool cmine = t < CX * CY && gcx < cnx && gcy < cny;
+    V2 zero;
+    zero.x = zero.y = RIN(0);
+    // the loads of a pair (planes z, z+1), raw in registers
+    V2 pa[2][NLD];
+    V4 pb[2];
+    auto load = [&](int z) {
+#pragma unroll
+        for (int h = 0; h < 2; h++) {
+#pragma unroll
+            for (int i = 0; i < NLD; i++) {
+                const int c = t + i * NT;
+                const int hx = x0 - 1 + c % PX, hy = y0 - 1 + c / PX;
+                pa[h][i] = zero;
+                if (c < PS && hx >= 0 && hx < F.nx && hy >= 0 && hy < F.ny)
+                    pa[h][i] = cell_ac(F, hx + (long long)F.nx * hy + nxy * (z + h));
+            }
+            if (mine) pb[h] = cell_B_raw(F, g0 + nxy * (z + h));
+        }
+    };
+    V2 below = zero;   // coefficients of this thread's cell on the plane below the pair
+    if (mine && z0 > 0) below = cell_ac(F, g0 + nxy * (z0 - 1));
+    if (z0 < z1) load(z0);
+    for (int z = z0; z < z1; z += 2) {
+#pragma unroll
+        for (int h = 0; h < 2; h++) {
+#pragma unroll
+            for (int i = 0; i < NLD; i++) {
+                const int c = t + i * NT;
+                if (c < PS) sac[h][c] = pa[h][i];
+            }
+        }
+        V4 bown[2];
+        bown[0] = pb[0];
+        bown[1] = pb[1];
+        __syncthreads();
+        if (z + 2 < z1) load(z + 2);
+        if (mine) {
+            const int c = (ly + 1) * PX + lx + 1;
+#pragma unroll
+            for (int h = 0; h < 2; h++) {
+                const V2 am = sac[h][c];
+                V2 wx = zero, wy = zero, wz = zero;
+                if ((gx & 1) == 0 && gx > 0) wx = harm2(am, sac[h][c - 1]);
+                if ((gy & 1) == 0 && gy > 0) wy = harm2(am, sac[h][c - PX]);
+                if (h == 0 && z > 0) wz = harm2(am, below);
+                sB[h][t] = cell_B_fin(F, bown[h]);
+                sf[h][0][t] = wx;
+                sf[h][1][t] = wy;
+                sf[h][2][t] = wz;
+                if (h == 1) below = am;
+            }
+        }
+        __syncthreads();
+        if (cmine) {
+            // children m = 4 h + 2 b + a: x, then y, then z order
+            double b4[4] = {0, 0, 0, 0};
+            double fs[3][2] = {{0, 0}, {0, 0}, {0, 0}};
+#pragma unroll
+            for (int h = 0; h < 2; h++) {
+#pragma unroll
+                for (int b = 0; b < 2; b++) {
+#pragma unroll
+                    for (int a = 0; a < 2; a++) {
+                        const int q = (2 * cyl + b) * TX + 2 * cxl + a;
+                        const V4 bq = sB[h][q];
+                        b4[0] += (double)bq.x;
+                        b4[1] += (double)bq.y;
+                        b4[2] += (double)bq.z;
+                        b4[3] += (double)bq.w;
+                        if (a == 0 && gcx > 0) {
+                            fs[0][0] += (double)sf[h][0][q].x;
+                            fs[0][1] += (double)sf[h][0][q].y;
+                        }
+                        if (b == 0 && gcy > 0) {
+                            fs[1][0] += (double)sf[h][1][q].x;
+                            fs[1][1] += (double)sf[h][1][q].y;
+                        }
+                        if (h == 0 && z > 0) {
+                            fs[2][0] += (double)sf[h][2][q].x;
+                            fs[2][1] += (double)sf[h][2][q].y;
+                        }
+                    }
+                }
+            }
+            const long long o = gcx + (long long)cnx * gcy + (long long)cnx * cny * (z >> 1);
+            const double inv_nc = 1.0 / 8, inv_nf = 1.0 / 4;
+            O4 ob;
+            ob.x = (ROUT)(b4[0] * inv_nc);
+            ob.y = (ROUT)(b4[1] * inv_nc);
+            ob.z = (ROUT)(b4[2] * inv_nc);
+            ob.w = (ROUT)(b4[3] * inv_nc);
+            Bo[o] = ob;
+            O2 w;
+            w.x = (ROUT)(fs[0][0] * inv_nf);
+            w.y = (ROUT)(fs[0][1] * inv_nf);
+            fx[o] = w;
+            w.x = (ROUT)(fs[1][0] * inv_nf);
+            w.y = (ROUT)(fs[1][1] * inv_nf);
+            fy[o] = w;
+            w.x = (ROUT)(fs[2][0] * inv_nf);
+            w.y = (ROUT)(fs[2][1] * inv_nf);
+            fz[o] = w;
+        }
+    }
+}
+
 template <typename RIN, typename ROUT>
 void launch_coarsen(int dim, int level0, const Lvl<RIN> &F, typename VT<ROUT>::v2 *fx,
                     typename VT<ROUT>::v2 *fy, typename VT<ROUT>::v2 *fz,
-                    typename VT<ROUT>::v4 *B, hipStream_t s)
+                    typename VT<ROUT>::v4 *B, hipStream_t s, bool zm)
 {
     const int cnx = F.nx / 2, cny = F.ny / 2, cnz = dim == 3 ? F.nz / 2 : 1;
     dim3 g(nblk((long long)cnx * cny * cnz)), b(kBlock);
+    if (dim == 3 && level0 && zm && !F.axm) {
+        const int tx = (F.nx + 63) / 64, ty = (F.ny + 3) / 4;
+        int zc = F.nz;   // even (the grid coarsens), kept even below
+        while (zc > 8 && (long long)tx * ty * ((F.nz + zc - 1) / zc) < 2048) zc = ((zc + 1) / 2 + 1) & ~1;
+        const int nt = tx * ty * ((F.nz + zc - 1) / zc);
+        hipLaunchKernelGGL((k_coarsen0_zm<RIN, ROUT>), dim3(nt), dim3(256), 0, s, F, zc, tx, ty, nt,
+                           fx, fy, fz, B);
+        return;
+    }
     if (dim == 3) {
         if (level0)
             hipLaunchKernelGGL((k_coarsen<RIN, ROUT, 3, true>), g, b, 0, s, F, cnx, cny, cnz, fx,
@@ -1058,11 +1217,11 @@ void launch_coarsen(int dim, int level0, const Lvl<RIN> &F, typename VT<ROUT>::v
     }
 }
 template void launch_coarsen<double, double>(int, int, const Lvl<double> &, double2 *, double2 *,
-                                             double2 *, double4 *, hipStream_t);
+                                             double2 *, double4 *, hipStream_t, bool);
 template void launch_coarsen<double, float>(int, int, const Lvl<double> &, float2 *, float2 *,
-                                            float2 *, float4 *, hipStream_t);
+                                            float2 *, float4 *, hipStream_t, bool);
 template void launch_coarsen<float, float>(int, int, const Lvl<float> &, float2 *, float2 *,
-                                           float2 *, float4 *, hipStream_t);
+                                           float2 *, float4 *, hipStream_t, bool);
 
 // ------------------------------------------------ coarsest-grid matrix
 // Dense FP64 matrix of the level operator, unknown (2*cell + component).

@@ -286,6 +286,42 @@ def test_hierarchy_graph_follows_fused_toggle(name):
             assert torch.equal(sol[0][0], sol[1][0]) and torch.equal(sol[0][1], sol[1][1])
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_level1_coarsening_3d_matches_reference(prec):
+    """3-D level 1 coarsened from the finest level by the plane-marching
+    kernel (PT_OPT_FUSED on) equals the gather kernel's (off) bit for bit,
+    on ragged 64 x 4 tiles and z chunks (40 x 24 x 56 and 160 x 48 x 56),
+    and so do every coarser level and the solve."""
+    import workloads.device as D
+    from paper_2206_11294_amd import ptmg
+    probs = [step_problems()["bubble3d_40x24x56"],
+             W.bubble_problem("b3c", 3, (160, 48, 56), [(0.4, 0.5, 0.5)], [0.25], W.P0,
+                              10 * W.P0, div_amp=1e-6, div_seed=15)]
+    for prob in probs:
+        stream = torch.cuda.Stream()
+        with torch.cuda.stream(stream):
+            h1, b_p, b_T, _ = D.setup(prob, prec, stream=stream)
+            h0, _, _, _ = D.setup(prob, prec, stream=stream)
+            h0.set_option(ptmg.PT_OPT_FUSED, 0)
+            s2, t2 = D.to_device(prob)
+            for h in (h1, h0):
+                h.update(s2, keepalive=t2)
+            for lv in range(1, h1.num_levels()):
+                F1, B1 = h1.get_operator(lv)
+                F0, B0 = h0.get_operator(lv)
+                assert torch.equal(F1, F0) and torch.equal(B1, B0), (prob.name, lv)
+            h0.set_option(ptmg.PT_OPT_FUSED, 1)
+            sol = []
+            for h in (h1, h0):
+                p, T = torch.empty_like(b_p), torch.empty_like(b_T)
+                info = h.solve(b_p, b_T, p, T, rtol=1e-12)
+                assert info["status"] == 0
+                sol.append((p, T, info["hist"]))
+            torch.cuda.synchronize()
+            assert sol[0][2] == sol[1][2]
+            assert torch.equal(sol[0][0], sol[1][0]) and torch.equal(sol[0][1], sol[1][1])
+
+
 @pytest.mark.parametrize("name", ["bubble2d_200x136", "bubble3d_40x24x56"])
 def test_hierarchy_graph_follows_time_step(name):
     """A mixed-precision phases handle keeps its finest block compact, with
