@@ -376,6 +376,56 @@ def serve_bench(args):
         print(json.dumps(window(rate, args.serve_sweep_seconds, 5.0)), flush=True)
 
 
+def grid_study():
+    """Cycles to relres 1e-12 against the grid size, per workload family:
+    the 2-D bubble at N = 64..1024 (FP64), the 3-D near-wall bubble at
+    N = 32..256 and the 3-D collapse at N = 64..512 (mixed precision),
+    each with the library's default smoothing (V(2,2) on every level,
+    omega = 1) and with the workload's bench smoothing.  One JSON line per
+    (family, N, smoothing): cycles, the residual history and the solve
+    time (zero guess, the paper right-hand side)."""
+    import time as _t
+
+    import torch
+
+    import workloads as W
+    import workloads.device as D
+    from paper_2206_11294_amd import ptmg
+    families = [("bubble2d", lambda n: W.bubble2d(n), ptmg.PT_PREC_FP64, (64, 128, 256, 512, 1024),
+                 "bubble2d_1024"),
+                ("wall3d", lambda n: W.wall3d(n), ptmg.PT_PREC_MIXED, (32, 64, 128, 256),
+                 "wall3d_256"),
+                ("collapse3d", lambda n: W.collapse3d(n), ptmg.PT_PREC_MIXED, (64, 128, 256, 512),
+                 "collapse3d_512")]
+    for fam, make, prec, sizes, wl in families:
+        for n in sizes:
+            prob = make(n)
+            h, b_p, b_T, _ = D.setup(prob, prec)
+            p, T = torch.empty_like(b_p), torch.empty_like(b_T)
+            nu1, nu2, coarse = SWEEPS[wl]
+            for label, (a, b, cs, om) in (("V(2,2)", (2, 2, 0, 1000)),
+                                          ("bench", (nu1, nu2, coarse, OMEGA.get(wl, 1000)))):
+                h.set_option(ptmg.PT_OPT_COARSE_SWEEPS, cs)
+                h.set_option(ptmg.PT_OPT_OMEGA, om)
+                info = None
+                for rep in range(3):
+                    torch.cuda.synchronize()
+                    t0 = _t.perf_counter()
+                    info = h.solve(b_p, b_T, p, T, rtol=1e-12, nu1=a, nu2=b, max_cycles=60,
+                                   raise_on_noconv=False)
+                    torch.cuda.synchronize()
+                    ms = (_t.perf_counter() - t0) * 1e3
+                hist = [max(x) for x in info["hist"]]
+                rates = [hist[k] / hist[k - 1] for k in range(2, len(hist))]
+                print(json.dumps({"family": fam, "n": n, "precision": "mixed" if prec else "fp64",
+                                  "smoothing": label, "sweeps": [a, b], "coarse_sweeps": cs,
+                                  "omega": om / 1000, "status": info["status"],
+                                  "cycles": info["cycles"], "relres_hist": hist,
+                                  "contraction_after_first": rates, "ms_per_solve": ms}),
+                      flush=True)
+            del h
+
+
 def stream_probe():
     """Attainable HBM bandwidth: plain copies of 2 GiB timed with HIP
     events (the library's copy kernel and torch's copy_), and the library's
@@ -470,6 +520,8 @@ def main():
                     help="time one finest-grid smoothing run in this many")
     ap.add_argument("--serve", action="store_true", help="the serving mix instead of a workload")
     ap.add_argument("--stream-probe", action="store_true", help="copy bandwidth, then exit")
+    ap.add_argument("--grid-study", action="store_true",
+                    help="cycles to tolerance against the grid size per workload family, then exit")
     ap.add_argument("--serve-rate", type=float, default=50.0)
     ap.add_argument("--serve-seconds", type=float, default=130.0,
                     help="open-loop run length, warm-up included")
@@ -506,6 +558,9 @@ def main():
 
     if args.stream_probe:
         stream_probe()
+        return
+    if args.grid_study:
+        grid_study()
         return
     if args.copy_calib:
         copy_calibration(args.copy_calib)
